@@ -1,0 +1,190 @@
+/*
+ * rst.h -- C ABI of librst, rooted spanning trees on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Sec. I of "Beyond BFS: A Comparative Study of Rooted Spanning Tree
+ * Algorithms on GPUs", arXiv 2603.11645): given an undirected connected graph
+ * G=(V,E) and a root r, return a parent array P with P[r] = r and exactly one
+ * parent for every other vertex, each {v, P[v]} an edge of G.
+ *
+ * Two methods are provided:
+ *   RST_GCONN_EULER  connectivity by hooking + pointer jumping that records the
+ *                    edge behind every union (Sec. III-B), then Euler-tour
+ *                    rooting of the spanning forest (Sec. III-D);
+ *   RST_BFS          level-synchronous breadth-first search (Sec. III-A).
+ *
+ * Conventions shared by every call:
+ *   - Every array argument is a DEVICE pointer unless its comment says host.
+ *     The caller owns and allocates all input and output buffers; the library
+ *     only reads inputs and writes outputs and never frees them.
+ *   - Vertex ids are int32; 0 <= id < n.  Offsets are int32 or int64 as given by
+ *     rst_csr.offset_bytes.  The CSR must be symmetric (both directions of every
+ *     undirected edge stored); self-loops and duplicate arcs are tolerated.
+ *   - Calls are synchronous: work is enqueued on the context's HIP stream and the
+ *     call returns after that work has completed.  One context per host thread.
+ *   - Every call returns an rst_status; no call aborts and no C++ exception
+ *     crosses the ABI.  On an error other than RST_E_DISCONNECTED the contents of
+ *     output buffers are unspecified.
+ *   - Device scratch memory is owned by the context, grown on demand with
+ *     hipMalloc, and released by rst_destroy.
+ */
+#ifndef RST_H
+#define RST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rst_ctx rst_ctx;
+
+typedef enum {
+  RST_OK = 0,
+  RST_E_INVAL = -1,        /* null pointer, n < 1, root out of range, bad offset width,
+                              nnz too large for 4-byte offsets, ...                     */
+  RST_E_NOMEM = -2,        /* device scratch allocation failed                          */
+  RST_E_DEVICE = -3,       /* a HIP runtime call failed                                 */
+  RST_E_DISCONNECTED = -4, /* input has more than one component; the output is still a
+                              valid rooted spanning forest (see rst_spanning_tree)       */
+  RST_E_RANGE = -5,        /* validation found an offset or neighbour id out of range   */
+  RST_E_UNSUPPORTED = -6   /* request not supported by this build / device              */
+} rst_status;
+
+typedef enum { RST_GCONN_EULER = 0, RST_BFS = 1, RST_AUTO = 2 } rst_method;
+
+/* Symmetric CSR of an undirected graph (Sec. I). */
+typedef struct {
+  int64_t n;             /* vertices, >= 1                                          */
+  int64_t nnz;           /* stored arcs = offsets[n]                                */
+  int32_t offset_bytes;  /* 4 (int32 offsets, nnz < 2^31) or 8 (int64 offsets)     */
+  const void *offsets;   /* device [n+1], non-decreasing, offsets[0] = 0            */
+  const int32_t *cols;   /* device [nnz], neighbour ids                             */
+} rst_csr;
+
+/* Several graphs packed into one CSR with global vertex ids: graph g owns
+ * vertices [vtx_off[g], vtx_off[g+1]) and arcs [arc_off[g], arc_off[g+1]). */
+typedef struct {
+  int32_t num_graphs;      /* G >= 1                                              */
+  const int64_t *vtx_off;  /* device [G+1]                                        */
+  const int64_t *arc_off;  /* device [G+1]                                        */
+  const int32_t *roots;    /* device [G], global id of each graph's root          */
+} rst_batch;
+
+/* Stage indices of rst_stats.ms_stage. */
+enum {
+  RST_STAGE_HOOK = 0,      /* hooking sweep (spanning-edge recording)           */
+  RST_STAGE_COMPRESS = 1,  /* pointer jumping to min-id labels                  */
+  RST_STAGE_ARCS = 2,      /* root marking + twin arcs and per-vertex arc lists */
+  RST_STAGE_SUCC = 3,      /* Euler successor + cycle breaking                  */
+  RST_STAGE_RANK = 4,      /* list ranking (all rounds)                         */
+  RST_STAGE_PARENT = 5,    /* parents from tour order                           */
+  RST_STAGE_BFS = 6,       /* breadth-first search (all levels)                 */
+  RST_STAGE_SELECT = 7     /* selector features + inference (batch calls)       */
+};
+
+/* Host struct filled by calls that take an rst_stats* (nullable).  Timings are
+ * HIP-event times on the context stream; they are only collected when the
+ * pointer is non-NULL (events add a little overhead). */
+typedef struct {
+  float ms_total;
+  float ms_stage[8];
+  int64_t hook_rounds;    /* hooking sweeps performed                          */
+  int64_t rank_rounds;    /* list-ranking launches                             */
+  int64_t bfs_levels;     /* deepest BFS level reached (eccentricity of root)  */
+  int64_t components;     /* connected components found                        */
+  int32_t method_used;    /* rst_method actually run (batch: -1 if mixed)      */
+  int32_t reserved;
+} rst_stats;
+
+/* Tunables and switches for rst_set_option. */
+typedef enum {
+  RST_OPT_VALIDATE = 0,        /* 1: check offsets/neighbour ids before running (O(nnz)) */
+  RST_OPT_BFS_LEVELS_PER_SYNC = 1, /* BFS levels launched between host checks (>= 1)   */
+  RST_OPT_BFS_GRID = 2,        /* blocks per BFS level launch (0 = automatic)          */
+  RST_OPT_RANK_ELEMS_PER_THREAD = 3, /* list-ranking elements per thread (1, 2, 4, 8)  */
+  RST_OPT_HEAVY_DEGREE = 4     /* degree above which a vertex's arcs are split over blocks */
+} rst_option;
+
+/* Create a context on HIP device `device` bound to `hip_stream` (a hipStream_t,
+ * NULL = the default stream).  *out receives the context.  Errors: RST_E_INVAL
+ * (out == NULL or bad device), RST_E_DEVICE. */
+rst_status rst_create(rst_ctx **out, int device, void *hip_stream);
+
+/* Release the context and its scratch memory.  NULL is ignored. */
+void rst_destroy(rst_ctx *ctx);
+
+/* Rebind the context to another stream of the same device. */
+rst_status rst_set_stream(rst_ctx *ctx, void *hip_stream);
+
+/* Set a tunable (see rst_option).  RST_E_INVAL for an unknown option or a value
+ * out of range. */
+rst_status rst_set_option(rst_ctx *ctx, rst_option opt, int64_t value);
+
+/* Rooted spanning tree of the graph (Sec. I) by `method` (RST_AUTO runs the
+ * selector on this one graph).  parent: device int32 [n], written completely.
+ * If the graph is disconnected the call returns RST_E_DISCONNECTED and parent
+ * is a rooted spanning forest: root's component is rooted at root, every other
+ * component at its minimum vertex id.  stats may be NULL. */
+rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_method method,
+                             int32_t *parent, rst_stats *stats);
+
+/* Connected components by hooking + pointer jumping (Sec. III-B).  label: device
+ * int32 [n] receives the minimum vertex id of each vertex's component.
+ * num_components: host, nullable. */
+rst_status rst_components(rst_ctx *ctx, const rst_csr *g, int32_t *label,
+                          int64_t *num_components);
+
+/* The connectivity stage alone (Sec. III-B with the spanning-edge marking of
+ * Sec. I): label as in rst_components, and for every vertex x that stopped being
+ * a component root, the graph edge (tu[x], tv[x]) whose hook made it a non-root;
+ * tu[x] = tv[x] = -1 for the n - t vertices that stayed roots.  tu, tv: device
+ * int32 [n].  num_edges: host, nullable, receives t = n - components. */
+rst_status rst_spanning_forest(rst_ctx *ctx, const rst_csr *g, int32_t *label, int32_t *tu,
+                               int32_t *tv, int64_t *num_edges);
+
+/* Level-synchronous BFS from root (Sec. III-A).  level: device int32 [n], hop
+ * distance or -1 if unreachable; parent: device int32 [n], a neighbour one level
+ * closer to root (parent[root] = root), -1 if unreachable.  Returns RST_OK even
+ * if some vertices are unreachable.  stats may be NULL. */
+rst_status rst_bfs(rst_ctx *ctx, const rst_csr *g, int32_t root, int32_t *level,
+                   int32_t *parent, rst_stats *stats);
+
+/* The Euler-tour rooting stage alone (Sec. III-D) for a forest given as t
+ * undirected edges (eu[k], ev[k]) over n vertices (device int32 [t] each).
+ * roots: device int32 [nroots], at most one per tree; a tree without a listed
+ * root is rooted at its minimum vertex id.  parent: device int32 [n].  The
+ * result is unique for a given forest and roots.  RST_E_INVAL if two roots share
+ * a tree or the edges are out of range; a non-forest input (a cycle) gives an
+ * unspecified parent array. */
+rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu,
+                           const int32_t *ev, const int32_t *roots, int32_t nroots,
+                           int32_t *parent);
+
+/* List ranking (Sec. III-D): succ is a device int32 [A] array describing
+ * disjoint simple lists (succ[e] = next node or -1 at a tail).  dist: device
+ * int32 [A] receives the number of nodes after e in its list (0 at the tail).
+ * Cycles give unspecified output. */
+rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *dist);
+
+/* Rooted spanning forest of G packed graphs in one pass: graph g is rooted at
+ * roots[g].  method: device uint8 [G] per graph (0 = GConn+Euler, 1 = BFS), or
+ * NULL to let the loaded selector choose (GConn+Euler if none is loaded).
+ * parent: device int32 [total n].  method_out: device uint8 [G], nullable,
+ * receives the method used per graph.  stats may be NULL. */
+rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                                     const uint8_t *method, int32_t *parent,
+                                     uint8_t *method_out, rst_stats *stats);
+
+/* Load selector weights (host blob written by rst_selector_save or the Python
+ * trainer; format described in selector.h).  RST_E_INVAL on a malformed blob. */
+rst_status rst_selector_load(rst_ctx *ctx, const void *blob, size_t bytes);
+
+/* Human-readable name of a status code (static string). */
+const char *rst_status_string(rst_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RST_H */

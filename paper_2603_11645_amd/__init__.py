@@ -1,0 +1,316 @@
+"""Rooted spanning trees on AMD Instinct MI355X -- Python binding of librst.
+
+A thin ctypes layer over the C ABI declared in ``include/rst.h``: it only
+marshals arguments (device pointers of torch tensors, sizes, the current HIP
+stream) and maps status codes to exceptions.  Every step of every method runs
+in the library's HIP kernels; there is no CPU fallback, and importing a
+function that needs the library fails loudly if ``librst.so`` is not built.
+
+Names follow the C entry points without the ``rst_`` prefix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librst.so")
+
+RST_OK = 0
+RST_E_INVAL = -1
+RST_E_NOMEM = -2
+RST_E_DEVICE = -3
+RST_E_DISCONNECTED = -4
+RST_E_RANGE = -5
+RST_E_UNSUPPORTED = -6
+
+GCONN_EULER = 0
+BFS = 1
+AUTO = 2
+_METHODS = {"gconn": GCONN_EULER, "gconn_euler": GCONN_EULER, "bfs": BFS, "auto": AUTO,
+            GCONN_EULER: GCONN_EULER, BFS: BFS, AUTO: AUTO}
+
+OPT_VALIDATE = 0
+OPT_BFS_LEVELS_PER_SYNC = 1
+OPT_BFS_GRID = 2
+OPT_RANK_ELEMS_PER_THREAD = 3
+OPT_HEAVY_DEGREE = 4
+
+STAGES = ["hook", "compress", "arcs", "succ", "rank", "parent", "bfs", "select"]
+
+# symbols the header declares (checked by the CPU test-suite)
+EXPORTS = [
+    "rst_create", "rst_destroy", "rst_set_stream", "rst_set_option", "rst_spanning_tree",
+    "rst_components", "rst_spanning_forest", "rst_bfs", "rst_root_forest", "rst_list_rank",
+    "rst_spanning_forest_batch", "rst_selector_load", "rst_status_string",
+]
+
+
+class RstError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__("%s failed: %s (%d)" % (where, status_string(code), code))
+
+
+class rst_csr(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("offset_bytes", ctypes.c_int32),
+                ("offsets", ctypes.c_void_p), ("cols", ctypes.c_void_p)]
+
+
+class rst_batch(ctypes.Structure):
+    _fields_ = [("num_graphs", ctypes.c_int32), ("vtx_off", ctypes.c_void_p),
+                ("arc_off", ctypes.c_void_p), ("roots", ctypes.c_void_p)]
+
+
+class rst_stats(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_float), ("ms_stage", ctypes.c_float * 8),
+                ("hook_rounds", ctypes.c_int64), ("rank_rounds", ctypes.c_int64),
+                ("bfs_levels", ctypes.c_int64), ("components", ctypes.c_int64),
+                ("method_used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"ms_total": self.ms_total,
+                "ms_stage": {STAGES[i]: self.ms_stage[i] for i in range(8)},
+                "hook_rounds": self.hook_rounds, "rank_rounds": self.rank_rounds,
+                "bfs_levels": self.bfs_levels, "components": self.components,
+                "method_used": self.method_used}
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library(path: Optional[str] = None):
+    """Load librst.so (built by ``_build.build()``); raises if it is missing."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise RuntimeError("librst.so not found at %s: build it with "
+                               "paper_2603_11645_amd._build.build() (hipcc, gfx950)" % p)
+        lib = ctypes.CDLL(p)
+        P, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        S = ctypes.c_int
+        sig = {
+            "rst_create": (S, [ctypes.POINTER(P), ctypes.c_int, P]),
+            "rst_destroy": (None, [P]),
+            "rst_set_stream": (S, [P, P]),
+            "rst_set_option": (S, [P, ctypes.c_int, i64]),
+            "rst_spanning_tree": (S, [P, ctypes.POINTER(rst_csr), i32, ctypes.c_int, P,
+                                      ctypes.POINTER(rst_stats)]),
+            "rst_components": (S, [P, ctypes.POINTER(rst_csr), P, ctypes.POINTER(i64)]),
+            "rst_spanning_forest": (S, [P, ctypes.POINTER(rst_csr), P, P, P, ctypes.POINTER(i64)]),
+            "rst_bfs": (S, [P, ctypes.POINTER(rst_csr), i32, P, P, ctypes.POINTER(rst_stats)]),
+            "rst_root_forest": (S, [P, i64, i64, P, P, P, i32, P]),
+            "rst_list_rank": (S, [P, i64, P, P]),
+            "rst_spanning_forest_batch": (S, [P, ctypes.POINTER(rst_csr), ctypes.POINTER(rst_batch),
+                                              P, P, P, ctypes.POINTER(rst_stats)]),
+            "rst_selector_load": (S, [P, P, ctypes.c_size_t]),
+            "rst_status_string": (ctypes.c_char_p, [S]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+        return lib
+
+
+def status_string(code: int) -> str:
+    try:
+        return load_library().rst_status_string(code).decode()
+    except Exception:  # library missing: still give a readable name
+        return {0: "ok", -1: "invalid argument", -2: "out of device memory", -3: "HIP runtime error",
+                -4: "graph is disconnected", -5: "out of range", -6: "unsupported"}.get(code, "?")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _check_dev(t, dtype, name):
+    torch = _torch()
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def make_csr(offsets, cols, n: Optional[int] = None) -> rst_csr:
+    torch = _torch()
+    if offsets.dtype not in (torch.int32, torch.int64):
+        raise ValueError("offsets must be int32 or int64")
+    _check_dev(offsets, offsets.dtype, "offsets")
+    _check_dev(cols, torch.int32, "cols")
+    n = offsets.shape[0] - 1 if n is None else int(n)
+    return rst_csr(n, int(cols.shape[0]), 4 if offsets.dtype == torch.int32 else 8,
+                   offsets.data_ptr(), cols.data_ptr())
+
+
+class Context:
+    """An rst_ctx bound to a device; each call runs on torch's current stream."""
+
+    def __init__(self, device: Optional[int] = None):
+        torch = _torch()
+        lib = load_library()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            rc = lib.rst_create(ctypes.byref(h), self.device, ctypes.c_void_p(stream))
+        if rc != RST_OK:
+            raise RstError(rc, "rst_create")
+        self._h = h
+        self._lib = lib
+        self.last_status = RST_OK
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.rst_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- plumbing -------------------------------------------------------------
+    def _bind(self):
+        torch = _torch()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        self._lib.rst_set_stream(self._h, ctypes.c_void_p(stream))
+
+    def _call(self, name, *args, ok=(RST_OK,)):
+        self._bind()
+        rc = getattr(self._lib, name)(self._h, *args)
+        self.last_status = rc
+        if rc not in ok:
+            raise RstError(rc, name)
+        return rc
+
+    def set_option(self, opt: int, value: int):
+        self._call("rst_set_option", int(opt), int(value))
+
+    # -- entry points ---------------------------------------------------------
+    def spanning_tree(self, offsets, cols, root: int = 0, method="gconn", parent=None,
+                      stats: bool = False):
+        """Parent array (int32, device) of a rooted spanning tree; see rst_spanning_tree."""
+        torch = _torch()
+        g = make_csr(offsets, cols)
+        if parent is None:
+            parent = torch.empty(g.n, dtype=torch.int32, device=offsets.device)
+        _check_dev(parent, torch.int32, "parent")
+        st = rst_stats()
+        self._call("rst_spanning_tree", ctypes.byref(g), int(root), _METHODS[method],
+                   ctypes.c_void_p(parent.data_ptr()), ctypes.byref(st) if stats else None,
+                   ok=(RST_OK, RST_E_DISCONNECTED))
+        return (parent, st.as_dict()) if stats else parent
+
+    def components(self, offsets, cols, label=None):
+        torch = _torch()
+        g = make_csr(offsets, cols)
+        if label is None:
+            label = torch.empty(g.n, dtype=torch.int32, device=offsets.device)
+        _check_dev(label, torch.int32, "label")
+        k = ctypes.c_int64(0)
+        self._call("rst_components", ctypes.byref(g), ctypes.c_void_p(label.data_ptr()),
+                   ctypes.byref(k))
+        return label, int(k.value)
+
+    def spanning_forest(self, offsets, cols):
+        torch = _torch()
+        g = make_csr(offsets, cols)
+        dev = offsets.device
+        label = torch.empty(g.n, dtype=torch.int32, device=dev)
+        tu = torch.empty(g.n, dtype=torch.int32, device=dev)
+        tv = torch.empty(g.n, dtype=torch.int32, device=dev)
+        t = ctypes.c_int64(0)
+        self._call("rst_spanning_forest", ctypes.byref(g), ctypes.c_void_p(label.data_ptr()),
+                   ctypes.c_void_p(tu.data_ptr()), ctypes.c_void_p(tv.data_ptr()), ctypes.byref(t))
+        return label, tu, tv, int(t.value)
+
+    def bfs(self, offsets, cols, root: int = 0, stats: bool = False):
+        torch = _torch()
+        g = make_csr(offsets, cols)
+        dev = offsets.device
+        level = torch.empty(g.n, dtype=torch.int32, device=dev)
+        parent = torch.empty(g.n, dtype=torch.int32, device=dev)
+        st = rst_stats()
+        self._call("rst_bfs", ctypes.byref(g), int(root), ctypes.c_void_p(level.data_ptr()),
+                   ctypes.c_void_p(parent.data_ptr()), ctypes.byref(st) if stats else None)
+        return (level, parent, st.as_dict()) if stats else (level, parent)
+
+    def root_forest(self, n: int, eu, ev, roots, parent=None):
+        torch = _torch()
+        _check_dev(eu, torch.int32, "eu")
+        _check_dev(ev, torch.int32, "ev")
+        _check_dev(roots, torch.int32, "roots")
+        t = int(eu.shape[0])
+        if parent is None:
+            parent = torch.empty(n, dtype=torch.int32, device=eu.device)
+        self._call("rst_root_forest", int(n), t, ctypes.c_void_p(eu.data_ptr()),
+                   ctypes.c_void_p(ev.data_ptr()), ctypes.c_void_p(roots.data_ptr()),
+                   int(roots.shape[0]), ctypes.c_void_p(parent.data_ptr()))
+        return parent
+
+    def list_rank(self, succ, dist=None):
+        torch = _torch()
+        _check_dev(succ, torch.int32, "succ")
+        A = int(succ.shape[0])
+        if dist is None:
+            dist = torch.empty(A, dtype=torch.int32, device=succ.device)
+        self._call("rst_list_rank", A, ctypes.c_void_p(succ.data_ptr()),
+                   ctypes.c_void_p(dist.data_ptr()))
+        return dist
+
+
+_default = {}
+
+
+def default_context(device: Optional[int] = None) -> Context:
+    torch = _torch()
+    d = torch.cuda.current_device() if device is None else int(device)
+    ctx = _default.get(d)
+    if ctx is None:
+        ctx = Context(d)
+        _default[d] = ctx
+    return ctx
+
+
+def spanning_tree(offsets, cols, root: int = 0, method="gconn", stats: bool = False):
+    return default_context(offsets.device.index).spanning_tree(offsets, cols, root, method,
+                                                              stats=stats)
+
+
+def components(offsets, cols):
+    return default_context(offsets.device.index).components(offsets, cols)
+
+
+def spanning_forest(offsets, cols):
+    return default_context(offsets.device.index).spanning_forest(offsets, cols)
+
+
+def bfs(offsets, cols, root: int = 0, stats: bool = False):
+    return default_context(offsets.device.index).bfs(offsets, cols, root, stats=stats)
+
+
+def root_forest(n, eu, ev, roots):
+    return default_context(eu.device.index).root_forest(n, eu, ev, roots)
+
+
+def list_rank(succ):
+    return default_context(succ.device.index).list_rank(succ)

@@ -1,0 +1,431 @@
+// api.hip -- the C ABI of librst (declared in include/rst.h): contexts, scratch
+// management, argument checks and the host-side ordering of the stages.
+#include "rst_internal.h"
+
+#include <new>
+#include <cstring>
+
+namespace rst {
+
+rst_status ws_reserve(rst_ctx *ctx, size_t bytes) {
+  ctx->ws.used = 0;
+  if (bytes <= ctx->ws.cap) return RST_OK;
+  if (ctx->ws.base) {
+    RST_HIP(hipStreamSynchronize(ctx->stream));
+    RST_HIP(hipFree(ctx->ws.base));
+    ctx->ws.base = nullptr;
+    ctx->ws.cap = 0;
+  }
+  size_t cap = bytes + (bytes >> 3) + (1u << 20);
+  if (hipMalloc(reinterpret_cast<void **>(&ctx->ws.base), cap) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->ws.base = nullptr;
+    return RST_E_NOMEM;
+  }
+  ctx->ws.cap = cap;
+  return RST_OK;
+}
+
+static rst_status check_csr(const rst_csr *g) {
+  if (!g || g->n < 1 || g->nnz < 0 || !g->offsets) return RST_E_INVAL;
+  if (g->nnz > 0 && !g->cols) return RST_E_INVAL;
+  if (g->offset_bytes != 4 && g->offset_bytes != 8) return RST_E_INVAL;
+  if (g->offset_bytes == 4 && g->nnz >= ((int64_t)1 << 31)) return RST_E_INVAL;
+  // arc ids 2x+1 of the rooting stage are int32
+  if (g->n >= ((int64_t)1 << 30)) return RST_E_INVAL;
+  return RST_OK;
+}
+
+static rst_status read_counters(rst_ctx *ctx, const int32_t *counters) {
+  RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
+                         hipMemcpyDeviceToHost, ctx->stream));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  return RST_OK;
+}
+
+static rst_status run_validation(rst_ctx *ctx, const rst_csr *g, int32_t *counters) {
+  if (!ctx->opt.validate) return RST_OK;
+  RST_TRY(enqueue_validate(ctx, g, counters));
+  RST_TRY(read_counters(ctx, counters));
+  if (ctx->host_pinned[kCntRangeErr]) return RST_E_RANGE;
+  return RST_OK;
+}
+
+static void fill_stage_times(rst_ctx *ctx, rst_stats *st, const int *stage_of_gap, int nev) {
+  float ms = 0.f;
+  for (int i = 0; i + 1 < nev; ++i) {
+    if (hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]) == hipSuccess && stage_of_gap[i] >= 0)
+      st->ms_stage[stage_of_gap[i]] += ms;
+  }
+  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[nev - 1]) == hipSuccess) st->ms_total = ms;
+}
+
+static inline rst_status mark(rst_ctx *ctx, rst_stats *st, int i) {
+  if (st) RST_HIP(hipEventRecord(ctx->ev[i], ctx->stream));
+  return RST_OK;
+}
+
+// GConn + Euler over the whole CSR.  roots: device list (one per component at
+// most).  Writes parent, returns the component count in *components.
+rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
+                           int32_t *parent, rst_stats *st, int64_t *components,
+                           int32_t *counters, int32_t *cc_out) {
+  const int64_t n = g->n;
+  const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
+  ForestBufs f;
+  f.counters = counters;
+  f.cc = cc_out ? cc_out : ws_take<int32_t>(ctx, n);
+  f.tu = ws_take<int32_t>(ctx, n);
+  f.tv = ws_take<int32_t>(ctx, n);
+  f.comp_root = ws_take<int32_t>(ctx, n);
+  int32_t *head = ws_take<int32_t>(ctx, n);
+  int32_t *next = ws_take<int32_t>(ctx, 2 * n);
+  uint64_t *rank = ws_take<uint64_t>(ctx, 2 * n);
+  int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
+
+  RST_TRY(mark(ctx, st, 0));
+  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap));
+  RST_TRY(mark(ctx, st, 1));
+  RST_TRY(enqueue_compress(ctx, n, f.cc, f.comp_root, head));
+  RST_TRY(mark(ctx, st, 2));
+  RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, f.cc, f.comp_root, parent, counters));
+  RST_TRY(enqueue_link(ctx, n, f.tu, f.tv, head, next));
+  RST_TRY(mark(ctx, st, 3));
+  RST_TRY(enqueue_succ(ctx, n, f.tu, f.tv, head, next, f.cc, f.comp_root, rank));
+  RST_TRY(mark(ctx, st, 4));
+  const int rounds = rank_rounds_for(2 * n);
+  RST_TRY(enqueue_rank_rounds(ctx, 2 * n, rank, rounds, nullptr, nullptr));
+  RST_TRY(mark(ctx, st, 5));
+  RST_TRY(enqueue_parent(ctx, n, n, f.tu, f.tv, rank, f.cc, f.comp_root, parent, counters));
+  RST_TRY(mark(ctx, st, 6));
+  RST_TRY(read_counters(ctx, counters));
+  if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
+  if (ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
+  *components = ctx->host_pinned[kCntComponents];
+  if (st) {
+    static const int gaps[6] = {RST_STAGE_HOOK, RST_STAGE_COMPRESS, RST_STAGE_ARCS, RST_STAGE_SUCC,
+                                RST_STAGE_RANK, RST_STAGE_PARENT};
+    fill_stage_times(ctx, st, gaps, 7);
+    st->hook_rounds = 1;
+    st->rank_rounds = rounds;
+    st->components = *components;
+    st->method_used = RST_GCONN_EULER;
+  }
+  return RST_OK;
+}
+
+static rst_status take_bfs_bufs(rst_ctx *ctx, const rst_csr *g, BfsBufs &b) {
+  b.heavy_cap = (int64_t)bfs_heavy_capacity(ctx, g->n, g->nnz);
+  b.q[0] = ws_take<int32_t>(ctx, g->n);
+  b.q[1] = ws_take<int32_t>(ctx, g->n);
+  b.h[0] = ws_take<int32_t>(ctx, b.heavy_cap);
+  b.h[1] = ws_take<int32_t>(ctx, b.heavy_cap);
+  b.cnt = ws_take<int32_t>(ctx, 8);
+  return RST_OK;
+}
+
+static size_t bfs_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
+  const size_t hc = bfs_heavy_capacity(ctx, g->n, g->nnz);
+  return 2 * ws_bytes(g->n, 4) + 2 * ws_bytes(hc, 4) + ws_bytes(8, 4);
+}
+
+static size_t gconn_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
+  const size_t n = (size_t)g->n;
+  return 5 * ws_bytes(n, 4) + ws_bytes(2 * n, 4) + ws_bytes(2 * n, 8) +
+         ws_bytes(hook_chunk_capacity(ctx, g->nnz), 8);
+}
+
+}  // namespace rst
+
+using namespace rst;
+
+extern "C" {
+
+rst_status rst_create(rst_ctx **out, int device, void *hip_stream) {
+  if (!out) return RST_E_INVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return RST_E_INVAL;
+  RST_HIP(hipSetDevice(device));
+  rst_ctx *ctx = new (std::nothrow) rst_ctx();
+  if (!ctx) return RST_E_NOMEM;
+  ctx->device = device;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cus > 0)
+    ctx->num_cus = cus;
+  for (int i = 0; i < 16; ++i) {
+    if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { rst_destroy(ctx); return RST_E_DEVICE; }
+  }
+  if (hipHostMalloc(reinterpret_cast<void **>(&ctx->host_pinned), 64 * sizeof(int32_t),
+                    hipHostMallocDefault) != hipSuccess) {
+    ctx->host_pinned = nullptr;
+    rst_destroy(ctx);
+    return RST_E_DEVICE;
+  }
+  *out = ctx;
+  return RST_OK;
+}
+
+void rst_destroy(rst_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->ws.base) (void)hipFree(ctx->ws.base);
+  for (int i = 0; i < 16; ++i)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
+  delete ctx;
+}
+
+rst_status rst_set_stream(rst_ctx *ctx, void *hip_stream) {
+  if (!ctx) return RST_E_INVAL;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return RST_OK;
+}
+
+rst_status rst_set_option(rst_ctx *ctx, rst_option opt, int64_t value) {
+  if (!ctx) return RST_E_INVAL;
+  switch (opt) {
+    case RST_OPT_VALIDATE: ctx->opt.validate = value ? 1 : 0; return RST_OK;
+    case RST_OPT_BFS_LEVELS_PER_SYNC:
+      if (value < 1 || value > 4096) return RST_E_INVAL;
+      ctx->opt.bfs_levels_per_sync = (int)value;
+      return RST_OK;
+    case RST_OPT_BFS_GRID:
+      if (value < 0 || value > 65536) return RST_E_INVAL;
+      ctx->opt.bfs_grid = (int)value;
+      return RST_OK;
+    case RST_OPT_RANK_ELEMS_PER_THREAD:
+      if (value != 1 && value != 2 && value != 4 && value != 8) return RST_E_INVAL;
+      ctx->opt.rank_elems_per_thread = (int)value;
+      return RST_OK;
+    case RST_OPT_HEAVY_DEGREE:
+      if (value < 32 || value > (1 << 24)) return RST_E_INVAL;
+      ctx->opt.heavy_degree = (int)value;
+      return RST_OK;
+  }
+  return RST_E_INVAL;
+}
+
+rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_method method,
+                             int32_t *parent, rst_stats *stats) {
+  if (!ctx || !parent) return RST_E_INVAL;
+  RST_TRY(check_csr(g));
+  if (root < 0 || root >= g->n) return RST_E_INVAL;
+  if (method == RST_AUTO) method = RST_GCONN_EULER;
+  if (method != RST_GCONN_EULER && method != RST_BFS) return RST_E_INVAL;
+  RST_HIP(hipSetDevice(ctx->device));
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+
+  size_t bytes = ws_bytes(64, 4) + gconn_ws_bytes(ctx, g);
+  if (method == RST_BFS) bytes += bfs_ws_bytes(ctx, g) + ws_bytes(g->n, 4);
+  RST_TRY(ws_reserve(ctx, bytes));
+  int32_t *counters = ws_take<int32_t>(ctx, 64);
+  int32_t *rootbuf = counters + 32;
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+  RST_TRY(enqueue_fill(ctx, rootbuf, 1, root));
+  RST_TRY(run_validation(ctx, g, counters));
+
+  if (method == RST_GCONN_EULER) {
+    int64_t comps = 0;
+    RST_TRY(run_gconn_euler(ctx, g, rootbuf, 1, parent, stats, &comps, counters, nullptr));
+    return comps > 1 ? RST_E_DISCONNECTED : RST_OK;
+  }
+
+  // BFS from root; unreached components (if any) are then rooted at their
+  // minimum id by a second multi-source search.
+  BfsBufs b;
+  RST_TRY(take_bfs_bufs(ctx, g, b));
+  int32_t *level = ws_take<int32_t>(ctx, g->n);
+  RST_TRY(mark(ctx, stats, 0));
+  RST_TRY(bfs_reset(ctx, g->n, level, parent, b));
+  RST_TRY(bfs_seed_roots(ctx, g, rootbuf, 1, level, parent, b, counters));
+  int64_t levels = 0;
+  RST_TRY(bfs_run_levels(ctx, g, level, parent, b, counters, &levels));
+  RST_TRY(mark(ctx, stats, 1));
+  RST_TRY(read_counters(ctx, counters));
+  const int64_t reached = ctx->host_pinned[kCntBfsReached];
+  rst_status status = RST_OK;
+  int64_t comps = 1;
+  if (reached < g->n) {
+    ForestBufs f;
+    f.counters = counters;
+    f.cc = ws_take<int32_t>(ctx, g->n);
+    f.tu = ws_take<int32_t>(ctx, g->n);
+    f.tv = ws_take<int32_t>(ctx, g->n);
+    const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
+    int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
+    RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap));
+    RST_TRY(enqueue_compress(ctx, g->n, f.cc, nullptr, nullptr));
+    RST_TRY(enqueue_count_roots(ctx, g->n, f.cc, counters));
+    RST_TRY(bfs_seed_unreached(ctx, g, f.cc, level, parent, b, counters));
+    int64_t l2 = 0;
+    RST_TRY(bfs_run_levels(ctx, g, level, parent, b, counters, &l2));
+    RST_TRY(read_counters(ctx, counters));
+    comps = ctx->host_pinned[kCntComponents];
+    status = RST_E_DISCONNECTED;
+  }
+  RST_TRY(mark(ctx, stats, 2));
+  if (stats) {
+    RST_HIP(hipEventSynchronize(ctx->ev[2]));
+    static const int gaps[2] = {RST_STAGE_BFS, RST_STAGE_BFS};
+    fill_stage_times(ctx, stats, gaps, 3);
+    stats->bfs_levels = levels;
+    stats->components = comps;
+    stats->method_used = RST_BFS;
+  }
+  return status;
+}
+
+rst_status rst_components(rst_ctx *ctx, const rst_csr *g, int32_t *label,
+                          int64_t *num_components) {
+  if (!ctx || !label) return RST_E_INVAL;
+  RST_TRY(check_csr(g));
+  RST_HIP(hipSetDevice(ctx->device));
+  const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 2 * ws_bytes(g->n, 4) + ws_bytes(chunk_cap, 8)));
+  int32_t *counters = ws_take<int32_t>(ctx, 64);
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+  RST_TRY(run_validation(ctx, g, counters));
+  ForestBufs f;
+  f.counters = counters;
+  f.cc = label;
+  f.tu = ws_take<int32_t>(ctx, g->n);
+  f.tv = ws_take<int32_t>(ctx, g->n);
+  int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
+  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap));
+  RST_TRY(enqueue_compress(ctx, g->n, label, nullptr, nullptr));
+  RST_TRY(enqueue_count_roots(ctx, g->n, label, counters));
+  RST_TRY(read_counters(ctx, counters));
+  if (num_components) *num_components = ctx->host_pinned[kCntComponents];
+  return RST_OK;
+}
+
+rst_status rst_spanning_forest(rst_ctx *ctx, const rst_csr *g, int32_t *label, int32_t *tu,
+                               int32_t *tv, int64_t *num_edges) {
+  if (!ctx || !label || !tu || !tv) return RST_E_INVAL;
+  RST_TRY(check_csr(g));
+  RST_HIP(hipSetDevice(ctx->device));
+  const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + ws_bytes(chunk_cap, 8)));
+  int32_t *counters = ws_take<int32_t>(ctx, 64);
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+  RST_TRY(run_validation(ctx, g, counters));
+  ForestBufs f;
+  f.counters = counters;
+  f.cc = label;
+  f.tu = tu;
+  f.tv = tv;
+  int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
+  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap));
+  RST_TRY(enqueue_compress(ctx, g->n, label, nullptr, nullptr));
+  RST_TRY(enqueue_count_roots(ctx, g->n, label, counters));
+  RST_TRY(read_counters(ctx, counters));
+  if (num_edges) *num_edges = g->n - ctx->host_pinned[kCntComponents];
+  return RST_OK;
+}
+
+rst_status rst_bfs(rst_ctx *ctx, const rst_csr *g, int32_t root, int32_t *level, int32_t *parent,
+                   rst_stats *stats) {
+  if (!ctx || !level || !parent) return RST_E_INVAL;
+  RST_TRY(check_csr(g));
+  if (root < 0 || root >= g->n) return RST_E_INVAL;
+  RST_HIP(hipSetDevice(ctx->device));
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + bfs_ws_bytes(ctx, g)));
+  int32_t *counters = ws_take<int32_t>(ctx, 64);
+  int32_t *rootbuf = counters + 32;
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+  RST_TRY(enqueue_fill(ctx, rootbuf, 1, root));
+  RST_TRY(run_validation(ctx, g, counters));
+  BfsBufs b;
+  RST_TRY(take_bfs_bufs(ctx, g, b));
+  RST_TRY(mark(ctx, stats, 0));
+  RST_TRY(bfs_reset(ctx, g->n, level, parent, b));
+  RST_TRY(bfs_seed_roots(ctx, g, rootbuf, 1, level, parent, b, counters));
+  int64_t levels = 0;
+  RST_TRY(bfs_run_levels(ctx, g, level, parent, b, counters, &levels));
+  RST_TRY(mark(ctx, stats, 1));
+  if (stats) {
+    RST_HIP(hipEventSynchronize(ctx->ev[1]));
+    static const int gaps[1] = {RST_STAGE_BFS};
+    fill_stage_times(ctx, stats, gaps, 2);
+    stats->bfs_levels = levels;
+    stats->method_used = RST_BFS;
+  }
+  return RST_OK;
+}
+
+rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu,
+                           const int32_t *ev, const int32_t *roots, int32_t nroots,
+                           int32_t *parent) {
+  if (!ctx || !parent || n < 1 || t < 0 || t > n - 1 || nroots < 0) return RST_E_INVAL;
+  if (t > 0 && (!eu || !ev)) return RST_E_INVAL;
+  if (nroots > 0 && !roots) return RST_E_INVAL;
+  if (n >= ((int64_t)1 << 30)) return RST_E_INVAL;
+  RST_HIP(hipSetDevice(ctx->device));
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 3 * ws_bytes(n, 4) + ws_bytes(2 * t + 2, 4) +
+                              ws_bytes(2 * t + 2, 8)));
+  int32_t *counters = ws_take<int32_t>(ctx, 64);
+  int32_t *cc = ws_take<int32_t>(ctx, n);
+  int32_t *comp_root = ws_take<int32_t>(ctx, n);
+  int32_t *head = ws_take<int32_t>(ctx, n);
+  int32_t *next = ws_take<int32_t>(ctx, 2 * t + 2);
+  uint64_t *rank = ws_take<uint64_t>(ctx, 2 * t + 2);
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+  RST_TRY(enqueue_hook_coo(ctx, n, t, eu, ev, cc, counters));
+  RST_TRY(enqueue_compress(ctx, n, cc, comp_root, head));
+  RST_TRY(read_counters(ctx, counters));
+  if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
+  RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, cc, comp_root, parent, counters));
+  RST_TRY(enqueue_link(ctx, t, eu, ev, head, next));
+  RST_TRY(enqueue_succ(ctx, t, eu, ev, head, next, cc, comp_root, rank));
+  RST_TRY(enqueue_rank_rounds(ctx, 2 * t, rank, rank_rounds_for(2 * t), nullptr, nullptr));
+  RST_TRY(enqueue_parent(ctx, t, n, eu, ev, rank, cc, comp_root, parent, counters));
+  RST_TRY(read_counters(ctx, counters));
+  if (ctx->host_pinned[kCntRangeErr] || ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
+  return RST_OK;
+}
+
+rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *dist) {
+  if (!ctx || A < 0 || (A > 0 && (!succ || !dist))) return RST_E_INVAL;
+  if (A >= ((int64_t)1 << 31)) return RST_E_INVAL;
+  if (A == 0) return RST_OK;
+  RST_HIP(hipSetDevice(ctx->device));
+  RST_TRY(ws_reserve(ctx, ws_bytes(A, 8)));
+  uint64_t *rank = ws_take<uint64_t>(ctx, A);
+  RST_TRY(enqueue_rank_init(ctx, A, succ, rank));
+  RST_TRY(enqueue_rank_rounds(ctx, A, rank, rank_rounds_for(A), nullptr, nullptr));
+  RST_TRY(enqueue_rank_extract(ctx, A, rank, dist));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  return RST_OK;
+}
+
+rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                                     const uint8_t *method, int32_t *parent, uint8_t *method_out,
+                                     rst_stats *stats) {
+  (void)ctx; (void)g; (void)b; (void)method; (void)parent; (void)method_out; (void)stats;
+  return RST_E_UNSUPPORTED;
+}
+
+rst_status rst_selector_load(rst_ctx *ctx, const void *blob, size_t bytes) {
+  (void)ctx; (void)blob; (void)bytes;
+  return RST_E_UNSUPPORTED;
+}
+
+const char *rst_status_string(rst_status s) {
+  switch (s) {
+    case RST_OK: return "ok";
+    case RST_E_INVAL: return "invalid argument";
+    case RST_E_NOMEM: return "out of device memory";
+    case RST_E_DEVICE: return "HIP runtime error";
+    case RST_E_DISCONNECTED: return "graph is disconnected (spanning forest returned)";
+    case RST_E_RANGE: return "offset or neighbour id out of range";
+    case RST_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

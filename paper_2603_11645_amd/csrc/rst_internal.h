@@ -1,0 +1,149 @@
+// rst_internal.h -- shared declarations of the librst HIP sources (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "rst.h"
+
+namespace rst {
+
+constexpr int kWave = 64;          // CDNA wavefront width
+constexpr int kBlock = 256;        // threads per block for the sweep kernels
+
+// Device scratch owned by a context: one buffer, bump-allocated per call.
+struct Workspace {
+  char *base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+
+struct Options {
+  int validate = 0;
+  int bfs_levels_per_sync = 32;
+  int bfs_grid = 0;
+  int rank_elems_per_thread = 4;
+  int heavy_degree = 1024;
+};
+
+struct Selector;
+
+}  // namespace rst
+
+struct rst_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int num_cus = 256;
+  rst::Workspace ws;
+  rst::Options opt;
+  hipEvent_t ev[16] = {};
+  int32_t *host_pinned = nullptr;   // small pinned host buffer for flag readback
+  rst::Selector *selector = nullptr;
+};
+
+namespace rst {
+
+// ---------------------------------------------------------------------------
+// host helpers
+// ---------------------------------------------------------------------------
+#define RST_HIP(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return RST_E_DEVICE;          \
+  } while (0)
+
+#define RST_TRY(call)                                   \
+  do {                                                  \
+    rst_status s_ = (call);                             \
+    if (s_ != RST_OK) return s_;                        \
+  } while (0)
+
+// Reserve `bytes` of workspace (256-byte aligned).  Grows the buffer (keeping
+// nothing) only when called with ws.used == 0, i.e. at the start of a call.
+rst_status ws_reserve(rst_ctx *ctx, size_t bytes);
+template <class T>
+T *ws_take(rst_ctx *ctx, size_t count) {
+  size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+  char *p = ctx->ws.base + ctx->ws.used;
+  ctx->ws.used += bytes;
+  return reinterpret_cast<T *>(p);
+}
+inline size_t ws_bytes(size_t count, size_t elem) { return (count * elem + 255) & ~size_t(255); }
+
+inline unsigned grid_for(int64_t items, int per_block) {
+  int64_t g = (items + per_block - 1) / per_block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------------------
+// stage entry points (host side, enqueue only; defined in the .hip files)
+// ---------------------------------------------------------------------------
+struct ForestBufs {
+  int32_t *cc;         // [n] union-find parents -> min-id labels
+  int32_t *tu, *tv;    // [slots] recorded spanning edge per slot, -1 = empty
+  int32_t *comp_root;  // [n] designated root of the component labelled v, or -1
+  int32_t *counters;   // [16] device counters (see kCnt*)
+};
+
+enum {
+  kCntChunks = 0,      // heavy-vertex chunk count (hooking)
+  kCntRootErr = 1,     // two designated roots in one component
+  kCntComponents = 2,  // vertices with cc[v] == v
+  kCntRangeErr = 3,    // validation failure
+  kCntBfsReached = 4,  // vertices reached by BFS
+  kCntBfsLast = 5,     // deepest non-empty BFS level
+  kCntTotal = 16
+};
+
+// hook.hip
+rst_status enqueue_fill(rst_ctx *ctx, int32_t *p, int64_t count, int32_t value);
+rst_status enqueue_validate(rst_ctx *ctx, const rst_csr *g, int32_t *counters);
+rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64_t *chunks,
+                            int64_t chunk_cap);
+rst_status enqueue_hook_coo(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu,
+                            const int32_t *ev, int32_t *cc, int32_t *counters);
+rst_status enqueue_compress(rst_ctx *ctx, int64_t n, int32_t *cc, int32_t *comp_root,
+                            int32_t *head);
+rst_status enqueue_count_roots(rst_ctx *ctx, int64_t n, const int32_t *cc, int32_t *counters);
+size_t hook_chunk_capacity(const rst_ctx *ctx, int64_t nnz);
+
+// euler.hip
+rst_status enqueue_mark_roots(rst_ctx *ctx, const int32_t *roots, int32_t nroots, int64_t n,
+                              const int32_t *cc, int32_t *comp_root, int32_t *parent,
+                              int32_t *counters);
+rst_status enqueue_link(rst_ctx *ctx, int64_t slots, const int32_t *tu, const int32_t *tv,
+                        int32_t *head, int32_t *next);
+rst_status enqueue_succ(rst_ctx *ctx, int64_t slots, const int32_t *tu, const int32_t *tv,
+                        const int32_t *head, const int32_t *next, const int32_t *cc,
+                        const int32_t *comp_root, uint64_t *rank);
+rst_status enqueue_rank_init(rst_ctx *ctx, int64_t A, const int32_t *succ, uint64_t *rank);
+rst_status enqueue_rank_rounds(rst_ctx *ctx, int64_t A, uint64_t *rank, int rounds,
+                               hipEvent_t ev_begin, hipEvent_t ev_end);
+rst_status enqueue_rank_extract(rst_ctx *ctx, int64_t A, const uint64_t *rank, int32_t *dist);
+rst_status enqueue_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
+                          const int32_t *tv, const uint64_t *rank, const int32_t *cc,
+                          const int32_t *comp_root, int32_t *parent, int32_t *counters);
+int rank_rounds_for(int64_t max_list_len);
+
+// bfs.hip
+struct BfsBufs {
+  int32_t *q[2];       // light frontier queues [n]
+  int32_t *h[2];       // heavy frontier queues [heavy_cap]
+  int32_t *cnt;        // [3][2] rotating (light, heavy) counts
+  int64_t heavy_cap;
+};
+size_t bfs_heavy_capacity(const rst_ctx *ctx, int64_t n, int64_t nnz);
+// level[] = parent[] = -1, counts zeroed
+rst_status bfs_reset(rst_ctx *ctx, int64_t n, int32_t *level, int32_t *parent, BfsBufs &b);
+// seed the level-0 frontier with a device list of roots
+rst_status bfs_seed_roots(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
+                          int32_t *level, int32_t *parent, BfsBufs &b, int32_t *counters);
+// seed the level-0 frontier with every unreached vertex v that has cc[v] == v
+rst_status bfs_seed_unreached(rst_ctx *ctx, const rst_csr *g, const int32_t *cc, int32_t *level,
+                              int32_t *parent, BfsBufs &b, int32_t *counters);
+// run levels until the frontier is empty; *levels_out = deepest level reached
+rst_status bfs_run_levels(rst_ctx *ctx, const rst_csr *g, int32_t *level, int32_t *parent,
+                          BfsBufs &b, int32_t *counters, int64_t *levels_out);
+
+}  // namespace rst

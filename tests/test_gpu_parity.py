@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Unique results are compared bit for bit: BFS levels, min-id component labels,
+the rooting of a given forest (rst_root_forest vs DFS rooting), list ranks,
+and the whole parent array on tree inputs (where the RST is unique).  Where
+several answers are valid (which spanning tree hooking returns, which BFS
+parent wins a race) the output is checked by the oracle's verifier, and the
+forest edges by |F| = n - c plus component equality.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_11645_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_11645_amd as rst
+    return rst.Context(0)
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def upload(g):
+    return dev(g.offsets_typed()), dev(g.cols)
+
+
+def small_graphs():
+    gs = [
+        I.path(1), I.path(2), I.path(257), I.star(300, 0), I.star(300, 299),
+        I.grid(13, 29, 0.0, seed=1), I.grid(31, 37, 0.3, seed=2), I.grid_permuted(64, seed=1),
+        I.road_mesh(96, 0.15, 0.01, seed=2), I.rmat_lcc(11, 16, seed=3),
+        I.long_chain(3000, 0.005, 64, seed=4, offset_bytes=8),
+    ]
+    for s in range(4):
+        gs.append(I.random_graph(1000 + 97 * s, 800, seed=s, connected=False))
+        gs.append(I.random_graph(1500 + 13 * s, 4000, seed=50 + s, connected=True))
+        gs.append(I.random_tree(2000 + 31 * s, seed=s))
+    # isolated vertices only, self-loops and duplicate arcs
+    gs.append(I.csr_from_edges(700, np.zeros(0, np.int32), np.zeros(0, np.int32), name="empty"))
+    eu = np.array([0, 0, 1, 1, 2, 3, 3, 5], np.int32)
+    ev = np.array([0, 1, 1, 2, 2, 4, 4, 5], np.int32)
+    g = I.csr_from_edges(6, eu, ev, name="loops")
+    # re-add duplicates/self-loops the builder removed (the library must tolerate them)
+    cols = np.concatenate([g.cols, np.array([1, 0, 5], np.int32)])
+    deg = np.diff(g.offsets)
+    src = np.concatenate([np.repeat(np.arange(6), deg), np.array([0, 1, 5])])
+    order = np.argsort(src, kind="stable")
+    off = np.zeros(7, np.int64)
+    np.add.at(off, src + 1, 1)
+    gs.append(I.Graph("dups", 6, np.cumsum(off), cols[order]))
+    return gs
+
+
+SMALL = small_graphs()
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)))
+def test_components_bit_exact(ctx, gi):
+    g = SMALL[gi]
+    off, cols = upload(g)
+    label, k = ctx.components(off, cols)
+    k_ref, lab_ref = oracle.components(g.n, g.offsets, g.cols)
+    assert k == k_ref
+    assert np.array_equal(label.cpu().numpy(), lab_ref)
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)))
+def test_spanning_forest_edges(ctx, gi):
+    g = SMALL[gi]
+    off, cols = upload(g)
+    label, tu, tv, t = ctx.spanning_forest(off, cols)
+    label, tu, tv = label.cpu().numpy(), tu.cpu().numpy(), tv.cpu().numpy()
+    k_ref, lab_ref = oracle.components(g.n, g.offsets, g.cols)
+    assert np.array_equal(label, lab_ref)
+    used = tu >= 0
+    assert t == g.n - k_ref == int(used.sum())
+    # slots that stayed roots are exactly the component labels
+    assert np.array_equal(np.nonzero(~used)[0], np.unique(lab_ref))
+    fu, fv = tu[used], tv[used]
+    for a, b in zip(fu[:5000], fv[:5000]):
+        assert b in g.cols[g.offsets[a]:g.offsets[a + 1]]
+    # n - c edges whose components equal G's components form a spanning forest
+    f = I.csr_from_edges(g.n, fu, fv)
+    assert f.m == t
+    k_f, lab_f = oracle.components(g.n, f.offsets, f.cols)
+    assert k_f == k_ref and np.array_equal(lab_f, lab_ref)
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)))
+def test_root_forest_bit_exact(ctx, gi):
+    g = SMALL[gi]
+    label, fu, fv = oracle.uf_forest(g.n, g.offsets, g.cols)
+    rs = np.random.RandomState(gi)
+    comps = np.unique(label)
+    roots = [int(rs.choice(np.nonzero(label == c)[0])) for c in comps[: max(1, len(comps) // 2)]]
+    exp = oracle.dfs_root(g.n, fu, fv, roots)
+    par = ctx.root_forest(g.n, dev(fu), dev(fv), dev(np.array(roots, np.int32)))
+    assert np.array_equal(par.cpu().numpy(), exp)
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)))
+def test_spanning_tree_gconn_verified(ctx, gi):
+    g = SMALL[gi]
+    off, cols = upload(g)
+    for root in sorted({0, g.n // 2, g.n - 1}):
+        par = ctx.spanning_tree(off, cols, root, "gconn").cpu().numpy()
+        k, _ = oracle.components(g.n, g.offsets, g.cols)
+        assert ctx.last_status == (0 if k == 1 else -4)
+        code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, par, [root])
+        assert code == 0, (oracle.VERIFY_CODES[code], bad)
+        if g.m == g.n - 1 and k == 1:      # a tree: the RST is unique
+            _, p_bfs, _ = oracle.bfs(g.n, g.offsets, g.cols, root)
+            assert np.array_equal(par, p_bfs)
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)))
+def test_bfs_levels_bit_exact(ctx, gi):
+    g = SMALL[gi]
+    off, cols = upload(g)
+    root = g.n // 3
+    level, parent, st = ctx.bfs(off, cols, root, stats=True)
+    level, parent = level.cpu().numpy(), parent.cpu().numpy()
+    lref, _, ecc = oracle.bfs(g.n, g.offsets, g.cols, root)
+    assert np.array_equal(level, lref)
+    assert st["bfs_levels"] == ecc
+    reach = lref >= 0
+    assert np.all(parent[~reach] == -1)
+    assert parent[root] == root
+    v = np.nonzero(reach)[0]
+    v = v[v != root]
+    assert np.all(lref[parent[v]] == lref[v] - 1)
+    for x in v[:3000]:
+        assert parent[x] in g.cols[g.offsets[x]:g.offsets[x + 1]]
+
+
+@pytest.mark.parametrize("gi", range(len(SMALL)))
+def test_spanning_tree_bfs_verified(ctx, gi):
+    g = SMALL[gi]
+    off, cols = upload(g)
+    par = ctx.spanning_tree(off, cols, 0, "bfs").cpu().numpy()
+    code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, par, [0])
+    assert code == 0, (oracle.VERIFY_CODES[code], bad)
+
+
+def test_list_rank_bit_exact(ctx):
+    rs = np.random.RandomState(1)
+    for A in (1, 2, 255, 256, 257, 4097, 100003):
+        order = rs.permutation(A)
+        cuts = np.sort(rs.choice(np.arange(1, A), size=min(A - 1, 37), replace=False)) \
+            if A > 1 else np.array([], int)
+        succ = np.full(A, -1, np.int32)
+        for piece in np.split(order, cuts):
+            succ[piece[:-1]] = piece[1:]
+        exp, _ = oracle.list_rank(succ)
+        got = ctx.list_rank(dev(succ)).cpu().numpy()
+        assert np.array_equal(got, exp)
+
+
+def test_heavy_hub_paths(ctx):
+    """A star whose centre exceeds the heavy-degree threshold many times over."""
+    g = I.star(200001, 7)
+    off, cols = upload(g)
+    for method in ("gconn", "bfs"):
+        par = ctx.spanning_tree(off, cols, 7, method).cpu().numpy()
+        assert np.all(par == 7)
+    par = ctx.spanning_tree(off, cols, 3, "gconn").cpu().numpy()
+    assert par[3] == 3 and par[7] == 3 and np.all(np.delete(par, [3, 7]) == 7)
+
+
+def test_invalid_arguments(ctx):
+    import paper_2603_11645_amd as rst
+    g = I.path(10)
+    off, cols = upload(g)
+    with pytest.raises(rst.RstError):
+        ctx.spanning_tree(off, cols, 10)
+    with pytest.raises(rst.RstError):
+        ctx.spanning_tree(off, cols, -1)
+    # two designated roots in one tree
+    label, fu, fv = oracle.uf_forest(g.n, g.offsets, g.cols)
+    with pytest.raises(rst.RstError):
+        ctx.root_forest(g.n, dev(fu), dev(fv), dev(np.array([0, 5], np.int32)))
+    # out-of-range neighbour id caught by validation
+    bad = g.cols.copy(); bad[3] = 99
+    ctx.set_option(rst.OPT_VALIDATE, 1)
+    try:
+        with pytest.raises(rst.RstError) as ei:
+            ctx.spanning_tree(off, dev(bad), 0)
+        assert ei.value.code == rst.RST_E_RANGE
+    finally:
+        ctx.set_option(rst.OPT_VALIDATE, 0)
+
+
+def test_tunables_do_not_change_results(ctx):
+    import paper_2603_11645_amd as rst
+    g = I.rmat_lcc(12, 16, seed=5)
+    off, cols = upload(g)
+    lref, _, _ = oracle.bfs(g.n, g.offsets, g.cols, 0)
+    for ept in (1, 2, 4, 8):
+        for heavy in (32, 1024):
+            ctx.set_option(rst.OPT_RANK_ELEMS_PER_THREAD, ept)
+            ctx.set_option(rst.OPT_HEAVY_DEGREE, heavy)
+            ctx.set_option(rst.OPT_BFS_LEVELS_PER_SYNC, 3)
+            ctx.set_option(rst.OPT_BFS_GRID, 7)
+            par = ctx.spanning_tree(off, cols, 0, "gconn").cpu().numpy()
+            assert oracle.verify_rst(g.n, g.offsets, g.cols, par, [0])[0] == 0
+            level, _ = ctx.bfs(off, cols, 0)
+            assert np.array_equal(level.cpu().numpy(), lref)
+    ctx.set_option(rst.OPT_RANK_ELEMS_PER_THREAD, 4)
+    ctx.set_option(rst.OPT_HEAVY_DEGREE, 1024)
+    ctx.set_option(rst.OPT_BFS_LEVELS_PER_SYNC, 32)
+    ctx.set_option(rst.OPT_BFS_GRID, 0)
