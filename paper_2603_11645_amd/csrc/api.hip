@@ -65,6 +65,27 @@ static inline rst_status mark(rst_ctx *ctx, rst_stats *st, int i) {
   return RST_OK;
 }
 
+static size_t rank_ws_bytes(int64_t A) {
+  return ws_bytes(rank_exit_capacity(A), 4) + ws_bytes(rank_exit_capacity(A), 8) +
+         ws_bytes(rank_tile_count(A), 4) + ws_bytes(rank_tile_count(A) + 1, 8);
+}
+
+struct RankBufs {
+  int32_t *exits;
+  uint64_t *crank;
+  int32_t *tile_exits;
+  int64_t *tile_base;
+};
+
+static RankBufs take_rank_bufs(rst_ctx *ctx, int64_t A) {
+  RankBufs r;
+  r.exits = ws_take<int32_t>(ctx, rank_exit_capacity(A));
+  r.crank = ws_take<uint64_t>(ctx, rank_exit_capacity(A));
+  r.tile_exits = ws_take<int32_t>(ctx, rank_tile_count(A));
+  r.tile_base = ws_take<int64_t>(ctx, rank_tile_count(A) + 1);
+  return r;
+}
+
 // GConn + Euler over the whole CSR.  roots: device list (one per component at
 // most).  Writes parent, returns the component count in *components.
 rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
@@ -82,9 +103,12 @@ rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
   int32_t *next = ws_take<int32_t>(ctx, 2 * n);
   uint64_t *rank = ws_take<uint64_t>(ctx, 2 * n);
   int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
+  int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
+  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_count(g->n));
+  RankBufs rb = take_rank_bufs(ctx, 2 * n);
 
   RST_TRY(mark(ctx, st, 0));
-  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap));
+  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
   RST_TRY(mark(ctx, st, 1));
   RST_TRY(enqueue_compress(ctx, n, f.cc, f.comp_root, head));
   RST_TRY(mark(ctx, st, 2));
@@ -93,8 +117,11 @@ rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
   RST_TRY(mark(ctx, st, 3));
   RST_TRY(enqueue_succ(ctx, n, f.tu, f.tv, head, next, f.cc, f.comp_root, rank));
   RST_TRY(mark(ctx, st, 4));
-  const int rounds = rank_rounds_for(2 * n);
-  RST_TRY(enqueue_rank_rounds(ctx, 2 * n, rank, rounds, nullptr, nullptr));
+  int rounds = 0;
+  int64_t exits_n = 0;
+  // next[] is dead after the successor pass: it holds the exit indices
+  RST_TRY(enqueue_rank_tiled(ctx, 2 * n, rank, next, rb.exits, rb.crank, rb.tile_exits,
+                             rb.tile_base, &exits_n, &rounds));
   RST_TRY(mark(ctx, st, 5));
   RST_TRY(enqueue_parent(ctx, n, n, f.tu, f.tv, rank, f.cc, f.comp_root, parent, counters));
   RST_TRY(mark(ctx, st, 6));
@@ -129,10 +156,15 @@ static size_t bfs_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
   return 2 * ws_bytes(g->n, 4) + 2 * ws_bytes(hc, 4) + ws_bytes(8, 4);
 }
 
+static size_t hook_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
+  return ws_bytes(hook_chunk_capacity(ctx, g->nnz), 8) + ws_bytes(hook_cross_capacity(g->nnz), 8) +
+         ws_bytes(hook_tile_count(g->n), 4);
+}
+
 static size_t gconn_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
   const size_t n = (size_t)g->n;
-  return 5 * ws_bytes(n, 4) + ws_bytes(2 * n, 4) + ws_bytes(2 * n, 8) +
-         ws_bytes(hook_chunk_capacity(ctx, g->nnz), 8);
+  return 5 * ws_bytes(n, 4) + ws_bytes(2 * n, 4) + ws_bytes(2 * n, 8) + hook_ws_bytes(ctx, g) +
+         rank_ws_bytes(2 * g->n);
 }
 
 }  // namespace rst
@@ -257,7 +289,9 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
     f.tv = ws_take<int32_t>(ctx, g->n);
     const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
     int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
-    RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap));
+    int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
+  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_count(g->n));
+    RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
     RST_TRY(enqueue_compress(ctx, g->n, f.cc, nullptr, nullptr));
     RST_TRY(enqueue_count_roots(ctx, g->n, f.cc, counters));
     RST_TRY(bfs_seed_unreached(ctx, g, f.cc, level, parent, b, counters));
@@ -285,7 +319,7 @@ rst_status rst_components(rst_ctx *ctx, const rst_csr *g, int32_t *label,
   RST_TRY(check_csr(g));
   RST_HIP(hipSetDevice(ctx->device));
   const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
-  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 2 * ws_bytes(g->n, 4) + ws_bytes(chunk_cap, 8)));
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 2 * ws_bytes(g->n, 4) + hook_ws_bytes(ctx, g)));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(run_validation(ctx, g, counters));
@@ -295,7 +329,9 @@ rst_status rst_components(rst_ctx *ctx, const rst_csr *g, int32_t *label,
   f.tu = ws_take<int32_t>(ctx, g->n);
   f.tv = ws_take<int32_t>(ctx, g->n);
   int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
-  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap));
+  int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
+  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_count(g->n));
+  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
   RST_TRY(enqueue_compress(ctx, g->n, label, nullptr, nullptr));
   RST_TRY(enqueue_count_roots(ctx, g->n, label, counters));
   RST_TRY(read_counters(ctx, counters));
@@ -309,7 +345,7 @@ rst_status rst_spanning_forest(rst_ctx *ctx, const rst_csr *g, int32_t *label, i
   RST_TRY(check_csr(g));
   RST_HIP(hipSetDevice(ctx->device));
   const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
-  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + ws_bytes(chunk_cap, 8)));
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + hook_ws_bytes(ctx, g)));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(run_validation(ctx, g, counters));
@@ -319,7 +355,9 @@ rst_status rst_spanning_forest(rst_ctx *ctx, const rst_csr *g, int32_t *label, i
   f.tu = tu;
   f.tv = tv;
   int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
-  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap));
+  int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
+  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_count(g->n));
+  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
   RST_TRY(enqueue_compress(ctx, g->n, label, nullptr, nullptr));
   RST_TRY(enqueue_count_roots(ctx, g->n, label, counters));
   RST_TRY(read_counters(ctx, counters));
@@ -367,13 +405,14 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
   if (n >= ((int64_t)1 << 30)) return RST_E_INVAL;
   RST_HIP(hipSetDevice(ctx->device));
   RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 3 * ws_bytes(n, 4) + ws_bytes(2 * t + 2, 4) +
-                              ws_bytes(2 * t + 2, 8)));
+                              ws_bytes(2 * t + 2, 8) + rank_ws_bytes(2 * t)));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
   int32_t *cc = ws_take<int32_t>(ctx, n);
   int32_t *comp_root = ws_take<int32_t>(ctx, n);
   int32_t *head = ws_take<int32_t>(ctx, n);
   int32_t *next = ws_take<int32_t>(ctx, 2 * t + 2);
   uint64_t *rank = ws_take<uint64_t>(ctx, 2 * t + 2);
+  RankBufs rb = take_rank_bufs(ctx, 2 * t);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(enqueue_hook_coo(ctx, n, t, eu, ev, cc, counters));
   RST_TRY(enqueue_compress(ctx, n, cc, comp_root, head));
@@ -382,7 +421,8 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
   RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, cc, comp_root, parent, counters));
   RST_TRY(enqueue_link(ctx, t, eu, ev, head, next));
   RST_TRY(enqueue_succ(ctx, t, eu, ev, head, next, cc, comp_root, rank));
-  RST_TRY(enqueue_rank_rounds(ctx, 2 * t, rank, rank_rounds_for(2 * t), nullptr, nullptr));
+  RST_TRY(enqueue_rank_tiled(ctx, 2 * t, rank, next, rb.exits, rb.crank, rb.tile_exits,
+                             rb.tile_base, nullptr, nullptr));
   RST_TRY(enqueue_parent(ctx, t, n, eu, ev, rank, cc, comp_root, parent, counters));
   RST_TRY(read_counters(ctx, counters));
   if (ctx->host_pinned[kCntRangeErr] || ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
@@ -394,10 +434,15 @@ rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *
   if (A >= ((int64_t)1 << 31)) return RST_E_INVAL;
   if (A == 0) return RST_OK;
   RST_HIP(hipSetDevice(ctx->device));
-  RST_TRY(ws_reserve(ctx, ws_bytes(A, 8)));
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + ws_bytes(A, 8) + ws_bytes(A, 4) + rank_ws_bytes(A)));
+  int32_t *counters = ws_take<int32_t>(ctx, 64);
   uint64_t *rank = ws_take<uint64_t>(ctx, A);
+  int32_t *xid = ws_take<int32_t>(ctx, A);
+  RankBufs rb = take_rank_bufs(ctx, A);
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(enqueue_rank_init(ctx, A, succ, rank));
-  RST_TRY(enqueue_rank_rounds(ctx, A, rank, rank_rounds_for(A), nullptr, nullptr));
+  RST_TRY(enqueue_rank_tiled(ctx, A, rank, xid, rb.exits, rb.crank, rb.tile_exits, rb.tile_base,
+                             nullptr, nullptr));
   RST_TRY(enqueue_rank_extract(ctx, A, rank, dist));
   RST_HIP(hipStreamSynchronize(ctx->stream));
   return RST_OK;

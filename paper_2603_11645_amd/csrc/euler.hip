@@ -137,6 +137,279 @@ __global__ __launch_bounds__(kBlock) void k_rank_round(int64_t A, uint64_t *rank
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tiled list ranking.  Arcs are cut into tiles of kRankTile consecutive ids.
+// Inside a tile the list splits into segments (maximal runs whose successor
+// stays in the tile); a workgroup ranks its tile's segments by pointer jumping
+// in LDS, so each arc learns the last arc of its segment (its "exit") and the
+// hops to it.  Only the exits -- arcs whose successor leaves the tile, and
+// list tails -- form the contracted list, which is ranked by Wyllie rounds;
+// a final pass adds each arc's in-tile hops to its exit's contracted distance.
+// When arc ids follow the tour's geometry (tiles of the hooking stage line up
+// with tiles of arcs) almost every successor stays in its tile and the global
+// pointer-jumping traffic shrinks by orders of magnitude; without locality the
+// contracted list is about as long as the input and the cost is that of plain
+// Wyllie plus two streaming passes.
+//
+// Word encoding after the tile pass: a non-exit arc e holds (exit of e, hops
+// to it), whose first half lies in e's own tile; an exit keeps (successor, 1)
+// with the successor outside the tile, or (-1, 0) at a list tail.
+// ---------------------------------------------------------------------------
+constexpr int kRankTile = 16384;
+constexpr int kRankThreads = 1024;
+constexpr int kRankPer = kRankTile / kRankThreads;
+constexpr int kRuler = 16;                           // every 16th arc is a ruler
+constexpr int kRulerSlots = 2048;                    // strided rulers + extra segment heads
+constexpr int kStrided = kRankTile / kRuler;
+
+__device__ __forceinline__ bool in_tile(int32_t id, int64_t e) {
+  return id >= 0 && ((int64_t)id / kRankTile) == (e / kRankTile);
+}
+
+// Within a tile: every segment head and every 16th arc is a ruler.  Each ruler
+// walks its piece of list (to the next ruler or the segment's exit) in LDS;
+// the rulers are then ranked by pointer jumping over at most 2048 slots, and a
+// second walk writes (exit, hops to exit) for every arc.  Total LDS work is two
+// linear passes; the walks are short because rulers are dense.  A tile with
+// more segment heads than ruler slots (no locality) is ranked by plain pointer
+// jumping in LDS instead.
+__global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t *rank, int32_t *xid,
+                                                            int32_t *exits, int32_t *tile_exits) {
+  __shared__ int16_t ls[kRankTile];                  // local successor, -1 at an exit
+  __shared__ __align__(16) unsigned char region[kRankTile * 2];   // flags+rulers, or hop counts
+  __shared__ int s_extra;
+  __shared__ int s_nexit;
+  uint8_t *haspred = region;                                        // [kRankTile]
+  int16_t *r_start = reinterpret_cast<int16_t *>(region + kRankTile);   // [kRulerSlots]
+  int16_t *r_next = r_start + kRulerSlots;
+  uint16_t *r_len = reinterpret_cast<uint16_t *>(r_next + kRulerSlots);
+  int16_t *r_exit = reinterpret_cast<int16_t *>(r_len + kRulerSlots);
+  uint16_t *dd = reinterpret_cast<uint16_t *>(region);             // fallback: [kRankTile]
+
+  const int tid = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * kRankTile;
+  const int cnt = (int)((A - e0) < kRankTile ? (A - e0) : kRankTile);
+  if (tid == 0) { s_extra = 0; s_nexit = 0; }
+  // issue every load of the tile before any dependent work
+  uint64_t w[kRankPer];
+#pragma unroll
+  for (int j = 0; j < kRankPer; ++j) {
+    const int i = tid + j * kRankThreads;
+    w[j] = i < cnt ? rank[e0 + i] : 0ull;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kRankPer; ++j) {
+    const int i = tid + j * kRankThreads;
+    bool is_exit = false;
+    haspred[i] = 0;
+    if (i < cnt) {
+      const int32_t sc = (int32_t)(uint32_t)w[j];
+      const int64_t sl = (int64_t)sc - e0;
+      if (sc >= 0 && sl >= 0 && sl < cnt) {
+        ls[i] = (int16_t)sl;
+      } else {
+        ls[i] = -1;
+        is_exit = true;
+      }
+    }
+    // exits of tile b go to exits[b*kRankTile + k], k from an LDS counter
+    const int slot = wave_append(is_exit, &s_nexit);
+    if (is_exit) exits[e0 + slot] = (int32_t)(e0 + i);
+    if (i < cnt) xid[e0 + i] = is_exit ? slot : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kRankPer; ++j) {
+    const int i = tid + j * kRankThreads;
+    if (i < cnt && ls[i] >= 0) haspred[ls[i]] = 1;
+  }
+  __syncthreads();
+  // strided rulers own slots 0..kStrided-1; heads off the stride get extra slots
+  for (int q = tid; q < kStrided; q += kRankThreads) r_start[q] = (int16_t)(q * kRuler);
+#pragma unroll
+  for (int j = 0; j < kRankPer; ++j) {
+    const int i = tid + j * kRankThreads;
+    if (i < cnt && (i % kRuler) != 0 && !haspred[i]) {
+      const int x = atomicAdd(&s_extra, 1);
+      if (kStrided + x < kRulerSlots) r_start[kStrided + x] = (int16_t)i;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) tile_exits[blockIdx.x] = s_nexit;
+  const int extra = s_extra;
+  if (kStrided + extra <= kRulerSlots) {
+    const int nslots = kStrided + extra;
+    // walk 1: hops to the next ruler, or to the exit
+    for (int q = tid; q < nslots; q += kRankThreads) {
+      int j = r_start[q];
+      int nx = -1, len = 0, ex = -1;
+      if (j < cnt) {
+        for (;;) {
+          const int sj = ls[j];
+          if (sj < 0) { ex = j; break; }
+          j = sj;
+          ++len;
+          if ((j % kRuler) == 0) { nx = j / kRuler; break; }
+          if (len > cnt) { ex = j; break; }      // only on a cycle (malformed input)
+        }
+      }
+      r_next[q] = (int16_t)nx;
+      r_len[q] = (uint16_t)len;
+      r_exit[q] = (int16_t)(ex < 0 ? 0 : ex);
+    }
+    __syncthreads();
+    // pointer jumping over the rulers
+    for (int round = 0; round < 12; ++round) {
+      int16_t nn[2], ne[2];
+      uint16_t nl[2];
+      bool changed = false;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int q = tid + k * kRankThreads;
+        if (q < nslots) {
+          const int x = r_next[q];
+          nn[k] = (int16_t)x; nl[k] = r_len[q]; ne[k] = r_exit[q];
+          if (x >= 0) {
+            nn[k] = r_next[x];
+            nl[k] = (uint16_t)(r_len[q] + r_len[x]);
+            ne[k] = r_exit[x];
+            changed = true;
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int q = tid + k * kRankThreads;
+        if (q < nslots) { r_next[q] = nn[k]; r_len[q] = nl[k]; r_exit[q] = ne[k]; }
+      }
+      if (!__syncthreads_or(changed)) break;
+    }
+    // walk 2: every non-exit arc gets (exit, hops to exit)
+    for (int q = tid; q < nslots; q += kRankThreads) {
+      int j = r_start[q];
+      if (j >= cnt) continue;
+      const int total = r_len[q];
+      const int32_t exg = (int32_t)(e0 + r_exit[q]);
+      for (int k = 0; k <= cnt; ++k) {
+        const int sj = ls[j];
+        if (sj < 0) break;
+        rank[e0 + j] = pack_rank(exg, (uint32_t)(total - k));
+        j = sj;
+        if ((j % kRuler) == 0) break;
+      }
+    }
+    return;
+  }
+  // fallback: pointer jumping over all arcs of the tile (ls as pointers, dd as hops)
+#pragma unroll
+  for (int j = 0; j < kRankPer; ++j) {
+    const int i = tid + j * kRankThreads;
+    if (i < cnt) {
+      const int sj = ls[i];
+      dd[i] = sj < 0 ? 0 : 1;
+      ls[i] = (int16_t)(sj < 0 ? i : sj);
+    }
+  }
+  __syncthreads();
+  for (int round = 0; round < 15; ++round) {
+    int16_t np[kRankPer];
+    uint16_t nd[kRankPer];
+    bool changed = false;
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {
+      const int i = tid + j * kRankThreads;
+      if (i < cnt) {
+        const int q = ls[i];
+        np[j] = ls[q];
+        nd[j] = (uint16_t)(dd[i] + dd[q]);
+        changed |= (np[j] != q);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {
+      const int i = tid + j * kRankThreads;
+      if (i < cnt) { ls[i] = np[j]; dd[i] = nd[j]; }
+    }
+    if (!__syncthreads_or(changed)) break;
+  }
+#pragma unroll
+  for (int j = 0; j < kRankPer; ++j) {
+    const int i = tid + j * kRankThreads;
+    if (i < cnt && ls[i] != i) rank[e0 + i] = pack_rank((int32_t)(e0 + ls[i]), dd[i]);
+  }
+}
+
+// Exclusive scan of the per-tile exit counts (one block): base[b], base[tiles] = M.
+__global__ __launch_bounds__(1024) void k_tile_scan(const int32_t *__restrict__ cnt, int64_t tiles,
+                                                    int64_t *base) {
+  __shared__ int s_wave[1024 / kWave];
+  __shared__ int64_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < tiles; b0 += 1024) {
+    const int64_t b = b0 + threadIdx.x;
+    const int x = b < tiles ? cnt[b] : 0;
+    int total;
+    const int excl = block_excl_scan<1024>(x, s_wave, &total);
+    if (b < tiles) base[b] = s_carry + excl;
+    __syncthreads();
+    if (threadIdx.x == 0) s_carry += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) base[tiles] = s_carry;
+}
+
+__device__ __forceinline__ int64_t exit_index(int32_t ex, const int32_t *xid, const int64_t *base) {
+  return base[ex / kRankTile] + xid[ex];
+}
+
+// Contracted list over the exits (one block per tile): next exit and weighted
+// hops to it.
+__global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restrict__ exits,
+                                                          const int32_t *__restrict__ tile_exits,
+                                                          const int64_t *__restrict__ base,
+                                                          const uint64_t *__restrict__ rank,
+                                                          const int32_t *__restrict__ xid,
+                                                          uint64_t *crank) {
+  const int64_t e0 = (int64_t)blockIdx.x * kRankTile;
+  const int cntb = tile_exits[blockIdx.x];
+  const int64_t b0 = base[blockIdx.x];
+  for (int j = threadIdx.x; j < cntb; j += kBlock) {
+    const int32_t x = exits[e0 + j];
+    const int32_t s = (int32_t)(uint32_t)rank[x];
+    if (s < 0) {
+      crank[b0 + j] = pack_rank(-1, 0);
+      continue;
+    }
+    const uint64_t ws = rank[s];
+    const int32_t id = (int32_t)(uint32_t)ws;
+    int32_t ex = s;
+    uint32_t dl = 0;
+    if (in_tile(id, s)) { ex = id; dl = (uint32_t)(ws >> 32); }
+    crank[b0 + j] = pack_rank((int32_t)exit_index(ex, xid, base), 1u + dl);
+  }
+}
+
+// dist[e] = hops to its exit + contracted distance of that exit, stored as (-1, dist)
+__global__ __launch_bounds__(kBlock) void k_rank_expand(int64_t A, uint64_t *rank,
+                                                        const int32_t *__restrict__ xid,
+                                                        const int64_t *__restrict__ base,
+                                                        const uint64_t *__restrict__ crank) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= A) return;
+  const uint64_t w = rank[e];
+  const int32_t id = (int32_t)(uint32_t)w;
+  uint32_t dist;
+  if (in_tile(id, e))
+    dist = (uint32_t)(w >> 32) + (uint32_t)(crank[exit_index(id, xid, base)] >> 32);
+  else
+    dist = (uint32_t)(crank[exit_index((int32_t)e, xid, base)] >> 32);
+  rank[e] = pack_rank(-1, dist);
+}
+
 __global__ __launch_bounds__(kBlock) void k_rank_extract(int64_t A, const uint64_t *__restrict__ rank,
                                                          int32_t *dist) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -239,6 +512,40 @@ rst_status enqueue_rank_rounds(rst_ctx *ctx, int64_t A, uint64_t *rank, int roun
     }
   }
   if (ev_end) RST_HIP(hipEventRecord(ev_end, ctx->stream));
+  return RST_OK;
+}
+
+size_t rank_exit_capacity(int64_t A) { return (size_t)(A + 1); }
+size_t rank_tile_count(int64_t A) { return (size_t)((A + kRankTile - 1) / kRankTile); }
+
+rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *xid,
+                              int32_t *exits, uint64_t *crank, int32_t *tile_exits,
+                              int64_t *tile_base, int64_t *exits_out, int *rounds_out) {
+  if (rounds_out) *rounds_out = 0;
+  if (exits_out) *exits_out = 0;
+  if (A <= 0) return RST_OK;
+  const int64_t tiles = (int64_t)rank_tile_count(A);
+  hipLaunchKernelGGL(k_rank_tile, dim3((unsigned)tiles), dim3(kRankThreads), 0, ctx->stream, A,
+                     rank, xid, exits, tile_exits);
+  RST_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, ctx->stream, tile_exits, tiles, tile_base);
+  RST_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_rank_contract, dim3((unsigned)tiles), dim3(kBlock), 0, ctx->stream, exits,
+                     tile_exits, tile_base, rank, xid, crank);
+  RST_HIP(hipGetLastError());
+  int64_t *hb = reinterpret_cast<int64_t *>(ctx->host_pinned + 48);
+  RST_HIP(hipMemcpyAsync(hb, tile_base + tiles, sizeof(int64_t), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  int64_t M = *hb;
+  if (M < 0 || M > A) M = A;
+  const int rounds = rank_rounds_for(M);
+  RST_TRY(enqueue_rank_rounds(ctx, M, crank, rounds, nullptr, nullptr));
+  hipLaunchKernelGGL(k_rank_expand, dim3(grid_for(A, kBlock)), dim3(kBlock), 0, ctx->stream, A,
+                     rank, xid, tile_base, crank);
+  RST_HIP(hipGetLastError());
+  if (rounds_out) *rounds_out = rounds;
+  if (exits_out) *exits_out = M;
   return RST_OK;
 }
 

@@ -95,56 +95,209 @@ __global__ void k_iota(int32_t *p, int64_t count) {
   if (i < count) p[i] = (int32_t)i;
 }
 
-// cc[v] = v, tu[v] = tv[v] = -1
-__global__ __launch_bounds__(kBlock) void k_hook_init(int64_t n, int32_t *cc, int32_t *tu,
-                                                      int32_t *tv) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) {
-    cc[v] = (int32_t)v;
-    tu[v] = -1;
-    tv[v] = -1;
+// ---------------------------------------------------------------------------
+// Tile phase.  One workgroup owns a tile of kTile consecutive vertex ids and
+// runs union-find for the edges with both endpoints in the tile entirely in
+// LDS, where compare-and-swap is cheap and coherent.  On graphs whose ids
+// follow geometry (meshes, road networks) most edges are tile-internal, so
+// global compare-and-swap traffic shrinks to the edges that cross tiles; those
+// are appended to a list for the cross phase.  Vertices above the heavy degree
+// are left to the chunked heavy pass.
+//
+// Inside the tile the hooking order is a fixed pseudo-random priority (a
+// bijective hash of the vertex id, Sec. III-B allows any priority that avoids
+// cycles): the root of lower priority is linked under the other.  Id-ordered
+// hooking on a row-major mesh would build 2048-long chains that every find has
+// to walk; random priorities keep trees shallow.  Afterwards every local tree
+// is re-rooted at its minimum id (the edge stored at that vertex moves to the
+// slot of the old root, so the set of recorded edges is unchanged) and every
+// vertex points straight at that minimum: the invariant cc[x] <= x the cross
+// phase relies on holds again.
+// ---------------------------------------------------------------------------
+constexpr int kTile = 8192;        // vertices per tile
+constexpr int kTileShift = 13;
+constexpr int kTileThreads = 1024;
+constexpr int kTilePer = kTile / kTileThreads;
+
+__device__ __forceinline__ uint32_t hook_priority(uint32_t x) {
+  x *= 0x9E3779B1u;
+  x ^= x >> 15;
+  x *= 0x85EBCA77u;
+  x ^= x >> 13;
+  return x;   // a bijection of 32-bit values: distinct vertices never tie
+}
+
+__device__ __forceinline__ int lds_find(int x, int *lp) {
+  int p = lp[x];
+  while (p != x) {
+    const int gp = lp[p];
+    lp[x] = gp;          // path halving: x now skips to its grandparent
+    x = p;
+    p = gp;
+  }
+  return x;
+}
+
+// Cross-tile edges of tile b are written to cross[off[b*kTile] + k], a region
+// as long as the tile's arc range, and counted in tile_cross[b]: no global
+// atomics, no compaction.
+template <class OffT>
+__global__ __launch_bounds__(kTileThreads) void k_hook_tile(
+    int64_t n, const OffT *__restrict__ off, const int32_t *__restrict__ cols, int32_t *cc,
+    int32_t *tu, int32_t *tv, int2 *cross, int32_t *tile_cross, int32_t *counters,
+    int64_t *chunks, int64_t chunk_cap, int heavy_deg) {
+  __shared__ int lp[kTile];
+  __shared__ int16_t eu[kTile];     // local endpoints of the edge held by a slot (-1: none)
+  __shared__ int16_t ev[kTile];
+  __shared__ int s_scan[kTileThreads + 1];
+  __shared__ OffT s_beg[kTileThreads];
+  __shared__ int s_wave[kTileThreads / kWave];
+  __shared__ int s_ncross;
+  const int tid = threadIdx.x;
+  const int64_t v0 = (int64_t)blockIdx.x * kTile;
+  const int cnt = (int)((n - v0) < kTile ? (n - v0) : kTile);
+  const int64_t region = (int64_t)off[v0];
+  for (int i = tid; i < kTile; i += kTileThreads) { lp[i] = i; eu[i] = -1; ev[i] = -1; }
+  if (tid == 0) s_ncross = 0;
+  __syncthreads();
+  for (int c = 0; c < cnt; c += kTileThreads) {
+    const int li = c + tid;
+    int deg = 0;
+    OffT beg = 0;
+    if (li < cnt) {
+      const int64_t v = v0 + li;
+      beg = off[v];
+      const int64_t d = (int64_t)(off[v + 1] - beg);
+      if (d > heavy_deg) {
+        const int64_t nc = (d + kChunk - 1) / kChunk;
+        const int64_t base = atomicAdd(&counters[kCntChunks], (int)nc);
+        for (int64_t k = 0; k < nc && base + k < chunk_cap; ++k) chunks[base + k] = (v << 32) | k;
+      } else {
+        deg = (int)d;
+      }
+    }
+    s_beg[tid] = beg;
+    int total;
+    const int excl = block_excl_scan<kTileThreads>(deg, s_wave, &total);
+    s_scan[tid] = excl;
+    if (tid == kTileThreads - 1) s_scan[kTileThreads] = excl + deg;
+    __syncthreads();
+    constexpr int U = 4;   // arcs in flight per thread: loads issued before any hooking
+    for (int b = 0; b < total; b += kTileThreads * U) {
+      int sl[U];
+      int32_t dst[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = b + u * kTileThreads + tid;
+        sl[u] = -1;
+        dst[u] = 0;
+        if (k < total) {
+          const int j = lds_upper_search(s_scan, kTileThreads, k);
+          sl[u] = c + j;
+          dst[u] = cols[(int64_t)s_beg[j] + (k - s_scan[j])];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        bool is_cross = false;
+        if (sl[u] >= 0) {
+          const int64_t dl = (int64_t)dst[u] - v0;
+          if (dl >= 0 && dl < sl[u]) {
+            int ra = lds_find(sl[u], lp), rb = lds_find((int)dl, lp);
+            while (ra != rb) {
+              const bool a_low =
+                  hook_priority((uint32_t)(v0 + ra)) < hook_priority((uint32_t)(v0 + rb));
+              const int lo = a_low ? ra : rb, hi = a_low ? rb : ra;
+              const int old = atomicCAS(&lp[lo], lo, hi);
+              if (old == lo) {
+                eu[lo] = (int16_t)sl[u];
+                ev[lo] = (int16_t)dl;
+                break;
+              }
+              if (ra == lo) ra = lds_find(old, lp); else rb = lds_find(old, lp);
+            }
+          } else {
+            is_cross = dl < 0;   // dst < v0 <= src; the reverse arc is skipped
+          }
+        }
+        const int slot = wave_append(is_cross, &s_ncross);   // LDS counter
+        if (is_cross) cross[region + slot] = make_int2((int32_t)(v0 + sl[u]), dst[u]);
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) tile_cross[blockIdx.x] = s_ncross;
+  // flatten, then re-root every local tree at its minimum id.  Roots store
+  // -(min+1); members lift it with atomicMax on the negated value.
+  int r[kTilePer];
+#pragma unroll
+  for (int j = 0; j < kTilePer; ++j) {
+    const int i = tid + j * kTileThreads;
+    r[j] = i < cnt ? lds_find(i, lp) : i;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTilePer; ++j) {
+    const int i = tid + j * kTileThreads;
+    if (i < cnt) lp[i] = (r[j] == i) ? -(i + 1) : r[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTilePer; ++j) {
+    const int i = tid + j * kTileThreads;
+    if (i < cnt && r[j] != i) atomicMax(&lp[r[j]], -(i + 1));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTilePer; ++j) {
+    const int i = tid + j * kTileThreads;
+    if (i < cnt && r[j] == i) {
+      const int m = -lp[i] - 1;
+      if (m != i) {           // the old root takes the edge of the new one
+        eu[i] = eu[m];
+        ev[i] = ev[m];
+        eu[m] = -1;
+        ev[m] = -1;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTilePer; ++j) {
+    const int i = tid + j * kTileThreads;
+    if (i < cnt) {
+      const int m = -lp[r[j]] - 1;
+      cc[v0 + i] = (int32_t)(v0 + m);
+      const int a = eu[i];
+      tu[v0 + i] = a >= 0 ? (int32_t)(v0 + a) : -1;
+      tv[v0 + i] = a >= 0 ? (int32_t)(v0 + ev[i]) : -1;
+    }
   }
 }
 
-// One block = 256 consecutive vertices; each undirected edge is hooked once,
-// from its larger endpoint (arc v -> u with u < v).
+// Level of a cross edge in the binary tree over tiles: tiles 2g and 2g+1 of
+// level l (groups of 2^l tiles) meet at level l.  All edges inside a group
+// have a smaller level, so merging level by level keeps the id-ordered trees
+// of the cross phase at most one hop deeper per level.
+__device__ __forceinline__ int cross_level(int32_t s, int32_t t) {
+  return 31 - __clz((uint32_t)((s >> kTileShift) ^ (t >> kTileShift)));
+}
+
+// Cross phase, one level: every block walks the cross region of some tiles
+// and hooks the edges of this level (asynchronous id-ordered union-find).
 template <class OffT>
-__global__ __launch_bounds__(kBlock) void k_hook_light(int64_t n, const OffT *__restrict__ off,
-                                                       const int32_t *__restrict__ cols,
-                                                       int32_t *cc, int32_t *tu, int32_t *tv,
-                                                       int64_t *chunks, int64_t chunk_cap,
-                                                       int32_t *counters, int heavy_deg) {
-  __shared__ int s_scan[kBlock + 1];
-  __shared__ OffT s_beg[kBlock];
-  __shared__ int s_wave[kBlock / kWave];
-  const int t = threadIdx.x;
-  const int64_t v0 = (int64_t)blockIdx.x * kBlock;
-  const int64_t v = v0 + t;
-  int deg = 0;
-  OffT beg = 0;
-  if (v < n) {
-    beg = off[v];
-    const int64_t d = (int64_t)(off[v + 1] - beg);
-    if (d > heavy_deg) {
-      const int64_t nc = (d + kChunk - 1) / kChunk;
-      const int64_t base = atomicAdd(&counters[kCntChunks], (int)nc);
-      for (int64_t k = 0; k < nc && base + k < chunk_cap; ++k)
-        chunks[base + k] = (v << 32) | k;
-    } else {
-      deg = (int)d;
+__global__ __launch_bounds__(kBlock) void k_hook_cross(int64_t n, const OffT *__restrict__ off,
+                                                       const int2 *__restrict__ cross,
+                                                       const int32_t *__restrict__ tile_cross,
+                                                       int tiles, int level, int32_t *cc,
+                                                       int32_t *tu, int32_t *tv) {
+  for (int b = blockIdx.x; b < tiles; b += gridDim.x) {
+    const int64_t region = (int64_t)off[(int64_t)b * kTile];
+    const int cntb = tile_cross[b];
+    for (int i = threadIdx.x; i < cntb; i += kBlock) {
+      const int2 e = cross[region + i];
+      if (cross_level(e.x, e.y) == level) hook_edge<true>(e.x, e.y, cc, tu, tv);
     }
-  }
-  s_beg[t] = beg;
-  int total;
-  const int excl = block_excl_scan<kBlock>(deg, s_wave, &total);
-  s_scan[t] = excl;
-  if (t == kBlock - 1) s_scan[kBlock] = excl + deg;
-  __syncthreads();
-  for (int k = t; k < total; k += kBlock) {
-    const int j = lds_upper_search(s_scan, kBlock, k);
-    const int32_t src = (int32_t)(v0 + j);
-    const int32_t dst = cols[(int64_t)s_beg[j] + (k - s_scan[j])];
-    if (dst < src) hook_edge<true>(src, dst, cc, tu, tv);
   }
 }
 
@@ -244,29 +397,44 @@ rst_status enqueue_validate(rst_ctx *ctx, const rst_csr *g, int32_t *counters) {
   return RST_OK;
 }
 
+// every arc (s -> t) with t < s may be listed, so nnz bounds the list for any CSR
+size_t hook_cross_capacity(int64_t nnz) { return (size_t)(nnz + 1); }
+size_t hook_tile_count(int64_t n) { return (size_t)((n + kTile - 1) / kTile); }
+
 rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64_t *chunks,
-                            int64_t chunk_cap) {
+                            int64_t chunk_cap, int2 *cross, int32_t *tile_cross) {
   const int64_t n = g->n;
-  hipLaunchKernelGGL(k_hook_init, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, n,
-                     f.cc, f.tu, f.tv);
-  RST_HIP(hipGetLastError());
+  const unsigned tiles = grid_for(n, kTile);
   const unsigned heavy_grid = (unsigned)(ctx->num_cus * 8);
+  const unsigned cross_grid = tiles < 2048 ? tiles : 2048;
+  int levels = 0;
+  while ((1u << levels) < tiles) ++levels;
   if (g->offset_bytes == 4) {
     const int32_t *off = (const int32_t *)g->offsets;
-    hipLaunchKernelGGL(k_hook_light<int32_t>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
-                       ctx->stream, n, off, g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap,
-                       f.counters, ctx->opt.heavy_degree);
+    hipLaunchKernelGGL(k_hook_tile<int32_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
+                       off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, f.counters, chunks,
+                       chunk_cap, ctx->opt.heavy_degree);
     RST_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_hook_heavy<int32_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream,
-                       off, g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters);
+    for (int l = 0; l < levels; ++l) {
+      hipLaunchKernelGGL(k_hook_cross<int32_t>, dim3(cross_grid), dim3(kBlock), 0, ctx->stream, n,
+                         off, cross, tile_cross, (int)tiles, l, f.cc, f.tu, f.tv);
+      RST_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_hook_heavy<int32_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream, off,
+                       g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters);
   } else {
     const int64_t *off = (const int64_t *)g->offsets;
-    hipLaunchKernelGGL(k_hook_light<int64_t>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
-                       ctx->stream, n, off, g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap,
-                       f.counters, ctx->opt.heavy_degree);
+    hipLaunchKernelGGL(k_hook_tile<int64_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
+                       off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, f.counters, chunks,
+                       chunk_cap, ctx->opt.heavy_degree);
     RST_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_hook_heavy<int64_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream,
-                       off, g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters);
+    for (int l = 0; l < levels; ++l) {
+      hipLaunchKernelGGL(k_hook_cross<int64_t>, dim3(cross_grid), dim3(kBlock), 0, ctx->stream, n,
+                         off, cross, tile_cross, (int)tiles, l, f.cc, f.tu, f.tv);
+      RST_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_hook_heavy<int64_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream, off,
+                       g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters);
   }
   RST_HIP(hipGetLastError());
   return RST_OK;

@@ -93,14 +93,19 @@ enum {
   kCntRangeErr = 3,    // validation failure
   kCntBfsReached = 4,  // vertices reached by BFS
   kCntBfsLast = 5,     // deepest non-empty BFS level
+  kCntCross = 6,       // cross-tile edges appended by the tile phase of hooking
+  kCntExits = 7,       // segment exits of the tiled list ranking
   kCntTotal = 16
 };
 
 // hook.hip
 rst_status enqueue_fill(rst_ctx *ctx, int32_t *p, int64_t count, int32_t value);
 rst_status enqueue_validate(rst_ctx *ctx, const rst_csr *g, int32_t *counters);
+// cross: int2 [hook_cross_capacity], tile_cross: int32 [hook_tile_count]
 rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64_t *chunks,
-                            int64_t chunk_cap);
+                            int64_t chunk_cap, int2 *cross, int32_t *tile_cross);
+size_t hook_cross_capacity(int64_t nnz);
+size_t hook_tile_count(int64_t n);
 rst_status enqueue_hook_coo(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu,
                             const int32_t *ev, int32_t *cc, int32_t *counters);
 rst_status enqueue_compress(rst_ctx *ctx, int64_t n, int32_t *cc, int32_t *comp_root,
@@ -125,6 +130,15 @@ rst_status enqueue_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t 
                           const int32_t *tv, const uint64_t *rank, const int32_t *cc,
                           const int32_t *comp_root, int32_t *parent, int32_t *counters);
 int rank_rounds_for(int64_t max_list_len);
+size_t rank_exit_capacity(int64_t A);
+size_t rank_tile_count(int64_t A);
+// tiled list ranking of A words (succ, hops); leaves (-1, distance to tail) in
+// every word.  xid: int32 [A], exits: int32 [A+1], crank: uint64 [A+1],
+// tile_exits: int32 [tiles], tile_base: int64 [tiles+1].  Reads the exit count
+// back to the host (one synchronisation).
+rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *xid,
+                              int32_t *exits, uint64_t *crank, int32_t *tile_exits,
+                              int64_t *tile_base, int64_t *exits_out, int *rounds_out);
 
 // bfs.hip
 struct BfsBufs {

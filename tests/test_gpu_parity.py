@@ -169,6 +169,33 @@ def test_list_rank_bit_exact(ctx):
         assert np.array_equal(got, exp)
 
 
+def _local_lists(A, block, seed):
+    """Lists that mostly stay inside blocks of consecutive ids (tour-like locality)."""
+    rs = np.random.RandomState(seed)
+    order = np.concatenate([b0 + rs.permutation(min(block, A - b0)) for b0 in range(0, A, block)])
+    # a few long-range hops: swap some pieces across blocks
+    k = max(1, A // 5000)
+    idx = rs.choice(A, size=2 * k, replace=False)
+    order[idx[:k]], order[idx[k:]] = order[idx[k:]].copy(), order[idx[:k]].copy()
+    return order
+
+
+def test_list_rank_tiled_locality(ctx):
+    """Lists with tile locality (few segment exits) and across many tiles."""
+    rs = np.random.RandomState(3)
+    for A, block, nlists in ((16384, 16384, 1), (16385, 3000, 3), (200000, 7000, 1),
+                             (1 << 20, 20000, 17), (50001, 1, 1)):
+        order = _local_lists(A, block, A) if block > 1 else np.arange(A)
+        cuts = np.sort(rs.choice(np.arange(1, A), size=nlists - 1, replace=False))
+        succ = np.full(A, -1, np.int32)
+        for piece in np.split(order, cuts):
+            succ[piece[:-1]] = piece[1:]
+        exp, k = oracle.list_rank(succ)
+        assert k == nlists
+        got = ctx.list_rank(dev(succ)).cpu().numpy()
+        assert np.array_equal(got, exp)
+
+
 def test_heavy_hub_paths(ctx):
     """A star whose centre exceeds the heavy-degree threshold many times over."""
     g = I.star(200001, 7)
