@@ -25,8 +25,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rank_round.json")
-RANK_SOURCE = os.path.join(ROOT, "paper_2603_11645_amd", "csrc", "euler.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCE = {"hook_tile": "hook.hip", "cross": "hook.hip", "rank_tile": "euler.hip",
+                 "link": "euler.hip"}
 
 WORKLOADS = {
     "C1": "grid 256x256, 4-neighbour, ids permuted (seed 1), root 0",
@@ -47,17 +48,21 @@ def source_digest(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def load_traffic(per_launch_words):
-    """Measured HBM bytes per rank-round launch from committed rocprofv3 --pmc
-    summaries, or None if absent or taken on a different kernel source."""
+def load_traffic(kernel, alg_bytes):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the plain-copy calibration), or
+    None if absent, for another workload, or taken on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
+            t = json.load(f).get(kernel)
+    except (OSError, ValueError, AttributeError):
         return None
-    if t.get("source_sha256_16") != source_digest(RANK_SOURCE):
+    if not t:
         return None
-    if t.get("arc_words") != per_launch_words:
+    src = os.path.join(ROOT, "paper_2603_11645_amd", "csrc", KERNEL_SOURCE[kernel])
+    if t.get("source_sha256_16") != source_digest(src):
+        return None
+    if t.get("algorithmic_bytes_per_launch") != int(alg_bytes):
         return None
     return t.get("bytes_per_launch")
 
@@ -165,22 +170,43 @@ def main():
     ms_step = wall * 1e3 / args.steps
     gpu_parent = outs[-1].cpu().numpy()
 
-    # dominant kernel: list-ranking rounds (stage times from HIP events on the
-    # library's stream, i.e. the stream the kernels are launched on)
-    rounds = stats[0]["rank_rounds"]
-    rank_ms = statistics.mean(s["ms_stage"]["rank"] for s in stats)
-    stage_ms = {k: statistics.mean(s["ms_stage"][k] for s in stats)
-                for k in ("hook", "compress", "arcs", "succ", "rank", "parent")}
-    A = 2 * g.n                                    # arc words per launch
-    per_launch_ms = rank_ms / max(rounds, 1)
-    alg_bytes = 24 * A                             # own read 8 + gather 8 + write 8 per word
-    achieved = alg_bytes / (per_launch_ms * 1e-3) / 1e9
-    traffic = load_traffic(A)
-    roofline = {"bound": "hbm", "kernel": "k_rank_round (one list-ranking round)",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "launch_ms": round(per_launch_ms, 5),
-                "algorithmic_bytes_per_launch": alg_bytes, "launches_per_step": rounds}
+    # Per-kernel HIP-event times (recorded by the library on the stream the
+    # kernels run on) and each kernel's algorithmic bytes per launch; the
+    # dominant one is reported as the roofline.
+    def mean(key, sub):
+        return statistics.mean(s[key][sub] for s in stats)
+    stage_ms = {k: mean("ms_stage", k) for k in ("hook", "compress", "arcs", "succ", "rank", "parent")}
+    kern_ms = {k: mean("ms_kernel", k) for k in ("hook_tile", "cross", "rank_tile", "link")}
+    n, nnz, A = g.n, g.nnz, 2 * g.n
+    w_o = g.offset_bytes
+    X = stats[-1]["cross_edges"]
+    levels = max(1, stats[-1]["hook_rounds"] - 1)
+    kern_bytes = {
+        # offsets + neighbour ids read, labels/edge slots written, cross list written
+        "hook_tile": w_o * (n + 1) + 4 * nnz + 12 * n + 8 * X,
+        # cross list scanned once over all levels (per launch: one level's share)
+        "cross": 8 * X / levels,
+        # per arc: slot edge (4) + next of twin (4) + end-of-list successor (2,
+        # half the arcs) + exit index (4) + ranking word (8)
+        "rank_tile": 22 * A,
+        # per slot: edge read (8) + two list-head exchanges (16) + next pair (8)
+        "link": 32 * n,
+    }
+    kern_launches = {"hook_tile": 1, "cross": levels, "rank_tile": 1, "link": 1}
+    kernels = {}
+    for k in kern_ms:
+        per_launch = kern_ms[k] / kern_launches[k]
+        gbs = kern_bytes[k] / (per_launch * 1e-3) / 1e9 if per_launch > 0 else 0.0
+        kernels[k] = {"ms_per_launch": round(per_launch, 5), "launches": kern_launches[k],
+                      "algorithmic_bytes_per_launch": int(kern_bytes[k]),
+                      "achieved_GBps": round(gbs, 1)}
+    dom = max(kern_ms, key=lambda k: kern_ms[k])
+    traffic = load_traffic(dom, kern_bytes[dom])
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["achieved_GBps"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(kernels[dom]["achieved_GBps"] / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "launch_ms": kernels[dom]["ms_per_launch"],
+                "algorithmic_bytes_per_launch": kernels[dom]["algorithmic_bytes_per_launch"]}
 
     bfs = None
     bfs_parent = bfs_level = None
@@ -217,7 +243,9 @@ def main():
                    "method": "gconn+euler", "parallelism": "single GPU"},
         "nnz_per_s": g.nnz / (ms_step * 1e-3),
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "rank_rounds": rounds,
+        "kernels": kernels,
+        "rank_rounds": stats[-1]["rank_rounds"], "rank_exits": stats[-1]["rank_exits"],
+        "cross_edges": X,
         "roofline": roofline,
         "bfs": bfs,
         "paper_context": "GConn+Euler up to 300x faster than optimised BFS on high-diameter "

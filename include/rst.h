@@ -89,13 +89,24 @@ enum {
 typedef struct {
   float ms_total;
   float ms_stage[8];
-  int64_t hook_rounds;    /* hooking sweeps performed                          */
-  int64_t rank_rounds;    /* list-ranking launches                             */
+  float ms_kernel[4];     /* single kernels, see RST_KERNEL_*                  */
+  int64_t hook_rounds;    /* hooking launches (tile pass + cross levels)       */
+  int64_t rank_rounds;    /* pointer-jumping launches on the contracted list   */
+  int64_t rank_exits;     /* length of the contracted list (segment exits)     */
+  int64_t cross_edges;    /* edges left to the global cross phase of hooking   */
   int64_t bfs_levels;     /* deepest BFS level reached (eccentricity of root)  */
   int64_t components;     /* connected components found                        */
   int32_t method_used;    /* rst_method actually run (batch: -1 if mixed)      */
   int32_t reserved;
 } rst_stats;
+
+/* Indices of rst_stats.ms_kernel (HIP-event time of one launch each). */
+enum {
+  RST_KERNEL_HOOK_TILE = 0,   /* LDS union-find over vertex tiles               */
+  RST_KERNEL_CROSS = 1,       /* all cross-tile hooking levels together         */
+  RST_KERNEL_RANK_TILE = 2,   /* LDS ruling-set ranking over arc tiles (+succ)  */
+  RST_KERNEL_LINK = 3         /* per-vertex out-arc lists                       */
+};
 
 /* Tunables and switches for rst_set_option. */
 typedef enum {

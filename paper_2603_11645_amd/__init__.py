@@ -64,16 +64,23 @@ class rst_batch(ctypes.Structure):
                 ("arc_off", ctypes.c_void_p), ("roots", ctypes.c_void_p)]
 
 
+KERNELS = ["hook_tile", "cross", "rank_tile", "link"]
+
+
 class rst_stats(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_float), ("ms_stage", ctypes.c_float * 8),
+                ("ms_kernel", ctypes.c_float * 4),
                 ("hook_rounds", ctypes.c_int64), ("rank_rounds", ctypes.c_int64),
+                ("rank_exits", ctypes.c_int64), ("cross_edges", ctypes.c_int64),
                 ("bfs_levels", ctypes.c_int64), ("components", ctypes.c_int64),
                 ("method_used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"ms_total": self.ms_total,
                 "ms_stage": {STAGES[i]: self.ms_stage[i] for i in range(8)},
+                "ms_kernel": {KERNELS[i]: self.ms_kernel[i] for i in range(4)},
                 "hook_rounds": self.hook_rounds, "rank_rounds": self.rank_rounds,
+                "rank_exits": self.rank_exits, "cross_edges": self.cross_edges,
                 "bfs_levels": self.bfs_levels, "components": self.components,
                 "method_used": self.method_used}
 

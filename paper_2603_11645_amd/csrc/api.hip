@@ -60,6 +60,22 @@ static void fill_stage_times(rst_ctx *ctx, rst_stats *st, const int *stage_of_ga
   if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[nev - 1]) == hipSuccess) st->ms_total = ms;
 }
 
+static void fill_kernel_times(rst_ctx *ctx, rst_stats *st) {
+  for (int k = 0; k < 4; ++k) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[kEvKernelBase + 2 * k], ctx->ev[kEvKernelBase + 2 * k + 1]) ==
+        hipSuccess)
+      st->ms_kernel[k] = ms;
+  }
+}
+
+// enables per-kernel events for the duration of one API call
+struct TimingScope {
+  rst_ctx *ctx;
+  TimingScope(rst_ctx *c, bool on) : ctx(c) { ctx->timing = on; }
+  ~TimingScope() { ctx->timing = false; }
+};
+
 static inline rst_status mark(rst_ctx *ctx, rst_stats *st, int i) {
   if (st) RST_HIP(hipEventRecord(ctx->ev[i], ctx->stream));
   return RST_OK;
@@ -104,7 +120,7 @@ rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
   uint64_t *rank = ws_take<uint64_t>(ctx, 2 * n);
   int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
   int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
-  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_count(g->n));
+  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
   RankBufs rb = take_rank_bufs(ctx, 2 * n);
 
   RST_TRY(mark(ctx, st, 0));
@@ -115,15 +131,17 @@ rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
   RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, f.cc, f.comp_root, parent, counters));
   RST_TRY(enqueue_link(ctx, n, f.tu, f.tv, head, next));
   RST_TRY(mark(ctx, st, 3));
-  RST_TRY(enqueue_succ(ctx, n, f.tu, f.tv, head, next, f.cc, f.comp_root, rank));
+  // the successor pass is fused into the first ranking pass (stage "succ" stays empty)
   RST_TRY(mark(ctx, st, 4));
   int rounds = 0;
   int64_t exits_n = 0;
-  // next[] is dead after the successor pass: it holds the exit indices
-  RST_TRY(enqueue_rank_tiled(ctx, 2 * n, rank, next, rb.exits, rb.crank, rb.tile_exits,
-                             rb.tile_base, &exits_n, &rounds));
+  int32_t *xid = ws_take<int32_t>(ctx, 2 * n);
+  SlotArcs arcs{f.tu, f.tv, next, head, f.cc, f.comp_root, n, ws_take<int32_t>(ctx, n)};
+  RST_TRY(enqueue_rank_tiled(ctx, 2 * n, rank, xid, rb.exits, rb.crank, rb.tile_exits,
+                             rb.tile_base, &exits_n, &rounds, &arcs, false));
   RST_TRY(mark(ctx, st, 5));
-  RST_TRY(enqueue_parent(ctx, n, n, f.tu, f.tv, rank, f.cc, f.comp_root, parent, counters));
+  RST_TRY(enqueue_expand_parent(ctx, n, n, f.tu, f.tv, rank, xid, rb.tile_base, rb.crank, f.cc,
+                                f.comp_root, parent, counters));
   RST_TRY(mark(ctx, st, 6));
   RST_TRY(read_counters(ctx, counters));
   if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
@@ -133,8 +151,11 @@ rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
     static const int gaps[6] = {RST_STAGE_HOOK, RST_STAGE_COMPRESS, RST_STAGE_ARCS, RST_STAGE_SUCC,
                                 RST_STAGE_RANK, RST_STAGE_PARENT};
     fill_stage_times(ctx, st, gaps, 7);
-    st->hook_rounds = 1;
+    fill_kernel_times(ctx, st);
+    st->hook_rounds = 1 + hook_level_count(n);
     st->rank_rounds = rounds;
+    st->rank_exits = exits_n;
+    st->cross_edges = ctx->host_pinned[kCntCross];
     st->components = *components;
     st->method_used = RST_GCONN_EULER;
   }
@@ -158,12 +179,12 @@ static size_t bfs_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
 
 static size_t hook_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
   return ws_bytes(hook_chunk_capacity(ctx, g->nnz), 8) + ws_bytes(hook_cross_capacity(g->nnz), 8) +
-         ws_bytes(hook_tile_count(g->n), 4);
+         ws_bytes(hook_tile_words(g->n), 4);
 }
 
 static size_t gconn_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
   const size_t n = (size_t)g->n;
-  return 5 * ws_bytes(n, 4) + ws_bytes(2 * n, 4) + ws_bytes(2 * n, 8) + hook_ws_bytes(ctx, g) +
+  return 6 * ws_bytes(n, 4) + 2 * ws_bytes(2 * n, 4) + ws_bytes(2 * n, 8) + hook_ws_bytes(ctx, g) +
          rank_ws_bytes(2 * g->n);
 }
 
@@ -250,6 +271,7 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
   if (method != RST_GCONN_EULER && method != RST_BFS) return RST_E_INVAL;
   RST_HIP(hipSetDevice(ctx->device));
   if (stats) std::memset(stats, 0, sizeof(*stats));
+  TimingScope timing(ctx, stats != nullptr);
 
   size_t bytes = ws_bytes(64, 4) + gconn_ws_bytes(ctx, g);
   if (method == RST_BFS) bytes += bfs_ws_bytes(ctx, g) + ws_bytes(g->n, 4);
@@ -290,7 +312,7 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
     const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
     int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
     int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
-  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_count(g->n));
+  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
     RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
     RST_TRY(enqueue_compress(ctx, g->n, f.cc, nullptr, nullptr));
     RST_TRY(enqueue_count_roots(ctx, g->n, f.cc, counters));
@@ -330,7 +352,7 @@ rst_status rst_components(rst_ctx *ctx, const rst_csr *g, int32_t *label,
   f.tv = ws_take<int32_t>(ctx, g->n);
   int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
   int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
-  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_count(g->n));
+  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
   RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
   RST_TRY(enqueue_compress(ctx, g->n, label, nullptr, nullptr));
   RST_TRY(enqueue_count_roots(ctx, g->n, label, counters));
@@ -356,7 +378,7 @@ rst_status rst_spanning_forest(rst_ctx *ctx, const rst_csr *g, int32_t *label, i
   f.tv = tv;
   int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
   int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
-  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_count(g->n));
+  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
   RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
   RST_TRY(enqueue_compress(ctx, g->n, label, nullptr, nullptr));
   RST_TRY(enqueue_count_roots(ctx, g->n, label, counters));
@@ -404,7 +426,7 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
   if (nroots > 0 && !roots) return RST_E_INVAL;
   if (n >= ((int64_t)1 << 30)) return RST_E_INVAL;
   RST_HIP(hipSetDevice(ctx->device));
-  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 3 * ws_bytes(n, 4) + ws_bytes(2 * t + 2, 4) +
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 4 * ws_bytes(n, 4) + 2 * ws_bytes(2 * t + 2, 4) +
                               ws_bytes(2 * t + 2, 8) + rank_ws_bytes(2 * t)));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
   int32_t *cc = ws_take<int32_t>(ctx, n);
@@ -412,6 +434,7 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
   int32_t *head = ws_take<int32_t>(ctx, n);
   int32_t *next = ws_take<int32_t>(ctx, 2 * t + 2);
   uint64_t *rank = ws_take<uint64_t>(ctx, 2 * t + 2);
+  int32_t *xid = ws_take<int32_t>(ctx, 2 * t + 2);
   RankBufs rb = take_rank_bufs(ctx, 2 * t);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(enqueue_hook_coo(ctx, n, t, eu, ev, cc, counters));
@@ -420,10 +443,11 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
   if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
   RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, cc, comp_root, parent, counters));
   RST_TRY(enqueue_link(ctx, t, eu, ev, head, next));
-  RST_TRY(enqueue_succ(ctx, t, eu, ev, head, next, cc, comp_root, rank));
-  RST_TRY(enqueue_rank_tiled(ctx, 2 * t, rank, next, rb.exits, rb.crank, rb.tile_exits,
-                             rb.tile_base, nullptr, nullptr));
-  RST_TRY(enqueue_parent(ctx, t, n, eu, ev, rank, cc, comp_root, parent, counters));
+  SlotArcs arcs{eu, ev, next, head, cc, comp_root, n, ws_take<int32_t>(ctx, n)};
+  RST_TRY(enqueue_rank_tiled(ctx, 2 * t, rank, xid, rb.exits, rb.crank, rb.tile_exits,
+                             rb.tile_base, nullptr, nullptr, &arcs, false));
+  RST_TRY(enqueue_expand_parent(ctx, t, n, eu, ev, rank, xid, rb.tile_base, rb.crank, cc,
+                                comp_root, parent, counters));
   RST_TRY(read_counters(ctx, counters));
   if (ctx->host_pinned[kCntRangeErr] || ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
   return RST_OK;
@@ -442,7 +466,7 @@ rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(enqueue_rank_init(ctx, A, succ, rank));
   RST_TRY(enqueue_rank_tiled(ctx, A, rank, xid, rb.exits, rb.crank, rb.tile_exits, rb.tile_base,
-                             nullptr, nullptr));
+                             nullptr, nullptr, nullptr, true));
   RST_TRY(enqueue_rank_extract(ctx, A, rank, dist));
   RST_HIP(hipStreamSynchronize(ctx->stream));
   return RST_OK;

@@ -158,29 +158,45 @@ __global__ __launch_bounds__(kBlock) void k_rank_round(int64_t A, uint64_t *rank
 constexpr int kRankTile = 16384;
 constexpr int kRankThreads = 1024;
 constexpr int kRankPer = kRankTile / kRankThreads;
-constexpr int kRuler = 16;                           // every 16th arc is a ruler
-constexpr int kRulerSlots = 2048;                    // strided rulers + extra segment heads
-constexpr int kStrided = kRankTile / kRuler;
+constexpr int kRuler = 8;                            // every 8th arc is a ruler
+constexpr int kStrided = kRankTile / kRuler;         // 2048 strided ruler slots
+constexpr int kRulerSlots = 3584;                    // + up to 1536 extra segment heads
 
 __device__ __forceinline__ bool in_tile(int32_t id, int64_t e) {
   return id >= 0 && ((int64_t)id / kRankTile) == (e / kRankTile);
 }
 
-// Within a tile: every segment head and every 16th arc is a ruler.  Each ruler
+// endsucc[v]: successor of an arc into v whose reverse ends v's out-arc list,
+// i.e. the first out-arc of v, or -1 (cycle break) when v is its tree's root.
+__global__ __launch_bounds__(kBlock) void k_endsucc(int64_t n, const int32_t *__restrict__ head,
+                                                    const int32_t *__restrict__ cc,
+                                                    const int32_t *__restrict__ comp_root,
+                                                    int32_t *endsucc) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) endsucc[v] = is_root((int32_t)v, cc, comp_root) ? -1 : head[v];
+}
+
+struct SlotSrc {            // arcs described by the forest slots (fused successor pass)
+  const int32_t *tu, *tv, *next, *endsucc;
+};
+
+// Within a tile: every segment head and every 8th arc is a ruler.  Each ruler
 // walks its piece of list (to the next ruler or the segment's exit) in LDS;
-// the rulers are then ranked by pointer jumping over at most 2048 slots, and a
-// second walk writes (exit, hops to exit) for every arc.  Total LDS work is two
-// linear passes; the walks are short because rulers are dense.  A tile with
-// more segment heads than ruler slots (no locality) is ranked by plain pointer
-// jumping in LDS instead.
+// the rulers are then ranked by pointer jumping, and a second walk writes
+// (exit, hops to exit) for every arc.  Total LDS work is two linear passes;
+// each thread walks two rulers at once so their LDS latencies overlap.  A
+// tile with more segment heads than ruler slots (no locality) is ranked by
+// plain pointer jumping in LDS instead.
+template <bool kFromSlots>
 __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t *rank, int32_t *xid,
-                                                            int32_t *exits, int32_t *tile_exits) {
+                                                            int32_t *exits, int32_t *tile_exits,
+                                                            SlotSrc src) {
   __shared__ int16_t ls[kRankTile];                  // local successor, -1 at an exit
   __shared__ __align__(16) unsigned char region[kRankTile * 2];   // flags+rulers, or hop counts
   __shared__ int s_extra;
   __shared__ int s_nexit;
-  uint8_t *haspred = region;                                        // [kRankTile]
-  int16_t *r_start = reinterpret_cast<int16_t *>(region + kRankTile);   // [kRulerSlots]
+  uint32_t *haspred = reinterpret_cast<uint32_t *>(region);          // [kRankTile / 32] bits
+  int16_t *r_start = reinterpret_cast<int16_t *>(region + kRankTile / 8);
   int16_t *r_next = r_start + kRulerSlots;
   uint16_t *r_len = reinterpret_cast<uint16_t *>(r_next + kRulerSlots);
   int16_t *r_exit = reinterpret_cast<int16_t *>(r_len + kRulerSlots);
@@ -190,39 +206,64 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
   const int64_t e0 = (int64_t)blockIdx.x * kRankTile;
   const int cnt = (int)((A - e0) < kRankTile ? (A - e0) : kRankTile);
   if (tid == 0) { s_extra = 0; s_nexit = 0; }
-  // issue every load of the tile before any dependent work
-  uint64_t w[kRankPer];
-#pragma unroll
-  for (int j = 0; j < kRankPer; ++j) {
-    const int i = tid + j * kRankThreads;
-    w[j] = i < cnt ? rank[e0 + i] : 0ull;
-  }
+  for (int q = tid; q < kRankTile / 32; q += kRankThreads) haspred[q] = 0u;
   __syncthreads();
+  // two half-passes of 8 arcs per thread: loads of a half are issued together
 #pragma unroll
-  for (int j = 0; j < kRankPer; ++j) {
-    const int i = tid + j * kRankThreads;
-    bool is_exit = false;
-    haspred[i] = 0;
-    if (i < cnt) {
-      const int32_t sc = (int32_t)(uint32_t)w[j];
-      const int64_t sl = (int64_t)sc - e0;
-      if (sc >= 0 && sl >= 0 && sl < cnt) {
-        ls[i] = (int16_t)sl;
-      } else {
-        ls[i] = -1;
-        is_exit = true;
+  for (int h = 0; h < 2; ++h) {
+    constexpr int H = kRankPer / 2;
+    uint64_t w[H];
+    if (kFromSlots) {
+      // successor: next(rev e), or at the end of dst's list endsucc[dst]
+      int32_t dst[H], sc[H];
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const int64_t e = e0 + tid + (h * H + j) * kRankThreads;
+        dst[j] = -1; sc[j] = -1;
+        if (e < A) {
+          const int32_t a = src.tu[e >> 1];
+          dst[j] = a < 0 ? -1 : ((e & 1) ? a : src.tv[e >> 1]);   // 2x = a->b, 2x+1 = b->a
+          sc[j] = src.next[e ^ 1];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < H; ++j)
+        if (dst[j] >= 0 && sc[j] == -1) sc[j] = src.endsucc[dst[j]];
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const int32_t t = dst[j] < 0 ? -1 : sc[j];
+        w[j] = pack_rank(t, t >= 0 ? 1u : 0u);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const int i = tid + (h * H + j) * kRankThreads;
+        w[j] = i < cnt ? rank[e0 + i] : 0ull;
       }
     }
-    // exits of tile b go to exits[b*kRankTile + k], k from an LDS counter
-    const int slot = wave_append(is_exit, &s_nexit);
-    if (is_exit) exits[e0 + slot] = (int32_t)(e0 + i);
-    if (i < cnt) xid[e0 + i] = is_exit ? slot : 0;
-  }
-  __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kRankPer; ++j) {
-    const int i = tid + j * kRankThreads;
-    if (i < cnt && ls[i] >= 0) haspred[ls[i]] = 1;
+    for (int j = 0; j < H; ++j) {
+      const int i = tid + (h * H + j) * kRankThreads;
+      bool is_exit = false;
+      if (i < cnt) {
+        const int32_t sc = (int32_t)(uint32_t)w[j];
+        const int64_t sl = (int64_t)sc - e0;
+        if (sc >= 0 && sl >= 0 && sl < cnt) {
+          ls[i] = (int16_t)sl;
+          atomicOr(&haspred[sl >> 5], 1u << (sl & 31));
+        } else {
+          ls[i] = -1;
+          is_exit = true;
+        }
+      }
+      // exits of tile b go to exits[b*kRankTile + k], k from an LDS counter
+      const int slot = wave_append(is_exit, &s_nexit);
+      if (is_exit) {
+        exits[e0 + slot] = (int32_t)(e0 + i);
+        if (kFromSlots) rank[e0 + i] = w[j];
+      }
+      if (i < cnt) xid[e0 + i] = is_exit ? slot : 0;
+    }
   }
   __syncthreads();
   // strided rulers own slots 0..kStrided-1; heads off the stride get extra slots
@@ -230,7 +271,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
 #pragma unroll
   for (int j = 0; j < kRankPer; ++j) {
     const int i = tid + j * kRankThreads;
-    if (i < cnt && (i % kRuler) != 0 && !haspred[i]) {
+    if (i < cnt && (i % kRuler) != 0 && !((haspred[i >> 5] >> (i & 31)) & 1u)) {
       const int x = atomicAdd(&s_extra, 1);
       if (kStrided + x < kRulerSlots) r_start[kStrided + x] = (int16_t)i;
     }
@@ -240,32 +281,45 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
   const int extra = s_extra;
   if (kStrided + extra <= kRulerSlots) {
     const int nslots = kStrided + extra;
-    // walk 1: hops to the next ruler, or to the exit
-    for (int q = tid; q < nslots; q += kRankThreads) {
-      int j = r_start[q];
-      int nx = -1, len = 0, ex = -1;
-      if (j < cnt) {
-        for (;;) {
-          const int sj = ls[j];
-          if (sj < 0) { ex = j; break; }
-          j = sj;
-          ++len;
-          if ((j % kRuler) == 0) { nx = j / kRuler; break; }
-          if (len > cnt) { ex = j; break; }      // only on a cycle (malformed input)
+    // walk 1, two rulers per thread in lock step: hops to the next ruler or exit
+    for (int qb = tid; qb < nslots; qb += 2 * kRankThreads) {
+      int q[2] = {qb, qb + kRankThreads};
+      int jj[2], len[2] = {0, 0}, nx[2] = {-1, -1}, ex[2] = {0, 0};
+      bool act[2];
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        jj[w] = q[w] < nslots ? r_start[q[w]] : cnt;
+        act[w] = jj[w] < cnt;
+      }
+      while (act[0] || act[1]) {
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          if (!act[w]) continue;
+          const int sj = ls[jj[w]];
+          if (sj < 0) { ex[w] = jj[w]; act[w] = false; continue; }
+          jj[w] = sj;
+          ++len[w];
+          if ((sj % kRuler) == 0) { nx[w] = sj / kRuler; act[w] = false; continue; }
+          if (len[w] > cnt) { ex[w] = sj; act[w] = false; }   // only on a cycle
         }
       }
-      r_next[q] = (int16_t)nx;
-      r_len[q] = (uint16_t)len;
-      r_exit[q] = (int16_t)(ex < 0 ? 0 : ex);
+#pragma unroll
+      for (int w = 0; w < 2; ++w)
+        if (q[w] < nslots) {
+          r_next[q[w]] = (int16_t)nx[w];
+          r_len[q[w]] = (uint16_t)len[w];
+          r_exit[q[w]] = (int16_t)ex[w];
+        }
     }
     __syncthreads();
     // pointer jumping over the rulers
-    for (int round = 0; round < 12; ++round) {
-      int16_t nn[2], ne[2];
-      uint16_t nl[2];
+    constexpr int QP = (kRulerSlots + kRankThreads - 1) / kRankThreads;
+    for (int round = 0; round < 13; ++round) {
+      int16_t nn[QP], ne[QP];
+      uint16_t nl[QP];
       bool changed = false;
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < QP; ++k) {
         const int q = tid + k * kRankThreads;
         if (q < nslots) {
           const int x = r_next[q];
@@ -280,24 +334,35 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
       }
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < 2; ++k) {
+      for (int k = 0; k < QP; ++k) {
         const int q = tid + k * kRankThreads;
         if (q < nslots) { r_next[q] = nn[k]; r_len[q] = nl[k]; r_exit[q] = ne[k]; }
       }
       if (!__syncthreads_or(changed)) break;
     }
-    // walk 2: every non-exit arc gets (exit, hops to exit)
-    for (int q = tid; q < nslots; q += kRankThreads) {
-      int j = r_start[q];
-      if (j >= cnt) continue;
-      const int total = r_len[q];
-      const int32_t exg = (int32_t)(e0 + r_exit[q]);
-      for (int k = 0; k <= cnt; ++k) {
-        const int sj = ls[j];
-        if (sj < 0) break;
-        rank[e0 + j] = pack_rank(exg, (uint32_t)(total - k));
-        j = sj;
-        if ((j % kRuler) == 0) break;
+    // walk 2, two rulers per thread: every non-exit arc gets (exit, hops to exit)
+    for (int qb = tid; qb < nslots; qb += 2 * kRankThreads) {
+      int q[2] = {qb, qb + kRankThreads};
+      int jj[2], k2[2] = {0, 0}, total[2] = {0, 0};
+      int32_t exg[2] = {0, 0};
+      bool act[2];
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        jj[w] = q[w] < nslots ? r_start[q[w]] : cnt;
+        act[w] = jj[w] < cnt;
+        if (act[w]) { total[w] = r_len[q[w]]; exg[w] = (int32_t)(e0 + r_exit[q[w]]); }
+      }
+      while (act[0] || act[1]) {
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+          if (!act[w]) continue;
+          const int sj = ls[jj[w]];
+          if (sj < 0 || k2[w] > cnt) { act[w] = false; continue; }
+          rank[e0 + jj[w]] = pack_rank(exg[w], (uint32_t)(total[w] - k2[w]));
+          jj[w] = sj;
+          ++k2[w];
+          if ((sj % kRuler) == 0) act[w] = false;
+        }
       }
     }
     return;
@@ -410,6 +475,47 @@ __global__ __launch_bounds__(kBlock) void k_rank_expand(int64_t A, uint64_t *ran
   rank[e] = pack_rank(-1, dist);
 }
 
+__device__ __forceinline__ uint32_t arc_dist(int64_t e, const uint64_t *__restrict__ rank,
+                                             const int32_t *__restrict__ xid,
+                                             const int64_t *__restrict__ base,
+                                             const uint64_t *__restrict__ crank) {
+  const uint64_t w = rank[e];
+  const int32_t id = (int32_t)(uint32_t)w;
+  if (in_tile(id, e)) return (uint32_t)(w >> 32) + (uint32_t)(crank[exit_index(id, xid, base)] >> 32);
+  return (uint32_t)(crank[exit_index((int32_t)e, xid, base)] >> 32);
+}
+
+// Distances of both arcs of a slot, then the parent rule; default component
+// roots get P[v] = v and are counted.
+__global__ __launch_bounds__(kBlock) void k_expand_parent(int64_t slots, int64_t n,
+                                                          const int32_t *__restrict__ tu,
+                                                          const int32_t *__restrict__ tv,
+                                                          const uint64_t *__restrict__ rank,
+                                                          const int32_t *__restrict__ xid,
+                                                          const int64_t *__restrict__ base,
+                                                          const uint64_t *__restrict__ crank,
+                                                          const int32_t *__restrict__ cc,
+                                                          const int32_t *__restrict__ comp_root,
+                                                          int32_t *parent, int32_t *counters) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < slots) {
+    const int32_t a = tu[x];
+    if (a >= 0) {
+      const int32_t b = tv[x];
+      const uint32_t d0 = arc_dist(2 * x, rank, xid, base, crank);
+      const uint32_t d1 = arc_dist(2 * x + 1, rank, xid, base, crank);
+      if (d0 > d1) parent[b] = a;   // a->b comes first in the tour: it descends
+      else parent[a] = b;
+    }
+  }
+  bool comp = false;
+  if (x < n) {
+    comp = cc[x] == (int32_t)x;
+    if (comp && comp_root[x] == -1) parent[x] = (int32_t)x;
+  }
+  wave_count(comp, &counters[kCntComponents]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_rank_extract(int64_t A, const uint64_t *__restrict__ rank,
                                                          int32_t *dist) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -466,9 +572,11 @@ rst_status enqueue_mark_roots(rst_ctx *ctx, const int32_t *roots, int32_t nroots
 rst_status enqueue_link(rst_ctx *ctx, int64_t slots, const int32_t *tu, const int32_t *tv,
                         int32_t *head, int32_t *next) {
   if (slots <= 0) return RST_OK;
+  RST_KMARK(ctx, RST_KERNEL_LINK, 0);
   hipLaunchKernelGGL(k_link, dim3(grid_for(slots, kBlock)), dim3(kBlock), 0, ctx->stream, slots,
                      tu, tv, head, next);
   RST_HIP(hipGetLastError());
+  RST_KMARK(ctx, RST_KERNEL_LINK, 1);
   return RST_OK;
 }
 
@@ -520,14 +628,29 @@ size_t rank_tile_count(int64_t A) { return (size_t)((A + kRankTile - 1) / kRankT
 
 rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *xid,
                               int32_t *exits, uint64_t *crank, int32_t *tile_exits,
-                              int64_t *tile_base, int64_t *exits_out, int *rounds_out) {
+                              int64_t *tile_base, int64_t *exits_out, int *rounds_out,
+                              const SlotArcs *from_slots, bool expand) {
   if (rounds_out) *rounds_out = 0;
   if (exits_out) *exits_out = 0;
   if (A <= 0) return RST_OK;
   const int64_t tiles = (int64_t)rank_tile_count(A);
-  hipLaunchKernelGGL(k_rank_tile, dim3((unsigned)tiles), dim3(kRankThreads), 0, ctx->stream, A,
-                     rank, xid, exits, tile_exits);
+  if (from_slots) {
+    hipLaunchKernelGGL(k_endsucc, dim3(grid_for(from_slots->n, kBlock)), dim3(kBlock), 0,
+                       ctx->stream, from_slots->n, from_slots->head, from_slots->cc,
+                       from_slots->comp_root, from_slots->endsucc);
+    RST_HIP(hipGetLastError());
+    SlotSrc src{from_slots->tu, from_slots->tv, from_slots->next, from_slots->endsucc};
+    RST_KMARK(ctx, RST_KERNEL_RANK_TILE, 0);
+    hipLaunchKernelGGL(k_rank_tile<true>, dim3((unsigned)tiles), dim3(kRankThreads), 0, ctx->stream,
+                       A, rank, xid, exits, tile_exits, src);
+  } else {
+    SlotSrc src{};
+    RST_KMARK(ctx, RST_KERNEL_RANK_TILE, 0);
+    hipLaunchKernelGGL(k_rank_tile<false>, dim3((unsigned)tiles), dim3(kRankThreads), 0,
+                       ctx->stream, A, rank, xid, exits, tile_exits, src);
+  }
   RST_HIP(hipGetLastError());
+  RST_KMARK(ctx, RST_KERNEL_RANK_TILE, 1);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, ctx->stream, tile_exits, tiles, tile_base);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_rank_contract, dim3((unsigned)tiles), dim3(kBlock), 0, ctx->stream, exits,
@@ -541,11 +664,24 @@ rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *
   if (M < 0 || M > A) M = A;
   const int rounds = rank_rounds_for(M);
   RST_TRY(enqueue_rank_rounds(ctx, M, crank, rounds, nullptr, nullptr));
-  hipLaunchKernelGGL(k_rank_expand, dim3(grid_for(A, kBlock)), dim3(kBlock), 0, ctx->stream, A,
-                     rank, xid, tile_base, crank);
-  RST_HIP(hipGetLastError());
+  if (expand) {
+    hipLaunchKernelGGL(k_rank_expand, dim3(grid_for(A, kBlock)), dim3(kBlock), 0, ctx->stream, A,
+                       rank, xid, tile_base, crank);
+    RST_HIP(hipGetLastError());
+  }
   if (rounds_out) *rounds_out = rounds;
   if (exits_out) *exits_out = M;
+  return RST_OK;
+}
+
+rst_status enqueue_expand_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
+                                 const int32_t *tv, const uint64_t *rank, const int32_t *xid,
+                                 const int64_t *tile_base, const uint64_t *crank, const int32_t *cc,
+                                 const int32_t *comp_root, int32_t *parent, int32_t *counters) {
+  const int64_t items = slots > n ? slots : n;
+  hipLaunchKernelGGL(k_expand_parent, dim3(grid_for(items, kBlock)), dim3(kBlock), 0, ctx->stream,
+                     slots, n, tu, tv, rank, xid, tile_base, crank, cc, comp_root, parent, counters);
+  RST_HIP(hipGetLastError());
   return RST_OK;
 }
 

@@ -39,6 +39,7 @@ struct rst_ctx {
   rst::Options opt;
   hipEvent_t ev[16] = {};
   int32_t *host_pinned = nullptr;   // small pinned host buffer for flag readback
+  bool timing = false;              // record per-kernel events (a stats struct was passed)
   rst::Selector *selector = nullptr;
 };
 
@@ -51,6 +52,14 @@ namespace rst {
   do {                                                  \
     hipError_t e_ = (call);                             \
     if (e_ != hipSuccess) return RST_E_DEVICE;          \
+  } while (0)
+
+// per-kernel event pairs in ctx->ev[8..15], recorded only while ctx->timing is set
+enum { kEvKernelBase = 8 };
+#define RST_KMARK(ctx, kernel, end)                                                          \
+  do {                                                                                        \
+    if ((ctx)->timing)                                                                        \
+      RST_HIP(hipEventRecord((ctx)->ev[kEvKernelBase + 2 * (kernel) + (end)], (ctx)->stream)); \
   } while (0)
 
 #define RST_TRY(call)                                   \
@@ -101,11 +110,13 @@ enum {
 // hook.hip
 rst_status enqueue_fill(rst_ctx *ctx, int32_t *p, int64_t count, int32_t value);
 rst_status enqueue_validate(rst_ctx *ctx, const rst_csr *g, int32_t *counters);
-// cross: int2 [hook_cross_capacity], tile_cross: int32 [hook_tile_count]
+// cross: int2 [hook_cross_capacity], tile_cross: int32 [hook_tile_words], 8-byte aligned
 rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64_t *chunks,
                             int64_t chunk_cap, int2 *cross, int32_t *tile_cross);
 size_t hook_cross_capacity(int64_t nnz);
 size_t hook_tile_count(int64_t n);
+int hook_level_count(int64_t n);
+size_t hook_tile_words(int64_t n);   // int32 words of the tile_cross buffer
 rst_status enqueue_hook_coo(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu,
                             const int32_t *ev, int32_t *cc, int32_t *counters);
 rst_status enqueue_compress(rst_ctx *ctx, int64_t n, int32_t *cc, int32_t *comp_root,
@@ -136,9 +147,24 @@ size_t rank_tile_count(int64_t A);
 // every word.  xid: int32 [A], exits: int32 [A+1], crank: uint64 [A+1],
 // tile_exits: int32 [tiles], tile_base: int64 [tiles+1].  Reads the exit count
 // back to the host (one synchronisation).
+// Arcs given by forest slots: the tile pass computes each arc's successor
+// itself (no separate successor pass).
+struct SlotArcs {
+  const int32_t *tu, *tv, *next, *head, *cc, *comp_root;
+  int64_t n;          // vertices
+  int32_t *endsucc;   // scratch [n]
+};
+// from_slots: NULL -> rank[] already holds (succ, hops) words.  expand: leave
+// (-1, distance) in every rank word (otherwise the caller expands, e.g. fused
+// with the parent rule).
 rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *xid,
                               int32_t *exits, uint64_t *crank, int32_t *tile_exits,
-                              int64_t *tile_base, int64_t *exits_out, int *rounds_out);
+                              int64_t *tile_base, int64_t *exits_out, int *rounds_out,
+                              const SlotArcs *from_slots, bool expand);
+rst_status enqueue_expand_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
+                                 const int32_t *tv, const uint64_t *rank, const int32_t *xid,
+                                 const int64_t *tile_base, const uint64_t *crank, const int32_t *cc,
+                                 const int32_t *comp_root, int32_t *parent, int32_t *counters);
 
 // bfs.hip
 struct BfsBufs {
