@@ -179,16 +179,63 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
 rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *dist);
 
 /* Rooted spanning forest of G packed graphs in one pass: graph g is rooted at
- * roots[g].  method: device uint8 [G] per graph (0 = GConn+Euler, 1 = BFS), or
- * NULL to let the loaded selector choose (GConn+Euler if none is loaded).
- * parent: device int32 [total n].  method_out: device uint8 [G], nullable,
- * receives the method used per graph.  stats may be NULL. */
+ * roots[g].  method: device uint8 [G] per graph (0 = GConn+Euler, nonzero =
+ * BFS), or NULL to let the loaded selector choose (GConn+Euler if none is
+ * loaded).  parent: device int32 [total n]; a graph that is itself
+ * disconnected gets its other components rooted at their minimum ids.
+ * method_out: device uint8 [G], nullable, receives the method used per graph.
+ * The number of kernel launches does not depend on G.  RST_E_INVAL if the
+ * offset tables disagree with the CSR or a root lies outside its graph.
+ * stats may be NULL. */
 rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
                                      const uint8_t *method, int32_t *parent,
                                      uint8_t *method_out, rst_stats *stats);
 
-/* Load selector weights (host blob written by rst_selector_save or the Python
- * trainer; format described in selector.h).  RST_E_INVAL on a malformed blob. */
+/* ---- learned BFS / GConn+Euler selector (per graph of a batch) ------------
+ * Features of graph g, feat[g*8 + k]: log n, log(1 + m), mean degree,
+ * log(1 + degree variance), log(1 + max degree), and for probes s = 0, 1, 2
+ * log2(1 + depth reached by a BFS capped at 64 levels) from the source
+ * vtx_off[g] + splitmix64(3g + s) mod n_g (splitmix64: Steele, Lea, Flood 2014,
+ * x += 0x9E3779B97F4A7C15 then the finaliser).  Degree moments use arcs of the
+ * CSR; m counts each undirected edge once (arcs / 2).
+ * Network: 8 -> 64 -> 64 -> 2 fully connected, ReLU, fp32, applied to z-scored
+ * features (x - mean) / max(std, 1e-6).  Output 0 scores GConn+Euler, output 1
+ * scores BFS; BFS is chosen only when its score is strictly larger and every
+ * feature and score is finite.
+ * Parameter vector (4866 floats, row-major): W1[64][8], b1[64], W2[64][64],
+ * b2[64], W3[2][64], b3[2].  Normalisation vector: mean[8], std[8].
+ * Selector blob (host bytes, little endian): "RSTSEL01" (8 bytes), int32 8,
+ * int32 64, then 16 floats of normalisation and the 4866 parameters; total
+ * 16 + 4 * 4882 = 19544 bytes. */
+
+/* Features of every graph of a packed batch.  feat: device float [G*8]. */
+rst_status rst_features(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, float *feat);
+
+/* Column mean and standard deviation of X (device float [B*8]) into norm
+ * (device float [16]: mean[8] then std[8]), accumulated in double. */
+rst_status rst_feature_stats(rst_ctx *ctx, const float *X, int64_t B, float *norm);
+
+/* Forward pass for B feature rows X (device float [B*8]).  logits: device
+ * float [B*2] (nullable); choice: device uint8 [B] (nullable) receives 1 for
+ * BFS, 0 for GConn+Euler.  norm/params: device, layouts above. */
+rst_status rst_mlp_forward(rst_ctx *ctx, const float *norm, const float *params, const float *X,
+                           int64_t B, float *logits, uint8_t *choice);
+
+/* One training step on a batch of B samples (all device arrays): features X
+ * [B*8], labels y [B] (0 GConn+Euler faster, 1 BFS faster), sample weights w
+ * [B].  Loss: mean over samples of w * softmax cross-entropy.  The gradient of
+ * the loss (device float [4866], nullable) is written to grad; if adam_m and
+ * adam_v (device float [4866] each, zero before step 1) are given and lr > 0,
+ * params are updated by Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected
+ * with the 1-based step).  loss_host: host float, nullable. */
+rst_status rst_mlp_train_step(rst_ctx *ctx, const float *norm, float *params, float *adam_m,
+                              float *adam_v, int64_t step, float lr, const float *X,
+                              const int32_t *y, const float *w, int64_t B, float *grad,
+                              float *loss_host);
+
+/* Load selector weights from a host blob (format above); the context keeps a
+ * device copy and uses it when rst_spanning_forest_batch gets method == NULL.
+ * RST_E_INVAL on a malformed or non-finite blob. */
 rst_status rst_selector_load(rst_ctx *ctx, const void *blob, size_t bytes);
 
 /* Human-readable name of a status code (static string). */

@@ -44,8 +44,14 @@ STAGES = ["hook", "compress", "arcs", "succ", "rank", "parent", "bfs", "select"]
 EXPORTS = [
     "rst_create", "rst_destroy", "rst_set_stream", "rst_set_option", "rst_spanning_tree",
     "rst_components", "rst_spanning_forest", "rst_bfs", "rst_root_forest", "rst_list_rank",
-    "rst_spanning_forest_batch", "rst_selector_load", "rst_status_string",
+    "rst_spanning_forest_batch", "rst_selector_load", "rst_status_string", "rst_features",
+    "rst_feature_stats", "rst_mlp_forward", "rst_mlp_train_step",
 ]
+
+N_FEATURES = 8
+N_HIDDEN = 64
+N_PARAMS = 4866
+SELECTOR_MAGIC = b"RSTSEL01"
 
 
 class RstError(RuntimeError):
@@ -118,6 +124,11 @@ def load_library(path: Optional[str] = None):
                                               P, P, P, ctypes.POINTER(rst_stats)]),
             "rst_selector_load": (S, [P, P, ctypes.c_size_t]),
             "rst_status_string": (ctypes.c_char_p, [S]),
+            "rst_features": (S, [P, ctypes.POINTER(rst_csr), ctypes.POINTER(rst_batch), P]),
+            "rst_feature_stats": (S, [P, P, i64, P]),
+            "rst_mlp_forward": (S, [P, P, P, P, i64, P, P]),
+            "rst_mlp_train_step": (S, [P, P, P, P, P, i64, ctypes.c_float, P, P, P, i64, P,
+                                       ctypes.POINTER(ctypes.c_float)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -283,6 +294,98 @@ class Context:
         self._call("rst_list_rank", A, ctypes.c_void_p(succ.data_ptr()),
                    ctypes.c_void_p(dist.data_ptr()))
         return dist
+
+
+    # -- batches and the selector ---------------------------------------------
+    def _batch(self, vtx_off, arc_off, roots):
+        torch = _torch()
+        _check_dev(vtx_off, torch.int64, "vtx_off")
+        _check_dev(arc_off, torch.int64, "arc_off")
+        _check_dev(roots, torch.int32, "roots")
+        return rst_batch(int(roots.shape[0]), vtx_off.data_ptr(), arc_off.data_ptr(),
+                         roots.data_ptr())
+
+    def spanning_forest_batch(self, offsets, cols, vtx_off, arc_off, roots, method=None,
+                              stats: bool = False, parent=None):
+        """Parents of all packed graphs and the method used per graph (uint8)."""
+        torch = _torch()
+        g = make_csr(offsets, cols)
+        b = self._batch(vtx_off, arc_off, roots)
+        dev = offsets.device
+        if parent is None:
+            parent = torch.empty(g.n, dtype=torch.int32, device=dev)
+        else:
+            _check_dev(parent, torch.int32, "parent")
+            if parent.numel() != g.n:
+                raise ValueError("parent must hold n entries")
+        mout = torch.empty(b.num_graphs, dtype=torch.uint8, device=dev)
+        if method is not None:
+            _check_dev(method, torch.uint8, "method")
+        st = rst_stats()
+        self._call("rst_spanning_forest_batch", ctypes.byref(g), ctypes.byref(b),
+                   ctypes.c_void_p(_ptr(method)) if method is not None else None,
+                   ctypes.c_void_p(parent.data_ptr()), ctypes.c_void_p(mout.data_ptr()),
+                   ctypes.byref(st) if stats else None)
+        return (parent, mout, st.as_dict()) if stats else (parent, mout)
+
+    def features(self, offsets, cols, vtx_off, arc_off, roots):
+        torch = _torch()
+        g = make_csr(offsets, cols)
+        b = self._batch(vtx_off, arc_off, roots)
+        feat = torch.empty((b.num_graphs, N_FEATURES), dtype=torch.float32, device=offsets.device)
+        self._call("rst_features", ctypes.byref(g), ctypes.byref(b),
+                   ctypes.c_void_p(feat.data_ptr()))
+        return feat
+
+    def feature_stats(self, X):
+        torch = _torch()
+        _check_dev(X, torch.float32, "X")
+        norm = torch.empty(2 * N_FEATURES, dtype=torch.float32, device=X.device)
+        self._call("rst_feature_stats", ctypes.c_void_p(X.data_ptr()), int(X.shape[0]),
+                   ctypes.c_void_p(norm.data_ptr()))
+        return norm
+
+    def mlp_forward(self, norm, params, X, logits: bool = True, choice: bool = True):
+        torch = _torch()
+        for t, nm in ((norm, "norm"), (params, "params"), (X, "X")):
+            _check_dev(t, torch.float32, nm)
+        B = int(X.shape[0])
+        lg = torch.empty((B, 2), dtype=torch.float32, device=X.device) if logits else None
+        ch = torch.empty(B, dtype=torch.uint8, device=X.device) if choice else None
+        self._call("rst_mlp_forward", ctypes.c_void_p(norm.data_ptr()),
+                   ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(X.data_ptr()), B,
+                   ctypes.c_void_p(_ptr(lg)) if lg is not None else None,
+                   ctypes.c_void_p(_ptr(ch)) if ch is not None else None)
+        return lg, ch
+
+    def mlp_train_step(self, norm, params, adam_m, adam_v, step, lr, X, y, w, grad=None):
+        """One step; returns the mean weighted loss before the update."""
+        torch = _torch()
+        loss = ctypes.c_float(0.0)
+        self._call("rst_mlp_train_step", ctypes.c_void_p(norm.data_ptr()),
+                   ctypes.c_void_p(params.data_ptr()),
+                   ctypes.c_void_p(_ptr(adam_m)) if adam_m is not None else None,
+                   ctypes.c_void_p(_ptr(adam_v)) if adam_v is not None else None,
+                   int(step), float(lr), ctypes.c_void_p(X.data_ptr()),
+                   ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                   int(X.shape[0]), ctypes.c_void_p(_ptr(grad)) if grad is not None else None,
+                   ctypes.byref(loss))
+        return float(loss.value)
+
+    def selector_load(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._call("rst_selector_load", ctypes.cast(buf, ctypes.c_void_p), len(blob))
+
+
+def selector_blob(norm, params) -> bytes:
+    """Serialise normalisation (16 floats) and parameters (4866 floats)."""
+    import struct
+    import numpy as np
+    norm = np.asarray(norm, dtype="<f4").reshape(-1)
+    params = np.asarray(params, dtype="<f4").reshape(-1)
+    assert norm.size == 2 * N_FEATURES and params.size == N_PARAMS
+    return SELECTOR_MAGIC + struct.pack("<ii", N_FEATURES, N_HIDDEN) + norm.tobytes() + \
+        params.tobytes()
 
 
 _default = {}

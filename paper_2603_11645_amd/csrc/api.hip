@@ -106,11 +106,12 @@ static RankBufs take_rank_bufs(rst_ctx *ctx, int64_t A) {
 // most).  Writes parent, returns the component count in *components.
 rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
                            int32_t *parent, rst_stats *st, int64_t *components,
-                           int32_t *counters, int32_t *cc_out) {
+                           int32_t *counters, int32_t *cc_out, const uint8_t *vmask = nullptr) {
   const int64_t n = g->n;
   const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
   ForestBufs f;
   f.counters = counters;
+  f.vmask = vmask;
   f.cc = cc_out ? cc_out : ws_take<int32_t>(ctx, n);
   f.tu = ws_take<int32_t>(ctx, n);
   f.tv = ws_take<int32_t>(ctx, n);
@@ -208,7 +209,7 @@ rst_status rst_create(rst_ctx **out, int device, void *hip_stream) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       cus > 0)
     ctx->num_cus = cus;
-  for (int i = 0; i < 16; ++i) {
+  for (int i = 0; i < 24; ++i) {
     if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { rst_destroy(ctx); return RST_E_DEVICE; }
   }
   if (hipHostMalloc(reinterpret_cast<void **>(&ctx->host_pinned), 64 * sizeof(int32_t),
@@ -226,8 +227,9 @@ void rst_destroy(rst_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws.base) (void)hipFree(ctx->ws.base);
-  for (int i = 0; i < 16; ++i)
+  for (int i = 0; i < 24; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  selector_free(ctx);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   delete ctx;
 }
@@ -475,13 +477,107 @@ rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *
 rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
                                      const uint8_t *method, int32_t *parent, uint8_t *method_out,
                                      rst_stats *stats) {
-  (void)ctx; (void)g; (void)b; (void)method; (void)parent; (void)method_out; (void)stats;
-  return RST_E_UNSUPPORTED;
-}
-
-rst_status rst_selector_load(rst_ctx *ctx, const void *blob, size_t bytes) {
-  (void)ctx; (void)blob; (void)bytes;
-  return RST_E_UNSUPPORTED;
+  if (!ctx || !parent || !b || b->num_graphs < 1 || !b->vtx_off || !b->arc_off || !b->roots)
+    return RST_E_INVAL;
+  RST_TRY(check_csr(g));
+  if (b->num_graphs > g->n) return RST_E_INVAL;
+  RST_HIP(hipSetDevice(ctx->device));
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  TimingScope timing(ctx, stats != nullptr);
+  const int32_t G = b->num_graphs;
+  const int64_t n = g->n;
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + gconn_ws_bytes(ctx, g) + bfs_ws_bytes(ctx, g) +
+                              ws_bytes(n, 4) + ws_bytes(n, 1) + ws_bytes(G, 1) +
+                              (method ? 0 : selector_scratch_bytes(ctx, g, G))));
+  int32_t *counters = ws_take<int32_t>(ctx, 64);
+  uint8_t *m = ws_take<uint8_t>(ctx, G);
+  uint8_t *vmask = ws_take<uint8_t>(ctx, n);
+  int32_t *level = ws_take<int32_t>(ctx, n);
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+  RST_TRY(run_validation(ctx, g, counters));
+  RST_TRY(enqueue_batch_check(ctx, g, b, counters));
+  RST_TRY(mark(ctx, stats, 16));
+  // per-graph method: given, chosen by the selector, or GConn+Euler for all
+  if (method) {
+    RST_TRY(enqueue_copy_u8(ctx, method, m, G));
+  } else if (ctx->selector) {
+    RST_TRY(run_selector(ctx, g, b, m));
+  } else {
+    RST_TRY(enqueue_fill_u8(ctx, m, G, 0));
+  }
+  RST_TRY(mark(ctx, stats, 17));
+  RST_TRY(enqueue_count_methods(ctx, b, m, counters));
+  RST_TRY(read_counters(ctx, counters));
+  if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
+  const int32_t nbfs = ctx->host_pinned[kCntBatchBfs];
+  const int64_t bfs_vertices = ctx->host_pinned[kCntBatchBfsVtx];
+  if (nbfs > 0) RST_TRY(enqueue_graph_mask(ctx, b, m, vmask));
+  int64_t comps = 0;
+  const size_t ws_after_common = ctx->ws.used;
+  if (nbfs < G) {
+    rst_stats inner;
+    RST_TRY(run_gconn_euler(ctx, g, b->roots, G, parent, stats ? &inner : nullptr, &comps,
+                            counters, nullptr, nbfs > 0 ? vmask : nullptr));
+    if (stats) {
+      for (int i = 0; i < 8; ++i) stats->ms_stage[i] += inner.ms_stage[i];
+      for (int i = 0; i < 4; ++i) stats->ms_kernel[i] = inner.ms_kernel[i];
+      stats->hook_rounds = inner.hook_rounds;
+      stats->rank_rounds = inner.rank_rounds;
+      stats->rank_exits = inner.rank_exits;
+      stats->cross_edges = inner.cross_edges;
+    }
+  }
+  // the GConn scratch is free again (work on the stream is ordered)
+  ctx->ws.used = ws_after_common;
+  int64_t levels = 0;
+  if (nbfs > 0) {
+    // multi-source BFS from the roots of the BFS graphs; parents of the other
+    // graphs' vertices are left as written above
+    BfsBufs bb;
+    RST_TRY(take_bfs_bufs(ctx, g, bb));
+    RST_TRY(mark(ctx, stats, 18));
+    RST_TRY(bfs_reset(ctx, n, level, nullptr, bb));
+    RST_TRY(bfs_seed_roots(ctx, g, b->roots, G, level, parent, bb, counters, m));
+    RST_TRY(bfs_run_levels(ctx, g, level, parent, bb, counters, &levels));
+    RST_TRY(read_counters(ctx, counters));
+    if (ctx->host_pinned[kCntBfsReached] < bfs_vertices) {
+      // a BFS graph is disconnected: its other components are searched from
+      // their minimum ids (labels of the whole packed graph; seeds restricted
+      // to vertices of BFS graphs)
+      ForestBufs f;
+      f.counters = counters;
+      f.cc = ws_take<int32_t>(ctx, n);
+      f.tu = ws_take<int32_t>(ctx, n);
+      f.tv = ws_take<int32_t>(ctx, n);
+      const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
+      int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
+      int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
+      int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(n));
+      // the heavy-chunk list is rebuilt from empty (the GConn stage used it)
+      RST_TRY(enqueue_fill(ctx, counters + kCntChunks, 1, 0));
+      RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
+      RST_TRY(enqueue_compress(ctx, n, f.cc, nullptr, nullptr));
+      RST_TRY(bfs_seed_unreached(ctx, g, f.cc, level, parent, bb, counters, vmask));
+      int64_t l2 = 0;
+      RST_TRY(bfs_run_levels(ctx, g, level, parent, bb, counters, &l2));
+    }
+    RST_TRY(mark(ctx, stats, 19));
+  }
+  if (method_out) RST_TRY(enqueue_copy_u8(ctx, m, method_out, G));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  if (stats) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[16], ctx->ev[17]) == hipSuccess)
+      stats->ms_stage[RST_STAGE_SELECT] = ms;
+    if (nbfs > 0 && hipEventElapsedTime(&ms, ctx->ev[18], ctx->ev[19]) == hipSuccess)
+      stats->ms_stage[RST_STAGE_BFS] = ms;
+    stats->ms_total = 0.f;
+    for (int i = 0; i < 8; ++i) stats->ms_total += stats->ms_stage[i];
+    stats->bfs_levels = levels;
+    stats->components = comps;
+    stats->method_used = nbfs == 0 ? RST_GCONN_EULER : (nbfs == G ? RST_BFS : -1);
+  }
+  return RST_OK;
 }
 
 const char *rst_status_string(rst_status s) {

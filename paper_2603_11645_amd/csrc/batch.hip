@@ -1,0 +1,114 @@
+// batch.hip -- many graphs packed into one CSR (global vertex ids) processed in
+// one pass.  Graphs never share a component, so the forest stages run over the
+// packed graph unchanged: cycle breaking happens once per designated root, the
+// generalisation to forests of Sec. III-D.  The number of launches does not
+// depend on the number of graphs: per-graph work is expressed as per-vertex
+// masks and per-root seeds, built here with one block per graph.
+#include "rst_internal.h"
+#include "device_common.h"
+
+namespace rst {
+
+// vmask[v] = method of v's graph (nonzero: not hooked, handled by BFS)
+__global__ __launch_bounds__(kBlock) void k_graph_mask(const int64_t *__restrict__ vtx_off,
+                                                       const uint8_t *__restrict__ method,
+                                                       uint8_t *vmask) {
+  const int g = blockIdx.x;
+  const int64_t b = vtx_off[g], e = vtx_off[g + 1];
+  const uint8_t m = method[g];
+  for (int64_t v = b + threadIdx.x; v < e; v += kBlock) vmask[v] = m;
+}
+
+// Consistency of the offset tables and roots: vtx_off non-decreasing, the
+// arc table matching the CSR offsets, every root inside its own graph.
+template <class OffT>
+__global__ __launch_bounds__(kBlock) void k_batch_check(int32_t G, int64_t n, int64_t nnz,
+                                                        const OffT *__restrict__ off,
+                                                        const int64_t *__restrict__ vtx_off,
+                                                        const int64_t *__restrict__ arc_off,
+                                                        const int32_t *__restrict__ roots,
+                                                        int32_t *counters) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const int64_t b = vtx_off[g], e = vtx_off[g + 1];
+  bool bad = b < 0 || e < b || e > n || (g == 0 && b != 0) || (g == G - 1 && e != n);
+  if (!bad) {
+    bad = arc_off[g] != (int64_t)off[b] || arc_off[g + 1] != (int64_t)off[e] ||
+          (g == G - 1 && arc_off[g + 1] != nnz);
+    const int32_t r = roots[g];
+    bad = bad || r < b || r >= e;
+  }
+  if (bad) atomicOr(&counters[kCntRangeErr], 1);
+}
+
+// counters[kCntBatchBfs] = graphs with a nonzero method (BFS),
+// counters[kCntBatchBfsVtx] = their vertices
+__global__ __launch_bounds__(kBlock) void k_count_methods(int32_t G,
+                                                          const int64_t *__restrict__ vtx_off,
+                                                          const uint8_t *__restrict__ m,
+                                                          int32_t *counters) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool bfs = g < G && m[g] != 0;
+  wave_count(bfs, &counters[kCntBatchBfs]);
+  if (bfs) atomicAdd(&counters[kCntBatchBfsVtx], (int32_t)(vtx_off[g + 1] - vtx_off[g]));
+}
+
+__global__ void k_copy_u8(const uint8_t *__restrict__ src, uint8_t *dst, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = src[i] ? 1 : 0;
+}
+
+__global__ void k_fill_u8(uint8_t *dst, int64_t count, uint8_t value) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = value;
+}
+
+rst_status enqueue_graph_mask(rst_ctx *ctx, const rst_batch *b, const uint8_t *method,
+                              uint8_t *vmask) {
+  hipLaunchKernelGGL(k_graph_mask, dim3((unsigned)b->num_graphs), dim3(kBlock), 0, ctx->stream,
+                     b->vtx_off, method, vmask);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
+rst_status enqueue_batch_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                               int32_t *counters) {
+  const unsigned grid = grid_for(b->num_graphs, kBlock);
+  if (g->offset_bytes == 4)
+    hipLaunchKernelGGL(k_batch_check<int32_t>, dim3(grid), dim3(kBlock), 0, ctx->stream,
+                       b->num_graphs, g->n, g->nnz, (const int32_t *)g->offsets, b->vtx_off,
+                       b->arc_off, b->roots, counters);
+  else
+    hipLaunchKernelGGL(k_batch_check<int64_t>, dim3(grid), dim3(kBlock), 0, ctx->stream,
+                       b->num_graphs, g->n, g->nnz, (const int64_t *)g->offsets, b->vtx_off,
+                       b->arc_off, b->roots, counters);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
+rst_status enqueue_count_methods(rst_ctx *ctx, const rst_batch *b, const uint8_t *m,
+                                 int32_t *counters) {
+  const int32_t G = b->num_graphs;
+  hipLaunchKernelGGL(k_count_methods, dim3(grid_for(G, kBlock)), dim3(kBlock), 0, ctx->stream, G,
+                     b->vtx_off, m, counters);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
+rst_status enqueue_copy_u8(rst_ctx *ctx, const uint8_t *src, uint8_t *dst, int64_t count) {
+  if (count <= 0) return RST_OK;
+  hipLaunchKernelGGL(k_copy_u8, dim3(grid_for(count, kBlock)), dim3(kBlock), 0, ctx->stream, src,
+                     dst, count);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
+rst_status enqueue_fill_u8(rst_ctx *ctx, uint8_t *dst, int64_t count, uint8_t value) {
+  if (count <= 0) return RST_OK;
+  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(count, kBlock)), dim3(kBlock), 0, ctx->stream, dst,
+                     count, value);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
+}  // namespace rst

@@ -22,7 +22,10 @@ namespace rst {
 
 __global__ void k_bfs_reset(int64_t n, int32_t *level, int32_t *parent, int32_t *cnt) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) { level[v] = -1; parent[v] = -1; }
+  if (v < n) {
+    level[v] = -1;
+    if (parent) parent[v] = -1;
+  }
   if (v < 6) cnt[v] = 0;
 }
 
@@ -46,14 +49,18 @@ __global__ __launch_bounds__(kBlock) void k_bfs_seed(const int32_t *__restrict__
                                                      const OffT *__restrict__ off, int32_t *level,
                                                      int32_t *parent, int32_t *q0, int32_t *h0,
                                                      int32_t *cnt0, int64_t heavy_cap,
-                                                     int32_t *counters, int heavy_deg) {
+                                                     int32_t *counters, int heavy_deg,
+                                                     const uint8_t *__restrict__ gsel) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   int32_t r = -1;
   bool win = false;
-  if (i < nroots) {
+  if (i < nroots && (!gsel || gsel[i])) {
     r = roots[i];
     if (r < 0 || r >= n) atomicOr(&counters[kCntRangeErr], 1);
-    else if (atomicCAS(&level[r], -1, 0) == -1) { win = true; parent[r] = r; }
+    else if (atomicCAS(&level[r], -1, 0) == -1) {
+      win = true;
+      if (parent) parent[r] = r;
+    }
   }
   bfs_enqueue<OffT>(win, r, off, heavy_deg, q0, h0, cnt0, heavy_cap, counters);
 }
@@ -64,10 +71,11 @@ __global__ __launch_bounds__(kBlock) void k_bfs_seed_unreached(int64_t n, const 
                                                                int32_t *level, int32_t *parent,
                                                                int32_t *q0, int32_t *h0, int32_t *cnt0,
                                                                int64_t heavy_cap, int32_t *counters,
-                                                               int heavy_deg) {
+                                                               int heavy_deg,
+                                                               const uint8_t *__restrict__ vsel) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool win = false;
-  if (v < n && cc[v] == (int32_t)v && level[v] == -1) {
+  if (v < n && cc[v] == (int32_t)v && level[v] == -1 && (!vsel || vsel[v])) {
     level[v] = 0;
     parent[v] = (int32_t)v;
     win = true;
@@ -122,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(
       bool win = false;
       if (w >= 0 && level[w] == -1 && atomicCAS(&level[w], -1, next_level) == -1) {
         win = true;
-        parent[w] = src;
+        if (parent) parent[w] = src;
       }
       bfs_enqueue<OffT>(win, w, off, heavy_deg, qout, hout, cout, heavy_cap, counters);
     }
@@ -138,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(
       bool win = false;
       if (w >= 0 && level[w] == -1 && atomicCAS(&level[w], -1, next_level) == -1) {
         win = true;
-        parent[w] = u;
+        if (parent) parent[w] = u;
       }
       bfs_enqueue<OffT>(win, w, off, heavy_deg, qout, hout, cout, heavy_cap, counters);
     }
@@ -164,33 +172,35 @@ rst_status bfs_reset(rst_ctx *ctx, int64_t n, int32_t *level, int32_t *parent, B
 }
 
 rst_status bfs_seed_roots(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
-                          int32_t *level, int32_t *parent, BfsBufs &b, int32_t *counters) {
+                          int32_t *level, int32_t *parent, BfsBufs &b, int32_t *counters,
+                          const uint8_t *gsel) {
   const int hd = ctx->opt.heavy_degree;
   if (g->offset_bytes == 4)
     hipLaunchKernelGGL(k_bfs_seed<int32_t>, dim3(grid_for(nroots, kBlock)), dim3(kBlock), 0,
                        ctx->stream, roots, nroots, g->n, (const int32_t *)g->offsets, level, parent,
-                       b.q[0], b.h[0], b.cnt, b.heavy_cap, counters, hd);
+                       b.q[0], b.h[0], b.cnt, b.heavy_cap, counters, hd, gsel);
   else
     hipLaunchKernelGGL(k_bfs_seed<int64_t>, dim3(grid_for(nroots, kBlock)), dim3(kBlock), 0,
                        ctx->stream, roots, nroots, g->n, (const int64_t *)g->offsets, level, parent,
-                       b.q[0], b.h[0], b.cnt, b.heavy_cap, counters, hd);
+                       b.q[0], b.h[0], b.cnt, b.heavy_cap, counters, hd, gsel);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }
 
 rst_status bfs_seed_unreached(rst_ctx *ctx, const rst_csr *g, const int32_t *cc, int32_t *level,
-                              int32_t *parent, BfsBufs &b, int32_t *counters) {
+                              int32_t *parent, BfsBufs &b, int32_t *counters,
+                              const uint8_t *vsel) {
   const int hd = ctx->opt.heavy_degree;
   // counts of slot 0 must start from zero for this new frontier
   RST_TRY(enqueue_fill(ctx, b.cnt, 6, 0));
   if (g->offset_bytes == 4)
     hipLaunchKernelGGL(k_bfs_seed_unreached<int32_t>, dim3(grid_for(g->n, kBlock)), dim3(kBlock), 0,
                        ctx->stream, g->n, (const int32_t *)g->offsets, cc, level, parent, b.q[0],
-                       b.h[0], b.cnt, b.heavy_cap, counters, hd);
+                       b.h[0], b.cnt, b.heavy_cap, counters, hd, vsel);
   else
     hipLaunchKernelGGL(k_bfs_seed_unreached<int64_t>, dim3(grid_for(g->n, kBlock)), dim3(kBlock), 0,
                        ctx->stream, g->n, (const int64_t *)g->offsets, cc, level, parent, b.q[0],
-                       b.h[0], b.cnt, b.heavy_cap, counters, hd);
+                       b.h[0], b.cnt, b.heavy_cap, counters, hd, vsel);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }
@@ -208,13 +218,13 @@ static rst_status launch_level(rst_ctx *ctx, const rst_csr *g, int32_t L, unsign
 }
 
 rst_status bfs_run_levels(rst_ctx *ctx, const rst_csr *g, int32_t *level, int32_t *parent,
-                          BfsBufs &b, int32_t *counters, int64_t *levels_out) {
+                          BfsBufs &b, int32_t *counters, int64_t *levels_out, int64_t max_levels) {
   const int per_sync = ctx->opt.bfs_levels_per_sync < 1 ? 1 : ctx->opt.bfs_levels_per_sync;
   const unsigned grid = ctx->opt.bfs_grid > 0 ? (unsigned)ctx->opt.bfs_grid
                                               : (unsigned)(ctx->num_cus * 4);
   int64_t L = 0;
   for (;;) {
-    for (int k = 0; k < per_sync; ++k, ++L) {
+    for (int k = 0; k < per_sync && (max_levels < 0 || L < max_levels); ++k, ++L) {
       if (g->offset_bytes == 4)
         RST_TRY(launch_level<int32_t>(ctx, g, (int32_t)L, grid, level, parent, b, counters));
       else
@@ -225,6 +235,7 @@ rst_status bfs_run_levels(rst_ctx *ctx, const rst_csr *g, int32_t *level, int32_
                            hipMemcpyDeviceToHost, ctx->stream));
     RST_HIP(hipStreamSynchronize(ctx->stream));
     if (ctx->host_pinned[0] == 0 && ctx->host_pinned[1] == 0) break;
+    if (max_levels >= 0 && L >= max_levels) break;   // capped search (depth probes)
     if (L > g->n + per_sync) return RST_E_DEVICE;   // cannot happen for a valid CSR
   }
   RST_HIP(hipMemcpyAsync(ctx->host_pinned + 2, counters + kCntBfsLast, sizeof(int32_t),

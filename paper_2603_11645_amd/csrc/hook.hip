@@ -153,7 +153,8 @@ template <class OffT>
 __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
     int64_t n, const OffT *__restrict__ off, const int32_t *__restrict__ cols, int32_t *cc,
     int32_t *tu, int32_t *tv, int2 *cross, int32_t *tile_cross, int32_t *tile_lvl,
-    int32_t *counters, int64_t *chunks, int64_t chunk_cap, int heavy_deg) {
+    int32_t *counters, int64_t *chunks, int64_t chunk_cap, int heavy_deg,
+    const uint8_t *__restrict__ vmask) {
   __shared__ int lp[kTile];
   __shared__ int16_t eu[kTile];     // local endpoints of the edge held by a slot (-1: none)
   __shared__ int16_t ev[kTile];
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
   for (int j = 0; j < kTilePer; ++j) {
     const int li = tid * kTilePer + j;
     dg[j] = 0;
-    if (li < cnt) {
+    // a masked vertex (its graph is handled by another method) offers no arcs
+    if (li < cnt && !(vmask && vmask[v0 + li])) {
       const int64_t d = (int64_t)(o[j + 1] - o[j]);
       if (d > heavy_deg) {
         const int64_t v = v0 + li;
@@ -524,7 +526,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 0);
     hipLaunchKernelGGL(k_hook_tile<int32_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
                        off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, f.counters,
-                       chunks, chunk_cap, ctx->opt.heavy_degree);
+                       chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     hipLaunchKernelGGL(k_tile_regions<int32_t>, dim3(grid_for(tiles, kBlock)), dim3(kBlock), 0,
@@ -539,7 +541,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 0);
     hipLaunchKernelGGL(k_hook_tile<int64_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
                        off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, f.counters,
-                       chunks, chunk_cap, ctx->opt.heavy_degree);
+                       chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     hipLaunchKernelGGL(k_tile_regions<int64_t>, dim3(grid_for(tiles, kBlock)), dim3(kBlock), 0,

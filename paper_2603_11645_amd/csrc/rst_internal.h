@@ -29,6 +29,21 @@ struct Options {
 
 struct Selector;
 
+// batch.hip
+rst_status enqueue_graph_mask(rst_ctx *ctx, const rst_batch *b, const uint8_t *method,
+                              uint8_t *vmask);
+rst_status enqueue_batch_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                               int32_t *counters);
+rst_status enqueue_count_methods(rst_ctx *ctx, const rst_batch *b, const uint8_t *m,
+                                 int32_t *counters);
+rst_status enqueue_copy_u8(rst_ctx *ctx, const uint8_t *src, uint8_t *dst, int64_t count);
+rst_status enqueue_fill_u8(rst_ctx *ctx, uint8_t *dst, int64_t count, uint8_t value);
+
+// selector.hip
+size_t selector_scratch_bytes(const rst_ctx *ctx, const rst_csr *g, int32_t G);
+rst_status run_selector(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, uint8_t *choice);
+void selector_free(rst_ctx *ctx);
+
 }  // namespace rst
 
 struct rst_ctx {
@@ -37,7 +52,7 @@ struct rst_ctx {
   int num_cus = 256;
   rst::Workspace ws;
   rst::Options opt;
-  hipEvent_t ev[16] = {};
+  hipEvent_t ev[24] = {};   // 0-6 stages, 8-15 kernel pairs, 16-19 batch marks
   int32_t *host_pinned = nullptr;   // small pinned host buffer for flag readback
   bool timing = false;              // record per-kernel events (a stats struct was passed)
   rst::Selector *selector = nullptr;
@@ -93,6 +108,7 @@ struct ForestBufs {
   int32_t *tu, *tv;    // [slots] recorded spanning edge per slot, -1 = empty
   int32_t *comp_root;  // [n] designated root of the component labelled v, or -1
   int32_t *counters;   // [16] device counters (see kCnt*)
+  const uint8_t *vmask = nullptr;   // [n] nonzero: vertex excluded from hooking (nullable)
 };
 
 enum {
@@ -104,6 +120,8 @@ enum {
   kCntBfsLast = 5,     // deepest non-empty BFS level
   kCntCross = 6,       // cross-tile edges appended by the tile phase of hooking
   kCntExits = 7,       // segment exits of the tiled list ranking
+  kCntBatchBfs = 8,    // graphs of a batch assigned to BFS
+  kCntBatchBfsVtx = 9, // vertices of those graphs
   kCntTotal = 16
 };
 
@@ -174,16 +192,37 @@ struct BfsBufs {
   int64_t heavy_cap;
 };
 size_t bfs_heavy_capacity(const rst_ctx *ctx, int64_t n, int64_t nnz);
-// level[] = parent[] = -1, counts zeroed
+// level[] = -1 (and parent[] = -1 unless parent is NULL), counts zeroed
 rst_status bfs_reset(rst_ctx *ctx, int64_t n, int32_t *level, int32_t *parent, BfsBufs &b);
-// seed the level-0 frontier with a device list of roots
+// seed the level-0 frontier with a device list of roots; with gsel non-NULL
+// only roots[g] with gsel[g] != 0 are seeded
 rst_status bfs_seed_roots(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
-                          int32_t *level, int32_t *parent, BfsBufs &b, int32_t *counters);
+                          int32_t *level, int32_t *parent, BfsBufs &b, int32_t *counters,
+                          const uint8_t *gsel = nullptr);
 // seed the level-0 frontier with every unreached vertex v that has cc[v] == v
+// (and vsel[v] != 0 when vsel is non-NULL)
 rst_status bfs_seed_unreached(rst_ctx *ctx, const rst_csr *g, const int32_t *cc, int32_t *level,
-                              int32_t *parent, BfsBufs &b, int32_t *counters);
+                              int32_t *parent, BfsBufs &b, int32_t *counters,
+                              const uint8_t *vsel = nullptr);
 // run levels until the frontier is empty; *levels_out = deepest level reached
+// parent may be NULL (levels only); max_levels >= 0 caps the search
 rst_status bfs_run_levels(rst_ctx *ctx, const rst_csr *g, int32_t *level, int32_t *parent,
-                          BfsBufs &b, int32_t *counters, int64_t *levels_out);
+                          BfsBufs &b, int32_t *counters, int64_t *levels_out,
+                          int64_t max_levels = -1);
+
+// batch.hip
+rst_status enqueue_graph_mask(rst_ctx *ctx, const rst_batch *b, const uint8_t *method,
+                              uint8_t *vmask);
+rst_status enqueue_batch_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                               int32_t *counters);
+rst_status enqueue_count_methods(rst_ctx *ctx, const rst_batch *b, const uint8_t *m,
+                                 int32_t *counters);
+rst_status enqueue_copy_u8(rst_ctx *ctx, const uint8_t *src, uint8_t *dst, int64_t count);
+rst_status enqueue_fill_u8(rst_ctx *ctx, uint8_t *dst, int64_t count, uint8_t value);
+
+// selector.hip
+size_t selector_scratch_bytes(const rst_ctx *ctx, const rst_csr *g, int32_t G);
+rst_status run_selector(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, uint8_t *choice);
+void selector_free(rst_ctx *ctx);
 
 }  // namespace rst
