@@ -180,19 +180,19 @@ def main():
     n, nnz, A = g.n, g.nnz, 2 * g.n
     w_o = g.offset_bytes
     X = stats[-1]["cross_edges"]
-    levels = max(1, stats[-1]["hook_rounds"] - 1)
     kern_bytes = {
         # offsets + neighbour ids read, labels/edge slots written, cross list written
         "hook_tile": w_o * (n + 1) + 4 * nnz + 12 * n + 8 * X,
-        # cross list scanned once over all levels (per launch: one level's share)
-        "cross": 8 * X / levels,
+        # cross stage (deduplication pass + level merges, timed as one unit):
+        # every cross edge read once and its two tree labels gathered
+        "cross": 16 * X,
         # per arc: slot edge (4) + next of twin (4) + end-of-list successor (2,
         # half the arcs) + exit index (4) + ranking word (8)
         "rank_tile": 22 * A,
         # per slot: edge read (8) + two list-head exchanges (16) + next pair (8)
         "link": 32 * n,
     }
-    kern_launches = {"hook_tile": 1, "cross": levels, "rank_tile": 1, "link": 1}
+    kern_launches = {"hook_tile": 1, "cross": 1, "rank_tile": 1, "link": 1}
     kernels = {}
     for k in kern_ms:
         per_launch = kern_ms[k] / kern_launches[k]

@@ -90,15 +90,24 @@ typedef struct {
   float ms_total;
   float ms_stage[8];
   float ms_kernel[4];     /* single kernels, see RST_KERNEL_*                  */
-  int64_t hook_rounds;    /* hooking launches (tile pass + cross levels)       */
-  int64_t rank_rounds;    /* pointer-jumping launches on the contracted list   */
+  int64_t hook_rounds;    /* levels of the binary tree over vertex tiles + 1   */
+  int64_t rank_rounds;    /* pointer-jumping rounds on the contracted list     */
   int64_t rank_exits;     /* length of the contracted list (segment exits)     */
-  int64_t cross_edges;    /* edges left to the global cross phase of hooking   */
+  int64_t cross_edges;    /* edges left to the cross-tile phase of hooking     */
   int64_t bfs_levels;     /* deepest BFS level reached (eccentricity of root)  */
   int64_t components;     /* connected components found                        */
   int32_t method_used;    /* rst_method actually run (batch: -1 if mixed)      */
-  int32_t reserved;
+  int32_t paths;          /* RST_PATH_* bits: which variant of a stage ran     */
 } rst_stats;
+
+/* Bits of rst_stats.paths.  Stages first try a one-workgroup variant and fall
+ * back to a multi-workgroup one when their data do not fit it. */
+enum {
+  RST_PATH_CROSS_GLOBAL = 1,  /* cross-tile merge ran in global memory (the     *
+                               * kept cross edges did not fit one workgroup)    */
+  RST_PATH_RANK_GLOBAL = 2    /* contracted list ranked by multi-workgroup      *
+                               * rounds (too long for one workgroup)            */
+};
 
 /* Indices of rst_stats.ms_kernel (HIP-event time of one launch each). */
 enum {
@@ -113,9 +122,16 @@ typedef enum {
   RST_OPT_VALIDATE = 0,        /* 1: check offsets/neighbour ids before running (O(nnz)) */
   RST_OPT_BFS_LEVELS_PER_SYNC = 1, /* BFS levels launched between host checks (>= 1)   */
   RST_OPT_BFS_GRID = 2,        /* blocks per BFS level launch (0 = automatic)          */
-  RST_OPT_RANK_ELEMS_PER_THREAD = 3, /* list-ranking elements per thread (1, 2, 4, 8)  */
-  RST_OPT_HEAVY_DEGREE = 4     /* degree above which a vertex's arcs are split over blocks */
+  RST_OPT_RANK_ELEMS_PER_THREAD = 3, /* words per thread of the multi-workgroup list-
+                                      * ranking rounds (1, 2, 4, 8)                 */
+  RST_OPT_HEAVY_DEGREE = 4,    /* hooking: degree above which a vertex's arcs are cut
+                                * into chunks hooked by many workgroups (32 .. 2^24) */
+  RST_OPT_SWEEP_BLOCK = 5,     /* threads per workgroup of the per-vertex and per-slot
+                                * sweeps (64, 128, 256, 512, 1024)                 */
+  RST_OPT_BFS_HEAVY_DEGREE = 6 /* BFS: degree above which a frontier vertex's arcs are
+                                * expanded by many workgroups (32 .. 2^24)          */
 } rst_option;
+#define RST_NUM_OPTIONS 7
 
 /* Create a context on HIP device `device` bound to `hip_stream` (a hipStream_t,
  * NULL = the default stream).  *out receives the context.  Errors: RST_E_INVAL
@@ -129,8 +145,12 @@ void rst_destroy(rst_ctx *ctx);
 rst_status rst_set_stream(rst_ctx *ctx, void *hip_stream);
 
 /* Set a tunable (see rst_option).  RST_E_INVAL for an unknown option or a value
- * out of range. */
+ * out of range.  Every value gives the same results; only the speed changes. */
 rst_status rst_set_option(rst_ctx *ctx, rst_option opt, int64_t value);
+
+/* Current value of a tunable into *value (host).  RST_E_INVAL for an unknown
+ * option or NULL pointers. */
+rst_status rst_get_option(const rst_ctx *ctx, rst_option opt, int64_t *value);
 
 /* Rooted spanning tree of the graph (Sec. I) by `method` (RST_AUTO runs the
  * selector on this one graph).  parent: device int32 [n], written completely.
@@ -237,6 +257,49 @@ rst_status rst_mlp_train_step(rst_ctx *ctx, const float *norm, float *params, fl
  * device copy and uses it when rst_spanning_forest_batch gets method == NULL.
  * RST_E_INVAL on a malformed or non-finite blob. */
 rst_status rst_selector_load(rst_ctx *ctx, const void *blob, size_t bytes);
+
+/* Check on the device that parent is a rooted spanning forest of g under the
+ * convention of rst_spanning_tree (Sec. I per component: root's component
+ * rooted at root, every other one at its minimum id): every entry a vertex id,
+ * exactly the designated roots self-parented, every other parent a neighbour,
+ * and every vertex reaching its component's root.  *num_failures (host)
+ * receives the number of failed checks (0: valid); *first_bad (host, nullable)
+ * the smallest failing vertex or -1.  parent: device int32 [n]. */
+rst_status rst_verify(rst_ctx *ctx, const rst_csr *g, int32_t root, const int32_t *parent,
+                      int64_t *num_failures, int64_t *first_bad);
+
+/* Result of rst_autotune (host struct). */
+typedef struct {
+  int32_t num_options;    /* entries used in options[] / values[]                 */
+  int32_t options[8];     /* rst_option ids of the method's knobs                  */
+  int64_t values[8];      /* the chosen value of each (now set on the context)      */
+  float ms_best;          /* median time per call with the chosen setting           */
+  float ms_default;       /* median time per call with the setting before tuning    */
+  int32_t candidates;     /* settings timed besides the starting one                */
+  int32_t rejected;       /* settings whose output failed rst_verify (never chosen) */
+} rst_tune_result;
+
+/* Autotune the context's tunables for `method` on graph g and root: coordinate
+ * descent over the method's knobs (GConn+Euler: sweep block size, hooking
+ * heavy degree, ranking words per thread; BFS: levels per sync, grid, heavy
+ * degree), each candidate timed as the median of `reps` calls (1..101) and its
+ * output checked with rst_verify.  The best setting is applied to the context
+ * and recorded in its tuning cache under (GPU architecture, method,
+ * floor(log2 n), floor(log2 nnz/n)).  Allocates a device buffer of n int32 for
+ * the duration of the call.  result: host, nullable. */
+rst_status rst_autotune(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_method method,
+                        int32_t reps, rst_tune_result *result);
+
+/* Write the context's tuning cache to a JSON file at host path `path`
+ * ({"format": "rst-tune-1", "entries": {key: {"ms": t, "options": {id: value}}}}). */
+rst_status rst_tune_save(const rst_ctx *ctx, const char *path);
+
+/* Merge the entries of a JSON tuning cache file into the context's cache; if g
+ * is non-NULL and an entry matches (architecture, method, size class of g),
+ * apply its setting (*applied = 1, host, nullable).  RST_E_INVAL for a missing
+ * or malformed file or an out-of-range value (nothing is applied then). */
+rst_status rst_tune_load(rst_ctx *ctx, const char *path, const rst_csr *g, rst_method method,
+                         int32_t *applied);
 
 /* Human-readable name of a status code (static string). */
 const char *rst_status_string(rst_status s);

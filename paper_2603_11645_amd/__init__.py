@@ -37,6 +37,11 @@ OPT_BFS_LEVELS_PER_SYNC = 1
 OPT_BFS_GRID = 2
 OPT_RANK_ELEMS_PER_THREAD = 3
 OPT_HEAVY_DEGREE = 4
+OPT_SWEEP_BLOCK = 5
+OPT_BFS_HEAVY_DEGREE = 6
+
+PATH_CROSS_GLOBAL = 1
+PATH_RANK_GLOBAL = 2
 
 STAGES = ["hook", "compress", "arcs", "succ", "rank", "parent", "bfs", "select"]
 
@@ -45,7 +50,8 @@ EXPORTS = [
     "rst_create", "rst_destroy", "rst_set_stream", "rst_set_option", "rst_spanning_tree",
     "rst_components", "rst_spanning_forest", "rst_bfs", "rst_root_forest", "rst_list_rank",
     "rst_spanning_forest_batch", "rst_selector_load", "rst_status_string", "rst_features",
-    "rst_feature_stats", "rst_mlp_forward", "rst_mlp_train_step",
+    "rst_feature_stats", "rst_mlp_forward", "rst_mlp_train_step", "rst_get_option",
+    "rst_verify", "rst_autotune", "rst_tune_save", "rst_tune_load",
 ]
 
 N_FEATURES = 8
@@ -73,13 +79,25 @@ class rst_batch(ctypes.Structure):
 KERNELS = ["hook_tile", "cross", "rank_tile", "link"]
 
 
+class rst_tune_result(ctypes.Structure):
+    _fields_ = [("num_options", ctypes.c_int32), ("options", ctypes.c_int32 * 8),
+                ("values", ctypes.c_int64 * 8), ("ms_best", ctypes.c_float),
+                ("ms_default", ctypes.c_float), ("candidates", ctypes.c_int32),
+                ("rejected", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {"options": {int(self.options[i]): int(self.values[i]) for i in range(self.num_options)},
+                "ms_best": self.ms_best, "ms_default": self.ms_default,
+                "candidates": self.candidates, "rejected": self.rejected}
+
+
 class rst_stats(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_float), ("ms_stage", ctypes.c_float * 8),
                 ("ms_kernel", ctypes.c_float * 4),
                 ("hook_rounds", ctypes.c_int64), ("rank_rounds", ctypes.c_int64),
                 ("rank_exits", ctypes.c_int64), ("cross_edges", ctypes.c_int64),
                 ("bfs_levels", ctypes.c_int64), ("components", ctypes.c_int64),
-                ("method_used", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("method_used", ctypes.c_int32), ("paths", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"ms_total": self.ms_total,
@@ -88,7 +106,7 @@ class rst_stats(ctypes.Structure):
                 "hook_rounds": self.hook_rounds, "rank_rounds": self.rank_rounds,
                 "rank_exits": self.rank_exits, "cross_edges": self.cross_edges,
                 "bfs_levels": self.bfs_levels, "components": self.components,
-                "method_used": self.method_used}
+                "method_used": self.method_used, "paths": self.paths}
 
 
 _lib = None
@@ -129,6 +147,14 @@ def load_library(path: Optional[str] = None):
             "rst_mlp_forward": (S, [P, P, P, P, i64, P, P]),
             "rst_mlp_train_step": (S, [P, P, P, P, P, i64, ctypes.c_float, P, P, P, i64, P,
                                        ctypes.POINTER(ctypes.c_float)]),
+            "rst_get_option": (S, [P, ctypes.c_int, ctypes.POINTER(i64)]),
+            "rst_verify": (S, [P, ctypes.POINTER(rst_csr), i32, P, ctypes.POINTER(i64),
+                               ctypes.POINTER(i64)]),
+            "rst_autotune": (S, [P, ctypes.POINTER(rst_csr), i32, ctypes.c_int, i32,
+                                 ctypes.POINTER(rst_tune_result)]),
+            "rst_tune_save": (S, [P, ctypes.c_char_p]),
+            "rst_tune_load": (S, [P, ctypes.c_char_p, ctypes.POINTER(rst_csr), ctypes.c_int,
+                                  ctypes.POINTER(i32)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(lib, name)
@@ -222,6 +248,39 @@ class Context:
 
     def set_option(self, opt: int, value: int):
         self._call("rst_set_option", int(opt), int(value))
+
+    def get_option(self, opt: int) -> int:
+        v = ctypes.c_int64(0)
+        self._call("rst_get_option", int(opt), ctypes.byref(v))
+        return int(v.value)
+
+    def verify(self, offsets, cols, root, parent):
+        """(failures, first failing vertex or -1) of the device check rst_verify."""
+        torch = _torch()
+        g = make_csr(offsets, cols)
+        _check_dev(parent, torch.int32, "parent")
+        bad, first = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._call("rst_verify", ctypes.byref(g), int(root), ctypes.c_void_p(parent.data_ptr()),
+                   ctypes.byref(bad), ctypes.byref(first))
+        return int(bad.value), int(first.value)
+
+    def autotune(self, offsets, cols, root=0, method="gconn", reps: int = 3) -> dict:
+        g = make_csr(offsets, cols)
+        res = rst_tune_result()
+        self._call("rst_autotune", ctypes.byref(g), int(root), _METHODS[method], int(reps),
+                   ctypes.byref(res))
+        return res.as_dict()
+
+    def tune_save(self, path: str):
+        self._call("rst_tune_save", os.fsencode(path))
+
+    def tune_load(self, path: str, offsets=None, cols=None, method="gconn") -> bool:
+        """Merge a tuning cache file; apply the entry matching the graph if given."""
+        g = make_csr(offsets, cols) if offsets is not None else None
+        applied = ctypes.c_int32(0)
+        self._call("rst_tune_load", os.fsencode(path), ctypes.byref(g) if g is not None else None,
+                   _METHODS[method], ctypes.byref(applied))
+        return bool(applied.value)
 
     # -- entry points ---------------------------------------------------------
     def spanning_tree(self, offsets, cols, root: int = 0, method="gconn", parent=None,

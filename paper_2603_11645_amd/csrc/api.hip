@@ -83,20 +83,15 @@ static inline rst_status mark(rst_ctx *ctx, rst_stats *st, int i) {
 
 static size_t rank_ws_bytes(int64_t A) {
   return ws_bytes(rank_exit_capacity(A), 4) + ws_bytes(rank_exit_capacity(A), 8) +
-         ws_bytes(rank_tile_count(A), 4) + ws_bytes(rank_tile_count(A) + 1, 8);
+         ws_bytes(rank_small_capacity(A), 8) + ws_bytes(rank_tile_count(A), 4) +
+         ws_bytes(rank_tile_count(A) + 1, 8);
 }
-
-struct RankBufs {
-  int32_t *exits;
-  uint64_t *crank;
-  int32_t *tile_exits;
-  int64_t *tile_base;
-};
 
 static RankBufs take_rank_bufs(rst_ctx *ctx, int64_t A) {
   RankBufs r;
   r.exits = ws_take<int32_t>(ctx, rank_exit_capacity(A));
   r.crank = ws_take<uint64_t>(ctx, rank_exit_capacity(A));
+  r.ctmp = ws_take<uint64_t>(ctx, rank_small_capacity(A));
   r.tile_exits = ws_take<int32_t>(ctx, rank_tile_count(A));
   r.tile_base = ws_take<int64_t>(ctx, rank_tile_count(A) + 1);
   return r;
@@ -134,17 +129,28 @@ rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
   RST_TRY(mark(ctx, st, 3));
   // the successor pass is fused into the first ranking pass (stage "succ" stays empty)
   RST_TRY(mark(ctx, st, 4));
-  int rounds = 0;
-  int64_t exits_n = 0;
   int32_t *xid = ws_take<int32_t>(ctx, 2 * n);
   SlotArcs arcs{f.tu, f.tv, next, head, f.cc, f.comp_root, n, ws_take<int32_t>(ctx, n)};
-  RST_TRY(enqueue_rank_tiled(ctx, 2 * n, rank, xid, rb.exits, rb.crank, rb.tile_exits,
-                             rb.tile_base, &exits_n, &rounds, &arcs, false));
+  RST_TRY(enqueue_rank_tiled(ctx, 2 * n, rank, xid, rb, counters, &arcs, false));
   RST_TRY(mark(ctx, st, 5));
   RST_TRY(enqueue_expand_parent(ctx, n, n, f.tu, f.tv, rank, xid, rb.tile_base, rb.crank, f.cc,
                                 f.comp_root, parent, counters));
   RST_TRY(mark(ctx, st, 6));
   RST_TRY(read_counters(ctx, counters));
+  const bool rank_fallback = ctx->host_pinned[kCntRankOverflow] != 0;
+  if (rank_fallback) {
+    // contracted list too long for the one-block ranking: rank it in
+    // multi-block rounds, then the parent rule runs again
+    RST_TRY(rank_overflow_fallback(ctx, rb, counters));
+    RST_TRY(enqueue_expand_parent(ctx, n, n, f.tu, f.tv, rank, xid, rb.tile_base, rb.crank, f.cc,
+                                  f.comp_root, parent, counters));
+    RST_TRY(mark(ctx, st, 6));
+    RST_TRY(read_counters(ctx, counters));
+  }
+  const int rounds = ctx->host_pinned[kCntRankRounds];
+  const int64_t exits_n = ctx->host_pinned[kCntExits];
+  const int32_t paths = (ctx->host_pinned[kCntCrossOverflow] ? RST_PATH_CROSS_GLOBAL : 0) |
+                        (rank_fallback ? RST_PATH_RANK_GLOBAL : 0);
   if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
   if (ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
   *components = ctx->host_pinned[kCntComponents];
@@ -159,6 +165,7 @@ rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
     st->cross_edges = ctx->host_pinned[kCntCross];
     st->components = *components;
     st->method_used = RST_GCONN_EULER;
+    st->paths = paths;
   }
   return RST_OK;
 }
@@ -230,6 +237,7 @@ void rst_destroy(rst_ctx *ctx) {
   for (int i = 0; i < 24; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   selector_free(ctx);
+  tune_free(ctx);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   delete ctx;
 }
@@ -260,6 +268,29 @@ rst_status rst_set_option(rst_ctx *ctx, rst_option opt, int64_t value) {
       if (value < 32 || value > (1 << 24)) return RST_E_INVAL;
       ctx->opt.heavy_degree = (int)value;
       return RST_OK;
+    case RST_OPT_SWEEP_BLOCK:
+      if (value != 64 && value != 128 && value != 256 && value != 512 && value != 1024)
+        return RST_E_INVAL;
+      ctx->opt.sweep_block = (int)value;
+      return RST_OK;
+    case RST_OPT_BFS_HEAVY_DEGREE:
+      if (value < 32 || value > (1 << 24)) return RST_E_INVAL;
+      ctx->opt.bfs_heavy_degree = (int)value;
+      return RST_OK;
+  }
+  return RST_E_INVAL;
+}
+
+rst_status rst_get_option(const rst_ctx *ctx, rst_option opt, int64_t *value) {
+  if (!ctx || !value) return RST_E_INVAL;
+  switch (opt) {
+    case RST_OPT_VALIDATE: *value = ctx->opt.validate; return RST_OK;
+    case RST_OPT_BFS_LEVELS_PER_SYNC: *value = ctx->opt.bfs_levels_per_sync; return RST_OK;
+    case RST_OPT_BFS_GRID: *value = ctx->opt.bfs_grid; return RST_OK;
+    case RST_OPT_RANK_ELEMS_PER_THREAD: *value = ctx->opt.rank_elems_per_thread; return RST_OK;
+    case RST_OPT_HEAVY_DEGREE: *value = ctx->opt.heavy_degree; return RST_OK;
+    case RST_OPT_SWEEP_BLOCK: *value = ctx->opt.sweep_block; return RST_OK;
+    case RST_OPT_BFS_HEAVY_DEGREE: *value = ctx->opt.bfs_heavy_degree; return RST_OK;
   }
   return RST_E_INVAL;
 }
@@ -363,6 +394,43 @@ rst_status rst_components(rst_ctx *ctx, const rst_csr *g, int32_t *label,
   return RST_OK;
 }
 
+rst_status rst_verify(rst_ctx *ctx, const rst_csr *g, int32_t root, const int32_t *parent,
+                      int64_t *num_failures, int64_t *first_bad) {
+  if (!ctx || !parent || !num_failures) return RST_E_INVAL;
+  RST_TRY(check_csr(g));
+  if (root < 0 || root >= g->n) return RST_E_INVAL;
+  RST_HIP(hipSetDevice(ctx->device));
+  const int64_t n = g->n;
+  const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 5 * ws_bytes(n, 4) + hook_ws_bytes(ctx, g)));
+  int32_t *counters = ws_take<int32_t>(ctx, 64);
+  int32_t *vc = counters + 40;
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+  RST_TRY(enqueue_fill(ctx, vc, 1, 0));
+  RST_TRY(enqueue_fill(ctx, vc + 1, 1, 0x7fffffff));
+  RST_TRY(run_validation(ctx, g, counters));
+  // component labels of the graph (min ids) by the library's own hooking
+  ForestBufs f;
+  f.counters = counters;
+  f.cc = ws_take<int32_t>(ctx, n);
+  f.tu = ws_take<int32_t>(ctx, n);
+  f.tv = ws_take<int32_t>(ctx, n);
+  int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
+  int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
+  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(n));
+  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
+  RST_TRY(enqueue_compress(ctx, n, f.cc, nullptr, nullptr));
+  int32_t *anc0 = ws_take<int32_t>(ctx, n);
+  int32_t *anc1 = ws_take<int32_t>(ctx, n);
+  RST_TRY(enqueue_verify(ctx, g, root, f.cc, parent, anc0, anc1, vc));
+  RST_HIP(hipMemcpyAsync(ctx->host_pinned + 40, vc, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  *num_failures = ctx->host_pinned[40];
+  if (first_bad) *first_bad = ctx->host_pinned[40] ? ctx->host_pinned[41] : -1;
+  return RST_OK;
+}
+
 rst_status rst_spanning_forest(rst_ctx *ctx, const rst_csr *g, int32_t *label, int32_t *tu,
                                int32_t *tv, int64_t *num_edges) {
   if (!ctx || !label || !tu || !tv) return RST_E_INVAL;
@@ -446,11 +514,16 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
   RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, cc, comp_root, parent, counters));
   RST_TRY(enqueue_link(ctx, t, eu, ev, head, next));
   SlotArcs arcs{eu, ev, next, head, cc, comp_root, n, ws_take<int32_t>(ctx, n)};
-  RST_TRY(enqueue_rank_tiled(ctx, 2 * t, rank, xid, rb.exits, rb.crank, rb.tile_exits,
-                             rb.tile_base, nullptr, nullptr, &arcs, false));
+  RST_TRY(enqueue_rank_tiled(ctx, 2 * t, rank, xid, rb, counters, &arcs, false));
   RST_TRY(enqueue_expand_parent(ctx, t, n, eu, ev, rank, xid, rb.tile_base, rb.crank, cc,
                                 comp_root, parent, counters));
   RST_TRY(read_counters(ctx, counters));
+  if (ctx->host_pinned[kCntRankOverflow]) {
+    RST_TRY(rank_overflow_fallback(ctx, rb, counters));
+    RST_TRY(enqueue_expand_parent(ctx, t, n, eu, ev, rank, xid, rb.tile_base, rb.crank, cc,
+                                  comp_root, parent, counters));
+    RST_TRY(read_counters(ctx, counters));
+  }
   if (ctx->host_pinned[kCntRangeErr] || ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
   return RST_OK;
 }
@@ -467,8 +540,12 @@ rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *
   RankBufs rb = take_rank_bufs(ctx, A);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(enqueue_rank_init(ctx, A, succ, rank));
-  RST_TRY(enqueue_rank_tiled(ctx, A, rank, xid, rb.exits, rb.crank, rb.tile_exits, rb.tile_base,
-                             nullptr, nullptr, nullptr, true));
+  RST_TRY(enqueue_rank_tiled(ctx, A, rank, xid, rb, counters, nullptr, true));
+  RST_TRY(read_counters(ctx, counters));
+  if (ctx->host_pinned[kCntRankOverflow]) {
+    RST_TRY(rank_overflow_fallback(ctx, rb, counters));
+    RST_TRY(enqueue_rank_expand(ctx, A, rank, xid, rb, counters));
+  }
   RST_TRY(enqueue_rank_extract(ctx, A, rank, dist));
   RST_HIP(hipStreamSynchronize(ctx->stream));
   return RST_OK;
@@ -525,6 +602,7 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
       stats->rank_rounds = inner.rank_rounds;
       stats->rank_exits = inner.rank_exits;
       stats->cross_edges = inner.cross_edges;
+      stats->paths = inner.paths;
     }
   }
   // the GConn scratch is free again (work on the stream is ordered)

@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_level(
 // ---------------------------------------------------------------------------
 
 size_t bfs_heavy_capacity(const rst_ctx *ctx, int64_t n, int64_t nnz) {
-  const int64_t heavy = ctx->opt.heavy_degree < 1 ? 1 : ctx->opt.heavy_degree;
+  const int64_t heavy = ctx->opt.bfs_heavy_degree < 1 ? 1 : ctx->opt.bfs_heavy_degree;
   int64_t cap = nnz / (heavy + 1) + 1;
   return (size_t)(cap < n ? cap : n);
 }
@@ -174,7 +174,7 @@ rst_status bfs_reset(rst_ctx *ctx, int64_t n, int32_t *level, int32_t *parent, B
 rst_status bfs_seed_roots(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
                           int32_t *level, int32_t *parent, BfsBufs &b, int32_t *counters,
                           const uint8_t *gsel) {
-  const int hd = ctx->opt.heavy_degree;
+  const int hd = ctx->opt.bfs_heavy_degree;
   if (g->offset_bytes == 4)
     hipLaunchKernelGGL(k_bfs_seed<int32_t>, dim3(grid_for(nroots, kBlock)), dim3(kBlock), 0,
                        ctx->stream, roots, nroots, g->n, (const int32_t *)g->offsets, level, parent,
@@ -190,7 +190,7 @@ rst_status bfs_seed_roots(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, 
 rst_status bfs_seed_unreached(rst_ctx *ctx, const rst_csr *g, const int32_t *cc, int32_t *level,
                               int32_t *parent, BfsBufs &b, int32_t *counters,
                               const uint8_t *vsel) {
-  const int hd = ctx->opt.heavy_degree;
+  const int hd = ctx->opt.bfs_heavy_degree;
   // counts of slot 0 must start from zero for this new frontier
   RST_TRY(enqueue_fill(ctx, b.cnt, 6, 0));
   if (g->offset_bytes == 4)
@@ -212,7 +212,7 @@ static rst_status launch_level(rst_ctx *ctx, const rst_csr *g, int32_t L, unsign
   hipLaunchKernelGGL(k_bfs_level<OffT>, dim3(grid), dim3(kBlock), 0, ctx->stream, L,
                      (const OffT *)g->offsets, g->cols, level, parent, b.q[L & 1], b.h[L & 1],
                      b.cnt + 2 * cur, b.q[(L + 1) & 1], b.h[(L + 1) & 1], b.cnt + 2 * nxt,
-                     b.cnt + 2 * clr, b.heavy_cap, counters, ctx->opt.heavy_degree);
+                     b.cnt + 2 * clr, b.heavy_cap, counters, ctx->opt.bfs_heavy_degree);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }

@@ -76,4 +76,14 @@ __device__ __forceinline__ int lds_upper_search(const int *s, int len, int k) {
   return lo;
 }
 
+// Device-scope release by the calling wave (agent-scope fence: this XCD's L2
+// is written back).  Kernels whose waves hook trees through compare-and-swap
+// and path-halving stores in global memory, from many workgroups at once, end
+// every wave with it: without it, a hook made by such a kernel was now and
+// then not yet seen by the kernels after it on other XCDs (measured on
+// MI355X).
+__device__ __forceinline__ void wave_release_device() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
 }  // namespace rst

@@ -58,7 +58,8 @@ __global__ void k_mark_roots(const int32_t *__restrict__ roots, int32_t nroots, 
 }
 
 // Per-vertex out-arc lists: next[e] = previous head of src(e), head = e.
-__global__ __launch_bounds__(kBlock) void k_link(int64_t slots, const int32_t *__restrict__ tu,
+template <int B>
+__global__ __launch_bounds__(B) void k_link(int64_t slots, const int32_t *__restrict__ tu,
                                                  const int32_t *__restrict__ tv, int32_t *head,
                                                  int32_t *next) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -168,7 +169,8 @@ __device__ __forceinline__ bool in_tile(int32_t id, int64_t e) {
 
 // endsucc[v]: successor of an arc into v whose reverse ends v's out-arc list,
 // i.e. the first out-arc of v, or -1 (cycle break) when v is its tree's root.
-__global__ __launch_bounds__(kBlock) void k_endsucc(int64_t n, const int32_t *__restrict__ head,
+template <int B>
+__global__ __launch_bounds__(B) void k_endsucc(int64_t n, const int32_t *__restrict__ head,
                                                     const int32_t *__restrict__ cc,
                                                     const int32_t *__restrict__ comp_root,
                                                     int32_t *endsucc) {
@@ -458,11 +460,124 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
   }
 }
 
+// The contracted list (M = base[tiles] words) ranked by one block: pointer
+// jumping until no word has a successor left, so the round count needs no host
+// round trip.  Up to kSmallLds words live in LDS (16-bit successor, 32-bit
+// hops); up to kSmallGlobal words jump in global memory, double-buffered
+// through tmp (only this block touches them, and each round ends at a block
+// barrier).  Longer lists raise counters[kCntRankOverflow] and change nothing:
+// the consumers then skip their work and the host ranks the list in
+// multi-block rounds.  counters[kCntExits] = M, counters[kCntRankRounds] =
+// rounds.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallPer = 26;
+constexpr int kSmallLds = kSmallPer * kSmallThreads;   // 26624 words, 156 KB of LDS
+constexpr int64_t kSmallGlobal = (int64_t)1 << 18;
+static_assert(kSmallLds < 32768, "LDS successors are 16-bit");
+
+__global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__restrict__ Mp,
+                                                              uint64_t *crank, uint64_t *tmp,
+                                                              int64_t tmp_cap, int32_t *counters) {
+  __shared__ int16_t s_succ[kSmallLds];
+  __shared__ uint32_t s_hops[kSmallLds];
+  const int tid = threadIdx.x;
+  const int64_t M = *Mp;
+  if (tid == 0) counters[kCntExits] = (int32_t)M;
+  int rounds = 0;
+  // a list of M words needs at most ceil(log2 M) rounds; the cap also ends the
+  // loop on malformed (cyclic) input
+  int max_rounds = 1;
+  while (((int64_t)1 << max_rounds) < M) ++max_rounds;
+  if (M <= kSmallLds) {
+    const int m = (int)M;
+    for (int i = tid; i < m; i += kSmallThreads) {
+      const uint64_t w = crank[i];
+      s_succ[i] = (int16_t)(int32_t)(uint32_t)w;
+      s_hops[i] = (uint32_t)(w >> 32);
+    }
+    bool active = __syncthreads_or(1);
+    while (active) {
+      int16_t ns[kSmallPer];
+      uint32_t nh[kSmallPer];
+      bool more = false;
+#pragma unroll
+      for (int k = 0; k < kSmallPer; ++k) {
+        const int i = tid + k * kSmallThreads;
+        ns[k] = -2;                       // -2: word unchanged this round
+        nh[k] = 0;
+        if (i < m) {
+          const int sc = s_succ[i];
+          if (sc >= 0) {
+            ns[k] = s_succ[sc];
+            nh[k] = s_hops[i] + s_hops[sc];
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < kSmallPer; ++k) {
+        const int i = tid + k * kSmallThreads;
+        if (ns[k] != -2) {
+          s_succ[i] = ns[k];
+          s_hops[i] = nh[k];
+          more |= ns[k] >= 0;
+        }
+      }
+      ++rounds;
+      active = __syncthreads_or(more) && rounds < max_rounds;
+    }
+    for (int i = tid; i < m; i += kSmallThreads) crank[i] = pack_rank(s_succ[i], s_hops[i]);
+  } else if (M <= kSmallGlobal && M <= tmp_cap) {
+    uint64_t *src = crank, *dst = tmp;
+    bool active = true;
+    while (active) {
+      bool more = false;
+      for (int64_t b = tid; b < M; b += 4 * kSmallThreads) {
+        uint64_t w[4], nb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t i = b + u * kSmallThreads;
+          w[u] = i < M ? src[i] : pack_rank(-1, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t sc = (int32_t)(uint32_t)w[u];
+          nb[u] = sc >= 0 ? src[sc] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int64_t i = b + u * kSmallThreads;
+          if (i < M) {
+            const int32_t sc = (int32_t)(uint32_t)w[u];
+            if (sc >= 0) {
+              dst[i] = (((w[u] >> 32) + (nb[u] >> 32)) << 32) | (nb[u] & 0xffffffffull);
+              more |= (int32_t)(uint32_t)nb[u] >= 0;
+            } else {
+              dst[i] = w[u];
+            }
+          }
+        }
+      }
+      ++rounds;
+      active = __syncthreads_or(more) && rounds < max_rounds;
+      uint64_t *t = src; src = dst; dst = t;
+    }
+    if (src != crank)
+      for (int64_t i = tid; i < M; i += kSmallThreads) crank[i] = src[i];
+  } else {
+    if (tid == 0) counters[kCntRankOverflow] = 1;
+    return;
+  }
+  if (tid == 0) counters[kCntRankRounds] = rounds;
+}
+
 // dist[e] = hops to its exit + contracted distance of that exit, stored as (-1, dist)
 __global__ __launch_bounds__(kBlock) void k_rank_expand(int64_t A, uint64_t *rank,
                                                         const int32_t *__restrict__ xid,
                                                         const int64_t *__restrict__ base,
-                                                        const uint64_t *__restrict__ crank) {
+                                                        const uint64_t *__restrict__ crank,
+                                                        const int32_t *__restrict__ counters) {
+  if (counters[kCntRankOverflow]) return;   // contracted list not ranked yet
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= A) return;
   const uint64_t w = rank[e];
@@ -487,7 +602,8 @@ __device__ __forceinline__ uint32_t arc_dist(int64_t e, const uint64_t *__restri
 
 // Distances of both arcs of a slot, then the parent rule; default component
 // roots get P[v] = v and are counted.
-__global__ __launch_bounds__(kBlock) void k_expand_parent(int64_t slots, int64_t n,
+template <int B>
+__global__ __launch_bounds__(B) void k_expand_parent(int64_t slots, int64_t n,
                                                           const int32_t *__restrict__ tu,
                                                           const int32_t *__restrict__ tv,
                                                           const uint64_t *__restrict__ rank,
@@ -497,6 +613,7 @@ __global__ __launch_bounds__(kBlock) void k_expand_parent(int64_t slots, int64_t
                                                           const int32_t *__restrict__ cc,
                                                           const int32_t *__restrict__ comp_root,
                                                           int32_t *parent, int32_t *counters) {
+  if (counters[kCntRankOverflow]) return;   // contracted list not ranked yet (block-uniform)
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x < slots) {
     const int32_t a = tu[x];
@@ -573,8 +690,7 @@ rst_status enqueue_link(rst_ctx *ctx, int64_t slots, const int32_t *tu, const in
                         int32_t *head, int32_t *next) {
   if (slots <= 0) return RST_OK;
   RST_KMARK(ctx, RST_KERNEL_LINK, 0);
-  hipLaunchKernelGGL(k_link, dim3(grid_for(slots, kBlock)), dim3(kBlock), 0, ctx->stream, slots,
-                     tu, tv, head, next);
+  RST_SWEEP(ctx, k_link, slots, slots, tu, tv, head, next);
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_LINK, 1);
   return RST_OK;
@@ -625,52 +741,60 @@ rst_status enqueue_rank_rounds(rst_ctx *ctx, int64_t A, uint64_t *rank, int roun
 
 size_t rank_exit_capacity(int64_t A) { return (size_t)(A + 1); }
 size_t rank_tile_count(int64_t A) { return (size_t)((A + kRankTile - 1) / kRankTile); }
+size_t rank_small_capacity(int64_t A) {
+  return (size_t)((A + 1) < kSmallGlobal ? (A + 1) : kSmallGlobal);
+}
 
 rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *xid,
-                              int32_t *exits, uint64_t *crank, int32_t *tile_exits,
-                              int64_t *tile_base, int64_t *exits_out, int *rounds_out,
-                              const SlotArcs *from_slots, bool expand) {
-  if (rounds_out) *rounds_out = 0;
-  if (exits_out) *exits_out = 0;
+                              const RankBufs &rb, int32_t *counters, const SlotArcs *from_slots,
+                              bool expand) {
   if (A <= 0) return RST_OK;
   const int64_t tiles = (int64_t)rank_tile_count(A);
   if (from_slots) {
-    hipLaunchKernelGGL(k_endsucc, dim3(grid_for(from_slots->n, kBlock)), dim3(kBlock), 0,
-                       ctx->stream, from_slots->n, from_slots->head, from_slots->cc,
-                       from_slots->comp_root, from_slots->endsucc);
+    RST_SWEEP(ctx, k_endsucc, from_slots->n, from_slots->n, from_slots->head, from_slots->cc,
+              from_slots->comp_root, from_slots->endsucc);
     RST_HIP(hipGetLastError());
     SlotSrc src{from_slots->tu, from_slots->tv, from_slots->next, from_slots->endsucc};
     RST_KMARK(ctx, RST_KERNEL_RANK_TILE, 0);
     hipLaunchKernelGGL(k_rank_tile<true>, dim3((unsigned)tiles), dim3(kRankThreads), 0, ctx->stream,
-                       A, rank, xid, exits, tile_exits, src);
+                       A, rank, xid, rb.exits, rb.tile_exits, src);
   } else {
     SlotSrc src{};
     RST_KMARK(ctx, RST_KERNEL_RANK_TILE, 0);
     hipLaunchKernelGGL(k_rank_tile<false>, dim3((unsigned)tiles), dim3(kRankThreads), 0,
-                       ctx->stream, A, rank, xid, exits, tile_exits, src);
+                       ctx->stream, A, rank, xid, rb.exits, rb.tile_exits, src);
   }
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_RANK_TILE, 1);
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, ctx->stream, tile_exits, tiles, tile_base);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, ctx->stream, rb.tile_exits, tiles,
+                     rb.tile_base);
   RST_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_rank_contract, dim3((unsigned)tiles), dim3(kBlock), 0, ctx->stream, exits,
-                     tile_exits, tile_base, rank, xid, crank);
+  hipLaunchKernelGGL(k_rank_contract, dim3((unsigned)tiles), dim3(kBlock), 0, ctx->stream, rb.exits,
+                     rb.tile_exits, rb.tile_base, rank, xid, rb.crank);
   RST_HIP(hipGetLastError());
-  int64_t *hb = reinterpret_cast<int64_t *>(ctx->host_pinned + 48);
-  RST_HIP(hipMemcpyAsync(hb, tile_base + tiles, sizeof(int64_t), hipMemcpyDeviceToHost,
-                         ctx->stream));
-  RST_HIP(hipStreamSynchronize(ctx->stream));
-  int64_t M = *hb;
-  if (M < 0 || M > A) M = A;
+  hipLaunchKernelGGL(k_rank_small, dim3(1), dim3(kSmallThreads), 0, ctx->stream,
+                     rb.tile_base + tiles, rb.crank, rb.ctmp, (int64_t)rank_small_capacity(A),
+                     counters);
+  RST_HIP(hipGetLastError());
+  if (expand) RST_TRY(enqueue_rank_expand(ctx, A, rank, xid, rb, counters));
+  return RST_OK;
+}
+
+rst_status enqueue_rank_expand(rst_ctx *ctx, int64_t A, uint64_t *rank, const int32_t *xid,
+                               const RankBufs &rb, const int32_t *counters) {
+  hipLaunchKernelGGL(k_rank_expand, dim3(grid_for(A, kBlock)), dim3(kBlock), 0, ctx->stream, A,
+                     rank, xid, rb.tile_base, rb.crank, counters);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
+rst_status rank_overflow_fallback(rst_ctx *ctx, const RankBufs &rb, int32_t *counters) {
+  int64_t M = ctx->host_pinned[kCntExits];
+  if (M < 0) return RST_E_DEVICE;
   const int rounds = rank_rounds_for(M);
-  RST_TRY(enqueue_rank_rounds(ctx, M, crank, rounds, nullptr, nullptr));
-  if (expand) {
-    hipLaunchKernelGGL(k_rank_expand, dim3(grid_for(A, kBlock)), dim3(kBlock), 0, ctx->stream, A,
-                       rank, xid, tile_base, crank);
-    RST_HIP(hipGetLastError());
-  }
-  if (rounds_out) *rounds_out = rounds;
-  if (exits_out) *exits_out = M;
+  RST_TRY(enqueue_rank_rounds(ctx, M, rb.crank, rounds, nullptr, nullptr));
+  RST_TRY(enqueue_fill(ctx, counters + kCntRankOverflow, 1, 0));
+  RST_TRY(enqueue_fill(ctx, counters + kCntRankRounds, 1, rounds));
   return RST_OK;
 }
 
@@ -679,8 +803,8 @@ rst_status enqueue_expand_parent(rst_ctx *ctx, int64_t slots, int64_t n, const i
                                  const int64_t *tile_base, const uint64_t *crank, const int32_t *cc,
                                  const int32_t *comp_root, int32_t *parent, int32_t *counters) {
   const int64_t items = slots > n ? slots : n;
-  hipLaunchKernelGGL(k_expand_parent, dim3(grid_for(items, kBlock)), dim3(kBlock), 0, ctx->stream,
-                     slots, n, tu, tv, rank, xid, tile_base, crank, cc, comp_root, parent, counters);
+  RST_SWEEP(ctx, k_expand_parent, items, slots, n, tu, tv, rank, xid, tile_base, crank, cc,
+            comp_root, parent, counters);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }

@@ -153,7 +153,7 @@ template <class OffT>
 __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
     int64_t n, const OffT *__restrict__ off, const int32_t *__restrict__ cols, int32_t *cc,
     int32_t *tu, int32_t *tv, int2 *cross, int32_t *tile_cross, int32_t *tile_lvl,
-    int32_t *counters, int64_t *chunks, int64_t chunk_cap, int heavy_deg,
+    int64_t *region_of, int32_t *counters, int64_t *chunks, int64_t chunk_cap, int heavy_deg,
     const uint8_t *__restrict__ vmask) {
   __shared__ int lp[kTile];
   __shared__ int16_t eu[kTile];     // local endpoints of the edge held by a slot (-1: none)
@@ -276,6 +276,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
   }
   __syncthreads();
   if (tid == 0) {
+    region_of[blockIdx.x] = region;
     tile_cross[blockIdx.x] = s_ncross;
     atomicAdd(&counters[kCntCross], s_ncross);
     tile_lvl[blockIdx.x] = (s_lmin << 8) | (s_lmax & 0xff);   // level range of its cross edges
@@ -328,65 +329,254 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
   }
 }
 
-// Cross phase, one level: every block walks the cross region of some tiles
-// and hooks the edges of this level (asynchronous id-ordered union-find).
-// All edges along one tile boundary usually join the same two trees, so the
-// block first deduplicates (root, root) pairs in an LDS hash table: only the
-// first edge of a pair issues global finds-and-CAS, the rest are dropped (the
-// winner's hook loop runs until the two trees are one).
-constexpr int kPairSlots = 1024;
+// Cross phase.  After the tile pass every vertex points at its tile-local
+// root, and the cross edges of a tile mostly join the same few pairs of local
+// trees (on a mesh, one big tree per tile and some small ones along its
+// borders).  The phase runs in steps:
+//  1. k_cross_dedupe: every cross edge (s,t) of a tile is keyed by the pair of
+//     trees it joins, (cc[s], cc[t]), and only the first edge of each pair is
+//     kept, compacted in place at the start of the tile's region;
+//     tile_cross[b] becomes the number kept.  A tile with more than
+//     kFlatCross cross edges has no locality to exploit: its edges are hooked
+//     right there (split over several blocks) and tile_cross[b] keeps its
+//     original value, which marks the tile as done for the later steps.
+//  2. k_cross_lds: one block takes all kept edges, maps the roots they join
+//     into LDS and runs the union-find there, level by level over the binary
+//     tree of tiles (cross_level), then writes the links back.  If the kept
+//     edges or their roots do not fit, it changes nothing and raises a flag.
+//  3. Only when flagged, k_cross_merge does the same in global memory: the
+//     levels below `split` join tiles of one group of 2^split tiles and run in
+//     one launch with a block per group; the remaining levels run in one block.
+// Merging level by level keeps the id-ordered trees at most about one hop
+// deeper per level.  A key read while another tile hooks may already be an
+// ancestor of the local root rather than the root itself: both name a vertex
+// of the same current tree, so dropping an edge with an equal key never loses
+// connectivity.
+constexpr int kDedupSlots = 8192;       // LDS hash slots (64 KB) of k_cross_dedupe
 constexpr int kFlatCross = kTile;       // above this a tile's cross edges are hooked flat
+constexpr int kDedupPer = kFlatCross / kTileThreads;
+constexpr int kMergeTopLevels = 7;      // levels merged by the single final block (fallback)
+constexpr int kLdsSlots = 16384;        // root slots of k_cross_lds (key + parent: 128 KB)
+constexpr int kLdsPer = 16;             // kept edges per thread in k_cross_lds
+constexpr int kLdsEdges = kLdsPer * kTileThreads;
+constexpr int kLdsTiles = 4096;         // tile prefix held in LDS by k_cross_lds
 
-__global__ __launch_bounds__(kBlock) void k_hook_cross_impl(const int64_t *__restrict__ region_of,
+__device__ __forceinline__ int kept_count(int c) { return c > kFlatCross ? 0 : c; }
+
+__global__ __launch_bounds__(kTileThreads) void k_cross_dedupe(const int64_t *__restrict__ region_of,
+                                                               int2 *cross, int32_t *tile_cross,
+                                                               int slices, int32_t *cc, int32_t *tu,
+                                                               int32_t *tv, int32_t *counters) {
+  __shared__ unsigned long long tab[kDedupSlots];
+  __shared__ int s_kept;
+  const int b = blockIdx.x / slices;
+  const int part = blockIdx.x % slices;
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0 && tid == 0) counters[kCntCrossOverflow] = 0;
+  const int64_t region = region_of[b];
+  const int cntb = tile_cross[b];
+  if (cntb > kFlatCross) {
+    for (int i = part * kTileThreads + tid; i < cntb; i += slices * kTileThreads) {
+      const int2 e = cross[region + i];
+      hook_edge<true>(e.x, e.y, cc, tu, tv);
+    }
+    wave_release_device();
+    return;
+  }
+  if (part != 0) return;
+  for (int i = tid; i < kDedupSlots; i += kTileThreads) tab[i] = ~0ull;
+  if (tid == 0) s_kept = 0;
+  // every edge of the tile is read (and its key formed) before any write-back
+  int2 e[kDedupPer];
+  bool keep[kDedupPer];
+#pragma unroll
+  for (int j = 0; j < kDedupPer; ++j) {
+    const int i = tid + j * kTileThreads;
+    e[j] = i < cntb ? cross[region + i] : make_int2(0, 0);
+  }
+  int32_t ka[kDedupPer], kb[kDedupPer];
+#pragma unroll
+  for (int j = 0; j < kDedupPer; ++j) {
+    const int i = tid + j * kTileThreads;
+    ka[j] = i < cntb ? cc[e[j].x] : 0;
+    kb[j] = i < cntb ? cc[e[j].y] : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kDedupPer; ++j) {
+    const int i = tid + j * kTileThreads;
+    keep[j] = false;
+    if (i < cntb && ka[j] != kb[j]) {
+      const uint32_t lo = (uint32_t)(ka[j] < kb[j] ? ka[j] : kb[j]);
+      const uint32_t hi = (uint32_t)(ka[j] < kb[j] ? kb[j] : ka[j]);
+      const unsigned long long key = ((unsigned long long)lo << 32) | hi;
+      uint32_t h = (uint32_t)(key * 0x9E3779B97F4A7C15ull >> 40) & (kDedupSlots - 1);
+      keep[j] = true;                   // also kept when the probe limit is hit
+      for (int probe = 0; probe < 64; ++probe) {
+        const unsigned long long old = atomicCAS(&tab[h], ~0ull, key);
+        if (old == ~0ull) break;        // first edge of this pair
+        if (old == key) { keep[j] = false; break; }
+        h = (h + 1) & (kDedupSlots - 1);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kDedupPer; ++j) {
+    const int slot = wave_append(keep[j], &s_kept);
+    if (keep[j]) cross[region + slot] = e[j];
+  }
+  __syncthreads();
+  if (tid == 0) tile_cross[b] = s_kept;
+}
+
+// Slot of global root `key` in the LDS table (inserted if new); -1 when the
+// probe limit is reached.
+__device__ __forceinline__ int lds_slot(int32_t key, int32_t *keys) {
+  uint32_t h = ((uint32_t)key * 0x9E3779B1u) >> (32 - 14);
+  for (int probe = 0; probe < 256; ++probe) {
+    const int32_t old = atomicCAS(&keys[h], -1, key);
+    if (old == -1 || old == key) return (int)h;
+    h = (h + 1) & (kLdsSlots - 1);
+  }
+  return -1;
+}
+static_assert(kLdsSlots == 1 << 14, "lds_slot hashes to 14 bits");
+
+__global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__restrict__ region_of,
                                                             const int2 *__restrict__ cross,
                                                             const int32_t *__restrict__ tile_cross,
-                                                            const int32_t *__restrict__ tile_lvl,
-                                                            int tiles, int level, int32_t *cc,
-                                                            int32_t *tu, int32_t *tv) {
-  __shared__ unsigned long long tab[kPairSlots];
-  for (int b = blockIdx.x; b < tiles; b += gridDim.x) {
-    const int lr = tile_lvl[b];
-    const int64_t region = region_of[b];
-    const int cntb = tile_cross[b];
-    if (cntb > kFlatCross) {
-      // Many cross edges (ids without locality): pairs rarely repeat, so the
-      // tile's edges are hooked directly, all levels in the first launch.
-      if (level == 0)
-        for (int i = threadIdx.x; i < cntb; i += kBlock) {
-          const int2 e = cross[region + i];
-          hook_edge<true>(e.x, e.y, cc, tu, tv);
-        }
-      continue;
-    }
-    if (level < (lr >> 8) || level > (lr & 0xff)) continue;   // block-uniform skip
-    for (int i = threadIdx.x; i < kPairSlots; i += kBlock) tab[i] = ~0ull;
+                                                            int tiles, int levels, int32_t *cc,
+                                                            int32_t *tu, int32_t *tv,
+                                                            int32_t *counters) {
+  __shared__ int32_t keys[kLdsSlots];   // global root held by a slot, -1: empty
+  __shared__ int par[kLdsSlots];        // union-find parent slot
+  __shared__ int s_pref[kLdsTiles + 1]; // exclusive prefix of kept counts over tiles
+  __shared__ int s_wave[kTileThreads / kWave];
+  __shared__ int s_carry, s_fail;
+  const int tid = threadIdx.x;
+  if (tiles > kLdsTiles) {
+    if (tid == 0) counters[kCntCrossOverflow] = 1;
+    return;
+  }
+  for (int i = tid; i < kLdsSlots; i += kTileThreads) { keys[i] = -1; par[i] = i; }
+  if (tid == 0) { s_carry = 0; s_fail = 0; }
+  __syncthreads();
+  for (int b0 = 0; b0 < tiles; b0 += kTileThreads) {
+    const int b = b0 + tid;
+    const int c = b < tiles ? kept_count(tile_cross[b]) : 0;
+    int total;
+    const int ex = block_excl_scan<kTileThreads>(c, s_wave, &total);
+    if (b < tiles) s_pref[b] = s_carry + ex;
     __syncthreads();
-    for (int i = threadIdx.x; i < cntb; i += kBlock) {
-      const int2 e = cross[region + i];
-      if (cross_level(e.x, e.y) != level) continue;
-      const int32_t ru = find_root(e.x, cc), rv = find_root(e.y, cc);
-      if (ru == rv) continue;
-      const unsigned long long key = ru < rv ? ((unsigned long long)(uint32_t)ru << 32) | (uint32_t)rv
-                                             : ((unsigned long long)(uint32_t)rv << 32) | (uint32_t)ru;
-      uint32_t h = (uint32_t)(key * 0x9E3779B97F4A7C15ull >> 40) & (kPairSlots - 1);
-      bool mine = true;
-      for (int probe = 0; probe < 32; ++probe) {
-        const unsigned long long old = atomicCAS(&tab[h], ~0ull, key);
-        if (old == ~0ull) break;            // first edge of this pair
-        if (old == key) { mine = false; break; }
-        h = (h + 1) & (kPairSlots - 1);
+    if (tid == 0) s_carry += total;
+    __syncthreads();
+  }
+  const int total = s_carry;
+  if (tid == 0) s_pref[tiles] = total;
+  if (total > kLdsEdges) {
+    if (tid == 0) counters[kCntCrossOverflow] = 1;
+    return;
+  }
+  if (total == 0) return;
+  __syncthreads();
+  // this thread's kept edges and the roots they join (only this block writes
+  // cc during the kernel, so the finds end at true roots)
+  int2 e[kLdsPer];
+  int sab[kLdsPer];                     // slot of the root of e.x (low 16) and e.y (high 16)
+#pragma unroll
+  for (int k = 0; k < kLdsPer; ++k) {
+    const int g = tid + k * kTileThreads;
+    e[k] = make_int2(-1, -1);
+    sab[k] = -1;
+    if (g < total) {
+      const int t = lds_upper_search(s_pref, tiles, g);
+      e[k] = cross[region_of[t] + (g - s_pref[t])];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kLdsPer; ++k) {
+    if (e[k].x >= 0) {
+      const int32_t ra = find_root(e[k].x, cc), rb = find_root(e[k].y, cc);
+      if (ra != rb) {
+        const int sa = lds_slot(ra, keys), sb = lds_slot(rb, keys);
+        if (sa < 0 || sb < 0) s_fail = 1;
+        else sab[k] = sa | (sb << 16);
       }
-      if (mine) hook_edge<true>(e.x, e.y, cc, tu, tv);
+    }
+  }
+  __syncthreads();
+  if (s_fail) {
+    if (tid == 0) counters[kCntCrossOverflow] = 1;
+    return;
+  }
+  for (int l = 0; l < levels; ++l) {
+#pragma unroll
+    for (int k = 0; k < kLdsPer; ++k) {
+      if (sab[k] >= 0 && cross_level(e[k].x, e[k].y) == l) {
+        int ra = lds_find(sab[k] & 0xffff, par), rb = lds_find(sab[k] >> 16, par);
+        while (ra != rb) {
+          const bool a_low = keys[ra] < keys[rb];
+          const int lo = a_low ? ra : rb, hi = a_low ? rb : ra;
+          const int old = atomicCAS(&par[hi], hi, lo);
+          if (old == hi) {
+            tu[keys[hi]] = e[k].x;
+            tv[keys[hi]] = e[k].y;
+            break;
+          }
+          if (ra == hi) ra = lds_find(old, par); else rb = lds_find(old, par);
+        }
+      }
     }
     __syncthreads();
   }
+  // every hooked root points straight at its final root
+  for (int i = tid; i < kLdsSlots; i += kTileThreads) {
+    if (keys[i] >= 0 && par[i] != i) cc[keys[i]] = keys[lds_find(i, par)];
+  }
+  wave_release_device();
 }
 
-// region_of[b] = off[b * kTile] as int64 (so the cross kernel needs no offset type)
-template <class OffT>
-__global__ void k_tile_regions(const OffT *__restrict__ off, int tiles, int64_t *region_of) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b < tiles) region_of[b] = (int64_t)off[(int64_t)b * kTile];
+// Fallback of k_cross_lds (runs only when it raised its flag): hook the kept
+// cross edges of levels [lo, hi) of the tiles of group blockIdx.x
+// (2^group_log consecutive tiles) in global memory, one level after another.
+__global__ __launch_bounds__(kTileThreads) void k_cross_merge(const int64_t *__restrict__ region_of,
+                                                              const int2 *__restrict__ cross,
+                                                              const int32_t *__restrict__ tile_cross,
+                                                              const int32_t *__restrict__ tile_lvl,
+                                                              int tiles, int lo, int hi,
+                                                              int group_log, int32_t *cc,
+                                                              int32_t *tu, int32_t *tv,
+                                                              const int32_t *counters) {
+  __shared__ int s_scan[kTileThreads + 1];
+  __shared__ int s_wave[kTileThreads / kWave];
+  if (counters[kCntCrossOverflow] == 0) return;   // block-uniform
+  const int tid = threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x << group_log;
+  const int64_t t1 = (t0 + ((int64_t)1 << group_log)) < tiles ? t0 + ((int64_t)1 << group_log)
+                                                                : (int64_t)tiles;
+  for (int l = lo; l < hi; ++l) {
+    for (int64_t base = t0; base < t1; base += kTileThreads) {
+      const int64_t tb = base + tid;
+      int c = 0;
+      if (tb < t1) {
+        const int lr = tile_lvl[tb];
+        if (l >= (lr >> 8) && l <= (lr & 0xff)) c = kept_count(tile_cross[tb]);
+      }
+      int total;
+      const int ex = block_excl_scan<kTileThreads>(c, s_wave, &total);
+      s_scan[tid] = ex;
+      if (tid == kTileThreads - 1) s_scan[kTileThreads] = total;
+      __syncthreads();
+      for (int idx = tid; idx < total; idx += kTileThreads) {
+        const int k = lds_upper_search(s_scan, kTileThreads, idx);
+        const int2 e = cross[region_of[base + k] + (idx - s_scan[k])];
+        if (cross_level(e.x, e.y) == l) hook_edge<true>(e.x, e.y, cc, tu, tv);
+      }
+      __syncthreads();
+    }
+  }
+  wave_release_device();
 }
 
 // Heavy-vertex chunks, grid-strided over the chunk list.
@@ -410,6 +600,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_heavy(const OffT *__restrict__ 
       if (dst < src) hook_edge<true>(src, dst, cc, tu, tv);
     }
   }
+  if (blockIdx.x < nc) wave_release_device();   // only blocks that hooked
 }
 
 // Edge-list hooking without recording (labels of a given forest).
@@ -425,11 +616,13 @@ __global__ __launch_bounds__(kBlock) void k_hook_coo(int64_t t, int64_t n,
     return;
   }
   if (u != v) hook_edge<false>(u, v, cc, nullptr, nullptr);
+  wave_release_device();
 }
 
 // Final pointer jumping: every vertex points at its root (= min id of its
 // component).  Also resets the per-vertex arrays the rooting stage needs.
-__global__ __launch_bounds__(kBlock) void k_compress(int64_t n, int32_t *cc, int32_t *comp_root,
+template <int B>
+__global__ __launch_bounds__(B) void k_compress(int64_t n, int32_t *cc, int32_t *comp_root,
                                                      int32_t *head) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
@@ -496,16 +689,32 @@ int hook_level_count(int64_t n) {
 // tile_cross buffer: int32 counts, int64 region starts, int32 level ranges
 size_t hook_tile_words(int64_t n) { return ((hook_tile_count(n) + 1) & ~size_t(1)) + 3 * hook_tile_count(n); }
 
-static rst_status launch_cross_levels(rst_ctx *ctx, unsigned tiles, int levels, unsigned grid,
-                                      const int64_t *region_of, const int2 *cross,
-                                      const int32_t *tile_cross, const int32_t *tile_lvl,
-                                      ForestBufs &f) {
+static rst_status launch_cross(rst_ctx *ctx, unsigned tiles, int levels,
+                               const int64_t *region_of, int2 *cross, int32_t *tile_cross,
+                               const int32_t *tile_lvl, ForestBufs &f) {
+  if (levels == 0) return RST_OK;       // one tile: no cross edges
   RST_KMARK(ctx, RST_KERNEL_CROSS, 0);
-  for (int l = 0; l < levels; ++l) {
-    hipLaunchKernelGGL(k_hook_cross_impl, dim3(grid), dim3(kBlock), 0, ctx->stream, region_of, cross,
-                       tile_cross, tile_lvl, (int)tiles, l, f.cc, f.tu, f.tv);
+  // flat tiles are split over several blocks when there are few tiles
+  unsigned slices = (1024 + tiles - 1) / tiles;
+  slices = slices < 1 ? 1 : (slices > 64 ? 64 : slices);
+  hipLaunchKernelGGL(k_cross_dedupe, dim3(tiles * slices), dim3(kTileThreads), 0, ctx->stream,
+                     region_of, cross, tile_cross, (int)slices, f.cc, f.tu, f.tv, f.counters);
+  RST_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_cross_lds, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of, cross,
+                     tile_cross, (int)tiles, levels, f.cc, f.tu, f.tv, f.counters);
+  RST_HIP(hipGetLastError());
+  const int split = levels > kMergeTopLevels ? levels - kMergeTopLevels : 0;
+  if (split > 0) {
+    const unsigned groups = (tiles + (1u << split) - 1) >> split;
+    hipLaunchKernelGGL(k_cross_merge, dim3(groups), dim3(kTileThreads), 0, ctx->stream, region_of,
+                       cross, tile_cross, tile_lvl, (int)tiles, 0, split, split, f.cc, f.tu, f.tv,
+                       f.counters);
     RST_HIP(hipGetLastError());
   }
+  hipLaunchKernelGGL(k_cross_merge, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of, cross,
+                     tile_cross, tile_lvl, (int)tiles, split, levels, levels, f.cc, f.tu, f.tv,
+                     f.counters);
+  RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_CROSS, 1);
   return RST_OK;
 }
@@ -518,37 +727,28 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
   const int64_t n = g->n;
   const unsigned tiles = grid_for(n, kTile);
   const unsigned heavy_grid = (unsigned)(ctx->num_cus * 8);
-  const unsigned cross_grid = tiles < 2048 ? tiles : 2048;
   int levels = 0;
   while ((1u << levels) < tiles) ++levels;
   if (g->offset_bytes == 4) {
     const int32_t *off = (const int32_t *)g->offsets;
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 0);
     hipLaunchKernelGGL(k_hook_tile<int32_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
-                       off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, f.counters,
-                       chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask);
+                       off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, region_of,
+                       f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
-    hipLaunchKernelGGL(k_tile_regions<int32_t>, dim3(grid_for(tiles, kBlock)), dim3(kBlock), 0,
-                       ctx->stream, off, (int)tiles, region_of);
-    RST_HIP(hipGetLastError());
-    RST_TRY(launch_cross_levels(ctx, tiles, levels, cross_grid, region_of, cross, tile_cross,
-                                tile_lvl, f));
+    RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, f));
     hipLaunchKernelGGL(k_hook_heavy<int32_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream, off,
                        g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters);
   } else {
     const int64_t *off = (const int64_t *)g->offsets;
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 0);
     hipLaunchKernelGGL(k_hook_tile<int64_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
-                       off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, f.counters,
-                       chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask);
+                       off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, region_of,
+                       f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
-    hipLaunchKernelGGL(k_tile_regions<int64_t>, dim3(grid_for(tiles, kBlock)), dim3(kBlock), 0,
-                       ctx->stream, off, (int)tiles, region_of);
-    RST_HIP(hipGetLastError());
-    RST_TRY(launch_cross_levels(ctx, tiles, levels, cross_grid, region_of, cross, tile_cross,
-                                tile_lvl, f));
+    RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, f));
     hipLaunchKernelGGL(k_hook_heavy<int64_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream, off,
                        g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters);
   }
@@ -570,8 +770,7 @@ rst_status enqueue_hook_coo(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *e
 
 rst_status enqueue_compress(rst_ctx *ctx, int64_t n, int32_t *cc, int32_t *comp_root,
                             int32_t *head) {
-  hipLaunchKernelGGL(k_compress, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, ctx->stream, n, cc,
-                     comp_root, head);
+  RST_SWEEP(ctx, k_compress, n, n, cc, comp_root, head);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }

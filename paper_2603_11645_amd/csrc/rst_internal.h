@@ -24,10 +24,32 @@ struct Options {
   int bfs_levels_per_sync = 32;
   int bfs_grid = 0;
   int rank_elems_per_thread = 4;
-  int heavy_degree = 1024;
+  int heavy_degree = 1024;       // hooking: arcs of heavier vertices are chunked
+  int sweep_block = 256;         // threads per block of the per-vertex/per-slot sweeps
+  int bfs_heavy_degree = 1024;   // BFS: frontier vertices above this are split over blocks
 };
 
+// Launch sweep kernel template `kern<B>` over `items` threads with the
+// context's block size B (64, 128, 256, 512 or 1024).
+#define RST_SWEEP(ctx, kern, items, ...)                                                        \
+  do {                                                                                          \
+    const int64_t it_ = (items);                                                                \
+    switch ((ctx)->opt.sweep_block) {                                                           \
+      case 64: hipLaunchKernelGGL(kern<64>, dim3(grid_for(it_, 64)), dim3(64), 0, (ctx)->stream, \
+                                  __VA_ARGS__); break;                                          \
+      case 128: hipLaunchKernelGGL(kern<128>, dim3(grid_for(it_, 128)), dim3(128), 0,            \
+                                   (ctx)->stream, __VA_ARGS__); break;                          \
+      case 512: hipLaunchKernelGGL(kern<512>, dim3(grid_for(it_, 512)), dim3(512), 0,            \
+                                   (ctx)->stream, __VA_ARGS__); break;                          \
+      case 1024: hipLaunchKernelGGL(kern<1024>, dim3(grid_for(it_, 1024)), dim3(1024), 0,        \
+                                    (ctx)->stream, __VA_ARGS__); break;                         \
+      default: hipLaunchKernelGGL(kern<256>, dim3(grid_for(it_, 256)), dim3(256), 0,             \
+                                  (ctx)->stream, __VA_ARGS__); break;                           \
+    }                                                                                           \
+  } while (0)
+
 struct Selector;
+struct TuneCache;
 
 // batch.hip
 rst_status enqueue_graph_mask(rst_ctx *ctx, const rst_batch *b, const uint8_t *method,
@@ -56,6 +78,7 @@ struct rst_ctx {
   int32_t *host_pinned = nullptr;   // small pinned host buffer for flag readback
   bool timing = false;              // record per-kernel events (a stats struct was passed)
   rst::Selector *selector = nullptr;
+  rst::TuneCache *tune = nullptr;   // autotuned settings by graph class
 };
 
 namespace rst {
@@ -122,6 +145,9 @@ enum {
   kCntExits = 7,       // segment exits of the tiled list ranking
   kCntBatchBfs = 8,    // graphs of a batch assigned to BFS
   kCntBatchBfsVtx = 9, // vertices of those graphs
+  kCntCrossOverflow = 10,  // kept cross edges did not fit the LDS merge (fallback ran)
+  kCntRankOverflow = 11,   // contracted list did not fit the one-block ranking
+  kCntRankRounds = 12,     // pointer-jumping rounds of the contracted list
   kCntTotal = 16
 };
 
@@ -161,10 +187,6 @@ rst_status enqueue_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t 
 int rank_rounds_for(int64_t max_list_len);
 size_t rank_exit_capacity(int64_t A);
 size_t rank_tile_count(int64_t A);
-// tiled list ranking of A words (succ, hops); leaves (-1, distance to tail) in
-// every word.  xid: int32 [A], exits: int32 [A+1], crank: uint64 [A+1],
-// tile_exits: int32 [tiles], tile_base: int64 [tiles+1].  Reads the exit count
-// back to the host (one synchronisation).
 // Arcs given by forest slots: the tile pass computes each arc's successor
 // itself (no separate successor pass).
 struct SlotArcs {
@@ -172,17 +194,45 @@ struct SlotArcs {
   int64_t n;          // vertices
   int32_t *endsucc;   // scratch [n]
 };
-// from_slots: NULL -> rank[] already holds (succ, hops) words.  expand: leave
-// (-1, distance) in every rank word (otherwise the caller expands, e.g. fused
-// with the parent rule).
+// Scratch of the tiled list ranking of A words: exits int32 [A+1], crank
+// uint64 [A+1], ctmp uint64 [rank_small_capacity(A)], tile_exits int32
+// [tiles], tile_base int64 [tiles+1].
+struct RankBufs {
+  int32_t *exits;
+  uint64_t *crank;
+  uint64_t *ctmp;
+  int32_t *tile_exits;
+  int64_t *tile_base;
+};
+size_t rank_small_capacity(int64_t A);
+// Tiled list ranking of A words (succ, hops), with no host round trip: leaves
+// (-1, distance to tail) in every word once the contracted list is ranked.
+// from_slots: NULL -> rank[] already holds (succ, hops) words.  expand: expand
+// here (otherwise the caller expands, e.g. fused with the parent rule).  When
+// the contracted list was too long for the one-block ranking,
+// counters[kCntRankOverflow] is set after the stream drains and every expand
+// kernel has skipped its work: the caller then runs rank_overflow_fallback
+// and expands again.
 rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *xid,
-                              int32_t *exits, uint64_t *crank, int32_t *tile_exits,
-                              int64_t *tile_base, int64_t *exits_out, int *rounds_out,
-                              const SlotArcs *from_slots, bool expand);
+                              const RankBufs &rb, int32_t *counters, const SlotArcs *from_slots,
+                              bool expand);
+rst_status enqueue_rank_expand(rst_ctx *ctx, int64_t A, uint64_t *rank, const int32_t *xid,
+                               const RankBufs &rb, const int32_t *counters);
+// multi-block rounds over the contracted list (M from the counters already read
+// back to the host), then clears the overflow flag
+rst_status rank_overflow_fallback(rst_ctx *ctx, const RankBufs &rb, int32_t *counters);
 rst_status enqueue_expand_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
                                  const int32_t *tv, const uint64_t *rank, const int32_t *xid,
                                  const int64_t *tile_base, const uint64_t *crank, const int32_t *cc,
                                  const int32_t *comp_root, int32_t *parent, int32_t *counters);
+
+// verify.hip: device check of a rooted spanning forest.  vc[0] += failures,
+// vc[1] = min failing vertex (caller initialises 0 and INT32_MAX); anc0/anc1:
+// int32 [n] scratch.
+rst_status enqueue_verify(rst_ctx *ctx, const rst_csr *g, int32_t root, const int32_t *label,
+                          const int32_t *parent, int32_t *anc0, int32_t *anc1, int32_t *vc);
+// tune.hip
+void tune_free(rst_ctx *ctx);
 
 // bfs.hip
 struct BfsBufs {

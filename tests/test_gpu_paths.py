@@ -1,0 +1,84 @@
+"""GPU tests at medium sizes that drive each variant of the forest and ranking
+stages, checked like the small cases: min-id labels bit-exact against the
+oracle, parent arrays accepted by the oracle verifier, list ranks bit-exact.
+
+Which variant ran is read from rst_stats.paths:
+  * vertex ids without locality: every tile's cross edges hooked flat, the
+    contracted tour list ranked by the one workgroup in global memory (C1
+    grid) or, when longer than that workgroup takes, by multi-workgroup
+    rounds (300k-vertex random graph);
+  * meshes: kept cross edges merged in LDS by one workgroup (light deletions)
+    or, when too many small trees meet at tile borders, in global memory (45%
+    deletions).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_11645_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rst():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_11645_amd as r
+    return r
+
+
+@pytest.fixture(scope="module")
+def ctx(rst):
+    return rst.Context(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+CASES = {
+    # name: (graph builder, expected rst_stats.paths bits)
+    "grid_permuted_256": (lambda: I.grid_permuted(256, seed=1), 0),
+    "grid_1024_del30": (lambda: I.grid(1024, 1024, 0.30, seed=7), 0),
+    "grid_1024_del45": (lambda: I.grid(1024, 1024, 0.45, seed=7), 1),
+    "road_512": (lambda: I.road_mesh(512, 0.15, 0.001, seed=2), 0),
+    # low-index tiles list few cross edges (only those to smaller ids), so they
+    # are not flat, and their kept edges (about 30k) overflow the LDS merge too
+    "random_300k": (lambda: I.random_graph(300000, 450000, seed=11, connected=True), 3),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_forest_paths_verified(ctx, rst, name):
+    build, paths = CASES[name]
+    g = build()
+    off, cols = dev(g.offsets_typed()), dev(g.cols)
+    k_ref, lab_ref = oracle.components(g.n, g.offsets, g.cols)
+    label, k = ctx.components(off, cols)
+    assert k == k_ref
+    assert np.array_equal(label.cpu().numpy(), lab_ref)
+    root = g.n // 2
+    par, st = ctx.spanning_tree(off, cols, root, "gconn", stats=True)
+    assert ctx.last_status == (0 if k_ref == 1 else rst.RST_E_DISCONNECTED)
+    assert st["paths"] == paths, st
+    assert st["components"] == k_ref
+    code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, par.cpu().numpy(), [root])
+    assert code == 0, (oracle.VERIFY_CODES[code], bad)
+
+
+def test_list_rank_paths(ctx):
+    """Random lists long enough for the global one-workgroup ranking and for
+    the multi-workgroup rounds."""
+    rs = np.random.RandomState(21)
+    for A in (100003, 600001):
+        order = rs.permutation(A)
+        cuts = np.sort(rs.choice(np.arange(1, A), size=5, replace=False))
+        succ = np.full(A, -1, np.int32)
+        for piece in np.split(order, cuts):
+            succ[piece[:-1]] = piece[1:]
+        exp, k = oracle.list_rank(succ)
+        assert k == 6
+        got = ctx.list_rank(dev(succ)).cpu().numpy()
+        assert np.array_equal(got, exp)

@@ -1,0 +1,170 @@
+"""GPU tests of the device verifier (rst_verify), of every sweep block size,
+and of the autotuner and its JSON cache.
+
+The verifier is checked against the oracle verifier on valid outputs and on
+parent arrays with planted mistakes (a non-edge, a two-cycle, a wrong root, an
+out-of-range id); the autotuner must return settings from its candidate sets,
+leave them applied, and produce verified trees with them; a saved cache must
+re-apply the same settings in a fresh context.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_11645_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rst():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_11645_amd as r
+    return r
+
+
+@pytest.fixture(scope="module")
+def ctx(rst):
+    return rst.Context(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def upload(g):
+    return dev(g.offsets_typed()), dev(g.cols)
+
+
+GRAPHS = [I.road_mesh(96, 0.15, 0.01, seed=2), I.rmat_lcc(11, 16, seed=3),
+          I.random_graph(3000, 1500, seed=5, connected=False), I.star(5000, 17), I.path(700)]
+
+
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
+def test_verify_accepts_valid_and_matches_oracle(ctx, gi):
+    g = GRAPHS[gi]
+    off, cols = upload(g)
+    root = g.n // 3
+    for method in ("gconn", "bfs"):
+        par = ctx.spanning_tree(off, cols, root, method)
+        bad, first = ctx.verify(off, cols, root, par)
+        code, _ = oracle.verify_rst(g.n, g.offsets, g.cols, par.cpu().numpy(), [root])
+        assert code == 0 and bad == 0 and first == -1
+
+
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
+def test_verify_rejects_planted_mistakes(ctx, gi):
+    g = GRAPHS[gi]
+    off, cols = upload(g)
+    root = g.n // 3
+    good = ctx.spanning_tree(off, cols, root, "gconn").cpu().numpy()
+    rs = np.random.RandomState(gi)
+    nonroot = np.nonzero(good != np.arange(g.n))[0]
+    cases = []
+    # a parent that is not a neighbour
+    v = int(rs.choice(nonroot))
+    nbrs = set(g.cols[g.offsets[v]:g.offsets[v + 1]].tolist())
+    w = next(x for x in rs.permutation(g.n) if x not in nbrs and x != v)
+    p = good.copy(); p[v] = w; cases.append(p)
+    # a two-cycle between a vertex and its parent (the parent is not a root)
+    cand = [x for x in nonroot if good[good[x]] != good[x]]
+    if cand:
+        x = int(cand[0]); y = int(good[x])
+        p = good.copy(); p[y] = x; cases.append(p)
+    # the designated root not self-parented
+    p = good.copy(); p[root] = int(g.cols[g.offsets[root]]) if g.offsets[root + 1] > g.offsets[root] else -1
+    cases.append(p)
+    # an out-of-range id
+    p = good.copy(); p[int(nonroot[-1])] = g.n + 5; cases.append(p)
+    for p in cases:
+        code, _ = oracle.verify_rst(g.n, g.offsets, g.cols, p, [root])
+        assert code != 0
+        bad, first = ctx.verify(off, cols, root, dev(p.astype(np.int32)))
+        assert bad > 0 and 0 <= first < g.n
+
+
+@pytest.mark.parametrize("block", [64, 128, 256, 512, 1024])
+def test_sweep_block_sizes(ctx, rst, block):
+    g = GRAPHS[0]
+    off, cols = upload(g)
+    old = ctx.get_option(rst.OPT_SWEEP_BLOCK)
+    try:
+        ctx.set_option(rst.OPT_SWEEP_BLOCK, block)
+        assert ctx.get_option(rst.OPT_SWEEP_BLOCK) == block
+        par = ctx.spanning_tree(off, cols, 5, "gconn").cpu().numpy()
+        code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, par, [5])
+        assert code == 0, (oracle.VERIFY_CODES[code], bad)
+    finally:
+        ctx.set_option(rst.OPT_SWEEP_BLOCK, old)
+    with pytest.raises(rst.RstError):
+        ctx.set_option(rst.OPT_SWEEP_BLOCK, 96)
+
+
+CANDIDATES = {5: {64, 128, 256, 512, 1024}, 4: {256, 1024, 4096, 16384}, 3: {1, 2, 4, 8},
+              1: {4, 8, 16, 32, 64, 128}, 2: {0, 512, 1024, 2048, 4096}, 6: {256, 1024, 4096, 16384}}
+
+
+@pytest.mark.parametrize("method,keys", [("gconn", {3, 4, 5}), ("bfs", {1, 2, 6})])
+def test_autotune_and_cache_round_trip(rst, tmp_path, method, keys):
+    g = I.road_mesh(128, 0.15, 0.01, seed=4)
+    off, cols = upload(g)
+    c1 = rst.Context(0)
+    res = c1.autotune(off, cols, 0, method, reps=2)
+    assert set(res["options"]) == keys
+    for k, v in res["options"].items():
+        assert v in CANDIDATES[k]
+        assert c1.get_option(k) == v
+    assert res["rejected"] == 0 and res["candidates"] > 0
+    assert 0 < res["ms_best"] <= res["ms_default"]
+    par = c1.spanning_tree(off, cols, 0, method).cpu().numpy()
+    assert oracle.verify_rst(g.n, g.offsets, g.cols, par, [0])[0] == 0
+    path = str(tmp_path / "tune.json")
+    c1.tune_save(path)
+    data = json.load(open(path))
+    assert data["format"] == "rst-tune-1" and len(data["entries"]) == 1
+    c2 = rst.Context(0)
+    assert c2.tune_load(path, off, cols, method)
+    for k, v in res["options"].items():
+        assert c2.get_option(k) == v
+    # another size class: merged but not applied
+    small = I.path(50)
+    so, sc = upload(small)
+    assert not rst.Context(0).tune_load(path, so, sc, method)
+
+
+def test_tune_load_rejects_malformed(rst, tmp_path):
+    c = rst.Context(0)
+    bad = tmp_path / "bad.json"
+    for text in ("", "{", '{"format": "other", "entries": {}}',
+                 '{"format": "rst-tune-1", "entries": {"k": {"ms": 1, "options": {"0": 1}}}}',
+                 '{"format": "rst-tune-1", "entries": {"k": {"ms": 1, "options": {"99": 1}}}}'):
+        bad.write_text(text)
+        with pytest.raises(rst.RstError):
+            c.tune_load(str(bad))
+    with pytest.raises(rst.RstError):
+        c.tune_load(str(tmp_path / "missing.json"))
+    # a matching entry with an out-of-range value is refused and changes nothing
+    g = I.path(50)
+    off, cols = upload(g)
+    before = c.get_option(5)
+    key_probe = tmp_path / "probe.json"
+    c.autotune(off, cols, 0, "gconn", reps=1)
+    c.tune_save(str(key_probe))
+    data = json.load(open(key_probe))
+    k = next(iter(data["entries"]))
+    data["entries"][k]["options"]["5"] = 96
+    key_probe.write_text(json.dumps(data))
+    c.set_option(5, before)
+    c3 = rst.Context(0)
+    with pytest.raises(rst.RstError):
+        c3.tune_load(str(key_probe), off, cols, "gconn")
+    assert c3.get_option(5) == 256
+    # and nothing was merged: saving the context's cache gives no entries
+    out = tmp_path / "after.json"
+    c3.tune_save(str(out))
+    assert json.load(open(out))["entries"] == {}
