@@ -342,17 +342,29 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
       }
       if (!__syncthreads_or(changed)) break;
     }
-    // walk 2, two rulers per thread: every non-exit arc gets (exit, hops to exit)
-    for (int qb = tid; qb < nslots; qb += 2 * kRankThreads) {
-      int q[2] = {qb, qb + kRankThreads};
-      int jj[2], k2[2] = {0, 0}, total[2] = {0, 0};
-      int32_t exg[2] = {0, 0};
+    // walk 2: every non-exit arc gets (exit, hops to exit).  The rulers' data
+    // go to registers first; then the region holds per-arc hop counts and ls
+    // the local exit of each arc it is done with, so that the rank words are
+    // written once, coalesced, at the end (written along the list they
+    // landed in partial lines).
+    int w_st[QP], w_tot[QP], w_ex[QP];
+#pragma unroll
+    for (int k = 0; k < QP; ++k) {
+      const int q = tid + k * kRankThreads;
+      w_st[k] = q < nslots ? r_start[q] : cnt;
+      w_tot[k] = q < nslots ? r_len[q] : 0;
+      w_ex[k] = q < nslots ? r_exit[q] : 0;
+    }
+    __syncthreads();
+    uint16_t *hp = reinterpret_cast<uint16_t *>(region);     // [kRankTile] hops to exit
+#pragma unroll
+    for (int k = 0; k < QP; k += 2) {
+      int jj[2], k2[2] = {0, 0};
       bool act[2];
 #pragma unroll
       for (int w = 0; w < 2; ++w) {
-        jj[w] = q[w] < nslots ? r_start[q[w]] : cnt;
+        jj[w] = (k + w < QP) ? w_st[k + w] : cnt;
         act[w] = jj[w] < cnt;
-        if (act[w]) { total[w] = r_len[q[w]]; exg[w] = (int32_t)(e0 + r_exit[q[w]]); }
       }
       while (act[0] || act[1]) {
 #pragma unroll
@@ -360,12 +372,20 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
           if (!act[w]) continue;
           const int sj = ls[jj[w]];
           if (sj < 0 || k2[w] > cnt) { act[w] = false; continue; }
-          rank[e0 + jj[w]] = pack_rank(exg[w], (uint32_t)(total[w] - k2[w]));
+          hp[jj[w]] = (uint16_t)(w_tot[k + w] - k2[w]);
+          ls[jj[w]] = (int16_t)w_ex[k + w];
           jj[w] = sj;
           ++k2[w];
           if ((sj % kRuler) == 0) act[w] = false;
         }
       }
+    }
+    __syncthreads();
+    // exits keep the word of the first pass; every other arc now has its exit
+#pragma unroll
+    for (int j = 0; j < kRankPer; ++j) {
+      const int i = tid + j * kRankThreads;
+      if (i < cnt && ls[i] >= 0) rank[e0 + i] = pack_rank((int32_t)(e0 + ls[i]), hp[i]);
     }
     return;
   }
@@ -470,16 +490,15 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
 // multi-block rounds.  counters[kCntExits] = M, counters[kCntRankRounds] =
 // rounds.
 constexpr int kSmallThreads = 1024;
-constexpr int kSmallPer = 26;
-constexpr int kSmallLds = kSmallPer * kSmallThreads;   // 26624 words, 156 KB of LDS
+constexpr int kSmallPer = 19;
+// 19456 words of 8 B (152 KB; the block-wide OR reduction takes a little LDS too)
+constexpr int kSmallLds = kSmallPer * kSmallThreads;
 constexpr int64_t kSmallGlobal = (int64_t)1 << 18;
-static_assert(kSmallLds < 32768, "LDS successors are 16-bit");
 
 __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__restrict__ Mp,
                                                               uint64_t *crank, uint64_t *tmp,
                                                               int64_t tmp_cap, int32_t *counters) {
-  __shared__ int16_t s_succ[kSmallLds];
-  __shared__ uint32_t s_hops[kSmallLds];
+  __shared__ uint64_t s_word[kSmallLds];   // (succ, hops) as in crank
   const int tid = threadIdx.x;
   const int64_t M = *Mp;
   if (tid == 0) counters[kCntExits] = (int32_t)M;
@@ -489,44 +508,42 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
   int max_rounds = 1;
   while (((int64_t)1 << max_rounds) < M) ++max_rounds;
   if (M <= kSmallLds) {
+    // Each thread keeps its own words in registers; a round gathers the
+    // successors' words from LDS, then (after a barrier) publishes its own.
     const int m = (int)M;
-    for (int i = tid; i < m; i += kSmallThreads) {
-      const uint64_t w = crank[i];
-      s_succ[i] = (int16_t)(int32_t)(uint32_t)w;
-      s_hops[i] = (uint32_t)(w >> 32);
+    uint64_t own[kSmallPer];
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+      const int i = tid + k * kSmallThreads;
+      own[k] = i < m ? crank[i] : pack_rank(-1, 0);
+      if (i < m) s_word[i] = own[k];
     }
     bool active = __syncthreads_or(1);
     while (active) {
-      int16_t ns[kSmallPer];
-      uint32_t nh[kSmallPer];
       bool more = false;
 #pragma unroll
       for (int k = 0; k < kSmallPer; ++k) {
-        const int i = tid + k * kSmallThreads;
-        ns[k] = -2;                       // -2: word unchanged this round
-        nh[k] = 0;
-        if (i < m) {
-          const int sc = s_succ[i];
-          if (sc >= 0) {
-            ns[k] = s_succ[sc];
-            nh[k] = s_hops[i] + s_hops[sc];
-          }
+        const int32_t sc = (int32_t)(uint32_t)own[k];
+        if (sc >= 0) {
+          const uint64_t nb = s_word[sc];
+          own[k] = (((own[k] >> 32) + (nb >> 32)) << 32) | (nb & 0xffffffffull);
+          more |= (int32_t)(uint32_t)nb >= 0;
         }
       }
       __syncthreads();
 #pragma unroll
       for (int k = 0; k < kSmallPer; ++k) {
         const int i = tid + k * kSmallThreads;
-        if (ns[k] != -2) {
-          s_succ[i] = ns[k];
-          s_hops[i] = nh[k];
-          more |= ns[k] >= 0;
-        }
+        if (i < m) s_word[i] = own[k];
       }
       ++rounds;
       active = __syncthreads_or(more) && rounds < max_rounds;
     }
-    for (int i = tid; i < m; i += kSmallThreads) crank[i] = pack_rank(s_succ[i], s_hops[i]);
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+      const int i = tid + k * kSmallThreads;
+      if (i < m) crank[i] = own[k];
+    }
   } else if (M <= kSmallGlobal && M <= tmp_cap) {
     uint64_t *src = crank, *dst = tmp;
     bool active = true;

@@ -276,6 +276,10 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
   }
   __syncthreads();
   if (tid == 0) {
+    if (blockIdx.x == 0) {   // read by the cross phase after this kernel
+      counters[kCntKept] = 0;
+      counters[kCntCrossOverflow] = 0;
+    }
     region_of[blockIdx.x] = region;
     tile_cross[blockIdx.x] = s_ncross;
     atomicAdd(&counters[kCntCross], s_ncross);
@@ -355,24 +359,22 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
 constexpr int kDedupSlots = 8192;       // LDS hash slots (64 KB) of k_cross_dedupe
 constexpr int kFlatCross = kTile;       // above this a tile's cross edges are hooked flat
 constexpr int kDedupPer = kFlatCross / kTileThreads;
-constexpr int kMergeTopLevels = 7;      // levels merged by the single final block (fallback)
 constexpr int kLdsSlots = 16384;        // root slots of k_cross_lds (key + parent: 128 KB)
 constexpr int kLdsPer = 16;             // kept edges per thread in k_cross_lds
 constexpr int kLdsEdges = kLdsPer * kTileThreads;
-constexpr int kLdsTiles = 4096;         // tile prefix held in LDS by k_cross_lds
 
 __device__ __forceinline__ int kept_count(int c) { return c > kFlatCross ? 0 : c; }
 
 __global__ __launch_bounds__(kTileThreads) void k_cross_dedupe(const int64_t *__restrict__ region_of,
                                                                int2 *cross, int32_t *tile_cross,
                                                                int slices, int32_t *cc, int32_t *tu,
-                                                               int32_t *tv, int32_t *counters) {
+                                                               int32_t *tv, int32_t *counters,
+                                                               int2 *kept_list, int split) {
   __shared__ unsigned long long tab[kDedupSlots];
-  __shared__ int s_kept;
+  __shared__ int s_kept, s_top, s_base;
   const int b = blockIdx.x / slices;
   const int part = blockIdx.x % slices;
   const int tid = threadIdx.x;
-  if (blockIdx.x == 0 && tid == 0) counters[kCntCrossOverflow] = 0;
   const int64_t region = region_of[b];
   const int cntb = tile_cross[b];
   if (cntb > kFlatCross) {
@@ -385,7 +387,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_dedupe(const int64_t *__
   }
   if (part != 0) return;
   for (int i = tid; i < kDedupSlots; i += kTileThreads) tab[i] = ~0ull;
-  if (tid == 0) s_kept = 0;
+  if (tid == 0) { s_kept = 0; s_top = 0; }
   // every edge of the tile is read (and its key formed) before any write-back
   int2 e[kDedupPer];
   bool keep[kDedupPer];
@@ -421,13 +423,30 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_dedupe(const int64_t *__
     }
   }
   __syncthreads();
+  int slot[kDedupPer];
 #pragma unroll
   for (int j = 0; j < kDedupPer; ++j) {
-    const int slot = wave_append(keep[j], &s_kept);
-    if (keep[j]) cross[region + slot] = e[j];
+    const int k = wave_append(keep[j], &s_kept);
+    if (keep[j]) cross[region + k] = e[j];
+    const bool top = keep[j] && cross_level(e[j].x, e[j].y) >= split;
+    slot[j] = wave_append(top, &s_top);
+    if (!top) slot[j] = -1;
   }
   __syncthreads();
-  if (tid == 0) tile_cross[b] = s_kept;
+  // kept edges of the levels >= split also go to one compact list (tiles in
+  // any order) for the final one-workgroup merge; past kLdsEdges that merge is
+  // not used, nor the list
+  if (tid == 0) {
+    tile_cross[b] = s_kept;
+    s_base = s_top ? atomicAdd(&counters[kCntKept], s_top) : 0;
+  }
+  __syncthreads();
+  const int kb0 = s_base;
+  if (kb0 + s_top <= kLdsEdges) {
+#pragma unroll
+    for (int j = 0; j < kDedupPer; ++j)
+      if (slot[j] >= 0) kept_list[kb0 + slot[j]] = e[j];
+  }
 }
 
 // Slot of global root `key` in the LDS table (inserted if new); -1 when the
@@ -443,65 +462,136 @@ __device__ __forceinline__ int lds_slot(int32_t key, int32_t *keys) {
 }
 static_assert(kLdsSlots == 1 << 14, "lds_slot hashes to 14 bits");
 
+// LDS union-find entries of k_cross_lds: parent slot in the low 14 bits; a
+// hooked slot also keeps 1 + the number of the kept edge that hooked it in
+// the bits above (roots hold just their own slot).  Path halving rewrites the
+// parent bits only.
+constexpr int kParMask = 0x3fff;
+
+__device__ __forceinline__ int lds_find_rec(int x, int *par) {
+  int w = par[x];
+  int p = w & kParMask;
+  while (p != x) {
+    const int wp = par[p];
+    const int gp = wp & kParMask;
+    par[x] = (w & ~kParMask) | gp;   // x's hook record is immutable, kept as is
+    x = p;
+    w = wp;
+    p = gp;
+  }
+  return x;
+}
+
+// One union in the LDS table (smaller global id wins); the winner of the
+// compare-and-swap stores the kept edge number g with the new parent.
+__device__ __forceinline__ void lds_union(int sa, int sb, int g, const int32_t *keys, int *par) {
+  int ra = lds_find_rec(sa, par), rb = lds_find_rec(sb, par);
+  while (ra != rb) {
+    const bool a_low = keys[ra] < keys[rb];
+    const int lo = a_low ? ra : rb, hi = a_low ? rb : ra;
+    const int old = atomicCAS(&par[hi], hi, lo | ((g + 1) << 14));
+    if (old == hi) return;
+    const int np = lds_find_rec(old & kParMask, par);
+    if (ra == hi) ra = np; else rb = np;
+  }
+}
+
+// Packed per-edge state of k_cross_lds: root slots (14 bits each) and level
+// (4 bits, below 15); ~0u marks no edge.
+__device__ __forceinline__ uint32_t pack_sab(int sa, int sb, int level) {
+  return (uint32_t)sa | ((uint32_t)sb << 14) | ((uint32_t)level << 28);
+}
+
+// One-workgroup LDS merge of the kept cross edges of levels [lo, hi).
+// kGroup: block g takes the tiles [g << group_log, (g + 1) << group_log) and
+// their kept edges below hi (their roots must lie in the group's vertex range,
+// else the block raises the flag and changes nothing); otherwise the single
+// block takes the compact list of the edges of the top levels.
+template <bool kGroup>
 __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__restrict__ region_of,
                                                             const int2 *__restrict__ cross,
                                                             const int32_t *__restrict__ tile_cross,
-                                                            int tiles, int levels, int32_t *cc,
-                                                            int32_t *tu, int32_t *tv,
-                                                            int32_t *counters) {
+                                                            const int2 *__restrict__ kept_list,
+                                                            int tiles, int lo, int hi,
+                                                            int group_log, int32_t *cc, int32_t *tu,
+                                                            int32_t *tv, int32_t *counters) {
   __shared__ int32_t keys[kLdsSlots];   // global root held by a slot, -1: empty
-  __shared__ int par[kLdsSlots];        // union-find parent slot
-  __shared__ int s_pref[kLdsTiles + 1]; // exclusive prefix of kept counts over tiles
+  __shared__ int par[kLdsSlots];        // union-find entries (see kParMask)
+  __shared__ int s_pref[kGroup ? kTileThreads + 1 : 1];   // kept counts of the group's tiles
   __shared__ int s_wave[kTileThreads / kWave];
-  __shared__ int s_carry, s_fail;
+  __shared__ int s_fail;
   const int tid = threadIdx.x;
-  if (tiles > kLdsTiles) {
-    if (tid == 0) counters[kCntCrossOverflow] = 1;
-    return;
-  }
-  for (int i = tid; i < kLdsSlots; i += kTileThreads) { keys[i] = -1; par[i] = i; }
-  if (tid == 0) { s_carry = 0; s_fail = 0; }
-  __syncthreads();
-  for (int b0 = 0; b0 < tiles; b0 += kTileThreads) {
-    const int b = b0 + tid;
-    const int c = b < tiles ? kept_count(tile_cross[b]) : 0;
-    int total;
+  const int64_t t0 = kGroup ? ((int64_t)blockIdx.x << group_log) : 0;
+  const int64_t t1 = kGroup ? ((t0 + ((int64_t)1 << group_log)) < tiles
+                                   ? t0 + ((int64_t)1 << group_log) : (int64_t)tiles) : 0;
+  int total;
+  if (kGroup) {
+    const int64_t tb = t0 + tid;
+    const int c = tb < t1 ? kept_count(tile_cross[tb]) : 0;
     const int ex = block_excl_scan<kTileThreads>(c, s_wave, &total);
-    if (b < tiles) s_pref[b] = s_carry + ex;
-    __syncthreads();
-    if (tid == 0) s_carry += total;
-    __syncthreads();
+    s_pref[tid] = ex;
+  } else {
+    total = counters[kCntKept];
   }
-  const int total = s_carry;
-  if (tid == 0) s_pref[tiles] = total;
-  if (total > kLdsEdges) {
+  if (total > kLdsEdges || hi >= 15) {
     if (tid == 0) counters[kCntCrossOverflow] = 1;
     return;
   }
   if (total == 0) return;
+  for (int i = tid; i < kLdsSlots; i += kTileThreads) { keys[i] = -1; par[i] = i; }
+  if (tid == 0) s_fail = 0;
   __syncthreads();
-  // this thread's kept edges and the roots they join (only this block writes
-  // cc during the kernel, so the finds end at true roots)
-  int2 e[kLdsPer];
-  int sab[kLdsPer];                     // slot of the root of e.x (low 16) and e.y (high 16)
+  const int32_t own_lo = kGroup ? (int32_t)(t0 << kTileShift) : 0;
+  const int32_t own_hi = kGroup ? (int32_t)((t1 << kTileShift) - 1) : 0x7fffffff;
+  auto edge_at = [&](int g) -> int2 {
+    if (!kGroup) return kept_list[g];
+    const int k = lds_upper_search(s_pref, kTileThreads, g);
+    return cross[region_of[t0 + k] + (g - s_pref[k])];
+  };
+  // Edge g = tid + k * kTileThreads is this thread's k-th.  The roots it joins
+  // are found with the first two hops of a batch of edges issued together
+  // (one hop reaches the tile-local root, usually a root already); only the
+  // rest walk on.  No other block writes these roots now, so the finds end at
+  // true roots.
+  uint32_t sab[kLdsPer];                // pack_sab(slot of root(x), slot of root(y), level)
+  constexpr int kBatch = 8;
 #pragma unroll
-  for (int k = 0; k < kLdsPer; ++k) {
-    const int g = tid + k * kTileThreads;
-    e[k] = make_int2(-1, -1);
-    sab[k] = -1;
-    if (g < total) {
-      const int t = lds_upper_search(s_pref, tiles, g);
-      e[k] = cross[region_of[t] + (g - s_pref[t])];
+  for (int k0 = 0; k0 < kLdsPer; k0 += kBatch) {
+    int2 e[kBatch];
+    int32_t fa[kBatch], fb[kBatch], ga[kBatch], gb[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int g = tid + (k0 + j) * kTileThreads;
+      e[j] = make_int2(-1, -1);
+      if (g < total) {
+        const int2 x = edge_at(g);
+        const int lv = cross_level(x.x, x.y);
+        if (lv >= lo && lv < hi) e[j] = x;
+      }
     }
-  }
 #pragma unroll
-  for (int k = 0; k < kLdsPer; ++k) {
-    if (e[k].x >= 0) {
-      const int32_t ra = find_root(e[k].x, cc), rb = find_root(e[k].y, cc);
-      if (ra != rb) {
-        const int sa = lds_slot(ra, keys), sb = lds_slot(rb, keys);
-        if (sa < 0 || sb < 0) s_fail = 1;
-        else sab[k] = sa | (sb << 16);
+    for (int j = 0; j < kBatch; ++j) {
+      fa[j] = e[j].x >= 0 ? cc[e[j].x] : 0;
+      fb[j] = e[j].x >= 0 ? cc[e[j].y] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      ga[j] = e[j].x >= 0 ? cc[fa[j]] : 0;
+      gb[j] = e[j].x >= 0 ? cc[fb[j]] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      sab[k0 + j] = ~0u;
+      if (e[j].x >= 0) {
+        const int32_t ra = ga[j] == fa[j] ? fa[j] : find_root(ga[j], cc);
+        const int32_t rb = gb[j] == fb[j] ? fb[j] : find_root(gb[j], cc);
+        if (ra < own_lo || ra > own_hi || rb < own_lo || rb > own_hi) {
+          s_fail = 1;                     // a root owned by another group
+        } else if (ra != rb) {
+          const int sa = lds_slot(ra, keys), sb = lds_slot(rb, keys);
+          if (sa < 0 || sb < 0) s_fail = 1;
+          else sab[k0 + j] = pack_sab(sa, sb, cross_level(e[j].x, e[j].y));
+        }
       }
     }
   }
@@ -510,29 +600,36 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
     if (tid == 0) counters[kCntCrossOverflow] = 1;
     return;
   }
-  for (int l = 0; l < levels; ++l) {
+  for (int l = lo; l < hi; ++l) {
 #pragma unroll
     for (int k = 0; k < kLdsPer; ++k) {
-      if (sab[k] >= 0 && cross_level(e[k].x, e[k].y) == l) {
-        int ra = lds_find(sab[k] & 0xffff, par), rb = lds_find(sab[k] >> 16, par);
-        while (ra != rb) {
-          const bool a_low = keys[ra] < keys[rb];
-          const int lo = a_low ? ra : rb, hi = a_low ? rb : ra;
-          const int old = atomicCAS(&par[hi], hi, lo);
-          if (old == hi) {
-            tu[keys[hi]] = e[k].x;
-            tv[keys[hi]] = e[k].y;
-            break;
-          }
-          if (ra == hi) ra = lds_find(old, par); else rb = lds_find(old, par);
-        }
-      }
+      const uint32_t v = sab[k];
+      if (v != ~0u && (int)(v >> 28) == l)
+        lds_union((int)(v & 0x3fff), (int)((v >> 14) & 0x3fff), tid + k * kTileThreads, keys, par);
     }
     __syncthreads();
   }
-  // every hooked root points straight at its final root
-  for (int i = tid; i < kLdsSlots; i += kTileThreads) {
-    if (keys[i] >= 0 && par[i] != i) cc[keys[i]] = keys[lds_find(i, par)];
+  // every hooked root points straight at its final root and records the
+  // kept edge that hooked it (all edge lookups issued together)
+  constexpr int kSlotsPer = kLdsSlots / kTileThreads;
+  int hooked[kSlotsPer];
+#pragma unroll
+  for (int k = 0; k < kSlotsPer; ++k) {
+    const int i = tid + k * kTileThreads;
+    const int w = par[i];
+    hooked[k] = (keys[i] >= 0 && (w & kParMask) != i) ? (w >> 14) - 1 : -1;
+  }
+  int2 he[kSlotsPer];
+#pragma unroll
+  for (int k = 0; k < kSlotsPer; ++k) he[k] = hooked[k] >= 0 ? edge_at(hooked[k]) : make_int2(0, 0);
+#pragma unroll
+  for (int k = 0; k < kSlotsPer; ++k) {
+    if (hooked[k] < 0) continue;
+    const int i = tid + k * kTileThreads;
+    const int32_t key = keys[i];
+    cc[key] = keys[lds_find_rec(i, par)];
+    tu[key] = he[k].x;
+    tv[key] = he[k].y;
   }
   wave_release_device();
 }
@@ -686,26 +783,42 @@ int hook_level_count(int64_t n) {
   while (((size_t)1 << l) < hook_tile_count(n)) ++l;
   return l;
 }
-// tile_cross buffer: int32 counts, int64 region starts, int32 level ranges
-size_t hook_tile_words(int64_t n) { return ((hook_tile_count(n) + 1) & ~size_t(1)) + 3 * hook_tile_count(n); }
+// tile_cross buffer: int32 counts, int64 region starts, int32 level ranges,
+// then the compact list of kept cross edges (int2 [kLdsEdges])
+size_t hook_tile_words(int64_t n) {
+  const size_t tc = hook_tile_count(n), even = (tc + 1) & ~size_t(1);
+  return even + 2 * tc + even + 2 * (size_t)kLdsEdges;
+}
 
 static rst_status launch_cross(rst_ctx *ctx, unsigned tiles, int levels,
                                const int64_t *region_of, int2 *cross, int32_t *tile_cross,
-                               const int32_t *tile_lvl, ForestBufs &f) {
+                               const int32_t *tile_lvl, int2 *kept_list, ForestBufs &f) {
   if (levels == 0) return RST_OK;       // one tile: no cross edges
   RST_KMARK(ctx, RST_KERNEL_CROSS, 0);
+  // levels below `split` are merged per group of 2^split tiles (one workgroup
+  // each), the rest by one workgroup
+  int split = levels <= 3 ? 0 : levels / 2;
+  if (split > 10) split = 10;
   // flat tiles are split over several blocks when there are few tiles
   unsigned slices = (1024 + tiles - 1) / tiles;
   slices = slices < 1 ? 1 : (slices > 64 ? 64 : slices);
   hipLaunchKernelGGL(k_cross_dedupe, dim3(tiles * slices), dim3(kTileThreads), 0, ctx->stream,
-                     region_of, cross, tile_cross, (int)slices, f.cc, f.tu, f.tv, f.counters);
+                     region_of, cross, tile_cross, (int)slices, f.cc, f.tu, f.tv, f.counters,
+                     kept_list, split);
   RST_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_cross_lds, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of, cross,
-                     tile_cross, (int)tiles, levels, f.cc, f.tu, f.tv, f.counters);
-  RST_HIP(hipGetLastError());
-  const int split = levels > kMergeTopLevels ? levels - kMergeTopLevels : 0;
+  const unsigned groups = (tiles + (1u << split) - 1) >> split;
   if (split > 0) {
-    const unsigned groups = (tiles + (1u << split) - 1) >> split;
+    hipLaunchKernelGGL(k_cross_lds<true>, dim3(groups), dim3(kTileThreads), 0, ctx->stream,
+                       region_of, cross, tile_cross, kept_list, (int)tiles, 0, split, split, f.cc,
+                       f.tu, f.tv, f.counters);
+    RST_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_cross_lds<false>, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of,
+                     cross, tile_cross, kept_list, (int)tiles, split, levels, levels, f.cc, f.tu,
+                     f.tv, f.counters);
+  RST_HIP(hipGetLastError());
+  // global-memory fallback, active only when a merge above raised the flag
+  if (split > 0) {
     hipLaunchKernelGGL(k_cross_merge, dim3(groups), dim3(kTileThreads), 0, ctx->stream, region_of,
                        cross, tile_cross, tile_lvl, (int)tiles, 0, split, split, f.cc, f.tu, f.tv,
                        f.counters);
@@ -724,6 +837,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
   const size_t tc = hook_tile_count(g->n);
   int64_t *region_of = reinterpret_cast<int64_t *>(tile_cross + ((tc + 1) & ~size_t(1)));
   int32_t *tile_lvl = reinterpret_cast<int32_t *>(region_of + tc);
+  int2 *kept_list = reinterpret_cast<int2 *>(tile_lvl + ((tc + 1) & ~size_t(1)));
   const int64_t n = g->n;
   const unsigned tiles = grid_for(n, kTile);
   const unsigned heavy_grid = (unsigned)(ctx->num_cus * 8);
@@ -737,7 +851,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
                        f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
-    RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, f));
+    RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));
     hipLaunchKernelGGL(k_hook_heavy<int32_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream, off,
                        g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters);
   } else {
@@ -748,7 +862,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
                        f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
-    RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, f));
+    RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));
     hipLaunchKernelGGL(k_hook_heavy<int64_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream, off,
                        g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters);
   }

@@ -148,6 +148,7 @@ enum {
   kCntCrossOverflow = 10,  // kept cross edges did not fit the LDS merge (fallback ran)
   kCntRankOverflow = 11,   // contracted list did not fit the one-block ranking
   kCntRankRounds = 12,     // pointer-jumping rounds of the contracted list
+  kCntKept = 13,           // cross edges kept by the deduplication pass
   kCntTotal = 16
 };
 

@@ -38,21 +38,38 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+def mesh_plus_hub(seed=13):
+    """A 512x512 road-like mesh (32 tiles) and one more tile of 8192 hub
+    vertices, each joined to 3 random mesh vertices: the hub tile lists far
+    more cross edges than vertices (hooked flat), and its hooks join trees of
+    high tiles to roots in low tiles, so a group of tiles meets a root outside
+    its own range and the LDS merge falls back to global memory."""
+    mesh = I.road_mesh(512, 0.15, 0.001, seed=2)
+    n0 = mesh.n
+    rs = np.random.RandomState(seed)
+    hub = np.repeat(np.arange(n0, n0 + 8192), 3)
+    far = rs.randint(0, n0, size=hub.size)
+    src = np.repeat(np.arange(n0), np.diff(mesh.offsets))
+    keep = src < mesh.cols
+    eu = np.concatenate([src[keep], hub]).astype(np.int32)
+    ev = np.concatenate([mesh.cols[keep], far]).astype(np.int32)
+    return I.csr_from_edges(n0 + 8192, eu, ev, name="mesh_plus_hub")
+
+
+# name: (graph builder, rst_stats.paths bits that must be set, bits that must not)
 CASES = {
-    # name: (graph builder, expected rst_stats.paths bits)
-    "grid_permuted_256": (lambda: I.grid_permuted(256, seed=1), 0),
-    "grid_1024_del30": (lambda: I.grid(1024, 1024, 0.30, seed=7), 0),
-    "grid_1024_del45": (lambda: I.grid(1024, 1024, 0.45, seed=7), 1),
-    "road_512": (lambda: I.road_mesh(512, 0.15, 0.001, seed=2), 0),
-    # low-index tiles list few cross edges (only those to smaller ids), so they
-    # are not flat, and their kept edges (about 30k) overflow the LDS merge too
-    "random_300k": (lambda: I.random_graph(300000, 450000, seed=11, connected=True), 3),
+    "grid_permuted_256": (lambda: I.grid_permuted(256, seed=1), 0, 3),
+    "grid_1024_del30": (lambda: I.grid(1024, 1024, 0.30, seed=7), 0, 3),
+    "grid_1024_del45": (lambda: I.grid(1024, 1024, 0.45, seed=7), 0, 3),
+    "road_512": (lambda: I.road_mesh(512, 0.15, 0.001, seed=2), 0, 3),
+    "random_300k": (lambda: I.random_graph(300000, 450000, seed=11, connected=True), 2, 0),
+    "mesh_plus_hub": (mesh_plus_hub, 1, 0),
 }
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
 def test_forest_paths_verified(ctx, rst, name):
-    build, paths = CASES[name]
+    build, must, must_not = CASES[name]
     g = build()
     off, cols = dev(g.offsets_typed()), dev(g.cols)
     k_ref, lab_ref = oracle.components(g.n, g.offsets, g.cols)
@@ -62,7 +79,7 @@ def test_forest_paths_verified(ctx, rst, name):
     root = g.n // 2
     par, st = ctx.spanning_tree(off, cols, root, "gconn", stats=True)
     assert ctx.last_status == (0 if k_ref == 1 else rst.RST_E_DISCONNECTED)
-    assert st["paths"] == paths, st
+    assert (st["paths"] & must) == must and (st["paths"] & must_not) == 0, st
     assert st["components"] == k_ref
     code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, par.cpu().numpy(), [root])
     assert code == 0, (oracle.VERIFY_CODES[code], bad)
