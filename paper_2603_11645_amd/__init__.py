@@ -435,6 +435,11 @@ class Context:
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._call("rst_selector_load", ctypes.cast(buf, ctypes.c_void_p), len(blob))
 
+    def selector_load_default(self):
+        """Load the selector weights shipped with the package (selector_weights.bin)."""
+        with open(os.path.join(_HERE, "selector_weights.bin"), "rb") as f:
+            self.selector_load(f.read())
+
 
 def selector_blob(norm, params) -> bytes:
     """Serialise normalisation (16 floats) and parameters (4866 floats)."""

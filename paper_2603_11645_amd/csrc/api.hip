@@ -51,20 +51,29 @@ static rst_status run_validation(rst_ctx *ctx, const rst_csr *g, int32_t *counte
   return RST_OK;
 }
 
+// Elapsed time between two events of this call; a failed query (an event the
+// call did not record) leaves no error behind for later hipGetLastError checks.
+static bool event_ms(hipEvent_t a, hipEvent_t b, float *ms) {
+  if (hipEventElapsedTime(ms, a, b) == hipSuccess) return true;
+  (void)hipGetLastError();
+  return false;
+}
+
 static void fill_stage_times(rst_ctx *ctx, rst_stats *st, const int *stage_of_gap, int nev) {
   float ms = 0.f;
   for (int i = 0; i + 1 < nev; ++i) {
-    if (hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]) == hipSuccess && stage_of_gap[i] >= 0)
+    if (stage_of_gap[i] >= 0 && event_ms(ctx->ev[i], ctx->ev[i + 1], &ms))
       st->ms_stage[stage_of_gap[i]] += ms;
   }
-  if (hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[nev - 1]) == hipSuccess) st->ms_total = ms;
+  if (event_ms(ctx->ev[0], ctx->ev[nev - 1], &ms)) st->ms_total = ms;
 }
 
+// kernels whose two events were recorded during this call only
 static void fill_kernel_times(rst_ctx *ctx, rst_stats *st) {
   for (int k = 0; k < 4; ++k) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ctx->ev[kEvKernelBase + 2 * k], ctx->ev[kEvKernelBase + 2 * k + 1]) ==
-        hipSuccess)
+    if (((ctx->kev_mask >> (2 * k)) & 3u) != 3u) continue;
+    if (event_ms(ctx->ev[kEvKernelBase + 2 * k], ctx->ev[kEvKernelBase + 2 * k + 1], &ms))
       st->ms_kernel[k] = ms;
   }
 }
@@ -72,7 +81,7 @@ static void fill_kernel_times(rst_ctx *ctx, rst_stats *st) {
 // enables per-kernel events for the duration of one API call
 struct TimingScope {
   rst_ctx *ctx;
-  TimingScope(rst_ctx *c, bool on) : ctx(c) { ctx->timing = on; }
+  TimingScope(rst_ctx *c, bool on) : ctx(c) { ctx->timing = on; ctx->kev_mask = 0; }
   ~TimingScope() { ctx->timing = false; }
 };
 
@@ -300,9 +309,26 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
   if (!ctx || !parent) return RST_E_INVAL;
   RST_TRY(check_csr(g));
   if (root < 0 || root >= g->n) return RST_E_INVAL;
-  if (method == RST_AUTO) method = RST_GCONN_EULER;
-  if (method != RST_GCONN_EULER && method != RST_BFS) return RST_E_INVAL;
+  if (method != RST_GCONN_EULER && method != RST_BFS && method != RST_AUTO) return RST_E_INVAL;
   RST_HIP(hipSetDevice(ctx->device));
+  if (method == RST_AUTO) {
+    // the selector's choice for this one graph (GConn+Euler without a selector)
+    method = RST_GCONN_EULER;
+    if (ctx->selector) {
+      RST_TRY(ws_reserve(ctx, 3 * ws_bytes(2, 8) + ws_bytes(1, 1) + selector_scratch_bytes(ctx, g, 1)));
+      int64_t *vtx_off = ws_take<int64_t>(ctx, 2);
+      int64_t *arc_off = ws_take<int64_t>(ctx, 2);
+      int32_t *roots = reinterpret_cast<int32_t *>(ws_take<int64_t>(ctx, 2));
+      uint8_t *choice = ws_take<uint8_t>(ctx, 1);
+      RST_TRY(enqueue_single_batch(ctx, g, root, vtx_off, arc_off, roots));
+      const rst_batch one{1, vtx_off, arc_off, roots};
+      RST_TRY(run_selector(ctx, g, &one, choice));
+      uint8_t *hc = reinterpret_cast<uint8_t *>(ctx->host_pinned + 44);
+      RST_HIP(hipMemcpyAsync(hc, choice, 1, hipMemcpyDeviceToHost, ctx->stream));
+      RST_HIP(hipStreamSynchronize(ctx->stream));
+      if (*hc) method = RST_BFS;
+    }
+  }
   if (stats) std::memset(stats, 0, sizeof(*stats));
   TimingScope timing(ctx, stats != nullptr);
 
@@ -645,10 +671,8 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
   RST_HIP(hipStreamSynchronize(ctx->stream));
   if (stats) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, ctx->ev[16], ctx->ev[17]) == hipSuccess)
-      stats->ms_stage[RST_STAGE_SELECT] = ms;
-    if (nbfs > 0 && hipEventElapsedTime(&ms, ctx->ev[18], ctx->ev[19]) == hipSuccess)
-      stats->ms_stage[RST_STAGE_BFS] = ms;
+    if (event_ms(ctx->ev[16], ctx->ev[17], &ms)) stats->ms_stage[RST_STAGE_SELECT] = ms;
+    if (nbfs > 0 && event_ms(ctx->ev[18], ctx->ev[19], &ms)) stats->ms_stage[RST_STAGE_BFS] = ms;
     stats->ms_total = 0.f;
     for (int i = 0; i < 8; ++i) stats->ms_total += stats->ms_stage[i];
     stats->bfs_levels = levels;

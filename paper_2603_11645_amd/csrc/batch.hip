@@ -63,6 +63,24 @@ __global__ void k_fill_u8(uint8_t *dst, int64_t count, uint8_t value) {
   if (i < count) dst[i] = value;
 }
 
+// The offset tables of a batch holding one graph (all n vertices, root r).
+__global__ void k_single_batch(int64_t n, int64_t nnz, int32_t root, int64_t *vtx_off,
+                               int64_t *arc_off, int32_t *roots) {
+  if (threadIdx.x == 0) {
+    vtx_off[0] = 0; vtx_off[1] = n;
+    arc_off[0] = 0; arc_off[1] = nnz;
+    roots[0] = root;
+  }
+}
+
+rst_status enqueue_single_batch(rst_ctx *ctx, const rst_csr *g, int32_t root, int64_t *vtx_off,
+                                int64_t *arc_off, int32_t *roots) {
+  hipLaunchKernelGGL(k_single_batch, dim3(1), dim3(64), 0, ctx->stream, g->n, g->nnz, root, vtx_off,
+                     arc_off, roots);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
 rst_status enqueue_graph_mask(rst_ctx *ctx, const rst_batch *b, const uint8_t *method,
                               uint8_t *vmask) {
   hipLaunchKernelGGL(k_graph_mask, dim3((unsigned)b->num_graphs), dim3(kBlock), 0, ctx->stream,

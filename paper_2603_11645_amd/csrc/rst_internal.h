@@ -59,6 +59,8 @@ rst_status enqueue_batch_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *
 rst_status enqueue_count_methods(rst_ctx *ctx, const rst_batch *b, const uint8_t *m,
                                  int32_t *counters);
 rst_status enqueue_copy_u8(rst_ctx *ctx, const uint8_t *src, uint8_t *dst, int64_t count);
+rst_status enqueue_single_batch(rst_ctx *ctx, const rst_csr *g, int32_t root, int64_t *vtx_off,
+                                int64_t *arc_off, int32_t *roots);
 rst_status enqueue_fill_u8(rst_ctx *ctx, uint8_t *dst, int64_t count, uint8_t value);
 
 // selector.hip
@@ -77,6 +79,7 @@ struct rst_ctx {
   hipEvent_t ev[24] = {};   // 0-6 stages, 8-15 kernel pairs, 16-19 batch marks
   int32_t *host_pinned = nullptr;   // small pinned host buffer for flag readback
   bool timing = false;              // record per-kernel events (a stats struct was passed)
+  unsigned kev_mask = 0;            // kernel events recorded during the current call
   rst::Selector *selector = nullptr;
   rst::TuneCache *tune = nullptr;   // autotuned settings by graph class
 };
@@ -96,8 +99,10 @@ namespace rst {
 enum { kEvKernelBase = 8 };
 #define RST_KMARK(ctx, kernel, end)                                                          \
   do {                                                                                        \
-    if ((ctx)->timing)                                                                        \
+    if ((ctx)->timing) {                                                                      \
       RST_HIP(hipEventRecord((ctx)->ev[kEvKernelBase + 2 * (kernel) + (end)], (ctx)->stream)); \
+      (ctx)->kev_mask |= 1u << (2 * (kernel) + (end));                                        \
+    }                                                                                         \
   } while (0)
 
 #define RST_TRY(call)                                   \

@@ -168,3 +168,18 @@ def test_tune_load_rejects_malformed(rst, tmp_path):
     out = tmp_path / "after.json"
     c3.tune_save(str(out))
     assert json.load(open(out))["entries"] == {}
+
+
+def test_stats_on_one_tile_graph_leave_no_error(rst):
+    """A one-tile graph has no cross stage: with stats on a fresh context its
+    kernel time reads 0 and the calls after it still succeed."""
+    c = rst.Context(0)
+    g = I.path(30)
+    off, cols = upload(g)
+    par, st = c.spanning_tree(off, cols, 0, "gconn", stats=True)
+    assert st["ms_kernel"]["cross"] == 0.0 and st["ms_kernel"]["hook_tile"] > 0.0
+    b = I.pack([g])
+    feat = c.features(off, cols, dev(b.vtx_off), dev(b.arc_off), dev(np.array([0], np.int32)))
+    assert feat.shape == (1, 8)
+    label, k = c.components(off, cols)
+    assert k == 1
