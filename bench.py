@@ -181,8 +181,9 @@ def main():
     w_o = g.offset_bytes
     X = stats[-1]["cross_edges"]
     kern_bytes = {
-        # offsets + neighbour ids read, labels/edge slots written, cross list written
-        "hook_tile": w_o * (n + 1) + 4 * nnz + 12 * n + 8 * X,
+        # offsets + neighbour ids read, labels/edge slots written, cross list
+        # written, arc-list heads and next pairs written
+        "hook_tile": w_o * (n + 1) + 4 * nnz + 12 * n + 8 * X + 12 * n,
         # cross stage (deduplication pass + level merges, timed as one unit):
         # every cross edge read once and its two tree labels gathered
         "cross": 16 * X,
@@ -190,10 +191,14 @@ def main():
         # half the arcs) + exit index (4) + ranking word (8)
         "rank_tile": 22 * A,
         # per slot: edge read (8) + two list-head exchanges (16) + next pair (8)
+        # (only when the separate link kernel runs)
         "link": 32 * n,
     }
     kern_launches = {"hook_tile": 1, "cross": 1, "rank_tile": 1, "link": 1}
     kernels = {}
+    # kernels the step actually ran (the arc lists are linked inside the hooking
+    # passes, so the separate link kernel does not run on this path)
+    kern_ms = {k: v for k, v in kern_ms.items() if v > 0}
     for k in kern_ms:
         per_launch = kern_ms[k] / kern_launches[k]
         gbs = kern_bytes[k] / (per_launch * 1e-3) / 1e9 if per_launch > 0 else 0.0

@@ -128,13 +128,16 @@ rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
   int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
   RankBufs rb = take_rank_bufs(ctx, 2 * n);
 
+  // the arc lists are built while hooking (tile pass in LDS, later hooks by
+  // atomic exchange), so no separate linking pass runs
+  f.head = head;
+  f.next = next;
   RST_TRY(mark(ctx, st, 0));
   RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
   RST_TRY(mark(ctx, st, 1));
-  RST_TRY(enqueue_compress(ctx, n, f.cc, f.comp_root, head));
+  RST_TRY(enqueue_compress(ctx, n, f.cc, f.comp_root, nullptr));
   RST_TRY(mark(ctx, st, 2));
   RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, f.cc, f.comp_root, parent, counters));
-  RST_TRY(enqueue_link(ctx, n, f.tu, f.tv, head, next));
   RST_TRY(mark(ctx, st, 3));
   // the successor pass is fused into the first ranking pass (stage "succ" stays empty)
   RST_TRY(mark(ctx, st, 4));

@@ -44,10 +44,22 @@ __device__ __forceinline__ int32_t find_root(int32_t x, int32_t *cc) {
   return cur;
 }
 
-// Hook the trees of u and v; on success record (u,v) at the hooked root.
+// Arcs 2x = a->b and 2x+1 = b->a of the edge recorded at slot x, each put in
+// front of its source's list.
+__device__ __forceinline__ void link_slot(int32_t x, int32_t a, int32_t b, int32_t *head,
+                                          int32_t *next) {
+  int2 nx;
+  nx.x = atomicExch(&head[a], 2 * x);
+  nx.y = atomicExch(&head[b], 2 * x + 1);
+  reinterpret_cast<int2 *>(next)[x] = nx;
+}
+
+// Hook the trees of u and v; on success record (u,v) at the hooked root (and
+// link its two arcs when head is non-NULL).
 template <bool kRecord>
 __device__ __forceinline__ void hook_edge(int32_t u, int32_t v, int32_t *cc, int32_t *tu,
-                                          int32_t *tv) {
+                                          int32_t *tv, int32_t *head = nullptr,
+                                          int32_t *next = nullptr) {
   int32_t ru = find_root(u, cc);
   int32_t rv = find_root(v, cc);
   while (ru != rv) {
@@ -55,7 +67,11 @@ __device__ __forceinline__ void hook_edge(int32_t u, int32_t v, int32_t *cc, int
     const int32_t hi = ru < rv ? rv : ru;
     const int32_t old = atomicCAS(&cc[hi], hi, lo);
     if (old == hi) {
-      if (kRecord) { tu[hi] = u; tv[hi] = v; }
+      if (kRecord) {
+        tu[hi] = u;
+        tv[hi] = v;
+        if (head) link_slot(hi, u, v, head, next);
+      }
       return;
     }
     // hi was hooked meanwhile: continue from its new parent (an ancestor)
@@ -154,7 +170,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
     int64_t n, const OffT *__restrict__ off, const int32_t *__restrict__ cols, int32_t *cc,
     int32_t *tu, int32_t *tv, int2 *cross, int32_t *tile_cross, int32_t *tile_lvl,
     int64_t *region_of, int32_t *counters, int64_t *chunks, int64_t chunk_cap, int heavy_deg,
-    const uint8_t *__restrict__ vmask) {
+    const uint8_t *__restrict__ vmask, int32_t *head, int32_t *next) {
   __shared__ int lp[kTile];
   __shared__ int16_t eu[kTile];     // local endpoints of the edge held by a slot (-1: none)
   __shared__ int16_t ev[kTile];
@@ -331,6 +347,41 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
       tv[v0 + i] = a >= 0 ? (int32_t)(v0 + ev[i]) : -1;
     }
   }
+  if (!head) return;
+  // Euler arc lists of the tile's own edges, built in LDS (the degree scan is
+  // no longer needed) and written once, coalesced: local arc 2i / 2i+1 of slot
+  // i is global arc 2(v0+i) / 2(v0+i)+1.
+  int *lhead = s_beg;                                   // [kTile] first local arc
+  int16_t *lnext = reinterpret_cast<int16_t *>(s_scan);  // [2 kTile] next local arc
+  for (int i = tid; i < kTile; i += kTileThreads) lhead[i] = -1;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kTilePer; ++j) {
+    const int i = tid + j * kTileThreads;
+    if (i < cnt) {
+      const int a = eu[i];
+      int16_t n0 = -1, n1 = -1;
+      if (a >= 0) {
+        n0 = (int16_t)atomicExch(&lhead[a], 2 * i);
+        n1 = (int16_t)atomicExch(&lhead[ev[i]], 2 * i + 1);
+      }
+      lnext[2 * i] = n0;
+      lnext[2 * i + 1] = n1;
+    }
+  }
+  __syncthreads();
+  const int32_t arc0 = (int32_t)(2 * v0);
+#pragma unroll
+  for (int j = 0; j < kTilePer; ++j) {
+    const int i = tid + j * kTileThreads;
+    if (i < cnt) {
+      const int h = lhead[i];
+      head[v0 + i] = h >= 0 ? arc0 + h : -1;
+      const int n0 = lnext[2 * i], n1 = lnext[2 * i + 1];
+      reinterpret_cast<int2 *>(next)[v0 + i] =
+          make_int2(n0 >= 0 ? arc0 + n0 : -1, n1 >= 0 ? arc0 + n1 : -1);
+    }
+  }
 }
 
 // Cross phase.  After the tile pass every vertex points at its tile-local
@@ -369,7 +420,8 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_dedupe(const int64_t *__
                                                                int2 *cross, int32_t *tile_cross,
                                                                int slices, int32_t *cc, int32_t *tu,
                                                                int32_t *tv, int32_t *counters,
-                                                               int2 *kept_list, int split) {
+                                                               int2 *kept_list, int split,
+                                                               int32_t *head, int32_t *next) {
   __shared__ unsigned long long tab[kDedupSlots];
   __shared__ int s_kept, s_top, s_base;
   const int b = blockIdx.x / slices;
@@ -380,7 +432,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_dedupe(const int64_t *__
   if (cntb > kFlatCross) {
     for (int i = part * kTileThreads + tid; i < cntb; i += slices * kTileThreads) {
       const int2 e = cross[region + i];
-      hook_edge<true>(e.x, e.y, cc, tu, tv);
+      hook_edge<true>(e.x, e.y, cc, tu, tv, head, next);
     }
     wave_release_device();
     return;
@@ -514,7 +566,8 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
                                                             const int2 *__restrict__ kept_list,
                                                             int tiles, int lo, int hi,
                                                             int group_log, int32_t *cc, int32_t *tu,
-                                                            int32_t *tv, int32_t *counters) {
+                                                            int32_t *tv, int32_t *counters,
+                                                            int32_t *head, int32_t *next) {
   __shared__ int32_t keys[kLdsSlots];   // global root held by a slot, -1: empty
   __shared__ int par[kLdsSlots];        // union-find entries (see kParMask)
   __shared__ int s_pref[kGroup ? kTileThreads + 1 : 1];   // kept counts of the group's tiles
@@ -630,6 +683,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
     cc[key] = keys[lds_find_rec(i, par)];
     tu[key] = he[k].x;
     tv[key] = he[k].y;
+    if (head) link_slot(key, he[k].x, he[k].y, head, next);
   }
   wave_release_device();
 }
@@ -644,7 +698,8 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_merge(const int64_t *__r
                                                               int tiles, int lo, int hi,
                                                               int group_log, int32_t *cc,
                                                               int32_t *tu, int32_t *tv,
-                                                              const int32_t *counters) {
+                                                              const int32_t *counters,
+                                                              int32_t *head, int32_t *next) {
   __shared__ int s_scan[kTileThreads + 1];
   __shared__ int s_wave[kTileThreads / kWave];
   if (counters[kCntCrossOverflow] == 0) return;   // block-uniform
@@ -668,7 +723,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_merge(const int64_t *__r
       for (int idx = tid; idx < total; idx += kTileThreads) {
         const int k = lds_upper_search(s_scan, kTileThreads, idx);
         const int2 e = cross[region_of[base + k] + (idx - s_scan[k])];
-        if (cross_level(e.x, e.y) == l) hook_edge<true>(e.x, e.y, cc, tu, tv);
+        if (cross_level(e.x, e.y) == l) hook_edge<true>(e.x, e.y, cc, tu, tv, head, next);
       }
       __syncthreads();
     }
@@ -682,7 +737,8 @@ __global__ __launch_bounds__(kBlock) void k_hook_heavy(const OffT *__restrict__ 
                                                        const int32_t *__restrict__ cols,
                                                        int32_t *cc, int32_t *tu, int32_t *tv,
                                                        const int64_t *chunks, int64_t chunk_cap,
-                                                       const int32_t *counters) {
+                                                       const int32_t *counters, int32_t *head,
+                                                       int32_t *next) {
   int64_t nc = counters[kCntChunks];
   if (nc > chunk_cap) nc = chunk_cap;
   for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
@@ -694,7 +750,7 @@ __global__ __launch_bounds__(kBlock) void k_hook_heavy(const OffT *__restrict__ 
     if (e > b + kChunk) e = b + kChunk;
     for (int64_t a = b + threadIdx.x; a < e; a += kBlock) {
       const int32_t dst = cols[a];
-      if (dst < src) hook_edge<true>(src, dst, cc, tu, tv);
+      if (dst < src) hook_edge<true>(src, dst, cc, tu, tv, head, next);
     }
   }
   if (blockIdx.x < nc) wave_release_device();   // only blocks that hooked
@@ -804,29 +860,29 @@ static rst_status launch_cross(rst_ctx *ctx, unsigned tiles, int levels,
   slices = slices < 1 ? 1 : (slices > 64 ? 64 : slices);
   hipLaunchKernelGGL(k_cross_dedupe, dim3(tiles * slices), dim3(kTileThreads), 0, ctx->stream,
                      region_of, cross, tile_cross, (int)slices, f.cc, f.tu, f.tv, f.counters,
-                     kept_list, split);
+                     kept_list, split, f.head, f.next);
   RST_HIP(hipGetLastError());
   const unsigned groups = (tiles + (1u << split) - 1) >> split;
   if (split > 0) {
     hipLaunchKernelGGL(k_cross_lds<true>, dim3(groups), dim3(kTileThreads), 0, ctx->stream,
                        region_of, cross, tile_cross, kept_list, (int)tiles, 0, split, split, f.cc,
-                       f.tu, f.tv, f.counters);
+                       f.tu, f.tv, f.counters, f.head, f.next);
     RST_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_cross_lds<false>, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of,
                      cross, tile_cross, kept_list, (int)tiles, split, levels, levels, f.cc, f.tu,
-                     f.tv, f.counters);
+                     f.tv, f.counters, f.head, f.next);
   RST_HIP(hipGetLastError());
   // global-memory fallback, active only when a merge above raised the flag
   if (split > 0) {
     hipLaunchKernelGGL(k_cross_merge, dim3(groups), dim3(kTileThreads), 0, ctx->stream, region_of,
                        cross, tile_cross, tile_lvl, (int)tiles, 0, split, split, f.cc, f.tu, f.tv,
-                       f.counters);
+                       f.counters, f.head, f.next);
     RST_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_cross_merge, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of, cross,
                      tile_cross, tile_lvl, (int)tiles, split, levels, levels, f.cc, f.tu, f.tv,
-                     f.counters);
+                     f.counters, f.head, f.next);
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_CROSS, 1);
   return RST_OK;
@@ -848,23 +904,27 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 0);
     hipLaunchKernelGGL(k_hook_tile<int32_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
                        off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, region_of,
-                       f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask);
+                       f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask, f.head,
+                       f.next);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));
     hipLaunchKernelGGL(k_hook_heavy<int32_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream, off,
-                       g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters);
+                       g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters, f.head,
+                       f.next);
   } else {
     const int64_t *off = (const int64_t *)g->offsets;
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 0);
     hipLaunchKernelGGL(k_hook_tile<int64_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
                        off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, region_of,
-                       f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask);
+                       f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask, f.head,
+                       f.next);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));
     hipLaunchKernelGGL(k_hook_heavy<int64_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream, off,
-                       g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters);
+                       g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters, f.head,
+                       f.next);
   }
   RST_HIP(hipGetLastError());
   return RST_OK;

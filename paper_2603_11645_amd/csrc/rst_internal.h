@@ -137,6 +137,12 @@ struct ForestBufs {
   int32_t *comp_root;  // [n] designated root of the component labelled v, or -1
   int32_t *counters;   // [16] device counters (see kCnt*)
   const uint8_t *vmask = nullptr;   // [n] nonzero: vertex excluded from hooking (nullable)
+  // Euler arc lists built while hooking (nullable): every recorded edge of
+  // slot x = (a, b) gives arcs 2x = a->b and 2x+1 = b->a, each put in front of
+  // its source's list (head [n], next [2n]); the tile pass builds the lists of
+  // its own edges in LDS, later hooks link with atomic exchanges.
+  int32_t *head = nullptr;
+  int32_t *next = nullptr;
 };
 
 enum {
