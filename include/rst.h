@@ -128,10 +128,15 @@ typedef enum {
                                 * into chunks hooked by many workgroups (32 .. 2^24) */
   RST_OPT_SWEEP_BLOCK = 5,     /* threads per workgroup of the per-vertex and per-slot
                                 * sweeps (64, 128, 256, 512, 1024)                 */
-  RST_OPT_BFS_HEAVY_DEGREE = 6 /* BFS: degree above which a frontier vertex's arcs are
-                                * expanded by many workgroups (32 .. 2^24)          */
+  RST_OPT_BFS_HEAVY_DEGREE = 6, /* BFS: degree above which a frontier vertex's arcs are
+                                 * expanded by many workgroups (32 .. 2^24)         */
+  RST_OPT_GRAPHS = 7           /* 1 (default): rst_spanning_tree by GConn+Euler without
+                                * stats or validation captures its device work as a
+                                * HIP graph on first use and replays it while the
+                                * graph pointers, sizes, root, parent buffer and
+                                * settings stay the same; 0: launch eagerly        */
 } rst_option;
-#define RST_NUM_OPTIONS 7
+#define RST_NUM_OPTIONS 8
 
 /* Create a context on HIP device `device` bound to `hip_stream` (a hipStream_t,
  * NULL = the default stream).  *out receives the context.  Errors: RST_E_INVAL

@@ -39,6 +39,7 @@ OPT_RANK_ELEMS_PER_THREAD = 3
 OPT_HEAVY_DEGREE = 4
 OPT_SWEEP_BLOCK = 5
 OPT_BFS_HEAVY_DEGREE = 6
+OPT_GRAPHS = 7
 
 PATH_CROSS_GLOBAL = 1
 PATH_RANK_GLOBAL = 2

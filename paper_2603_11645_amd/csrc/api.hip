@@ -92,70 +92,96 @@ static inline rst_status mark(rst_ctx *ctx, rst_stats *st, int i) {
 
 static size_t rank_ws_bytes(int64_t A) {
   return ws_bytes(rank_exit_capacity(A), 4) + ws_bytes(rank_exit_capacity(A), 8) +
-         ws_bytes(rank_small_capacity(A), 8) + ws_bytes(rank_tile_count(A), 4) +
-         ws_bytes(rank_tile_count(A) + 1, 8);
+         ws_bytes(rank_tile_count(A), 4) + ws_bytes(rank_tile_count(A) + 1, 8);
 }
 
 static RankBufs take_rank_bufs(rst_ctx *ctx, int64_t A) {
   RankBufs r;
   r.exits = ws_take<int32_t>(ctx, rank_exit_capacity(A));
   r.crank = ws_take<uint64_t>(ctx, rank_exit_capacity(A));
-  r.ctmp = ws_take<uint64_t>(ctx, rank_small_capacity(A));
   r.tile_exits = ws_take<int32_t>(ctx, rank_tile_count(A));
   r.tile_base = ws_take<int64_t>(ctx, rank_tile_count(A) + 1);
   return r;
 }
 
-// GConn + Euler over the whole CSR.  roots: device list (one per component at
-// most).  Writes parent, returns the component count in *components.
-rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
-                           int32_t *parent, rst_stats *st, int64_t *components,
-                           int32_t *counters, int32_t *cc_out, const uint8_t *vmask = nullptr) {
-  const int64_t n = g->n;
-  const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
+// Device buffers of one GConn+Euler run, taken from the workspace in a fixed
+// order (the same pointers for the same graph size and workspace).
+struct GconnWork {
   ForestBufs f;
-  f.counters = counters;
-  f.vmask = vmask;
-  f.cc = cc_out ? cc_out : ws_take<int32_t>(ctx, n);
-  f.tu = ws_take<int32_t>(ctx, n);
-  f.tv = ws_take<int32_t>(ctx, n);
-  f.comp_root = ws_take<int32_t>(ctx, n);
-  int32_t *head = ws_take<int32_t>(ctx, n);
-  int32_t *next = ws_take<int32_t>(ctx, 2 * n);
-  uint64_t *rank = ws_take<uint64_t>(ctx, 2 * n);
-  int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
-  int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
-  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
-  RankBufs rb = take_rank_bufs(ctx, 2 * n);
+  int64_t chunk_cap;
+  int64_t *chunks;
+  int2 *cross;
+  int32_t *tile_cross;
+  uint64_t *rank;
+  int32_t *xid;
+  int32_t *endsucc;
+  RankBufs rb;
+};
 
+static GconnWork take_gconn_work(rst_ctx *ctx, const rst_csr *g, int32_t *counters,
+                                 int32_t *cc_out, const uint8_t *vmask) {
+  const int64_t n = g->n;
+  GconnWork w;
+  w.chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
+  w.f.counters = counters;
+  w.f.vmask = vmask;
+  w.f.cc = cc_out ? cc_out : ws_take<int32_t>(ctx, n);
+  w.f.tu = ws_take<int32_t>(ctx, n);
+  w.f.tv = ws_take<int32_t>(ctx, n);
+  w.f.comp_root = ws_take<int32_t>(ctx, n);
   // the arc lists are built while hooking (tile pass in LDS, later hooks by
   // atomic exchange), so no separate linking pass runs
-  f.head = head;
-  f.next = next;
+  w.f.head = ws_take<int32_t>(ctx, n);
+  w.f.next = ws_take<int32_t>(ctx, 2 * n);
+  w.rank = ws_take<uint64_t>(ctx, 2 * n);
+  w.chunks = ws_take<int64_t>(ctx, w.chunk_cap);
+  w.cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
+  w.tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
+  w.rb = take_rank_bufs(ctx, 2 * n);
+  w.xid = ws_take<int32_t>(ctx, 2 * n);
+  w.endsucc = ws_take<int32_t>(ctx, n);
+  return w;
+}
+
+// All device work of GConn + Euler (no host round trip): hooking, compress,
+// roots, tiled ranking, parents.  roots: device list (one per component at
+// most).
+static rst_status enqueue_gconn(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
+                                int32_t nroots, int32_t *parent, rst_stats *st, GconnWork &w) {
+  const int64_t n = g->n;
   RST_TRY(mark(ctx, st, 0));
-  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
+  RST_TRY(enqueue_hook_csr(ctx, g, w.f, w.chunks, w.chunk_cap, w.cross, w.tile_cross));
   RST_TRY(mark(ctx, st, 1));
-  RST_TRY(enqueue_compress(ctx, n, f.cc, f.comp_root, nullptr));
+  RST_TRY(enqueue_compress(ctx, n, w.f.cc, w.f.comp_root, nullptr));
   RST_TRY(mark(ctx, st, 2));
-  RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, f.cc, f.comp_root, parent, counters));
+  RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, w.f.cc, w.f.comp_root, parent, w.f.counters));
   RST_TRY(mark(ctx, st, 3));
   // the successor pass is fused into the first ranking pass (stage "succ" stays empty)
   RST_TRY(mark(ctx, st, 4));
-  int32_t *xid = ws_take<int32_t>(ctx, 2 * n);
-  SlotArcs arcs{f.tu, f.tv, next, head, f.cc, f.comp_root, n, ws_take<int32_t>(ctx, n)};
-  RST_TRY(enqueue_rank_tiled(ctx, 2 * n, rank, xid, rb, counters, &arcs, false));
+  SlotArcs arcs{w.f.tu, w.f.tv, w.f.next, w.f.head, w.f.cc, w.f.comp_root, n, w.endsucc};
+  RST_TRY(enqueue_rank_tiled(ctx, 2 * n, w.rank, w.xid, w.rb, w.f.counters, &arcs, false));
   RST_TRY(mark(ctx, st, 5));
-  RST_TRY(enqueue_expand_parent(ctx, n, n, f.tu, f.tv, rank, xid, rb.tile_base, rb.crank, f.cc,
-                                f.comp_root, parent, counters));
+  RST_TRY(enqueue_expand_parent(ctx, n, n, w.f.tu, w.f.tv, w.rank, w.xid, w.rb.tile_base,
+                                w.rb.crank, w.f.cc, w.f.comp_root, parent, w.f.counters));
   RST_TRY(mark(ctx, st, 6));
+  return RST_OK;
+}
+
+// Host side after the device work: read the counters (the call's one
+// synchronisation), run the multi-workgroup ranking fallback if it was
+// needed, fill the stats.  *components = components found.
+static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, rst_stats *st,
+                               int64_t *components, GconnWork &w) {
+  const int64_t n = g->n;
+  int32_t *counters = w.f.counters;
   RST_TRY(read_counters(ctx, counters));
   const bool rank_fallback = ctx->host_pinned[kCntRankOverflow] != 0;
   if (rank_fallback) {
     // contracted list too long for the one-block ranking: rank it in
     // multi-block rounds, then the parent rule runs again
-    RST_TRY(rank_overflow_fallback(ctx, rb, counters));
-    RST_TRY(enqueue_expand_parent(ctx, n, n, f.tu, f.tv, rank, xid, rb.tile_base, rb.crank, f.cc,
-                                  f.comp_root, parent, counters));
+    RST_TRY(rank_overflow_fallback(ctx, w.rb, counters));
+    RST_TRY(enqueue_expand_parent(ctx, n, n, w.f.tu, w.f.tv, w.rank, w.xid, w.rb.tile_base,
+                                  w.rb.crank, w.f.cc, w.f.comp_root, parent, counters));
     RST_TRY(mark(ctx, st, 6));
     RST_TRY(read_counters(ctx, counters));
   }
@@ -179,6 +205,85 @@ rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
     st->method_used = RST_GCONN_EULER;
     st->paths = paths;
   }
+  return RST_OK;
+}
+
+// GConn + Euler over the whole CSR, launched eagerly.  Writes parent, returns
+// the component count in *components.
+rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
+                           int32_t *parent, rst_stats *st, int64_t *components,
+                           int32_t *counters, int32_t *cc_out, const uint8_t *vmask = nullptr) {
+  GconnWork w = take_gconn_work(ctx, g, counters, cc_out, vmask);
+  RST_TRY(enqueue_gconn(ctx, g, roots, nroots, parent, st, w));
+  return finish_gconn(ctx, g, parent, st, components, w);
+}
+
+// ---------------------------------------------------------------------------
+// captured HIP graphs of the device work of a call
+// ---------------------------------------------------------------------------
+
+// What a captured graph depends on: every pointer, size and value its kernels
+// were launched with.
+struct GraphKey {
+  const void *offsets, *cols, *parent, *ws_base;
+  int64_t n, nnz, ws_cap;
+  int32_t offset_bytes, root;
+  Options opt;
+  bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
+};
+
+struct GraphCache {
+  GraphKey key;
+  hipGraphExec_t exec = nullptr;
+};
+
+void graph_free(rst_ctx *ctx) {
+  if (ctx->graph) {
+    if (ctx->graph->exec) (void)hipGraphExecDestroy(ctx->graph->exec);
+    delete ctx->graph;
+    ctx->graph = nullptr;
+  }
+  if (ctx->cap_stream) {
+    (void)hipStreamDestroy(ctx->cap_stream);
+    ctx->cap_stream = nullptr;
+  }
+}
+
+// Launch the device work `seq` on the context stream: replay the cached graph
+// if its key matches, else capture `seq` (on a private stream, so that any
+// user stream works) and launch the new graph.  Allocates nothing on the
+// device outside the graph itself.
+template <class Seq>
+static rst_status run_graph(rst_ctx *ctx, const GraphKey &key, Seq seq) {
+  if (ctx->graph && ctx->graph->exec && ctx->graph->key == key) {
+    RST_HIP(hipGraphLaunch(ctx->graph->exec, ctx->stream));
+    return RST_OK;
+  }
+  if (!ctx->graph) ctx->graph = new GraphCache;
+  if (ctx->graph->exec) {
+    RST_HIP(hipGraphExecDestroy(ctx->graph->exec));
+    ctx->graph->exec = nullptr;
+  }
+  if (!ctx->cap_stream) RST_HIP(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  RST_HIP(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipStream_t user = ctx->stream;
+  ctx->stream = ctx->cap_stream;
+  const rst_status s = seq();
+  ctx->stream = user;
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+  if (s != RST_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return s != RST_OK ? s : RST_E_DEVICE;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  RST_HIP(ie);
+  ctx->graph->exec = exec;
+  ctx->graph->key = key;
+  RST_HIP(hipGraphLaunch(exec, ctx->stream));
   return RST_OK;
 }
 
@@ -250,6 +355,7 @@ void rst_destroy(rst_ctx *ctx) {
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   selector_free(ctx);
   tune_free(ctx);
+  graph_free(ctx);
   if (ctx->host_pinned) (void)hipHostFree(ctx->host_pinned);
   delete ctx;
 }
@@ -289,6 +395,9 @@ rst_status rst_set_option(rst_ctx *ctx, rst_option opt, int64_t value) {
       if (value < 32 || value > (1 << 24)) return RST_E_INVAL;
       ctx->opt.bfs_heavy_degree = (int)value;
       return RST_OK;
+    case RST_OPT_GRAPHS:
+      ctx->opt.graphs = value ? 1 : 0;
+      return RST_OK;
   }
   return RST_E_INVAL;
 }
@@ -303,6 +412,7 @@ rst_status rst_get_option(const rst_ctx *ctx, rst_option opt, int64_t *value) {
     case RST_OPT_HEAVY_DEGREE: *value = ctx->opt.heavy_degree; return RST_OK;
     case RST_OPT_SWEEP_BLOCK: *value = ctx->opt.sweep_block; return RST_OK;
     case RST_OPT_BFS_HEAVY_DEGREE: *value = ctx->opt.bfs_heavy_degree; return RST_OK;
+    case RST_OPT_GRAPHS: *value = ctx->opt.graphs; return RST_OK;
   }
   return RST_E_INVAL;
 }
@@ -340,6 +450,27 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
   RST_TRY(ws_reserve(ctx, bytes));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
   int32_t *rootbuf = counters + 32;
+
+  if (method == RST_GCONN_EULER && ctx->opt.graphs && !stats && !ctx->opt.validate) {
+    // the whole device part of the call as one captured graph, replayed while
+    // the graph, buffers and settings stay the same
+    GconnWork w = take_gconn_work(ctx, g, counters, nullptr, nullptr);
+    GraphKey key;
+    std::memset(&key, 0, sizeof key);
+    key.offsets = g->offsets; key.cols = g->cols; key.parent = parent;
+    key.ws_base = ctx->ws.base; key.ws_cap = (int64_t)ctx->ws.cap;
+    key.n = g->n; key.nnz = g->nnz; key.offset_bytes = g->offset_bytes; key.root = root;
+    key.opt = ctx->opt;
+    RST_TRY(run_graph(ctx, key, [&]() -> rst_status {
+      RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+      RST_TRY(enqueue_fill(ctx, rootbuf, 1, root));
+      return enqueue_gconn(ctx, g, rootbuf, 1, parent, nullptr, w);
+    }));
+    int64_t comps = 0;
+    RST_TRY(finish_gconn(ctx, g, parent, nullptr, &comps, w));
+    return comps > 1 ? RST_E_DISCONNECTED : RST_OK;
+  }
+
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(enqueue_fill(ctx, rootbuf, 1, root));
   RST_TRY(run_validation(ctx, g, counters));

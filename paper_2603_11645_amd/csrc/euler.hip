@@ -481,23 +481,19 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
 }
 
 // The contracted list (M = base[tiles] words) ranked by one block: pointer
-// jumping until no word has a successor left, so the round count needs no host
-// round trip.  Up to kSmallLds words live in LDS (16-bit successor, 32-bit
-// hops); up to kSmallGlobal words jump in global memory, double-buffered
-// through tmp (only this block touches them, and each round ends at a block
-// barrier).  Longer lists raise counters[kCntRankOverflow] and change nothing:
-// the consumers then skip their work and the host ranks the list in
-// multi-block rounds.  counters[kCntExits] = M, counters[kCntRankRounds] =
+// jumping in LDS until no word has a successor left, so the round count needs
+// no host round trip.  Longer lists (more than kSmallLds words; one CU would
+// be slower on them than multi-block rounds) raise counters[kCntRankOverflow]
+// and change nothing: the consumers then skip their work and the host ranks
+// the list in multi-block rounds.  counters[kCntExits] = M, counters[kCntRankRounds] =
 // rounds.
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallPer = 19;
 // 19456 words of 8 B (152 KB; the block-wide OR reduction takes a little LDS too)
 constexpr int kSmallLds = kSmallPer * kSmallThreads;
-constexpr int64_t kSmallGlobal = (int64_t)1 << 18;
 
 __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__restrict__ Mp,
-                                                              uint64_t *crank, uint64_t *tmp,
-                                                              int64_t tmp_cap, int32_t *counters) {
+                                                              uint64_t *crank, int32_t *counters) {
   __shared__ uint64_t s_word[kSmallLds];   // (succ, hops) as in crank
   const int tid = threadIdx.x;
   const int64_t M = *Mp;
@@ -544,43 +540,6 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
       const int i = tid + k * kSmallThreads;
       if (i < m) crank[i] = own[k];
     }
-  } else if (M <= kSmallGlobal && M <= tmp_cap) {
-    uint64_t *src = crank, *dst = tmp;
-    bool active = true;
-    while (active) {
-      bool more = false;
-      for (int64_t b = tid; b < M; b += 4 * kSmallThreads) {
-        uint64_t w[4], nb[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t i = b + u * kSmallThreads;
-          w[u] = i < M ? src[i] : pack_rank(-1, 0);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int32_t sc = (int32_t)(uint32_t)w[u];
-          nb[u] = sc >= 0 ? src[sc] : 0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int64_t i = b + u * kSmallThreads;
-          if (i < M) {
-            const int32_t sc = (int32_t)(uint32_t)w[u];
-            if (sc >= 0) {
-              dst[i] = (((w[u] >> 32) + (nb[u] >> 32)) << 32) | (nb[u] & 0xffffffffull);
-              more |= (int32_t)(uint32_t)nb[u] >= 0;
-            } else {
-              dst[i] = w[u];
-            }
-          }
-        }
-      }
-      ++rounds;
-      active = __syncthreads_or(more) && rounds < max_rounds;
-      uint64_t *t = src; src = dst; dst = t;
-    }
-    if (src != crank)
-      for (int64_t i = tid; i < M; i += kSmallThreads) crank[i] = src[i];
   } else {
     if (tid == 0) counters[kCntRankOverflow] = 1;
     return;
@@ -758,9 +717,6 @@ rst_status enqueue_rank_rounds(rst_ctx *ctx, int64_t A, uint64_t *rank, int roun
 
 size_t rank_exit_capacity(int64_t A) { return (size_t)(A + 1); }
 size_t rank_tile_count(int64_t A) { return (size_t)((A + kRankTile - 1) / kRankTile); }
-size_t rank_small_capacity(int64_t A) {
-  return (size_t)((A + 1) < kSmallGlobal ? (A + 1) : kSmallGlobal);
-}
 
 rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *xid,
                               const RankBufs &rb, int32_t *counters, const SlotArcs *from_slots,
@@ -790,8 +746,7 @@ rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *
                      rb.tile_exits, rb.tile_base, rank, xid, rb.crank);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_rank_small, dim3(1), dim3(kSmallThreads), 0, ctx->stream,
-                     rb.tile_base + tiles, rb.crank, rb.ctmp, (int64_t)rank_small_capacity(A),
-                     counters);
+                     rb.tile_base + tiles, rb.crank, counters);
   RST_HIP(hipGetLastError());
   if (expand) RST_TRY(enqueue_rank_expand(ctx, A, rank, xid, rb, counters));
   return RST_OK;

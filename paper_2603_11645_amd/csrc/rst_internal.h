@@ -27,6 +27,7 @@ struct Options {
   int heavy_degree = 1024;       // hooking: arcs of heavier vertices are chunked
   int sweep_block = 256;         // threads per block of the per-vertex/per-slot sweeps
   int bfs_heavy_degree = 1024;   // BFS: frontier vertices above this are split over blocks
+  int graphs = 1;                // capture the device work of a call as a HIP graph and replay it
 };
 
 // Launch sweep kernel template `kern<B>` over `items` threads with the
@@ -50,6 +51,7 @@ struct Options {
 
 struct Selector;
 struct TuneCache;
+struct GraphCache;
 
 // batch.hip
 rst_status enqueue_graph_mask(rst_ctx *ctx, const rst_batch *b, const uint8_t *method,
@@ -82,6 +84,8 @@ struct rst_ctx {
   unsigned kev_mask = 0;            // kernel events recorded during the current call
   rst::Selector *selector = nullptr;
   rst::TuneCache *tune = nullptr;   // autotuned settings by graph class
+  rst::GraphCache *graph = nullptr; // last captured graph of a call's device work
+  hipStream_t cap_stream = nullptr; // private stream the capture runs on
 };
 
 namespace rst {
@@ -207,16 +211,13 @@ struct SlotArcs {
   int32_t *endsucc;   // scratch [n]
 };
 // Scratch of the tiled list ranking of A words: exits int32 [A+1], crank
-// uint64 [A+1], ctmp uint64 [rank_small_capacity(A)], tile_exits int32
-// [tiles], tile_base int64 [tiles+1].
+// uint64 [A+1], tile_exits int32 [tiles], tile_base int64 [tiles+1].
 struct RankBufs {
   int32_t *exits;
   uint64_t *crank;
-  uint64_t *ctmp;
   int32_t *tile_exits;
   int64_t *tile_base;
 };
-size_t rank_small_capacity(int64_t A);
 // Tiled list ranking of A words (succ, hops), with no host round trip: leaves
 // (-1, distance to tail) in every word once the contracted list is ranked.
 // from_slots: NULL -> rank[] already holds (succ, hops) words.  expand: expand
@@ -245,6 +246,8 @@ rst_status enqueue_verify(rst_ctx *ctx, const rst_csr *g, int32_t root, const in
                           const int32_t *parent, int32_t *anc0, int32_t *anc1, int32_t *vc);
 // tune.hip
 void tune_free(rst_ctx *ctx);
+// api.hip
+void graph_free(rst_ctx *ctx);
 
 // bfs.hip
 struct BfsBufs {

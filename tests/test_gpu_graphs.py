@@ -1,0 +1,94 @@
+"""GPU tests of the captured-graph path of rst_spanning_tree (RST_OPT_GRAPHS).
+
+Replays are checked one by one, with the program's own eager work and
+synchronisations between them: every replayed parent array must pass the
+oracle verifier, equal the eager result on trees (where the rooted spanning
+tree is unique), and stay correct when the graph, parent buffer, root or a
+setting changes (which recaptures).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_11645_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rst():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_11645_amd as r
+    return r
+
+
+def upload(g):
+    return (torch.from_numpy(np.ascontiguousarray(g.offsets_typed())).cuda(),
+            torch.from_numpy(np.ascontiguousarray(g.cols)).cuda())
+
+
+def check(g, par, root):
+    code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, par.cpu().numpy(), [root])
+    assert code == 0, (oracle.VERIFY_CODES[code], bad)
+
+
+def test_replays_verified_with_eager_work_between(rst):
+    c = rst.Context(0)
+    assert c.get_option(rst.OPT_GRAPHS) == 1
+    g = I.road_mesh(300, 0.15, 0.001, seed=5)
+    off, cols = upload(g)
+    par = torch.empty(g.n, dtype=torch.int32).cuda()
+    other = I.rmat_lcc(12, 8, seed=6)
+    ooff, ocols = upload(other)
+    for i in range(6):
+        par.fill_(-3)
+        c.spanning_tree(off, cols, 7, "gconn", parent=par)
+        check(g, par, 7)
+        # eager work of the program and of the library between replays
+        x = torch.arange(1000, device="cuda").sum().item()
+        assert x == 499500
+        if i % 2:
+            lab, k = c.components(ooff, ocols)
+            assert k == 1
+        if i == 3:
+            _, st = c.spanning_tree(off, cols, 7, "gconn", stats=True)   # eager, with events
+        torch.cuda.synchronize()
+
+
+def test_replay_equals_eager_on_trees(rst):
+    g = I.random_tree(50000, seed=9)
+    off, cols = upload(g)
+    eager = rst.Context(0)
+    eager.set_option(rst.OPT_GRAPHS, 0)
+    ref = eager.spanning_tree(off, cols, 123, "gconn").cpu().numpy()
+    c = rst.Context(0)
+    par = torch.empty(g.n, dtype=torch.int32).cuda()
+    for _ in range(4):
+        par.fill_(-1)
+        c.spanning_tree(off, cols, 123, "gconn", parent=par)
+        assert np.array_equal(par.cpu().numpy(), ref)
+
+
+def test_recapture_on_changes(rst):
+    c = rst.Context(0)
+    g1 = I.grid(200, 200, 0.2, seed=3)
+    g2 = I.long_chain(30000, 0.01, 64, seed=4, offset_bytes=8)
+    o1, c1 = upload(g1)
+    o2, c2 = upload(g2)
+    p1 = torch.empty(g1.n, dtype=torch.int32).cuda()
+    p2 = torch.empty(g1.n, dtype=torch.int32).cuda()
+    for root in (0, 999):
+        c.spanning_tree(o1, c1, root, "gconn", parent=p1)
+        check(g1, p1, root)
+    c.spanning_tree(o1, c1, 5, "gconn", parent=p2)          # other parent buffer
+    check(g1, p2, 5)
+    c.set_option(rst.OPT_SWEEP_BLOCK, 512)                    # other setting
+    c.spanning_tree(o1, c1, 5, "gconn", parent=p2)
+    check(g1, p2, 5)
+    c.set_option(rst.OPT_SWEEP_BLOCK, 256)
+    par = c.spanning_tree(o2, c2, 11, "gconn")                # other graph (int64 offsets)
+    check(g2, par, 11)
+    c.spanning_tree(o1, c1, 5, "gconn", parent=p1)            # back to the first one
+    check(g1, p1, 5)

@@ -58,9 +58,10 @@ def mesh_plus_hub(seed=13):
 
 # name: (graph builder, rst_stats.paths bits that must be set, bits that must not)
 CASES = {
-    "grid_permuted_256": (lambda: I.grid_permuted(256, seed=1), 0, 3),
-    "grid_1024_del30": (lambda: I.grid(1024, 1024, 0.30, seed=7), 0, 3),
-    "grid_1024_del45": (lambda: I.grid(1024, 1024, 0.45, seed=7), 0, 3),
+    "grid_permuted_256": (lambda: I.grid_permuted(256, seed=1), 2, 1),
+    # thousands of trees: the contracted tour lists may exceed the LDS ranking
+    "grid_1024_del30": (lambda: I.grid(1024, 1024, 0.30, seed=7), 0, 1),
+    "grid_1024_del45": (lambda: I.grid(1024, 1024, 0.45, seed=7), 0, 1),
     "road_512": (lambda: I.road_mesh(512, 0.15, 0.001, seed=2), 0, 3),
     "random_300k": (lambda: I.random_graph(300000, 450000, seed=11, connected=True), 2, 0),
     "mesh_plus_hub": (mesh_plus_hub, 1, 0),
