@@ -158,10 +158,15 @@ __global__ __launch_bounds__(kBlock) void k_rank_round(int64_t A, uint64_t *rank
 // ---------------------------------------------------------------------------
 constexpr int kRankTile = 16384;
 constexpr int kRankThreads = 1024;
-constexpr int kRankPer = kRankTile / kRankThreads;
-constexpr int kRuler = 8;                            // every 8th arc is a ruler
-constexpr int kStrided = kRankTile / kRuler;         // 2048 strided ruler slots
-constexpr int kRulerSlots = 3584;                    // + up to 1536 extra segment heads
+constexpr int kRankPer = kRankTile / kRankThreads;     // 16 arcs (8 twin pairs) per thread
+constexpr int kRankWaves = kRankThreads / 64;
+constexpr int kRuler = 8;                              // every 8th arc starts a ruler
+constexpr int kStrided = kRankTile / kRuler;           // 2048 strided rulers
+constexpr int kPiece = 16;                             // a walk opens a new ruler after 16 arcs
+constexpr int kRulerSlots = 4096;                      // ruler ids fit 12 bits
+constexpr int kMaxRulers = kRulerSlots - 1;            // id 4095 unused: its codes could read as -1
+// static rulers (strided + segment heads) that leave room for every opened one
+constexpr int kMaxStatic = kMaxRulers - kRankTile / kPiece;
 
 __device__ __forceinline__ bool in_tile(int32_t id, int64_t e) {
   return id >= 0 && ((int64_t)id / kRankTile) == (e / kRankTile);
@@ -182,210 +187,223 @@ struct SlotSrc {            // arcs described by the forest slots (fused success
   const int32_t *tu, *tv, *next, *endsucc;
 };
 
-// Within a tile: every segment head and every 8th arc is a ruler.  Each ruler
-// walks its piece of list (to the next ruler or the segment's exit) in LDS;
-// the rulers are then ranked by pointer jumping, and a second walk writes
-// (exit, hops to exit) for every arc.  Total LDS work is two linear passes;
-// each thread walks two rulers at once so their LDS latencies overlap.  A
-// tile with more segment heads than ruler slots (no locality) is ranked by
-// plain pointer jumping in LDS instead.
+// Within a tile: every segment head and every 8th arc starts a ruler.  One
+// walk per ruler follows its piece of list in LDS to the next ruler, to the
+// segment's exit, or for 16 arcs, where it opens a new ruler and goes on; every
+// arc it passes is overwritten with (ruler << 4 | offset), so a single walk
+// gives each arc its place.  Lanes of a wave take the rulers of the wave's
+// share one after another as they become free (a wave costs the sum of its
+// walks over 64 lanes, not 64 times its longest).  The rulers are then ranked
+// by in-place pointer jumping on 32-bit words (last-ruler flag, ruler reached,
+// hops); an arc's word follows from its ruler's: the exit of the last ruler of
+// the chain, and the ruler's hops less the arc's offset.  A tile with more
+// segment heads than static ruler slots (no locality) is ranked by plain
+// pointer jumping over all its arcs in LDS instead.
 template <bool kFromSlots>
 __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t *rank, int32_t *xid,
                                                             int32_t *exits, int32_t *tile_exits,
                                                             SlotSrc src) {
-  __shared__ int16_t ls[kRankTile];                  // local successor, -1 at an exit
-  __shared__ __align__(16) unsigned char region[kRankTile * 2];   // flags+rulers, or hop counts
-  __shared__ int s_extra;
-  __shared__ int s_nexit;
-  uint32_t *haspred = reinterpret_cast<uint32_t *>(region);          // [kRankTile / 32] bits
-  int16_t *r_start = reinterpret_cast<int16_t *>(region + kRankTile / 8);
-  int16_t *r_next = r_start + kRulerSlots;
-  uint16_t *r_len = reinterpret_cast<uint16_t *>(r_next + kRulerSlots);
-  int16_t *r_exit = reinterpret_cast<int16_t *>(r_len + kRulerSlots);
-  uint16_t *dd = reinterpret_cast<uint16_t *>(region);             // fallback: [kRankTile]
+  __shared__ int16_t ls[kRankTile];   // successor in the tile (-1 at an exit), then the arc's code
+  __shared__ __align__(16) unsigned char region[kRankTile * 2];   // rulers, or the fallback's hops
+  __shared__ int s_extra, s_nexit, s_ndyn, s_or[3];
+  uint32_t *haspred = reinterpret_cast<uint32_t *>(region);                 // [kRankTile / 32] bits
+  int16_t *r_start = reinterpret_cast<int16_t *>(region + kRankTile / 8);  // [kMaxStatic + 1]
+  uint32_t *r_word = reinterpret_cast<uint32_t *>(region + kRankTile / 8 + 2 * (kMaxStatic + 1));
+  int16_t *r_exit = reinterpret_cast<int16_t *>(r_word + kRulerSlots);     // [kRulerSlots]
+  static_assert(kRankTile / 8 + 2 * (kMaxStatic + 1) + 6 * kRulerSlots <= kRankTile * 2,
+                "ruler tables fit the region");
+  uint16_t *dd = reinterpret_cast<uint16_t *>(region);                    // fallback: [kRankTile]
 
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * kRankTile;
   const int cnt = (int)((A - e0) < kRankTile ? (A - e0) : kRankTile);
-  if (tid == 0) { s_extra = 0; s_nexit = 0; }
+  if (tid == 0) { s_extra = 0; s_nexit = 0; s_ndyn = 0; s_or[0] = s_or[1] = s_or[2] = 0; }
   for (int q = tid; q < kRankTile / 32; q += kRankThreads) haspred[q] = 0u;
   __syncthreads();
-  // two half-passes of 8 arcs per thread: loads of a half are issued together
+  // Thread t takes the twin pairs p = t + k * kRankThreads (arcs 2p and 2p+1
+  // of the tile), four pairs per half; the loads of a half are issued together.
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    constexpr int H = kRankPer / 2;
-    uint64_t w[H];
+    constexpr int H = kRankPer / 4;
+    uint64_t w[2 * H];
     if (kFromSlots) {
-      // successor: next(rev e), or at the end of dst's list endsucc[dst]
-      int32_t dst[H], sc[H];
+      // successor of a->b: next(b->a), or at the end of b's list endsucc[b]
+      int32_t dst[2 * H], sc[2 * H];
 #pragma unroll
-      for (int j = 0; j < H; ++j) {
-        const int64_t e = e0 + tid + (h * H + j) * kRankThreads;
-        dst[j] = -1; sc[j] = -1;
-        if (e < A) {
-          const int32_t a = src.tu[e >> 1];
-          dst[j] = a < 0 ? -1 : ((e & 1) ? a : src.tv[e >> 1]);   // 2x = a->b, 2x+1 = b->a
-          sc[j] = src.next[e ^ 1];
+      for (int k = 0; k < H; ++k) {
+        const int i0 = 2 * (tid + (h * H + k) * kRankThreads);
+        dst[2 * k] = dst[2 * k + 1] = -1;
+        sc[2 * k] = sc[2 * k + 1] = -1;
+        if (i0 < cnt) {   // cnt is even here: a slot's two arcs share a tile
+          const int64_t x = (e0 + i0) >> 1;
+          const int32_t a = src.tu[x];
+          const int32_t b = src.tv[x];
+          const int2 nx = reinterpret_cast<const int2 *>(src.next)[x];
+          if (a >= 0) {
+            dst[2 * k] = b;     sc[2 * k] = nx.y;       // 2x = a->b, rev = 2x+1
+            dst[2 * k + 1] = a; sc[2 * k + 1] = nx.x;   // 2x+1 = b->a, rev = 2x
+          }
         }
       }
 #pragma unroll
-      for (int j = 0; j < H; ++j)
+      for (int j = 0; j < 2 * H; ++j)
         if (dst[j] >= 0 && sc[j] == -1) sc[j] = src.endsucc[dst[j]];
 #pragma unroll
-      for (int j = 0; j < H; ++j) {
+      for (int j = 0; j < 2 * H; ++j) {
         const int32_t t = dst[j] < 0 ? -1 : sc[j];
         w[j] = pack_rank(t, t >= 0 ? 1u : 0u);
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < H; ++j) {
-        const int i = tid + (h * H + j) * kRankThreads;
-        w[j] = i < cnt ? rank[e0 + i] : 0ull;
+      for (int k = 0; k < H; ++k) {
+        const int i0 = 2 * (tid + (h * H + k) * kRankThreads);
+        w[2 * k] = w[2 * k + 1] = 0ull;
+        if (i0 + 1 < cnt) {
+          const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(rank + e0)[i0 >> 1];
+          w[2 * k] = v.x; w[2 * k + 1] = v.y;
+        } else if (i0 < cnt) {
+          w[2 * k] = rank[e0 + i0];
+        }
       }
     }
 #pragma unroll
-    for (int j = 0; j < H; ++j) {
-      const int i = tid + (h * H + j) * kRankThreads;
-      bool is_exit = false;
-      if (i < cnt) {
-        const int32_t sc = (int32_t)(uint32_t)w[j];
-        const int64_t sl = (int64_t)sc - e0;
-        if (sc >= 0 && sl >= 0 && sl < cnt) {
-          ls[i] = (int16_t)sl;
-          atomicOr(&haspred[sl >> 5], 1u << (sl & 31));
-        } else {
-          ls[i] = -1;
-          is_exit = true;
+    for (int k = 0; k < H; ++k) {
+      const int i0 = 2 * (tid + (h * H + k) * kRankThreads);
+      uint32_t lv[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int i = i0 + s;
+        bool is_exit = false;
+        lv[s] = 0xffffu;
+        if (i < cnt) {
+          const int32_t sc = (int32_t)(uint32_t)w[2 * k + s];
+          const int64_t sl = (int64_t)sc - e0;
+          if (sc >= 0 && sl >= 0 && sl < cnt) {
+            lv[s] = (uint32_t)sl;
+            atomicOr(&haspred[sl >> 5], 1u << (sl & 31));
+          } else {
+            is_exit = true;
+          }
+        }
+        // exits of tile b go to exits[b*kRankTile + k], k from an LDS counter;
+        // only exits are ever looked up in xid
+        const int slot = wave_append(is_exit, &s_nexit);
+        if (is_exit) {
+          exits[e0 + slot] = (int32_t)(e0 + i);
+          xid[e0 + i] = slot;
+          if (kFromSlots) rank[e0 + i] = w[2 * k + s];
         }
       }
-      // exits of tile b go to exits[b*kRankTile + k], k from an LDS counter
-      const int slot = wave_append(is_exit, &s_nexit);
-      if (is_exit) {
-        exits[e0 + slot] = (int32_t)(e0 + i);
-        if (kFromSlots) rank[e0 + i] = w[j];
-      }
-      if (i < cnt) xid[e0 + i] = is_exit ? slot : 0;
+      if (i0 < cnt) *reinterpret_cast<uint32_t *>(&ls[i0]) = lv[0] | (lv[1] << 16);
     }
   }
   __syncthreads();
-  // strided rulers own slots 0..kStrided-1; heads off the stride get extra slots
+  // strided rulers own slots 0..kStrided-1; heads off the stride get the next ones
   for (int q = tid; q < kStrided; q += kRankThreads) r_start[q] = (int16_t)(q * kRuler);
 #pragma unroll
   for (int j = 0; j < kRankPer; ++j) {
     const int i = tid + j * kRankThreads;
-    if (i < cnt && (i % kRuler) != 0 && !((haspred[i >> 5] >> (i & 31)) & 1u)) {
-      const int x = atomicAdd(&s_extra, 1);
-      if (kStrided + x < kRulerSlots) r_start[kStrided + x] = (int16_t)i;
-    }
+    const bool head = i < cnt && (i % kRuler) != 0 && !((haspred[i >> 5] >> (i & 31)) & 1u);
+    const int x = wave_append(head, &s_extra);
+    if (head && kStrided + x < kMaxStatic) r_start[kStrided + x] = (int16_t)i;
   }
   __syncthreads();
   if (tid == 0) tile_exits[blockIdx.x] = s_nexit;
-  const int extra = s_extra;
-  if (kStrided + extra <= kRulerSlots) {
-    const int nslots = kStrided + extra;
-    // walk 1, two rulers per thread in lock step: hops to the next ruler or exit
-    for (int qb = tid; qb < nslots; qb += 2 * kRankThreads) {
-      int q[2] = {qb, qb + kRankThreads};
-      int jj[2], len[2] = {0, 0}, nx[2] = {-1, -1}, ex[2] = {0, 0};
-      bool act[2];
-#pragma unroll
-      for (int w = 0; w < 2; ++w) {
-        jj[w] = q[w] < nslots ? r_start[q[w]] : cnt;
-        act[w] = jj[w] < cnt;
+  const int nstatic = kStrided + s_extra;
+  if (nstatic <= kMaxStatic) {
+    // the walk: lanes take the wave's share of static rulers as they free up
+    const int wid = tid >> 6;
+    const int per = (nstatic + kRankWaves - 1) / kRankWaves;
+    int qn = wid * per;
+    const int qe = min(nstatic, qn + per);
+    int q = -1, j = 0, len = 0;
+    while (true) {
+      const uint64_t idle = __ballot(q < 0);
+      if (qn < qe && idle != 0ull) {
+        const int r = qn + lanes_below(idle);
+        if (q < 0 && r < qe) { q = r; j = r_start[r]; len = 0; }
+        qn += (int)__popcll(idle);
       }
-      while (act[0] || act[1]) {
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-          if (!act[w]) continue;
-          const int sj = ls[jj[w]];
-          if (sj < 0) { ex[w] = jj[w]; act[w] = false; continue; }
-          jj[w] = sj;
-          ++len[w];
-          if ((sj % kRuler) == 0) { nx[w] = sj / kRuler; act[w] = false; continue; }
-          if (len[w] > cnt) { ex[w] = sj; act[w] = false; }   // only on a cycle
+      if (__ballot(q >= 0) == 0ull) break;
+      bool open = false;   // the piece reached kPiece arcs: continue as a new ruler
+      if (q >= 0) {
+        int fin = -2, ex = 0;   // -2 walking on, -1 ended at an exit, else the next ruler
+        if (j >= cnt) {
+          fin = -1;             // strided ruler past the end of a short tile
+        } else {
+          const int sj = ls[j];
+          if (sj < 0) {
+            fin = -1;
+            ex = j;
+          } else {
+            ls[j] = (int16_t)((q << 4) | len);
+            j = sj & (kRankTile - 1);
+            ++len;
+            if ((j & (kRuler - 1)) == 0) fin = j / kRuler;
+            else if (len == kPiece) open = true;
+          }
+        }
+        if (fin != -2) {
+          r_word[q] = fin < 0 ? (0x80000000u | ((uint32_t)q << 16) | (uint32_t)len)
+                              : (((uint32_t)fin << 16) | (uint32_t)len);
+          r_exit[q] = (int16_t)ex;
+          q = -1;
         }
       }
-#pragma unroll
-      for (int w = 0; w < 2; ++w)
-        if (q[w] < nslots) {
-          r_next[q[w]] = (int16_t)nx[w];
-          r_len[q[w]] = (uint16_t)len[w];
-          r_exit[q[w]] = (int16_t)ex[w];
+      const int d = wave_append(open, &s_ndyn);
+      if (open) {
+        const int x = nstatic + d;
+        if (x < kMaxRulers) {
+          r_word[q] = ((uint32_t)x << 16) | (uint32_t)len;
+          r_exit[q] = 0;
+          q = x;
+          len = 0;
+        } else {   // not reached on simple lists (at most kRankTile / kPiece are opened)
+          r_word[q] = 0x80000000u | ((uint32_t)q << 16) | (uint32_t)len;
+          r_exit[q] = (int16_t)j;
+          q = -1;
         }
+      }
     }
     __syncthreads();
-    // pointer jumping over the rulers
-    constexpr int QP = (kRulerSlots + kRankThreads - 1) / kRankThreads;
+    const int nrul = min(nstatic + s_ndyn, kMaxRulers);
+    // pointer jumping over the rulers, in place: a word read while its owner
+    // rewrites it is either version, and both are consistent (ruler, hops)
+    // pairs.  Round flags rotate over three words so that one barrier a round
+    // suffices: the flag cleared in a round was last read two rounds earlier.
+    constexpr int QP = kRulerSlots / kRankThreads;
     for (int round = 0; round < 13; ++round) {
-      int16_t nn[QP], ne[QP];
-      uint16_t nl[QP];
-      bool changed = false;
+      bool pending = false;
 #pragma unroll
       for (int k = 0; k < QP; ++k) {
-        const int q = tid + k * kRankThreads;
-        if (q < nslots) {
-          const int x = r_next[q];
-          nn[k] = (int16_t)x; nl[k] = r_len[q]; ne[k] = r_exit[q];
-          if (x >= 0) {
-            nn[k] = r_next[x];
-            nl[k] = (uint16_t)(r_len[q] + r_len[x]);
-            ne[k] = r_exit[x];
-            changed = true;
+        const int r = tid + k * kRankThreads;
+        if (r < nrul) {
+          const uint32_t w = r_word[r];
+          if (!(w >> 31)) {
+            const uint32_t w2 = r_word[(w >> 16) & 0xfffu];
+            const uint32_t nw = (w2 & 0xffff0000u) | ((w + w2) & 0xffffu);
+            r_word[r] = nw;
+            pending |= !(nw >> 31);
           }
         }
       }
+      if (pending) s_or[round % 3] = 1;
+      if (tid == 0) s_or[(round + 1) % 3] = 0;
       __syncthreads();
-#pragma unroll
-      for (int k = 0; k < QP; ++k) {
-        const int q = tid + k * kRankThreads;
-        if (q < nslots) { r_next[q] = nn[k]; r_len[q] = nl[k]; r_exit[q] = ne[k]; }
-      }
-      if (!__syncthreads_or(changed)) break;
+      if (!s_or[round % 3]) break;
     }
-    // walk 2: every non-exit arc gets (exit, hops to exit).  The rulers' data
-    // go to registers first; then the region holds per-arc hop counts and ls
-    // the local exit of each arc it is done with, so that the rank words are
-    // written once, coalesced, at the end (written along the list they
-    // landed in partial lines).
-    int w_st[QP], w_tot[QP], w_ex[QP];
+    // every arc but the exits: (exit of its chain, ruler hops - offset), coalesced
 #pragma unroll
-    for (int k = 0; k < QP; ++k) {
-      const int q = tid + k * kRankThreads;
-      w_st[k] = q < nslots ? r_start[q] : cnt;
-      w_tot[k] = q < nslots ? r_len[q] : 0;
-      w_ex[k] = q < nslots ? r_exit[q] : 0;
-    }
-    __syncthreads();
-    uint16_t *hp = reinterpret_cast<uint16_t *>(region);     // [kRankTile] hops to exit
-#pragma unroll
-    for (int k = 0; k < QP; k += 2) {
-      int jj[2], k2[2] = {0, 0};
-      bool act[2];
-#pragma unroll
-      for (int w = 0; w < 2; ++w) {
-        jj[w] = (k + w < QP) ? w_st[k + w] : cnt;
-        act[w] = jj[w] < cnt;
-      }
-      while (act[0] || act[1]) {
-#pragma unroll
-        for (int w = 0; w < 2; ++w) {
-          if (!act[w]) continue;
-          const int sj = ls[jj[w]];
-          if (sj < 0 || k2[w] > cnt) { act[w] = false; continue; }
-          hp[jj[w]] = (uint16_t)(w_tot[k + w] - k2[w]);
-          ls[jj[w]] = (int16_t)w_ex[k + w];
-          jj[w] = sj;
-          ++k2[w];
-          if ((sj % kRuler) == 0) act[w] = false;
+    for (int k = 0; k < kRankPer; ++k) {
+      const int i = tid + k * kRankThreads;
+      if (i < cnt) {
+        const uint32_t c = (uint16_t)ls[i];
+        if (c != 0xffffu) {
+          const uint32_t w = r_word[c >> 4];
+          const int f = (int)((w >> 16) & 0xfffu);
+          rank[e0 + i] = pack_rank((int32_t)(e0 + r_exit[f]), (w & 0xffffu) - (c & 15u));
         }
       }
-    }
-    __syncthreads();
-    // exits keep the word of the first pass; every other arc now has its exit
-#pragma unroll
-    for (int j = 0; j < kRankPer; ++j) {
-      const int i = tid + j * kRankThreads;
-      if (i < cnt && ls[i] >= 0) rank[e0 + i] = pack_rank((int32_t)(e0 + ls[i]), hp[i]);
     }
     return;
   }
@@ -403,7 +421,6 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
   for (int round = 0; round < 15; ++round) {
     int16_t np[kRankPer];
     uint16_t nd[kRankPer];
-    bool changed = false;
 #pragma unroll
     for (int j = 0; j < kRankPer; ++j) {
       const int i = tid + j * kRankThreads;
@@ -411,7 +428,6 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
         const int q = ls[i];
         np[j] = ls[q];
         nd[j] = (uint16_t)(dd[i] + dd[q]);
-        changed |= (np[j] != q);
       }
     }
     __syncthreads();
@@ -420,7 +436,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
       const int i = tid + j * kRankThreads;
       if (i < cnt) { ls[i] = np[j]; dd[i] = nd[j]; }
     }
-    if (!__syncthreads_or(changed)) break;
+    __syncthreads();   // fixed 15 rounds: enough for the 16384 arcs of a tile
   }
 #pragma unroll
   for (int j = 0; j < kRankPer; ++j) {

@@ -196,6 +196,50 @@ def test_list_rank_tiled_locality(ctx):
         assert np.array_equal(got, exp)
 
 
+def _lists_with_heads(A, heads, rs):
+    """Lists over 0..A-1 whose first elements are exactly `heads` (the other
+    ids follow in random order, split among the lists)."""
+    rest = rs.permutation(np.setdiff1d(np.arange(A), heads))
+    cuts = np.sort(rs.choice(np.arange(1, len(rest)), size=len(heads) - 1, replace=False))
+    succ = np.full(A, -1, np.int32)
+    for h, piece in zip(heads, np.split(rest, cuts)):
+        chain = np.concatenate([[h], piece])
+        succ[chain[:-1]] = chain[1:]
+    return succ
+
+
+def test_list_rank_tile_rulers(ctx):
+    """In-tile ranking at its limits: a list that runs through 14336 arcs off
+    the 8-stride before reaching a strided one (hundreds of capped pieces), and
+    tiles with 1023 and 1024 segment heads off the stride (the last count that
+    the ruler walk takes and the first that goes to all-arc jumping), also in a
+    ragged multi-tile input."""
+    rs = np.random.RandomState(5)
+    T = 16384
+    ids = np.arange(T)
+    order = np.concatenate([ids[ids % 8 != 0], ids[ids % 8 == 0]])
+    succ = np.full(T, -1, np.int32)
+    succ[order[:-1]] = order[1:]
+    cases = [succ]
+    off_stride = ids[ids % 8 != 0]
+    for nh in (1023, 1024):
+        heads = np.sort(rs.choice(off_stride, size=nh, replace=False))
+        cases.append(_lists_with_heads(T, heads, rs))
+    # three tiles and a ragged tail, each tile's lists kept inside it
+    parts, base = [], 0
+    for size, nh in ((T, 1023), (T, 1), (T, 1024), (4101, 9)):
+        loc = np.arange(size)
+        heads = np.sort(rs.choice(loc[loc % 8 != 0], size=nh, replace=False))
+        sub = _lists_with_heads(size, heads, rs)
+        parts.append(np.where(sub >= 0, sub + base, -1).astype(np.int32))
+        base += size
+    cases.append(np.concatenate(parts))
+    for succ in cases:
+        exp, _ = oracle.list_rank(succ)
+        got = ctx.list_rank(dev(succ)).cpu().numpy()
+        assert np.array_equal(got, exp)
+
+
 def test_heavy_hub_paths(ctx):
     """A star whose centre exceeds the heavy-degree threshold many times over."""
     g = I.star(200001, 7)
