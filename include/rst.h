@@ -105,8 +105,12 @@ typedef struct {
 enum {
   RST_PATH_CROSS_GLOBAL = 1,  /* cross-tile merge ran in global memory (the     *
                                * kept cross edges did not fit one workgroup)    */
-  RST_PATH_RANK_GLOBAL = 2    /* contracted list ranked by multi-workgroup      *
+  RST_PATH_RANK_GLOBAL = 2,   /* contracted list ranked by multi-workgroup      *
                                * rounds (too long for one workgroup)            */
+  RST_PATH_CROSS_GROUPS = 4   /* kept cross edges too many for the one-workgroup *
+                               * merge of all levels: merged per group of tiles *
+                               * and then the top levels (graphs of more than   *
+                               * 8 tiles of 8192 vertices only)                 */
 };
 
 /* Indices of rst_stats.ms_kernel (HIP-event time of one launch each). */

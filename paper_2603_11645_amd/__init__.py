@@ -43,6 +43,7 @@ OPT_GRAPHS = 7
 
 PATH_CROSS_GLOBAL = 1
 PATH_RANK_GLOBAL = 2
+PATH_CROSS_GROUPS = 4
 
 STAGES = ["hook", "compress", "arcs", "succ", "rank", "parent", "bfs", "select"]
 

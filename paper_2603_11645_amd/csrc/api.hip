@@ -187,8 +187,11 @@ static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, 
   }
   const int rounds = ctx->host_pinned[kCntRankRounds];
   const int64_t exits_n = ctx->host_pinned[kCntExits];
+  // the one-block merge of all levels is tried when there are more than 3 levels
+  const bool groups = hook_level_count(n) > 3 && !ctx->host_pinned[kCntCrossDone];
   const int32_t paths = (ctx->host_pinned[kCntCrossOverflow] ? RST_PATH_CROSS_GLOBAL : 0) |
-                        (rank_fallback ? RST_PATH_RANK_GLOBAL : 0);
+                        (rank_fallback ? RST_PATH_RANK_GLOBAL : 0) |
+                        (groups ? RST_PATH_CROSS_GROUPS : 0);
   if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
   if (ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
   *components = ctx->host_pinned[kCntComponents];

@@ -294,6 +294,8 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
   if (tid == 0) {
     if (blockIdx.x == 0) {   // read by the cross phase after this kernel
       counters[kCntKept] = 0;
+      counters[kCntKeptTop] = 0;
+      counters[kCntCrossDone] = 0;
       counters[kCntCrossOverflow] = 0;
     }
     region_of[blockIdx.x] = region;
@@ -397,8 +399,11 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
 //     original value, which marks the tile as done for the later steps.
 //  2. k_cross_lds: one block takes all kept edges, maps the roots they join
 //     into LDS and runs the union-find there, level by level over the binary
-//     tree of tiles (cross_level), then writes the links back.  If the kept
-//     edges or their roots do not fit, it changes nothing and raises a flag.
+//     tree of tiles (cross_level), then writes the links back.  If there are
+//     too many kept edges or roots for one block, it changes nothing, and the
+//     levels below `split` are merged the same way by one block per group of
+//     2^split tiles, the rest by one block from a list of their edges; if
+//     those do not fit either, they raise a flag.
 //  3. Only when flagged, k_cross_merge does the same in global memory: the
 //     levels below `split` join tiles of one group of 2^split tiles and run in
 //     one launch with a block per group; the remaining levels run in one block.
@@ -413,17 +418,21 @@ constexpr int kDedupPer = kFlatCross / kTileThreads;
 constexpr int kLdsSlots = 16384;        // root slots of k_cross_lds (key + parent: 128 KB)
 constexpr int kLdsPer = 16;             // kept edges per thread in k_cross_lds
 constexpr int kLdsEdges = kLdsPer * kTileThreads;
+// The one-block merge of all levels takes at most this many kept edges: one
+// CU gathers about a cache line per clock, so longer lists go faster through
+// the group merges spread over many CUs.
+constexpr int kAllEdges = 2048;
 
 __device__ __forceinline__ int kept_count(int c) { return c > kFlatCross ? 0 : c; }
 
-__global__ __launch_bounds__(kTileThreads) void k_cross_dedupe(const int64_t *__restrict__ region_of,
+__global__ __launch_bounds__(kTileThreads, 8) void k_cross_dedupe(const int64_t *__restrict__ region_of,
                                                                int2 *cross, int32_t *tile_cross,
                                                                int slices, int32_t *cc, int32_t *tu,
                                                                int32_t *tv, int32_t *counters,
                                                                int2 *kept_list, int split,
                                                                int32_t *head, int32_t *next) {
   __shared__ unsigned long long tab[kDedupSlots];
-  __shared__ int s_kept, s_top, s_base;
+  __shared__ int s_kept, s_top, s_base, s_base_all;
   const int b = blockIdx.x / slices;
   const int part = blockIdx.x % slices;
   const int tid = threadIdx.x;
@@ -475,29 +484,38 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_dedupe(const int64_t *__
     }
   }
   __syncthreads();
-  int slot[kDedupPer];
+  int slot[kDedupPer], slot_all[kDedupPer];
 #pragma unroll
   for (int j = 0; j < kDedupPer; ++j) {
     const int k = wave_append(keep[j], &s_kept);
     if (keep[j]) cross[region + k] = e[j];
+    slot_all[j] = keep[j] ? k : -1;
     const bool top = keep[j] && cross_level(e[j].x, e[j].y) >= split;
     slot[j] = wave_append(top, &s_top);
     if (!top) slot[j] = -1;
   }
   __syncthreads();
-  // kept edges of the levels >= split also go to one compact list (tiles in
-  // any order) for the final one-workgroup merge; past kLdsEdges that merge is
-  // not used, nor the list
+  // Every kept edge also goes to one compact list (tiles in any order) for the
+  // one-workgroup merge of all levels, and those of the levels >= split to a
+  // second one for the top-level merge; a list past kLdsEdges is not used.
   if (tid == 0) {
     tile_cross[b] = s_kept;
-    s_base = s_top ? atomicAdd(&counters[kCntKept], s_top) : 0;
+    s_base_all = s_kept ? atomicAdd(&counters[kCntKept], s_kept) : 0;
+    s_base = s_top ? atomicAdd(&counters[kCntKeptTop], s_top) : 0;
   }
   __syncthreads();
+  const int kba = s_base_all;
+  if (kba + s_kept <= kLdsEdges) {
+#pragma unroll
+    for (int j = 0; j < kDedupPer; ++j)
+      if (slot_all[j] >= 0) kept_list[kba + slot_all[j]] = e[j];
+  }
   const int kb0 = s_base;
+  int2 *kept_top = kept_list + kLdsEdges;
   if (kb0 + s_top <= kLdsEdges) {
 #pragma unroll
     for (int j = 0; j < kDedupPer; ++j)
-      if (slot[j] >= 0) kept_list[kb0 + slot[j]] = e[j];
+      if (slot[j] >= 0) kept_top[kb0 + slot[j]] = e[j];
   }
 }
 
@@ -557,47 +575,54 @@ __device__ __forceinline__ uint32_t pack_sab(int sa, int sb, int level) {
 // One-workgroup LDS merge of the kept cross edges of levels [lo, hi).
 // kGroup: block g takes the tiles [g << group_log, (g + 1) << group_log) and
 // their kept edges below hi (their roots must lie in the group's vertex range,
-// else the block raises the flag and changes nothing); otherwise the single
-// block takes the compact list of the edges of the top levels.
+// else the block raises the flag and changes nothing).  Otherwise one block
+// takes a compact list: with `all`, the list of every kept edge (levels
+// [0, hi)) if it holds at most kAllEdges; when that succeeds it sets
+// counters[kCntCrossDone] and the group and top-level merges return at once,
+// otherwise it changes nothing and leaves them to run.  Without `all`, the
+// list of the edges of the top levels.
 template <bool kGroup>
 __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__restrict__ region_of,
                                                             const int2 *__restrict__ cross,
                                                             const int32_t *__restrict__ tile_cross,
                                                             const int2 *__restrict__ kept_list,
                                                             int tiles, int lo, int hi,
-                                                            int group_log, int32_t *cc, int32_t *tu,
-                                                            int32_t *tv, int32_t *counters,
-                                                            int32_t *head, int32_t *next) {
+                                                            int group_log, int all, int32_t *cc,
+                                                            int32_t *tu, int32_t *tv,
+                                                            int32_t *counters, int32_t *head,
+                                                            int32_t *next) {
   __shared__ int32_t keys[kLdsSlots];   // global root held by a slot, -1: empty
   __shared__ int par[kLdsSlots];        // union-find entries (see kParMask)
   __shared__ int s_pref[kGroup ? kTileThreads + 1 : 1];   // kept counts of the group's tiles
   __shared__ int s_wave[kTileThreads / kWave];
-  __shared__ int s_fail;
+  __shared__ int s_fail, s_nrec;
   const int tid = threadIdx.x;
   const int64_t t0 = kGroup ? ((int64_t)blockIdx.x << group_log) : 0;
   const int64_t t1 = kGroup ? ((t0 + ((int64_t)1 << group_log)) < tiles
                                    ? t0 + ((int64_t)1 << group_log) : (int64_t)tiles) : 0;
   int total;
+  if (!all && counters[kCntCrossDone]) return;   // block-uniform
+  const int2 *list = kept_list + (all ? 0 : kLdsEdges);
   if (kGroup) {
     const int64_t tb = t0 + tid;
     const int c = tb < t1 ? kept_count(tile_cross[tb]) : 0;
     const int ex = block_excl_scan<kTileThreads>(c, s_wave, &total);
     s_pref[tid] = ex;
   } else {
-    total = counters[kCntKept];
+    total = counters[all ? kCntKept : kCntKeptTop];
   }
-  if (total > kLdsEdges || hi >= 15) {
-    if (tid == 0) counters[kCntCrossOverflow] = 1;
+  if (total > (all ? kAllEdges : kLdsEdges) || hi >= 15) {
+    if (tid == 0 && !all) counters[kCntCrossOverflow] = 1;
     return;
   }
   if (total == 0) return;
   for (int i = tid; i < kLdsSlots; i += kTileThreads) { keys[i] = -1; par[i] = i; }
-  if (tid == 0) s_fail = 0;
+  if (tid == 0) { s_fail = 0; s_nrec = 0; }
   __syncthreads();
   const int32_t own_lo = kGroup ? (int32_t)(t0 << kTileShift) : 0;
   const int32_t own_hi = kGroup ? (int32_t)((t1 << kTileShift) - 1) : 0x7fffffff;
   auto edge_at = [&](int g) -> int2 {
-    if (!kGroup) return kept_list[g];
+    if (!kGroup) return list[g];
     const int k = lds_upper_search(s_pref, kTileThreads, g);
     return cross[region_of[t0 + k] + (g - s_pref[k])];
   };
@@ -650,7 +675,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
   }
   __syncthreads();
   if (s_fail) {
-    if (tid == 0) counters[kCntCrossOverflow] = 1;
+    if (tid == 0 && !all) counters[kCntCrossOverflow] = 1;
     return;
   }
   for (int l = lo; l < hi; ++l) {
@@ -662,29 +687,51 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
     }
     __syncthreads();
   }
-  // every hooked root points straight at its final root and records the
-  // kept edge that hooked it (all edge lookups issued together)
+  // Every hooked root points straight at its final root and records the kept
+  // edge that hooked it.  The hooked slots are few and scattered over the
+  // table: they are gathered into a compact list first (in the par region,
+  // free once every find is done), so that each is finished by its own thread
+  // and their edge lookups and global writes all proceed in parallel.
   constexpr int kSlotsPer = kLdsSlots / kTileThreads;
-  int hooked[kSlotsPer];
+  constexpr int kRecMax = kLdsSlots / 3;
+  int32_t hk_g[kSlotsPer], hk_key[kSlotsPer], hk_root[kSlotsPer];
 #pragma unroll
   for (int k = 0; k < kSlotsPer; ++k) {
     const int i = tid + k * kTileThreads;
     const int w = par[i];
-    hooked[k] = (keys[i] >= 0 && (w & kParMask) != i) ? (w >> 14) - 1 : -1;
+    const bool hooked = keys[i] >= 0 && (w & kParMask) != i;
+    hk_g[k] = hooked ? (w >> 14) - 1 : -1;
+    hk_key[k] = hooked ? keys[i] : 0;
+    hk_root[k] = hooked ? keys[lds_find_rec(i, par)] : 0;
   }
-  int2 he[kSlotsPer];
-#pragma unroll
-  for (int k = 0; k < kSlotsPer; ++k) he[k] = hooked[k] >= 0 ? edge_at(hooked[k]) : make_int2(0, 0);
+  __syncthreads();
+  int *rec = par;   // [3 * kRecMax]: key, final root, kept edge number
 #pragma unroll
   for (int k = 0; k < kSlotsPer; ++k) {
-    if (hooked[k] < 0) continue;
-    const int i = tid + k * kTileThreads;
-    const int32_t key = keys[i];
-    cc[key] = keys[lds_find_rec(i, par)];
-    tu[key] = he[k].x;
-    tv[key] = he[k].y;
-    if (head) link_slot(key, he[k].x, he[k].y, head, next);
+    const int r = wave_append(hk_g[k] >= 0, &s_nrec);
+    if (hk_g[k] >= 0 && r < kRecMax) {
+      rec[3 * r] = hk_key[k];
+      rec[3 * r + 1] = hk_root[k];
+      rec[3 * r + 2] = hk_g[k];
+    }
   }
+  __syncthreads();
+  const int nrec = s_nrec;
+  auto finish = [&](int32_t key, int32_t root, int g) {
+    const int2 e = edge_at(g);
+    cc[key] = root;
+    tu[key] = e.x;
+    tv[key] = e.y;
+    if (head) link_slot(key, e.x, e.y, head, next);
+  };
+  if (nrec <= kRecMax) {
+    for (int r = tid; r < nrec; r += kTileThreads) finish(rec[3 * r], rec[3 * r + 1], rec[3 * r + 2]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kSlotsPer; ++k)
+      if (hk_g[k] >= 0) finish(hk_key[k], hk_root[k], hk_g[k]);
+  }
+  if (all && tid == 0) counters[kCntCrossDone] = 1;
   wave_release_device();
 }
 
@@ -840,10 +887,11 @@ int hook_level_count(int64_t n) {
   return l;
 }
 // tile_cross buffer: int32 counts, int64 region starts, int32 level ranges,
-// then the compact list of kept cross edges (int2 [kLdsEdges])
+// then the compact lists of kept cross edges, all levels and the top levels
+// (int2 [kLdsEdges] each)
 size_t hook_tile_words(int64_t n) {
   const size_t tc = hook_tile_count(n), even = (tc + 1) & ~size_t(1);
-  return even + 2 * tc + even + 2 * (size_t)kLdsEdges;
+  return even + 2 * tc + even + 4 * (size_t)kLdsEdges;
 }
 
 static rst_status launch_cross(rst_ctx *ctx, unsigned tiles, int levels,
@@ -864,13 +912,19 @@ static rst_status launch_cross(rst_ctx *ctx, unsigned tiles, int levels,
   RST_HIP(hipGetLastError());
   const unsigned groups = (tiles + (1u << split) - 1) >> split;
   if (split > 0) {
+    // all levels at once when every kept edge fits one workgroup; else (it
+    // changes nothing then) per group below `split` and one block above
+    hipLaunchKernelGGL(k_cross_lds<false>, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of,
+                       cross, tile_cross, kept_list, (int)tiles, 0, levels, levels, 1, f.cc, f.tu,
+                       f.tv, f.counters, f.head, f.next);
+    RST_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_cross_lds<true>, dim3(groups), dim3(kTileThreads), 0, ctx->stream,
-                       region_of, cross, tile_cross, kept_list, (int)tiles, 0, split, split, f.cc,
-                       f.tu, f.tv, f.counters, f.head, f.next);
+                       region_of, cross, tile_cross, kept_list, (int)tiles, 0, split, split, 0,
+                       f.cc, f.tu, f.tv, f.counters, f.head, f.next);
     RST_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_cross_lds<false>, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of,
-                     cross, tile_cross, kept_list, (int)tiles, split, levels, levels, f.cc, f.tu,
+                     cross, tile_cross, kept_list, (int)tiles, split, levels, levels, 0, f.cc, f.tu,
                      f.tv, f.counters, f.head, f.next);
   RST_HIP(hipGetLastError());
   // global-memory fallback, active only when a merge above raised the flag

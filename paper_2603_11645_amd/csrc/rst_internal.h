@@ -164,6 +164,8 @@ enum {
   kCntRankOverflow = 11,   // contracted list did not fit the one-block ranking
   kCntRankRounds = 12,     // pointer-jumping rounds of the contracted list
   kCntKept = 13,           // cross edges kept by the deduplication pass
+  kCntKeptTop = 14,        // of those, the edges of the levels merged by the top pass
+  kCntCrossDone = 15,      // the one-block merge of all kept edges succeeded
   kCntTotal = 16
 };
 

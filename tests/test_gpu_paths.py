@@ -7,9 +7,12 @@ Which variant ran is read from rst_stats.paths:
     contracted tour list ranked by the one workgroup in global memory (C1
     grid) or, when longer than that workgroup takes, by multi-workgroup
     rounds (300k-vertex random graph);
-  * meshes: kept cross edges merged in LDS by one workgroup (light deletions)
-    or, when too many small trees meet at tile borders, in global memory (45%
-    deletions).
+  * meshes: kept cross edges of all levels merged in LDS by one workgroup
+    (a few hundred on a lightly thinned mesh); when more small trees meet at
+    tile borders (30% and 45% deletions), merged in LDS per group of tiles and
+    then the top levels; and
+    in global memory when a group meets a root outside its tiles as well
+    (45% deletions plus a tile of hub vertices).
 """
 import numpy as np
 import pytest
@@ -38,13 +41,15 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def mesh_plus_hub(seed=13):
-    """A 512x512 road-like mesh (32 tiles) and one more tile of 8192 hub
-    vertices, each joined to 3 random mesh vertices: the hub tile lists far
-    more cross edges than vertices (hooked flat), and its hooks join trees of
-    high tiles to roots in low tiles, so a group of tiles meets a root outside
-    its own range and the LDS merge falls back to global memory."""
-    mesh = I.road_mesh(512, 0.15, 0.001, seed=2)
+def mesh_plus_hub(mesh=None, seed=13):
+    """A mesh (default a 512x512 road-like one, 32 tiles) and one more tile of
+    8192 hub vertices, each joined to 3 random mesh vertices: the hub tile
+    lists far more cross edges than vertices (hooked flat), and its hooks join
+    trees of high tiles to roots in low tiles, so a group of tiles meets a root
+    outside its own range.  The one-workgroup merge of all levels has no such
+    limit; when the kept edges are too many for it, the group merge falls back
+    to global memory."""
+    mesh = mesh if mesh is not None else I.road_mesh(512, 0.15, 0.001, seed=2)
     n0 = mesh.n
     rs = np.random.RandomState(seed)
     hub = np.repeat(np.arange(n0, n0 + 8192), 3)
@@ -58,13 +63,15 @@ def mesh_plus_hub(seed=13):
 
 # name: (graph builder, rst_stats.paths bits that must be set, bits that must not)
 CASES = {
-    "grid_permuted_256": (lambda: I.grid_permuted(256, seed=1), 2, 1),
-    # thousands of trees: the contracted tour lists may exceed the LDS ranking
-    "grid_1024_del30": (lambda: I.grid(1024, 1024, 0.30, seed=7), 0, 1),
-    "grid_1024_del45": (lambda: I.grid(1024, 1024, 0.45, seed=7), 0, 1),
-    "road_512": (lambda: I.road_mesh(512, 0.15, 0.001, seed=2), 0, 3),
+    "grid_permuted_256": (lambda: I.grid_permuted(256, seed=1), 2, 5),
+    # thousands of trees: the contracted tour lists may exceed the LDS ranking;
+    # about 8k and 37k kept cross edges (group merges)
+    "grid_1024_del30": (lambda: I.grid(1024, 1024, 0.30, seed=7), 4, 1),
+    "grid_1024_del45": (lambda: I.grid(1024, 1024, 0.45, seed=7), 4, 1),
+    "road_512": (lambda: I.road_mesh(512, 0.15, 0.001, seed=2), 0, 7),
     "random_300k": (lambda: I.random_graph(300000, 450000, seed=11, connected=True), 2, 0),
-    "mesh_plus_hub": (mesh_plus_hub, 1, 0),
+    "mesh_plus_hub": (mesh_plus_hub, 0, 5),
+    "grid45_plus_hub": (lambda: mesh_plus_hub(I.grid(1024, 1024, 0.45, seed=7)), 5, 0),
 }
 
 
