@@ -170,14 +170,14 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
     int64_t n, const OffT *__restrict__ off, const int32_t *__restrict__ cols, int32_t *cc,
     int32_t *tu, int32_t *tv, int2 *cross, int32_t *tile_cross, int32_t *tile_lvl,
     int64_t *region_of, int32_t *counters, int64_t *chunks, int64_t chunk_cap, int heavy_deg,
-    const uint8_t *__restrict__ vmask, int32_t *head, int32_t *next) {
+    const uint8_t *__restrict__ vmask, int32_t *head, int32_t *next, int vec_cols) {
   __shared__ int lp[kTile];
   __shared__ int16_t eu[kTile];     // local endpoints of the edge held by a slot (-1: none)
   __shared__ int16_t ev[kTile];
   __shared__ int s_scan[kTile + 1]; // exclusive prefix of light degrees over the tile
   __shared__ int s_beg[kTile];      // first arc of each vertex, relative to off[v0]
   __shared__ int s_wave[kTileThreads / kWave];
-  __shared__ int s_ncross, s_lmin, s_lmax;
+  __shared__ int s_ncross, s_lmin, s_lmax, s_gap;
   const int tid = threadIdx.x;
   const int64_t v0 = (int64_t)blockIdx.x * kTile;
   const int cnt = (int)((n - v0) < kTile ? (n - v0) : kTile);
@@ -214,68 +214,137 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
   }
   int total;
   int run = block_excl_scan<kTileThreads>(mine, s_wave, &total);
+  // s_gap: some vertex of the tile offers fewer arcs than it has (heavy or
+  // masked), so the light arcs do not form one contiguous range of cols
+  if (tid == 0) s_gap = 0;
+  __syncthreads();
+  bool gap = false;
 #pragma unroll
   for (int j = 0; j < kTilePer; ++j) {
     const int li = tid * kTilePer + j;
     s_scan[li] = run;
     s_beg[li] = (int)(o[j] - base_off);
     run += dg[j];
+    gap |= li < cnt && (int64_t)dg[j] != (int64_t)(o[j + 1] - o[j]);
   }
+  if (gap) s_gap = 1;
   if (tid == 0) s_scan[kTile] = total;
   __syncthreads();
   // Arcs: thread t takes the t-th equal share of the tile's light arcs (merge
   // path over the degree scan) -- one binary search per thread, then a walk
-  // along its share; loads are issued U at a time before any hooking.
+  // along its share.
   const int share = (total + kTileThreads - 1) / kTileThreads;
   const int k_begin = tid * share < total ? tid * share : total;
   const int k_end = k_begin + share < total ? k_begin + share : total;
   int j = k_begin < total ? lds_upper_search(s_scan, kTile, k_begin) : 0;
   int lvmin = 63, lvmax = -1;
-  constexpr int U = 8;
-  for (int kb = k_begin; kb < k_begin + share; kb += U) {
-    int sl[U];
-    int32_t dst[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = kb + u;
-      sl[u] = -1;
-      dst[u] = 0;
-      if (k < k_end) {
-        while (s_scan[j + 1] <= k) ++j;           // next vertex with arcs left
-        sl[u] = j;
-        dst[u] = cols[region + s_beg[j] + (k - s_scan[j])];
+  // Arc (v0 + src) -> dst: hook it if both ends lie in the tile (one of the
+  // two arcs of an edge does it); true if it is a cross arc to keep, i.e.
+  // dst < v0 <= src (the reverse arc is skipped).
+  auto visit = [&](int src, int32_t dst) -> bool {
+    const int64_t dl = (int64_t)dst - v0;
+    if (dl >= 0 && dl < src) {
+      int ra = lds_find(src, lp), rb = lds_find((int)dl, lp);
+      while (ra != rb) {
+        const bool a_low = hook_priority((uint32_t)(v0 + ra)) < hook_priority((uint32_t)(v0 + rb));
+        const int lo = a_low ? ra : rb, hi = a_low ? rb : ra;
+        const int old = atomicCAS(&lp[lo], lo, hi);
+        if (old == lo) {
+          eu[lo] = (int16_t)src;
+          ev[lo] = (int16_t)dl;
+          break;
+        }
+        if (ra == lo) ra = lds_find(old, lp); else rb = lds_find(old, lp);
       }
+      return false;
     }
+    return dl < 0;
+  };
+  auto keep_cross = [&](int slot, int src, int32_t dst) {
+    const int32_t sg = (int32_t)(v0 + src);
+    cross[region + slot] = make_int2(sg, dst);
+    const int lv = cross_level(sg, dst);
+    lvmin = lv < lvmin ? lv : lvmin;
+    lvmax = lv > lvmax ? lv : lvmax;
+  };
+  if (!s_gap && vec_cols) {
+    // The share is the contiguous range [region + k_begin, region + k_end) of
+    // cols: read as aligned 16-byte vectors, 32 arcs issued at once (the
+    // vectors may reach into the neighbours' shares, never past the tile's
+    // arcs).  Cross arcs are appended four arcs at a time, one LDS atomic per
+    // wave for all four.
+    const int64_t p0 = region + k_begin, p1 = region + k_end, pend = region + total;
+    constexpr int V = 8;
+    // the same trip count in every lane (the ballots below need the whole wave)
+    const int nit = (share + 3 + 4 * V - 1) / (4 * V);
+    for (int it = 0; it < nit; ++it) {
+      const int64_t pa = (p0 & ~(int64_t)3) + (int64_t)it * (4 * V);
+      int32_t cv[4 * V];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      bool is_cross = false;
-      if (sl[u] >= 0) {
-        const int64_t dl = (int64_t)dst[u] - v0;
-        if (dl >= 0 && dl < sl[u]) {
-          int ra = lds_find(sl[u], lp), rb = lds_find((int)dl, lp);
-          while (ra != rb) {
-            const bool a_low =
-                hook_priority((uint32_t)(v0 + ra)) < hook_priority((uint32_t)(v0 + rb));
-            const int lo = a_low ? ra : rb, hi = a_low ? rb : ra;
-            const int old = atomicCAS(&lp[lo], lo, hi);
-            if (old == lo) {
-              eu[lo] = (int16_t)sl[u];
-              ev[lo] = (int16_t)dl;
-              break;
-            }
-            if (ra == lo) ra = lds_find(old, lp); else rb = lds_find(old, lp);
-          }
+      for (int v = 0; v < V; ++v) {
+        const int64_t q = pa + 4 * v;
+        if (q + 4 <= pend) {
+          const int4 x = *reinterpret_cast<const int4 *>(cols + q);
+          cv[4 * v] = x.x; cv[4 * v + 1] = x.y; cv[4 * v + 2] = x.z; cv[4 * v + 3] = x.w;
         } else {
-          is_cross = dl < 0;   // dst < v0 <= src; the reverse arc is skipped
+#pragma unroll
+          for (int c = 0; c < 4; ++c) cv[4 * v + c] = q + c < p1 ? cols[q + c] : 0;
         }
       }
-      const int slot = wave_append(is_cross, &s_ncross);   // LDS counter
-      if (is_cross) {
-        const int32_t sg = (int32_t)(v0 + sl[u]);
-        cross[region + slot] = make_int2(sg, dst[u]);
-        const int lv = cross_level(sg, dst[u]);
-        lvmin = lv < lvmin ? lv : lvmin;
-        lvmax = lv > lvmax ? lv : lvmax;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        bool isc[4];
+        int js[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t q = pa + 4 * v + c;
+          isc[c] = false;
+          js[c] = 0;
+          if (q >= p0 && q < p1) {
+            const int k = (int)(q - region);
+            while (s_scan[j + 1] <= k) ++j;       // next vertex with arcs left
+            js[c] = j;
+            isc[c] = visit(j, cv[4 * v + c]);
+          }
+        }
+        uint64_t m[4];
+        int tot = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) { m[c] = __ballot(isc[c]); tot += (int)__popcll(m[c]); }
+        if (tot) {
+          int base = 0;
+          if ((tid & 63) == 0) base = atomicAdd(&s_ncross, tot);
+          base = __shfl(base, 0, 64);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (isc[c]) keep_cross(base + lanes_below(m[c]), js[c], cv[4 * v + c]);
+            base += (int)__popcll(m[c]);
+          }
+        }
+      }
+    }
+  } else {
+    // loads are issued U at a time before any hooking
+    constexpr int U = 8;
+    for (int kb = k_begin; kb < k_begin + share; kb += U) {
+      int sl[U];
+      int32_t dst[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = kb + u;
+        sl[u] = -1;
+        dst[u] = 0;
+        if (k < k_end) {
+          while (s_scan[j + 1] <= k) ++j;           // next vertex with arcs left
+          sl[u] = j;
+          dst[u] = cols[region + s_beg[j] + (k - s_scan[j])];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool is_cross = sl[u] >= 0 && visit(sl[u], dst[u]);
+        const int slot = wave_append(is_cross, &s_ncross);   // LDS counter
+        if (is_cross) keep_cross(slot, sl[u], dst[u]);
       }
     }
   }
@@ -951,6 +1020,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
   const int64_t n = g->n;
   const unsigned tiles = grid_for(n, kTile);
   const unsigned heavy_grid = (unsigned)(ctx->num_cus * 8);
+  const int vec_cols = ((uintptr_t)g->cols & 15) == 0;   // 16-byte loads of cols allowed
   int levels = 0;
   while ((1u << levels) < tiles) ++levels;
   if (g->offset_bytes == 4) {
@@ -959,7 +1029,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     hipLaunchKernelGGL(k_hook_tile<int32_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
                        off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, region_of,
                        f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask, f.head,
-                       f.next);
+                       f.next, vec_cols);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));
@@ -972,7 +1042,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     hipLaunchKernelGGL(k_hook_tile<int64_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
                        off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, region_of,
                        f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask, f.head,
-                       f.next);
+                       f.next, vec_cols);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));

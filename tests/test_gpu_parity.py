@@ -196,6 +196,25 @@ def test_list_rank_tiled_locality(ctx):
         assert np.array_equal(got, exp)
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_spanning_tree_unaligned_cols(ctx, shift):
+    """Neighbour ids at an address that is not 16-byte aligned (a view into a
+    larger buffer): the tile pass reads them without vector loads; labels and
+    the parent array must come out the same as from an aligned copy."""
+    for g in (I.road_mesh(160, 0.15, 0.01, seed=9), I.grid(100, 300, 0.2, seed=4)):
+        off = dev(g.offsets_typed())
+        buf = torch.zeros(g.nnz + shift, dtype=torch.int32, device="cuda")
+        buf[shift:] = dev(g.cols)
+        cols = buf[shift:]
+        assert cols.data_ptr() % 16 != 0
+        k_ref, lab_ref = oracle.components(g.n, g.offsets, g.cols)
+        label, k = ctx.components(off, cols)
+        assert k == k_ref and np.array_equal(label.cpu().numpy(), lab_ref)
+        par = ctx.spanning_tree(off, cols, 3, "gconn").cpu().numpy()
+        code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, par, [3])
+        assert code == 0, (oracle.VERIFY_CODES[code], bad)
+
+
 def _lists_with_heads(A, heads, rs):
     """Lists over 0..A-1 whose first elements are exactly `heads` (the other
     ids follow in random order, split among the lists)."""
