@@ -496,48 +496,202 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
   }
 }
 
-// The contracted list (M = base[tiles] words) ranked by one block: pointer
-// jumping in LDS until no word has a successor left, so the round count needs
-// no host round trip.  Longer lists (more than kSmallLds words; one CU would
-// be slower on them than multi-block rounds) raise counters[kCntRankOverflow]
-// and change nothing: the consumers then skip their work and the host ranks
-// the list in multi-block rounds.  counters[kCntExits] = M, counters[kCntRankRounds] =
-// rounds.
+// The contracted list (M = base[tiles] words, (successor, hops to it)) ranked
+// by one block, with no host round trip.  Like the tile pass: every 8th word
+// and every list head starts a ruler; one walk per ruler follows its piece
+// (opening a new ruler after 16 words), overwriting each word with (ruler,
+// weighted distance from the ruler's start); the rulers are ranked by in-place
+// pointer jumping on 64-bit words (last-ruler flag, next ruler, distance) and
+// every word's distance to its tail follows.  Lists with too many heads for
+// the ruler table (many small trees) are ranked by plain pointer jumping over
+// all words in LDS instead.  Longer lists (more than kSmallLds words; one CU
+// would be slower on them than multi-block rounds) raise
+// counters[kCntRankOverflow] and change nothing: the consumers then skip their
+// work and the host ranks the list in multi-block rounds.  counters[kCntExits]
+// = M, counters[kCntRankRounds] = pointer-jumping rounds.  Output: crank[i] =
+// (-1, distance from word i to the tail of its list).
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallPer = 19;
-// 19456 words of 8 B (152 KB; the block-wide OR reduction takes a little LDS too)
-constexpr int kSmallLds = kSmallPer * kSmallThreads;
+constexpr int kSmallLds = kSmallPer * kSmallThreads;    // 19456 words
+constexpr int kSmallRulers = 4096;
+constexpr int kSmallPiece = 16;
+// LDS, ruler path: successor int16 [kSmallLds] (then the word's ruler),
+// weight uint32 [kSmallLds] (then the word's distance from its ruler's start),
+// has-predecessor bits, ruler starts int16 [kSmallRulers], ruler words uint64
+// [kSmallRulers]; all-words path: (successor, hops) uint64 [kSmallLds].
+constexpr int kSmOffW = 2 * kSmallLds;
+constexpr int kSmOffHp = kSmOffW + 4 * kSmallLds;
+constexpr int kSmOffRs = kSmOffHp + kSmallLds / 8;
+constexpr int kSmOffRw = kSmOffRs + 2 * kSmallRulers;
+constexpr int kSmBytes = kSmOffRw + 8 * kSmallRulers;
+static_assert(kSmOffRw % 8 == 0 && kSmBytes >= 8 * kSmallLds, "ruler path LDS layout");
+constexpr uint64_t kSmFinal = 1ull << 63;
 
 __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__restrict__ Mp,
                                                               uint64_t *crank, int32_t *counters) {
-  __shared__ uint64_t s_word[kSmallLds];   // (succ, hops) as in crank
+  __shared__ __align__(16) unsigned char s_raw[kSmBytes];
+  __shared__ int s_extra, s_ndyn, s_or[3];
   const int tid = threadIdx.x;
   const int64_t M = *Mp;
-  if (tid == 0) counters[kCntExits] = (int32_t)M;
+  if (tid == 0) {
+    counters[kCntExits] = (int32_t)M;
+    s_extra = 0;
+    s_ndyn = 0;
+    s_or[0] = s_or[1] = s_or[2] = 0;
+  }
+  if (M > kSmallLds) {
+    if (tid == 0) counters[kCntRankOverflow] = 1;
+    return;
+  }
+  const int m = (int)M;
+  int16_t *sc = reinterpret_cast<int16_t *>(s_raw);
+  uint32_t *wt = reinterpret_cast<uint32_t *>(s_raw + kSmOffW);
+  uint32_t *haspred = reinterpret_cast<uint32_t *>(s_raw + kSmOffHp);
+  int16_t *r_start = reinterpret_cast<int16_t *>(s_raw + kSmOffRs);
+  uint64_t *r_word = reinterpret_cast<uint64_t *>(s_raw + kSmOffRw);
+  uint64_t own[kSmallPer];
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k) {
+    const int i = tid + k * kSmallThreads;
+    own[k] = i < m ? crank[i] : pack_rank(-1, 0);
+  }
+  for (int q = tid; q < kSmallLds / 32; q += kSmallThreads) haspred[q] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k) {
+    const int i = tid + k * kSmallThreads;
+    if (i < m) {
+      int32_t t = (int32_t)(uint32_t)own[k];
+      if (t >= m) t = -1;   // out-of-range successors end the list
+      sc[i] = (int16_t)t;
+      wt[i] = (uint32_t)(own[k] >> 32);
+      if (t >= 0) atomicOr(&haspred[t >> 5], 1u << (t & 31));
+    }
+  }
+  __syncthreads();
+  const int nstr = (m + kRuler - 1) / kRuler;
+  for (int q = tid; q < nstr; q += kSmallThreads) r_start[q] = (int16_t)(q * kRuler);
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k) {
+    const int i = tid + k * kSmallThreads;
+    const bool head = i < m && (i % kRuler) != 0 && !((haspred[i >> 5] >> (i & 31)) & 1u);
+    const int x = wave_append(head, &s_extra);
+    if (head && nstr + x < kSmallRulers) r_start[nstr + x] = (int16_t)i;
+  }
+  __syncthreads();
+  const int nstatic = nstr + s_extra;
   int rounds = 0;
-  // a list of M words needs at most ceil(log2 M) rounds; the cap also ends the
-  // loop on malformed (cyclic) input
-  int max_rounds = 1;
-  while (((int64_t)1 << max_rounds) < M) ++max_rounds;
-  if (M <= kSmallLds) {
-    // Each thread keeps its own words in registers; a round gathers the
-    // successors' words from LDS, then (after a barrier) publishes its own.
-    const int m = (int)M;
-    uint64_t own[kSmallPer];
+  if (nstatic + (m + kSmallPiece - 1) / kSmallPiece <= kSmallRulers) {
+    // the walk: lanes take the wave's share of static rulers as they free up
+    const int wid = tid >> 6;
+    const int per = (nstatic + kSmallThreads / 64 - 1) / (kSmallThreads / 64);
+    int qn = wid * per;
+    const int qe = min(nstatic, qn + per);
+    int q = -1, j = 0, len = 0;
+    uint32_t acc = 0;
+    while (true) {
+      const uint64_t idle = __ballot(q < 0);
+      if (qn < qe && idle != 0ull) {
+        const int r = qn + lanes_below(idle);
+        if (q < 0 && r < qe) { q = r; j = r_start[r]; len = 0; acc = 0; }
+        qn += (int)__popcll(idle);
+      }
+      if (__ballot(q >= 0) == 0ull) break;
+      bool open = false;
+      if (q >= 0) {
+        const int t = sc[j];
+        const uint32_t wj = wt[j];
+        sc[j] = (int16_t)q;
+        wt[j] = acc;
+        if (t < 0) {                       // the tail: its ruler is the last of the chain
+          r_word[q] = kSmFinal | ((uint64_t)q << 32) | acc;
+          q = -1;
+        } else {
+          acc += wj;
+          j = t;
+          ++len;
+          if ((j & (kRuler - 1)) == 0) {
+            r_word[q] = ((uint64_t)(j / kRuler) << 32) | acc;
+            q = -1;
+          } else if (len == kSmallPiece) {
+            open = true;
+          }
+        }
+      }
+      const int d = wave_append(open, &s_ndyn);
+      if (open) {
+        const int x = nstatic + d;
+        if (x < kSmallRulers) {
+          r_word[q] = ((uint64_t)x << 32) | acc;
+          q = x;
+          len = 0;
+          acc = 0;
+        } else {   // not reached on simple lists (at most m / kSmallPiece are opened)
+          r_word[q] = kSmFinal | ((uint64_t)q << 32) | acc;
+          q = -1;
+        }
+      }
+    }
+    __syncthreads();
+    const int nrul = min(nstatic + s_ndyn, kSmallRulers);
+    // pointer jumping over the rulers, in place (a word read while its owner
+    // rewrites it is either version, both consistent); three rotating flags
+    // let one barrier a round suffice
+    constexpr int QP = kSmallRulers / kSmallThreads;
+    for (int round = 0; round < 14; ++round) {
+      bool pending = false;
+#pragma unroll
+      for (int k = 0; k < QP; ++k) {
+        const int r = tid + k * kSmallThreads;
+        if (r < nrul) {
+          const uint64_t w = r_word[r];
+          if (!(w & kSmFinal)) {
+            const uint64_t w2 = r_word[(w >> 32) & (kSmallRulers - 1)];
+            const uint64_t nw = (w2 & 0xffffffff00000000ull) | (uint32_t)((uint32_t)w + (uint32_t)w2);
+            r_word[r] = nw;
+            pending |= !(nw & kSmFinal);
+          }
+        }
+      }
+      ++rounds;
+      if (pending) s_or[round % 3] = 1;
+      if (tid == 0) s_or[(round + 1) % 3] = 0;
+      __syncthreads();
+      if (!s_or[round % 3]) break;
+    }
 #pragma unroll
     for (int k = 0; k < kSmallPer; ++k) {
       const int i = tid + k * kSmallThreads;
-      own[k] = i < m ? crank[i] : pack_rank(-1, 0);
-      if (i < m) s_word[i] = own[k];
+      if (i < m) {
+        const uint32_t dist = (uint32_t)r_word[sc[i] & (kSmallRulers - 1)] - wt[i];
+        crank[i] = pack_rank(-1, dist);
+      }
     }
-    bool active = __syncthreads_or(1);
-    while (active) {
+  } else {
+    // all-words pointer jumping: each thread keeps its own words in registers;
+    // a round gathers the successors' words from LDS, then (after a barrier)
+    // publishes its own.  ceil(log2 M) rounds suffice; the cap also ends the
+    // loop on malformed (cyclic) input.
+    int max_rounds = 1;
+    while (((int64_t)1 << max_rounds) < M) ++max_rounds;
+    uint64_t *s_word = reinterpret_cast<uint64_t *>(s_raw);
+    __syncthreads();   // every thread is done with the ruler tables
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+      const int i = tid + k * kSmallThreads;
+      if (i < m) {
+        if ((int32_t)(uint32_t)own[k] >= m) own[k] = pack_rank(-1, (uint32_t)(own[k] >> 32));
+        s_word[i] = own[k];
+      }
+    }
+    __syncthreads();
+    for (int round = 0; round < max_rounds; ++round) {
       bool more = false;
 #pragma unroll
       for (int k = 0; k < kSmallPer; ++k) {
-        const int32_t sc = (int32_t)(uint32_t)own[k];
-        if (sc >= 0) {
-          const uint64_t nb = s_word[sc];
+        const int32_t t = (int32_t)(uint32_t)own[k];
+        if (t >= 0) {
+          const uint64_t nb = s_word[t];
           own[k] = (((own[k] >> 32) + (nb >> 32)) << 32) | (nb & 0xffffffffull);
           more |= (int32_t)(uint32_t)nb >= 0;
         }
@@ -549,16 +703,16 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
         if (i < m) s_word[i] = own[k];
       }
       ++rounds;
-      active = __syncthreads_or(more) && rounds < max_rounds;
+      if (more) s_or[round % 3] = 1;
+      if (tid == 0) s_or[(round + 1) % 3] = 0;
+      __syncthreads();
+      if (!s_or[round % 3]) break;
     }
 #pragma unroll
     for (int k = 0; k < kSmallPer; ++k) {
       const int i = tid + k * kSmallThreads;
       if (i < m) crank[i] = own[k];
     }
-  } else {
-    if (tid == 0) counters[kCntRankOverflow] = 1;
-    return;
   }
   if (tid == 0) counters[kCntRankRounds] = rounds;
 }

@@ -259,6 +259,32 @@ def test_list_rank_tile_rulers(ctx):
         assert np.array_equal(got, exp)
 
 
+def test_list_rank_contracted_heads(ctx):
+    """The contracted list of exits ranked in one workgroup, with few and with
+    many list heads: lists that cross tiles often (one long list and 40 lists
+    over 3 tiles), and 6000 two-element lists inside one tile, whose 6000
+    tails form a contracted list of 6000 one-word lists -- more heads than
+    the ruler table takes, so that workgroup ranks all words by pointer
+    jumping instead."""
+    rs = np.random.RandomState(8)
+    cases = []
+    for A, nl in ((40000, 1), (45000, 40)):
+        order = rs.permutation(A)
+        cuts = np.sort(rs.choice(np.arange(1, A), size=nl - 1, replace=False))
+        succ = np.full(A, -1, np.int32)
+        for piece in np.split(order, cuts):
+            succ[piece[:-1]] = piece[1:]
+        cases.append(succ)
+    order = rs.permutation(12000).reshape(-1, 2)
+    succ = np.full(12000, -1, np.int32)
+    succ[order[:, 0]] = order[:, 1]
+    cases.append(succ)
+    for succ in cases:
+        exp, _ = oracle.list_rank(succ)
+        got = ctx.list_rank(dev(succ)).cpu().numpy()
+        assert np.array_equal(got, exp)
+
+
 def test_heavy_hub_paths(ctx):
     """A star whose centre exceeds the heavy-degree threshold many times over."""
     g = I.star(200001, 7)
