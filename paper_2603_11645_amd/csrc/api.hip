@@ -152,13 +152,24 @@ static rst_status enqueue_gconn(rst_ctx *ctx, const rst_csr *g, const int32_t *r
   RST_TRY(mark(ctx, st, 0));
   RST_TRY(enqueue_hook_csr(ctx, g, w.f, w.chunks, w.chunk_cap, w.cross, w.tile_cross));
   RST_TRY(mark(ctx, st, 1));
-  RST_TRY(enqueue_compress(ctx, n, w.f.cc, w.f.comp_root, nullptr));
-  RST_TRY(mark(ctx, st, 2));
-  RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, w.f.cc, w.f.comp_root, parent, w.f.counters));
-  RST_TRY(mark(ctx, st, 3));
+  SlotArcs arcs{w.f.tu, w.f.tv, w.f.next, w.f.head, w.f.cc, w.f.comp_root, n, w.endsucc};
+  if (nroots == 1) {
+    // one pass: final labels, the root's claim, end-of-list successors (the
+    // "roots" stage stays empty)
+    RST_TRY(enqueue_settle(ctx, n, roots, w.f.cc, w.f.comp_root, w.f.head, w.endsucc, parent,
+                           w.f.counters));
+    arcs.endsucc_ready = true;
+    RST_TRY(mark(ctx, st, 2));
+    RST_TRY(mark(ctx, st, 3));
+  } else {
+    RST_TRY(enqueue_compress(ctx, n, w.f.cc, w.f.comp_root, nullptr));
+    RST_TRY(mark(ctx, st, 2));
+    RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, w.f.cc, w.f.comp_root, parent,
+                               w.f.counters));
+    RST_TRY(mark(ctx, st, 3));
+  }
   // the successor pass is fused into the first ranking pass (stage "succ" stays empty)
   RST_TRY(mark(ctx, st, 4));
-  SlotArcs arcs{w.f.tu, w.f.tv, w.f.next, w.f.head, w.f.cc, w.f.comp_root, n, w.endsucc};
   RST_TRY(enqueue_rank_tiled(ctx, 2 * n, w.rank, w.xid, w.rb, w.f.counters, &arcs, false));
   RST_TRY(mark(ctx, st, 5));
   RST_TRY(enqueue_expand_parent(ctx, n, n, w.f.tu, w.f.tv, w.rank, w.xid, w.rb.tile_base,

@@ -57,6 +57,40 @@ __global__ void k_mark_roots(const int32_t *__restrict__ roots, int32_t nroots, 
   parent[r] = r;
 }
 
+// Final pointer jumping fused with the root marking and the end-of-list
+// successors, for one designated root R = roots[0]: every vertex points at its
+// tree's root (the minimum id of its component, as after k_compress);
+// comp_root holds R at that root of R's component and -1 at every other
+// vertex; P[R] = R; endsucc[v] is v's first out-arc, or -1 where v roots its
+// tree (R in R's component, the minimum id in the others).  The chain from R
+// is walked by every thread (the same few words, cached); concurrent
+// shortcuts only replace a pointer by an ancestor, so every walk still ends at
+// the root.
+template <int B>
+__global__ __launch_bounds__(B) void k_settle(int64_t n, const int32_t *__restrict__ roots,
+                                                   int32_t *cc, int32_t *comp_root,
+                                                   const int32_t *__restrict__ head,
+                                                   int32_t *endsucc, int32_t *parent,
+                                                   int32_t *counters) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t R = roots[0];
+  if (R < 0 || R >= n) {
+    if (v == 0) atomicOr(&counters[kCntRangeErr], 1);
+    return;
+  }
+  int32_t cR = R, nx;
+  while (cR > (nx = cc[cR])) cR = nx;
+  int32_t r = cc[v];
+  const int32_t first = r;
+  while (r > (nx = cc[r])) r = nx;
+  if (r != first) cc[v] = r;
+  comp_root[v] = (v == cR) ? R : -1;
+  const bool tree_root = (r == cR) ? (v == R) : (r == (int32_t)v);
+  endsucc[v] = tree_root ? -1 : head[v];
+  if (v == R) parent[v] = R;
+}
+
 // Per-vertex out-arc lists: next[e] = previous head of src(e), head = e.
 template <int B>
 __global__ __launch_bounds__(B) void k_link(int64_t slots, const int32_t *__restrict__ tu,
@@ -822,6 +856,14 @@ int rank_rounds_for(int64_t max_list_len) {
   return r;
 }
 
+rst_status enqueue_settle(rst_ctx *ctx, int64_t n, const int32_t *roots, int32_t *cc,
+                          int32_t *comp_root, const int32_t *head, int32_t *endsucc,
+                          int32_t *parent, int32_t *counters) {
+  RST_SWEEP(ctx, k_settle, n, n, roots, cc, comp_root, head, endsucc, parent, counters);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
 rst_status enqueue_mark_roots(rst_ctx *ctx, const int32_t *roots, int32_t nroots, int64_t n,
                               const int32_t *cc, int32_t *comp_root, int32_t *parent,
                               int32_t *counters) {
@@ -894,9 +936,11 @@ rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *
   if (A <= 0) return RST_OK;
   const int64_t tiles = (int64_t)rank_tile_count(A);
   if (from_slots) {
-    RST_SWEEP(ctx, k_endsucc, from_slots->n, from_slots->n, from_slots->head, from_slots->cc,
-              from_slots->comp_root, from_slots->endsucc);
-    RST_HIP(hipGetLastError());
+    if (!from_slots->endsucc_ready) {
+      RST_SWEEP(ctx, k_endsucc, from_slots->n, from_slots->n, from_slots->head, from_slots->cc,
+                from_slots->comp_root, from_slots->endsucc);
+      RST_HIP(hipGetLastError());
+    }
     SlotSrc src{from_slots->tu, from_slots->tv, from_slots->next, from_slots->endsucc};
     RST_KMARK(ctx, RST_KERNEL_RANK_TILE, 0);
     hipLaunchKernelGGL(k_rank_tile<true>, dim3((unsigned)tiles), dim3(kRankThreads), 0, ctx->stream,

@@ -187,6 +187,9 @@ rst_status enqueue_count_roots(rst_ctx *ctx, int64_t n, const int32_t *cc, int32
 size_t hook_chunk_capacity(const rst_ctx *ctx, int64_t nnz);
 
 // euler.hip
+rst_status enqueue_settle(rst_ctx *ctx, int64_t n, const int32_t *roots, int32_t *cc,
+                          int32_t *comp_root, const int32_t *head, int32_t *endsucc,
+                          int32_t *parent, int32_t *counters);
 rst_status enqueue_mark_roots(rst_ctx *ctx, const int32_t *roots, int32_t nroots, int64_t n,
                               const int32_t *cc, int32_t *comp_root, int32_t *parent,
                               int32_t *counters);
@@ -211,6 +214,7 @@ struct SlotArcs {
   const int32_t *tu, *tv, *next, *head, *cc, *comp_root;
   int64_t n;          // vertices
   int32_t *endsucc;   // scratch [n]
+  bool endsucc_ready = false;   // already filled (by enqueue_settle)
 };
 // Scratch of the tiled list ranking of A words: exits int32 [A+1], crank
 // uint64 [A+1], tile_exits int32 [tiles], tile_base int64 [tiles+1].
