@@ -387,10 +387,15 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
     if (i < cnt) lp[i] = (r[j] == i) ? -(i + 1) : r[j];
   }
   __syncthreads();
+  // Only the first lane of a run of lanes with the same root does the atomic
+  // (it holds the run's smallest id): on a mesh tile nearly every vertex has
+  // the same root, and 8192 atomics on one LDS word serialise.
 #pragma unroll
   for (int j = 0; j < kTilePer; ++j) {
     const int i = tid + j * kTileThreads;
-    if (i < cnt && r[j] != i) atomicMax(&lp[r[j]], -(i + 1));
+    const int left = __shfl_up(r[j], 1, 64);
+    const bool first = (tid & 63) == 0 || left != r[j];
+    if (i < cnt && r[j] != i && first) atomicMax(&lp[r[j]], -(i + 1));
   }
   __syncthreads();
 #pragma unroll
