@@ -143,12 +143,26 @@ __device__ __forceinline__ uint32_t hook_priority(uint32_t x) {
   return x;   // a bijection of 32-bit values: distinct vertices never tie
 }
 
-__device__ __forceinline__ int lds_find(int x, int *lp) {
-  int p = lp[x];
+// vertices per group of the tile's degree prefix, and the largest degree a
+// vertex may have to be hooked by its tile (its arcs beyond would not fit the
+// 16-bit in-group prefix; such a vertex goes to the chunked heavy pass)
+constexpr int kTileGroup = 64;
+constexpr int kTileLightMax = 1023;
+constexpr int kTileMask = kTile - 1;
+
+// LDS word of a tile vertex while hooking: its parent in the low 13 bits and,
+// once it has been hooked as a root, 1 + the local source of the hooking edge
+// above them (the edge's other end is kept in ev[]).  Path halving rewrites
+// the parent bits only; a non-root's upper bits never change again.
+__device__ __forceinline__ int lds_find_tile(int x, int *lp) {
+  int w = lp[x];
+  int p = w & kTileMask;
   while (p != x) {
-    const int gp = lp[p];
-    lp[x] = gp;          // path halving: x now skips to its grandparent
+    const int wp = lp[p];
+    const int gp = wp & kTileMask;
+    lp[x] = (w & ~kTileMask) | gp;   // path halving: x now skips to its grandparent
     x = p;
+    w = wp;
     p = gp;
   }
   return x;
@@ -165,26 +179,33 @@ __device__ __forceinline__ int cross_level(int32_t s, int32_t t) {
 // Cross-tile edges of tile b are written to cross[off[b*kTile] + k], a region
 // as long as the tile's arc range, and counted in tile_cross[b]: no global
 // atomics, no compaction.
+//
+// LDS (64.6 KB, two workgroups per CU): lp, the hooking words, later the tree
+// minima, then the heads of the tile's arc lists; s16, first the in-group
+// degree prefix and ev (other end of each root's hooking edge), then eu and ev,
+// then the tile's next-arc links; the group bases of the degree prefix.
 template <class OffT>
-__global__ __launch_bounds__(kTileThreads) void k_hook_tile(
+__global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
     int64_t n, const OffT *__restrict__ off, const int32_t *__restrict__ cols, int32_t *cc,
     int32_t *tu, int32_t *tv, int2 *cross, int32_t *tile_cross, int32_t *tile_lvl,
     int64_t *region_of, int32_t *counters, int64_t *chunks, int64_t chunk_cap, int heavy_deg,
     const uint8_t *__restrict__ vmask, int32_t *head, int32_t *next, int vec_cols) {
   __shared__ int lp[kTile];
-  __shared__ int16_t eu[kTile];     // local endpoints of the edge held by a slot (-1: none)
-  __shared__ int16_t ev[kTile];
-  __shared__ int s_scan[kTile + 1]; // exclusive prefix of light degrees over the tile
-  __shared__ int s_beg[kTile];      // first arc of each vertex, relative to off[v0]
+  __shared__ __align__(16) int16_t s16[2 * kTile];
+  __shared__ int s_gbase[kTile / kTileGroup + 1];   // light arcs before each group; [last] = all
   __shared__ int s_wave[kTileThreads / kWave];
   __shared__ int s_ncross, s_lmin, s_lmax, s_gap;
+  uint16_t *sc16 = reinterpret_cast<uint16_t *>(s16);   // light arcs before a vertex, in its group
+  int16_t *eu = s16;                                     // after the arcs: source of each root's edge
+  int16_t *ev = s16 + kTile;
   const int tid = threadIdx.x;
   const int64_t v0 = (int64_t)blockIdx.x * kTile;
   const int cnt = (int)((n - v0) < kTile ? (n - v0) : kTile);
   const OffT base_off = off[v0];
   const int64_t region = (int64_t)base_off;
-  for (int i = tid; i < kTile; i += kTileThreads) { lp[i] = i; eu[i] = -1; ev[i] = -1; }
-  if (tid == 0) { s_ncross = 0; s_lmin = 63; s_lmax = -1; }
+  const int light_max = heavy_deg < kTileLightMax ? heavy_deg : kTileLightMax;
+  for (int i = tid; i < kTile; i += kTileThreads) { lp[i] = i; ev[i] = -1; }
+  if (tid == 0) { s_ncross = 0; s_lmin = 63; s_lmax = -1; s_gap = 0; }
   // all offsets of the tile in one round trip: thread t owns vertices 8t..8t+7
   OffT o[kTilePer + 1];
 #pragma unroll
@@ -194,6 +215,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
   }
   int dg[kTilePer];
   int mine = 0;
+  bool gap = false;
 #pragma unroll
   for (int j = 0; j < kTilePer; ++j) {
     const int li = tid * kTilePer + j;
@@ -201,7 +223,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
     // a masked vertex (its graph is handled by another method) offers no arcs
     if (li < cnt && !(vmask && vmask[v0 + li])) {
       const int64_t d = (int64_t)(o[j + 1] - o[j]);
-      if (d > heavy_deg) {
+      if (d > light_max) {
         const int64_t v = v0 + li;
         const int64_t nc = (d + kChunk - 1) / kChunk;
         const int64_t cb = atomicAdd(&counters[kCntChunks], (int)nc);
@@ -210,33 +232,46 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
         dg[j] = (int)d;
       }
     }
+    // s_gap: some vertex offers fewer arcs than it has (heavy or masked), so
+    // the light arcs are not one contiguous range of cols
+    gap |= li < cnt && (int64_t)dg[j] != (int64_t)(o[j + 1] - o[j]);
     mine += dg[j];
   }
   int total;
-  int run = block_excl_scan<kTileThreads>(mine, s_wave, &total);
-  // s_gap: some vertex of the tile offers fewer arcs than it has (heavy or
-  // masked), so the light arcs do not form one contiguous range of cols
-  if (tid == 0) s_gap = 0;
-  __syncthreads();
-  bool gap = false;
+  const int run0 = block_excl_scan<kTileThreads>(mine, s_wave, &total);
+  // the 8 threads of a 64-vertex group sit in one wave: the group's base is
+  // the prefix of its first thread
+  const int gb = __shfl(run0, (tid & 63) & ~(kTileGroup / kTilePer - 1), 64);
+  if ((tid & (kTileGroup / kTilePer - 1)) == 0) s_gbase[tid / (kTileGroup / kTilePer)] = run0;
+  if (tid == 0) s_gbase[kTile / kTileGroup] = total;
+  int run = run0 - gb;
 #pragma unroll
   for (int j = 0; j < kTilePer; ++j) {
-    const int li = tid * kTilePer + j;
-    s_scan[li] = run;
-    s_beg[li] = (int)(o[j] - base_off);
+    sc16[tid * kTilePer + j] = (uint16_t)run;
     run += dg[j];
-    gap |= li < cnt && (int64_t)dg[j] != (int64_t)(o[j + 1] - o[j]);
   }
   if (gap) s_gap = 1;
-  if (tid == 0) s_scan[kTile] = total;
   __syncthreads();
+  // light arcs before vertex j of the tile (j = kTile: all of them)
+  auto scan_at = [&](int q) -> int {
+    return s_gbase[q / kTileGroup] + (q < kTile ? (int)sc16[q] : 0);
+  };
   // Arcs: thread t takes the t-th equal share of the tile's light arcs (merge
-  // path over the degree scan) -- one binary search per thread, then a walk
+  // path over the degree prefix) -- one binary search per thread, then a walk
   // along its share.
   const int share = (total + kTileThreads - 1) / kTileThreads;
   const int k_begin = tid * share < total ? tid * share : total;
   const int k_end = k_begin + share < total ? k_begin + share : total;
-  int j = k_begin < total ? lds_upper_search(s_scan, kTile, k_begin) : 0;
+  int j = 0;
+  if (k_begin < total) {
+    int lo = 0, hi = kTile;   // largest j with scan_at(j) <= k_begin
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (scan_at(mid) <= k_begin) lo = mid; else hi = mid;
+    }
+    j = lo;
+  }
+  int next_start = scan_at(j + 1);
   int lvmin = 63, lvmax = -1;
   // Arc (v0 + src) -> dst: hook it if both ends lie in the tile (one of the
   // two arcs of an edge does it); true if it is a cross arc to keep, i.e.
@@ -244,17 +279,17 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
   auto visit = [&](int src, int32_t dst) -> bool {
     const int64_t dl = (int64_t)dst - v0;
     if (dl >= 0 && dl < src) {
-      int ra = lds_find(src, lp), rb = lds_find((int)dl, lp);
+      int ra = lds_find_tile(src, lp), rb = lds_find_tile((int)dl, lp);
       while (ra != rb) {
         const bool a_low = hook_priority((uint32_t)(v0 + ra)) < hook_priority((uint32_t)(v0 + rb));
         const int lo = a_low ? ra : rb, hi = a_low ? rb : ra;
-        const int old = atomicCAS(&lp[lo], lo, hi);
+        const int old = atomicCAS(&lp[lo], lo, hi | ((src + 1) << kTileShift));
         if (old == lo) {
-          eu[lo] = (int16_t)src;
           ev[lo] = (int16_t)dl;
           break;
         }
-        if (ra == lo) ra = lds_find(old, lp); else rb = lds_find(old, lp);
+        const int np = lds_find_tile(old & kTileMask, lp);
+        if (ra == lo) ra = np; else rb = np;
       }
       return false;
     }
@@ -267,14 +302,14 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
     lvmin = lv < lvmin ? lv : lvmin;
     lvmax = lv > lvmax ? lv : lvmax;
   };
-  if (!s_gap && vec_cols) {
+  if (!s_gap) {
     // The share is the contiguous range [region + k_begin, region + k_end) of
-    // cols: read as aligned 16-byte vectors, 32 arcs issued at once (the
-    // vectors may reach into the neighbours' shares, never past the tile's
-    // arcs).  Cross arcs are appended four arcs at a time, one LDS atomic per
-    // wave for all four.
+    // cols: read 16 arcs at a time, as aligned 16-byte vectors when cols is
+    // 16-byte aligned (the vectors may reach into the neighbours' shares,
+    // never past the tile's arcs).  Cross arcs are appended four arcs at a
+    // time, one LDS atomic per wave for all four.
     const int64_t p0 = region + k_begin, p1 = region + k_end, pend = region + total;
-    constexpr int V = 8;
+    constexpr int V = 4;
     // the same trip count in every lane (the ballots below need the whole wave)
     const int nit = (share + 3 + 4 * V - 1) / (4 * V);
     for (int it = 0; it < nit; ++it) {
@@ -283,12 +318,12 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const int64_t q = pa + 4 * v;
-        if (q + 4 <= pend) {
+        if (vec_cols && q + 4 <= pend) {
           const int4 x = *reinterpret_cast<const int4 *>(cols + q);
           cv[4 * v] = x.x; cv[4 * v + 1] = x.y; cv[4 * v + 2] = x.z; cv[4 * v + 3] = x.w;
         } else {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) cv[4 * v + c] = q + c < p1 ? cols[q + c] : 0;
+          for (int c = 0; c < 4; ++c) cv[4 * v + c] = (q + c >= p0 && q + c < p1) ? cols[q + c] : 0;
         }
       }
 #pragma unroll
@@ -302,7 +337,7 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
           js[c] = 0;
           if (q >= p0 && q < p1) {
             const int k = (int)(q - region);
-            while (s_scan[j + 1] <= k) ++j;       // next vertex with arcs left
+            while (next_start <= k) next_start = scan_at(++j + 1);   // next vertex with arcs left
             js[c] = j;
             isc[c] = visit(j, cv[4 * v + c]);
           }
@@ -324,22 +359,28 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
       }
     }
   } else {
-    // loads are issued U at a time before any hooking
-    constexpr int U = 8;
+    // heavy or masked vertices: arc k of vertex j is cols[off[v0 + j] + k -
+    // scan_at(j)]; the owners of U arcs, then their offsets, then their ids
+    // are fetched U at a time before any hooking
+    constexpr int U = 4;
     for (int kb = k_begin; kb < k_begin + share; kb += U) {
       int sl[U];
-      int32_t dst[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = kb + u;
         sl[u] = -1;
-        dst[u] = 0;
         if (k < k_end) {
-          while (s_scan[j + 1] <= k) ++j;           // next vertex with arcs left
+          while (next_start <= k) next_start = scan_at(++j + 1);
           sl[u] = j;
-          dst[u] = cols[region + s_beg[j] + (k - s_scan[j])];
         }
       }
+      int64_t ci[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        ci[u] = sl[u] >= 0 ? (int64_t)off[v0 + sl[u]] + (kb + u - scan_at(sl[u])) : 0;
+      int32_t dst[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) dst[u] = sl[u] >= 0 ? cols[ci[u]] : 0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const bool is_cross = sl[u] >= 0 && visit(sl[u], dst[u]);
@@ -376,32 +417,37 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
   // -(min+1); members lift it with atomicMax on the negated value.
   int r[kTilePer];
 #pragma unroll
-  for (int j = 0; j < kTilePer; ++j) {
-    const int i = tid + j * kTileThreads;
-    r[j] = i < cnt ? lds_find(i, lp) : i;
+  for (int j2 = 0; j2 < kTilePer; ++j2) {
+    const int i = tid + j2 * kTileThreads;
+    r[j2] = i < cnt ? lds_find_tile(i, lp) : i;
   }
   __syncthreads();
+  // the degree prefix is done with: the sources of the hooking edges move out
+  // of the words into eu
 #pragma unroll
-  for (int j = 0; j < kTilePer; ++j) {
-    const int i = tid + j * kTileThreads;
-    if (i < cnt) lp[i] = (r[j] == i) ? -(i + 1) : r[j];
+  for (int j2 = 0; j2 < kTilePer; ++j2) {
+    const int i = tid + j2 * kTileThreads;
+    if (i < cnt) {
+      eu[i] = (int16_t)((lp[i] >> kTileShift) - 1);
+      lp[i] = (r[j2] == i) ? -(i + 1) : r[j2];
+    }
   }
   __syncthreads();
   // Only the first lane of a run of lanes with the same root does the atomic
   // (it holds the run's smallest id): on a mesh tile nearly every vertex has
   // the same root, and 8192 atomics on one LDS word serialise.
 #pragma unroll
-  for (int j = 0; j < kTilePer; ++j) {
-    const int i = tid + j * kTileThreads;
-    const int left = __shfl_up(r[j], 1, 64);
-    const bool first = (tid & 63) == 0 || left != r[j];
-    if (i < cnt && r[j] != i && first) atomicMax(&lp[r[j]], -(i + 1));
+  for (int j2 = 0; j2 < kTilePer; ++j2) {
+    const int i = tid + j2 * kTileThreads;
+    const int left = __shfl_up(r[j2], 1, 64);
+    const bool first = (tid & 63) == 0 || left != r[j2];
+    if (i < cnt && r[j2] != i && first) atomicMax(&lp[r[j2]], -(i + 1));
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTilePer; ++j) {
-    const int i = tid + j * kTileThreads;
-    if (i < cnt && r[j] == i) {
+  for (int j2 = 0; j2 < kTilePer; ++j2) {
+    const int i = tid + j2 * kTileThreads;
+    if (i < cnt && r[j2] == i) {
       const int m = -lp[i] - 1;
       if (m != i) {           // the old root takes the edge of the new one
         eu[i] = eu[m];
@@ -412,34 +458,37 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
     }
   }
   __syncthreads();
+  int ea[kTilePer], eb[kTilePer];
 #pragma unroll
-  for (int j = 0; j < kTilePer; ++j) {
-    const int i = tid + j * kTileThreads;
+  for (int j2 = 0; j2 < kTilePer; ++j2) {
+    const int i = tid + j2 * kTileThreads;
+    ea[j2] = -1;
+    eb[j2] = -1;
     if (i < cnt) {
-      const int m = -lp[r[j]] - 1;
+      const int m = -lp[r[j2]] - 1;
       cc[v0 + i] = (int32_t)(v0 + m);
-      const int a = eu[i];
-      tu[v0 + i] = a >= 0 ? (int32_t)(v0 + a) : -1;
-      tv[v0 + i] = a >= 0 ? (int32_t)(v0 + ev[i]) : -1;
+      ea[j2] = eu[i];
+      eb[j2] = ev[i];
+      tu[v0 + i] = ea[j2] >= 0 ? (int32_t)(v0 + ea[j2]) : -1;
+      tv[v0 + i] = ea[j2] >= 0 ? (int32_t)(v0 + eb[j2]) : -1;
     }
   }
   if (!head) return;
-  // Euler arc lists of the tile's own edges, built in LDS (the degree scan is
-  // no longer needed) and written once, coalesced: local arc 2i / 2i+1 of slot
-  // i is global arc 2(v0+i) / 2(v0+i)+1.
-  int *lhead = s_beg;                                   // [kTile] first local arc
-  int16_t *lnext = reinterpret_cast<int16_t *>(s_scan);  // [2 kTile] next local arc
+  // Euler arc lists of the tile's own edges, built in LDS and written once,
+  // coalesced: local arc 2i / 2i+1 of slot i is global arc 2(v0+i) / 2(v0+i)+1.
+  __syncthreads();                                      // lp, eu, ev read by all
+  int *lhead = lp;                                      // [kTile] first local arc
+  int16_t *lnext = s16;                                 // [2 kTile] next local arc
   for (int i = tid; i < kTile; i += kTileThreads) lhead[i] = -1;
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kTilePer; ++j) {
-    const int i = tid + j * kTileThreads;
+  for (int j2 = 0; j2 < kTilePer; ++j2) {
+    const int i = tid + j2 * kTileThreads;
     if (i < cnt) {
-      const int a = eu[i];
       int16_t n0 = -1, n1 = -1;
-      if (a >= 0) {
-        n0 = (int16_t)atomicExch(&lhead[a], 2 * i);
-        n1 = (int16_t)atomicExch(&lhead[ev[i]], 2 * i + 1);
+      if (ea[j2] >= 0) {
+        n0 = (int16_t)atomicExch(&lhead[ea[j2]], 2 * i);
+        n1 = (int16_t)atomicExch(&lhead[eb[j2]], 2 * i + 1);
       }
       lnext[2 * i] = n0;
       lnext[2 * i + 1] = n1;
@@ -448,8 +497,8 @@ __global__ __launch_bounds__(kTileThreads) void k_hook_tile(
   __syncthreads();
   const int32_t arc0 = (int32_t)(2 * v0);
 #pragma unroll
-  for (int j = 0; j < kTilePer; ++j) {
-    const int i = tid + j * kTileThreads;
+  for (int j2 = 0; j2 < kTilePer; ++j2) {
+    const int i = tid + j2 * kTileThreads;
     if (i < cnt) {
       const int h = lhead[i];
       head[v0 + i] = h >= 0 ? arc0 + h : -1;
@@ -928,7 +977,8 @@ rst_status enqueue_count_roots(rst_ctx *ctx, int64_t n, const int32_t *cc, int32
 }
 
 size_t hook_chunk_capacity(const rst_ctx *ctx, int64_t nnz) {
-  const int64_t heavy = ctx->opt.heavy_degree < 1 ? 1 : ctx->opt.heavy_degree;
+  int64_t heavy = ctx->opt.heavy_degree < 1 ? 1 : ctx->opt.heavy_degree;
+  if (heavy > kTileLightMax) heavy = kTileLightMax;   // the tile pass takes no larger degree
   return (size_t)(nnz / kChunk + nnz / (heavy + 1) + 2);
 }
 
