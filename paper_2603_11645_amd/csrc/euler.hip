@@ -255,65 +255,65 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
   for (int q = tid; q < kRankTile / 32; q += kRankThreads) haspred[q] = 0u;
   __syncthreads();
   // Thread t takes the twin pairs p = t + k * kRankThreads (arcs 2p and 2p+1
-  // of the tile), four pairs per half; the loads of a half are issued together.
+  // of the tile), four pairs per half; the loads of a half are issued
+  // together, then the end-of-list successors they need.
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    constexpr int H = kRankPer / 4;
-    uint64_t w[2 * H];
+    constexpr int P = kRankPer / 4;
+    int32_t t[2 * P];                 // successor of each arc, -1 at a tail
     if (kFromSlots) {
       // successor of a->b: next(b->a), or at the end of b's list endsucc[b]
-      int32_t dst[2 * H], sc[2 * H];
+      int32_t dst[2 * P];
 #pragma unroll
-      for (int k = 0; k < H; ++k) {
-        const int i0 = 2 * (tid + (h * H + k) * kRankThreads);
+      for (int k = 0; k < P; ++k) {
+        const int i0 = 2 * (tid + (h * P + k) * kRankThreads);
         dst[2 * k] = dst[2 * k + 1] = -1;
-        sc[2 * k] = sc[2 * k + 1] = -1;
+        t[2 * k] = t[2 * k + 1] = -1;
         if (i0 < cnt) {   // cnt is even here: a slot's two arcs share a tile
           const int64_t x = (e0 + i0) >> 1;
           const int32_t a = src.tu[x];
           const int32_t b = src.tv[x];
           const int2 nx = reinterpret_cast<const int2 *>(src.next)[x];
           if (a >= 0) {
-            dst[2 * k] = b;     sc[2 * k] = nx.y;       // 2x = a->b, rev = 2x+1
-            dst[2 * k + 1] = a; sc[2 * k + 1] = nx.x;   // 2x+1 = b->a, rev = 2x
+            dst[2 * k] = b;     t[2 * k] = nx.y;       // 2x = a->b, rev = 2x+1
+            dst[2 * k + 1] = a; t[2 * k + 1] = nx.x;   // 2x+1 = b->a, rev = 2x
           }
         }
       }
 #pragma unroll
-      for (int j = 0; j < 2 * H; ++j)
-        if (dst[j] >= 0 && sc[j] == -1) sc[j] = src.endsucc[dst[j]];
+      for (int q = 0; q < 2 * P; ++q)
+        if (dst[q] >= 0 && t[q] == -1) t[q] = src.endsucc[dst[q]];
 #pragma unroll
-      for (int j = 0; j < 2 * H; ++j) {
-        const int32_t t = dst[j] < 0 ? -1 : sc[j];
-        w[j] = pack_rank(t, t >= 0 ? 1u : 0u);
-      }
+      for (int q = 0; q < 2 * P; ++q)
+        if (dst[q] < 0) t[q] = -1;
     } else {
 #pragma unroll
-      for (int k = 0; k < H; ++k) {
-        const int i0 = 2 * (tid + (h * H + k) * kRankThreads);
-        w[2 * k] = w[2 * k + 1] = 0ull;
+      for (int k = 0; k < P; ++k) {
+        const int i0 = 2 * (tid + (h * P + k) * kRankThreads);
+        t[2 * k] = t[2 * k + 1] = -1;
         if (i0 + 1 < cnt) {
           const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(rank + e0)[i0 >> 1];
-          w[2 * k] = v.x; w[2 * k + 1] = v.y;
+          t[2 * k] = (int32_t)(uint32_t)v.x;
+          t[2 * k + 1] = (int32_t)(uint32_t)v.y;
         } else if (i0 < cnt) {
-          w[2 * k] = rank[e0 + i0];
+          t[2 * k] = (int32_t)(uint32_t)rank[e0 + i0];
         }
       }
     }
 #pragma unroll
-    for (int k = 0; k < H; ++k) {
-      const int i0 = 2 * (tid + (h * H + k) * kRankThreads);
+    for (int k = 0; k < P; ++k) {
+      const int i0 = 2 * (tid + (h * P + k) * kRankThreads);
       uint32_t lv[2];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        const int i = i0 + s;
+      for (int c = 0; c < 2; ++c) {
+        const int i = i0 + c;
         bool is_exit = false;
-        lv[s] = 0xffffu;
+        lv[c] = 0xffffu;
         if (i < cnt) {
-          const int32_t sc = (int32_t)(uint32_t)w[2 * k + s];
+          const int32_t sc = t[2 * k + c];
           const int64_t sl = (int64_t)sc - e0;
           if (sc >= 0 && sl >= 0 && sl < cnt) {
-            lv[s] = (uint32_t)sl;
+            lv[c] = (uint32_t)sl;
             atomicOr(&haspred[sl >> 5], 1u << (sl & 31));
           } else {
             is_exit = true;
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
         if (is_exit) {
           exits[e0 + slot] = (int32_t)(e0 + i);
           xid[e0 + i] = slot;
-          if (kFromSlots) rank[e0 + i] = w[2 * k + s];
+          if (kFromSlots) rank[e0 + i] = pack_rank(t[2 * k + c], t[2 * k + c] >= 0 ? 1u : 0u);
         }
       }
       if (i0 < cnt) *reinterpret_cast<uint32_t *>(&ls[i0]) = lv[0] | (lv[1] << 16);
@@ -334,12 +334,27 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
   __syncthreads();
   // strided rulers own slots 0..kStrided-1; heads off the stride get the next ones
   for (int q = tid; q < kStrided; q += kRankThreads) r_start[q] = (int16_t)(q * kRuler);
-#pragma unroll
-  for (int j = 0; j < kRankPer; ++j) {
-    const int i = tid + j * kRankThreads;
-    const bool head = i < cnt && (i % kRuler) != 0 && !((haspred[i >> 5] >> (i & 31)) & 1u);
-    const int x = wave_append(head, &s_extra);
-    if (head && kStrided + x < kMaxStatic) r_start[kStrided + x] = (int16_t)i;
+  {
+    // thread t < kRankTile / 32 reads word t of the has-predecessor bits:
+    // arcs of the tile without a predecessor, off the 8-stride
+    uint32_t hb = 0u;
+    if (tid < kRankTile / 32) {
+      const int b0 = tid * 32;
+      const uint32_t valid = b0 >= cnt ? 0u : (cnt - b0 >= 32 ? ~0u : (1u << (cnt - b0)) - 1u);
+      hb = ~haspred[tid] & valid & 0xFEFEFEFEu;
+    }
+    const int c = __popc(hb);
+    const int incl = wave_incl_scan(c);
+    const int wtot = __shfl(incl, 63, 64);
+    int base = 0;
+    if ((tid & 63) == 63 && wtot) base = atomicAdd(&s_extra, wtot);
+    int x = __shfl(base, 63, 64) + incl - c;
+    while (hb) {
+      const int bit = __ffs(hb) - 1;
+      hb &= hb - 1u;
+      if (kStrided + x < kMaxStatic) r_start[kStrided + x] = (int16_t)(tid * 32 + bit);
+      ++x;
+    }
   }
   __syncthreads();
   if (tid == 0) tile_exits[blockIdx.x] = s_nexit;
@@ -360,28 +375,32 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
       }
       if (__ballot(q >= 0) == 0ull) break;
       bool open = false;   // the piece reached kPiece arcs: continue as a new ruler
-      if (q >= 0) {
-        int fin = -2, ex = 0;   // -2 walking on, -1 ended at an exit, else the next ruler
-        if (j >= cnt) {
-          fin = -1;             // strided ruler past the end of a short tile
-        } else {
-          const int sj = ls[j];
-          if (sj < 0) {
-            fin = -1;
-            ex = j;
+      // two steps of the walk per round of the loop's wave-wide bookkeeping
+#pragma unroll
+      for (int rep = 0; rep < 2; ++rep) {
+        if (q >= 0 && !open) {
+          int fin = -2, ex = 0;   // -2 walking on, -1 ended at an exit, else the next ruler
+          if (j >= cnt) {
+            fin = -1;             // strided ruler past the end of a short tile
           } else {
-            ls[j] = (int16_t)((q << 4) | len);
-            j = sj & (kRankTile - 1);
-            ++len;
-            if ((j & (kRuler - 1)) == 0) fin = j / kRuler;
-            else if (len == kPiece) open = true;
+            const int sj = ls[j];
+            if (sj < 0) {
+              fin = -1;
+              ex = j;
+            } else {
+              ls[j] = (int16_t)((q << 4) | len);
+              j = sj & (kRankTile - 1);
+              ++len;
+              if ((j & (kRuler - 1)) == 0) fin = j / kRuler;
+              else if (len == kPiece) open = true;
+            }
           }
-        }
-        if (fin != -2) {
-          r_word[q] = fin < 0 ? (0x80000000u | ((uint32_t)q << 16) | (uint32_t)len)
-                              : (((uint32_t)fin << 16) | (uint32_t)len);
-          r_exit[q] = (int16_t)ex;
-          q = -1;
+          if (fin != -2) {
+            r_word[q] = fin < 0 ? (0x80000000u | ((uint32_t)q << 16) | (uint32_t)len)
+                                : (((uint32_t)fin << 16) | (uint32_t)len);
+            r_exit[q] = (int16_t)ex;
+            q = -1;
+          }
         }
       }
       const int d = wave_append(open, &s_ndyn);
@@ -605,12 +624,18 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
   __syncthreads();
   const int nstr = (m + kRuler - 1) / kRuler;
   for (int q = tid; q < nstr; q += kSmallThreads) r_start[q] = (int16_t)(q * kRuler);
-#pragma unroll
-  for (int k = 0; k < kSmallPer; ++k) {
-    const int i = tid + k * kSmallThreads;
-    const bool head = i < m && (i % kRuler) != 0 && !((haspred[i >> 5] >> (i & 31)) & 1u);
-    const int x = wave_append(head, &s_extra);
-    if (head && nstr + x < kSmallRulers) r_start[nstr + x] = (int16_t)i;
+  // list heads off the 8-stride, read 32 words at a time from the bits
+  for (int wd = tid; wd < (kSmallLds + 31) / 32; wd += kSmallThreads) {
+    const int b0 = wd * 32;
+    const uint32_t valid = b0 >= m ? 0u : (m - b0 >= 32 ? ~0u : (1u << (m - b0)) - 1u);
+    uint32_t hb = ~haspred[wd] & valid & 0xFEFEFEFEu;
+    int x = hb ? atomicAdd(&s_extra, __popc(hb)) : 0;
+    while (hb) {
+      const int bit = __ffs(hb) - 1;
+      hb &= hb - 1u;
+      if (nstr + x < kSmallRulers) r_start[nstr + x] = (int16_t)(b0 + bit);
+      ++x;
+    }
   }
   __syncthreads();
   const int nstatic = nstr + s_extra;
@@ -632,23 +657,27 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
       }
       if (__ballot(q >= 0) == 0ull) break;
       bool open = false;
-      if (q >= 0) {
-        const int t = sc[j];
-        const uint32_t wj = wt[j];
-        sc[j] = (int16_t)q;
-        wt[j] = acc;
-        if (t < 0) {                       // the tail: its ruler is the last of the chain
-          r_word[q] = kSmFinal | ((uint64_t)q << 32) | acc;
-          q = -1;
-        } else {
-          acc += wj;
-          j = t;
-          ++len;
-          if ((j & (kRuler - 1)) == 0) {
-            r_word[q] = ((uint64_t)(j / kRuler) << 32) | acc;
+      // two steps of the walk per round of the loop's wave-wide bookkeeping
+#pragma unroll
+      for (int rep = 0; rep < 2; ++rep) {
+        if (q >= 0 && !open) {
+          const int t = sc[j];
+          const uint32_t wj = wt[j];
+          sc[j] = (int16_t)q;
+          wt[j] = acc;
+          if (t < 0) {                       // the tail: its ruler is the last of the chain
+            r_word[q] = kSmFinal | ((uint64_t)q << 32) | acc;
             q = -1;
-          } else if (len == kSmallPiece) {
-            open = true;
+          } else {
+            acc += wj;
+            j = t;
+            ++len;
+            if ((j & (kRuler - 1)) == 0) {
+              r_word[q] = ((uint64_t)(j / kRuler) << 32) | acc;
+              q = -1;
+            } else if (len == kSmallPiece) {
+              open = true;
+            }
           }
         }
       }
