@@ -725,8 +725,14 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
                                    ? t0 + ((int64_t)1 << group_log) : (int64_t)tiles) : 0;
   int total;
   if (!all && counters[kCntCrossDone]) return;   // block-uniform
-  const int2 *list = kept_list + (all ? 0 : kLdsEdges);
-  if (kGroup) {
+  // a group block takes its edges from the list of all kept edges when that
+  // list is complete (it then filters by level and group), else from its
+  // tiles' regions of the cross list
+  const bool from_list = !kGroup || counters[kCntKept] <= kLdsEdges;
+  const int2 *list = kept_list + (all || kGroup ? 0 : kLdsEdges);
+  if (kGroup && from_list) {
+    total = counters[kCntKept];
+  } else if (kGroup) {
     const int64_t tb = t0 + tid;
     const int c = tb < t1 ? kept_count(tile_cross[tb]) : 0;
     const int ex = block_excl_scan<kTileThreads>(c, s_wave, &total);
@@ -745,7 +751,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
   const int32_t own_lo = kGroup ? (int32_t)(t0 << kTileShift) : 0;
   const int32_t own_hi = kGroup ? (int32_t)((t1 << kTileShift) - 1) : 0x7fffffff;
   auto edge_at = [&](int g) -> int2 {
-    if (!kGroup) return list[g];
+    if (from_list) return list[g];
     const int k = lds_upper_search(s_pref, kTileThreads, g);
     return cross[region_of[t0 + k] + (g - s_pref[k])];
   };
@@ -767,7 +773,9 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
       if (g < total) {
         const int2 x = edge_at(g);
         const int lv = cross_level(x.x, x.y);
-        if (lv >= lo && lv < hi) e[j] = x;
+        // (a group block reading the full list keeps its own group's edges)
+        if (lv >= lo && lv < hi && (!kGroup || !from_list || (x.x >> (kTileShift + group_log)) == (int32_t)blockIdx.x))
+          e[j] = x;
       }
     }
 #pragma unroll
@@ -801,15 +809,15 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
     if (tid == 0 && !all) counters[kCntCrossOverflow] = 1;
     return;
   }
-  for (int l = lo; l < hi; ++l) {
+  // all levels in one pass: in LDS the order of the unions only changes
+  // which spanning edges are chosen, and path halving keeps the finds short
 #pragma unroll
-    for (int k = 0; k < kLdsPer; ++k) {
-      const uint32_t v = sab[k];
-      if (v != ~0u && (int)(v >> 28) == l)
-        lds_union((int)(v & 0x3fff), (int)((v >> 14) & 0x3fff), tid + k * kTileThreads, keys, par);
-    }
-    __syncthreads();
+  for (int k = 0; k < kLdsPer; ++k) {
+    const uint32_t v = sab[k];
+    if (v != ~0u)
+      lds_union((int)(v & 0x3fff), (int)((v >> 14) & 0x3fff), tid + k * kTileThreads, keys, par);
   }
+  __syncthreads();
   // Every hooked root points straight at its final root and records the kept
   // edge that hooked it.  The hooked slots are few and scattered over the
   // table: they are gathered into a compact list first (in the par region,
