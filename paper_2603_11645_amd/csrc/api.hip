@@ -476,8 +476,7 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
     key.n = g->n; key.nnz = g->nnz; key.offset_bytes = g->offset_bytes; key.root = root;
     key.opt = ctx->opt;
     RST_TRY(run_graph(ctx, key, [&]() -> rst_status {
-      RST_TRY(enqueue_fill(ctx, counters, 32, 0));
-      RST_TRY(enqueue_fill(ctx, rootbuf, 1, root));
+      RST_TRY(enqueue_reset_counters(ctx, counters, root));
       return enqueue_gconn(ctx, g, rootbuf, 1, parent, nullptr, w);
     }));
     int64_t comps = 0;
@@ -485,8 +484,7 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
     return comps > 1 ? RST_E_DISCONNECTED : RST_OK;
   }
 
-  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
-  RST_TRY(enqueue_fill(ctx, rootbuf, 1, root));
+  RST_TRY(enqueue_reset_counters(ctx, counters, root));
   RST_TRY(run_validation(ctx, g, counters));
 
   if (method == RST_GCONN_EULER) {
@@ -641,8 +639,7 @@ rst_status rst_bfs(rst_ctx *ctx, const rst_csr *g, int32_t root, int32_t *level,
   RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + bfs_ws_bytes(ctx, g)));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
   int32_t *rootbuf = counters + 32;
-  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
-  RST_TRY(enqueue_fill(ctx, rootbuf, 1, root));
+  RST_TRY(enqueue_reset_counters(ctx, counters, root));
   RST_TRY(run_validation(ctx, g, counters));
   BfsBufs b;
   RST_TRY(take_bfs_bufs(ctx, g, b));

@@ -83,6 +83,13 @@ __device__ __forceinline__ void hook_edge(int32_t u, int32_t v, int32_t *cc, int
 // kernels
 // ---------------------------------------------------------------------------
 
+// counters[0..31] = 0 and counters[32] = root (the one-root buffer) in one launch
+__global__ void k_reset_counters(int32_t *counters, int32_t root) {
+  const int i = threadIdx.x;
+  if (i < 32) counters[i] = 0;
+  else if (i == 32) counters[32] = root;
+}
+
 __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = value;
@@ -407,6 +414,7 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
       counters[kCntKeptTop] = 0;
       counters[kCntCrossDone] = 0;
       counters[kCntCrossOverflow] = 0;
+      counters[kCntMergeDone] = 0;
     }
     region_of[blockIdx.x] = region;
     tile_cross[blockIdx.x] = s_ncross;
@@ -698,20 +706,19 @@ __device__ __forceinline__ uint32_t pack_sab(int sa, int sb, int level) {
 // One-workgroup LDS merge of the kept cross edges of levels [lo, hi).
 // kGroup: block g takes the tiles [g << group_log, (g + 1) << group_log) and
 // their kept edges below hi (their roots must lie in the group's vertex range,
-// else the block raises the flag and changes nothing).  Otherwise one block
-// takes a compact list: with `all`, the list of every kept edge (levels
-// [0, hi)) if it holds at most kAllEdges; when that succeeds it sets
-// counters[kCntCrossDone] and the group and top-level merges return at once,
-// otherwise it changes nothing and leaves them to run.  Without `all`, the
-// list of the edges of the top levels.
+// else the block raises the flag and changes nothing) -- unless there are at
+// most kAllEdges kept edges: then block 0 alone takes all of them, levels
+// [0, all_hi), sets counters[kCntCrossDone] so that the top-level merge
+// returns at once, and raises the flag if they do not fit.  Otherwise (one
+// block) the compact list of the edges of the top levels.
 template <bool kGroup>
 __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__restrict__ region_of,
                                                             const int2 *__restrict__ cross,
                                                             const int32_t *__restrict__ tile_cross,
                                                             const int2 *__restrict__ kept_list,
                                                             int tiles, int lo, int hi,
-                                                            int group_log, int all, int32_t *cc,
-                                                            int32_t *tu, int32_t *tv,
+                                                            int group_log, int all_hi,
+                                                            int32_t *cc, int32_t *tu, int32_t *tv,
                                                             int32_t *counters, int32_t *head,
                                                             int32_t *next) {
   __shared__ int32_t keys[kLdsSlots];   // global root held by a slot, -1: empty
@@ -720,36 +727,41 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
   __shared__ int s_wave[kTileThreads / kWave];
   __shared__ int s_fail, s_nrec;
   const int tid = threadIdx.x;
-  const int64_t t0 = kGroup ? ((int64_t)blockIdx.x << group_log) : 0;
-  const int64_t t1 = kGroup ? ((t0 + ((int64_t)1 << group_log)) < tiles
-                                   ? t0 + ((int64_t)1 << group_log) : (int64_t)tiles) : 0;
+  // every branch below is block-uniform
+  const bool all = kGroup && counters[kCntKept] <= kAllEdges;
+  if (all && blockIdx.x != 0) return;
+  if (!kGroup && counters[kCntCrossDone]) return;
+  const bool grp = kGroup && !all;
+  if (all) { lo = 0; hi = all_hi; }
+  const int64_t t0 = grp ? ((int64_t)blockIdx.x << group_log) : 0;
+  const int64_t t1 = grp ? ((t0 + ((int64_t)1 << group_log)) < tiles
+                                ? t0 + ((int64_t)1 << group_log) : (int64_t)tiles) : 0;
   int total;
-  if (!all && counters[kCntCrossDone]) return;   // block-uniform
   // a group block takes its edges from the list of all kept edges when that
   // list is complete (it then filters by level and group), else from its
   // tiles' regions of the cross list
-  const bool from_list = !kGroup || counters[kCntKept] <= kLdsEdges;
-  const int2 *list = kept_list + (all || kGroup ? 0 : kLdsEdges);
-  if (kGroup && from_list) {
+  const bool from_list = !grp || counters[kCntKept] <= kLdsEdges;
+  const int2 *list = kept_list + (kGroup ? 0 : kLdsEdges);
+  if (all || (grp && from_list)) {
     total = counters[kCntKept];
-  } else if (kGroup) {
+  } else if (grp) {
     const int64_t tb = t0 + tid;
     const int c = tb < t1 ? kept_count(tile_cross[tb]) : 0;
     const int ex = block_excl_scan<kTileThreads>(c, s_wave, &total);
     s_pref[tid] = ex;
   } else {
-    total = counters[all ? kCntKept : kCntKeptTop];
+    total = counters[kCntKeptTop];
   }
-  if (total > (all ? kAllEdges : kLdsEdges) || hi >= 15) {
-    if (tid == 0 && !all) counters[kCntCrossOverflow] = 1;
+  if (total > kLdsEdges) {
+    if (tid == 0) counters[kCntCrossOverflow] = 1;
     return;
   }
   if (total == 0) return;
   for (int i = tid; i < kLdsSlots; i += kTileThreads) { keys[i] = -1; par[i] = i; }
   if (tid == 0) { s_fail = 0; s_nrec = 0; }
   __syncthreads();
-  const int32_t own_lo = kGroup ? (int32_t)(t0 << kTileShift) : 0;
-  const int32_t own_hi = kGroup ? (int32_t)((t1 << kTileShift) - 1) : 0x7fffffff;
+  const int32_t own_lo = grp ? (int32_t)(t0 << kTileShift) : 0;
+  const int32_t own_hi = grp ? (int32_t)((t1 << kTileShift) - 1) : 0x7fffffff;
   auto edge_at = [&](int g) -> int2 {
     if (from_list) return list[g];
     const int k = lds_upper_search(s_pref, kTileThreads, g);
@@ -774,7 +786,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
         const int2 x = edge_at(g);
         const int lv = cross_level(x.x, x.y);
         // (a group block reading the full list keeps its own group's edges)
-        if (lv >= lo && lv < hi && (!kGroup || !from_list || (x.x >> (kTileShift + group_log)) == (int32_t)blockIdx.x))
+        if (lv >= lo && lv < hi && (!grp || !from_list || (x.x >> (kTileShift + group_log)) == (int32_t)blockIdx.x))
           e[j] = x;
       }
     }
@@ -799,14 +811,14 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
         } else if (ra != rb) {
           const int sa = lds_slot(ra, keys), sb = lds_slot(rb, keys);
           if (sa < 0 || sb < 0) s_fail = 1;
-          else sab[k0 + j] = pack_sab(sa, sb, cross_level(e[j].x, e[j].y));
+          else sab[k0 + j] = pack_sab(sa, sb, 0);
         }
       }
     }
   }
   __syncthreads();
   if (s_fail) {
-    if (tid == 0 && !all) counters[kCntCrossOverflow] = 1;
+    if (tid == 0) counters[kCntCrossOverflow] = 1;
     return;
   }
   // all levels in one pass: in LDS the order of the unions only changes
@@ -862,29 +874,19 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
     for (int k = 0; k < kSlotsPer; ++k)
       if (hk_g[k] >= 0) finish(hk_key[k], hk_root[k], hk_g[k]);
   }
-  if (all && tid == 0) counters[kCntCrossDone] = 1;
+  if (all && tid == 0) counters[kCntCrossDone] = 1;   // (visible to the next kernel)
   wave_release_device();
 }
 
-// Fallback of k_cross_lds (runs only when it raised its flag): hook the kept
-// cross edges of levels [lo, hi) of the tiles of group blockIdx.x
-// (2^group_log consecutive tiles) in global memory, one level after another.
-__global__ __launch_bounds__(kTileThreads) void k_cross_merge(const int64_t *__restrict__ region_of,
-                                                              const int2 *__restrict__ cross,
-                                                              const int32_t *__restrict__ tile_cross,
-                                                              const int32_t *__restrict__ tile_lvl,
-                                                              int tiles, int lo, int hi,
-                                                              int group_log, int32_t *cc,
-                                                              int32_t *tu, int32_t *tv,
-                                                              const int32_t *counters,
-                                                              int32_t *head, int32_t *next) {
-  __shared__ int s_scan[kTileThreads + 1];
-  __shared__ int s_wave[kTileThreads / kWave];
-  if (counters[kCntCrossOverflow] == 0) return;   // block-uniform
+// Hook the kept cross edges of levels [lo, hi) of tiles [t0, t1) in global
+// memory, one level after another (the fallback of the LDS merges).  Called
+// by every thread of the block.
+__device__ void merge_levels(int64_t t0, int64_t t1, int lo, int hi,
+                             const int64_t *__restrict__ region_of, const int2 *__restrict__ cross,
+                             const int32_t *__restrict__ tile_cross,
+                             const int32_t *__restrict__ tile_lvl, int32_t *cc, int32_t *tu,
+                             int32_t *tv, int32_t *head, int32_t *next, int *s_scan, int *s_wave) {
   const int tid = threadIdx.x;
-  const int64_t t0 = (int64_t)blockIdx.x << group_log;
-  const int64_t t1 = (t0 + ((int64_t)1 << group_log)) < tiles ? t0 + ((int64_t)1 << group_log)
-                                                                : (int64_t)tiles;
   for (int l = lo; l < hi; ++l) {
     for (int64_t base = t0; base < t1; base += kTileThreads) {
       const int64_t tb = base + tid;
@@ -906,32 +908,60 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_merge(const int64_t *__r
       __syncthreads();
     }
   }
-  wave_release_device();
 }
 
-// Heavy-vertex chunks, grid-strided over the chunk list.
+// Global-memory hooking after the LDS merges, in one launch.  Blocks
+// [0, groups): only when an LDS merge raised the flag, the fallback merge of
+// the levels [0, split) of group blockIdx.x (2^split tiles); the last of them
+// to finish then takes the levels [split, levels) of all tiles.  Blocks
+// [groups, gridDim.x): the heavy-vertex chunks, grid-strided.  Both hook by
+// compare-and-swap, so they may run side by side.
 template <class OffT>
-__global__ __launch_bounds__(kBlock) void k_hook_heavy(const OffT *__restrict__ off,
-                                                       const int32_t *__restrict__ cols,
-                                                       int32_t *cc, int32_t *tu, int32_t *tv,
-                                                       const int64_t *chunks, int64_t chunk_cap,
-                                                       const int32_t *counters, int32_t *head,
-                                                       int32_t *next) {
+__global__ __launch_bounds__(kTileThreads) void k_late_hooks(
+    const int64_t *__restrict__ region_of, const int2 *__restrict__ cross,
+    const int32_t *__restrict__ tile_cross, const int32_t *__restrict__ tile_lvl, int tiles,
+    int groups, int split, int levels, const OffT *__restrict__ off,
+    const int32_t *__restrict__ cols, const int64_t *chunks, int64_t chunk_cap, int32_t *cc,
+    int32_t *tu, int32_t *tv, int32_t *counters, int32_t *head, int32_t *next) {
+  __shared__ int s_scan[kTileThreads + 1];
+  __shared__ int s_wave[kTileThreads / kWave];
+  __shared__ int s_last;
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.x < groups) {
+    if (counters[kCntCrossOverflow] == 0) return;   // block-uniform
+    const int64_t t0 = (int64_t)blockIdx.x << split;
+    const int64_t t1 = (t0 + ((int64_t)1 << split)) < tiles ? t0 + ((int64_t)1 << split)
+                                                            : (int64_t)tiles;
+    merge_levels(t0, t1, 0, split, region_of, cross, tile_cross, tile_lvl, cc, tu, tv, head, next,
+                 s_scan, s_wave);
+    wave_release_device();
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&counters[kCntMergeDone], 1) == groups - 1;
+    __syncthreads();
+    if (!s_last) return;
+    // every group's hooks are released before its count: see them, then merge on
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    merge_levels(0, tiles, split, levels, region_of, cross, tile_cross, tile_lvl, cc, tu, tv, head,
+                 next, s_scan, s_wave);
+    wave_release_device();
+    return;
+  }
   int64_t nc = counters[kCntChunks];
   if (nc > chunk_cap) nc = chunk_cap;
-  for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
+  const int64_t hb = (int64_t)blockIdx.x - groups, nhb = (int64_t)gridDim.x - groups;
+  for (int64_t c = hb; c < nc; c += nhb) {
     const int64_t w = chunks[c];
     const int32_t src = (int32_t)(w >> 32);
     const int64_t k = w & 0xffffffffll;
     const int64_t b = (int64_t)off[src] + k * kChunk;
     int64_t e = (int64_t)off[src + 1];
     if (e > b + kChunk) e = b + kChunk;
-    for (int64_t a = b + threadIdx.x; a < e; a += kBlock) {
+    for (int64_t a = b + tid; a < e; a += kTileThreads) {
       const int32_t dst = cols[a];
       if (dst < src) hook_edge<true>(src, dst, cc, tu, tv, head, next);
     }
   }
-  if (blockIdx.x < nc) wave_release_device();   // only blocks that hooked
+  if (hb < nc) wave_release_device();   // only blocks that hooked
 }
 
 // Edge-list hooking without recording (labels of a given forest).
@@ -990,6 +1020,12 @@ size_t hook_chunk_capacity(const rst_ctx *ctx, int64_t nnz) {
   return (size_t)(nnz / kChunk + nnz / (heavy + 1) + 2);
 }
 
+rst_status enqueue_reset_counters(rst_ctx *ctx, int32_t *counters, int32_t root) {
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, ctx->stream, counters, root);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
 rst_status enqueue_fill(rst_ctx *ctx, int32_t *p, int64_t count, int32_t value) {
   if (count <= 0) return RST_OK;
   hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(count, kBlock)), dim3(kBlock), 0, ctx->stream,
@@ -1044,33 +1080,38 @@ static rst_status launch_cross(rst_ctx *ctx, unsigned tiles, int levels,
   RST_HIP(hipGetLastError());
   const unsigned groups = (tiles + (1u << split) - 1) >> split;
   if (split > 0) {
-    // all levels at once when every kept edge fits one workgroup; else (it
-    // changes nothing then) per group below `split` and one block above
-    hipLaunchKernelGGL(k_cross_lds<false>, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of,
-                       cross, tile_cross, kept_list, (int)tiles, 0, levels, levels, 1, f.cc, f.tu,
-                       f.tv, f.counters, f.head, f.next);
-    RST_HIP(hipGetLastError());
+    // per group of 2^split tiles below `split` (or, with few kept edges, all
+    // levels in block 0), then one block for the levels above
     hipLaunchKernelGGL(k_cross_lds<true>, dim3(groups), dim3(kTileThreads), 0, ctx->stream,
-                       region_of, cross, tile_cross, kept_list, (int)tiles, 0, split, split, 0,
-                       f.cc, f.tu, f.tv, f.counters, f.head, f.next);
+                       region_of, cross, tile_cross, kept_list, (int)tiles, 0, split, split,
+                       levels, f.cc, f.tu, f.tv, f.counters, f.head, f.next);
     RST_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_cross_lds<false>, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of,
-                     cross, tile_cross, kept_list, (int)tiles, split, levels, levels, 0, f.cc, f.tu,
-                     f.tv, f.counters, f.head, f.next);
-  RST_HIP(hipGetLastError());
-  // global-memory fallback, active only when a merge above raised the flag
-  if (split > 0) {
-    hipLaunchKernelGGL(k_cross_merge, dim3(groups), dim3(kTileThreads), 0, ctx->stream, region_of,
-                       cross, tile_cross, tile_lvl, (int)tiles, 0, split, split, f.cc, f.tu, f.tv,
-                       f.counters, f.head, f.next);
-    RST_HIP(hipGetLastError());
-  }
-  hipLaunchKernelGGL(k_cross_merge, dim3(1), dim3(kTileThreads), 0, ctx->stream, region_of, cross,
-                     tile_cross, tile_lvl, (int)tiles, split, levels, levels, f.cc, f.tu, f.tv,
-                     f.counters, f.head, f.next);
+                     cross, tile_cross, kept_list, (int)tiles, split, levels, levels, levels, f.cc,
+                     f.tu, f.tv, f.counters, f.head, f.next);
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_CROSS, 1);
+  return RST_OK;
+}
+
+// The global-memory fallback of the cross merges (active only when an LDS
+// merge raised its flag) and the heavy chunks, in one launch.
+template <class OffT>
+static rst_status launch_late_hooks(rst_ctx *ctx, unsigned tiles, int levels,
+                                    const int64_t *region_of, const int2 *cross,
+                                    const int32_t *tile_cross, const int32_t *tile_lvl,
+                                    const OffT *off, const int32_t *cols, const int64_t *chunks,
+                                    int64_t chunk_cap, ForestBufs &f) {
+  int split = levels <= 3 ? 0 : levels / 2;
+  if (split > 10) split = 10;
+  if (split == 0) split = levels;   // one group of all tiles takes every level
+  const int groups = levels == 0 ? 0 : (int)((tiles + (1u << split) - 1) >> split);
+  const unsigned grid = (unsigned)groups + (unsigned)(ctx->num_cus * 2);
+  hipLaunchKernelGGL(k_late_hooks<OffT>, dim3(grid), dim3(kTileThreads), 0, ctx->stream, region_of,
+                     cross, tile_cross, tile_lvl, (int)tiles, groups, split, levels, off, cols,
+                     chunks, chunk_cap, f.cc, f.tu, f.tv, f.counters, f.head, f.next);
+  RST_HIP(hipGetLastError());
   return RST_OK;
 }
 
@@ -1082,7 +1123,6 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
   int2 *kept_list = reinterpret_cast<int2 *>(tile_lvl + ((tc + 1) & ~size_t(1)));
   const int64_t n = g->n;
   const unsigned tiles = grid_for(n, kTile);
-  const unsigned heavy_grid = (unsigned)(ctx->num_cus * 8);
   const int vec_cols = ((uintptr_t)g->cols & 15) == 0;   // 16-byte loads of cols allowed
   int levels = 0;
   while ((1u << levels) < tiles) ++levels;
@@ -1096,9 +1136,8 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));
-    hipLaunchKernelGGL(k_hook_heavy<int32_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream, off,
-                       g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters, f.head,
-                       f.next);
+    RST_TRY(launch_late_hooks(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, off,
+                              g->cols, chunks, chunk_cap, f));
   } else {
     const int64_t *off = (const int64_t *)g->offsets;
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 0);
@@ -1109,9 +1148,8 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));
-    hipLaunchKernelGGL(k_hook_heavy<int64_t>, dim3(heavy_grid), dim3(kBlock), 0, ctx->stream, off,
-                       g->cols, f.cc, f.tu, f.tv, chunks, chunk_cap, f.counters, f.head,
-                       f.next);
+    RST_TRY(launch_late_hooks(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, off,
+                              g->cols, chunks, chunk_cap, f));
   }
   RST_HIP(hipGetLastError());
   return RST_OK;

@@ -139,7 +139,7 @@ struct ForestBufs {
   int32_t *cc;         // [n] union-find parents -> min-id labels
   int32_t *tu, *tv;    // [slots] recorded spanning edge per slot, -1 = empty
   int32_t *comp_root;  // [n] designated root of the component labelled v, or -1
-  int32_t *counters;   // [16] device counters (see kCnt*)
+  int32_t *counters;   // [64] device counters (see kCnt*)
   const uint8_t *vmask = nullptr;   // [n] nonzero: vertex excluded from hooking (nullable)
   // Euler arc lists built while hooking (nullable): every recorded edge of
   // slot x = (a, b) gives arcs 2x = a->b and 2x+1 = b->a, each put in front of
@@ -166,11 +166,14 @@ enum {
   kCntKept = 13,           // cross edges kept by the deduplication pass
   kCntKeptTop = 14,        // of those, the edges of the levels merged by the top pass
   kCntCrossDone = 15,      // the one-block merge of all kept edges succeeded
-  kCntTotal = 16
+  kCntTotal = 16,          // counters read back after a call (the ones above)
+  kCntMergeDone = 16,      // group blocks done with the global-memory merge fallback
 };
 
 // hook.hip
 rst_status enqueue_fill(rst_ctx *ctx, int32_t *p, int64_t count, int32_t value);
+// counters[0..31] = 0, counters[32] = root (the one-root buffer that follows them)
+rst_status enqueue_reset_counters(rst_ctx *ctx, int32_t *counters, int32_t root);
 rst_status enqueue_validate(rst_ctx *ctx, const rst_csr *g, int32_t *counters);
 // cross: int2 [hook_cross_capacity], tile_cross: int32 [hook_tile_words], 8-byte aligned
 rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64_t *chunks,
