@@ -367,24 +367,33 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
     }
   } else {
     // heavy or masked vertices: arc k of vertex j is cols[off[v0 + j] + k -
-    // scan_at(j)]; the owners of U arcs, then their offsets, then their ids
-    // are fetched U at a time before any hooking
+    // scan_at(j)].  The thread keeps the offset of its current vertex and has
+    // the next one's in flight, so a batch of U arcs costs one round trip
+    // unless the walk passes several vertices in it.
     constexpr int U = 4;
+    int cur_start = scan_at(j);
+    int64_t ob_cur = (int64_t)off[v0 + j];
+    int64_t ob_next = (int64_t)off[v0 + j + 1];   // j < cnt, so v0 + j + 1 <= n
     for (int kb = k_begin; kb < k_begin + share; kb += U) {
       int sl[U];
+      int64_t ci[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = kb + u;
         sl[u] = -1;
+        ci[u] = 0;
         if (k < k_end) {
-          while (next_start <= k) next_start = scan_at(++j + 1);
+          if (next_start <= k) {
+            int jn = j;
+            while (next_start <= k) { cur_start = next_start; next_start = scan_at(++jn + 1); }
+            ob_cur = jn == j + 1 ? ob_next : (int64_t)off[v0 + jn];
+            j = jn;
+            ob_next = (int64_t)off[v0 + j + 1];
+          }
           sl[u] = j;
+          ci[u] = ob_cur + (k - cur_start);
         }
       }
-      int64_t ci[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        ci[u] = sl[u] >= 0 ? (int64_t)off[v0 + sl[u]] + (kb + u - scan_at(sl[u])) : 0;
       int32_t dst[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) dst[u] = sl[u] >= 0 ? cols[ci[u]] : 0;
@@ -414,7 +423,6 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
       counters[kCntKeptTop] = 0;
       counters[kCntCrossDone] = 0;
       counters[kCntCrossOverflow] = 0;
-      counters[kCntMergeDone] = 0;
     }
     region_of[blockIdx.x] = region;
     tile_cross[blockIdx.x] = s_ncross;
@@ -528,18 +536,16 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
 //     kFlatCross cross edges has no locality to exploit: its edges are hooked
 //     right there (split over several blocks) and tile_cross[b] keeps its
 //     original value, which marks the tile as done for the later steps.
-//  2. k_cross_lds: one block takes all kept edges, maps the roots they join
-//     into LDS and runs the union-find there, level by level over the binary
-//     tree of tiles (cross_level), then writes the links back.  If there are
-//     too many kept edges or roots for one block, it changes nothing, and the
-//     levels below `split` are merged the same way by one block per group of
-//     2^split tiles, the rest by one block from a list of their edges; if
-//     those do not fit either, they raise a flag.
-//  3. Only when flagged, k_cross_merge does the same in global memory: the
-//     levels below `split` join tiles of one group of 2^split tiles and run in
-//     one launch with a block per group; the remaining levels run in one block.
-// Merging level by level keeps the id-ordered trees at most about one hop
-// deeper per level.  A key read while another tile hooks may already be an
+//  2. k_cross_lds: the levels of the binary tree of tiles (cross_level) below
+//     `split` are merged by one block per group of 2^split tiles, the rest by
+//     one block from a list of their edges: a block maps the roots its kept
+//     edges join into LDS, runs the union-find there and writes the links
+//     back.  With few kept edges, one block takes all levels.  A block whose
+//     edges or roots do not fit changes nothing and raises a flag.
+//  3. Only when flagged, k_late_hooks hooks every kept edge in global memory
+//     by compare-and-swap, spread over the whole grid.
+// Splitting by levels keeps each group's roots inside its own tiles, so the
+// group merges are independent.  A key read while another tile hooks may already be an
 // ancestor of the local root rather than the root itself: both name a vertex
 // of the same current tree, so dropping an edge with an equal key never loses
 // connectivity.
@@ -878,78 +884,38 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
   wave_release_device();
 }
 
-// Hook the kept cross edges of levels [lo, hi) of tiles [t0, t1) in global
-// memory, one level after another (the fallback of the LDS merges).  Called
-// by every thread of the block.
-__device__ void merge_levels(int64_t t0, int64_t t1, int lo, int hi,
-                             const int64_t *__restrict__ region_of, const int2 *__restrict__ cross,
-                             const int32_t *__restrict__ tile_cross,
-                             const int32_t *__restrict__ tile_lvl, int32_t *cc, int32_t *tu,
-                             int32_t *tv, int32_t *head, int32_t *next, int *s_scan, int *s_wave) {
-  const int tid = threadIdx.x;
-  for (int l = lo; l < hi; ++l) {
-    for (int64_t base = t0; base < t1; base += kTileThreads) {
-      const int64_t tb = base + tid;
-      int c = 0;
-      if (tb < t1) {
-        const int lr = tile_lvl[tb];
-        if (l >= (lr >> 8) && l <= (lr & 0xff)) c = kept_count(tile_cross[tb]);
-      }
-      int total;
-      const int ex = block_excl_scan<kTileThreads>(c, s_wave, &total);
-      s_scan[tid] = ex;
-      if (tid == kTileThreads - 1) s_scan[kTileThreads] = total;
-      __syncthreads();
-      for (int idx = tid; idx < total; idx += kTileThreads) {
-        const int k = lds_upper_search(s_scan, kTileThreads, idx);
-        const int2 e = cross[region_of[base + k] + (idx - s_scan[k])];
-        if (cross_level(e.x, e.y) == l) hook_edge<true>(e.x, e.y, cc, tu, tv, head, next);
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Global-memory hooking after the LDS merges, in one launch.  Blocks
-// [0, groups): only when an LDS merge raised the flag, the fallback merge of
-// the levels [0, split) of group blockIdx.x (2^split tiles); the last of them
-// to finish then takes the levels [split, levels) of all tiles.  Blocks
-// [groups, gridDim.x): the heavy-vertex chunks, grid-strided.  Both hook by
-// compare-and-swap, so they may run side by side.
+// Global-memory hooking after the LDS merges, in one launch.  Only when an LDS
+// merge raised the flag (its kept edges or roots did not fit), every kept
+// cross edge is hooked here by compare-and-swap, the tiles' kept edges spread
+// over the whole grid in no particular order (hooking is correct in any order;
+// on the graphs that get here -- ids without locality, millions of kept edges
+// -- one workgroup per level or group would serialise the work).  The heavy-
+// vertex chunks are hooked by the same grid, side by side.
 template <class OffT>
 __global__ __launch_bounds__(kTileThreads) void k_late_hooks(
     const int64_t *__restrict__ region_of, const int2 *__restrict__ cross,
-    const int32_t *__restrict__ tile_cross, const int32_t *__restrict__ tile_lvl, int tiles,
-    int groups, int split, int levels, const OffT *__restrict__ off,
+    const int32_t *__restrict__ tile_cross, int tiles, int slices, const OffT *__restrict__ off,
     const int32_t *__restrict__ cols, const int64_t *chunks, int64_t chunk_cap, int32_t *cc,
     int32_t *tu, int32_t *tv, int32_t *counters, int32_t *head, int32_t *next) {
-  __shared__ int s_scan[kTileThreads + 1];
-  __shared__ int s_wave[kTileThreads / kWave];
-  __shared__ int s_last;
   const int tid = threadIdx.x;
-  if ((int)blockIdx.x < groups) {
-    if (counters[kCntCrossOverflow] == 0) return;   // block-uniform
-    const int64_t t0 = (int64_t)blockIdx.x << split;
-    const int64_t t1 = (t0 + ((int64_t)1 << split)) < tiles ? t0 + ((int64_t)1 << split)
-                                                            : (int64_t)tiles;
-    merge_levels(t0, t1, 0, split, region_of, cross, tile_cross, tile_lvl, cc, tu, tv, head, next,
-                 s_scan, s_wave);
-    wave_release_device();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&counters[kCntMergeDone], 1) == groups - 1;
-    __syncthreads();
-    if (!s_last) return;
-    // every group's hooks are released before its count: see them, then merge on
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    merge_levels(0, tiles, split, levels, region_of, cross, tile_cross, tile_lvl, cc, tu, tv, head,
-                 next, s_scan, s_wave);
-    wave_release_device();
-    return;
+  bool hooked = false;
+  if (counters[kCntCrossOverflow]) {   // block-uniform
+    // tile b's kept edges by blocks b*slices .. (b+1)*slices-1 (mod the grid)
+    for (int64_t w = blockIdx.x; w < (int64_t)tiles * slices; w += gridDim.x) {
+      const int64_t b = w / slices;
+      const int part = (int)(w % slices);
+      const int kept = kept_count(tile_cross[b]);
+      const int64_t region = region_of[b];
+      for (int i = part * kTileThreads + tid; i < kept; i += slices * kTileThreads) {
+        const int2 e = cross[region + i];
+        hook_edge<true>(e.x, e.y, cc, tu, tv, head, next);
+      }
+      hooked = true;
+    }
   }
   int64_t nc = counters[kCntChunks];
   if (nc > chunk_cap) nc = chunk_cap;
-  const int64_t hb = (int64_t)blockIdx.x - groups, nhb = (int64_t)gridDim.x - groups;
-  for (int64_t c = hb; c < nc; c += nhb) {
+  for (int64_t c = blockIdx.x; c < nc; c += gridDim.x) {
     const int64_t w = chunks[c];
     const int32_t src = (int32_t)(w >> 32);
     const int64_t k = w & 0xffffffffll;
@@ -960,8 +926,9 @@ __global__ __launch_bounds__(kTileThreads) void k_late_hooks(
       const int32_t dst = cols[a];
       if (dst < src) hook_edge<true>(src, dst, cc, tu, tv, head, next);
     }
+    hooked = true;
   }
-  if (hb < nc) wave_release_device();   // only blocks that hooked
+  if (hooked) wave_release_device();   // block-uniform: only blocks that hooked
 }
 
 // Edge-list hooking without recording (labels of a given forest).
@@ -1100,17 +1067,15 @@ static rst_status launch_cross(rst_ctx *ctx, unsigned tiles, int levels,
 template <class OffT>
 static rst_status launch_late_hooks(rst_ctx *ctx, unsigned tiles, int levels,
                                     const int64_t *region_of, const int2 *cross,
-                                    const int32_t *tile_cross, const int32_t *tile_lvl,
-                                    const OffT *off, const int32_t *cols, const int64_t *chunks,
-                                    int64_t chunk_cap, ForestBufs &f) {
-  int split = levels <= 3 ? 0 : levels / 2;
-  if (split > 10) split = 10;
-  if (split == 0) split = levels;   // one group of all tiles takes every level
-  const int groups = levels == 0 ? 0 : (int)((tiles + (1u << split) - 1) >> split);
-  const unsigned grid = (unsigned)groups + (unsigned)(ctx->num_cus * 2);
+                                    const int32_t *tile_cross, const OffT *off,
+                                    const int32_t *cols, const int64_t *chunks, int64_t chunk_cap,
+                                    ForestBufs &f) {
+  const unsigned grid = (unsigned)(ctx->num_cus * 4);
+  unsigned slices = (grid + tiles - 1) / tiles;
+  slices = slices < 1 ? 1 : (slices > 64 ? 64 : slices);
   hipLaunchKernelGGL(k_late_hooks<OffT>, dim3(grid), dim3(kTileThreads), 0, ctx->stream, region_of,
-                     cross, tile_cross, tile_lvl, (int)tiles, groups, split, levels, off, cols,
-                     chunks, chunk_cap, f.cc, f.tu, f.tv, f.counters, f.head, f.next);
+                     cross, tile_cross, levels == 0 ? 0 : (int)tiles, (int)slices, off, cols, chunks,
+                     chunk_cap, f.cc, f.tu, f.tv, f.counters, f.head, f.next);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }
@@ -1136,8 +1101,8 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));
-    RST_TRY(launch_late_hooks(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, off,
-                              g->cols, chunks, chunk_cap, f));
+    RST_TRY(launch_late_hooks(ctx, tiles, levels, region_of, cross, tile_cross, off, g->cols,
+                              chunks, chunk_cap, f));
   } else {
     const int64_t *off = (const int64_t *)g->offsets;
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 0);
@@ -1148,8 +1113,8 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));
-    RST_TRY(launch_late_hooks(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, off,
-                              g->cols, chunks, chunk_cap, f));
+    RST_TRY(launch_late_hooks(ctx, tiles, levels, region_of, cross, tile_cross, off, g->cols,
+                              chunks, chunk_cap, f));
   }
   RST_HIP(hipGetLastError());
   return RST_OK;

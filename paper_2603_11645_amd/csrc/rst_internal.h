@@ -167,7 +167,6 @@ enum {
   kCntKeptTop = 14,        // of those, the edges of the levels merged by the top pass
   kCntCrossDone = 15,      // the one-block merge of all kept edges succeeded
   kCntTotal = 16,          // counters read back after a call (the ones above)
-  kCntMergeDone = 16,      // group blocks done with the global-memory merge fallback
 };
 
 // hook.hip
