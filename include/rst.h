@@ -129,7 +129,9 @@ typedef enum {
   RST_OPT_RANK_ELEMS_PER_THREAD = 3, /* words per thread of the multi-workgroup list-
                                       * ranking rounds (1, 2, 4, 8)                 */
   RST_OPT_HEAVY_DEGREE = 4,    /* hooking: degree above which a vertex's arcs are cut
-                                * into chunks hooked by many workgroups (32 .. 2^24) */
+                                * into chunks hooked by many workgroups (32 .. 2^24;
+                                * values above 1023 act as 1023: the tile pass
+                                * takes no vertex of larger degree)                */
   RST_OPT_SWEEP_BLOCK = 5,     /* threads per workgroup of the per-vertex and per-slot
                                 * sweeps (64, 128, 256, 512, 1024)                 */
   RST_OPT_BFS_HEAVY_DEGREE = 6, /* BFS: degree above which a frontier vertex's arcs are
