@@ -115,6 +115,7 @@ struct GconnWork {
   uint64_t *rank;
   int32_t *xid;
   int32_t *endsucc;
+  bool settled = false;   // k_settle ran (one root): components' own parents and count done
   RankBufs rb;
 };
 
@@ -156,8 +157,7 @@ static rst_status enqueue_gconn(rst_ctx *ctx, const rst_csr *g, const int32_t *r
   if (nroots == 1) {
     // one pass: final labels, the root's claim, end-of-list successors (the
     // "roots" stage stays empty)
-    RST_TRY(enqueue_settle(ctx, n, roots, w.f.cc, w.f.comp_root, w.f.head, w.endsucc, parent,
-                           w.f.counters));
+    RST_TRY(enqueue_settle(ctx, n, roots, w.f.cc, w.f.head, w.endsucc, parent, w.f.counters));
     arcs.endsucc_ready = true;
     RST_TRY(mark(ctx, st, 2));
     RST_TRY(mark(ctx, st, 3));
@@ -172,8 +172,11 @@ static rst_status enqueue_gconn(rst_ctx *ctx, const rst_csr *g, const int32_t *r
   RST_TRY(mark(ctx, st, 4));
   RST_TRY(enqueue_rank_tiled(ctx, 2 * n, w.rank, w.xid, w.rb, w.f.counters, &arcs, false));
   RST_TRY(mark(ctx, st, 5));
+  // with one root, k_settle already set the components' own parents and counted them
+  w.settled = nroots == 1;
+  const int32_t *comp_cc = w.settled ? nullptr : w.f.cc;
   RST_TRY(enqueue_expand_parent(ctx, n, n, w.f.tu, w.f.tv, w.rank, w.xid, w.rb.tile_base,
-                                w.rb.crank, w.f.cc, w.f.comp_root, parent, w.f.counters));
+                                w.rb.crank, comp_cc, w.f.comp_root, parent, w.f.counters));
   RST_TRY(mark(ctx, st, 6));
   return RST_OK;
 }
@@ -192,7 +195,8 @@ static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, 
     // multi-block rounds, then the parent rule runs again
     RST_TRY(rank_overflow_fallback(ctx, w.rb, counters));
     RST_TRY(enqueue_expand_parent(ctx, n, n, w.f.tu, w.f.tv, w.rank, w.xid, w.rb.tile_base,
-                                  w.rb.crank, w.f.cc, w.f.comp_root, parent, counters));
+                                  w.rb.crank, w.settled ? nullptr : w.f.cc, w.f.comp_root, parent,
+                                  counters));
     RST_TRY(mark(ctx, st, 6));
     RST_TRY(read_counters(ctx, counters));
   }
@@ -469,6 +473,7 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
     // the whole device part of the call as one captured graph, replayed while
     // the graph, buffers and settings stay the same
     GconnWork w = take_gconn_work(ctx, g, counters, nullptr, nullptr);
+    w.settled = true;   // one root (a replay does not run enqueue_gconn's host code)
     GraphKey key;
     std::memset(&key, 0, sizeof key);
     key.offsets = g->offsets; key.cols = g->cols; key.parent = parent;

@@ -60,16 +60,15 @@ __global__ void k_mark_roots(const int32_t *__restrict__ roots, int32_t nroots, 
 // Final pointer jumping fused with the root marking and the end-of-list
 // successors, for one designated root R = roots[0]: every vertex points at its
 // tree's root (the minimum id of its component, as after k_compress);
-// comp_root holds R at that root of R's component and -1 at every other
-// vertex; P[R] = R; endsucc[v] is v's first out-arc, or -1 where v roots its
-// tree (R in R's component, the minimum id in the others).  The chain from R
+// endsucc[v] is v's first out-arc, or -1 where v roots its tree (R in R's
+// component, the minimum id in the others), and such a v gets P[v] = v; the
+// components are counted (so the parent pass need not).  The chain from R
 // is walked by every thread (the same few words, cached); concurrent
 // shortcuts only replace a pointer by an ancestor, so every walk still ends at
 // the root.
 template <int B>
 __global__ __launch_bounds__(B) void k_settle(int64_t n, const int32_t *__restrict__ roots,
-                                                   int32_t *cc, int32_t *comp_root,
-                                                   const int32_t *__restrict__ head,
+                                                   int32_t *cc, const int32_t *__restrict__ head,
                                                    int32_t *endsucc, int32_t *parent,
                                                    int32_t *counters) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -85,10 +84,10 @@ __global__ __launch_bounds__(B) void k_settle(int64_t n, const int32_t *__restri
   const int32_t first = r;
   while (r > (nx = cc[r])) r = nx;
   if (r != first) cc[v] = r;
-  comp_root[v] = (v == cR) ? R : -1;
   const bool tree_root = (r == cR) ? (v == R) : (r == (int32_t)v);
   endsucc[v] = tree_root ? -1 : head[v];
-  if (v == R) parent[v] = R;
+  if (tree_root) parent[v] = (int32_t)v;
+  wave_count(r == (int32_t)v, &counters[kCntComponents]);
 }
 
 // Per-vertex out-arc lists: next[e] = previous head of src(e), head = e.
@@ -834,6 +833,7 @@ __global__ __launch_bounds__(B) void k_expand_parent(int64_t slots, int64_t n,
       else parent[a] = b;
     }
   }
+  if (!cc) return;   // components' own parents and the count already done (k_settle)
   bool comp = false;
   if (x < n) {
     comp = cc[x] == (int32_t)x;
@@ -886,9 +886,9 @@ int rank_rounds_for(int64_t max_list_len) {
 }
 
 rst_status enqueue_settle(rst_ctx *ctx, int64_t n, const int32_t *roots, int32_t *cc,
-                          int32_t *comp_root, const int32_t *head, int32_t *endsucc,
-                          int32_t *parent, int32_t *counters) {
-  RST_SWEEP(ctx, k_settle, n, n, roots, cc, comp_root, head, endsucc, parent, counters);
+                          const int32_t *head, int32_t *endsucc, int32_t *parent,
+                          int32_t *counters) {
+  RST_SWEEP(ctx, k_settle, n, n, roots, cc, head, endsucc, parent, counters);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }
@@ -1017,7 +1017,7 @@ rst_status enqueue_expand_parent(rst_ctx *ctx, int64_t slots, int64_t n, const i
                                  const int32_t *tv, const uint64_t *rank, const int32_t *xid,
                                  const int64_t *tile_base, const uint64_t *crank, const int32_t *cc,
                                  const int32_t *comp_root, int32_t *parent, int32_t *counters) {
-  const int64_t items = slots > n ? slots : n;
+  const int64_t items = (cc && n > slots) ? n : slots;
   RST_SWEEP(ctx, k_expand_parent, items, slots, n, tu, tv, rank, xid, tile_base, crank, cc,
             comp_root, parent, counters);
   RST_HIP(hipGetLastError());

@@ -92,3 +92,21 @@ def test_recapture_on_changes(rst):
     check(g2, par, 11)
     c.spanning_tree(o1, c1, 5, "gconn", parent=p1)            # back to the first one
     check(g1, p1, 5)
+
+
+def test_replays_with_contracted_list_fallback(rst):
+    """A graph whose contracted tour list is too long for the one-workgroup
+    ranking: every replay finishes with the multi-workgroup fallback after the
+    call's synchronisation, and must still give a verified tree and report one
+    component (the components are counted once, in the replayed pass)."""
+    c = rst.Context(0)
+    g = I.random_graph(300000, 450000, seed=11, connected=True)
+    off, cols = upload(g)
+    par = torch.empty(g.n, dtype=torch.int32).cuda()
+    _, st = c.spanning_tree(off, cols, 11, "gconn", stats=True)
+    assert st["paths"] & rst.PATH_RANK_GLOBAL and st["components"] == 1
+    for _ in range(3):
+        par.fill_(-3)
+        c.spanning_tree(off, cols, 11, "gconn", parent=par)   # raises if not one component
+        assert c.last_status == 0
+        check(g, par, 11)
