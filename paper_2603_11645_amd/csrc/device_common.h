@@ -86,4 +86,16 @@ __device__ __forceinline__ void wave_release_device() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
 }
 
+// The same for a whole workgroup at once (called by all its threads): each
+// wave waits until its own stores and atomics have completed, the barrier
+// orders them before one wave's release fence, and that fence (which writes
+// back this XCD's L2 as a whole) releases them all.  One write-back per
+// workgroup instead of one per wave: when every wave of a large grid fenced,
+// the write-backs queued up (measured on MI355X).
+__device__ __forceinline__ void block_release_device() {
+  __builtin_amdgcn_s_waitcnt(0);   // vmcnt, expcnt and lgkmcnt all zero
+  __syncthreads();
+  if (threadIdx.x < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+}
+
 }  // namespace rst

@@ -580,7 +580,7 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_cross_dedupe(const int64_t 
       const int2 e = cross[region + i];
       hook_edge<true>(e.x, e.y, cc, tu, tv, head, next);
     }
-    wave_release_device();
+    block_release_device();
     return;
   }
   if (part != 0) return;
@@ -881,7 +881,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
       if (hk_g[k] >= 0) finish(hk_key[k], hk_root[k], hk_g[k]);
   }
   if (all && tid == 0) counters[kCntCrossDone] = 1;   // (visible to the next kernel)
-  wave_release_device();
+  block_release_device();
 }
 
 // Global-memory hooking after the LDS merges, in one launch.  Only when an LDS
@@ -928,7 +928,7 @@ __global__ __launch_bounds__(kTileThreads) void k_late_hooks(
     }
     hooked = true;
   }
-  if (hooked) wave_release_device();   // block-uniform: only blocks that hooked
+  if (hooked) block_release_device();   // block-uniform: only blocks that hooked
 }
 
 // Edge-list hooking without recording (labels of a given forest).
