@@ -1038,8 +1038,11 @@ static rst_status launch_cross(rst_ctx *ctx, unsigned tiles, int levels,
   // each), the rest by one workgroup
   int split = levels <= 3 ? 0 : levels / 2;
   if (split > 10) split = 10;
-  // flat tiles are split over several blocks when there are few tiles
-  unsigned slices = (1024 + tiles - 1) / tiles;
+  // flat tiles are split over several blocks when there are fewer tiles than
+  // two per CU (every extra block is dispatched, and leaves at once, for every
+  // tile that is not flat)
+  const unsigned target = (unsigned)(ctx->num_cus * 2);
+  unsigned slices = (target + tiles - 1) / tiles;
   slices = slices < 1 ? 1 : (slices > 64 ? 64 : slices);
   hipLaunchKernelGGL(k_cross_dedupe, dim3(tiles * slices), dim3(kTileThreads), 0, ctx->stream,
                      region_of, cross, tile_cross, (int)slices, f.cc, f.tu, f.tv, f.counters,
@@ -1070,7 +1073,7 @@ static rst_status launch_late_hooks(rst_ctx *ctx, unsigned tiles, int levels,
                                     const int32_t *tile_cross, const OffT *off,
                                     const int32_t *cols, const int64_t *chunks, int64_t chunk_cap,
                                     ForestBufs &f) {
-  const unsigned grid = (unsigned)(ctx->num_cus * 4);
+  const unsigned grid = (unsigned)(ctx->num_cus * 2);
   unsigned slices = (grid + tiles - 1) / tiles;
   slices = slices < 1 ? 1 : (slices > 64 ? 64 : slices);
   hipLaunchKernelGGL(k_late_hooks<OffT>, dim3(grid), dim3(kTileThreads), 0, ctx->stream, region_of,
