@@ -552,7 +552,7 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
 constexpr int kDedupSlots = 8192;       // LDS hash slots (64 KB) of k_cross_dedupe
 constexpr int kFlatCross = kTile;       // above this a tile's cross edges are hooked flat
 constexpr int kDedupPer = kFlatCross / kTileThreads;
-constexpr int kLdsSlots = 16384;        // root slots of k_cross_lds (key + parent: 128 KB)
+constexpr int kLdsSlots = 8192;         // root slots of k_cross_lds (key + parent: 64 KB)
 constexpr int kLdsPer = 16;             // kept edges per thread in k_cross_lds
 constexpr int kLdsEdges = kLdsPer * kTileThreads;
 // The one-block merge of all levels takes at most this many kept edges: one
@@ -659,7 +659,7 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_cross_dedupe(const int64_t 
 // Slot of global root `key` in the LDS table (inserted if new); -1 when the
 // probe limit is reached.
 __device__ __forceinline__ int lds_slot(int32_t key, int32_t *keys) {
-  uint32_t h = ((uint32_t)key * 0x9E3779B1u) >> (32 - 14);
+  uint32_t h = ((uint32_t)key * 0x9E3779B1u) >> (32 - 13);
   for (int probe = 0; probe < 256; ++probe) {
     const int32_t old = atomicCAS(&keys[h], -1, key);
     if (old == -1 || old == key) return (int)h;
@@ -667,7 +667,7 @@ __device__ __forceinline__ int lds_slot(int32_t key, int32_t *keys) {
   }
   return -1;
 }
-static_assert(kLdsSlots == 1 << 14, "lds_slot hashes to 14 bits");
+static_assert(kLdsSlots == 1 << 13, "lds_slot hashes to 13 bits");
 
 // LDS union-find entries of k_cross_lds: parent slot in the low 14 bits; a
 // hooked slot also keeps 1 + the number of the kept edge that hooked it in
@@ -690,14 +690,19 @@ __device__ __forceinline__ int lds_find_rec(int x, int *par) {
 }
 
 // One union in the LDS table (smaller global id wins); the winner of the
-// compare-and-swap stores the kept edge number g with the new parent.
-__device__ __forceinline__ void lds_union(int sa, int sb, int g, const int32_t *keys, int *par) {
+// compare-and-swap stores the kept edge number g with the new parent and adds
+// the hooked slot to the list `hooks`.
+__device__ __forceinline__ void lds_union(int sa, int sb, int g, const int32_t *keys, int *par,
+                                          int *hooks, int *nhooks) {
   int ra = lds_find_rec(sa, par), rb = lds_find_rec(sb, par);
   while (ra != rb) {
     const bool a_low = keys[ra] < keys[rb];
     const int lo = a_low ? ra : rb, hi = a_low ? rb : ra;
     const int old = atomicCAS(&par[hi], hi, lo | ((g + 1) << 14));
-    if (old == hi) return;
+    if (old == hi) {
+      hooks[atomicAdd(nhooks, 1)] = hi;   // each slot is hooked once
+      return;
+    }
     const int np = lds_find_rec(old & kParMask, par);
     if (ra == hi) ra = np; else rb = np;
   }
@@ -729,9 +734,10 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
                                                             int32_t *next) {
   __shared__ int32_t keys[kLdsSlots];   // global root held by a slot, -1: empty
   __shared__ int par[kLdsSlots];        // union-find entries (see kParMask)
+  __shared__ int s_hooks[kLdsSlots];    // slots hooked by the unions
   __shared__ int s_pref[kGroup ? kTileThreads + 1 : 1];   // kept counts of the group's tiles
   __shared__ int s_wave[kTileThreads / kWave];
-  __shared__ int s_fail, s_nrec;
+  __shared__ int s_fail, s_nhooks;
   const int tid = threadIdx.x;
   // every branch below is block-uniform
   const bool all = kGroup && counters[kCntKept] <= kAllEdges;
@@ -764,7 +770,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
   }
   if (total == 0) return;
   for (int i = tid; i < kLdsSlots; i += kTileThreads) { keys[i] = -1; par[i] = i; }
-  if (tid == 0) { s_fail = 0; s_nrec = 0; }
+  if (tid == 0) { s_fail = 0; s_nhooks = 0; }
   __syncthreads();
   const int32_t own_lo = grp ? (int32_t)(t0 << kTileShift) : 0;
   const int32_t own_hi = grp ? (int32_t)((t1 << kTileShift) - 1) : 0x7fffffff;
@@ -833,52 +839,24 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
   for (int k = 0; k < kLdsPer; ++k) {
     const uint32_t v = sab[k];
     if (v != ~0u)
-      lds_union((int)(v & 0x3fff), (int)((v >> 14) & 0x3fff), tid + k * kTileThreads, keys, par);
+      lds_union((int)(v & 0x3fff), (int)((v >> 14) & 0x3fff), tid + k * kTileThreads, keys, par,
+                s_hooks, &s_nhooks);
   }
   __syncthreads();
   // Every hooked root points straight at its final root and records the kept
-  // edge that hooked it.  The hooked slots are few and scattered over the
-  // table: they are gathered into a compact list first (in the par region,
-  // free once every find is done), so that each is finished by its own thread
-  // and their edge lookups and global writes all proceed in parallel.
-  constexpr int kSlotsPer = kLdsSlots / kTileThreads;
-  constexpr int kRecMax = kLdsSlots / 3;
-  int32_t hk_g[kSlotsPer], hk_key[kSlotsPer], hk_root[kSlotsPer];
-#pragma unroll
-  for (int k = 0; k < kSlotsPer; ++k) {
-    const int i = tid + k * kTileThreads;
-    const int w = par[i];
-    const bool hooked = keys[i] >= 0 && (w & kParMask) != i;
-    hk_g[k] = hooked ? (w >> 14) - 1 : -1;
-    hk_key[k] = hooked ? keys[i] : 0;
-    hk_root[k] = hooked ? keys[lds_find_rec(i, par)] : 0;
-  }
-  __syncthreads();
-  int *rec = par;   // [3 * kRecMax]: key, final root, kept edge number
-#pragma unroll
-  for (int k = 0; k < kSlotsPer; ++k) {
-    const int r = wave_append(hk_g[k] >= 0, &s_nrec);
-    if (hk_g[k] >= 0 && r < kRecMax) {
-      rec[3 * r] = hk_key[k];
-      rec[3 * r + 1] = hk_root[k];
-      rec[3 * r + 2] = hk_g[k];
-    }
-  }
-  __syncthreads();
-  const int nrec = s_nrec;
-  auto finish = [&](int32_t key, int32_t root, int g) {
+  // edge that hooked it; the unions listed the hooked slots, one thread each
+  // finishes them, so their edge lookups and global writes proceed in parallel.
+  const int nh = s_nhooks;
+  for (int r = tid; r < nh; r += kTileThreads) {
+    const int hi = s_hooks[r];
+    const int g = (par[hi] >> 14) - 1;
+    const int32_t key = keys[hi];
+    const int32_t root = keys[lds_find_rec(hi, par)];
     const int2 e = edge_at(g);
     cc[key] = root;
     tu[key] = e.x;
     tv[key] = e.y;
     if (head) link_slot(key, e.x, e.y, head, next);
-  };
-  if (nrec <= kRecMax) {
-    for (int r = tid; r < nrec; r += kTileThreads) finish(rec[3 * r], rec[3 * r + 1], rec[3 * r + 2]);
-  } else {
-#pragma unroll
-    for (int k = 0; k < kSlotsPer; ++k)
-      if (hk_g[k] >= 0) finish(hk_key[k], hk_root[k], hk_g[k]);
   }
   if (all && tid == 0) counters[kCntCrossDone] = 1;   // (visible to the next kernel)
   block_release_device();
