@@ -155,7 +155,8 @@ static rst_status enqueue_gconn(rst_ctx *ctx, const rst_csr *g, const int32_t *r
   RST_TRY(mark(ctx, st, 1));
   SlotArcs arcs{w.f.tu, w.f.tv, w.f.next, w.f.head, w.f.cc, w.f.comp_root, n, w.endsucc};
   if (nroots == 1) {
-    // one pass: final labels, the root's claim, end-of-list successors (the
+    // one pass: the root's claim, end-of-list successors, the components' own
+    // parents and count (the labels are not needed further on this path; the
     // "roots" stage stays empty)
     RST_TRY(enqueue_settle(ctx, n, roots, w.f.cc, w.f.head, w.endsucc, parent, w.f.counters));
     arcs.endsucc_ready = true;

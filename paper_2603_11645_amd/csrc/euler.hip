@@ -57,18 +57,18 @@ __global__ void k_mark_roots(const int32_t *__restrict__ roots, int32_t nroots, 
   parent[r] = r;
 }
 
-// Final pointer jumping fused with the root marking and the end-of-list
-// successors, for one designated root R = roots[0]: every vertex points at its
-// tree's root (the minimum id of its component, as after k_compress);
-// endsucc[v] is v's first out-arc, or -1 where v roots its tree (R in R's
-// component, the minimum id in the others), and such a v gets P[v] = v; the
-// components are counted (so the parent pass need not).  The chain from R
-// is walked by every thread (the same few words, cached); concurrent
-// shortcuts only replace a pointer by an ancestor, so every walk still ends at
-// the root.
+// Root marking fused with the end-of-list successors, for one designated root
+// R = roots[0], after all hooks: a vertex roots its tree when it is R, or
+// when it is its own parent (the minimum id of its component) and R lies in
+// another component.  endsucc[v] is v's first out-arc, or -1 where v roots its
+// tree (the cycle break), and such a v gets P[v] = v; the components are
+// counted.  The labels are left as the hooks made them (the tour needs only
+// the roots, which are final); the chain from R to its component's root is
+// walked by every thread (the same few words, cached).
 template <int B>
 __global__ __launch_bounds__(B) void k_settle(int64_t n, const int32_t *__restrict__ roots,
-                                                   int32_t *cc, const int32_t *__restrict__ head,
+                                                   const int32_t *__restrict__ cc,
+                                                   const int32_t *__restrict__ head,
                                                    int32_t *endsucc, int32_t *parent,
                                                    int32_t *counters) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -80,14 +80,11 @@ __global__ __launch_bounds__(B) void k_settle(int64_t n, const int32_t *__restri
   }
   int32_t cR = R, nx;
   while (cR > (nx = cc[cR])) cR = nx;
-  int32_t r = cc[v];
-  const int32_t first = r;
-  while (r > (nx = cc[r])) r = nx;
-  if (r != first) cc[v] = r;
-  const bool tree_root = (r == cR) ? (v == R) : (r == (int32_t)v);
+  const bool comp_root = cc[v] == (int32_t)v;
+  const bool tree_root = v == R || (comp_root && v != cR);
   endsucc[v] = tree_root ? -1 : head[v];
   if (tree_root) parent[v] = (int32_t)v;
-  wave_count(r == (int32_t)v, &counters[kCntComponents]);
+  wave_count(comp_root, &counters[kCntComponents]);
 }
 
 // Per-vertex out-arc lists: next[e] = previous head of src(e), head = e.
@@ -522,16 +519,50 @@ __device__ __forceinline__ int64_t exit_index(int32_t ex, const int32_t *xid, co
 }
 
 // Contracted list over the exits (one block per tile): next exit and weighted
-// hops to it.
+// hops to it.  With kScan, every block first forms the exclusive prefix of the
+// tiles' exit counts itself (up to kContractTiles tiles, in LDS) and block b
+// stores base[b] (block 0 also base[tiles] = M), so no separate scan launch
+// is needed; otherwise base comes from k_tile_scan.
+constexpr int kContractTiles = 4096;
+template <bool kScan>
 __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restrict__ exits,
                                                           const int32_t *__restrict__ tile_exits,
-                                                          const int64_t *__restrict__ base,
+                                                          int64_t *base, int64_t tiles,
                                                           const uint64_t *__restrict__ rank,
                                                           const int32_t *__restrict__ xid,
                                                           uint64_t *crank) {
+  __shared__ int64_t s_base[kScan ? kContractTiles + 1 : 1];
+  __shared__ int s_wave[kBlock / kWave];
+  const int64_t *bs = base;
+  if (kScan) {
+    constexpr int PER = kContractTiles / kBlock;
+    const int tid = threadIdx.x;
+    int c[PER];
+    int sum = 0;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = tid * PER + q;
+      c[q] = t < tiles ? tile_exits[t] : 0;
+      sum += c[q];
+    }
+    int total;
+    int64_t run = block_excl_scan<kBlock>(sum, s_wave, &total);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      s_base[tid * PER + q] = run;
+      run += c[q];
+    }
+    if (tid == 0) s_base[kContractTiles] = total;
+    __syncthreads();
+    if (tid == 0) {
+      base[blockIdx.x] = s_base[blockIdx.x];
+      if (blockIdx.x == 0) base[tiles] = total;
+    }
+    bs = s_base;
+  }
   const int64_t e0 = (int64_t)blockIdx.x * kRankTile;
   const int cntb = tile_exits[blockIdx.x];
-  const int64_t b0 = base[blockIdx.x];
+  const int64_t b0 = bs[blockIdx.x];
   for (int j = threadIdx.x; j < cntb; j += kBlock) {
     const int32_t x = exits[e0 + j];
     const int32_t s = (int32_t)(uint32_t)rank[x];
@@ -544,7 +575,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
     int32_t ex = s;
     uint32_t dl = 0;
     if (in_tile(id, s)) { ex = id; dl = (uint32_t)(ws >> 32); }
-    crank[b0 + j] = pack_rank((int32_t)exit_index(ex, xid, base), 1u + dl);
+    crank[b0 + j] = pack_rank((int32_t)exit_index(ex, xid, bs), 1u + dl);
   }
 }
 
@@ -580,10 +611,19 @@ static_assert(kSmOffRw % 8 == 0 && kSmBytes >= 8 * kSmallLds, "ruler path LDS la
 constexpr uint64_t kSmFinal = 1ull << 63;
 
 __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__restrict__ Mp,
-                                                              uint64_t *crank, int32_t *counters) {
+                                                              uint64_t *crank, int64_t cap,
+                                                              int32_t *counters) {
   __shared__ __align__(16) unsigned char s_raw[kSmBytes];
   __shared__ int s_extra, s_ndyn, s_or[3];
   const int tid = threadIdx.x;
+  // the words are loaded before their count is known (cap = words the buffer
+  // holds), so that both loads overlap
+  uint64_t own[kSmallPer];
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k) {
+    const int i = tid + k * kSmallThreads;
+    own[k] = i < cap ? crank[i] : pack_rank(-1, 0);
+  }
   const int64_t M = *Mp;
   if (tid == 0) {
     counters[kCntExits] = (int32_t)M;
@@ -601,12 +641,6 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
   uint32_t *haspred = reinterpret_cast<uint32_t *>(s_raw + kSmOffHp);
   int16_t *r_start = reinterpret_cast<int16_t *>(s_raw + kSmOffRs);
   uint64_t *r_word = reinterpret_cast<uint64_t *>(s_raw + kSmOffRw);
-  uint64_t own[kSmallPer];
-#pragma unroll
-  for (int k = 0; k < kSmallPer; ++k) {
-    const int i = tid + k * kSmallThreads;
-    own[k] = i < m ? crank[i] : pack_rank(-1, 0);
-  }
   for (int q = tid; q < kSmallLds / 32; q += kSmallThreads) haspred[q] = 0u;
   __syncthreads();
 #pragma unroll
@@ -885,7 +919,7 @@ int rank_rounds_for(int64_t max_list_len) {
   return r;
 }
 
-rst_status enqueue_settle(rst_ctx *ctx, int64_t n, const int32_t *roots, int32_t *cc,
+rst_status enqueue_settle(rst_ctx *ctx, int64_t n, const int32_t *roots, const int32_t *cc,
                           const int32_t *head, int32_t *endsucc, int32_t *parent,
                           int32_t *counters) {
   RST_SWEEP(ctx, k_settle, n, n, roots, cc, head, endsucc, parent, counters);
@@ -982,14 +1016,19 @@ rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *
   }
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_RANK_TILE, 1);
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, ctx->stream, rb.tile_exits, tiles,
-                     rb.tile_base);
-  RST_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_rank_contract, dim3((unsigned)tiles), dim3(kBlock), 0, ctx->stream, rb.exits,
-                     rb.tile_exits, rb.tile_base, rank, xid, rb.crank);
+  if (tiles <= kContractTiles) {
+    hipLaunchKernelGGL(k_rank_contract<true>, dim3((unsigned)tiles), dim3(kBlock), 0, ctx->stream,
+                       rb.exits, rb.tile_exits, rb.tile_base, tiles, rank, xid, rb.crank);
+  } else {
+    hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, ctx->stream, rb.tile_exits, tiles,
+                       rb.tile_base);
+    RST_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_rank_contract<false>, dim3((unsigned)tiles), dim3(kBlock), 0, ctx->stream,
+                       rb.exits, rb.tile_exits, rb.tile_base, tiles, rank, xid, rb.crank);
+  }
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_rank_small, dim3(1), dim3(kSmallThreads), 0, ctx->stream,
-                     rb.tile_base + tiles, rb.crank, counters);
+                     rb.tile_base + tiles, rb.crank, (int64_t)rank_exit_capacity(A), counters);
   RST_HIP(hipGetLastError());
   if (expand) RST_TRY(enqueue_rank_expand(ctx, A, rank, xid, rb, counters));
   return RST_OK;

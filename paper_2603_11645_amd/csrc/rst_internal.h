@@ -189,9 +189,10 @@ rst_status enqueue_count_roots(rst_ctx *ctx, int64_t n, const int32_t *cc, int32
 size_t hook_chunk_capacity(const rst_ctx *ctx, int64_t nnz);
 
 // euler.hip
-// one designated root: compress, the root's claim, end-of-list successors,
-// the components' own parents and their count, in one pass (comp_root unused)
-rst_status enqueue_settle(rst_ctx *ctx, int64_t n, const int32_t *roots, int32_t *cc,
+// one designated root, after all hooks: the root's claim, end-of-list
+// successors, the components' own parents and their count, in one pass
+// (comp_root unused; the labels are not compressed)
+rst_status enqueue_settle(rst_ctx *ctx, int64_t n, const int32_t *roots, const int32_t *cc,
                           const int32_t *head, int32_t *endsucc, int32_t *parent,
                           int32_t *counters);
 rst_status enqueue_mark_roots(rst_ctx *ctx, const int32_t *roots, int32_t nroots, int64_t n,
