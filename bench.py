@@ -201,8 +201,9 @@ def main():
         # every cross edge read once and its two tree labels gathered
         "cross": 16 * X,
         # per arc: slot edge (4) + next of twin (4) + end-of-list successor (2,
-        # half the arcs) + ranking word (8); exit records are a few per tile
-        "rank_tile": 18 * A,
+        # half the arcs) + its half of the slot record (4); exit records are a
+        # few per tile
+        "rank_tile": 14 * A,
         # per slot: edge read (8) + two list-head exchanges (16) + next pair (8)
         # (only when the separate link kernel runs)
         "link": 32 * n,

@@ -198,6 +198,16 @@ constexpr int kMaxRulers = kRulerSlots - 1;            // id 4095 unused: its co
 // static rulers (strided + segment heads) that leave room for every opened one
 constexpr int kMaxStatic = kMaxRulers - kRankTile / kPiece;
 
+// Slot records of the tile pass over forest slots: for the twin arcs 2x and
+// 2x+1 of slot x, the local id (in the arc tile) of the segment exit each one
+// reaches and its hops to it, arc c in bits [32c, 32c + 28): exit | hops << 14.
+// An exit reaches itself in 0 hops.  The successor of each exit goes to a
+// second array beside the exits list.  The records take the first half of the
+// rank buffer (A/2 words of 8 bytes), the successors its second half.
+__device__ __forceinline__ uint32_t rec_half(int ex_local, uint32_t hops) {
+  return (uint32_t)ex_local | (hops << 14);
+}
+
 __device__ __forceinline__ bool in_tile(int32_t id, int64_t e) {
   return id >= 0 && ((int64_t)id / kRankTile) == (e / kRankTile);
 }
@@ -321,7 +331,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
         if (is_exit) {
           exits[e0 + slot] = (int32_t)(e0 + i);
           xid[e0 + i] = slot;
-          if (kFromSlots) rank[e0 + i] = pack_rank(t[2 * k + c], t[2 * k + c] >= 0 ? 1u : 0u);
+          if (kFromSlots) reinterpret_cast<int32_t *>(rank)[A + e0 + slot] = t[2 * k + c];
         }
       }
       if (i0 < cnt) *reinterpret_cast<uint32_t *>(&ls[i0]) = lv[0] | (lv[1] << 16);
@@ -441,6 +451,27 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
       __syncthreads();
       if (!s_or[round % 3]) break;
     }
+    if (kFromSlots) {
+      // one record per slot, coalesced: (exit, hops) of both twin arcs
+#pragma unroll
+      for (int k = 0; k < kRankPer / 2; ++k) {
+        const int i0 = 2 * (tid + k * kRankThreads);
+        if (i0 < cnt) {
+          uint32_t half[2];
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const uint32_t code = (uint16_t)ls[i0 + c];
+            half[c] = rec_half(i0 + c, 0u);
+            if (code != 0xffffu) {
+              const uint32_t w = r_word[code >> 4];
+              half[c] = rec_half(r_exit[(w >> 16) & 0xfffu], (w & 0xffffu) - (code & 15u));
+            }
+          }
+          rank[(e0 + i0) >> 1] = ((uint64_t)half[1] << 32) | half[0];
+        }
+      }
+      return;
+    }
     // every arc but the exits: (exit of its chain, ruler hops - offset), coalesced
 #pragma unroll
     for (int k = 0; k < kRankPer; ++k) {
@@ -487,6 +518,16 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
     }
     __syncthreads();   // fixed 15 rounds: enough for the 16384 arcs of a tile
   }
+  if (kFromSlots) {
+#pragma unroll
+    for (int k = 0; k < kRankPer / 2; ++k) {
+      const int i0 = 2 * (tid + k * kRankThreads);
+      if (i0 < cnt)
+        rank[(e0 + i0) >> 1] = ((uint64_t)rec_half(ls[i0 + 1], dd[i0 + 1]) << 32) |
+                               rec_half(ls[i0], dd[i0]);
+    }
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < kRankPer; ++j) {
     const int i = tid + j * kRankThreads;
@@ -524,10 +565,11 @@ __device__ __forceinline__ int64_t exit_index(int32_t ex, const int32_t *xid, co
 // stores base[b] (block 0 also base[tiles] = M), so no separate scan launch
 // is needed; otherwise base comes from k_tile_scan.
 constexpr int kContractTiles = 4096;
-template <bool kScan>
+// kSlots: the tile pass wrote slot records (forest slots), else per-arc words.
+template <bool kScan, bool kSlots>
 __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restrict__ exits,
                                                           const int32_t *__restrict__ tile_exits,
-                                                          int64_t *base, int64_t tiles,
+                                                          int64_t *base, int64_t tiles, int64_t A,
                                                           const uint64_t *__restrict__ rank,
                                                           const int32_t *__restrict__ xid,
                                                           uint64_t *crank) {
@@ -564,17 +606,33 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
   const int cntb = tile_exits[blockIdx.x];
   const int64_t b0 = bs[blockIdx.x];
   for (int j = threadIdx.x; j < cntb; j += kBlock) {
-    const int32_t x = exits[e0 + j];
-    const int32_t s = (int32_t)(uint32_t)rank[x];
-    if (s < 0) {
-      crank[b0 + j] = pack_rank(-1, 0);
-      continue;
-    }
-    const uint64_t ws = rank[s];
-    const int32_t id = (int32_t)(uint32_t)ws;
-    int32_t ex = s;
+    int32_t s, ex;
     uint32_t dl = 0;
-    if (in_tile(id, s)) { ex = id; dl = (uint32_t)(ws >> 32); }
+    if (kSlots) {
+      s = reinterpret_cast<const int32_t *>(rank)[A + e0 + j];   // the exit's successor
+      if (s < 0) {
+        crank[b0 + j] = pack_rank(-1, 0);
+        continue;
+      }
+      const uint32_t h = (uint32_t)(rank[s >> 1] >> (32 * (s & 1)));
+      const int sl = s & (kRankTile - 1);
+      ex = s;                                  // s is an exit itself when it reaches itself
+      if ((int)(h & 0x3fffu) != sl) {
+        ex = (s & ~(kRankTile - 1)) + (int32_t)(h & 0x3fffu);
+        dl = h >> 14;
+      }
+    } else {
+      const int32_t x = exits[e0 + j];
+      s = (int32_t)(uint32_t)rank[x];
+      if (s < 0) {
+        crank[b0 + j] = pack_rank(-1, 0);
+        continue;
+      }
+      const uint64_t ws = rank[s];
+      const int32_t id = (int32_t)(uint32_t)ws;
+      ex = s;
+      if (in_tile(id, s)) { ex = id; dl = (uint32_t)(ws >> 32); }
+    }
     crank[b0 + j] = pack_rank((int32_t)exit_index(ex, xid, bs), 1u + dl);
   }
 }
@@ -832,18 +890,9 @@ __global__ __launch_bounds__(kBlock) void k_rank_expand(int64_t A, uint64_t *ran
   rank[e] = pack_rank(-1, dist);
 }
 
-__device__ __forceinline__ uint32_t arc_dist(int64_t e, const uint64_t *__restrict__ rank,
-                                             const int32_t *__restrict__ xid,
-                                             const int64_t *__restrict__ base,
-                                             const uint64_t *__restrict__ crank) {
-  const uint64_t w = rank[e];
-  const int32_t id = (int32_t)(uint32_t)w;
-  if (in_tile(id, e)) return (uint32_t)(w >> 32) + (uint32_t)(crank[exit_index(id, xid, base)] >> 32);
-  return (uint32_t)(crank[exit_index((int32_t)e, xid, base)] >> 32);
-}
-
-// Distances of both arcs of a slot, then the parent rule; default component
-// roots get P[v] = v and are counted.
+// Distances of both arcs of a slot from its record (tile pass) and the
+// contracted distances, then the parent rule; default component roots get
+// P[v] = v and are counted (unless cc is null: done by k_settle).
 template <int B>
 __global__ __launch_bounds__(B) void k_expand_parent(int64_t slots, int64_t n,
                                                           const int32_t *__restrict__ tu,
@@ -861,8 +910,16 @@ __global__ __launch_bounds__(B) void k_expand_parent(int64_t slots, int64_t n,
     const int32_t a = tu[x];
     if (a >= 0) {
       const int32_t b = tv[x];
-      const uint32_t d0 = arc_dist(2 * x, rank, xid, base, crank);
-      const uint32_t d1 = arc_dist(2 * x + 1, rank, xid, base, crank);
+      // the slot record: exit and hops of both twin arcs; with one exit the
+      // hops alone decide, else each adds its exit's contracted distance
+      const uint64_t rec = rank[x];
+      const uint32_t h0 = (uint32_t)rec, h1 = (uint32_t)(rec >> 32);
+      uint32_t d0 = h0 >> 14, d1 = h1 >> 14;
+      if ((h0 & 0x3fffu) != (h1 & 0x3fffu)) {
+        const int64_t t0 = (2 * x) & ~(int64_t)(kRankTile - 1);
+        d0 += (uint32_t)(crank[exit_index((int32_t)(t0 + (h0 & 0x3fffu)), xid, base)] >> 32);
+        d1 += (uint32_t)(crank[exit_index((int32_t)(t0 + (h1 & 0x3fffu)), xid, base)] >> 32);
+      }
       if (d0 > d1) parent[b] = a;   // a->b comes first in the tour: it descends
       else parent[a] = b;
     }
@@ -1017,14 +1074,26 @@ rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_RANK_TILE, 1);
   if (tiles <= kContractTiles) {
-    hipLaunchKernelGGL(k_rank_contract<true>, dim3((unsigned)tiles), dim3(kBlock), 0, ctx->stream,
-                       rb.exits, rb.tile_exits, rb.tile_base, tiles, rank, xid, rb.crank);
+    if (from_slots)
+      hipLaunchKernelGGL((k_rank_contract<true, true>), dim3((unsigned)tiles), dim3(kBlock), 0,
+                         ctx->stream, rb.exits, rb.tile_exits, rb.tile_base, tiles, A, rank, xid,
+                         rb.crank);
+    else
+      hipLaunchKernelGGL((k_rank_contract<true, false>), dim3((unsigned)tiles), dim3(kBlock), 0,
+                         ctx->stream, rb.exits, rb.tile_exits, rb.tile_base, tiles, A, rank, xid,
+                         rb.crank);
   } else {
     hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, ctx->stream, rb.tile_exits, tiles,
                        rb.tile_base);
     RST_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_rank_contract<false>, dim3((unsigned)tiles), dim3(kBlock), 0, ctx->stream,
-                       rb.exits, rb.tile_exits, rb.tile_base, tiles, rank, xid, rb.crank);
+    if (from_slots)
+      hipLaunchKernelGGL((k_rank_contract<false, true>), dim3((unsigned)tiles), dim3(kBlock), 0,
+                         ctx->stream, rb.exits, rb.tile_exits, rb.tile_base, tiles, A, rank, xid,
+                         rb.crank);
+    else
+      hipLaunchKernelGGL((k_rank_contract<false, false>), dim3((unsigned)tiles), dim3(kBlock), 0,
+                         ctx->stream, rb.exits, rb.tile_exits, rb.tile_base, tiles, A, rank, xid,
+                         rb.crank);
   }
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_rank_small, dim3(1), dim3(kSmallThreads), 0, ctx->stream,
