@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
                                                             SlotSrc src) {
   __shared__ int16_t ls[kRankTile];   // successor in the tile (-1 at an exit), then the arc's code
   __shared__ __align__(16) unsigned char region[kRankTile * 2];   // rulers, or the fallback's hops
-  __shared__ int s_extra, s_nexit, s_ndyn, s_or[3];
+  __shared__ int s_extra, s_nexit, s_ndyn, s_qnext, s_or[3];
   uint32_t *haspred = reinterpret_cast<uint32_t *>(region);                 // [kRankTile / 32] bits
   int16_t *r_start = reinterpret_cast<int16_t *>(region + kRankTile / 8);  // [kMaxStatic + 1]
   uint32_t *r_word = reinterpret_cast<uint32_t *>(region + kRankTile / 8 + 2 * (kMaxStatic + 1));
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * kRankTile;
   const int cnt = (int)((A - e0) < kRankTile ? (A - e0) : kRankTile);
-  if (tid == 0) { s_extra = 0; s_nexit = 0; s_ndyn = 0; s_or[0] = s_or[1] = s_or[2] = 0; }
+  if (tid == 0) { s_extra = 0; s_nexit = 0; s_ndyn = 0; s_qnext = 0; s_or[0] = s_or[1] = s_or[2] = 0; }
   for (int q = tid; q < kRankTile / 32; q += kRankThreads) haspred[q] = 0u;
   __syncthreads();
   // Thread t takes the twin pairs p = t + k * kRankThreads (arcs 2p and 2p+1
@@ -366,18 +366,20 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
   if (tid == 0) tile_exits[blockIdx.x] = s_nexit;
   const int nstatic = kStrided + s_extra;
   if (nstatic <= kMaxStatic) {
-    // the walk: lanes take the wave's share of static rulers as they free up
-    const int wid = tid >> 6;
-    const int per = (nstatic + kRankWaves - 1) / kRankWaves;
-    int qn = wid * per;
-    const int qe = min(nstatic, qn + per);
+    // the walk: lanes take static rulers from one queue of the block as they
+    // free up (one LDS atomic per wave and refill), so no wave idles while
+    // another still has a share
+    bool more = true;   // wave-uniform: the queue may hold rulers
     int q = -1, j = 0, len = 0;
     while (true) {
       const uint64_t idle = __ballot(q < 0);
-      if (qn < qe && idle != 0ull) {
-        const int r = qn + lanes_below(idle);
-        if (q < 0 && r < qe) { q = r; j = r_start[r]; len = 0; }
-        qn += (int)__popcll(idle);
+      if (more && idle != 0ull) {
+        int base = 0;
+        if ((tid & 63) == 0) base = atomicAdd(&s_qnext, (int)__popcll(idle));
+        base = __shfl(base, 0, 64);
+        const int r = base + lanes_below(idle);
+        if (q < 0 && r < nstatic) { q = r; j = r_start[r]; len = 0; }
+        more = base + (int)__popcll(idle) < nstatic;
       }
       if (__ballot(q >= 0) == 0ull) break;
       bool open = false;   // the piece reached kPiece arcs: continue as a new ruler
@@ -672,7 +674,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
                                                               uint64_t *crank, int64_t cap,
                                                               int32_t *counters) {
   __shared__ __align__(16) unsigned char s_raw[kSmBytes];
-  __shared__ int s_extra, s_ndyn, s_or[3];
+  __shared__ int s_extra, s_ndyn, s_qnext, s_or[3];
   const int tid = threadIdx.x;
   // the words are loaded before their count is known (cap = words the buffer
   // holds), so that both loads overlap
@@ -687,6 +689,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
     counters[kCntExits] = (int32_t)M;
     s_extra = 0;
     s_ndyn = 0;
+    s_qnext = 0;
     s_or[0] = s_or[1] = s_or[2] = 0;
   }
   if (M > kSmallLds) {
@@ -732,19 +735,20 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
   const int nstatic = nstr + s_extra;
   int rounds = 0;
   if (nstatic + (m + kSmallPiece - 1) / kSmallPiece <= kSmallRulers) {
-    // the walk: lanes take the wave's share of static rulers as they free up
-    const int wid = tid >> 6;
-    const int per = (nstatic + kSmallThreads / 64 - 1) / (kSmallThreads / 64);
-    int qn = wid * per;
-    const int qe = min(nstatic, qn + per);
+    // the walk: lanes take static rulers from one queue of the block as they
+    // free up (one LDS atomic per wave and refill)
+    bool more = true;
     int q = -1, j = 0, len = 0;
     uint32_t acc = 0;
     while (true) {
       const uint64_t idle = __ballot(q < 0);
-      if (qn < qe && idle != 0ull) {
-        const int r = qn + lanes_below(idle);
-        if (q < 0 && r < qe) { q = r; j = r_start[r]; len = 0; acc = 0; }
-        qn += (int)__popcll(idle);
+      if (more && idle != 0ull) {
+        int base = 0;
+        if ((tid & 63) == 0) base = atomicAdd(&s_qnext, (int)__popcll(idle));
+        base = __shfl(base, 0, 64);
+        const int r = base + lanes_below(idle);
+        if (q < 0 && r < nstatic) { q = r; j = r_start[r]; len = 0; acc = 0; }
+        more = base + (int)__popcll(idle) < nstatic;
       }
       if (__ballot(q >= 0) == 0ull) break;
       bool open = false;
