@@ -190,13 +190,19 @@ constexpr int kRankTile = 16384;
 constexpr int kRankThreads = 1024;
 constexpr int kRankPer = kRankTile / kRankThreads;     // 16 arcs (8 twin pairs) per thread
 constexpr int kRankWaves = kRankThreads / 64;
-constexpr int kRuler = 8;                              // every 8th arc starts a ruler
-constexpr int kStrided = kRankTile / kRuler;           // 2048 strided rulers
-constexpr int kPiece = 16;                             // a walk opens a new ruler after 16 arcs
-constexpr int kRulerSlots = 4096;                      // ruler ids fit 12 bits
-constexpr int kMaxRulers = kRulerSlots - 1;            // id 4095 unused: its codes could read as -1
+constexpr int kRuler = 4;                              // every 4th arc starts a ruler
+constexpr int kStrided = kRankTile / kRuler;           // 4096 strided rulers
+constexpr int kPieceBits = 3;
+constexpr int kPiece = 1 << kPieceBits;                // a walk opens a new ruler after 8 arcs
+constexpr int kRulerSlots = 1 << (16 - kPieceBits);    // 8192: ruler ids fit the other 13 bits
+constexpr int kMaxRulers = kRulerSlots - 1;            // id 8191 unused: its codes could read as -1
 // static rulers (strided + segment heads) that leave room for every opened one
 constexpr int kMaxStatic = kMaxRulers - kRankTile / kPiece;
+// the 32-bit words of a 32-arc block whose arcs are off the stride
+constexpr uint32_t kOffStride = kRuler == 4 ? 0xEEEEEEEEu : 0xFEFEFEFEu;
+// LDS region of k_rank_tile: has-predecessor bits, ruler starts, ruler words
+constexpr int kRegionBytes = kRankTile / 8 + 2 * (kMaxStatic + 1) + 4 * kRulerSlots;
+static_assert(kRuler == 4 || kRuler == 8, "stride mask");
 
 // Slot records of the tile pass over forest slots: for the twin arcs 2x and
 // 2x+1 of slot x, the local id (in the arc tile) of the segment exit each one
@@ -227,31 +233,31 @@ struct SlotSrc {            // arcs described by the forest slots (fused success
   const int32_t *tu, *tv, *next, *endsucc;
 };
 
-// Within a tile: every segment head and every 8th arc starts a ruler.  One
+// Within a tile: every segment head and every 4th arc starts a ruler.  One
 // walk per ruler follows its piece of list in LDS to the next ruler, to the
-// segment's exit, or for 16 arcs, where it opens a new ruler and goes on; every
-// arc it passes is overwritten with (ruler << 4 | offset), so a single walk
+// segment's exit, or for 8 arcs, where it opens a new ruler and goes on; every
+// arc it passes is overwritten with (ruler << 3 | offset), so a single walk
 // gives each arc its place.  Lanes of a wave take the rulers of the wave's
 // share one after another as they become free (a wave costs the sum of its
 // walks over 64 lanes, not 64 times its longest).  The rulers are then ranked
-// by in-place pointer jumping on 32-bit words (last-ruler flag, ruler reached,
-// hops); an arc's word follows from its ruler's: the exit of the last ruler of
-// the chain, and the ruler's hops less the arc's offset.  A tile with more
+// by in-place pointer jumping on 32-bit words (last-ruler flag, the ruler
+// reached -- or at the last ruler of a chain, the segment's exit -- and hops);
+// an arc's (exit, hops) follows from its ruler's: the exit its chain ends at,
+// and the ruler's hops less the arc's offset.  A tile with more
 // segment heads than static ruler slots (no locality) is ranked by plain
 // pointer jumping over all its arcs in LDS instead.
 template <bool kFromSlots>
-__global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t *rank, int32_t *xid,
+__global__ __launch_bounds__(kRankThreads, 8) void k_rank_tile(int64_t A, uint64_t *rank, int32_t *xid,
                                                             int32_t *exits, int32_t *tile_exits,
                                                             SlotSrc src) {
   __shared__ int16_t ls[kRankTile];   // successor in the tile (-1 at an exit), then the arc's code
-  __shared__ __align__(16) unsigned char region[kRankTile * 2];   // rulers, or the fallback's hops
+  __shared__ __align__(16) unsigned char region[kRegionBytes];   // rulers, or the fallback's hops
   __shared__ int s_extra, s_nexit, s_ndyn, s_qnext, s_or[3];
   uint32_t *haspred = reinterpret_cast<uint32_t *>(region);                 // [kRankTile / 32] bits
   int16_t *r_start = reinterpret_cast<int16_t *>(region + kRankTile / 8);  // [kMaxStatic + 1]
   uint32_t *r_word = reinterpret_cast<uint32_t *>(region + kRankTile / 8 + 2 * (kMaxStatic + 1));
-  int16_t *r_exit = reinterpret_cast<int16_t *>(r_word + kRulerSlots);     // [kRulerSlots]
-  static_assert(kRankTile / 8 + 2 * (kMaxStatic + 1) + 6 * kRulerSlots <= kRankTile * 2,
-                "ruler tables fit the region");
+  static_assert(kRegionBytes >= kRankTile / 8 + 2 * (kMaxStatic + 1) + 4 * kRulerSlots &&
+                kRegionBytes >= 2 * kRankTile, "ruler tables and fallback hops fit the region");
   uint16_t *dd = reinterpret_cast<uint16_t *>(region);                    // fallback: [kRankTile]
 
   const int tid = threadIdx.x;
@@ -347,7 +353,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
     if (tid < kRankTile / 32) {
       const int b0 = tid * 32;
       const uint32_t valid = b0 >= cnt ? 0u : (cnt - b0 >= 32 ? ~0u : (1u << (cnt - b0)) - 1u);
-      hb = ~haspred[tid] & valid & 0xFEFEFEFEu;
+      hb = ~haspred[tid] & valid & kOffStride;
     }
     const int c = __popc(hb);
     const int incl = wave_incl_scan(c);
@@ -396,17 +402,16 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
               fin = -1;
               ex = j;
             } else {
-              ls[j] = (int16_t)((q << 4) | len);
+              ls[j] = (int16_t)((q << kPieceBits) | len);
               j = sj & (kRankTile - 1);
               ++len;
               if ((j & (kRuler - 1)) == 0) fin = j / kRuler;
               else if (len == kPiece) open = true;
             }
           }
-          if (fin != -2) {
-            r_word[q] = fin < 0 ? (0x80000000u | ((uint32_t)q << 16) | (uint32_t)len)
+          if (fin != -2) {   // a last ruler's word holds its exit in place of a next ruler
+            r_word[q] = fin < 0 ? (0x80000000u | ((uint32_t)ex << 16) | (uint32_t)len)
                                 : (((uint32_t)fin << 16) | (uint32_t)len);
-            r_exit[q] = (int16_t)ex;
             q = -1;
           }
         }
@@ -416,12 +421,10 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
         const int x = nstatic + d;
         if (x < kMaxRulers) {
           r_word[q] = ((uint32_t)x << 16) | (uint32_t)len;
-          r_exit[q] = 0;
           q = x;
           len = 0;
         } else {   // not reached on simple lists (at most kRankTile / kPiece are opened)
-          r_word[q] = 0x80000000u | ((uint32_t)q << 16) | (uint32_t)len;
-          r_exit[q] = (int16_t)j;
+          r_word[q] = 0x80000000u | ((uint32_t)j << 16) | (uint32_t)len;
           q = -1;
         }
       }
@@ -441,7 +444,7 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
         if (r < nrul) {
           const uint32_t w = r_word[r];
           if (!(w >> 31)) {
-            const uint32_t w2 = r_word[(w >> 16) & 0xfffu];
+            const uint32_t w2 = r_word[(w >> 16) & (kRulerSlots - 1)];
             const uint32_t nw = (w2 & 0xffff0000u) | ((w + w2) & 0xffffu);
             r_word[r] = nw;
             pending |= !(nw >> 31);
@@ -465,8 +468,8 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
             const uint32_t code = (uint16_t)ls[i0 + c];
             half[c] = rec_half(i0 + c, 0u);
             if (code != 0xffffu) {
-              const uint32_t w = r_word[code >> 4];
-              half[c] = rec_half(r_exit[(w >> 16) & 0xfffu], (w & 0xffffu) - (code & 15u));
+              const uint32_t w = r_word[code >> kPieceBits];
+              half[c] = rec_half((w >> 16) & 0x3fffu, (w & 0xffffu) - (code & (kPiece - 1)));
             }
           }
           rank[(e0 + i0) >> 1] = ((uint64_t)half[1] << 32) | half[0];
@@ -481,9 +484,9 @@ __global__ __launch_bounds__(kRankThreads) void k_rank_tile(int64_t A, uint64_t 
       if (i < cnt) {
         const uint32_t c = (uint16_t)ls[i];
         if (c != 0xffffu) {
-          const uint32_t w = r_word[c >> 4];
-          const int f = (int)((w >> 16) & 0xfffu);
-          rank[e0 + i] = pack_rank((int32_t)(e0 + r_exit[f]), (w & 0xffffu) - (c & 15u));
+          const uint32_t w = r_word[c >> kPieceBits];
+          rank[e0 + i] = pack_rank((int32_t)(e0 + ((w >> 16) & 0x3fffu)),
+                                   (w & 0xffffu) - (c & (kPiece - 1)));
         }
       }
     }
@@ -658,6 +661,7 @@ constexpr int kSmallPer = 19;
 constexpr int kSmallLds = kSmallPer * kSmallThreads;    // 19456 words
 constexpr int kSmallRulers = 4096;
 constexpr int kSmallPiece = 16;
+constexpr int kSmallRuler = 8;                          // every 8th word starts a ruler
 // LDS, ruler path: successor int16 [kSmallLds] (then the word's ruler),
 // weight uint32 [kSmallLds] (then the word's distance from its ruler's start),
 // has-predecessor bits, ruler starts int16 [kSmallRulers], ruler words uint64
@@ -716,8 +720,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
     }
   }
   __syncthreads();
-  const int nstr = (m + kRuler - 1) / kRuler;
-  for (int q = tid; q < nstr; q += kSmallThreads) r_start[q] = (int16_t)(q * kRuler);
+  const int nstr = (m + kSmallRuler - 1) / kSmallRuler;
+  for (int q = tid; q < nstr; q += kSmallThreads) r_start[q] = (int16_t)(q * kSmallRuler);
   // list heads off the 8-stride, read 32 words at a time from the bits
   for (int wd = tid; wd < (kSmallLds + 31) / 32; wd += kSmallThreads) {
     const int b0 = wd * 32;
@@ -767,8 +771,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
             acc += wj;
             j = t;
             ++len;
-            if ((j & (kRuler - 1)) == 0) {
-              r_word[q] = ((uint64_t)(j / kRuler) << 32) | acc;
+            if ((j & (kSmallRuler - 1)) == 0) {
+              r_word[q] = ((uint64_t)(j / kSmallRuler) << 32) | acc;
               q = -1;
             } else if (len == kSmallPiece) {
               open = true;

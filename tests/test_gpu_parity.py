@@ -228,27 +228,27 @@ def _lists_with_heads(A, heads, rs):
 
 
 def test_list_rank_tile_rulers(ctx):
-    """In-tile ranking at its limits: a list that runs through 14336 arcs off
-    the 8-stride before reaching a strided one (hundreds of capped pieces), and
-    tiles with 1023 and 1024 segment heads off the stride (the last count that
-    the ruler walk takes and the first that goes to all-arc jumping), also in a
-    ragged multi-tile input."""
+    """In-tile ranking at its limits (rulers every 4th arc): a list that runs
+    through 12288 arcs off the stride before reaching a strided one (hundreds
+    of opened rulers), and tiles with 2047 and 2048 segment heads off the
+    stride (the last count that the ruler walk takes and the first that goes
+    to all-arc jumping), also in a ragged multi-tile input."""
     rs = np.random.RandomState(5)
-    T = 16384
+    T, S = 16384, 4
     ids = np.arange(T)
-    order = np.concatenate([ids[ids % 8 != 0], ids[ids % 8 == 0]])
+    order = np.concatenate([ids[ids % S != 0], ids[ids % S == 0]])
     succ = np.full(T, -1, np.int32)
     succ[order[:-1]] = order[1:]
     cases = [succ]
-    off_stride = ids[ids % 8 != 0]
-    for nh in (1023, 1024):
+    off_stride = ids[ids % S != 0]
+    for nh in (2047, 2048):
         heads = np.sort(rs.choice(off_stride, size=nh, replace=False))
         cases.append(_lists_with_heads(T, heads, rs))
     # three tiles and a ragged tail, each tile's lists kept inside it
     parts, base = [], 0
-    for size, nh in ((T, 1023), (T, 1), (T, 1024), (4101, 9)):
+    for size, nh in ((T, 2047), (T, 1), (T, 2048), (4101, 9)):
         loc = np.arange(size)
-        heads = np.sort(rs.choice(loc[loc % 8 != 0], size=nh, replace=False))
+        heads = np.sort(rs.choice(loc[loc % S != 0], size=nh, replace=False))
         sub = _lists_with_heads(size, heads, rs)
         parts.append(np.where(sub >= 0, sub + base, -1).astype(np.int32))
         base += size
