@@ -286,7 +286,10 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
   auto visit = [&](int src, int32_t dst) -> bool {
     const int64_t dl = (int64_t)dst - v0;
     if (dl >= 0 && dl < src) {
-      int ra = lds_find_tile(src, lp), rb = lds_find_tile((int)dl, lp);
+      // same parent, or one the other's parent: same tree, no walk needed
+      const int pa = lp[src] & kTileMask, pb = lp[dl] & kTileMask;
+      if (pa == pb || pa == (int)dl || pb == src) return false;
+      int ra = lds_find_tile(pa, lp), rb = lds_find_tile(pb, lp);
       while (ra != rb) {
         const bool a_low = hook_priority((uint32_t)(v0 + ra)) < hook_priority((uint32_t)(v0 + rb));
         const int lo = a_low ? ra : rb, hi = a_low ? rb : ra;
