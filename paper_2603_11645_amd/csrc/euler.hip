@@ -564,6 +564,17 @@ __device__ __forceinline__ int64_t exit_index(int32_t ex, const int32_t *xid, co
   return base[ex / kRankTile] + xid[ex];
 }
 
+// One workgroup ranks contracted lists of up to kSmallLds words (k_rank_small).
+// For such lists the contraction writes each word packed in 32 bits: weighted
+// hops (at most one tile's arcs, 17 bits) above the next word's index (15
+// bits, kPkEnd at a tail); longer lists get 64-bit (next, hops) words for the
+// multi-block rounds.
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallPer = 19;
+constexpr int kSmallLds = kSmallPer * kSmallThreads;    // 19456 words
+constexpr uint32_t kPkEnd = 0x7fffu;
+static_assert(kSmallLds < (int)kPkEnd && kRankTile < (1 << 17), "packed contracted words");
+
 // Contracted list over the exits (one block per tile): next exit and weighted
 // hops to it.  With kScan, every block first forms the exclusive prefix of the
 // tiles' exit counts itself (up to kContractTiles tiles, in LDS) and block b
@@ -610,13 +621,16 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
   const int64_t e0 = (int64_t)blockIdx.x * kRankTile;
   const int cntb = tile_exits[blockIdx.x];
   const int64_t b0 = bs[blockIdx.x];
+  const bool packed = bs[kScan ? kContractTiles : tiles] <= kSmallLds;   // M words in all
+  uint32_t *cpk = reinterpret_cast<uint32_t *>(crank);
   for (int j = threadIdx.x; j < cntb; j += kBlock) {
     int32_t s, ex;
     uint32_t dl = 0;
     if (kSlots) {
       s = reinterpret_cast<const int32_t *>(rank)[A + e0 + j];   // the exit's successor
       if (s < 0) {
-        crank[b0 + j] = pack_rank(-1, 0);
+        if (packed) cpk[b0 + j] = kPkEnd;
+        else crank[b0 + j] = pack_rank(-1, 0);
         continue;
       }
       const uint32_t h = (uint32_t)(rank[s >> 1] >> (32 * (s & 1)));
@@ -630,7 +644,8 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
       const int32_t x = exits[e0 + j];
       s = (int32_t)(uint32_t)rank[x];
       if (s < 0) {
-        crank[b0 + j] = pack_rank(-1, 0);
+        if (packed) cpk[b0 + j] = kPkEnd;
+        else crank[b0 + j] = pack_rank(-1, 0);
         continue;
       }
       const uint64_t ws = rank[s];
@@ -638,40 +653,58 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
       ex = s;
       if (in_tile(id, s)) { ex = id; dl = (uint32_t)(ws >> 32); }
     }
-    crank[b0 + j] = pack_rank((int32_t)exit_index(ex, xid, bs), 1u + dl);
+    const int32_t nx = (int32_t)exit_index(ex, xid, bs);
+    if (packed) cpk[b0 + j] = ((1u + dl) << 15) | (uint32_t)nx;
+    else crank[b0 + j] = pack_rank(nx, 1u + dl);
   }
 }
 
-// The contracted list (M = base[tiles] words, (successor, hops to it)) ranked
-// by one block, with no host round trip.  Like the tile pass: every 8th word
-// and every list head starts a ruler; one walk per ruler follows its piece
-// (opening a new ruler after 16 words), overwriting each word with (ruler,
-// weighted distance from the ruler's start); the rulers are ranked by in-place
-// pointer jumping on 64-bit words (last-ruler flag, next ruler, distance) and
-// every word's distance to its tail follows.  Lists with too many heads for
-// the ruler table (many small trees) are ranked by plain pointer jumping over
-// all words in LDS instead.  Longer lists (more than kSmallLds words; one CU
-// would be slower on them than multi-block rounds) raise
-// counters[kCntRankOverflow] and change nothing: the consumers then skip their
-// work and the host ranks the list in multi-block rounds.  counters[kCntExits]
-// = M, counters[kCntRankRounds] = pointer-jumping rounds.  Output: crank[i] =
-// (-1, distance from word i to the tail of its list).
-constexpr int kSmallThreads = 1024;
-constexpr int kSmallPer = 19;
-constexpr int kSmallLds = kSmallPer * kSmallThreads;    // 19456 words
+// The contracted list (M = base[tiles] words, packed (hops to the next word,
+// next word)) ranked by one block, with no host round trip.  Like the tile
+// pass: every 8th word and every list head starts a ruler; one walk per ruler
+// follows its piece (opening a new ruler after 16 words), overwriting each
+// word in place with (weighted distance from the ruler's start : 20, ruler :
+// 12); the rulers are ranked by in-place pointer jumping on 64-bit words
+// (last-ruler flag, next ruler, distance) and every word's distance to its
+// tail follows.  Lists with too many heads for the ruler table (many small
+// trees) are ranked by plain pointer jumping over all words in LDS instead.
+// Longer lists (more than kSmallLds words; one CU would be slower on them
+// than multi-block rounds) raise counters[kCntRankOverflow] and change
+// nothing: the consumers then skip their work and the host ranks the list in
+// multi-block rounds.  counters[kCntExits] = M, counters[kCntRankRounds] =
+// pointer-jumping rounds.  Output: crank[i] = (-1, distance from word i to the
+// tail of its list), 64-bit words over the packed input.
 constexpr int kSmallRulers = 4096;
 constexpr int kSmallPiece = 16;
 constexpr int kSmallRuler = 8;                          // every 8th word starts a ruler
-// LDS, ruler path: successor int16 [kSmallLds] (then the word's ruler),
-// weight uint32 [kSmallLds] (then the word's distance from its ruler's start),
-// has-predecessor bits, ruler starts int16 [kSmallRulers], ruler words uint64
-// [kSmallRulers]; all-words path: (successor, hops) uint64 [kSmallLds].
-constexpr int kSmOffW = 2 * kSmallLds;
-constexpr int kSmOffHp = kSmOffW + 4 * kSmallLds;
-constexpr int kSmOffRs = kSmOffHp + kSmallLds / 8;
+// LDS, ruler path: words uint32 [kSmallLds + 64] (the last 64 are a slot per
+// lane for idle lanes' accesses), has-predecessor bytes [kSmallLds], ruler
+// starts int16 [kSmallRulers], ruler words uint64 [kSmallRulers]; all-words
+// path: (successor, hops) uint64 [kSmallLds].
+constexpr int kSmOffHp = 4 * (kSmallLds + 64);
+constexpr int kSmOffRs = kSmOffHp + kSmallLds;
 constexpr int kSmOffRw = kSmOffRs + 2 * kSmallRulers;
-constexpr int kSmBytes = kSmOffRw + 8 * kSmallRulers;
-static_assert(kSmOffRw % 8 == 0 && kSmBytes >= 8 * kSmallLds, "ruler path LDS layout");
+constexpr int kSmBytes = (kSmOffRw + 8 * kSmallRulers) > 8 * kSmallLds ? (kSmOffRw + 8 * kSmallRulers)
+                                                                       : 8 * kSmallLds;
+static_assert(kSmOffHp % 16 == 0 && kSmallLds % 32 == 0 && kSmOffRw % 8 == 0, "ruler path LDS layout");
+constexpr int kWalkSteps = 3;   // steps of every walk between two refills
+constexpr bool kWaveShare = true;   // each wave walks its own range of static rulers
+constexpr int kAsyncIters = 16;     // barrier-free jumping rounds before the synchronous ones
+
+// bit k of the result set where byte k of the 32 bytes at b (0 or 1 each) is set
+__device__ __forceinline__ uint32_t byte_flags32(const unsigned char *b) {
+  const uint4 lo = *reinterpret_cast<const uint4 *>(b);
+  const uint4 hi = *reinterpret_cast<const uint4 *>(b + 16);
+  const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  uint32_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t x = w[k];
+    r |= ((x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xfu) << (4 * k);
+  }
+  return r;
+}
+static_assert(kSmallRulers <= 4096 && kSmallPiece * kRankTile < (1 << 20), "walk word fields");
 constexpr uint64_t kSmFinal = 1ull << 63;
 
 __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__restrict__ Mp,
@@ -680,13 +713,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
   __shared__ __align__(16) unsigned char s_raw[kSmBytes];
   __shared__ int s_extra, s_ndyn, s_qnext, s_or[3];
   const int tid = threadIdx.x;
-  // the words are loaded before their count is known (cap = words the buffer
-  // holds), so that both loads overlap
-  uint64_t own[kSmallPer];
+  // the words are loaded before their count is known (cap = 64-bit words the
+  // buffer holds), so that both loads overlap
+  const uint32_t *cpk = reinterpret_cast<const uint32_t *>(crank);
+  uint32_t own[kSmallPer];
 #pragma unroll
   for (int k = 0; k < kSmallPer; ++k) {
     const int i = tid + k * kSmallThreads;
-    own[k] = i < cap ? crank[i] : pack_rank(-1, 0);
+    own[k] = i < 2 * cap ? cpk[i] : kPkEnd;
   }
   const int64_t M = *Mp;
   if (tid == 0) {
@@ -701,22 +735,25 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
     return;
   }
   const int m = (int)M;
-  int16_t *sc = reinterpret_cast<int16_t *>(s_raw);
-  uint32_t *wt = reinterpret_cast<uint32_t *>(s_raw + kSmOffW);
-  uint32_t *haspred = reinterpret_cast<uint32_t *>(s_raw + kSmOffHp);
+  // out-of-range successors end the list; words past the list end at once
+#pragma unroll
+  for (int k = 0; k < kSmallPer; ++k)
+    if (tid + k * kSmallThreads >= m || (int)(own[k] & kPkEnd) >= m) own[k] |= kPkEnd;
+  uint32_t *L = reinterpret_cast<uint32_t *>(s_raw);
+  unsigned char *haspred = s_raw + kSmOffHp;
   int16_t *r_start = reinterpret_cast<int16_t *>(s_raw + kSmOffRs);
   uint64_t *r_word = reinterpret_cast<uint64_t *>(s_raw + kSmOffRw);
-  for (int q = tid; q < kSmallLds / 32; q += kSmallThreads) haspred[q] = 0u;
+  for (int q = tid; q < kSmallLds / 16; q += kSmallThreads)
+    reinterpret_cast<uint4 *>(haspred)[q] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
+  // plain byte stores mark the successors (an LDS atomic per word serialises)
 #pragma unroll
   for (int k = 0; k < kSmallPer; ++k) {
     const int i = tid + k * kSmallThreads;
     if (i < m) {
-      int32_t t = (int32_t)(uint32_t)own[k];
-      if (t >= m) t = -1;   // out-of-range successors end the list
-      sc[i] = (int16_t)t;
-      wt[i] = (uint32_t)(own[k] >> 32);
-      if (t >= 0) atomicOr(&haspred[t >> 5], 1u << (t & 31));
+      const uint32_t t = own[k] & kPkEnd;
+      L[i] = own[k];
+      if (t != kPkEnd) haspred[t] = 1;
     }
   }
   __syncthreads();
@@ -726,7 +763,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
   for (int wd = tid; wd < (kSmallLds + 31) / 32; wd += kSmallThreads) {
     const int b0 = wd * 32;
     const uint32_t valid = b0 >= m ? 0u : (m - b0 >= 32 ? ~0u : (1u << (m - b0)) - 1u);
-    uint32_t hb = ~haspred[wd] & valid & 0xFEFEFEFEu;
+    uint32_t hb = ~byte_flags32(haspred + b0) & valid & 0xFEFEFEFEu;
     int x = hb ? atomicAdd(&s_extra, __popc(hb)) : 0;
     while (hb) {
       const int bit = __ffs(hb) - 1;
@@ -739,46 +776,54 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
   const int nstatic = nstr + s_extra;
   int rounds = 0;
   if (nstatic + (m + kSmallPiece - 1) / kSmallPiece <= kSmallRulers) {
-    // the walk: lanes take static rulers from one queue of the block as they
-    // free up (one LDS atomic per wave and refill)
-    bool more = true;
+    // the walk: lanes take the next static ruler as they free up, from their
+    // wave's own range (no atomics; the ranges hold about equal work) or from
+    // one queue of the block (one LDS atomic per wave and refill)
+    constexpr int kWaves = kSmallThreads / 64;
+    const int share = (nstatic + kWaves - 1) / kWaves;
+    int qnext = kWaveShare ? __builtin_amdgcn_readfirstlane(tid >> 6) * share : 0;
+    const int qend = kWaveShare ? min(qnext + share, nstatic) : nstatic;
+    bool more = qnext < qend;
     int q = -1, j = 0, len = 0;
     uint32_t acc = 0;
+    const int dummy = kSmallLds + (tid & 63);
     while (true) {
       const uint64_t idle = __ballot(q < 0);
       if (more && idle != 0ull) {
-        int base = 0;
-        if ((tid & 63) == 0) base = atomicAdd(&s_qnext, (int)__popcll(idle));
-        base = __shfl(base, 0, 64);
+        int base = qnext;
+        if (!kWaveShare) {
+          if ((tid & 63) == 0) base = atomicAdd(&s_qnext, (int)__popcll(idle));
+          base = __shfl(base, 0, 64);
+        }
         const int r = base + lanes_below(idle);
-        if (q < 0 && r < nstatic) { q = r; j = r_start[r]; len = 0; acc = 0; }
-        more = base + (int)__popcll(idle) < nstatic;
+        if (q < 0 && r < qend) { q = r; j = r_start[r]; len = 0; acc = 0; }
+        qnext = base + (int)__popcll(idle);
+        more = qnext < qend;
       }
       if (__ballot(q >= 0) == 0ull) break;
       bool open = false;
-      // two steps of the walk per round of the loop's wave-wide bookkeeping
+      // kWalkSteps steps per round of the wave-wide bookkeeping, written with
+      // selects (idle lanes read and write their own spare word) so that the
+      // steps need no branches
 #pragma unroll
-      for (int rep = 0; rep < 2; ++rep) {
-        if (q >= 0 && !open) {
-          const int t = sc[j];
-          const uint32_t wj = wt[j];
-          sc[j] = (int16_t)q;
-          wt[j] = acc;
-          if (t < 0) {                       // the tail: its ruler is the last of the chain
-            r_word[q] = kSmFinal | ((uint64_t)q << 32) | acc;
-            q = -1;
-          } else {
-            acc += wj;
-            j = t;
-            ++len;
-            if ((j & (kSmallRuler - 1)) == 0) {
-              r_word[q] = ((uint64_t)(j / kSmallRuler) << 32) | acc;
-              q = -1;
-            } else if (len == kSmallPiece) {
-              open = true;
-            }
-          }
-        }
+      for (int rep = 0; rep < kWalkSteps; ++rep) {
+        const bool act = q >= 0 && !open;
+        const int jj = act ? j : dummy;
+        const uint32_t p = L[jj];
+        L[jj] = (acc << 12) | ((uint32_t)q & (kSmallRulers - 1));
+        const uint32_t t = p & kPkEnd;
+        const bool end = t == kPkEnd;                       // the tail: last ruler of the chain
+        const bool str = (t & (kSmallRuler - 1)) == 0;      // reaches the next static ruler
+        const uint32_t nacc = acc + (p >> 15);
+        const bool stop = act && (end || str);
+        const uint32_t rw_hi = end ? (0x80000000u | (uint32_t)q) : t / kSmallRuler;
+        const uint32_t rw_lo = end ? acc : nacc;
+        if (stop) r_word[q] = ((uint64_t)rw_hi << 32) | rw_lo;
+        open = open || (act && !end && !str && len == kSmallPiece - 1);
+        q = stop ? -1 : q;
+        j = act ? (int)t : j;
+        acc = act ? nacc : acc;
+        len = act ? len + 1 : len;
       }
       const int d = wave_append(open, &s_ndyn);
       if (open) {
@@ -797,9 +842,38 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
     __syncthreads();
     const int nrul = min(nstatic + s_ndyn, kSmallRulers);
     // pointer jumping over the rulers, in place (a word read while its owner
-    // rewrites it is either version, both consistent); three rotating flags
-    // let one barrier a round suffice
+    // rewrites it is either version, both consistent).  First without
+    // barriers: each thread advances its own words, reading whatever version
+    // of the others' it finds (every version is a true (ruler reached,
+    // distance) pair, so any interleaving only speeds the jumps up), for at
+    // most kAsyncIters rounds; then barrier-separated rounds finish (three
+    // rotating flags let one barrier a round suffice), usually in one.
     constexpr int QP = kSmallRulers / kSmallThreads;
+    if (kAsyncIters > 0) {
+      uint64_t ownw[QP];
+#pragma unroll
+      for (int k = 0; k < QP; ++k) {
+        const int r = tid + k * kSmallThreads;
+        ownw[k] = r < nrul ? r_word[r] : kSmFinal;
+      }
+      for (int it = 0; it < kAsyncIters; ++it) {
+        ++rounds;
+        bool pending = false;
+#pragma unroll
+        for (int k = 0; k < QP; ++k) {
+          if (!(ownw[k] & kSmFinal)) {
+            const uint64_t w2 = __hip_atomic_load(&r_word[(ownw[k] >> 32) & (kSmallRulers - 1)],
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            ownw[k] = (w2 & 0xffffffff00000000ull) | (uint32_t)((uint32_t)ownw[k] + (uint32_t)w2);
+            __hip_atomic_store(&r_word[tid + k * kSmallThreads], ownw[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+            pending |= !(ownw[k] & kSmFinal);
+          }
+        }
+        if (__ballot(pending) == 0ull) break;
+      }
+      __syncthreads();
+    }
     for (int round = 0; round < 14; ++round) {
       bool pending = false;
 #pragma unroll
@@ -825,36 +899,40 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
     for (int k = 0; k < kSmallPer; ++k) {
       const int i = tid + k * kSmallThreads;
       if (i < m) {
-        const uint32_t dist = (uint32_t)r_word[sc[i] & (kSmallRulers - 1)] - wt[i];
+        const uint32_t c = L[i];
+        const uint32_t dist = (uint32_t)r_word[c & (kSmallRulers - 1)] - (c >> 12);
         crank[i] = pack_rank(-1, dist);
       }
     }
   } else {
-    // all-words pointer jumping: each thread keeps its own words in registers;
-    // a round gathers the successors' words from LDS, then (after a barrier)
-    // publishes its own.  ceil(log2 M) rounds suffice; the cap also ends the
-    // loop on malformed (cyclic) input.
+    // all-words pointer jumping: each thread keeps its own words in registers
+    // as 64-bit (next, hops); a round gathers the successors' words from LDS,
+    // then (after a barrier) publishes its own.  ceil(log2 M) rounds suffice;
+    // the cap also ends the loop on malformed (cyclic) input.
     int max_rounds = 1;
     while (((int64_t)1 << max_rounds) < M) ++max_rounds;
     uint64_t *s_word = reinterpret_cast<uint64_t *>(s_raw);
+    uint64_t ow[kSmallPer];
+#pragma unroll
+    for (int k = 0; k < kSmallPer; ++k) {
+      const uint32_t t = own[k] & kPkEnd;
+      ow[k] = pack_rank(t == kPkEnd ? -1 : (int32_t)t, own[k] >> 15);
+    }
     __syncthreads();   // every thread is done with the ruler tables
 #pragma unroll
     for (int k = 0; k < kSmallPer; ++k) {
       const int i = tid + k * kSmallThreads;
-      if (i < m) {
-        if ((int32_t)(uint32_t)own[k] >= m) own[k] = pack_rank(-1, (uint32_t)(own[k] >> 32));
-        s_word[i] = own[k];
-      }
+      if (i < m) s_word[i] = ow[k];
     }
     __syncthreads();
     for (int round = 0; round < max_rounds; ++round) {
       bool more = false;
 #pragma unroll
       for (int k = 0; k < kSmallPer; ++k) {
-        const int32_t t = (int32_t)(uint32_t)own[k];
+        const int32_t t = (int32_t)(uint32_t)ow[k];
         if (t >= 0) {
           const uint64_t nb = s_word[t];
-          own[k] = (((own[k] >> 32) + (nb >> 32)) << 32) | (nb & 0xffffffffull);
+          ow[k] = (((ow[k] >> 32) + (nb >> 32)) << 32) | (nb & 0xffffffffull);
           more |= (int32_t)(uint32_t)nb >= 0;
         }
       }
@@ -862,7 +940,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
 #pragma unroll
       for (int k = 0; k < kSmallPer; ++k) {
         const int i = tid + k * kSmallThreads;
-        if (i < m) s_word[i] = own[k];
+        if (i < m) s_word[i] = ow[k];
       }
       ++rounds;
       if (more) s_or[round % 3] = 1;
@@ -873,7 +951,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_rank_small(const int64_t *__r
 #pragma unroll
     for (int k = 0; k < kSmallPer; ++k) {
       const int i = tid + k * kSmallThreads;
-      if (i < m) crank[i] = own[k];
+      if (i < m) crank[i] = ow[k];
     }
   }
   if (tid == 0) counters[kCntRankRounds] = rounds;
