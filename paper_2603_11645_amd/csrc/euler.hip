@@ -35,6 +35,20 @@ __device__ __forceinline__ uint64_t pack_rank(int32_t succ, uint32_t hops) {
   return ((uint64_t)hops << 32) | (uint32_t)succ;
 }
 
+// bit k of the result set where byte k of the 32 bytes at b (0 or 1 each) is set
+__device__ __forceinline__ uint32_t byte_flags32(const unsigned char *b) {
+  const uint4 lo = *reinterpret_cast<const uint4 *>(b);
+  const uint4 hi = *reinterpret_cast<const uint4 *>(b + 16);
+  const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+  uint32_t r = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t x = w[k];
+    r |= ((x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xfu) << (4 * k);
+  }
+  return r;
+}
+
 __device__ __forceinline__ bool is_root(int32_t v, const int32_t *cc, const int32_t *comp_root) {
   const int32_t c = cc[v];
   const int32_t d = comp_root[c];
@@ -201,7 +215,7 @@ constexpr int kMaxStatic = kMaxRulers - kRankTile / kPiece;
 // the 32-bit words of a 32-arc block whose arcs are off the stride
 constexpr uint32_t kOffStride = kRuler == 4 ? 0xEEEEEEEEu : 0xFEFEFEFEu;
 // LDS region of k_rank_tile: has-predecessor bits, ruler starts, ruler words
-constexpr int kRegionBytes = kRankTile / 8 + 2 * (kMaxStatic + 1) + 4 * kRulerSlots;
+constexpr int kRegionBytes = 2 * (kMaxStatic + 1) + 4 * kRulerSlots;
 static_assert(kRuler == 4 || kRuler == 8, "stride mask");
 
 // Slot records of the tile pass over forest slots: for the twin arcs 2x and
@@ -253,18 +267,21 @@ __global__ __launch_bounds__(kRankThreads, 8) void k_rank_tile(int64_t A, uint64
   __shared__ int16_t ls[kRankTile];   // successor in the tile (-1 at an exit), then the arc's code
   __shared__ __align__(16) unsigned char region[kRegionBytes];   // rulers, or the fallback's hops
   __shared__ int s_extra, s_nexit, s_ndyn, s_qnext, s_or[3];
-  uint32_t *haspred = reinterpret_cast<uint32_t *>(region);                 // [kRankTile / 32] bits
-  int16_t *r_start = reinterpret_cast<int16_t *>(region + kRankTile / 8);  // [kMaxStatic + 1]
-  uint32_t *r_word = reinterpret_cast<uint32_t *>(region + kRankTile / 8 + 2 * (kMaxStatic + 1));
-  static_assert(kRegionBytes >= kRankTile / 8 + 2 * (kMaxStatic + 1) + 4 * kRulerSlots &&
-                kRegionBytes >= 2 * kRankTile, "ruler tables and fallback hops fit the region");
+  int16_t *r_start = reinterpret_cast<int16_t *>(region);                  // [kMaxStatic + 1]
+  uint32_t *r_word = reinterpret_cast<uint32_t *>(region + 2 * (kMaxStatic + 1));
+  // until the walk, the ruler words' space holds one has-predecessor byte per arc
+  unsigned char *haspred = reinterpret_cast<unsigned char *>(r_word);
+  static_assert(kRegionBytes >= 2 * (kMaxStatic + 1) + 4 * kRulerSlots && 4 * kRulerSlots >= kRankTile &&
+                (2 * (kMaxStatic + 1)) % 16 == 0 && kRegionBytes >= 2 * kRankTile,
+                "ruler tables, predecessor bytes and fallback hops fit the region");
   uint16_t *dd = reinterpret_cast<uint16_t *>(region);                    // fallback: [kRankTile]
 
   const int tid = threadIdx.x;
   const int64_t e0 = (int64_t)blockIdx.x * kRankTile;
   const int cnt = (int)((A - e0) < kRankTile ? (A - e0) : kRankTile);
   if (tid == 0) { s_extra = 0; s_nexit = 0; s_ndyn = 0; s_qnext = 0; s_or[0] = s_or[1] = s_or[2] = 0; }
-  for (int q = tid; q < kRankTile / 32; q += kRankThreads) haspred[q] = 0u;
+  for (int q = tid; q < kRankTile / 16; q += kRankThreads)
+    reinterpret_cast<uint4 *>(haspred)[q] = make_uint4(0u, 0u, 0u, 0u);
   __syncthreads();
   // Thread t takes the twin pairs p = t + k * kRankThreads (arcs 2p and 2p+1
   // of the tile), four pairs per half; the loads of a half are issued
@@ -326,7 +343,7 @@ __global__ __launch_bounds__(kRankThreads, 8) void k_rank_tile(int64_t A, uint64
           const int64_t sl = (int64_t)sc - e0;
           if (sc >= 0 && sl >= 0 && sl < cnt) {
             lv[c] = (uint32_t)sl;
-            atomicOr(&haspred[sl >> 5], 1u << (sl & 31));
+            haspred[sl] = 1;   // a plain byte store: an LDS atomic per arc serialises
           } else {
             is_exit = true;
           }
@@ -347,13 +364,13 @@ __global__ __launch_bounds__(kRankThreads, 8) void k_rank_tile(int64_t A, uint64
   // strided rulers own slots 0..kStrided-1; heads off the stride get the next ones
   for (int q = tid; q < kStrided; q += kRankThreads) r_start[q] = (int16_t)(q * kRuler);
   {
-    // thread t < kRankTile / 32 reads word t of the has-predecessor bits:
-    // arcs of the tile without a predecessor, off the 8-stride
+    // thread t < kRankTile / 32 reads the has-predecessor bytes of arcs
+    // 32t..32t+31: arcs of the tile without a predecessor, off the stride
     uint32_t hb = 0u;
     if (tid < kRankTile / 32) {
       const int b0 = tid * 32;
       const uint32_t valid = b0 >= cnt ? 0u : (cnt - b0 >= 32 ? ~0u : (1u << (cnt - b0)) - 1u);
-      hb = ~haspred[tid] & valid & kOffStride;
+      hb = ~byte_flags32(haspred + b0) & valid & kOffStride;
     }
     const int c = __popc(hb);
     const int incl = wave_incl_scan(c);
@@ -691,19 +708,6 @@ constexpr int kWalkSteps = 3;   // steps of every walk between two refills
 constexpr bool kWaveShare = true;   // each wave walks its own range of static rulers
 constexpr int kAsyncIters = 16;     // barrier-free jumping rounds before the synchronous ones
 
-// bit k of the result set where byte k of the 32 bytes at b (0 or 1 each) is set
-__device__ __forceinline__ uint32_t byte_flags32(const unsigned char *b) {
-  const uint4 lo = *reinterpret_cast<const uint4 *>(b);
-  const uint4 hi = *reinterpret_cast<const uint4 *>(b + 16);
-  const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
-  uint32_t r = 0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint32_t x = w[k];
-    r |= ((x | (x >> 7) | (x >> 14) | (x >> 21)) & 0xfu) << (4 * k);
-  }
-  return r;
-}
 static_assert(kSmallRulers <= 4096 && kSmallPiece * kRankTile < (1 << 20), "walk word fields");
 constexpr uint64_t kSmFinal = 1ull << 63;
 
