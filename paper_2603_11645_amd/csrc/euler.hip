@@ -203,6 +203,9 @@ __global__ __launch_bounds__(kBlock) void k_rank_round(int64_t A, uint64_t *rank
 constexpr int kRankTile = 16384;
 constexpr int kRankThreads = 1024;
 constexpr int kRankPer = kRankTile / kRankThreads;     // 16 arcs (8 twin pairs) per thread
+constexpr int kTileWalkSteps = 2;      // walk steps between two refills
+constexpr bool kTileWaveShare = false; // rulers from the block's queue
+constexpr int kTileAsync = 12;         // barrier-free jumping rounds before the synchronous ones
 constexpr int kRankWaves = kRankThreads / 64;
 constexpr int kRuler = 4;                              // every 4th arc starts a ruler
 constexpr int kStrided = kRankTile / kRuler;           // 4096 strided rulers
@@ -264,7 +267,9 @@ template <bool kFromSlots>
 __global__ __launch_bounds__(kRankThreads, 8) void k_rank_tile(int64_t A, uint64_t *rank, int32_t *xid,
                                                             int32_t *exits, int32_t *tile_exits,
                                                             SlotSrc src) {
-  __shared__ int16_t ls[kRankTile];   // successor in the tile (-1 at an exit), then the arc's code
+  // successor in the tile (-1 at an exit), then the arc's code; the last 64
+  // entries are a spare slot per lane for idle lanes' accesses during the walk
+  __shared__ int16_t ls[kRankTile + 64];
   __shared__ __align__(16) unsigned char region[kRegionBytes];   // rulers, or the fallback's hops
   __shared__ int s_extra, s_nexit, s_ndyn, s_qnext, s_or[3];
   int16_t *r_start = reinterpret_cast<int16_t *>(region);                  // [kMaxStatic + 1]
@@ -389,49 +394,54 @@ __global__ __launch_bounds__(kRankThreads, 8) void k_rank_tile(int64_t A, uint64
   if (tid == 0) tile_exits[blockIdx.x] = s_nexit;
   const int nstatic = kStrided + s_extra;
   if (nstatic <= kMaxStatic) {
-    // the walk: lanes take static rulers from one queue of the block as they
-    // free up (one LDS atomic per wave and refill), so no wave idles while
-    // another still has a share
-    bool more = true;   // wave-uniform: the queue may hold rulers
+    // the walk: lanes take static rulers as they free up, from one queue of
+    // the block (one LDS atomic per wave and refill: no wave idles while
+    // another still has a share) or from their wave's own range
+    constexpr int kWaves = kRankThreads / 64;
+    const int share = (nstatic + kWaves - 1) / kWaves;
+    int qnext = kTileWaveShare ? __builtin_amdgcn_readfirstlane(tid >> 6) * share : 0;
+    const int qend = kTileWaveShare ? min(qnext + share, nstatic) : nstatic;
+    bool more = qnext < qend;   // wave-uniform: the queue may hold rulers
     int q = -1, j = 0, len = 0;
+    const int dummy = kRankTile + (tid & 63);
     while (true) {
       const uint64_t idle = __ballot(q < 0);
       if (more && idle != 0ull) {
-        int base = 0;
-        if ((tid & 63) == 0) base = atomicAdd(&s_qnext, (int)__popcll(idle));
-        base = __shfl(base, 0, 64);
+        int base = qnext;
+        if (!kTileWaveShare) {
+          if ((tid & 63) == 0) base = atomicAdd(&s_qnext, (int)__popcll(idle));
+          base = __shfl(base, 0, 64);
+        }
         const int r = base + lanes_below(idle);
-        if (q < 0 && r < nstatic) { q = r; j = r_start[r]; len = 0; }
-        more = base + (int)__popcll(idle) < nstatic;
+        if (q < 0 && r < qend) { q = r; j = r_start[r]; len = 0; }
+        qnext = base + (int)__popcll(idle);
+        more = qnext < qend;
       }
       if (__ballot(q >= 0) == 0ull) break;
       bool open = false;   // the piece reached kPiece arcs: continue as a new ruler
-      // two steps of the walk per round of the loop's wave-wide bookkeeping
+      // kTileWalkSteps steps per round of the wave-wide bookkeeping, written
+      // with selects (idle lanes read and write their own spare entry)
 #pragma unroll
-      for (int rep = 0; rep < 2; ++rep) {
-        if (q >= 0 && !open) {
-          int fin = -2, ex = 0;   // -2 walking on, -1 ended at an exit, else the next ruler
-          if (j >= cnt) {
-            fin = -1;             // strided ruler past the end of a short tile
-          } else {
-            const int sj = ls[j];
-            if (sj < 0) {
-              fin = -1;
-              ex = j;
-            } else {
-              ls[j] = (int16_t)((q << kPieceBits) | len);
-              j = sj & (kRankTile - 1);
-              ++len;
-              if ((j & (kRuler - 1)) == 0) fin = j / kRuler;
-              else if (len == kPiece) open = true;
-            }
-          }
-          if (fin != -2) {   // a last ruler's word holds its exit in place of a next ruler
-            r_word[q] = fin < 0 ? (0x80000000u | ((uint32_t)ex << 16) | (uint32_t)len)
-                                : (((uint32_t)fin << 16) | (uint32_t)len);
-            q = -1;
-          }
-        }
+      for (int rep = 0; rep < kTileWalkSteps; ++rep) {
+        const bool act = q >= 0 && !open;
+        const bool inr = j < cnt;          // a strided ruler past the end of a short tile ends at once
+        const int jj = (act && inr) ? j : dummy;
+        const int sj = ls[jj];
+        const bool isexit = !inr || sj < 0;
+        ls[jj] = isexit ? (int16_t)sj : (int16_t)((q << kPieceBits) | len);
+        const int nj = sj & (kRankTile - 1);
+        const bool str = !isexit && (nj & (kRuler - 1)) == 0;
+        const int len1 = len + 1;
+        const bool stop = act && (isexit || str);
+        // a last ruler's word holds its exit in place of a next ruler
+        const uint32_t rw = isexit ? (0x80000000u | ((uint32_t)(inr ? j : 0) << 16) | (uint32_t)len)
+                                   : (((uint32_t)(nj / kRuler) << 16) | (uint32_t)len1);
+        if (stop) r_word[q] = rw;
+        const bool step = act && !isexit;
+        open = open || (step && !str && len1 == kPiece);
+        q = stop ? -1 : q;
+        j = step ? nj : j;
+        len = step ? len1 : len;
       }
       const int d = wave_append(open, &s_ndyn);
       if (open) {
@@ -450,9 +460,37 @@ __global__ __launch_bounds__(kRankThreads, 8) void k_rank_tile(int64_t A, uint64
     const int nrul = min(nstatic + s_ndyn, kMaxRulers);
     // pointer jumping over the rulers, in place: a word read while its owner
     // rewrites it is either version, and both are consistent (ruler, hops)
-    // pairs.  Round flags rotate over three words so that one barrier a round
-    // suffices: the flag cleared in a round was last read two rounds earlier.
+    // pairs.  First without barriers (each thread advances its own words on
+    // whatever versions of the others' it finds, which only speeds the jumps
+    // up) for at most kTileAsync rounds, then barrier-separated rounds finish,
+    // usually in one.  Round flags rotate over three words so that one
+    // barrier a round suffices: the flag cleared in a round was last read two
+    // rounds earlier.
     constexpr int QP = kRulerSlots / kRankThreads;
+    if (kTileAsync > 0) {
+      uint32_t ownw[QP];
+#pragma unroll
+      for (int k = 0; k < QP; ++k) {
+        const int r = tid + k * kRankThreads;
+        ownw[k] = r < nrul ? r_word[r] : 0x80000000u;
+      }
+      for (int it = 0; it < kTileAsync; ++it) {
+        bool pending = false;
+#pragma unroll
+        for (int k = 0; k < QP; ++k) {
+          if (!(ownw[k] >> 31)) {
+            const uint32_t w2 = __hip_atomic_load(&r_word[(ownw[k] >> 16) & (kRulerSlots - 1)],
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            ownw[k] = (w2 & 0xffff0000u) | ((ownw[k] + w2) & 0xffffu);
+            __hip_atomic_store(&r_word[tid + k * kRankThreads], ownw[k], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+            pending |= !(ownw[k] >> 31);
+          }
+        }
+        if (__ballot(pending) == 0ull) break;
+      }
+      __syncthreads();
+    }
     for (int round = 0; round < 13; ++round) {
       bool pending = false;
 #pragma unroll

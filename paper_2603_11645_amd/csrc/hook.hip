@@ -214,11 +214,29 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
   for (int i = tid; i < kTile; i += kTileThreads) { lp[i] = i; ev[i] = -1; }
   if (tid == 0) { s_ncross = 0; s_lmin = 63; s_lmax = -1; s_gap = 0; }
   // all offsets of the tile in one round trip: thread t owns vertices 8t..8t+7
+  // (read as 16-byte vectors when the offsets are 16-byte aligned)
   OffT o[kTilePer + 1];
+  if ((vec_cols & 2) && tid * kTilePer + kTilePer <= cnt) {
+    const int4 *o4 = reinterpret_cast<const int4 *>(off + v0 + tid * kTilePer);
+    constexpr int PV = 16 / (int)sizeof(OffT);
 #pragma unroll
-  for (int j = 0; j <= kTilePer; ++j) {
-    const int li = tid * kTilePer + j;
-    o[j] = li <= cnt ? off[v0 + li] : (OffT)0;
+    for (int q = 0; q < kTilePer / PV; ++q) {
+      const int4 w = o4[q];
+      if (PV == 4) {
+        o[4 * q] = (OffT)w.x; o[4 * q + 1] = (OffT)w.y;
+        o[4 * q + 2] = (OffT)w.z; o[4 * q + 3] = (OffT)w.w;
+      } else {
+        o[2 * q] = (OffT)(((uint64_t)(uint32_t)w.y << 32) | (uint32_t)w.x);
+        o[2 * q + 1] = (OffT)(((uint64_t)(uint32_t)w.w << 32) | (uint32_t)w.z);
+      }
+    }
+    o[kTilePer] = off[v0 + tid * kTilePer + kTilePer];
+  } else {
+#pragma unroll
+    for (int j = 0; j <= kTilePer; ++j) {
+      const int li = tid * kTilePer + j;
+      o[j] = li <= cnt ? off[v0 + li] : (OffT)0;
+    }
   }
   int dg[kTilePer];
   int mine = 0;
@@ -328,7 +346,7 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const int64_t q = pa + 4 * v;
-        if (vec_cols && q + 4 <= pend) {
+        if ((vec_cols & 1) && q + 4 <= pend) {
           const int4 x = *reinterpret_cast<const int4 *>(cols + q);
           cv[4 * v] = x.x; cv[4 * v + 1] = x.y; cv[4 * v + 2] = x.z; cv[4 * v + 3] = x.w;
         } else {
@@ -1072,7 +1090,8 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
   int2 *kept_list = reinterpret_cast<int2 *>(tile_lvl + ((tc + 1) & ~size_t(1)));
   const int64_t n = g->n;
   const unsigned tiles = grid_for(n, kTile);
-  const int vec_cols = ((uintptr_t)g->cols & 15) == 0;   // 16-byte loads of cols allowed
+  // bit 0: 16-byte loads of cols allowed, bit 1: of the offsets
+  const int vec_cols = (((uintptr_t)g->cols & 15) == 0 ? 1 : 0) | (((uintptr_t)g->offsets & 15) == 0 ? 2 : 0);
   int levels = 0;
   while ((1u << levels) < tiles) ++levels;
   if (g->offset_bytes == 4) {

@@ -215,6 +215,29 @@ def test_spanning_tree_unaligned_cols(ctx, shift):
         assert code == 0, (oracle.VERIFY_CODES[code], bad)
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_spanning_tree_unaligned_offsets(ctx, shift):
+    """Offsets (4- and 8-byte) at an address that is not 16-byte aligned: the
+    tile pass reads them without vector loads; labels and the parent array
+    must come out right."""
+    for g in (I.road_mesh(160, 0.15, 0.01, seed=9), I.grid(100, 300, 0.2, seed=4)):
+        cols = dev(g.cols)
+        for dt in (torch.int32, torch.int64):
+            o = torch.from_numpy(g.offsets.astype(np.int64)).to(dt)
+            buf = torch.zeros(g.n + 1 + shift, dtype=dt, device="cuda")
+            buf[shift:] = o.cuda()
+            off = buf[shift:]
+            # int64 with shift 2 lands on a 16-byte boundary again (vector path)
+            assert (off.data_ptr() % 16 == 0) == (shift * off.element_size() % 16 == 0)
+            k_ref, lab_ref = oracle.components(g.n, g.offsets, g.cols)
+            label, k = ctx.components(off, cols)
+            assert k == k_ref and np.array_equal(label.cpu().numpy(), lab_ref)
+            par = ctx.spanning_tree(off, cols, 3, "gconn").cpu().numpy()
+            code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, par, [3])
+            assert code == 0, (oracle.VERIFY_CODES[code], bad)
+
+
 def _lists_with_heads(A, heads, rs):
     """Lists over 0..A-1 whose first elements are exactly `heads` (the other
     ids follow in random order, split among the lists)."""
