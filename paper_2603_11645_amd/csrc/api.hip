@@ -116,6 +116,7 @@ struct GconnWork {
   int32_t *xid;
   int32_t *endsucc;
   bool settled = false;   // k_settle ran (one root): components' own parents and count done
+  bool exported = false;  // the device work ends by writing the counters to host_pinned
   RankBufs rb;
 };
 
@@ -189,7 +190,8 @@ static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, 
                                int64_t *components, GconnWork &w) {
   const int64_t n = g->n;
   int32_t *counters = w.f.counters;
-  RST_TRY(read_counters(ctx, counters));
+  if (w.exported) RST_HIP(hipStreamSynchronize(ctx->stream));
+  else RST_TRY(read_counters(ctx, counters));
   const bool rank_fallback = ctx->host_pinned[kCntRankOverflow] != 0;
   if (rank_fallback) {
     // contracted list too long for the one-block ranking: rank it in
@@ -361,6 +363,11 @@ rst_status rst_create(rst_ctx **out, int device, void *hip_stream) {
     rst_destroy(ctx);
     return RST_E_DEVICE;
   }
+  if (hipHostGetDevicePointer(reinterpret_cast<void **>(&ctx->host_pinned_dev), ctx->host_pinned, 0) !=
+      hipSuccess) {
+    ctx->host_pinned_dev = nullptr;   // counters are then read back by copies
+    (void)hipGetLastError();
+  }
   *out = ctx;
   return RST_OK;
 }
@@ -475,6 +482,7 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
     // the graph, buffers and settings stay the same
     GconnWork w = take_gconn_work(ctx, g, counters, nullptr, nullptr);
     w.settled = true;   // one root (a replay does not run enqueue_gconn's host code)
+    w.exported = ctx->host_pinned_dev != nullptr;
     GraphKey key;
     std::memset(&key, 0, sizeof key);
     key.offsets = g->offsets; key.cols = g->cols; key.parent = parent;
@@ -483,7 +491,8 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
     key.opt = ctx->opt;
     RST_TRY(run_graph(ctx, key, [&]() -> rst_status {
       RST_TRY(enqueue_reset_counters(ctx, counters, root));
-      return enqueue_gconn(ctx, g, rootbuf, 1, parent, nullptr, w);
+      RST_TRY(enqueue_gconn(ctx, g, rootbuf, 1, parent, nullptr, w));
+      return w.exported ? enqueue_export_counters(ctx, counters, ctx->host_pinned_dev) : RST_OK;
     }));
     int64_t comps = 0;
     RST_TRY(finish_gconn(ctx, g, parent, nullptr, &comps, w));

@@ -80,6 +80,7 @@ struct rst_ctx {
   rst::Options opt;
   hipEvent_t ev[24] = {};   // 0-6 stages, 8-15 kernel pairs, 16-19 batch marks
   int32_t *host_pinned = nullptr;   // small pinned host buffer for flag readback
+  int32_t *host_pinned_dev = nullptr;   // its device address (null: read back by copies only)
   bool timing = false;              // record per-kernel events (a stats struct was passed)
   unsigned kev_mask = 0;            // kernel events recorded during the current call
   rst::Selector *selector = nullptr;
@@ -173,6 +174,8 @@ enum {
 rst_status enqueue_fill(rst_ctx *ctx, int32_t *p, int64_t count, int32_t value);
 // counters[0..31] = 0, counters[32] = root (the one-root buffer that follows them)
 rst_status enqueue_reset_counters(rst_ctx *ctx, int32_t *counters, int32_t root);
+// counters[0..kCntTotal) to host memory through its device address (host_dev)
+rst_status enqueue_export_counters(rst_ctx *ctx, const int32_t *counters, int32_t *host_dev);
 rst_status enqueue_validate(rst_ctx *ctx, const rst_csr *g, int32_t *counters);
 // cross: int2 [hook_cross_capacity], tile_cross: int32 [hook_tile_words], 8-byte aligned
 rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64_t *chunks,
