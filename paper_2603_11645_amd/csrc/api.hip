@@ -116,7 +116,7 @@ struct GconnWork {
   int32_t *xid;
   int32_t *endsucc;
   bool settled = false;   // k_settle ran (one root): components' own parents and count done
-  bool exported = false;  // the device work ends by writing the counters to host_pinned
+  bool exported = false;  // the last kernel writes the counters to host_pinned (graph path)
   RankBufs rb;
 };
 
@@ -177,8 +177,11 @@ static rst_status enqueue_gconn(rst_ctx *ctx, const rst_csr *g, const int32_t *r
   // with one root, k_settle already set the components' own parents and counted them
   w.settled = nroots == 1;
   const int32_t *comp_cc = w.settled ? nullptr : w.f.cc;
+  // with one root the counters are final before this pass, which then also
+  // exports them when the call reads them that way
   RST_TRY(enqueue_expand_parent(ctx, n, n, w.f.tu, w.f.tv, w.rank, w.xid, w.rb.tile_base,
-                                w.rb.crank, comp_cc, w.f.comp_root, parent, w.f.counters));
+                                w.rb.crank, comp_cc, w.f.comp_root, parent, w.f.counters,
+                                w.exported && w.settled ? ctx->host_pinned_dev : nullptr));
   RST_TRY(mark(ctx, st, 6));
   return RST_OK;
 }
@@ -491,8 +494,7 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
     key.opt = ctx->opt;
     RST_TRY(run_graph(ctx, key, [&]() -> rst_status {
       RST_TRY(enqueue_reset_counters(ctx, counters, root));
-      RST_TRY(enqueue_gconn(ctx, g, rootbuf, 1, parent, nullptr, w));
-      return w.exported ? enqueue_export_counters(ctx, counters, ctx->host_pinned_dev) : RST_OK;
+      return enqueue_gconn(ctx, g, rootbuf, 1, parent, nullptr, w);
     }));
     int64_t comps = 0;
     RST_TRY(finish_gconn(ctx, g, parent, nullptr, &comps, w));

@@ -1020,7 +1020,10 @@ __global__ __launch_bounds__(kBlock) void k_rank_expand(int64_t A, uint64_t *ran
 
 // Distances of both arcs of a slot from its record (tile pass) and the
 // contracted distances, then the parent rule; default component roots get
-// P[v] = v and are counted (unless cc is null: done by k_settle).
+// P[v] = v and are counted (unless cc is null: done by k_settle).  With cc
+// null the counters are final before this pass, and block 0 also copies them
+// to host memory through host_out when given (system-scope stores), so that
+// the call needs no copy after its last kernel.
 template <int B>
 __global__ __launch_bounds__(B) void k_expand_parent(int64_t slots, int64_t n,
                                                           const int32_t *__restrict__ tu,
@@ -1031,7 +1034,11 @@ __global__ __launch_bounds__(B) void k_expand_parent(int64_t slots, int64_t n,
                                                           const uint64_t *__restrict__ crank,
                                                           const int32_t *__restrict__ cc,
                                                           const int32_t *__restrict__ comp_root,
-                                                          int32_t *parent, int32_t *counters) {
+                                                          int32_t *parent, int32_t *counters,
+                                                          int32_t *host_out) {
+  if (host_out && blockIdx.x == 0 && threadIdx.x < kCntTotal)
+    __hip_atomic_store(&host_out[threadIdx.x], counters[threadIdx.x], __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
   if (counters[kCntRankOverflow]) return;   // contracted list not ranked yet (block-uniform)
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x < slots) {
@@ -1252,10 +1259,12 @@ rst_status rank_overflow_fallback(rst_ctx *ctx, const RankBufs &rb, int32_t *cou
 rst_status enqueue_expand_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
                                  const int32_t *tv, const uint64_t *rank, const int32_t *xid,
                                  const int64_t *tile_base, const uint64_t *crank, const int32_t *cc,
-                                 const int32_t *comp_root, int32_t *parent, int32_t *counters) {
+                                 const int32_t *comp_root, int32_t *parent, int32_t *counters,
+                                 int32_t *host_out) {
   const int64_t items = (cc && n > slots) ? n : slots;
+  if (cc) host_out = nullptr;   // the component count is only final after this pass
   RST_SWEEP(ctx, k_expand_parent, items, slots, n, tu, tv, rank, xid, tile_base, crank, cc,
-            comp_root, parent, counters);
+            comp_root, parent, counters, host_out);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }

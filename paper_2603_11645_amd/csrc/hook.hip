@@ -90,15 +90,6 @@ __global__ void k_reset_counters(int32_t *counters, int32_t root) {
   else if (i == 32) counters[32] = root;
 }
 
-// The call's counters copied into mapped pinned host memory at the end of its
-// device work (in place of a device-to-host copy after it), made visible to
-// the host before the kernel ends.
-__global__ void k_export_counters(const int32_t *__restrict__ counters, int32_t *host) {
-  const int i = threadIdx.x;
-  if (i < kCntTotal) host[i] = counters[i];
-  __threadfence_system();
-}
-
 __global__ void k_fill_i32(int32_t *p, int64_t count, int32_t value) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = value;
@@ -997,12 +988,6 @@ size_t hook_chunk_capacity(const rst_ctx *ctx, int64_t nnz) {
 
 rst_status enqueue_reset_counters(rst_ctx *ctx, int32_t *counters, int32_t root) {
   hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, ctx->stream, counters, root);
-  RST_HIP(hipGetLastError());
-  return RST_OK;
-}
-
-rst_status enqueue_export_counters(rst_ctx *ctx, const int32_t *counters, int32_t *host_dev) {
-  hipLaunchKernelGGL(k_export_counters, dim3(1), dim3(64), 0, ctx->stream, counters, host_dev);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }

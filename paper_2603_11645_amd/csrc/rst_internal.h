@@ -174,8 +174,6 @@ enum {
 rst_status enqueue_fill(rst_ctx *ctx, int32_t *p, int64_t count, int32_t value);
 // counters[0..31] = 0, counters[32] = root (the one-root buffer that follows them)
 rst_status enqueue_reset_counters(rst_ctx *ctx, int32_t *counters, int32_t root);
-// counters[0..kCntTotal) to host memory through its device address (host_dev)
-rst_status enqueue_export_counters(rst_ctx *ctx, const int32_t *counters, int32_t *host_dev);
 rst_status enqueue_validate(rst_ctx *ctx, const rst_csr *g, int32_t *counters);
 // cross: int2 [hook_cross_capacity], tile_cross: int32 [hook_tile_words], 8-byte aligned
 rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64_t *chunks,
@@ -251,7 +249,8 @@ rst_status rank_overflow_fallback(rst_ctx *ctx, const RankBufs &rb, int32_t *cou
 rst_status enqueue_expand_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
                                  const int32_t *tv, const uint64_t *rank, const int32_t *xid,
                                  const int64_t *tile_base, const uint64_t *crank, const int32_t *cc,
-                                 const int32_t *comp_root, int32_t *parent, int32_t *counters);
+                                 const int32_t *comp_root, int32_t *parent, int32_t *counters,
+                                 int32_t *host_out = nullptr);
 
 // verify.hip: device check of a rooted spanning forest.  vc[0] += failures,
 // vc[1] = min failing vertex (caller initialises 0 and INT32_MAX); anc0/anc1:

@@ -110,3 +110,34 @@ def test_replays_with_contracted_list_fallback(rst):
         c.spanning_tree(off, cols, 11, "gconn", parent=par)   # raises if not one component
         assert c.last_status == 0
         check(g, par, 11)
+
+
+def test_replays_report_disconnected_and_counts(rst):
+    """The replayed calls read their counters as the last kernel left them:
+    a graph of two components reports RST_E_DISCONNECTED on every replay, and a
+    connected graph on the same context afterwards (a new capture) succeeds on
+    every replay, its tree verified each time."""
+    c = rst.Context(0)
+    a = I.road_mesh(120, 0.1, 0.01, seed=21)
+    n = a.n
+    # two copies of the mesh side by side: two components at least
+    offs = np.concatenate([a.offsets[:-1], a.offsets + a.nnz]).astype(np.int64)
+    cols = np.concatenate([a.cols, a.cols + n]).astype(np.int32)
+    k_ref, _ = oracle.components(2 * n, offs, cols)
+    assert k_ref >= 2
+    doff = torch.from_numpy(offs.astype(np.int32)).cuda()
+    dcols = torch.from_numpy(cols).cuda()
+    par = torch.empty(2 * n, dtype=torch.int32).cuda()
+    for _ in range(3):
+        c.spanning_tree(doff, dcols, 0, "gconn", parent=par)
+        assert c.last_status == rst.RST_E_DISCONNECTED
+        p = par.cpu().numpy()
+        roots = np.flatnonzero(p == np.arange(2 * n))   # the root and the second copy's own root
+        assert len(roots) == 2 and roots[0] == 0 and n <= roots[1] < 2 * n
+    off1, cols1 = upload(a)
+    par1 = torch.empty(n, dtype=torch.int32).cuda()
+    for _ in range(3):
+        par1.fill_(-3)
+        c.spanning_tree(off1, cols1, 5, "gconn", parent=par1)
+        assert c.last_status == 0
+        check(a, par1, 5)
