@@ -658,8 +658,14 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_cross_dedupe(const int64_t 
   // second one for the top-level merge; a list past kLdsEdges is not used.
   if (tid == 0) {
     tile_cross[b] = s_kept;
-    s_base_all = s_kept ? atomicAdd(&counters[kCntKept], s_kept) : 0;
-    s_base = s_top ? atomicAdd(&counters[kCntKeptTop], s_top) : 0;
+    // both list bases from one 8-byte atomic (512 blocks queue on one word)
+    static_assert(kCntKeptTop == kCntKept + 1 && kCntKept % 2 == 0, "kept counters share a word");
+    const unsigned long long old =
+        s_kept ? atomicAdd(reinterpret_cast<unsigned long long *>(&counters[kCntKept]),
+                           ((unsigned long long)(uint32_t)s_top << 32) | (uint32_t)s_kept)
+               : 0ull;
+    s_base_all = (int)(uint32_t)old;
+    s_base = (int)(uint32_t)(old >> 32);
   }
   __syncthreads();
   const int kba = s_base_all;

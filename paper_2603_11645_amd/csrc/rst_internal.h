@@ -164,9 +164,10 @@ enum {
   kCntCrossOverflow = 10,  // kept cross edges did not fit the LDS merge (fallback ran)
   kCntRankOverflow = 11,   // contracted list did not fit the one-block ranking
   kCntRankRounds = 12,     // pointer-jumping rounds of the contracted list
-  kCntKept = 13,           // cross edges kept by the deduplication pass
-  kCntKeptTop = 14,        // of those, the edges of the levels merged by the top pass
-  kCntCrossDone = 15,      // the one-block merge of all kept edges succeeded
+  kCntCrossDone = 13,      // the one-block merge of all kept edges succeeded
+  kCntKept = 14,           // cross edges kept by the deduplication pass
+  kCntKeptTop = 15,        // of those, the edges of the levels merged by the top pass
+                           // (kCntKept and kCntKeptTop: one 8-byte word, added to at once)
   kCntTotal = 16,          // counters read back after a call (the ones above)
 };
 
