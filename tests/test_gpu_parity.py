@@ -308,6 +308,39 @@ def test_list_rank_contracted_heads(ctx):
         assert np.array_equal(got, exp)
 
 
+def _list_with_exits(M, tiles, seed, tile=16384):
+    """One list over tiles * tile ids whose tour leaves its tile exactly M - 1
+    times (runs alternate over the tiles), so that the tiled ranking has
+    exactly M segment exits (the tail included)."""
+    rs = np.random.RandomState(seed)
+    runs_of = [[] for _ in range(tiles)]
+    for t in range(tiles):
+        n_t = len(range(t, M, tiles))              # runs r with r % tiles == t
+        ids = t * tile + rs.permutation(tile)
+        cuts = np.sort(rs.choice(np.arange(1, tile), size=n_t - 1, replace=False))
+        runs_of[t] = np.split(ids, cuts)
+    order = np.concatenate([runs_of[r % tiles][r // tiles] for r in range(M)])
+    succ = np.full(tiles * tile, -1, np.int32)
+    succ[order[:-1]] = order[1:]
+    return succ
+
+
+def test_list_rank_contracted_capacity(ctx):
+    """Contracted lists of exactly as many words as one workgroup ranks
+    (19,456: packed 32-bit words), one more (64-bit words and the multi-block
+    rounds), and small ones: the ranks match the oracle in every case."""
+    for M, seed in ((19456, 1), (19457, 2), (19455, 3), (3, 4)):
+        succ = _list_with_exits(M, 3, seed)
+        nxt = succ.astype(np.int64)
+        tile_of = np.arange(len(succ)) // 16384
+        exits = np.count_nonzero((nxt < 0) | (tile_of != np.where(nxt < 0, -1, nxt) // 16384))
+        assert exits == M
+        exp, k = oracle.list_rank(succ)
+        assert k == 1
+        got = ctx.list_rank(dev(succ)).cpu().numpy()
+        assert np.array_equal(got, exp), M
+
+
 def test_heavy_hub_paths(ctx):
     """A star whose centre exceeds the heavy-degree threshold many times over."""
     g = I.star(200001, 7)
