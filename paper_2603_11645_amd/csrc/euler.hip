@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_round(int64_t A, uint64_t *rank
 constexpr int kRankTile = 16384;
 constexpr int kRankThreads = 1024;
 constexpr int kRankPer = kRankTile / kRankThreads;     // 16 arcs (8 twin pairs) per thread
-constexpr int kTileWalkSteps = 2;      // walk steps between two refills
+constexpr int kTileWalkSteps = 4;      // walk steps between two refills
 constexpr bool kTileWaveShare = false; // rulers from the block's queue
 constexpr int kTileAsync = 12;         // barrier-free jumping rounds before the synchronous ones
 constexpr int kRankWaves = kRankThreads / 64;
