@@ -742,7 +742,7 @@ constexpr int kSmOffRw = kSmOffRs + 2 * kSmallRulers;
 constexpr int kSmBytes = (kSmOffRw + 8 * kSmallRulers) > 8 * kSmallLds ? (kSmOffRw + 8 * kSmallRulers)
                                                                        : 8 * kSmallLds;
 static_assert(kSmOffHp % 16 == 0 && kSmallLds % 32 == 0 && kSmOffRw % 8 == 0, "ruler path LDS layout");
-constexpr int kWalkSteps = 3;   // steps of every walk between two refills
+constexpr int kWalkSteps = 4;   // steps of every walk between two refills
 constexpr bool kWaveShare = true;   // each wave walks its own range of static rulers
 constexpr int kAsyncIters = 16;     // barrier-free jumping rounds before the synchronous ones
 
