@@ -717,7 +717,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
 // The contracted list (M = base[tiles] words, packed (hops to the next word,
 // next word)) ranked by one block, with no host round trip.  Like the tile
 // pass: every 8th word and every list head starts a ruler; one walk per ruler
-// follows its piece (opening a new ruler after 16 words), overwriting each
+// follows its piece (opening a new ruler after 24 words), overwriting each
 // word in place with (weighted distance from the ruler's start : 20, ruler :
 // 12); the rulers are ranked by in-place pointer jumping on 64-bit words
 // (last-ruler flag, next ruler, distance) and every word's distance to its
@@ -730,7 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_rank_contract(const int32_t *__restr
 // pointer-jumping rounds.  Output: crank[i] = (-1, distance from word i to the
 // tail of its list), 64-bit words over the packed input.
 constexpr int kSmallRulers = 4096;
-constexpr int kSmallPiece = 16;
+constexpr int kSmallPiece = 24;
 constexpr int kSmallRuler = 8;                          // every 8th word starts a ruler
 // LDS, ruler path: words uint32 [kSmallLds + 64] (the last 64 are a slot per
 // lane for idle lanes' accesses), has-predecessor bytes [kSmallLds], ruler
