@@ -131,7 +131,8 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: multi-GPU execution is not part of this "
-              "library (see DESIGN.md for how the path would shard)", file=sys.stderr)
+              "library (the connectivity phase would shard by vertex ranges with one "
+              "all-gather of the forest edges; the Euler stage runs on one GPU)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
