@@ -226,8 +226,9 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
  * Features of graph g, feat[g*8 + k]: log n, log(1 + m), mean degree,
  * log(1 + degree variance), log(1 + max degree), and for probes s = 0, 1, 2
  * log2(1 + depth reached by a BFS capped at 64 levels) from the source
- * vtx_off[g] + splitmix64(3g + s) mod n_g (splitmix64: Steele, Lea, Flood 2014,
- * x += 0x9E3779B97F4A7C15 then the finaliser).  Degree moments use arcs of the
+ * vtx_off[g] + (the (3g + s + 1)-th output of the splitmix64 generator seeded
+ * with 0) mod n_g (splitmix64: Steele, Lea, Flood 2014; state += 0x9E3779B97F4A7C15,
+ * then the finaliser).  Degree moments use arcs of the
  * CSR; m counts each undirected edge once (arcs / 2).
  * Network: 8 -> 64 -> 64 -> 2 fully connected, ReLU, fp32, applied to z-scored
  * features (x - mean) / max(std, 1e-6).  Output 0 scores GConn+Euler, output 1

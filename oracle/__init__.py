@@ -66,6 +66,10 @@ def _load():
     lib.oracle_verify_rst.argtypes = [i64, P, P, P, P, i32, ctypes.POINTER(i64)]
     lib.oracle_components.restype = i64
     lib.oracle_components.argtypes = [i64, P, P, P]
+    lib.oracle_tree_depth.restype = i64
+    lib.oracle_tree_depth.argtypes = [i64, P, P]
+    lib.oracle_pr_rst.restype = i64
+    lib.oracle_pr_rst.argtypes = [i64, P, P, P, i32, i64, P]
     _lib = lib
     return lib
 
@@ -195,21 +199,29 @@ def verify_rst(n, offsets, cols, parent, roots):
 
 
 def tree_depth(parent):
-    """Depth of every vertex in a rooted forest (root depth 0), iterative."""
-    parent = np.asarray(parent, dtype=np.int64)
-    n = parent.shape[0]
-    depth = np.full(n, -1, dtype=np.int64)
-    for v in range(n):
-        if depth[v] >= 0:
-            continue
-        path = []
-        x = v
-        while depth[x] < 0 and parent[x] != x:
-            path.append(x)
-            x = int(parent[x])
-        base = 0 if parent[x] == x and depth[x] < 0 else depth[x]
-        if depth[x] < 0:
-            depth[x] = 0
-        for i, y in enumerate(reversed(path)):
-            depth[y] = base + i + 1
-    return depth
+    """(depth[n], max depth): parent steps from every vertex to its tree's root."""
+    par = np.ascontiguousarray(parent, dtype=np.int32)
+    n = int(par.shape[0])
+    depth = np.empty(max(n, 1), dtype=np.int32)
+    d = _load().oracle_tree_depth(n, _p(par if n else np.zeros(1, np.int32)), _p(depth))
+    if d == -7:
+        raise ValueError("oracle_tree_depth: parent out of range")
+    if d == -8:
+        raise ValueError("oracle_tree_depth: cycle in parent pointers")
+    if d < 0:
+        raise MemoryError
+    return depth[:n].copy(), int(d)
+
+
+def pr_rst(n, offsets, cols, roots, max_iters: int = -1):
+    """Path-Reversal RST (Sec. III-C), sequential: (parent[n], hooking iterations).
+    max_iters >= 0 stops after that many iterations (forest as it stands)."""
+    off, c = _csr(offsets, cols)
+    r, nr = _roots(roots)
+    parent = np.empty(n, dtype=np.int32)
+    it = _load().oracle_pr_rst(n, _p(off), _p(c), _p(r), nr, int(max_iters), _p(parent))
+    if it == -100:
+        raise MemoryError
+    if it < 0:
+        raise ValueError("oracle_pr_rst failed (%d)" % it)
+    return parent, int(it)

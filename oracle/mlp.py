@@ -28,8 +28,16 @@ def splitmix64(x: int) -> int:
     return x ^ (x >> 31)
 
 
+GAMMA = 0x9E3779B97F4A7C15
+
+
 def probe_source(g: int, s: int, b: int, n: int) -> int:
-    return b + (splitmix64(g * PROBES + s) % n if n > 0 else 0)
+    """Source of probe s of graph g (first vertex b, n vertices): b plus the
+    (3g + s + 1)-th output of the splitmix64 generator seeded with 0, mod n.
+    The k-th output of that generator is the finaliser of k * GAMMA, i.e.
+    splitmix64((k - 1) * GAMMA) here."""
+    k = g * PROBES + s + 1
+    return b + (splitmix64(((k - 1) * GAMMA) & _M64) % n if n > 0 else 0)
 
 
 def features(offsets, cols, vtx_off):

@@ -419,3 +419,154 @@ int64_t oracle_components(int64_t n, const int64_t *off, const int32_t *cols, in
   free(fu); free(fv);
   return t < 0 ? t : n - t;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Depth of every vertex in a rooted forest (the tree-depth property compared */
+/* across methods in Sec. IV-B, Fig. 2): depth[v] = number of parent steps    */
+/* from v to the root of its tree (P[root] = root, depth 0).  Plain walk up   */
+/* the parent pointers with memoisation.  Returns the largest depth, -7 for a */
+/* parent out of range, -8 for a cycle.                                       */
+/* ------------------------------------------------------------------------- */
+int64_t oracle_tree_depth(int64_t n, const int32_t *parent, int32_t *depth) {
+  int32_t *path = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n + 1));
+  if (!path) return ORC_ENOMEM;
+  int64_t maxd = 0, rc = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    if (parent[v] < 0 || parent[v] >= n) { rc = -7; goto done; }
+    depth[v] = -1;
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    if (depth[v] >= 0) continue;
+    int64_t len = 0;
+    int32_t x = (int32_t)v;
+    /* climb until a vertex of known depth or a root; -2 marks "on this walk" */
+    while (depth[x] == -1 && parent[x] != x) {
+      depth[x] = -2;
+      path[len++] = x;
+      x = parent[x];
+    }
+    if (depth[x] == -2) { rc = -8; goto done; }
+    if (depth[x] == -1) depth[x] = 0;          /* x is a root */
+    int32_t d = depth[x];
+    for (int64_t i = len - 1; i >= 0; --i) depth[path[i]] = ++d;
+    if (d > maxd) maxd = d;
+  }
+  rc = maxd;
+done:
+  free(path);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Path-Reversal RST (Sec. III-C, after Cong and Bader), sequential, in the   */
+/* order of the paper.  A rooted spanning forest P (every vertex its own root */
+/* at the start) is kept at all times.  Each iteration:                       */
+/*  1. pointer jumping with history: anc[0] = P, anc[k+1][v] =                */
+/*     anc[k][anc[k][v]] for K = ceil(log2 n) + 1 levels (the "special        */
+/*     ancestors" at distances 2^k); rep[v] = anc[K-1][v], the root of v;     */
+/*  2. hooking, alternating max and min: on even iterations the component of  */
+/*     the larger representative is the target of every edge joining two      */
+/*     components, on odd ones the smaller; the other root r gets one hooking */
+/*     edge (x in r's tree, y in the target's tree); here the first such arc  */
+/*     in CSR order wins (on the GPU any may);                                */
+/*  3. path marking: x is on the path, and in round k = 0..K-1 every marked   */
+/*     vertex marks its 2^k-th ancestor (all marked vertices are ancestors    */
+/*     of x, so marking within a round is harmless);                          */
+/*  4. reversal: for every marked non-root v, P'[P[v]] = v; then P'[x] = y    */
+/*     grafts r's tree, re-rooted at x, onto y.                               */
+/* The loop ends when no edge joins two components.  Finally every tree is    */
+/* re-rooted at its designated root d, or at its minimum id if it holds none, */
+/* by the same marking and reversal (P'[d] = d).                              */
+/* Returns the number of hooking iterations, or a negative error (see         */
+/* root_flags; -9 if the iteration cap 4 n + 64 is exceeded).  max_iters >= 0 */
+/* stops after that many iterations and returns the forest as it stands, not  */
+/* re-rooted (for checking single steps).                                     */
+/* ------------------------------------------------------------------------- */
+static int ceil_log2_levels(int64_t n) {
+  int k = 1;
+  while (((int64_t)1 << (k - 1)) < n) ++k;
+  return k;
+}
+
+/* anc[k] for k < K (anc + k*n), from P */
+static void special_ancestors(int64_t n, int K, const int32_t *P, int32_t *anc) {
+  memcpy(anc, P, sizeof(int32_t) * (size_t)n);
+  for (int k = 1; k < K; ++k) {
+    const int32_t *a = anc + (size_t)(k - 1) * (size_t)n;
+    int32_t *b = anc + (size_t)k * (size_t)n;
+    for (int64_t v = 0; v < n; ++v) b[v] = a[a[v]];
+  }
+}
+
+/* mark the tree path from every start vertex (on[v] = 1 already) to its root */
+static void mark_paths(int64_t n, int K, const int32_t *anc, uint8_t *on) {
+  for (int k = 0; k < K; ++k) {
+    const int32_t *a = anc + (size_t)k * (size_t)n;
+    for (int64_t v = 0; v < n; ++v)
+      if (on[v]) on[a[v]] = 1;
+  }
+}
+
+int64_t oracle_pr_rst(int64_t n, const int64_t *off, const int32_t *cols, const int32_t *roots,
+                      int32_t nroots, int64_t max_iters, int32_t *parent) {
+  const int K = ceil_log2_levels(n);
+  int32_t *anc = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)K);
+  int32_t *np = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *wx = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *wy = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  uint8_t *on = (uint8_t *)malloc((size_t)n);
+  int32_t *label = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *fu = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t *fv = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  uint8_t *is_root = (uint8_t *)malloc((size_t)n);
+  int64_t iters = 0;
+  if (!anc || !np || !wx || !wy || !on || !label || !fu || !fv || !is_root) { iters = ORC_ENOMEM; goto done; }
+  /* designated roots are checked first (two in one component is an error) */
+  if (oracle_uf_forest(n, off, cols, label, fu, fv) < 0) { iters = -1; goto done; }
+  { int rc = root_flags(n, label, roots, nroots, is_root); if (rc) { iters = rc; goto done; } }
+  for (int64_t v = 0; v < n; ++v) parent[v] = (int32_t)v;
+  for (;;) {
+    if (max_iters >= 0 && iters >= max_iters) goto done;          /* stop early: no re-rooting */
+    if (iters > 4 * n + 64) { iters = -9; goto done; }
+    special_ancestors(n, K, parent, anc);                          /* step 1 */
+    const int32_t *rep = anc + (size_t)(K - 1) * (size_t)n;
+    const int max_round = (iters % 2) == 0;
+    int64_t hooks = 0;
+    for (int64_t v = 0; v < n; ++v) wx[v] = -1;
+    for (int64_t u = 0; u < n; ++u) {                              /* step 2 */
+      for (int64_t i = off[u]; i < off[u + 1]; ++i) {
+        const int32_t w = cols[i];
+        const int32_t ru = rep[u], rw = rep[w];
+        if (ru == rw) continue;
+        const int32_t target = max_round ? (ru > rw ? ru : rw) : (ru < rw ? ru : rw);
+        const int32_t r = target == ru ? rw : ru;                  /* the root that is grafted */
+        if (wx[r] >= 0) continue;
+        wx[r] = target == ru ? w : (int32_t)u;                     /* endpoint in r's tree */
+        wy[r] = target == ru ? (int32_t)u : w;                     /* endpoint in the target's */
+        ++hooks;
+      }
+    }
+    if (hooks == 0) break;
+    memset(on, 0, (size_t)n);                                      /* step 3 */
+    for (int64_t r = 0; r < n; ++r) if (wx[r] >= 0) on[wx[r]] = 1;
+    mark_paths(n, K, anc, on);
+    memcpy(np, parent, sizeof(int32_t) * (size_t)n);               /* step 4 */
+    for (int64_t v = 0; v < n; ++v)
+      if (on[v] && parent[v] != v) np[parent[v]] = (int32_t)v;
+    for (int64_t r = 0; r < n; ++r) if (wx[r] >= 0) np[wx[r]] = wy[r];
+    memcpy(parent, np, sizeof(int32_t) * (size_t)n);
+    ++iters;
+  }
+  /* re-root every tree at its designated root, or at its minimum id */
+  special_ancestors(n, K, parent, anc);
+  memcpy(on, is_root, (size_t)n);
+  mark_paths(n, K, anc, on);
+  memcpy(np, parent, sizeof(int32_t) * (size_t)n);
+  for (int64_t v = 0; v < n; ++v)
+    if (on[v] && parent[v] != v) np[parent[v]] = (int32_t)v;
+  for (int64_t v = 0; v < n; ++v) if (is_root[v]) np[v] = (int32_t)v;
+  memcpy(parent, np, sizeof(int32_t) * (size_t)n);
+done:
+  free(anc); free(np); free(wx); free(wy); free(on); free(label); free(fu); free(fv); free(is_root);
+  return iters;
+}

@@ -82,7 +82,8 @@ __global__ __launch_bounds__(kBlock) void k_degree_moments(const OffT *__restric
 }
 
 // splitmix64 (Steele, Lea, Flood, OOPSLA 2014): the state is advanced by the
-// golden-ratio increment and finalised; counter-based here, x = 3g + s.
+// golden-ratio increment and finalised.  splitmix64((k - 1) * gamma) is the
+// k-th output of the generator seeded with 0.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   x += 0x9E3779B97F4A7C15ull;
   x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -90,13 +91,14 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-// probe source of every graph for probe s: vtx_off[g] + splitmix64(3g+s) mod n_g
+// probe source of every graph for probe s: vtx_off[g] + (the (3g + s + 1)-th
+// output of splitmix64 seeded with 0) mod n_g
 __global__ void k_probe_sources(int32_t G, const int64_t *__restrict__ vtx_off, int s,
                                 int32_t *src) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   const int64_t b = vtx_off[g], n = vtx_off[g + 1] - b;
-  const uint64_t h = splitmix64((uint64_t)g * kProbes + (uint64_t)s);
+  const uint64_t h = splitmix64(((uint64_t)g * kProbes + (uint64_t)s) * 0x9E3779B97F4A7C15ull);
   src[g] = (int32_t)(b + (n > 0 ? (int64_t)(h % (uint64_t)n) : 0));
 }
 

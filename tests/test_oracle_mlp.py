@@ -10,11 +10,36 @@ from oracle import mlp as M
 from paper_2603_11645_amd import inputs as I
 
 
+# The first five outputs of the splitmix64 generator seeded with 0 (published
+# reference implementation: state += golden gamma, then the finaliser).
+SPLITMIX64_SEED0 = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F,
+                    0xF88BB8A8724C81EC, 0x1B39896A51A8749B]
+
+
 def test_splitmix64_reference_sequence():
-    # the generator seeded with 0 yields these first two values (published
-    # reference implementation: state += golden gamma, then the finaliser)
     assert M.splitmix64(0) == 16294208416658607535
     assert M.splitmix64(0x9E3779B97F4A7C15) == 7960286522194355700
+    for k, want in enumerate(SPLITMIX64_SEED0):
+        assert M.splitmix64((k * M.GAMMA) % 2**64) == want
+
+
+def test_probe_sources_are_the_published_outputs():
+    # probe s of graph g takes the (3g + s + 1)-th output: graphs 0 and 1 use
+    # outputs 1..3 and 4..6
+    for (g, s), want in zip([(0, 0), (0, 1), (0, 2), (1, 0), (1, 1)], SPLITMIX64_SEED0):
+        for b, n in ((0, 1000), (17, 7), (5, 2**31 - 1), (123456, 200000)):
+            assert M.probe_source(g, s, b, n) == b + want % n
+    assert M.probe_source(3, 1, 40, 1) == 40     # a one-vertex graph probes itself
+
+
+def test_normalise_non_unit_moments_and_floor():
+    X = np.array([[3.0, -2.0, 0.5, 10.0, 1.0, 2.0, -1.0, 4.0]])
+    mean = np.array([1.0, 0.0, 0.5, -2.0, 0.0, 1.0, 1.0, 4.0])
+    std = np.array([2.0, 4.0, 0.25, 3.0, 1e-9, 0.0, 0.5, 1e-6])
+    Xn = M.normalise(X, np.concatenate([mean, std]))
+    # (x - mean) / std, with std floored at 1e-6
+    want = [1.0, -0.5, 0.0, 4.0, 1e6, 1e6, -4.0, 0.0]
+    assert np.allclose(Xn[0], want, rtol=1e-12, atol=0)
 
 
 def _random_case(seed, B=37):
