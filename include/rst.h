@@ -89,7 +89,7 @@ enum {
 typedef struct {
   float ms_total;
   float ms_stage[8];
-  float ms_kernel[4];     /* single kernels, see RST_KERNEL_*                  */
+  float ms_kernel[8];     /* single kernels, see RST_KERNEL_*                  */
   int64_t hook_rounds;    /* levels of the binary tree over vertex tiles + 1   */
   int64_t rank_rounds;    /* pointer-jumping rounds on the contracted list     */
   int64_t rank_exits;     /* length of the contracted list (segment exits)     */
@@ -105,12 +105,16 @@ typedef struct {
 enum {
   RST_PATH_CROSS_GLOBAL = 1,  /* cross-tile merge ran in global memory (the     *
                                * kept cross edges did not fit one workgroup)    */
-  RST_PATH_RANK_GLOBAL = 2,   /* contracted list ranked by multi-workgroup      *
-                               * rounds (too long for one workgroup)            */
-  RST_PATH_CROSS_GROUPS = 4   /* kept cross edges too many for the one-workgroup *
+  RST_PATH_RANK_GLOBAL = 2,   /* last resort: every arc ranked by multi-        *
+                               * workgroup pointer-jumping rounds (more lists   *
+                               * than the sparse ruling set holds)              */
+  RST_PATH_CROSS_GROUPS = 4,  /* kept cross edges too many for the one-workgroup *
                                * merge of all levels: merged per group of tiles *
                                * and then the top levels (graphs of more than   *
                                * 8 tiles of 8192 vertices only)                 */
+  RST_PATH_RANK_SPARSE = 8    /* the tour was ranked by the sparse ruling set in *
+                               * global memory (ids without locality), not per  *
+                               * arc tile                                        */
 };
 
 /* Indices of rst_stats.ms_kernel (HIP-event time of one launch each). */
@@ -118,7 +122,9 @@ enum {
   RST_KERNEL_HOOK_TILE = 0,   /* LDS union-find over vertex tiles               */
   RST_KERNEL_CROSS = 1,       /* all cross-tile hooking levels together         */
   RST_KERNEL_RANK_TILE = 2,   /* LDS ruling-set ranking over arc tiles (+succ)  */
-  RST_KERNEL_LINK = 3         /* per-vertex out-arc lists                       */
+  RST_KERNEL_LINK = 3,        /* per-vertex out-arc lists                       */
+  RST_KERNEL_RANK_WALK = 4    /* sparse ruling set in global memory: the walks  *
+                               * of the first level (tours without id locality) */
 };
 
 /* Tunables and switches for rst_set_option. */
@@ -136,13 +142,17 @@ typedef enum {
                                 * sweeps (64, 128, 256, 512, 1024)                 */
   RST_OPT_BFS_HEAVY_DEGREE = 6, /* BFS: degree above which a frontier vertex's arcs are
                                  * expanded by many workgroups (32 .. 2^24)         */
-  RST_OPT_GRAPHS = 7           /* 1 (default): rst_spanning_tree by GConn+Euler without
-                                * stats or validation captures its device work as a
-                                * HIP graph on first use and replays it while the
-                                * graph pointers, sizes, root, parent buffer and
-                                * settings stay the same; 0: launch eagerly        */
+  RST_OPT_GRAPHS = 7,          /* 1 (default): rst_spanning_tree by GConn+Euler without
+                                * stats or validation runs eagerly on the first call
+                                * with given graph pointers, sizes, root, parent
+                                * buffer and settings, captures its device work as a
+                                * HIP graph on the second and replays it while they
+                                * stay the same; 0: launch eagerly                 */
+  RST_OPT_RANK_STRIDE = 8      /* sparse ruling set (tours without id locality):
+                                * every k-th arc starts a ruler, k in 4, 8, 16
+                                * (default), 32, 64                                */
 } rst_option;
-#define RST_NUM_OPTIONS 8
+#define RST_NUM_OPTIONS 9
 
 /* Create a context on HIP device `device` bound to `hip_stream` (a hipStream_t,
  * NULL = the default stream).  *out receives the context.  Errors: RST_E_INVAL

@@ -70,7 +70,7 @@ static void fill_stage_times(rst_ctx *ctx, rst_stats *st, const int *stage_of_ga
 
 // kernels whose two events were recorded during this call only
 static void fill_kernel_times(rst_ctx *ctx, rst_stats *st) {
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < kNumKernelTimes; ++k) {
     float ms = 0.f;
     if (((ctx->kev_mask >> (2 * k)) & 3u) != 3u) continue;
     if (event_ms(ctx->ev[kEvKernelBase + 2 * k], ctx->ev[kEvKernelBase + 2 * k + 1], &ms))
@@ -104,6 +104,18 @@ static RankBufs take_rank_bufs(rst_ctx *ctx, int64_t A) {
   return r;
 }
 
+// The ranking of the tour: per-tile in LDS (arc ids with locality, euler.hip)
+// or by the sparse ruling set in global memory (glrank.hip).  Chosen from the
+// hooking counters: when more than half as many edges crossed vertex tiles as
+// there are vertices, the ids carry little locality and the tour leaves its
+// tiles at almost every arc.
+static bool prefer_sparse_rank(int64_t cross_edges, int64_t n) { return 2 * cross_edges > n; }
+
+static GlistPlan gconn_glist_plan(const rst_ctx *ctx, int64_t n) {
+  // lists: one per tree with an edge, at most n / 2
+  return glist_plan(2 * n, n / 2 + 1, ctx->opt.rank_stride);
+}
+
 // Device buffers of one GConn+Euler run, taken from the workspace in a fixed
 // order (the same pointers for the same graph size and workspace).
 struct GconnWork {
@@ -117,7 +129,11 @@ struct GconnWork {
   int32_t *endsucc;
   bool settled = false;   // k_settle ran (one root): components' own parents and count done
   bool exported = false;  // the last kernel writes the counters to host_pinned (graph path)
+  bool sparse = false;    // rank by the sparse ruling set (else per tile)
+  bool sparse_ran = false;   // the sparse ruling set ran in this call (directly or as fallback)
   RankBufs rb;
+  GlistBufs gl;
+  int32_t *w1() const { return reinterpret_cast<int32_t *>(rank); }   // level-1 words alias rank
 };
 
 static GconnWork take_gconn_work(rst_ctx *ctx, const rst_csr *g, int32_t *counters,
@@ -142,25 +158,25 @@ static GconnWork take_gconn_work(rst_ctx *ctx, const rst_csr *g, int32_t *counte
   w.rb = take_rank_bufs(ctx, 2 * n);
   w.xid = ws_take<int32_t>(ctx, 2 * n);
   w.endsucc = ws_take<int32_t>(ctx, n);
+  glist_take(ctx, gconn_glist_plan(ctx, n), w.gl);
   return w;
 }
 
-// All device work of GConn + Euler (no host round trip): hooking, compress,
-// roots, tiled ranking, parents.  roots: device list (one per component at
-// most).
-static rst_status enqueue_gconn(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
-                                int32_t nroots, int32_t *parent, rst_stats *st, GconnWork &w) {
+// Device work of the forest part (no host round trip): hooking, then either
+// the one-root settle pass or compress + root marking.
+static rst_status enqueue_gconn_forest(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
+                                       int32_t nroots, int32_t *parent, rst_stats *st,
+                                       GconnWork &w) {
   const int64_t n = g->n;
   RST_TRY(mark(ctx, st, 0));
   RST_TRY(enqueue_hook_csr(ctx, g, w.f, w.chunks, w.chunk_cap, w.cross, w.tile_cross));
   RST_TRY(mark(ctx, st, 1));
-  SlotArcs arcs{w.f.tu, w.f.tv, w.f.next, w.f.head, w.f.cc, w.f.comp_root, n, w.endsucc};
-  if (nroots == 1) {
+  w.settled = nroots == 1;
+  if (w.settled) {
     // one pass: the root's claim, end-of-list successors, the components' own
     // parents and count (the labels are not needed further on this path; the
     // "roots" stage stays empty)
     RST_TRY(enqueue_settle(ctx, n, roots, w.f.cc, w.f.head, w.endsucc, parent, w.f.counters));
-    arcs.endsucc_ready = true;
     RST_TRY(mark(ctx, st, 2));
     RST_TRY(mark(ctx, st, 3));
   } else {
@@ -170,49 +186,96 @@ static rst_status enqueue_gconn(rst_ctx *ctx, const rst_csr *g, const int32_t *r
                                w.f.counters));
     RST_TRY(mark(ctx, st, 3));
   }
+  return RST_OK;
+}
+
+// The sparse ruling set from the forest slots, then the parent rule.
+static rst_status enqueue_gconn_sparse(rst_ctx *ctx, int64_t n, int32_t *parent, GconnWork &w,
+                                       bool endsucc_ready, int32_t *host_out) {
+  if (!endsucc_ready)
+    RST_TRY(enqueue_endsucc(ctx, n, w.f.head, w.f.cc, w.f.comp_root, w.endsucc));
+  RST_TRY(enqueue_glist_from_slots(ctx, n, n, w.f.tu, w.f.tv, w.f.next, w.endsucc, w.f.head,
+                                   w.w1(), w.gl, w.f.counters));
+  RST_TRY(enqueue_glist_rank(ctx, w.w1(), w.gl, w.f.counters));
+  return enqueue_glist_parent(ctx, n, n, w.f.tu, w.f.tv, w.w1(), w.gl,
+                              w.settled ? nullptr : w.f.cc, w.f.comp_root, parent, w.f.counters,
+                              host_out);
+}
+
+// Device work of the rooting part (no host round trip): successors, ranking
+// (per tile or sparse ruling set, as w.sparse says), parents.
+static rst_status enqueue_gconn_rank(rst_ctx *ctx, const rst_csr *g, int32_t *parent,
+                                     rst_stats *st, GconnWork &w) {
+  const int64_t n = g->n;
+  // with one root the counters are final before the parent pass, which then
+  // also exports them when the call reads them that way
+  int32_t *host_out = w.exported && w.settled ? ctx->host_pinned_dev : nullptr;
   // the successor pass is fused into the first ranking pass (stage "succ" stays empty)
   RST_TRY(mark(ctx, st, 4));
+  if (w.sparse) {
+    w.sparse_ran = true;
+    if (!w.settled) RST_TRY(enqueue_endsucc(ctx, n, w.f.head, w.f.cc, w.f.comp_root, w.endsucc));
+    RST_TRY(enqueue_glist_from_slots(ctx, n, n, w.f.tu, w.f.tv, w.f.next, w.endsucc, w.f.head,
+                                     w.w1(), w.gl, w.f.counters));
+    RST_TRY(enqueue_glist_rank(ctx, w.w1(), w.gl, w.f.counters));
+    RST_TRY(mark(ctx, st, 5));
+    RST_TRY(enqueue_glist_parent(ctx, n, n, w.f.tu, w.f.tv, w.w1(), w.gl,
+                                 w.settled ? nullptr : w.f.cc, w.f.comp_root, parent,
+                                 w.f.counters, host_out));
+    RST_TRY(mark(ctx, st, 6));
+    return RST_OK;
+  }
+  SlotArcs arcs{w.f.tu, w.f.tv, w.f.next, w.f.head, w.f.cc, w.f.comp_root, n, w.endsucc};
+  arcs.endsucc_ready = w.settled;
   RST_TRY(enqueue_rank_tiled(ctx, 2 * n, w.rank, w.xid, w.rb, w.f.counters, &arcs, false));
   RST_TRY(mark(ctx, st, 5));
   // with one root, k_settle already set the components' own parents and counted them
-  w.settled = nroots == 1;
   const int32_t *comp_cc = w.settled ? nullptr : w.f.cc;
-  // with one root the counters are final before this pass, which then also
-  // exports them when the call reads them that way
   RST_TRY(enqueue_expand_parent(ctx, n, n, w.f.tu, w.f.tv, w.rank, w.xid, w.rb.tile_base,
                                 w.rb.crank, comp_cc, w.f.comp_root, parent, w.f.counters,
-                                w.exported && w.settled ? ctx->host_pinned_dev : nullptr));
+                                host_out));
   RST_TRY(mark(ctx, st, 6));
   return RST_OK;
 }
 
 // Host side after the device work: read the counters (the call's one
-// synchronisation), run the multi-workgroup ranking fallback if it was
-// needed, fill the stats.  *components = components found.
+// synchronisation), run a fallback ranking if one was flagged, fill the
+// stats.  *components = components found.
 static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, rst_stats *st,
                                int64_t *components, GconnWork &w) {
   const int64_t n = g->n;
   int32_t *counters = w.f.counters;
   if (w.exported) RST_HIP(hipStreamSynchronize(ctx->stream));
   else RST_TRY(read_counters(ctx, counters));
-  const bool rank_fallback = ctx->host_pinned[kCntRankOverflow] != 0;
+  const bool rank_fallback = !w.sparse && ctx->host_pinned[kCntRankOverflow] != 0;
   if (rank_fallback) {
-    // contracted list too long for the one-block ranking: rank it in
-    // multi-block rounds, then the parent rule runs again
-    RST_TRY(rank_overflow_fallback(ctx, w.rb, counters));
-    RST_TRY(enqueue_expand_parent(ctx, n, n, w.f.tu, w.f.tv, w.rank, w.xid, w.rb.tile_base,
-                                  w.rb.crank, w.settled ? nullptr : w.f.cc, w.f.comp_root, parent,
-                                  counters));
+    // contracted list too long for the one-block ranking: rank the tour from
+    // the slots by the sparse ruling set (the per-tile results are dropped)
+    w.sparse_ran = true;
+    RST_TRY(enqueue_fill(ctx, counters + kCntRankOverflow, 1, 0));
+    RST_TRY(enqueue_gconn_sparse(ctx, n, parent, w, true, nullptr));
     RST_TRY(mark(ctx, st, 6));
     RST_TRY(read_counters(ctx, counters));
   }
-  const int rounds = ctx->host_pinned[kCntRankRounds];
-  const int64_t exits_n = ctx->host_pinned[kCntExits];
+  const bool last_resort = w.sparse_ran && ctx->host_pinned[kCntGOverflow] != 0;
+  if (last_resort) {
+    // more list heads or rulers than the sparse ruling set holds
+    RST_TRY(glist_wyllie_parent(ctx, n, n, w.f.tu, w.f.tv, w.f.next, w.endsucc, w.rank,
+                                w.settled ? nullptr : w.f.cc, w.f.comp_root, parent, counters));
+    RST_TRY(mark(ctx, st, 6));
+    RST_TRY(read_counters(ctx, counters));
+  }
+  const int rounds = w.sparse_ran ? w.gl.plan.levels : ctx->host_pinned[kCntRankRounds];
+  const int64_t exits_n =
+      w.sparse_ran ? (2 * n + w.gl.plan.k1 - 1) / w.gl.plan.k1 + ctx->host_pinned[kCntGHeads] +
+                         ctx->host_pinned[kCntGDyn]
+                   : ctx->host_pinned[kCntExits];
   // the one-block merge of all levels is tried when there are more than 3 levels
   const bool groups = hook_level_count(n) > 3 && !ctx->host_pinned[kCntCrossDone];
   const int32_t paths = (ctx->host_pinned[kCntCrossOverflow] ? RST_PATH_CROSS_GLOBAL : 0) |
-                        (rank_fallback ? RST_PATH_RANK_GLOBAL : 0) |
-                        (groups ? RST_PATH_CROSS_GROUPS : 0);
+                        (last_resort ? RST_PATH_RANK_GLOBAL : 0) |
+                        (groups ? RST_PATH_CROSS_GROUPS : 0) |
+                        (w.sparse_ran && !last_resort ? RST_PATH_RANK_SPARSE : 0);
   if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
   if (ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
   *components = ctx->host_pinned[kCntComponents];
@@ -232,13 +295,20 @@ static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, 
   return RST_OK;
 }
 
-// GConn + Euler over the whole CSR, launched eagerly.  Writes parent, returns
-// the component count in *components.
+// GConn + Euler over the whole CSR, launched eagerly: the forest part, one
+// read of the hooking counters to choose the ranking, the rooting part.
+// Writes parent, returns the component count in *components; *sparse (host,
+// nullable) receives the ranking chosen.
 rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
                            int32_t *parent, rst_stats *st, int64_t *components,
-                           int32_t *counters, int32_t *cc_out, const uint8_t *vmask = nullptr) {
+                           int32_t *counters, int32_t *cc_out, const uint8_t *vmask = nullptr,
+                           bool *sparse = nullptr) {
   GconnWork w = take_gconn_work(ctx, g, counters, cc_out, vmask);
-  RST_TRY(enqueue_gconn(ctx, g, roots, nroots, parent, st, w));
+  RST_TRY(enqueue_gconn_forest(ctx, g, roots, nroots, parent, st, w));
+  RST_TRY(read_counters(ctx, counters));
+  w.sparse = prefer_sparse_rank(ctx->host_pinned[kCntCross], g->n);
+  if (sparse) *sparse = w.sparse;
+  RST_TRY(enqueue_gconn_rank(ctx, g, parent, st, w));
   return finish_gconn(ctx, g, parent, st, components, w);
 }
 
@@ -259,6 +329,7 @@ struct GraphKey {
 struct GraphCache {
   GraphKey key;
   hipGraphExec_t exec = nullptr;
+  bool sparse = false;   // ranking captured for this key (sparse ruling set or per tile)
 };
 
 void graph_free(rst_ctx *ctx) {
@@ -277,6 +348,14 @@ void graph_free(rst_ctx *ctx) {
 // if its key matches, else capture `seq` (on a private stream, so that any
 // user stream works) and launch the new graph.  Allocates nothing on the
 // device outside the graph itself.
+// Drop the captured graph (keeping the cache entry, now empty).
+static void graph_forget(rst_ctx *ctx) {
+  if (!ctx->graph) ctx->graph = new GraphCache;
+  if (ctx->graph->exec) (void)hipGraphExecDestroy(ctx->graph->exec);
+  ctx->graph->exec = nullptr;
+  std::memset(&ctx->graph->key, 0, sizeof ctx->graph->key);
+}
+
 template <class Seq>
 static rst_status run_graph(rst_ctx *ctx, const GraphKey &key, Seq seq) {
   if (ctx->graph && ctx->graph->exec && ctx->graph->key == key) {
@@ -317,13 +396,13 @@ static rst_status take_bfs_bufs(rst_ctx *ctx, const rst_csr *g, BfsBufs &b) {
   b.q[1] = ws_take<int32_t>(ctx, g->n);
   b.h[0] = ws_take<int32_t>(ctx, b.heavy_cap);
   b.h[1] = ws_take<int32_t>(ctx, b.heavy_cap);
-  b.cnt = ws_take<int32_t>(ctx, 8);
+  b.cnt = ws_take<int32_t>(ctx, kBfsCntWords);
   return RST_OK;
 }
 
 static size_t bfs_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
   const size_t hc = bfs_heavy_capacity(ctx, g->n, g->nnz);
-  return 2 * ws_bytes(g->n, 4) + 2 * ws_bytes(hc, 4) + ws_bytes(8, 4);
+  return 2 * ws_bytes(g->n, 4) + 2 * ws_bytes(hc, 4) + ws_bytes(kBfsCntWords, 4);
 }
 
 static size_t hook_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
@@ -334,7 +413,7 @@ static size_t hook_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
 static size_t gconn_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
   const size_t n = (size_t)g->n;
   return 6 * ws_bytes(n, 4) + 2 * ws_bytes(2 * n, 4) + ws_bytes(2 * n, 8) + hook_ws_bytes(ctx, g) +
-         rank_ws_bytes(2 * g->n);
+         rank_ws_bytes(2 * g->n) + glist_ws_bytes(gconn_glist_plan(ctx, g->n));
 }
 
 }  // namespace rst
@@ -357,7 +436,7 @@ rst_status rst_create(rst_ctx **out, int device, void *hip_stream) {
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       cus > 0)
     ctx->num_cus = cus;
-  for (int i = 0; i < 24; ++i) {
+  for (int i = 0; i < kNumEvents; ++i) {
     if (hipEventCreate(&ctx->ev[i]) != hipSuccess) { rst_destroy(ctx); return RST_E_DEVICE; }
   }
   if (hipHostMalloc(reinterpret_cast<void **>(&ctx->host_pinned), 64 * sizeof(int32_t),
@@ -380,7 +459,7 @@ void rst_destroy(rst_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws.base) (void)hipFree(ctx->ws.base);
-  for (int i = 0; i < 24; ++i)
+  for (int i = 0; i < kNumEvents; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
   selector_free(ctx);
   tune_free(ctx);
@@ -427,6 +506,10 @@ rst_status rst_set_option(rst_ctx *ctx, rst_option opt, int64_t value) {
     case RST_OPT_GRAPHS:
       ctx->opt.graphs = value ? 1 : 0;
       return RST_OK;
+    case RST_OPT_RANK_STRIDE:
+      if (value != 4 && value != 8 && value != 16 && value != 32 && value != 64) return RST_E_INVAL;
+      ctx->opt.rank_stride = (int)value;
+      return RST_OK;
   }
   return RST_E_INVAL;
 }
@@ -442,6 +525,7 @@ rst_status rst_get_option(const rst_ctx *ctx, rst_option opt, int64_t *value) {
     case RST_OPT_SWEEP_BLOCK: *value = ctx->opt.sweep_block; return RST_OK;
     case RST_OPT_BFS_HEAVY_DEGREE: *value = ctx->opt.bfs_heavy_degree; return RST_OK;
     case RST_OPT_GRAPHS: *value = ctx->opt.graphs; return RST_OK;
+    case RST_OPT_RANK_STRIDE: *value = ctx->opt.rank_stride; return RST_OK;
   }
   return RST_E_INVAL;
 }
@@ -483,21 +567,44 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
   if (method == RST_GCONN_EULER && ctx->opt.graphs && !stats && !ctx->opt.validate) {
     // the whole device part of the call as one captured graph, replayed while
     // the graph, buffers and settings stay the same
-    GconnWork w = take_gconn_work(ctx, g, counters, nullptr, nullptr);
-    w.settled = true;   // one root (a replay does not run enqueue_gconn's host code)
-    w.exported = ctx->host_pinned_dev != nullptr;
     GraphKey key;
     std::memset(&key, 0, sizeof key);
     key.offsets = g->offsets; key.cols = g->cols; key.parent = parent;
     key.ws_base = ctx->ws.base; key.ws_cap = (int64_t)ctx->ws.cap;
     key.n = g->n; key.nnz = g->nnz; key.offset_bytes = g->offset_bytes; key.root = root;
     key.opt = ctx->opt;
+    int64_t comps = 0;
+    if (!ctx->graph || !(ctx->graph->key == key)) {
+      // first call with these buffers and settings: run eagerly, choosing the
+      // ranking from the hooking counters; the next call captures that choice
+      RST_TRY(enqueue_reset_counters(ctx, counters, root));
+      bool sparse = false;
+      RST_TRY(run_gconn_euler(ctx, g, rootbuf, 1, parent, nullptr, &comps, counters, nullptr,
+                              nullptr, &sparse));
+      graph_forget(ctx);
+      ctx->graph->key = key;
+      ctx->graph->sparse = sparse;
+      return comps > 1 ? RST_E_DISCONNECTED : RST_OK;
+    }
+    GconnWork w = take_gconn_work(ctx, g, counters, nullptr, nullptr);
+    w.settled = true;   // one root (a replay does not run the host code of the enqueue functions)
+    w.exported = ctx->host_pinned_dev != nullptr;
+    w.sparse = ctx->graph->sparse;
     RST_TRY(run_graph(ctx, key, [&]() -> rst_status {
       RST_TRY(enqueue_reset_counters(ctx, counters, root));
-      return enqueue_gconn(ctx, g, rootbuf, 1, parent, nullptr, w);
+      RST_TRY(enqueue_gconn_forest(ctx, g, rootbuf, 1, parent, nullptr, w));
+      return enqueue_gconn_rank(ctx, g, parent, nullptr, w);
     }));
-    int64_t comps = 0;
+    w.sparse_ran = w.sparse;
     RST_TRY(finish_gconn(ctx, g, parent, nullptr, &comps, w));
+    // the data under these buffers may have changed since the capture: when
+    // the other ranking suits it now, the next call captures that one
+    const bool want = prefer_sparse_rank(ctx->host_pinned[kCntCross], g->n);
+    if (want != w.sparse && ctx->graph->exec) {
+      RST_HIP(hipGraphExecDestroy(ctx->graph->exec));
+      ctx->graph->exec = nullptr;
+      ctx->graph->sparse = want;
+    }
     return comps > 1 ? RST_E_DISCONNECTED : RST_OK;
   }
 
@@ -684,16 +791,22 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
   if (nroots > 0 && !roots) return RST_E_INVAL;
   if (n >= ((int64_t)1 << 30)) return RST_E_INVAL;
   RST_HIP(hipSetDevice(ctx->device));
-  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 4 * ws_bytes(n, 4) + 2 * ws_bytes(2 * t + 2, 4) +
-                              ws_bytes(2 * t + 2, 8) + rank_ws_bytes(2 * t)));
+  const int64_t lists = (t < n / 2 ? t : n / 2) + 1;
+  const GlistPlan plan = glist_plan(2 * t, lists, ctx->opt.rank_stride);
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 5 * ws_bytes(n, 4) + 2 * ws_bytes(2 * t + 2, 4) +
+                              ws_bytes(2 * t + 2, 8) + rank_ws_bytes(2 * t) +
+                              glist_ws_bytes(plan)));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
   int32_t *cc = ws_take<int32_t>(ctx, n);
   int32_t *comp_root = ws_take<int32_t>(ctx, n);
   int32_t *head = ws_take<int32_t>(ctx, n);
+  int32_t *endsucc = ws_take<int32_t>(ctx, n);
   int32_t *next = ws_take<int32_t>(ctx, 2 * t + 2);
   uint64_t *rank = ws_take<uint64_t>(ctx, 2 * t + 2);
   int32_t *xid = ws_take<int32_t>(ctx, 2 * t + 2);
   RankBufs rb = take_rank_bufs(ctx, 2 * t);
+  GlistBufs gl;
+  glist_take(ctx, plan, gl);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(enqueue_hook_coo(ctx, n, t, eu, ev, cc, counters));
   RST_TRY(enqueue_compress(ctx, n, cc, comp_root, head));
@@ -701,16 +814,26 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
   if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
   RST_TRY(enqueue_mark_roots(ctx, roots, nroots, n, cc, comp_root, parent, counters));
   RST_TRY(enqueue_link(ctx, t, eu, ev, head, next));
-  SlotArcs arcs{eu, ev, next, head, cc, comp_root, n, ws_take<int32_t>(ctx, n)};
+  SlotArcs arcs{eu, ev, next, head, cc, comp_root, n, endsucc};
   RST_TRY(enqueue_rank_tiled(ctx, 2 * t, rank, xid, rb, counters, &arcs, false));
   RST_TRY(enqueue_expand_parent(ctx, t, n, eu, ev, rank, xid, rb.tile_base, rb.crank, cc,
                                 comp_root, parent, counters));
   RST_TRY(read_counters(ctx, counters));
   if (ctx->host_pinned[kCntRankOverflow]) {
-    RST_TRY(rank_overflow_fallback(ctx, rb, counters));
-    RST_TRY(enqueue_expand_parent(ctx, t, n, eu, ev, rank, xid, rb.tile_base, rb.crank, cc,
-                                  comp_root, parent, counters));
+    // contracted list too long for one workgroup: the sparse ruling set over
+    // the tour (endsucc was filled by the per-tile pass)
+    int32_t *w1 = reinterpret_cast<int32_t *>(rank);
+    RST_TRY(enqueue_fill(ctx, counters + kCntRankOverflow, 1, 0));
+    RST_TRY(enqueue_glist_from_slots(ctx, t, n, eu, ev, next, endsucc, head, w1, gl, counters));
+    RST_TRY(enqueue_glist_rank(ctx, w1, gl, counters));
+    RST_TRY(enqueue_glist_parent(ctx, t, n, eu, ev, w1, gl, cc, comp_root, parent, counters,
+                                 nullptr));
     RST_TRY(read_counters(ctx, counters));
+    if (ctx->host_pinned[kCntGOverflow]) {
+      RST_TRY(glist_wyllie_parent(ctx, t, n, eu, ev, next, endsucc, rank, cc, comp_root, parent,
+                                  counters));
+      RST_TRY(read_counters(ctx, counters));
+    }
   }
   if (ctx->host_pinned[kCntRangeErr] || ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
   return RST_OK;
@@ -721,18 +844,37 @@ rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *
   if (A >= ((int64_t)1 << 31)) return RST_E_INVAL;
   if (A == 0) return RST_OK;
   RST_HIP(hipSetDevice(ctx->device));
-  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + ws_bytes(A, 8) + ws_bytes(A, 4) + rank_ws_bytes(A)));
+  const GlistPlan plan = glist_plan(A, A, ctx->opt.rank_stride);
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + ws_bytes(A, 8) + ws_bytes(A, 4) + rank_ws_bytes(A) +
+                              glist_ws_bytes(plan)));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
   uint64_t *rank = ws_take<uint64_t>(ctx, A);
   int32_t *xid = ws_take<int32_t>(ctx, A);
   RankBufs rb = take_rank_bufs(ctx, A);
+  GlistBufs gl;
+  glist_take(ctx, plan, gl);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(enqueue_rank_init(ctx, A, succ, rank));
   RST_TRY(enqueue_rank_tiled(ctx, A, rank, xid, rb, counters, nullptr, true));
   RST_TRY(read_counters(ctx, counters));
   if (ctx->host_pinned[kCntRankOverflow]) {
-    RST_TRY(rank_overflow_fallback(ctx, rb, counters));
-    RST_TRY(enqueue_rank_expand(ctx, A, rank, xid, rb, counters));
+    // contracted list too long for one workgroup: the sparse ruling set over
+    // the input lists (level-1 words in rank, has-predecessor bytes in xid)
+    int32_t *w1 = reinterpret_cast<int32_t *>(rank);
+    RST_TRY(enqueue_fill(ctx, counters + kCntRankOverflow, 1, 0));
+    RST_TRY(enqueue_glist_from_succ(ctx, A, succ, w1, reinterpret_cast<uint8_t *>(xid), gl,
+                                    counters));
+    RST_TRY(enqueue_glist_rank(ctx, w1, gl, counters));
+    RST_TRY(enqueue_glist_dist(ctx, A, w1, gl, dist, counters));
+    RST_TRY(read_counters(ctx, counters));
+    if (ctx->host_pinned[kCntGOverflow]) {
+      // more lists than the sparse ruling set holds: Wyllie rounds over all nodes
+      RST_TRY(enqueue_rank_init(ctx, A, succ, rank));
+      RST_TRY(enqueue_rank_rounds(ctx, A, rank, rank_rounds_for(A), nullptr, nullptr));
+      RST_TRY(enqueue_rank_extract(ctx, A, rank, dist));
+    }
+    RST_HIP(hipStreamSynchronize(ctx->stream));
+    return RST_OK;
   }
   RST_TRY(enqueue_rank_extract(ctx, A, rank, dist));
   RST_HIP(hipStreamSynchronize(ctx->stream));
@@ -761,7 +903,7 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(run_validation(ctx, g, counters));
   RST_TRY(enqueue_batch_check(ctx, g, b, counters));
-  RST_TRY(mark(ctx, stats, 16));
+  RST_TRY(mark(ctx, stats, kEvBatchBase));
   // per-graph method: given, chosen by the selector, or GConn+Euler for all
   if (method) {
     RST_TRY(enqueue_copy_u8(ctx, method, m, G));
@@ -770,7 +912,7 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
   } else {
     RST_TRY(enqueue_fill_u8(ctx, m, G, 0));
   }
-  RST_TRY(mark(ctx, stats, 17));
+  RST_TRY(mark(ctx, stats, kEvBatchBase + 1));
   RST_TRY(enqueue_count_methods(ctx, b, m, counters));
   RST_TRY(read_counters(ctx, counters));
   if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
@@ -785,7 +927,7 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
                             counters, nullptr, nbfs > 0 ? vmask : nullptr));
     if (stats) {
       for (int i = 0; i < 8; ++i) stats->ms_stage[i] += inner.ms_stage[i];
-      for (int i = 0; i < 4; ++i) stats->ms_kernel[i] = inner.ms_kernel[i];
+      for (int i = 0; i < kNumKernelTimes; ++i) stats->ms_kernel[i] = inner.ms_kernel[i];
       stats->hook_rounds = inner.hook_rounds;
       stats->rank_rounds = inner.rank_rounds;
       stats->rank_exits = inner.rank_exits;
@@ -801,7 +943,7 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
     // graphs' vertices are left as written above
     BfsBufs bb;
     RST_TRY(take_bfs_bufs(ctx, g, bb));
-    RST_TRY(mark(ctx, stats, 18));
+    RST_TRY(mark(ctx, stats, kEvBatchBase + 2));
     RST_TRY(bfs_reset(ctx, n, level, nullptr, bb));
     RST_TRY(bfs_seed_roots(ctx, g, b->roots, G, level, parent, bb, counters, m));
     RST_TRY(bfs_run_levels(ctx, g, level, parent, bb, counters, &levels));
@@ -827,14 +969,14 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
       int64_t l2 = 0;
       RST_TRY(bfs_run_levels(ctx, g, level, parent, bb, counters, &l2));
     }
-    RST_TRY(mark(ctx, stats, 19));
+    RST_TRY(mark(ctx, stats, kEvBatchBase + 3));
   }
   if (method_out) RST_TRY(enqueue_copy_u8(ctx, m, method_out, G));
   RST_HIP(hipStreamSynchronize(ctx->stream));
   if (stats) {
     float ms = 0.f;
-    if (event_ms(ctx->ev[16], ctx->ev[17], &ms)) stats->ms_stage[RST_STAGE_SELECT] = ms;
-    if (nbfs > 0 && event_ms(ctx->ev[18], ctx->ev[19], &ms)) stats->ms_stage[RST_STAGE_BFS] = ms;
+    if (event_ms(ctx->ev[kEvBatchBase], ctx->ev[kEvBatchBase + 1], &ms)) stats->ms_stage[RST_STAGE_SELECT] = ms;
+    if (nbfs > 0 && event_ms(ctx->ev[kEvBatchBase + 2], ctx->ev[kEvBatchBase + 3], &ms)) stats->ms_stage[RST_STAGE_BFS] = ms;
     stats->ms_total = 0.f;
     for (int i = 0; i < 8; ++i) stats->ms_total += stats->ms_stage[i];
     stats->bfs_levels = levels;

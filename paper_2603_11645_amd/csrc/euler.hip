@@ -1111,6 +1111,13 @@ int rank_rounds_for(int64_t max_list_len) {
   return r;
 }
 
+rst_status enqueue_endsucc(rst_ctx *ctx, int64_t n, const int32_t *head, const int32_t *cc,
+                           const int32_t *comp_root, int32_t *endsucc) {
+  RST_SWEEP(ctx, k_endsucc, n, n, head, cc, comp_root, endsucc);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
 rst_status enqueue_settle(rst_ctx *ctx, int64_t n, const int32_t *roots, const int32_t *cc,
                           const int32_t *head, int32_t *endsucc, int32_t *parent,
                           int32_t *counters) {
@@ -1191,11 +1198,9 @@ rst_status enqueue_rank_tiled(rst_ctx *ctx, int64_t A, uint64_t *rank, int32_t *
   if (A <= 0) return RST_OK;
   const int64_t tiles = (int64_t)rank_tile_count(A);
   if (from_slots) {
-    if (!from_slots->endsucc_ready) {
-      RST_SWEEP(ctx, k_endsucc, from_slots->n, from_slots->n, from_slots->head, from_slots->cc,
-                from_slots->comp_root, from_slots->endsucc);
-      RST_HIP(hipGetLastError());
-    }
+    if (!from_slots->endsucc_ready)
+      RST_TRY(enqueue_endsucc(ctx, from_slots->n, from_slots->head, from_slots->cc,
+                              from_slots->comp_root, from_slots->endsucc));
     SlotSrc src{from_slots->tu, from_slots->tv, from_slots->next, from_slots->endsucc};
     RST_KMARK(ctx, RST_KERNEL_RANK_TILE, 0);
     hipLaunchKernelGGL(k_rank_tile<true>, dim3((unsigned)tiles), dim3(kRankThreads), 0, ctx->stream,

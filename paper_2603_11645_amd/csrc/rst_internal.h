@@ -28,6 +28,7 @@ struct Options {
   int sweep_block = 256;         // threads per block of the per-vertex/per-slot sweeps
   int bfs_heavy_degree = 1024;   // BFS: frontier vertices above this are split over blocks
   int graphs = 1;                // capture the device work of a call as a HIP graph and replay it
+  int rank_stride = 16;          // sparse ruling set: every k-th arc starts a ruler
 };
 
 // Launch sweep kernel template `kern<B>` over `items` threads with the
@@ -78,7 +79,7 @@ struct rst_ctx {
   int num_cus = 256;
   rst::Workspace ws;
   rst::Options opt;
-  hipEvent_t ev[24] = {};   // 0-6 stages, 8-15 kernel pairs, 16-19 batch marks
+  hipEvent_t ev[32] = {};   // 0-6 stages, 8-23 kernel pairs, 24-27 batch marks
   int32_t *host_pinned = nullptr;   // small pinned host buffer for flag readback
   int32_t *host_pinned_dev = nullptr;   // its device address (null: read back by copies only)
   bool timing = false;              // record per-kernel events (a stats struct was passed)
@@ -101,7 +102,7 @@ namespace rst {
   } while (0)
 
 // per-kernel event pairs in ctx->ev[8..15], recorded only while ctx->timing is set
-enum { kEvKernelBase = 8 };
+enum { kEvKernelBase = 8, kNumKernelTimes = 8, kEvBatchBase = 24, kNumEvents = 32 };
 #define RST_KMARK(ctx, kernel, end)                                                          \
   do {                                                                                        \
     if ((ctx)->timing) {                                                                      \
@@ -168,7 +169,11 @@ enum {
   kCntKept = 14,           // cross edges kept by the deduplication pass
   kCntKeptTop = 15,        // of those, the edges of the levels merged by the top pass
                            // (kCntKept and kCntKeptTop: one 8-byte word, added to at once)
-  kCntTotal = 16,          // counters read back after a call (the ones above)
+  kCntGHeads = 16,         // sparse ruling set: list heads found
+  kCntGDyn = 17,           //   rulers opened by walks that reached the piece cap
+  kCntGOverflow = 18,      //   heads or ruler ids beyond capacity (caller ranks otherwise)
+  kCntGTopWords = 19,      //   words of the top level (one workgroup)
+  kCntTotal = 24,          // counters read back after a call (the ones above)
 };
 
 // hook.hip
@@ -253,6 +258,53 @@ rst_status enqueue_expand_parent(rst_ctx *ctx, int64_t slots, int64_t n, const i
                                  const int32_t *comp_root, int32_t *parent, int32_t *counters,
                                  int32_t *host_out = nullptr);
 
+// glrank.hip: list ranking by a sparse ruling set in global memory (tours
+// without id locality).  Level-1 words are int32 per arc (successor, then the
+// arc's code); every later level is 64-bit (next, weight) words.
+constexpr int kGlMaxLevels = 8;
+constexpr int kGlStrideUpper = 16;   // ruler stride of the levels above the first
+struct GlistPlan {
+  int64_t A = 0;                      // level-1 words
+  int64_t hcap = 1;                   // list heads the buffers hold
+  int k1 = 16, k = kGlStrideUpper;    // ruler strides: level 1, the levels above
+  int levels = 2;                     // walks at levels 1 .. levels-1, one workgroup at `levels`
+  int64_t cap[kGlMaxLevels] = {};     // cap[L]: ruler words of level L
+};
+struct GlistBufs {
+  GlistPlan plan;
+  int32_t *heads[2] = {nullptr, nullptr};   // list heads per level (alternating)
+  uint64_t *rw[kGlMaxLevels] = {};          // rw[L]: ruler words of level L
+};
+// max_heads: an upper bound on the number of lists (capped internally)
+GlistPlan glist_plan(int64_t A, int64_t max_heads, int k1);
+size_t glist_ws_bytes(const GlistPlan &p);
+void glist_take(rst_ctx *ctx, const GlistPlan &p, GlistBufs &g);
+// level-1 words and list heads from forest slots (vertices with endsucc -1
+// root their trees; their first out-arcs head the lists)
+rst_status enqueue_glist_from_slots(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
+                                    const int32_t *tv, const int32_t *next,
+                                    const int32_t *endsucc, const int32_t *head, int32_t *w1,
+                                    GlistBufs &g, int32_t *counters);
+// level-1 words and list heads from a successor array; haspred: A bytes scratch
+rst_status enqueue_glist_from_succ(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *w1,
+                                   uint8_t *haspred, GlistBufs &g, int32_t *counters);
+rst_status enqueue_glist_rank(rst_ctx *ctx, int32_t *w1, GlistBufs &g, int32_t *counters);
+rst_status enqueue_glist_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
+                                const int32_t *tv, const int32_t *w1, const GlistBufs &g,
+                                const int32_t *cc, const int32_t *comp_root, int32_t *parent,
+                                int32_t *counters, int32_t *host_out);
+rst_status enqueue_glist_dist(rst_ctx *ctx, int64_t A, const int32_t *w1, const GlistBufs &g,
+                              int32_t *dist, const int32_t *counters);
+// last resort after counters[kCntGOverflow]: Wyllie rounds over every arc
+// (rank: uint64 [2 slots]), the parent rule, and the flag cleared
+rst_status glist_wyllie_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
+                               const int32_t *tv, const int32_t *next, const int32_t *endsucc,
+                               uint64_t *rank, const int32_t *cc, const int32_t *comp_root,
+                               int32_t *parent, int32_t *counters);
+// end-of-list successors (one per vertex, -1 where the vertex roots its tree)
+rst_status enqueue_endsucc(rst_ctx *ctx, int64_t n, const int32_t *head, const int32_t *cc,
+                           const int32_t *comp_root, int32_t *endsucc);
+
 // verify.hip: device check of a rooted spanning forest.  vc[0] += failures,
 // vc[1] = min failing vertex (caller initialises 0 and INT32_MAX); anc0/anc1:
 // int32 [n] scratch.
@@ -267,9 +319,12 @@ void graph_free(rst_ctx *ctx);
 struct BfsBufs {
   int32_t *q[2];       // light frontier queues [n]
   int32_t *h[2];       // heavy frontier queues [heavy_cap]
-  int32_t *cnt;        // [3][2] rotating (light, heavy) counts
+  int32_t *cnt;        // [kBfsCntWords]: [3][2] rotating (light, heavy) counts, then the
+                       // level state of the steps (see bfs.hip)
   int64_t heavy_cap;
 };
+constexpr int kBfsStateWord = 8;    // cnt[8..11]: level by launch parity, "wide next" by parity
+constexpr int kBfsCntWords = 16;
 size_t bfs_heavy_capacity(const rst_ctx *ctx, int64_t n, int64_t nnz);
 // level[] = -1 (and parent[] = -1 unless parent is NULL), counts zeroed
 rst_status bfs_reset(rst_ctx *ctx, int64_t n, int32_t *level, int32_t *parent, BfsBufs &b);

@@ -309,7 +309,7 @@ rst_status run_selector(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, uint
   bb.q[1] = ws_take<int32_t>(ctx, g->n);
   bb.h[0] = ws_take<int32_t>(ctx, bb.heavy_cap);
   bb.h[1] = ws_take<int32_t>(ctx, bb.heavy_cap);
-  bb.cnt = ws_take<int32_t>(ctx, 8);
+  bb.cnt = ws_take<int32_t>(ctx, kBfsCntWords);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(enqueue_features(ctx, g, b, feat, src, level, bb, counters));
   return enqueue_mlp_forward(ctx, G, ctx->selector->dev, ctx->selector->dev + 16, feat, nullptr,
@@ -319,7 +319,7 @@ rst_status run_selector(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, uint
 size_t selector_scratch_bytes(const rst_ctx *ctx, const rst_csr *g, int32_t G) {
   const size_t hc = bfs_heavy_capacity(ctx, g->n, g->nnz);
   return ws_bytes((size_t)G * kIn, 4) + ws_bytes(G, 4) + 3 * ws_bytes(g->n, 4) + ws_bytes(64, 4) +
-         2 * ws_bytes(hc, 4) + ws_bytes(8, 4);
+         2 * ws_bytes(hc, 4) + ws_bytes(kBfsCntWords, 4);
 }
 
 void selector_free(rst_ctx *ctx) {
@@ -352,7 +352,7 @@ rst_status rst_features(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, floa
   bb.q[1] = ws_take<int32_t>(ctx, g->n);
   bb.h[0] = ws_take<int32_t>(ctx, bb.heavy_cap);
   bb.h[1] = ws_take<int32_t>(ctx, bb.heavy_cap);
-  bb.cnt = ws_take<int32_t>(ctx, 8);
+  bb.cnt = ws_take<int32_t>(ctx, kBfsCntWords);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(enqueue_features(ctx, g, b, feat, src, level, bb, counters));
   RST_HIP(hipStreamSynchronize(ctx->stream));

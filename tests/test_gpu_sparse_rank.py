@@ -1,0 +1,179 @@
+"""GPU parity of the sparse ruling set in global memory (list ranking of
+Sec. III-D for lists and tours whose ids carry no locality).
+
+Ranks are unique given the successors, so they are compared bit for bit with
+the oracle's sequential walk; rooting a fixed forest is unique, so
+rst_root_forest is compared bit for bit with DFS rooting; on tree inputs the
+whole GConn+Euler parent array is unique.  Covered: one random list of 2^25
+nodes, many lists, a list whose ruler-free stretch forces opened rulers, more
+lists than the ruling set holds (the Wyllie last resort), every ruler stride,
+random-id forests through rst_root_forest, random-id graphs and trees through
+rst_spanning_tree (eager first call, captured second call, replays, and a
+switch of the data under the same buffers).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_11645_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rst():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_11645_amd as r
+    return r
+
+
+@pytest.fixture(scope="module")
+def ctx(rst):
+    return rst.Context(0)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def lists_from_order(order, nlists, rs):
+    A = len(order)
+    succ = np.full(A, -1, np.int32)
+    cuts = np.sort(rs.choice(np.arange(1, A), size=nlists - 1, replace=False)) if nlists > 1 \
+        else np.array([], np.int64)
+    for piece in np.split(order, cuts):
+        succ[piece[:-1]] = piece[1:]
+    return succ
+
+
+def check_rank(ctx, succ):
+    exp, k = oracle.list_rank(succ)
+    got = ctx.list_rank(dev(succ)).cpu().numpy()
+    assert np.array_equal(got, exp)
+    return k
+
+
+def test_random_list_2_pow_25(ctx):
+    rs = np.random.RandomState(25)
+    A = 1 << 25
+    succ = lists_from_order(rs.permutation(A).astype(np.int32), 1, rs)
+    assert check_rank(ctx, succ) == 1
+
+
+@pytest.mark.parametrize("A,nlists", [(20001, 1), (300007, 13), (1 << 22, 1000), (999999, 77777)])
+def test_random_lists(ctx, A, nlists):
+    rs = np.random.RandomState(A % 1000 + nlists)
+    succ = lists_from_order(rs.permutation(A).astype(np.int32), nlists, rs)
+    assert check_rank(ctx, succ) == nlists
+
+
+def test_opened_rulers(ctx):
+    """A list that runs through every id off the stride first: with strided
+    rulers only at ids 0 mod k its first stretch has none, so walks open
+    rulers every 255 arcs."""
+    rs = np.random.RandomState(7)
+    A = 200000
+    ids = rs.permutation(A).astype(np.int32)
+    order = np.concatenate([ids[ids % 64 != 0], ids[ids % 64 == 0]])
+    check_rank(ctx, lists_from_order(order, 1, rs))
+    # and two such lists interleaved with short ones
+    check_rank(ctx, lists_from_order(order, 9, rs))
+
+
+def test_more_lists_than_rulers_hold(ctx):
+    """1.1 million two-node lists over random ids: more list heads than the
+    sparse ruling set holds, ranked by the Wyllie last resort."""
+    rs = np.random.RandomState(11)
+    A = 2200000
+    pairs = rs.permutation(A).astype(np.int32).reshape(-1, 2)
+    succ = np.full(A, -1, np.int32)
+    succ[pairs[:, 0]] = pairs[:, 1]
+    assert check_rank(ctx, succ) == A // 2
+
+
+def test_every_stride(ctx, rst):
+    rs = np.random.RandomState(4)
+    A = 700001
+    succ = lists_from_order(rs.permutation(A).astype(np.int32), 5, rs)
+    exp, _ = oracle.list_rank(succ)
+    try:
+        for k in (4, 8, 16, 32, 64):
+            ctx.set_option(rst.OPT_RANK_STRIDE, k)
+            assert ctx.get_option(rst.OPT_RANK_STRIDE) == k
+            got = ctx.list_rank(dev(succ)).cpu().numpy()
+            assert np.array_equal(got, exp), k
+        with pytest.raises(rst.RstError):
+            ctx.set_option(rst.OPT_RANK_STRIDE, 12)
+    finally:
+        ctx.set_option(rst.OPT_RANK_STRIDE, 16)
+
+
+@pytest.mark.parametrize("n,ntrees", [(300000, 1), (400000, 5), (250000, 3000)])
+def test_root_forest_random_ids(ctx, n, ntrees):
+    """Forests over random ids (the per-tile ranking overflows and the sparse
+    ruling set takes over): parents equal DFS rooting bit for bit."""
+    rs = np.random.RandomState(n + ntrees)
+    perm = rs.permutation(n).astype(np.int32)
+    # a random recursive forest: vertex i > 0 hangs below a random earlier one,
+    # except the first vertex of each of the ntrees blocks
+    starts = set(np.linspace(0, n, ntrees, endpoint=False).astype(np.int64).tolist())
+    eu, ev = [], []
+    for i in range(1, n):
+        if i in starts:
+            continue
+        eu.append(perm[i])
+        ev.append(perm[rs.randint(0, i)])
+    eu = np.array(eu, np.int32)
+    ev = np.array(ev, np.int32)
+    roots = np.array([perm[s] for s in sorted(starts)][: max(1, ntrees // 2)], np.int32)
+    exp = oracle.dfs_root(n, eu, ev, roots)
+    got = ctx.root_forest(n, dev(eu), dev(ev), dev(roots)).cpu().numpy()
+    assert np.array_equal(got, exp)
+
+
+def test_spanning_tree_random_ids(ctx, rst):
+    """Graphs with random ids rank their tour by the sparse ruling set; the
+    trees pass the verifier (and on a tree input equal the unique answer)."""
+    for g, root in ((I.grid_permuted(256, seed=1), 0), (I.long_chain(1 << 20, 0.005, 64, seed=4), 0),
+                    (I.rmat_lcc(16, 16, seed=3), 0), (I.random_graph(200000, 300000, seed=5), 17)):
+        off, cols = dev(g.offsets_typed()), dev(g.cols)
+        par, st = ctx.spanning_tree(off, cols, root, "gconn", stats=True)
+        assert st["paths"] & rst.PATH_RANK_SPARSE, st
+        p = par.cpu().numpy()
+        code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, p, [root])
+        assert code == 0, (g.name, oracle.VERIFY_CODES[code], bad)
+    t = I.random_tree(500000, seed=9)
+    eu, ev = t.edge_list()
+    exp = oracle.dfs_root(t.n, eu, ev, [123])
+    off, cols = dev(t.offsets_typed()), dev(t.cols)
+    par, st = ctx.spanning_tree(off, cols, 123, "gconn", stats=True)
+    assert st["paths"] & rst.PATH_RANK_SPARSE
+    assert np.array_equal(par.cpu().numpy(), exp)
+
+
+def test_graph_path_choice_and_switch(ctx, rst):
+    """The captured-graph path: the first call runs eagerly and chooses the
+    ranking, the second captures it, later calls replay; when the data under
+    the same buffers changes to ids with locality (or back), the replayed
+    result is still exact and the next capture takes the other ranking."""
+    n = 300000
+    rs = np.random.RandomState(3)
+    perm = rs.permutation(n).astype(np.int32)
+    trees = [I.path(n, perm=perm), I.path(n), I.path(n, perm=perm)]
+    off = dev(trees[0].offsets_typed())
+    cols = dev(trees[0].cols)
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
+    root = 77
+    for t in trees:
+        off.copy_(dev(t.offsets_typed()))
+        cols.copy_(dev(t.cols))
+        eu, ev = t.edge_list()
+        exp = oracle.dfs_root(n, eu, ev, [root])
+        for _ in range(4):
+            parent.fill_(-5)
+            ctx.spanning_tree(off, cols, root, "gconn", parent=parent)
+            assert ctx.last_status == 0
+            assert np.array_equal(parent.cpu().numpy(), exp)
+            torch.cuda.synchronize()
