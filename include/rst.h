@@ -219,6 +219,17 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
  * Cycles give unspecified output. */
 rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *dist);
 
+/* Depth of every vertex of a rooted forest (the tree-depth comparison of
+ * Sec. IV-B, Fig. 2), computed from its Euler tour (Sec. III-D): arcs weigh
+ * +1 going down and -1 going up, and the depth of v is the weighted position
+ * of the arc into v, found by weighted list ranking.  parent: device int32
+ * [n], P[r] = r at roots (an entry outside [0, n) is taken as a root); depth:
+ * device int32 [n] receives the number of tree edges from each vertex to its
+ * root; max_depth: host, nullable, receives the largest.  A parent array with
+ * a cycle gives unspecified depths for the vertices on or below it. */
+rst_status rst_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *depth,
+                          int64_t *max_depth);
+
 /* Rooted spanning forest of G packed graphs in one pass: graph g is rooted at
  * roots[g].  method: device uint8 [G] per graph (0 = GConn+Euler, nonzero =
  * BFS), or NULL to let the loaded selector choose (GConn+Euler if none is

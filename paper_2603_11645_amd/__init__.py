@@ -55,7 +55,7 @@ EXPORTS = [
     "rst_components", "rst_spanning_forest", "rst_bfs", "rst_root_forest", "rst_list_rank",
     "rst_spanning_forest_batch", "rst_selector_load", "rst_status_string", "rst_features",
     "rst_feature_stats", "rst_mlp_forward", "rst_mlp_train_step", "rst_get_option",
-    "rst_verify", "rst_autotune", "rst_tune_save", "rst_tune_load",
+    "rst_verify", "rst_autotune", "rst_tune_save", "rst_tune_load", "rst_tree_depth",
 ]
 
 N_FEATURES = 8
@@ -157,6 +157,7 @@ def load_library(path: Optional[str] = None):
             "rst_autotune": (S, [P, ctypes.POINTER(rst_csr), i32, ctypes.c_int, i32,
                                  ctypes.POINTER(rst_tune_result)]),
             "rst_tune_save": (S, [P, ctypes.c_char_p]),
+            "rst_tree_depth": (S, [P, i64, P, P, ctypes.POINTER(i64)]),
             "rst_tune_load": (S, [P, ctypes.c_char_p, ctypes.POINTER(rst_csr), ctypes.c_int,
                                   ctypes.POINTER(i32)]),
         }
@@ -358,6 +359,19 @@ class Context:
                    ctypes.c_void_p(dist.data_ptr()))
         return dist
 
+
+    def tree_depth(self, parent, depth=None):
+        """(depth int32 device [n], max depth) of the rooted forest `parent`."""
+        torch = _torch()
+        _check_dev(parent, torch.int32, "parent")
+        n = int(parent.shape[0])
+        if depth is None:
+            depth = torch.empty(n, dtype=torch.int32, device=parent.device)
+        _check_dev(depth, torch.int32, "depth")
+        mx = ctypes.c_int64(0)
+        self._call("rst_tree_depth", n, ctypes.c_void_p(parent.data_ptr()),
+                   ctypes.c_void_p(depth.data_ptr()), ctypes.byref(mx))
+        return depth, int(mx.value)
 
     # -- batches and the selector ---------------------------------------------
     def _batch(self, vtx_off, arc_off, roots):

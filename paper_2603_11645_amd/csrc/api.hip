@@ -196,7 +196,7 @@ static rst_status enqueue_gconn_sparse(rst_ctx *ctx, int64_t n, int32_t *parent,
     RST_TRY(enqueue_endsucc(ctx, n, w.f.head, w.f.cc, w.f.comp_root, w.endsucc));
   RST_TRY(enqueue_glist_from_slots(ctx, n, n, w.f.tu, w.f.tv, w.f.next, w.endsucc, w.f.head,
                                    w.w1(), w.gl, w.f.counters));
-  RST_TRY(enqueue_glist_rank(ctx, w.w1(), w.gl, w.f.counters));
+  RST_TRY(enqueue_glist_rank(ctx, w.w1(), false, w.gl, w.f.counters));
   return enqueue_glist_parent(ctx, n, n, w.f.tu, w.f.tv, w.w1(), w.gl,
                               w.settled ? nullptr : w.f.cc, w.f.comp_root, parent, w.f.counters,
                               host_out);
@@ -217,7 +217,7 @@ static rst_status enqueue_gconn_rank(rst_ctx *ctx, const rst_csr *g, int32_t *pa
     if (!w.settled) RST_TRY(enqueue_endsucc(ctx, n, w.f.head, w.f.cc, w.f.comp_root, w.endsucc));
     RST_TRY(enqueue_glist_from_slots(ctx, n, n, w.f.tu, w.f.tv, w.f.next, w.endsucc, w.f.head,
                                      w.w1(), w.gl, w.f.counters));
-    RST_TRY(enqueue_glist_rank(ctx, w.w1(), w.gl, w.f.counters));
+    RST_TRY(enqueue_glist_rank(ctx, w.w1(), false, w.gl, w.f.counters));
     RST_TRY(mark(ctx, st, 5));
     RST_TRY(enqueue_glist_parent(ctx, n, n, w.f.tu, w.f.tv, w.w1(), w.gl,
                                  w.settled ? nullptr : w.f.cc, w.f.comp_root, parent,
@@ -825,7 +825,7 @@ rst_status rst_root_forest(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu
     int32_t *w1 = reinterpret_cast<int32_t *>(rank);
     RST_TRY(enqueue_fill(ctx, counters + kCntRankOverflow, 1, 0));
     RST_TRY(enqueue_glist_from_slots(ctx, t, n, eu, ev, next, endsucc, head, w1, gl, counters));
-    RST_TRY(enqueue_glist_rank(ctx, w1, gl, counters));
+    RST_TRY(enqueue_glist_rank(ctx, w1, false, gl, counters));
     RST_TRY(enqueue_glist_parent(ctx, t, n, eu, ev, w1, gl, cc, comp_root, parent, counters,
                                  nullptr));
     RST_TRY(read_counters(ctx, counters));
@@ -864,7 +864,7 @@ rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *
     RST_TRY(enqueue_fill(ctx, counters + kCntRankOverflow, 1, 0));
     RST_TRY(enqueue_glist_from_succ(ctx, A, succ, w1, reinterpret_cast<uint8_t *>(xid), gl,
                                     counters));
-    RST_TRY(enqueue_glist_rank(ctx, w1, gl, counters));
+    RST_TRY(enqueue_glist_rank(ctx, w1, false, gl, counters));
     RST_TRY(enqueue_glist_dist(ctx, A, w1, gl, dist, counters));
     RST_TRY(read_counters(ctx, counters));
     if (ctx->host_pinned[kCntGOverflow]) {
@@ -984,6 +984,14 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
     stats->method_used = nbfs == 0 ? RST_GCONN_EULER : (nbfs == G ? RST_BFS : -1);
   }
   return RST_OK;
+}
+
+rst_status rst_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *depth,
+                          int64_t *max_depth) {
+  if (!ctx || !parent || !depth || n < 1) return RST_E_INVAL;
+  if (n >= ((int64_t)1 << 30)) return RST_E_INVAL;
+  RST_HIP(hipSetDevice(ctx->device));
+  return run_tree_depth(ctx, n, parent, depth, max_depth);
 }
 
 const char *rst_status_string(rst_status s) {

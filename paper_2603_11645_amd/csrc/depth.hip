@@ -1,0 +1,161 @@
+// depth.hip -- depth of every vertex of a rooted forest by its Euler tour
+// (the tree-depth comparison of Sec. IV-B, Fig. 2; the tour of Sec. III-D).
+//
+// The forest is given by its parent array.  Non-root v holds the edge
+// (P[v], v) in slot v: arc 2v = P[v] -> v goes down, arc 2v+1 = v -> P[v]
+// goes up; every vertex's out-arcs form a list (atomic exchange), the tour
+// successor is next(rev e) or, at the end of a list, the first out-arc of the
+// arc's head, and the tour of each tree starts at its root's first out-arc and
+// ends at the arc whose successor would wrap around to it.  Along a tour the
+// arcs weigh +1 (down) and -1 (up); the depth of v is the sum of the weights
+// up to and including its down arc, and since a tour sums to zero, that is
+// minus the sum of the weights after it.  Each arc's word holds (successor,
+// weight of the successor), so the weighted distance to the tail computed
+// by the sparse ruling set of glrank.hip is exactly that sum.
+#include "rst_internal.h"
+#include "device_common.h"
+
+namespace rst {
+
+__device__ __forceinline__ bool depth_is_root(int32_t v, int32_t p, int64_t n) {
+  return p == v || p < 0 || p >= n;   // out-of-range parents are taken as roots
+}
+
+// Out-arc lists of the forest of parent edges (head = -1 beforehand).
+template <int B>
+__global__ __launch_bounds__(B) void k_depth_link(int64_t n, const int32_t *__restrict__ parent,
+                                                  int32_t *head, int32_t *next) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const int32_t p = parent[x];
+  int2 nx = make_int2(-1, -1);
+  if (!depth_is_root((int32_t)x, p, n)) {
+    nx.x = atomicExch(&head[p], (int32_t)(2 * x));        // arc 2x = p -> x
+    nx.y = atomicExch(&head[x], (int32_t)(2 * x + 1));    // arc 2x+1 = x -> p
+  }
+  reinterpret_cast<int2 *>(next)[x] = nx;
+}
+
+__device__ __forceinline__ uint64_t depth_word(int32_t succ) {
+  // weight of the successor arc: +1 down (even id), -1 up (odd id), 0 past the tail
+  const uint32_t w = succ < 0 ? 0u : ((succ & 1) ? 0xffffffffu : 1u);
+  return ((uint64_t)w << 32) | (uint32_t)succ;
+}
+
+// Level-1 words (successor, weight) of both arcs of every slot, and the list
+// heads (the first out-arc of every root with arcs).
+template <int B>
+__global__ __launch_bounds__(B) void k_depth_words(int64_t n, const int32_t *__restrict__ parent,
+                                                   const int32_t *__restrict__ head,
+                                                   const int32_t *__restrict__ next, uint64_t *w,
+                                                   int32_t *heads, int64_t hcap, int32_t *counters) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool is_head = false;
+  int32_t h = -1;
+  if (x < n) {
+    const int32_t p = parent[x];
+    ulonglong2 out = make_ulonglong2(0x00000000fffffffeull, 0x00000000fffffffeull);   // no list
+    if (depth_is_root((int32_t)x, p, n)) {
+      h = head[x];
+      is_head = h >= 0;
+    } else {
+      const int2 nx = reinterpret_cast<const int2 *>(next)[x];
+      // successor of 2x = p -> x: the arc after 2x+1 in x's list, or x's first
+      // (x is no root, so its list holds at least 2x+1)
+      const int32_t s0 = nx.y != -1 ? nx.y : head[x];
+      // successor of 2x+1 = x -> p: the arc after 2x in p's list, or p's
+      // first unless p roots its tree (the end of the tour)
+      int32_t s1 = nx.x;
+      if (s1 == -1) s1 = depth_is_root(p, parent[p], n) ? -1 : head[p];
+      out.x = depth_word(s0);
+      out.y = depth_word(s1);
+    }
+    reinterpret_cast<ulonglong2 *>(w)[x] = out;
+  }
+  const int slot = wave_append(is_head, &counters[kCntGHeads]);
+  if (is_head && slot < hcap) heads[slot] = h;
+}
+
+// depth[x] = -(weighted distance after the down arc 2x), 0 at roots; the
+// largest depth goes to counters[kCntDepthMax].
+template <int B>
+__global__ __launch_bounds__(B) void k_depth_out(int64_t n, const int32_t *__restrict__ parent,
+                                                 const uint64_t *__restrict__ w,
+                                                 const uint64_t *__restrict__ rw1, int64_t rw1_cap,
+                                                 int32_t *depth, int32_t *counters) {
+  if (counters[kCntGOverflow]) return;   // block-uniform: the caller falls back
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t d = 0;
+  if (x < n) {
+    if (!depth_is_root((int32_t)x, parent[x], n)) {
+      const uint64_t c = w[2 * x];
+      const uint32_t rid = (uint32_t)c;
+      const uint32_t dist = rid < rw1_cap ? (uint32_t)(rw1[rid] >> 32) - (uint32_t)(c >> 32) : 0u;
+      d = -(int32_t)dist;
+    }
+    depth[x] = d;
+  }
+  // wave maximum, one atomic per wave
+  for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(&counters[kCntDepthMax], d);
+}
+
+// Fallback after counters[kCntGOverflow] (more trees than the ruling set
+// holds): Wyllie rounds over the same weighted words, then the same output.
+template <int B>
+__global__ __launch_bounds__(B) void k_depth_out_rounds(int64_t n, const int32_t *__restrict__ parent,
+                                                        const uint64_t *__restrict__ w,
+                                                        int32_t *depth, int32_t *counters) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t d = 0;
+  if (x < n) {
+    if (!depth_is_root((int32_t)x, parent[x], n)) d = -(int32_t)(uint32_t)(w[2 * x] >> 32);
+    depth[x] = d;
+  }
+  for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(&counters[kCntDepthMax], d);
+}
+
+size_t depth_ws_bytes(int64_t n, const GlistPlan &p) {
+  return ws_bytes(64, 4) + ws_bytes((size_t)n, 4) + ws_bytes(2 * (size_t)n, 4) +
+         ws_bytes(2 * (size_t)n, 8) + glist_ws_bytes(p);
+}
+
+rst_status run_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *depth,
+                          int64_t *max_depth) {
+  const GlistPlan plan = glist_plan(2 * n, n / 2 + 1, ctx->opt.rank_stride);
+  RST_TRY(ws_reserve(ctx, depth_ws_bytes(n, plan)));
+  int32_t *counters = ws_take<int32_t>(ctx, 64);
+  int32_t *head = ws_take<int32_t>(ctx, n);
+  int32_t *next = ws_take<int32_t>(ctx, 2 * n);
+  uint64_t *w = ws_take<uint64_t>(ctx, 2 * n);
+  GlistBufs gl;
+  glist_take(ctx, plan, gl);
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+  RST_TRY(enqueue_fill(ctx, head, n, -1));
+  RST_SWEEP(ctx, k_depth_link, n, n, parent, head, next);
+  RST_HIP(hipGetLastError());
+  RST_SWEEP(ctx, k_depth_words, n, n, parent, head, next, w, gl.heads[0], plan.hcap, counters);
+  RST_HIP(hipGetLastError());
+  RST_TRY(enqueue_glist_rank(ctx, w, true, gl, counters));
+  RST_SWEEP(ctx, k_depth_out, n, n, parent, w, gl.rw[1], plan.cap[1], depth, counters);
+  RST_HIP(hipGetLastError());
+  RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
+                         hipMemcpyDeviceToHost, ctx->stream));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->host_pinned[kCntGOverflow]) {
+    // rebuild the words (the walks overwrote them) and rank every arc
+    RST_SWEEP(ctx, k_depth_words, n, n, parent, head, next, w, gl.heads[0], plan.hcap, counters);
+    RST_HIP(hipGetLastError());
+    RST_TRY(enqueue_rank_rounds(ctx, 2 * n, w, rank_rounds_for(2 * n), nullptr, nullptr));
+    RST_SWEEP(ctx, k_depth_out_rounds, n, n, parent, w, depth, counters);
+    RST_HIP(hipGetLastError());
+    RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    RST_HIP(hipStreamSynchronize(ctx->stream));
+  }
+  if (max_depth) *max_depth = ctx->host_pinned[kCntDepthMax];
+  return RST_OK;
+}
+
+}  // namespace rst

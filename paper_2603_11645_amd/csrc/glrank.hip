@@ -455,20 +455,26 @@ rst_status enqueue_glist_from_succ(rst_ctx *ctx, int64_t A, const int32_t *succ,
   return RST_OK;
 }
 
-rst_status enqueue_glist_rank(rst_ctx *ctx, int32_t *w1, GlistBufs &g, int32_t *counters) {
+rst_status enqueue_glist_rank(rst_ctx *ctx, void *w1, bool w1_wide, GlistBufs &g,
+                              int32_t *counters) {
   const GlistPlan &p = g.plan;
   // walks, bottom up
   for (int L = 1; L < p.levels; ++L) {
-    void *words = L == 1 ? static_cast<void *>(w1) : static_cast<void *>(g.rw[L - 1]);
+    void *words = L == 1 ? w1 : static_cast<void *>(g.rw[L - 1]);
     // rulers of level L: about (words / stride) + heads
     const int64_t words_bound = L == 1 ? p.A : p.cap[L - 1];
     const int kk = L == 1 ? p.k1 : p.k;
     const unsigned grid = gl_grid(ctx, words_bound / kk + p.hcap);
     if (L == 1) {
       RST_KMARK(ctx, RST_KERNEL_RANK_WALK, 0);
-      hipLaunchKernelGGL(k_gwalk<true>, dim3(grid), dim3(kGlThreads), 0, ctx->stream, L, p.A,
-                         p.k1, p.k, words, g.heads[0], g.heads[1], g.rw[1], p.cap[1], p.hcap,
-                         counters);
+      if (w1_wide)   // 64-bit (successor, weight) words at level 1 as well
+        hipLaunchKernelGGL(k_gwalk<false>, dim3(grid), dim3(kGlThreads), 0, ctx->stream, L, p.A,
+                           p.k1, p.k1, words, g.heads[0], g.heads[1], g.rw[1], p.cap[1], p.hcap,
+                           counters);
+      else
+        hipLaunchKernelGGL(k_gwalk<true>, dim3(grid), dim3(kGlThreads), 0, ctx->stream, L, p.A,
+                           p.k1, p.k, words, g.heads[0], g.heads[1], g.rw[1], p.cap[1], p.hcap,
+                           counters);
       RST_HIP(hipGetLastError());
       RST_KMARK(ctx, RST_KERNEL_RANK_WALK, 1);
     } else {

@@ -173,6 +173,7 @@ enum {
   kCntGDyn = 17,           //   rulers opened by walks that reached the piece cap
   kCntGOverflow = 18,      //   heads or ruler ids beyond capacity (caller ranks otherwise)
   kCntGTopWords = 19,      //   words of the top level (one workgroup)
+  kCntDepthMax = 20,       // largest depth of a forest (rst_tree_depth)
   kCntTotal = 24,          // counters read back after a call (the ones above)
 };
 
@@ -288,7 +289,10 @@ rst_status enqueue_glist_from_slots(rst_ctx *ctx, int64_t slots, int64_t n, cons
 // level-1 words and list heads from a successor array; haspred: A bytes scratch
 rst_status enqueue_glist_from_succ(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *w1,
                                    uint8_t *haspred, GlistBufs &g, int32_t *counters);
-rst_status enqueue_glist_rank(rst_ctx *ctx, int32_t *w1, GlistBufs &g, int32_t *counters);
+// w1: int32 level-1 words (unit weights), or with w1_wide uint64 (successor,
+// weight) words, whose codes become (offset << 32 | ruler)
+rst_status enqueue_glist_rank(rst_ctx *ctx, void *w1, bool w1_wide, GlistBufs &g,
+                              int32_t *counters);
 rst_status enqueue_glist_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
                                 const int32_t *tv, const int32_t *w1, const GlistBufs &g,
                                 const int32_t *cc, const int32_t *comp_root, int32_t *parent,
@@ -304,6 +308,11 @@ rst_status glist_wyllie_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int
 // end-of-list successors (one per vertex, -1 where the vertex roots its tree)
 rst_status enqueue_endsucc(rst_ctx *ctx, int64_t n, const int32_t *head, const int32_t *cc,
                            const int32_t *comp_root, int32_t *endsucc);
+
+// depth.hip: depth of every vertex of the forest given by parent (device),
+// *max_depth (host, nullable) the largest; synchronous
+rst_status run_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *depth,
+                          int64_t *max_depth);
 
 // verify.hip: device check of a rooted spanning forest.  vc[0] += failures,
 // vc[1] = min failing vertex (caller initialises 0 and INT32_MAX); anc0/anc1:
