@@ -10,7 +10,12 @@
  *   RST_GCONN_EULER  connectivity by hooking + pointer jumping that records the
  *                    edge behind every union (Sec. III-B), then Euler-tour
  *                    rooting of the spanning forest (Sec. III-D);
- *   RST_BFS          level-synchronous breadth-first search (Sec. III-A).
+ *   RST_BFS          level-synchronous breadth-first search (Sec. III-A);
+ *   RST_PR_RST       Path-Reversal RST (Sec. III-C): a rooted forest kept
+ *                    through hooking rounds that alternate max and min
+ *                    representatives, each graft re-rooting the grafted tree
+ *                    by reversing the path marked through its vertices'
+ *                    ancestors at power-of-two distances.
  *
  * Conventions shared by every call:
  *   - Every array argument is a DEVICE pointer unless its comment says host.
@@ -51,7 +56,7 @@ typedef enum {
   RST_E_UNSUPPORTED = -6   /* request not supported by this build / device              */
 } rst_status;
 
-typedef enum { RST_GCONN_EULER = 0, RST_BFS = 1, RST_AUTO = 2 } rst_method;
+typedef enum { RST_GCONN_EULER = 0, RST_BFS = 1, RST_AUTO = 2, RST_PR_RST = 3 } rst_method;
 
 /* Symmetric CSR of an undirected graph (Sec. I). */
 typedef struct {
@@ -89,7 +94,7 @@ enum {
 typedef struct {
   float ms_total;
   float ms_stage[8];
-  float ms_kernel[8];     /* single kernels, see RST_KERNEL_*                  */
+  float ms_kernel[10];    /* single kernels, see RST_KERNEL_*                  */
   int64_t hook_rounds;    /* levels of the binary tree over vertex tiles + 1   */
   int64_t rank_rounds;    /* pointer-jumping rounds on the contracted list     */
   int64_t rank_exits;     /* length of the contracted list (segment exits)     */
@@ -123,8 +128,14 @@ enum {
   RST_KERNEL_CROSS = 1,       /* all cross-tile hooking levels together         */
   RST_KERNEL_RANK_TILE = 2,   /* LDS ruling-set ranking over arc tiles (+succ)  */
   RST_KERNEL_LINK = 3,        /* per-vertex out-arc lists                       */
-  RST_KERNEL_RANK_WALK = 4    /* sparse ruling set in global memory: the walks  *
+  RST_KERNEL_RANK_WALK = 4,   /* sparse ruling set in global memory: the walks  *
                                * of the first level (tours without id locality) */
+  RST_KERNEL_LATE_HOOKS = 5,  /* global-memory hooking of cross edges that the  *
+                               * LDS merges did not take, and heavy vertices     */
+  RST_KERNEL_SETTLE = 6,      /* one-root pass: roots, end-of-list successors    */
+  RST_KERNEL_PARENT = 7,      /* parent rule from the ranks (either ranking)     */
+  RST_KERNEL_RANK_WORDS = 8   /* sparse ruling set: successors of every arc from *
+                               * the forest slots, list heads                    */
 };
 
 /* Tunables and switches for rst_set_option. */
@@ -174,7 +185,8 @@ rst_status rst_set_option(rst_ctx *ctx, rst_option opt, int64_t value);
 rst_status rst_get_option(const rst_ctx *ctx, rst_option opt, int64_t *value);
 
 /* Rooted spanning tree of the graph (Sec. I) by `method` (RST_AUTO runs the
- * selector on this one graph).  parent: device int32 [n], written completely.
+ * selector on this one graph; RST_PR_RST reports its hooking iterations in
+ * stats->hook_rounds).  parent: device int32 [n], written completely.
  * If the graph is disconnected the call returns RST_E_DISCONNECTED and parent
  * is a rooted spanning forest: root's component is rooted at root, every other
  * component at its minimum vertex id.  stats may be NULL. */

@@ -29,8 +29,9 @@ RST_E_UNSUPPORTED = -6
 GCONN_EULER = 0
 BFS = 1
 AUTO = 2
+PR_RST = 3
 _METHODS = {"gconn": GCONN_EULER, "gconn_euler": GCONN_EULER, "bfs": BFS, "auto": AUTO,
-            GCONN_EULER: GCONN_EULER, BFS: BFS, AUTO: AUTO}
+            "pr_rst": PR_RST, GCONN_EULER: GCONN_EULER, BFS: BFS, AUTO: AUTO, PR_RST: PR_RST}
 
 OPT_VALIDATE = 0
 OPT_BFS_LEVELS_PER_SYNC = 1
@@ -80,7 +81,8 @@ class rst_batch(ctypes.Structure):
                 ("arc_off", ctypes.c_void_p), ("roots", ctypes.c_void_p)]
 
 
-KERNELS = ["hook_tile", "cross", "rank_tile", "link", "rank_walk", "k5", "k6", "k7"]
+KERNELS = ["hook_tile", "cross", "rank_tile", "link", "rank_walk", "late_hooks", "settle",
+           "parent", "rank_words", "k9"]
 
 
 class rst_tune_result(ctypes.Structure):
@@ -97,7 +99,7 @@ class rst_tune_result(ctypes.Structure):
 
 class rst_stats(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_float), ("ms_stage", ctypes.c_float * 8),
-                ("ms_kernel", ctypes.c_float * 8),
+                ("ms_kernel", ctypes.c_float * 10),
                 ("hook_rounds", ctypes.c_int64), ("rank_rounds", ctypes.c_int64),
                 ("rank_exits", ctypes.c_int64), ("cross_edges", ctypes.c_int64),
                 ("bfs_levels", ctypes.c_int64), ("components", ctypes.c_int64),
@@ -106,7 +108,7 @@ class rst_stats(ctypes.Structure):
     def as_dict(self) -> dict:
         return {"ms_total": self.ms_total,
                 "ms_stage": {STAGES[i]: self.ms_stage[i] for i in range(8)},
-                "ms_kernel": {KERNELS[i]: self.ms_kernel[i] for i in range(5)},
+                "ms_kernel": {KERNELS[i]: self.ms_kernel[i] for i in range(9)},
                 "hook_rounds": self.hook_rounds, "rank_rounds": self.rank_rounds,
                 "rank_exits": self.rank_exits, "cross_edges": self.cross_edges,
                 "bfs_levels": self.bfs_levels, "components": self.components,

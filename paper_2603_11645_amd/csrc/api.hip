@@ -535,8 +535,32 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
   if (!ctx || !parent) return RST_E_INVAL;
   RST_TRY(check_csr(g));
   if (root < 0 || root >= g->n) return RST_E_INVAL;
-  if (method != RST_GCONN_EULER && method != RST_BFS && method != RST_AUTO) return RST_E_INVAL;
+  if (method != RST_GCONN_EULER && method != RST_BFS && method != RST_AUTO &&
+      method != RST_PR_RST)
+    return RST_E_INVAL;
   RST_HIP(hipSetDevice(ctx->device));
+  if (method == RST_PR_RST) {
+    if (stats) std::memset(stats, 0, sizeof(*stats));
+    if (ctx->opt.validate) {
+      RST_TRY(ws_reserve(ctx, ws_bytes(64, 4)));
+      int32_t *counters = ws_take<int32_t>(ctx, 64);
+      RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+      RST_TRY(run_validation(ctx, g, counters));
+    }
+    RST_HIP(hipEventRecord(ctx->ev[0], ctx->stream));
+    int64_t iters = 0, comps = 0;
+    RST_TRY(run_pr_rst(ctx, g, root, parent, &iters, &comps));
+    if (stats) {
+      RST_HIP(hipEventRecord(ctx->ev[1], ctx->stream));
+      RST_HIP(hipEventSynchronize(ctx->ev[1]));
+      float ms = 0.f;
+      if (event_ms(ctx->ev[0], ctx->ev[1], &ms)) stats->ms_total = ms;
+      stats->hook_rounds = iters;
+      stats->components = comps;
+      stats->method_used = RST_PR_RST;
+    }
+    return comps > 1 ? RST_E_DISCONNECTED : RST_OK;
+  }
   if (method == RST_AUTO) {
     // the selector's choice for this one graph (GConn+Euler without a selector)
     method = RST_GCONN_EULER;

@@ -1121,8 +1121,10 @@ rst_status enqueue_endsucc(rst_ctx *ctx, int64_t n, const int32_t *head, const i
 rst_status enqueue_settle(rst_ctx *ctx, int64_t n, const int32_t *roots, const int32_t *cc,
                           const int32_t *head, int32_t *endsucc, int32_t *parent,
                           int32_t *counters) {
+  RST_KMARK(ctx, RST_KERNEL_SETTLE, 0);
   RST_SWEEP(ctx, k_settle, n, n, roots, cc, head, endsucc, parent, counters);
   RST_HIP(hipGetLastError());
+  RST_KMARK(ctx, RST_KERNEL_SETTLE, 1);
   return RST_OK;
 }
 
@@ -1268,9 +1270,11 @@ rst_status enqueue_expand_parent(rst_ctx *ctx, int64_t slots, int64_t n, const i
                                  int32_t *host_out) {
   const int64_t items = (cc && n > slots) ? n : slots;
   if (cc) host_out = nullptr;   // the component count is only final after this pass
+  RST_KMARK(ctx, RST_KERNEL_PARENT, 0);
   RST_SWEEP(ctx, k_expand_parent, items, slots, n, tu, tv, rank, xid, tile_base, crank, cc,
             comp_root, parent, counters, host_out);
   RST_HIP(hipGetLastError());
+  RST_KMARK(ctx, RST_KERNEL_PARENT, 1);
   return RST_OK;
 }
 

@@ -437,9 +437,11 @@ rst_status enqueue_glist_from_slots(rst_ctx *ctx, int64_t slots, int64_t n, cons
                                     const int32_t *endsucc, const int32_t *head, int32_t *w1,
                                     GlistBufs &g, int32_t *counters) {
   const int64_t items = slots > n ? slots : n;
+  RST_KMARK(ctx, RST_KERNEL_RANK_WORDS, 0);
   RST_SWEEP(ctx, k_gslot_words, items, slots, n, tu, tv, next, endsucc, head, w1, g.heads[0],
             g.plan.hcap, counters);
   RST_HIP(hipGetLastError());
+  RST_KMARK(ctx, RST_KERNEL_RANK_WORDS, 1);
   return RST_OK;
 }
 
@@ -502,9 +504,11 @@ rst_status enqueue_glist_parent(rst_ctx *ctx, int64_t slots, int64_t n, const in
                                 int32_t *counters, int32_t *host_out) {
   const int64_t items = (cc && n > slots) ? n : slots;
   if (cc) host_out = nullptr;   // the component count is only final after this pass
+  RST_KMARK(ctx, RST_KERNEL_PARENT, 0);
   RST_SWEEP(ctx, k_gparent, items, slots, n, tu, tv, w1, g.rw[1], g.plan.cap[1], cc, comp_root,
             parent, counters, host_out);
   RST_HIP(hipGetLastError());
+  RST_KMARK(ctx, RST_KERNEL_PARENT, 1);
   return RST_OK;
 }
 

@@ -1081,10 +1081,12 @@ static rst_status launch_late_hooks(rst_ctx *ctx, unsigned tiles, int levels,
   const unsigned grid = (unsigned)(ctx->num_cus * 2);
   unsigned slices = (grid + tiles - 1) / tiles;
   slices = slices < 1 ? 1 : (slices > 64 ? 64 : slices);
+  RST_KMARK(ctx, RST_KERNEL_LATE_HOOKS, 0);
   hipLaunchKernelGGL(k_late_hooks<OffT>, dim3(grid), dim3(kTileThreads), 0, ctx->stream, region_of,
                      cross, tile_cross, levels == 0 ? 0 : (int)tiles, (int)slices, off, cols, chunks,
                      chunk_cap, f.cc, f.tu, f.tv, f.counters, f.head, f.next);
   RST_HIP(hipGetLastError());
+  RST_KMARK(ctx, RST_KERNEL_LATE_HOOKS, 1);
   return RST_OK;
 }
 

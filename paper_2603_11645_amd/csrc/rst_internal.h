@@ -79,7 +79,7 @@ struct rst_ctx {
   int num_cus = 256;
   rst::Workspace ws;
   rst::Options opt;
-  hipEvent_t ev[32] = {};   // 0-6 stages, 8-23 kernel pairs, 24-27 batch marks
+  hipEvent_t ev[32] = {};   // 0-6 stages, 8-27 kernel pairs, 28-31 batch marks
   int32_t *host_pinned = nullptr;   // small pinned host buffer for flag readback
   int32_t *host_pinned_dev = nullptr;   // its device address (null: read back by copies only)
   bool timing = false;              // record per-kernel events (a stats struct was passed)
@@ -102,7 +102,7 @@ namespace rst {
   } while (0)
 
 // per-kernel event pairs in ctx->ev[8..15], recorded only while ctx->timing is set
-enum { kEvKernelBase = 8, kNumKernelTimes = 8, kEvBatchBase = 24, kNumEvents = 32 };
+enum { kEvKernelBase = 8, kNumKernelTimes = 10, kEvBatchBase = 28, kNumEvents = 32 };
 #define RST_KMARK(ctx, kernel, end)                                                          \
   do {                                                                                        \
     if ((ctx)->timing) {                                                                      \
@@ -174,6 +174,7 @@ enum {
   kCntGOverflow = 18,      //   heads or ruler ids beyond capacity (caller ranks otherwise)
   kCntGTopWords = 19,      //   words of the top level (one workgroup)
   kCntDepthMax = 20,       // largest depth of a forest (rst_tree_depth)
+  kCntPrHooks = 21,        // PR-RST: some edge joined two trees in this iteration
   kCntTotal = 24,          // counters read back after a call (the ones above)
 };
 
@@ -313,6 +314,10 @@ rst_status enqueue_endsucc(rst_ctx *ctx, int64_t n, const int32_t *head, const i
 // *max_depth (host, nullable) the largest; synchronous
 rst_status run_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *depth,
                           int64_t *max_depth);
+
+// prrst.hip: Path-Reversal RST of g rooted at root (synchronous; host loop)
+rst_status run_pr_rst(rst_ctx *ctx, const rst_csr *g, int32_t root, int32_t *parent,
+                      int64_t *iterations, int64_t *components);
 
 // verify.hip: device check of a rooted spanning forest.  vc[0] += failures,
 // vc[1] = min failing vertex (caller initialises 0 and INT32_MAX); anc0/anc1:
