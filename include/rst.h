@@ -249,7 +249,9 @@ rst_status rst_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_
  * disconnected gets its other components rooted at their minimum ids.
  * method_out: device uint8 [G], nullable, receives the method used per graph.
  * The number of kernel launches does not depend on G.  RST_E_INVAL if the
- * offset tables disagree with the CSR or a root lies outside its graph.
+ * offset tables disagree with the CSR or a root lies outside its graph; with
+ * RST_OPT_VALIDATE, RST_E_RANGE if an arc's neighbour lies outside the arc's
+ * graph.
  * stats may be NULL. */
 rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
                                      const uint8_t *method, int32_t *parent,
@@ -326,12 +328,14 @@ typedef struct {
 
 /* Autotune the context's tunables for `method` on graph g and root: coordinate
  * descent over the method's knobs (GConn+Euler: sweep block size, hooking
- * heavy degree, ranking words per thread; BFS: levels per sync, grid, heavy
- * degree), each candidate timed as the median of `reps` calls (1..101) and its
- * output checked with rst_verify.  The best setting is applied to the context
+ * heavy degree, ranking words per thread, sparse ruling-set stride; BFS:
+ * levels per sync, grid, heavy degree), each candidate timed as the median of
+ * `reps` calls (1..101) and rejected unless every call returns the status of
+ * the starting setting and its output passes the rst_verify checks against
+ * component labels computed once, before the search, with that setting.  The best setting is applied to the context
  * and recorded in its tuning cache under (GPU architecture, method,
- * floor(log2 n), floor(log2 nnz/n)).  Allocates a device buffer of n int32 for
- * the duration of the call.  result: host, nullable. */
+ * floor(log2 n), floor(log2 nnz/n)).  Allocates a device buffer of 2n int32
+ * for the duration of the call.  result: host, nullable. */
 rst_status rst_autotune(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_method method,
                         int32_t reps, rst_tune_result *result);
 

@@ -927,6 +927,7 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(run_validation(ctx, g, counters));
   RST_TRY(enqueue_batch_check(ctx, g, b, counters));
+  if (ctx->opt.validate) RST_TRY(enqueue_batch_arcs_check(ctx, g, b, counters));
   RST_TRY(mark(ctx, stats, kEvBatchBase));
   // per-graph method: given, chosen by the selector, or GConn+Euler for all
   if (method) {
@@ -940,6 +941,7 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
   RST_TRY(enqueue_count_methods(ctx, b, m, counters));
   RST_TRY(read_counters(ctx, counters));
   if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
+  if (ctx->host_pinned[kCntBatchArcErr]) return RST_E_RANGE;
   const int32_t nbfs = ctx->host_pinned[kCntBatchBfs];
   const int64_t bfs_vertices = ctx->host_pinned[kCntBatchBfsVtx];
   if (nbfs > 0) RST_TRY(enqueue_graph_mask(ctx, b, m, vmask));

@@ -41,6 +41,34 @@ __global__ __launch_bounds__(kBlock) void k_batch_check(int32_t G, int64_t n, in
   if (bad) atomicOr(&counters[kCntRangeErr], 1);
 }
 
+// Validation of a batch's arcs: every neighbour id of graph g lies in
+// [vtx_off[g], vtx_off[g+1]) (the graph of an arc is found by binary search
+// in arc_off); otherwise graphs would share components.
+__global__ __launch_bounds__(kBlock) void k_batch_arcs_check(int32_t G, int64_t nnz,
+                                                             const int64_t *__restrict__ vtx_off,
+                                                             const int64_t *__restrict__ arc_off,
+                                                             const int32_t *__restrict__ cols,
+                                                             int32_t *counters) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nnz) return;
+  int lo = 0, hi = G;   // largest g in [0, G) with arc_off[g] <= a
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (arc_off[mid] <= a) lo = mid; else hi = mid;
+  }
+  const int32_t c = cols[a];
+  if (c < vtx_off[lo] || c >= vtx_off[lo + 1]) atomicOr(&counters[kCntBatchArcErr], 1);
+}
+
+rst_status enqueue_batch_arcs_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                                    int32_t *counters) {
+  if (g->nnz <= 0) return RST_OK;
+  hipLaunchKernelGGL(k_batch_arcs_check, dim3(grid_for(g->nnz, kBlock)), dim3(kBlock), 0,
+                     ctx->stream, b->num_graphs, g->nnz, b->vtx_off, b->arc_off, g->cols, counters);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
 // counters[kCntBatchBfs] = graphs with a nonzero method (BFS),
 // counters[kCntBatchBfsVtx] = their vertices
 __global__ __launch_bounds__(kBlock) void k_count_methods(int32_t G,

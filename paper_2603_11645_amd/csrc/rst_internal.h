@@ -59,6 +59,8 @@ rst_status enqueue_graph_mask(rst_ctx *ctx, const rst_batch *b, const uint8_t *m
                               uint8_t *vmask);
 rst_status enqueue_batch_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
                                int32_t *counters);
+rst_status enqueue_batch_arcs_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                                    int32_t *counters);
 rst_status enqueue_count_methods(rst_ctx *ctx, const rst_batch *b, const uint8_t *m,
                                  int32_t *counters);
 rst_status enqueue_copy_u8(rst_ctx *ctx, const uint8_t *src, uint8_t *dst, int64_t count);
@@ -175,6 +177,7 @@ enum {
   kCntGTopWords = 19,      //   words of the top level (one workgroup)
   kCntDepthMax = 20,       // largest depth of a forest (rst_tree_depth)
   kCntPrHooks = 21,        // PR-RST: some edge joined two trees in this iteration
+  kCntBatchArcErr = 22,    // validation: an arc of a batch leaves its graph
   kCntTotal = 24,          // counters read back after a call (the ones above)
 };
 
@@ -363,6 +366,8 @@ rst_status enqueue_graph_mask(rst_ctx *ctx, const rst_batch *b, const uint8_t *m
                               uint8_t *vmask);
 rst_status enqueue_batch_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
                                int32_t *counters);
+rst_status enqueue_batch_arcs_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                                    int32_t *counters);
 rst_status enqueue_count_methods(rst_ctx *ctx, const rst_batch *b, const uint8_t *m,
                                  int32_t *counters);
 rst_status enqueue_copy_u8(rst_ctx *ctx, const uint8_t *src, uint8_t *dst, int64_t count);

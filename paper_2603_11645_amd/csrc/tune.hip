@@ -4,8 +4,9 @@
 // The search is coordinate descent from the context's current setting: for
 // each knob of the method, every candidate value is timed (median of `reps`
 // runs of the whole call, HIP events on the context stream, after one warm-up
-// run) and its output is checked on the device (rst_verify); a candidate whose
-// output fails is rejected.  The best value is kept before the next knob.
+// run) and its output is checked on the device against component labels
+// computed once before the search; a candidate whose output fails, or whose
+// calls return another status than the starting setting's, is rejected.  The best value is kept before the next knob.
 // Entries are keyed by (GPU architecture, method, floor(log2 n),
 // floor(log2 average degree)) so that one tuning serves graphs of a similar
 // size and density.
@@ -67,20 +68,47 @@ static std::vector<Knob> knobs_for(rst_method method) {
             {RST_OPT_BFS_HEAVY_DEGREE, {256, 1024, 4096, 16384}}};
   return {{RST_OPT_SWEEP_BLOCK, {64, 128, 256, 512, 1024}},
           {RST_OPT_HEAVY_DEGREE, {256, 1024, 4096, 16384}},
-          {RST_OPT_RANK_ELEMS_PER_THREAD, {1, 2, 4, 8}}};
+          {RST_OPT_RANK_ELEMS_PER_THREAD, {1, 2, 4, 8}},
+          {RST_OPT_RANK_STRIDE, {4, 8, 16, 32, 64}}};
 }
 
-// Median time of `reps` calls (after one warm-up call); *ok = output verified.
+// Device check of a candidate's output against component labels computed
+// once, before the search, under the settings the search started from: a
+// knob-dependent fault in the library's own hooking cannot make the labels
+// and the parent array wrong in the same way.  *bad = failed checks.
+static rst_status verify_against(rst_ctx *ctx, const rst_csr *g, int32_t root,
+                                 const int32_t *ref_label, const int32_t *parent, int64_t *bad) {
+  const int64_t n = g->n;
+  RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + 2 * ws_bytes(n, 4)));
+  int32_t *vc = ws_take<int32_t>(ctx, 64);
+  int32_t *anc0 = ws_take<int32_t>(ctx, n);
+  int32_t *anc1 = ws_take<int32_t>(ctx, n);
+  RST_TRY(enqueue_fill(ctx, vc, 1, 0));
+  RST_TRY(enqueue_fill(ctx, vc + 1, 1, 0x7fffffff));
+  RST_TRY(enqueue_verify(ctx, g, root, ref_label, parent, anc0, anc1, vc));
+  RST_HIP(hipMemcpyAsync(ctx->host_pinned + 40, vc, 2 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  *bad = ctx->host_pinned[40];
+  return RST_OK;
+}
+
+// Median time of `reps` calls (after one warm-up call); *ok = every call
+// returned `want` (the status of the starting setting) and the last output
+// passes the check against the reference labels.
 static rst_status time_config(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_method method,
-                              int32_t reps, int32_t *parent, hipEvent_t e0, hipEvent_t e1,
-                              float *ms, bool *ok) {
+                              int32_t reps, int32_t *parent, const int32_t *ref_label,
+                              rst_status want, hipEvent_t e0, hipEvent_t e1, float *ms, bool *ok) {
+  bool same = true;
   rst_status s = rst_spanning_tree(ctx, g, root, method, parent, nullptr);
   if (s != RST_OK && s != RST_E_DISCONNECTED) return s;
+  same = same && s == want;
   std::vector<float> t;
   for (int r = 0; r < reps; ++r) {
     RST_HIP(hipEventRecord(e0, ctx->stream));
     s = rst_spanning_tree(ctx, g, root, method, parent, nullptr);
     if (s != RST_OK && s != RST_E_DISCONNECTED) return s;
+    same = same && s == want;
     RST_HIP(hipEventRecord(e1, ctx->stream));
     RST_HIP(hipEventSynchronize(e1));
     float x = 0.f;
@@ -89,9 +117,9 @@ static rst_status time_config(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_
   }
   std::sort(t.begin(), t.end());
   *ms = t[t.size() / 2];
-  int64_t bad = 0, first = 0;
-  RST_TRY(rst_verify(ctx, g, root, parent, &bad, &first));
-  *ok = bad == 0;
+  int64_t bad = 0;
+  RST_TRY(verify_against(ctx, g, root, ref_label, parent, &bad));
+  *ok = same && bad == 0;
   return RST_OK;
 }
 
@@ -196,11 +224,21 @@ rst_status rst_autotune(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_method
   if (method != RST_GCONN_EULER && method != RST_BFS) return RST_E_INVAL;
   if (g->n < 1 || root < 0 || root >= g->n) return RST_E_INVAL;
   RST_HIP(hipSetDevice(ctx->device));
+  // the output buffer and the reference labels (component minima, computed
+  // once under the starting settings)
   int32_t *parent = nullptr;
-  if (hipMalloc(reinterpret_cast<void **>(&parent), (size_t)g->n * sizeof(int32_t)) != hipSuccess) {
+  if (hipMalloc(reinterpret_cast<void **>(&parent), 2 * (size_t)g->n * sizeof(int32_t)) !=
+      hipSuccess) {
     (void)hipGetLastError();
     return RST_E_NOMEM;
   }
+  int32_t *ref_label = parent + g->n;
+  int64_t ref_comps = 0;
+  {
+    const rst_status ls = rst_components(ctx, g, ref_label, &ref_comps);
+    if (ls != RST_OK) { (void)hipFree(parent); return ls; }
+  }
+  const rst_status want = ref_comps > 1 ? RST_E_DISCONNECTED : RST_OK;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   rst_status status = RST_OK;
   float ms_default = 0.f, ms_best = 0.f;
@@ -212,7 +250,8 @@ rst_status rst_autotune(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_method
       break;
     }
     bool ok = false;
-    status = time_config(ctx, g, root, method, reps, parent, e0, e1, &ms_default, &ok);
+    status = time_config(ctx, g, root, method, reps, parent, ref_label, want, e0, e1, &ms_default,
+                         &ok);
     if (status != RST_OK) break;
     if (!ok) { status = RST_E_DEVICE; break; }   // the current setting itself fails
     ms_best = ms_default;
@@ -223,7 +262,8 @@ rst_status rst_autotune(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_method
         if (v == best_v) continue;
         if (rst_set_option(ctx, k.opt, v) != RST_OK) continue;
         float ms = 0.f;
-        status = time_config(ctx, g, root, method, reps, parent, e0, e1, &ms, &ok);
+        status = time_config(ctx, g, root, method, reps, parent, ref_label, want, e0, e1, &ms,
+                             &ok);
         if (status != RST_OK) break;
         ++candidates;
         if (!ok) { ++rejected; continue; }

@@ -183,3 +183,23 @@ def test_selector_drives_batch_choice(ctx, rst):
     bad[-4:] = np.array([np.nan], np.float32).tobytes()
     with pytest.raises(rst.RstError):
         ctx.selector_load(bytes(bad))
+
+
+def test_batch_cross_graph_arc_rejected(ctx, rst):
+    """With validation on, an arc whose neighbour lies in another graph of the
+    batch is reported (RST_E_RANGE); the same batch without it passes."""
+    a, b2 = I.path(50), I.path(60)
+    b = I.pack([a, b2])
+    g = b.graph
+    cols = g.cols.copy()
+    cols[g.offsets[10]] = 55          # vertex 10 of graph 0 -> a vertex of graph 1
+    off, _, vo, ao, ro = upload_batch(b)
+    ctx.set_option(rst.OPT_VALIDATE, 1)
+    try:
+        with pytest.raises(rst.RstError) as ei:
+            ctx.spanning_forest_batch(off, dev(cols), vo, ao, ro)
+        assert ei.value.code == rst.RST_E_RANGE
+        par, _ = ctx.spanning_forest_batch(off, dev(g.cols), vo, ao, ro)
+        check_forest(b, par.cpu().numpy())
+    finally:
+        ctx.set_option(rst.OPT_VALIDATE, 0)
