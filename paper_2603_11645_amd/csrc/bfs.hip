@@ -33,18 +33,32 @@ __global__ void k_bfs_reset(int64_t n, int32_t *level, int32_t *parent, int32_t 
   if (v < kBfsCntWords) cnt[v] = 0;
 }
 
+// Arcs of a level's light frontier, counted exactly up to kBsArcsCount and
+// left above it once passed (adds stop there, so the count cannot overflow):
+// a step knows before it starts whether the level fits the narrow mode.
+constexpr int kBsArcsCount = 4096;   // equals kBsArcs below
+
 template <class OffT>
 __device__ __forceinline__ void bfs_enqueue(bool win, int32_t w, const OffT *off, int heavy_deg,
                                             int32_t *qout, int32_t *hout, int32_t *cout,
-                                            int64_t heavy_cap, int32_t *counters) {
+                                            int32_t *arcs, int64_t heavy_cap, int32_t *counters) {
   bool heavy = false;
-  if (win) heavy = (int64_t)(off[w + 1] - off[w]) > heavy_deg;
+  int64_t deg = 0;
+  if (win) {
+    deg = (int64_t)(off[w + 1] - off[w]);
+    heavy = deg > heavy_deg;
+  }
   const bool light = win && !heavy;
   const int sl = wave_append(light, &cout[0]);
   if (light) qout[sl] = w;
   const int sh = wave_append(win && heavy, &cout[1]);
   if (win && heavy && sh < heavy_cap) hout[sh] = w;
   wave_count(win, &counters[kCntBfsReached]);
+  // wave sum of the light degrees (each clamped), one add per wave
+  int d = light ? (int)(deg > kBsArcsCount ? kBsArcsCount + 1 : deg) : 0;
+  for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+  if ((threadIdx.x & 63) == 0 && d > 0 && *reinterpret_cast<volatile int32_t *>(arcs) <= kBsArcsCount)
+    atomicAdd(arcs, d > kBsArcsCount ? kBsArcsCount + 1 : d);
 }
 
 template <class OffT>
@@ -66,7 +80,8 @@ __global__ __launch_bounds__(kBlock) void k_bfs_seed(const int32_t *__restrict__
       if (parent) parent[r] = r;
     }
   }
-  bfs_enqueue<OffT>(win, r, off, heavy_deg, q0, h0, cnt0, heavy_cap, counters);
+  bfs_enqueue<OffT>(win, r, off, heavy_deg, q0, h0, cnt0, cnt0 + kBfsArcsWord, heavy_cap,
+                    counters);
 }
 
 template <class OffT>
@@ -84,7 +99,8 @@ __global__ __launch_bounds__(kBlock) void k_bfs_seed_unreached(int64_t n, const 
     parent[v] = (int32_t)v;
     win = true;
   }
-  bfs_enqueue<OffT>(win, (int32_t)v, off, heavy_deg, q0, h0, cnt0, heavy_cap, counters);
+  bfs_enqueue<OffT>(win, (int32_t)v, off, heavy_deg, q0, h0, cnt0, cnt0 + kBfsArcsWord,
+                    heavy_cap, counters);
 }
 
 // ---------------------------------------------------------------------------
@@ -112,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_seed_unreached(int64_t n, const 
 // ---------------------------------------------------------------------------
 constexpr int kBfsThreads = 1024;
 constexpr int kBsMax = 2048;           // frontier vertices held in LDS (narrow mode)
-constexpr int kBsArcs = 4096;          // arcs one narrow level may expand
+constexpr int kBsArcs = kBsArcsCount;  // arcs one narrow level may expand
 constexpr int kBsHash = 8192;          // deduplication slots, > 2 * kBsArcs: never full
 constexpr int kBsBudget = 1 << 18;     // narrow levels per launch
 static_assert(kBsHash >= 2 * kBsArcs && kBsMax == 2 * kBfsThreads, "narrow-mode sizes");
@@ -154,12 +170,13 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_step(
   const bool force_wide = state[2 + par] != 0;
   int nl = cnt[2 * (L % 3)];
   int nh = cnt[2 * (L % 3) + 1];
+  const int arcs_l = cnt[kBfsArcsWord + L % 3];
   if (nh > heavy_cap) nh = (int)heavy_cap;
   if (L >= level_stop || nl + nh == 0) {
     if (blockIdx.x == 0 && t == 0) { state[par ^ 1] = L; state[2 + (par ^ 1)] = 0; }
     return;
   }
-  if (nh == 0 && nl <= kBsMax && !force_wide) {
+  if (nh == 0 && nl <= kBsMax && arcs_l <= kBsArcs && !force_wide) {
     // ------------------------------------------------------------ narrow
     if (blockIdx.x != 0) return;
     const int32_t *qin = (L & 1) ? q1 : q0;
@@ -253,10 +270,18 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_step(
       const int m = nf < kBsMax ? nf : kBsMax;
       for (int i = t; i < m; i += kBfsThreads) q[i] = sh.nar.v[c][i];
     }
+    // arcs of that frontier (only needed when it fits LDS)
+    int ad = 0;
+    if (nf <= kBsMax)
+      for (int i = t; i < nf; i += kBfsThreads) ad += sh.nar.d[c][i];
+    int atot;
+    (void)block_excl_scan<kBfsThreads>(ad, sh.wave, &atot);
     if (t == 0) {
       cnt[2 * (L % 3)] = nf;              // light count (heavy count already there)
+      cnt[kBfsArcsWord + L % 3] = nf <= kBsMax ? atot : kBsArcs + 1;
       cnt[2 * ((L + 1) % 3)] = 0;         // the next step appends here
       cnt[2 * ((L + 1) % 3) + 1] = 0;
+      cnt[kBfsArcsWord + (L + 1) % 3] = 0;
       state[par ^ 1] = L;
       state[2 + (par ^ 1)] = wide_next ? 1 : 0;
     }
@@ -269,7 +294,9 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_step(
   int32_t *qout = (L & 1) ? q0 : q1;
   int32_t *hout = (L & 1) ? h0 : h1;
   int32_t *cout = cnt + 2 * nxt;
+  int32_t *aout = cnt + kBfsArcsWord + nxt;
   if (blockIdx.x == 0 && t < 2) cnt[2 * clr + t] = 0;
+  if (blockIdx.x == 0 && t == 2) cnt[kBfsArcsWord + clr] = 0;
   if (blockIdx.x == 0 && t == 0) {
     counters[kCntBfsLast] = L;
     state[par ^ 1] = L + 1;
@@ -309,7 +336,7 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_step(
         win = true;
         if (parent) parent[w] = src;
       }
-      bfs_enqueue<OffT>(win, w, off, heavy_deg, qout, hout, cout, heavy_cap, counters);
+      bfs_enqueue<OffT>(win, w, off, heavy_deg, qout, hout, cout, aout, heavy_cap, counters);
     }
     __syncthreads();
   }
@@ -326,7 +353,7 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_step(
         win = true;
         if (parent) parent[w] = u;
       }
-      bfs_enqueue<OffT>(win, w, off, heavy_deg, qout, hout, cout, heavy_cap, counters);
+      bfs_enqueue<OffT>(win, w, off, heavy_deg, qout, hout, cout, aout, heavy_cap, counters);
     }
   }
 }
@@ -392,6 +419,23 @@ static rst_status launch_step(rst_ctx *ctx, const rst_csr *g, int par, unsigned 
                      b.h[1], b.cnt, b.cnt + kBfsStateWord, b.heavy_cap, counters,
                      ctx->opt.bfs_heavy_degree, level_stop);
   RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
+rst_status bfs_enqueue_steps(rst_ctx *ctx, const rst_csr *g, int32_t *level, int32_t *parent,
+                             BfsBufs &b, int32_t *counters, int64_t steps, int64_t max_levels) {
+  const unsigned grid = ctx->opt.bfs_grid > 0 ? (unsigned)ctx->opt.bfs_grid
+                                              : (unsigned)ctx->num_cus;
+  const int32_t level_stop = max_levels >= 0 && max_levels < 0x7fffffff ? (int32_t)max_levels
+                                                                         : 0x7fffffff;
+  steps += steps & 1;   // an even count leaves the level in state[0]
+  for (int64_t k = 0; k < steps; ++k) {
+    const int par = (int)(k & 1);
+    if (g->offset_bytes == 4)
+      RST_TRY(launch_step<int32_t>(ctx, g, par, grid, level, parent, b, counters, level_stop));
+    else
+      RST_TRY(launch_step<int64_t>(ctx, g, par, grid, level, parent, b, counters, level_stop));
+  }
   return RST_OK;
 }
 

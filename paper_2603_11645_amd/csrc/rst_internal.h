@@ -341,6 +341,7 @@ struct BfsBufs {
   int64_t heavy_cap;
 };
 constexpr int kBfsStateWord = 8;    // cnt[8..11]: level by launch parity, "wide next" by parity
+constexpr int kBfsArcsWord = 12;    // cnt[12..14]: arcs of each rotating frontier slot
 constexpr int kBfsCntWords = 16;
 size_t bfs_heavy_capacity(const rst_ctx *ctx, int64_t n, int64_t nnz);
 // level[] = -1 (and parent[] = -1 unless parent is NULL), counts zeroed
@@ -357,6 +358,11 @@ rst_status bfs_seed_unreached(rst_ctx *ctx, const rst_csr *g, const int32_t *cc,
                               const uint8_t *vsel = nullptr);
 // run levels until the frontier is empty; *levels_out = deepest level reached
 // parent may be NULL (levels only); max_levels >= 0 caps the search
+// enqueue `steps` level steps (rounded up to even) with no host
+// synchronisation; every step expands at least one level until the search
+// is done or max_levels is reached, so `steps` >= levels suffices
+rst_status bfs_enqueue_steps(rst_ctx *ctx, const rst_csr *g, int32_t *level, int32_t *parent,
+                             BfsBufs &b, int32_t *counters, int64_t steps, int64_t max_levels);
 rst_status bfs_run_levels(rst_ctx *ctx, const rst_csr *g, int32_t *level, int32_t *parent,
                           BfsBufs &b, int32_t *counters, int64_t *levels_out,
                           int64_t max_levels = -1);

@@ -279,8 +279,10 @@ rst_status enqueue_features(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, 
     RST_HIP(hipGetLastError());
     RST_TRY(bfs_reset(ctx, g->n, level, nullptr, bb));
     RST_TRY(bfs_seed_roots(ctx, g, src, G, level, nullptr, bb, counters, nullptr));
-    int64_t lv = 0;
-    RST_TRY(bfs_run_levels(ctx, g, level, nullptr, bb, counters, &lv, kProbeLevels));
+    // every step expands at least one level: a fixed count covers the cap,
+    // with no host synchronisation (the batch call can capture it)
+    RST_TRY(bfs_enqueue_steps(ctx, g, level, nullptr, bb, counters, kProbeLevels + 2,
+                              kProbeLevels));
     hipLaunchKernelGGL(k_probe_depth, dim3((unsigned)G), dim3(kBlock), 0, ctx->stream, b->vtx_off,
                        level, s, feat);
     RST_HIP(hipGetLastError());
