@@ -94,17 +94,36 @@ def test_recapture_on_changes(rst):
     check(g1, p1, 5)
 
 
+def chains_linked_across_tiles(n, seed):
+    """Chains of 8 consecutive ids, each chain's first vertex joined to a
+    random vertex of a random earlier chain: few edges cross vertex tiles
+    (ids keep their locality), yet the tour leaves its arc tile at about a
+    quarter of the arcs, far more exits than one workgroup ranks."""
+    rs = np.random.RandomState(seed)
+    v = np.arange(n)
+    inner = v[(v % 8) != 7]
+    inner = inner[inner + 1 < n]
+    starts = np.arange(8, n, 8)
+    links = rs.randint(0, starts)
+    eu = np.concatenate([inner, starts]).astype(np.int32)
+    ev = np.concatenate([inner + 1, links]).astype(np.int32)
+    return I.csr_from_edges(n, eu, ev, name="linked_chains")
+
+
 def test_replays_with_contracted_list_fallback(rst):
     """A graph whose contracted tour list is too long for the one-workgroup
-    ranking: every replay finishes with the multi-workgroup fallback after the
-    call's synchronisation, and must still give a verified tree and report one
+    ranking: every replay finishes with the sparse ruling set after the call's
+    synchronisation, and must still give a verified tree and report one
     component (the components are counted once, in the replayed pass)."""
     c = rst.Context(0)
-    g = I.random_graph(300000, 450000, seed=11, connected=True)
+    g = chains_linked_across_tiles(300000, seed=11)
     off, cols = upload(g)
     par = torch.empty(g.n, dtype=torch.int32).cuda()
-    _, st = c.spanning_tree(off, cols, 11, "gconn", stats=True)
-    assert st["paths"] & rst.PATH_RANK_GLOBAL and st["components"] == 1
+    p0, st = c.spanning_tree(off, cols, 11, "gconn", stats=True)
+    check(g, p0, 11)
+    assert 2 * st["cross_edges"] <= g.n, st          # the per-tile ranking is chosen
+    assert st["paths"] & rst.PATH_RANK_SPARSE and st["components"] == 1, st
+    assert not st["paths"] & rst.PATH_RANK_GLOBAL, st
     for _ in range(3):
         par.fill_(-3)
         c.spanning_tree(off, cols, 11, "gconn", parent=par)   # raises if not one component
