@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCE = {"hook_tile": "hook.hip", "cross": "hook.hip", "late_hooks": "hook.hip",
+                 "hook_sample": "ghook.hip", "hook_global": "ghook.hip",
                  "rank_tile": "euler.hip", "settle": "euler.hip", "rank_walk": "glrank.hip",
                  "rank_words": "glrank.hip", "parent": "glrank.hip"}
 
@@ -117,6 +118,7 @@ def kernel_bytes(name, g, st):
     the method must move (int32 ids, w_o-byte offsets), not what the caches do."""
     n, nnz, A = g.n, g.nnz, 2 * g.n
     w_o = g.offset_bytes
+    T = n - st["components"]
     X = st["cross_edges"]
     R1 = st["rank_exits"]          # rulers of the sparse ruling set (words of level 2)
     return {
@@ -129,6 +131,15 @@ def kernel_bytes(name, g, st):
         # gathers (8); each of the n - 1 tree edges: compare-and-swap (4),
         # edge recorded (8), two list-head exchanges and the next pair (16)
         "late_hooks": 16 * X + 28 * (n - 1),
+        # global hooking, first part: every vertex's label, edge slot and list
+        # head initialised (16 n); with sampling, per vertex its offsets and
+        # first arcs read and their two labels gathered
+        "hook_sample": 16 * n,
+        # global hooking sweep: offsets + neighbour ids read, one label gather
+        # per arc (both ends of each edge), one label read per vertex; each of
+        # the T tree edges: compare-and-swap (4), edge recorded (8), two
+        # list-head exchanges and the next pair (16)
+        "hook_global": w_o * (n + 1) + 6 * nnz + 4 * n + 28 * T,
         # labels and heads read, end-of-list successors written
         "settle": 12 * n,
         # per tour arc: its word read and its code written (4 + 4); per ruler
@@ -233,8 +244,8 @@ def main():
         return statistics.mean(s[key][sub] for s in stats)
     stage_ms = {k: mean("ms_stage", k) for k in ("hook", "compress", "arcs", "succ", "rank", "parent")}
     kernels = {}
-    for k in ("hook_tile", "cross", "late_hooks", "settle", "rank_tile", "rank_words",
-              "rank_walk", "parent"):
+    for k in ("hook_tile", "cross", "late_hooks", "hook_sample", "hook_global", "settle",
+              "rank_tile", "rank_words", "rank_walk", "parent"):
         ms = mean("ms_kernel", k)
         if ms <= 0:
             continue                      # not run on this path

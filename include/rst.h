@@ -94,7 +94,7 @@ enum {
 typedef struct {
   float ms_total;
   float ms_stage[8];
-  float ms_kernel[10];    /* single kernels, see RST_KERNEL_*                  */
+  float ms_kernel[12];    /* single kernels, see RST_KERNEL_*                  */
   int64_t hook_rounds;    /* levels of the binary tree over vertex tiles + 1   */
   int64_t rank_rounds;    /* pointer-jumping rounds on the contracted list     */
   int64_t rank_exits;     /* length of the contracted list (segment exits)     */
@@ -117,9 +117,13 @@ enum {
                                * merge of all levels: merged per group of tiles *
                                * and then the top levels (graphs of more than   *
                                * 8 tiles of 8192 vertices only)                 */
-  RST_PATH_RANK_SPARSE = 8    /* the tour was ranked by the sparse ruling set in *
+  RST_PATH_RANK_SPARSE = 8,   /* the tour was ranked by the sparse ruling set in *
                                * global memory (ids without locality), not per  *
                                * arc tile                                        */
+  RST_PATH_HOOK_GLOBAL = 16,  /* hooking swept the CSR in global memory (ids     *
+                               * without locality), no vertex tiles              */
+  RST_PATH_HOOK_GIANT = 32    /* ... after sampling each vertex's first arcs,    *
+                               * with the vertices of the dominant tree skipped  */
 };
 
 /* Indices of rst_stats.ms_kernel (HIP-event time of one launch each). */
@@ -134,8 +138,11 @@ enum {
                                * LDS merges did not take, and heavy vertices     */
   RST_KERNEL_SETTLE = 6,      /* one-root pass: roots, end-of-list successors    */
   RST_KERNEL_PARENT = 7,      /* parent rule from the ranks (either ranking)     */
-  RST_KERNEL_RANK_WORDS = 8   /* sparse ruling set: successors of every arc from *
+  RST_KERNEL_RANK_WORDS = 8,  /* sparse ruling set: successors of every arc from *
                                * the forest slots, list heads                    */
+  RST_KERNEL_HOOK_SAMPLE = 9, /* global hooking: initialisation, sampled arcs,   *
+                               * dominant root (three launches together)         */
+  RST_KERNEL_HOOK_GLOBAL = 10 /* global hooking: the sweep over the CSR          */
 };
 
 /* Tunables and switches for rst_set_option. */
@@ -159,11 +166,19 @@ typedef enum {
                                 * buffer and settings, captures its device work as a
                                 * HIP graph on the second and replays it while they
                                 * stay the same; 0: launch eagerly                 */
-  RST_OPT_RANK_STRIDE = 8      /* sparse ruling set (tours without id locality):
+  RST_OPT_RANK_STRIDE = 8,     /* sparse ruling set (tours without id locality):
                                 * every k-th arc starts a ruler, k in 4, 8, 16
                                 * (default), 32, 64                                */
+  RST_OPT_HOOK_MODE = 9,       /* hooking of GConn+Euler and rst_components: 0
+                                * (default) chooses by sampling arcs: when most
+                                * leave their source's 8192-id tile the global
+                                * sweep runs, else the tile pass; 1: tile pass;
+                                * 2: global sweep (needs nnz < 2^31, else tiles) */
+  RST_OPT_HOOK_SAMPLE = 10     /* global sweep: arcs per vertex hooked before the
+                                * dominant tree is sought, 0 .. 4; -1 (default):
+                                * 2 when nnz >= 6 n, else 0                       */
 } rst_option;
-#define RST_NUM_OPTIONS 9
+#define RST_NUM_OPTIONS 11
 
 /* Create a context on HIP device `device` bound to `hip_stream` (a hipStream_t,
  * NULL = the default stream).  *out receives the context.  Errors: RST_E_INVAL

@@ -42,11 +42,15 @@ OPT_SWEEP_BLOCK = 5
 OPT_BFS_HEAVY_DEGREE = 6
 OPT_GRAPHS = 7
 OPT_RANK_STRIDE = 8
+OPT_HOOK_MODE = 9
+OPT_HOOK_SAMPLE = 10
 
 PATH_CROSS_GLOBAL = 1
 PATH_RANK_GLOBAL = 2
 PATH_CROSS_GROUPS = 4
 PATH_RANK_SPARSE = 8
+PATH_HOOK_GLOBAL = 16
+PATH_HOOK_GIANT = 32
 
 STAGES = ["hook", "compress", "arcs", "succ", "rank", "parent", "bfs", "select"]
 
@@ -82,7 +86,7 @@ class rst_batch(ctypes.Structure):
 
 
 KERNELS = ["hook_tile", "cross", "rank_tile", "link", "rank_walk", "late_hooks", "settle",
-           "parent", "rank_words", "k9"]
+           "parent", "rank_words", "hook_sample", "hook_global", "k11"]
 
 
 class rst_tune_result(ctypes.Structure):
@@ -99,7 +103,7 @@ class rst_tune_result(ctypes.Structure):
 
 class rst_stats(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_float), ("ms_stage", ctypes.c_float * 8),
-                ("ms_kernel", ctypes.c_float * 10),
+                ("ms_kernel", ctypes.c_float * 12),
                 ("hook_rounds", ctypes.c_int64), ("rank_rounds", ctypes.c_int64),
                 ("rank_exits", ctypes.c_int64), ("cross_edges", ctypes.c_int64),
                 ("bfs_levels", ctypes.c_int64), ("components", ctypes.c_int64),
@@ -108,7 +112,7 @@ class rst_stats(ctypes.Structure):
     def as_dict(self) -> dict:
         return {"ms_total": self.ms_total,
                 "ms_stage": {STAGES[i]: self.ms_stage[i] for i in range(8)},
-                "ms_kernel": {KERNELS[i]: self.ms_kernel[i] for i in range(9)},
+                "ms_kernel": {KERNELS[i]: self.ms_kernel[i] for i in range(11)},
                 "hook_rounds": self.hook_rounds, "rank_rounds": self.rank_rounds,
                 "rank_exits": self.rank_exits, "cross_edges": self.cross_edges,
                 "bfs_levels": self.bfs_levels, "components": self.components,

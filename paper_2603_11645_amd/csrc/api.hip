@@ -111,6 +111,46 @@ static RankBufs take_rank_bufs(rst_ctx *ctx, int64_t A) {
 // tiles at almost every arc.
 static bool prefer_sparse_rank(int64_t cross_edges, int64_t n) { return 2 * cross_edges > n; }
 
+// Hooking variant of a call: the tile pass (hook.hip) or, for ids without
+// locality, the global sweep (ghook.hip).  RST_OPT_HOOK_MODE 1 or 2 decides;
+// in mode 0 one workgroup samples arcs, and when more than half of them leave
+// their source's 8192-id tile the global sweep runs (one read-back of the
+// counters, which the caller has zeroed).
+static rst_status choose_hook(rst_ctx *ctx, const rst_csr *g, const uint8_t *vmask,
+                              int32_t *counters, bool *global) {
+  *global = false;
+  if (g->nnz >= ((int64_t)1 << 31) || ctx->opt.hook_mode == 1) return RST_OK;
+  if (ctx->opt.hook_mode == 2) { *global = true; return RST_OK; }
+  RST_TRY(enqueue_fill(ctx, counters + kCntProbeArcs, 2, 0));
+  RST_TRY(enqueue_locality_probe(ctx, g, vmask, counters));
+  RST_TRY(read_counters(ctx, counters));
+  *global = 2 * (int64_t)ctx->host_pinned[kCntProbeCross] > (int64_t)ctx->host_pinned[kCntProbeArcs];
+  return RST_OK;
+}
+
+// After a replayed call (counters read back): whether the hooking and the
+// ranking it captured still suit the data under its buffers.  The tile pass
+// counts the edges that left their tiles, the global sweep the vertices whose
+// first arc stayed in theirs.
+static bool replay_wants_global(const rst_ctx *ctx, const rst_csr *g, bool global) {
+  if (g->nnz >= ((int64_t)1 << 31) || ctx->opt.hook_mode == 1) return false;
+  if (ctx->opt.hook_mode == 2) return true;
+  if (global) return 2 * (int64_t)ctx->host_pinned[kCntLocal] < g->n;
+  return 4 * (int64_t)ctx->host_pinned[kCntCross] > g->nnz;
+}
+
+static bool wants_sparse_rank(const rst_ctx *ctx, const rst_csr *g, bool global) {
+  if (global) return 2 * (int64_t)ctx->host_pinned[kCntLocal] < g->n;
+  return prefer_sparse_rank(ctx->host_pinned[kCntCross], g->n);
+}
+
+static rst_status enqueue_hook(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, bool global,
+                               int64_t *chunks, int64_t chunk_cap, int2 *cross,
+                               int32_t *tile_cross) {
+  if (global) return enqueue_hook_global(ctx, g, f);
+  return enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross);
+}
+
 static GlistPlan gconn_glist_plan(const rst_ctx *ctx, int64_t n) {
   // lists: one per tree with an edge, at most n / 2
   return glist_plan(2 * n, n / 2 + 1, ctx->opt.rank_stride);
@@ -131,6 +171,7 @@ struct GconnWork {
   bool exported = false;  // the last kernel writes the counters to host_pinned (graph path)
   bool sparse = false;    // rank by the sparse ruling set (else per tile)
   bool sparse_ran = false;   // the sparse ruling set ran in this call (directly or as fallback)
+  bool global_hook = false;  // hooking by the global sweep (else the tile pass)
   RankBufs rb;
   GlistBufs gl;
   int32_t *w1() const { return reinterpret_cast<int32_t *>(rank); }   // level-1 words alias rank
@@ -169,7 +210,7 @@ static rst_status enqueue_gconn_forest(rst_ctx *ctx, const rst_csr *g, const int
                                        GconnWork &w) {
   const int64_t n = g->n;
   RST_TRY(mark(ctx, st, 0));
-  RST_TRY(enqueue_hook_csr(ctx, g, w.f, w.chunks, w.chunk_cap, w.cross, w.tile_cross));
+  RST_TRY(enqueue_hook(ctx, g, w.f, w.global_hook, w.chunks, w.chunk_cap, w.cross, w.tile_cross));
   RST_TRY(mark(ctx, st, 1));
   w.settled = nroots == 1;
   if (w.settled) {
@@ -271,11 +312,14 @@ static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, 
                          ctx->host_pinned[kCntGDyn]
                    : ctx->host_pinned[kCntExits];
   // the one-block merge of all levels is tried when there are more than 3 levels
-  const bool groups = hook_level_count(n) > 3 && !ctx->host_pinned[kCntCrossDone];
-  const int32_t paths = (ctx->host_pinned[kCntCrossOverflow] ? RST_PATH_CROSS_GLOBAL : 0) |
-                        (last_resort ? RST_PATH_RANK_GLOBAL : 0) |
-                        (groups ? RST_PATH_CROSS_GROUPS : 0) |
-                        (w.sparse_ran && !last_resort ? RST_PATH_RANK_SPARSE : 0);
+  const bool groups =
+      !w.global_hook && hook_level_count(n) > 3 && !ctx->host_pinned[kCntCrossDone];
+  const int32_t paths =
+      (!w.global_hook && ctx->host_pinned[kCntCrossOverflow] ? RST_PATH_CROSS_GLOBAL : 0) |
+      (last_resort ? RST_PATH_RANK_GLOBAL : 0) | (groups ? RST_PATH_CROSS_GROUPS : 0) |
+      (w.sparse_ran && !last_resort ? RST_PATH_RANK_SPARSE : 0) |
+      (w.global_hook ? RST_PATH_HOOK_GLOBAL : 0) |
+      (w.global_hook && ctx->host_pinned[kCntGiant] >= 0 ? RST_PATH_HOOK_GIANT : 0);
   if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
   if (ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
   *components = ctx->host_pinned[kCntComponents];
@@ -284,7 +328,8 @@ static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, 
                                 RST_STAGE_RANK, RST_STAGE_PARENT};
     fill_stage_times(ctx, st, gaps, 7);
     fill_kernel_times(ctx, st);
-    st->hook_rounds = 1 + hook_level_count(n);
+    st->hook_rounds = w.global_hook ? (ghook_sample_arcs(ctx, g) > 0 ? 2 : 1)
+                                    : 1 + hook_level_count(n);
     st->rank_rounds = rounds;
     st->rank_exits = exits_n;
     st->cross_edges = ctx->host_pinned[kCntCross];
@@ -302,11 +347,13 @@ static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, 
 rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
                            int32_t *parent, rst_stats *st, int64_t *components,
                            int32_t *counters, int32_t *cc_out, const uint8_t *vmask = nullptr,
-                           bool *sparse = nullptr) {
+                           bool *sparse = nullptr, bool *global_hook = nullptr) {
   GconnWork w = take_gconn_work(ctx, g, counters, cc_out, vmask);
+  RST_TRY(choose_hook(ctx, g, vmask, counters, &w.global_hook));
+  if (global_hook) *global_hook = w.global_hook;
   RST_TRY(enqueue_gconn_forest(ctx, g, roots, nroots, parent, st, w));
   RST_TRY(read_counters(ctx, counters));
-  w.sparse = prefer_sparse_rank(ctx->host_pinned[kCntCross], g->n);
+  w.sparse = wants_sparse_rank(ctx, g, w.global_hook);
   if (sparse) *sparse = w.sparse;
   RST_TRY(enqueue_gconn_rank(ctx, g, parent, st, w));
   return finish_gconn(ctx, g, parent, st, components, w);
@@ -330,6 +377,7 @@ struct GraphCache {
   GraphKey key;
   hipGraphExec_t exec = nullptr;
   bool sparse = false;   // ranking captured for this key (sparse ruling set or per tile)
+  bool global_hook = false;   // hooking captured for this key (global sweep or tile pass)
 };
 
 void graph_free(rst_ctx *ctx) {
@@ -510,6 +558,14 @@ rst_status rst_set_option(rst_ctx *ctx, rst_option opt, int64_t value) {
       if (value != 4 && value != 8 && value != 16 && value != 32 && value != 64) return RST_E_INVAL;
       ctx->opt.rank_stride = (int)value;
       return RST_OK;
+    case RST_OPT_HOOK_MODE:
+      if (value < 0 || value > 2) return RST_E_INVAL;
+      ctx->opt.hook_mode = (int)value;
+      return RST_OK;
+    case RST_OPT_HOOK_SAMPLE:
+      if (value < -1 || value > 4) return RST_E_INVAL;
+      ctx->opt.hook_sample = (int)value;
+      return RST_OK;
   }
   return RST_E_INVAL;
 }
@@ -526,6 +582,8 @@ rst_status rst_get_option(const rst_ctx *ctx, rst_option opt, int64_t *value) {
     case RST_OPT_BFS_HEAVY_DEGREE: *value = ctx->opt.bfs_heavy_degree; return RST_OK;
     case RST_OPT_GRAPHS: *value = ctx->opt.graphs; return RST_OK;
     case RST_OPT_RANK_STRIDE: *value = ctx->opt.rank_stride; return RST_OK;
+    case RST_OPT_HOOK_MODE: *value = ctx->opt.hook_mode; return RST_OK;
+    case RST_OPT_HOOK_SAMPLE: *value = ctx->opt.hook_sample; return RST_OK;
   }
   return RST_E_INVAL;
 }
@@ -602,18 +660,20 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
       // first call with these buffers and settings: run eagerly, choosing the
       // ranking from the hooking counters; the next call captures that choice
       RST_TRY(enqueue_reset_counters(ctx, counters, root));
-      bool sparse = false;
+      bool sparse = false, global_hook = false;
       RST_TRY(run_gconn_euler(ctx, g, rootbuf, 1, parent, nullptr, &comps, counters, nullptr,
-                              nullptr, &sparse));
+                              nullptr, &sparse, &global_hook));
       graph_forget(ctx);
       ctx->graph->key = key;
       ctx->graph->sparse = sparse;
+      ctx->graph->global_hook = global_hook;
       return comps > 1 ? RST_E_DISCONNECTED : RST_OK;
     }
     GconnWork w = take_gconn_work(ctx, g, counters, nullptr, nullptr);
     w.settled = true;   // one root (a replay does not run the host code of the enqueue functions)
     w.exported = ctx->host_pinned_dev != nullptr;
     w.sparse = ctx->graph->sparse;
+    w.global_hook = ctx->graph->global_hook;
     RST_TRY(run_graph(ctx, key, [&]() -> rst_status {
       RST_TRY(enqueue_reset_counters(ctx, counters, root));
       RST_TRY(enqueue_gconn_forest(ctx, g, rootbuf, 1, parent, nullptr, w));
@@ -622,12 +682,16 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
     w.sparse_ran = w.sparse;
     RST_TRY(finish_gconn(ctx, g, parent, nullptr, &comps, w));
     // the data under these buffers may have changed since the capture: when
-    // the other ranking suits it now, the next call captures that one
-    const bool want = prefer_sparse_rank(ctx->host_pinned[kCntCross], g->n);
-    if (want != w.sparse && ctx->graph->exec) {
+    // the other hooking or ranking suits it now, the next call captures that
+    const bool want_global = replay_wants_global(ctx, g, w.global_hook);
+    const bool want_sparse = want_global == w.global_hook
+                                 ? wants_sparse_rank(ctx, g, w.global_hook)
+                                 : want_global;
+    if ((want_sparse != w.sparse || want_global != w.global_hook) && ctx->graph->exec) {
       RST_HIP(hipGraphExecDestroy(ctx->graph->exec));
       ctx->graph->exec = nullptr;
-      ctx->graph->sparse = want;
+      ctx->graph->sparse = want_sparse;
+      ctx->graph->global_hook = want_global;
     }
     return comps > 1 ? RST_E_DISCONNECTED : RST_OK;
   }
@@ -665,8 +729,10 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
     const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
     int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
     int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
-  int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
-    RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
+    int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
+    bool global_hook = false;
+    RST_TRY(choose_hook(ctx, g, f.vmask, f.counters, &global_hook));
+    RST_TRY(enqueue_hook(ctx, g, f, global_hook, chunks, chunk_cap, cross, tile_cross));
     RST_TRY(enqueue_compress(ctx, g->n, f.cc, nullptr, nullptr));
     RST_TRY(enqueue_count_roots(ctx, g->n, f.cc, counters));
     RST_TRY(bfs_seed_unreached(ctx, g, f.cc, level, parent, b, counters));
@@ -706,7 +772,9 @@ rst_status rst_components(rst_ctx *ctx, const rst_csr *g, int32_t *label,
   int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
   int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
   int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
-  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
+  bool global_hook = false;
+  RST_TRY(choose_hook(ctx, g, f.vmask, f.counters, &global_hook));
+  RST_TRY(enqueue_hook(ctx, g, f, global_hook, chunks, chunk_cap, cross, tile_cross));
   RST_TRY(enqueue_compress(ctx, g->n, label, nullptr, nullptr));
   RST_TRY(enqueue_count_roots(ctx, g->n, label, counters));
   RST_TRY(read_counters(ctx, counters));
@@ -738,7 +806,9 @@ rst_status rst_verify(rst_ctx *ctx, const rst_csr *g, int32_t root, const int32_
   int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
   int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
   int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(n));
-  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
+  bool global_hook = false;
+  RST_TRY(choose_hook(ctx, g, f.vmask, f.counters, &global_hook));
+  RST_TRY(enqueue_hook(ctx, g, f, global_hook, chunks, chunk_cap, cross, tile_cross));
   RST_TRY(enqueue_compress(ctx, n, f.cc, nullptr, nullptr));
   int32_t *anc0 = ws_take<int32_t>(ctx, n);
   int32_t *anc1 = ws_take<int32_t>(ctx, n);
@@ -769,7 +839,9 @@ rst_status rst_spanning_forest(rst_ctx *ctx, const rst_csr *g, int32_t *label, i
   int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
   int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
   int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(g->n));
-  RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
+  bool global_hook = false;
+  RST_TRY(choose_hook(ctx, g, f.vmask, f.counters, &global_hook));
+  RST_TRY(enqueue_hook(ctx, g, f, global_hook, chunks, chunk_cap, cross, tile_cross));
   RST_TRY(enqueue_compress(ctx, g->n, label, nullptr, nullptr));
   RST_TRY(enqueue_count_roots(ctx, g->n, label, counters));
   RST_TRY(read_counters(ctx, counters));
@@ -989,7 +1061,9 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
       int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(n));
       // the heavy-chunk list is rebuilt from empty (the GConn stage used it)
       RST_TRY(enqueue_fill(ctx, counters + kCntChunks, 1, 0));
-      RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
+      bool global_hook = false;
+      RST_TRY(choose_hook(ctx, g, f.vmask, f.counters, &global_hook));
+      RST_TRY(enqueue_hook(ctx, g, f, global_hook, chunks, chunk_cap, cross, tile_cross));
       RST_TRY(enqueue_compress(ctx, n, f.cc, nullptr, nullptr));
       RST_TRY(bfs_seed_unreached(ctx, g, f.cc, level, parent, bb, counters, vmask));
       int64_t l2 = 0;

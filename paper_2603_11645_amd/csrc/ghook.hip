@@ -1,0 +1,275 @@
+// ghook.hip -- hooking in global memory for graphs whose vertex ids carry no
+// locality (random labels: R-MAT, permuted meshes, long chains).  Same hooking
+// rule as hook.hip (Sec. III-B: the larger root is linked under the smaller by
+// compare-and-swap, the edge behind every successful hook recorded at the
+// hooked root, Sec. I) and the same Euler arc lists (link_slot), but no vertex
+// tiles: on such graphs almost every edge crosses tiles, so the tile pass and
+// the cross-tile merges only add work.
+//
+// Sec. III-B leaves the order of hooking open.  The sweep here follows the
+// sampling idea of Afforest (Sutton et al.): a vertex first hooks along its
+// first K arcs, which on graphs of average degree well above 2 already joins
+// most vertices into one dominant tree; one workgroup then finds the most
+// frequent root in a sample of vertices.  The full sweep visits the remaining
+// arcs, and a vertex that is already in the dominant tree offers none: the
+// arcs it skips lead either into the dominant tree too or to a vertex outside
+// it, which offers the reverse arc itself (the CSR is symmetric).  Without a
+// dominant tree (chains, meshes: no sample root holds half the sample) each
+// edge is visited once instead, from its larger end.
+#include "rst_internal.h"
+#include "device_common.h"
+#include "unionfind.h"
+
+namespace rst {
+
+constexpr int kGhThreads = 1024;      // vertices per workgroup of the arc sweep
+constexpr int kGhSampleThreads = 1024;
+constexpr int kGhSamplePer = 4;       // sampled vertices per thread (giant, probe)
+constexpr int kGhHash = 8192;         // LDS hash slots of the root count
+constexpr int kGhTileShift = 13;      // the tile pass's tile: 8192 consecutive ids
+
+// counter-based sample index (splitmix64 finaliser of seed ^ i)
+__device__ __forceinline__ uint64_t gh_mix(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// root of x without writes (cc[y] <= y, equality at roots)
+__device__ __forceinline__ int32_t gh_root(int32_t x, const int32_t *cc) {
+  int32_t r = x, nx;
+  while (r > (nx = cc[r])) r = nx;
+  return r;
+}
+
+// Every vertex its own tree, every slot empty, every arc list empty.
+template <int B>
+__global__ __launch_bounds__(B) void k_gh_init(int64_t n, int32_t *cc, int32_t *tu, int32_t *tv,
+                                               int32_t *head) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  cc[v] = (int32_t)v;
+  tu[v] = -1;
+  tv[v] = -1;
+  if (head) head[v] = -1;
+}
+
+// Each vertex hooks along its first K arcs (grid-stride over the vertices: a
+// few workgroups per CU, each ending with one device-scope release).
+template <class OffT>
+__global__ __launch_bounds__(kBlock) void k_gh_sample(int64_t n, const OffT *__restrict__ off,
+                                                      const int32_t *__restrict__ cols, int K,
+                                                      const uint8_t *__restrict__ vmask, int32_t *cc,
+                                                      int32_t *tu, int32_t *tv, int32_t *head,
+                                                      int32_t *next) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    if (vmask && vmask[v]) continue;
+    const OffT b = off[v], e = off[v + 1];
+    for (int r = 0; r < K && b + (OffT)r < e; ++r) {
+      const int32_t w = cols[b + (OffT)r];
+      if (w != (int32_t)v) hook_edge<true>((int32_t)v, w, cc, tu, tv, head, next);
+    }
+  }
+  block_release_device();
+}
+
+// One workgroup: roots of kGhSampleThreads * kGhSamplePer sampled vertices
+// counted in LDS; the most frequent becomes the dominant root when it holds at
+// least half of the (unmasked) samples, else -1.
+__global__ __launch_bounds__(kGhSampleThreads) void k_gh_giant(int64_t n, const int32_t *__restrict__ cc,
+                                                               const uint8_t *__restrict__ vmask,
+                                                               int32_t *counters) {
+  __shared__ int32_t keys[kGhHash];
+  __shared__ int32_t cnts[kGhHash];
+  __shared__ int s_valid;
+  __shared__ unsigned long long s_best;
+  const int t = threadIdx.x;
+  for (int i = t; i < kGhHash; i += kGhSampleThreads) { keys[i] = -1; cnts[i] = 0; }
+  if (t == 0) { s_valid = 0; s_best = 0ull; }
+  __syncthreads();
+  int valid = 0;
+#pragma unroll
+  for (int s = 0; s < kGhSamplePer; ++s) {
+    const uint64_t i = (uint64_t)t * kGhSamplePer + s;
+    const int32_t v = (int32_t)(gh_mix(0x5eedull ^ (i << 20)) % (uint64_t)n);
+    if (vmask && vmask[v]) continue;
+    ++valid;
+    const int32_t r = gh_root(v, cc);
+    uint32_t h = ((uint32_t)r * 0x9E3779B1u) >> (32 - 13);
+    while (true) {   // at most 4096 keys in 8192 slots: a free slot exists
+      const int32_t old = atomicCAS(&keys[h], -1, r);
+      if (old == -1 || old == r) { atomicAdd(&cnts[h], 1); break; }
+      h = (h + 1) & (kGhHash - 1);
+    }
+  }
+  atomicAdd(&s_valid, valid);
+  __syncthreads();
+  for (int i = t; i < kGhHash; i += kGhSampleThreads)
+    if (cnts[i] > 0)
+      atomicMax(&s_best, ((unsigned long long)(uint32_t)cnts[i] << 32) | (uint32_t)keys[i]);
+  __syncthreads();
+  if (t == 0) {
+    const int best = (int)(s_best >> 32);
+    counters[kCntGiant] = (s_valid > 0 && 2 * best >= s_valid) ? (int32_t)(uint32_t)s_best : -1;
+  }
+}
+
+// The full sweep: a workgroup takes kGhThreads consecutive vertices at a
+// time (grid-stride over such chunks, a few workgroups per CU), scans the
+// degrees of their remaining arcs (from the K-th on) in LDS and walks the
+// union of those arcs with unit stride.  With a dominant root D (counters
+// [kCntGiant] >= 0) a vertex whose root is D offers nothing and the others
+// offer every remaining arc; without one, an arc is hooked from its larger
+// end only.  Also counts the vertices whose first arc stays in their 8192-id
+// tile (counters[kCntLocal]), so that a later call on the same buffers can
+// tell whether the ids have gained locality.  Each workgroup ends with one
+// device-scope release.
+template <class OffT>
+__global__ __launch_bounds__(kGhThreads) void k_gh_sweep(int64_t n, const OffT *__restrict__ off,
+                                                         const int32_t *__restrict__ cols, int K,
+                                                         const uint8_t *__restrict__ vmask,
+                                                         int32_t *cc, int32_t *tu, int32_t *tv,
+                                                         int32_t *head, int32_t *next,
+                                                         int32_t *counters) {
+  __shared__ int s_scan[kGhThreads + 1];
+  __shared__ OffT s_beg[kGhThreads];
+  __shared__ int s_wave[kGhThreads / kWave];
+  const int t = threadIdx.x;
+  const int32_t giant = counters[kCntGiant];
+  const int64_t chunks = (n + kGhThreads - 1) / kGhThreads;
+  int locals = 0;
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const int64_t v0 = c * kGhThreads;
+    const int64_t v = v0 + t;
+    int deg = 0;
+    OffT beg = 0;
+    if (v < n && !(vmask && vmask[v])) {
+      const OffT b = off[v], e = off[v + 1];
+      if (e > b) locals += (cols[b] >> kGhTileShift) == (int32_t)(v >> kGhTileShift);
+      beg = b + (OffT)K;
+      if (e > beg && !(giant >= 0 && find_root((int32_t)v, cc) == giant)) deg = (int)(e - beg);
+    }
+    s_beg[t] = beg;
+    int total;
+    const int excl = block_excl_scan<kGhThreads>(deg, s_wave, &total);
+    s_scan[t] = excl;
+    if (t == kGhThreads - 1) s_scan[kGhThreads] = excl + deg;
+    __syncthreads();
+    for (int b0 = 0; b0 < total; b0 += kGhThreads) {
+      const int k = b0 + t;
+      if (k < total) {
+        const int j = lds_upper_search(s_scan, kGhThreads, k);
+        const int32_t u = (int32_t)(v0 + j);
+        const int32_t w = cols[s_beg[j] + (OffT)(k - s_scan[j])];
+        if (giant >= 0 ? w != u : w < u) hook_edge<true>(u, w, cc, tu, tv, head, next);
+      }
+    }
+    __syncthreads();   // s_scan and s_beg are rewritten for the next chunk
+  }
+  for (int o = 32; o > 0; o >>= 1) locals += __shfl_xor(locals, o, 64);
+  if ((t & 63) == 0 && locals) atomicAdd(&counters[kCntLocal], locals);
+  block_release_device();
+}
+
+// One workgroup: the share of sampled arcs that leave their source's 8192-id
+// tile (counters[kCntProbeArcs], counters[kCntProbeCross]); up to 4 arcs of
+// each of kGhSampleThreads * kGhSamplePer sampled vertices.
+template <class OffT>
+__global__ __launch_bounds__(kGhSampleThreads) void k_gh_probe(int64_t n, const OffT *__restrict__ off,
+                                                               const int32_t *__restrict__ cols,
+                                                               const uint8_t *__restrict__ vmask,
+                                                               int32_t *counters) {
+  int arcs = 0, cross = 0;
+#pragma unroll
+  for (int s = 0; s < kGhSamplePer; ++s) {
+    const uint64_t i = (uint64_t)threadIdx.x * kGhSamplePer + s;
+    const int64_t v = (int64_t)(gh_mix(0x9b0beull ^ (i << 20)) % (uint64_t)n);
+    if (vmask && vmask[v]) continue;
+    const OffT b = off[v], e = off[v + 1];
+    for (OffT a = b; a < e && a < b + 4; ++a) {
+      ++arcs;
+      cross += (cols[a] >> kGhTileShift) != (int32_t)(v >> kGhTileShift);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    arcs += __shfl_xor(arcs, o, 64);
+    cross += __shfl_xor(cross, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&counters[kCntProbeArcs], arcs);
+    atomicAdd(&counters[kCntProbeCross], cross);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+// Grid of the hooking kernels: every workgroup ends with a device-scope
+// release (a write-back of its XCD's L2), so they loop over their work with
+// `per_cu` workgroups per CU instead of one workgroup per piece.
+static unsigned gh_grid(const rst_ctx *ctx, unsigned pieces, int per_cu) {
+  const unsigned cap = (unsigned)(ctx->num_cus * per_cu);
+  return pieces < cap ? pieces : cap;
+}
+
+int ghook_sample_arcs(const rst_ctx *ctx, const rst_csr *g) {
+  if (ctx->opt.hook_sample >= 0) return ctx->opt.hook_sample;
+  // sampling pays where the average degree is well above a chain's or a mesh's
+  return g->nnz >= 6 * g->n ? 2 : 0;
+}
+
+rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f) {
+  const int64_t n = g->n;
+  const int K = ghook_sample_arcs(ctx, g);
+  RST_KMARK(ctx, RST_KERNEL_HOOK_SAMPLE, 0);
+  RST_SWEEP(ctx, k_gh_init, n, n, f.cc, f.tu, f.tv, f.head);
+  RST_HIP(hipGetLastError());
+  if (K > 0) {
+    const unsigned sgrid = gh_grid(ctx, grid_for(n, kBlock), 8);
+    if (g->offset_bytes == 4)
+      hipLaunchKernelGGL(k_gh_sample<int32_t>, dim3(sgrid), dim3(kBlock), 0, ctx->stream, n,
+                         (const int32_t *)g->offsets, g->cols, K, f.vmask, f.cc, f.tu, f.tv,
+                         f.head, f.next);
+    else
+      hipLaunchKernelGGL(k_gh_sample<int64_t>, dim3(sgrid), dim3(kBlock), 0, ctx->stream, n,
+                         (const int64_t *)g->offsets, g->cols, K, f.vmask, f.cc, f.tu, f.tv,
+                         f.head, f.next);
+    RST_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_gh_giant, dim3(1), dim3(kGhSampleThreads), 0, ctx->stream, n, f.cc,
+                       f.vmask, f.counters);
+    RST_HIP(hipGetLastError());
+  } else {
+    RST_TRY(enqueue_fill(ctx, f.counters + kCntGiant, 1, -1));
+  }
+  RST_KMARK(ctx, RST_KERNEL_HOOK_SAMPLE, 1);
+  RST_KMARK(ctx, RST_KERNEL_HOOK_GLOBAL, 0);
+  const unsigned grid = gh_grid(ctx, grid_for(n, kGhThreads), 2);
+  if (g->offset_bytes == 4)
+    hipLaunchKernelGGL(k_gh_sweep<int32_t>, dim3(grid), dim3(kGhThreads), 0, ctx->stream, n,
+                       (const int32_t *)g->offsets, g->cols, K, f.vmask, f.cc, f.tu, f.tv, f.head,
+                       f.next, f.counters);
+  else
+    hipLaunchKernelGGL(k_gh_sweep<int64_t>, dim3(grid), dim3(kGhThreads), 0, ctx->stream, n,
+                       (const int64_t *)g->offsets, g->cols, K, f.vmask, f.cc, f.tu, f.tv, f.head,
+                       f.next, f.counters);
+  RST_HIP(hipGetLastError());
+  RST_KMARK(ctx, RST_KERNEL_HOOK_GLOBAL, 1);
+  return enqueue_l2_invalidate(ctx);
+}
+
+rst_status enqueue_locality_probe(rst_ctx *ctx, const rst_csr *g, const uint8_t *vmask,
+                                  int32_t *counters) {
+  if (g->offset_bytes == 4)
+    hipLaunchKernelGGL(k_gh_probe<int32_t>, dim3(1), dim3(kGhSampleThreads), 0, ctx->stream, g->n,
+                       (const int32_t *)g->offsets, g->cols, vmask, counters);
+  else
+    hipLaunchKernelGGL(k_gh_probe<int64_t>, dim3(1), dim3(kGhSampleThreads), 0, ctx->stream, g->n,
+                       (const int64_t *)g->offsets, g->cols, vmask, counters);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
+}  // namespace rst

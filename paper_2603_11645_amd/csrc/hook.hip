@@ -19,68 +19,14 @@
 // so a 10^5-degree hub cannot serialise one block.
 #include "rst_internal.h"
 #include "device_common.h"
+#include "unionfind.h"
 
 namespace rst {
 
 constexpr int kChunk = 4096;   // arcs per heavy-vertex chunk
 
 // ---------------------------------------------------------------------------
-// union-find core
-// ---------------------------------------------------------------------------
-
-// Root of x with path halving.  Invariant cc[y] <= y (equality iff y is a root)
-// makes the walk strictly decreasing, so it ends even on stale reads; the plain
-// stores only ever replace a non-root's pointer by one of its ancestors.
-__device__ __forceinline__ int32_t find_root(int32_t x, int32_t *cc) {
-  int32_t cur = cc[x];
-  if (cur != x) {
-    int32_t prev = x, nxt;
-    while (cur > (nxt = cc[cur])) {
-      cc[prev] = nxt;
-      prev = cur;
-      cur = nxt;
-    }
-  }
-  return cur;
-}
-
-// Arcs 2x = a->b and 2x+1 = b->a of the edge recorded at slot x, each put in
-// front of its source's list.
-__device__ __forceinline__ void link_slot(int32_t x, int32_t a, int32_t b, int32_t *head,
-                                          int32_t *next) {
-  int2 nx;
-  nx.x = atomicExch(&head[a], 2 * x);
-  nx.y = atomicExch(&head[b], 2 * x + 1);
-  reinterpret_cast<int2 *>(next)[x] = nx;
-}
-
-// Hook the trees of u and v; on success record (u,v) at the hooked root (and
-// link its two arcs when head is non-NULL).
-template <bool kRecord>
-__device__ __forceinline__ void hook_edge(int32_t u, int32_t v, int32_t *cc, int32_t *tu,
-                                          int32_t *tv, int32_t *head = nullptr,
-                                          int32_t *next = nullptr) {
-  int32_t ru = find_root(u, cc);
-  int32_t rv = find_root(v, cc);
-  while (ru != rv) {
-    const int32_t lo = ru < rv ? ru : rv;
-    const int32_t hi = ru < rv ? rv : ru;
-    const int32_t old = atomicCAS(&cc[hi], hi, lo);
-    if (old == hi) {
-      if (kRecord) {
-        tu[hi] = u;
-        tv[hi] = v;
-        if (head) link_slot(hi, u, v, head, next);
-      }
-      return;
-    }
-    // hi was hooked meanwhile: continue from its new parent (an ancestor)
-    if (ru == hi) ru = old; else rv = old;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// kernels
+// kernels (the union-find steps themselves are in unionfind.h)
 // ---------------------------------------------------------------------------
 
 // counters[0..31] = 0 and counters[32] = root (the one-root buffer) in one launch
@@ -936,6 +882,24 @@ __global__ __launch_bounds__(kTileThreads) void k_late_hooks(
   if (hooked) block_release_device();   // block-uniform: only blocks that hooked
 }
 
+// Drops every line of every XCD's L2 (an agent-scope acquire by one wave of
+// each workgroup; workgroups are dealt to the XCDs in turn, so a grid of one
+// workgroup per CU reaches all of them).  Runs once after the last hooking
+// kernel: the hooks were made by compare-and-swap and list heads changed by
+// exchanges, which update memory beyond the L2 of the XCD that issued them,
+// while a line of those arrays that another XCD read during hooking could
+// still sit in its L2; the kernels after hooking read labels and list heads
+// with plain loads.
+__global__ __launch_bounds__(64) void k_l2_invalidate() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+rst_status enqueue_l2_invalidate(rst_ctx *ctx) {
+  hipLaunchKernelGGL(k_l2_invalidate, dim3(ctx->num_cus), dim3(64), 0, ctx->stream);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
 // Edge-list hooking without recording (labels of a given forest).
 __global__ __launch_bounds__(kBlock) void k_hook_coo(int64_t t, int64_t n,
                                                      const int32_t *__restrict__ eu,
@@ -1128,7 +1092,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
                               chunks, chunk_cap, f));
   }
   RST_HIP(hipGetLastError());
-  return RST_OK;
+  return enqueue_l2_invalidate(ctx);
 }
 
 rst_status enqueue_hook_coo(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu,
@@ -1139,6 +1103,7 @@ rst_status enqueue_hook_coo(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *e
     hipLaunchKernelGGL(k_hook_coo, dim3(grid_for(t, kBlock)), dim3(kBlock), 0, ctx->stream, t, n,
                        eu, ev, cc, counters);
     RST_HIP(hipGetLastError());
+    RST_TRY(enqueue_l2_invalidate(ctx));
   }
   return RST_OK;
 }

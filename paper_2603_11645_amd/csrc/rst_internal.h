@@ -29,6 +29,8 @@ struct Options {
   int bfs_heavy_degree = 1024;   // BFS: frontier vertices above this are split over blocks
   int graphs = 1;                // capture the device work of a call as a HIP graph and replay it
   int rank_stride = 16;          // sparse ruling set: every k-th arc starts a ruler
+  int hook_mode = 0;             // 0: by a locality probe, 1: vertex tiles, 2: global sweep
+  int hook_sample = -1;          // global sweep: arcs each vertex hooks first (-1: by degree)
 };
 
 // Launch sweep kernel template `kern<B>` over `items` threads with the
@@ -81,7 +83,7 @@ struct rst_ctx {
   int num_cus = 256;
   rst::Workspace ws;
   rst::Options opt;
-  hipEvent_t ev[32] = {};   // 0-6 stages, 8-27 kernel pairs, 28-31 batch marks
+  hipEvent_t ev[36] = {};   // 0-6 stages, 8-31 kernel pairs, 32-35 batch marks
   int32_t *host_pinned = nullptr;   // small pinned host buffer for flag readback
   int32_t *host_pinned_dev = nullptr;   // its device address (null: read back by copies only)
   bool timing = false;              // record per-kernel events (a stats struct was passed)
@@ -103,8 +105,8 @@ namespace rst {
     if (e_ != hipSuccess) return RST_E_DEVICE;          \
   } while (0)
 
-// per-kernel event pairs in ctx->ev[8..15], recorded only while ctx->timing is set
-enum { kEvKernelBase = 8, kNumKernelTimes = 10, kEvBatchBase = 28, kNumEvents = 32 };
+// per-kernel event pairs in ctx->ev[8..31], recorded only while ctx->timing is set
+enum { kEvKernelBase = 8, kNumKernelTimes = 12, kEvBatchBase = 32, kNumEvents = 36 };
 #define RST_KMARK(ctx, kernel, end)                                                          \
   do {                                                                                        \
     if ((ctx)->timing) {                                                                      \
@@ -178,7 +180,11 @@ enum {
   kCntDepthMax = 20,       // largest depth of a forest (rst_tree_depth)
   kCntPrHooks = 21,        // PR-RST: some edge joined two trees in this iteration
   kCntBatchArcErr = 22,    // validation: an arc of a batch leaves its graph
-  kCntTotal = 24,          // counters read back after a call (the ones above)
+  kCntGiant = 23,          // global hooking: the dominant root after sampling, or -1
+  kCntLocal = 24,          //   vertices whose first arc stays in their 8192-id tile
+  kCntProbeArcs = 25,      // locality probe: sampled arcs
+  kCntProbeCross = 26,     //   of those, arcs leaving their source's 8192-id tile
+  kCntTotal = 28,          // counters read back after a call (the ones above)
 };
 
 // hook.hip
@@ -186,6 +192,9 @@ rst_status enqueue_fill(rst_ctx *ctx, int32_t *p, int64_t count, int32_t value);
 // counters[0..31] = 0, counters[32] = root (the one-root buffer that follows them)
 rst_status enqueue_reset_counters(rst_ctx *ctx, int32_t *counters, int32_t root);
 rst_status enqueue_validate(rst_ctx *ctx, const rst_csr *g, int32_t *counters);
+// one small launch that drops every line of every XCD's L2 (run after hooking,
+// before plain loads of the labels and list heads that atomics changed)
+rst_status enqueue_l2_invalidate(rst_ctx *ctx);
 // cross: int2 [hook_cross_capacity], tile_cross: int32 [hook_tile_words], 8-byte aligned
 rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64_t *chunks,
                             int64_t chunk_cap, int2 *cross, int32_t *tile_cross);
@@ -199,6 +208,18 @@ rst_status enqueue_compress(rst_ctx *ctx, int64_t n, int32_t *cc, int32_t *comp_
                             int32_t *head);
 rst_status enqueue_count_roots(rst_ctx *ctx, int64_t n, const int32_t *cc, int32_t *counters);
 size_t hook_chunk_capacity(const rst_ctx *ctx, int64_t nnz);
+
+// ghook.hip: hooking by a sweep over the CSR in global memory (ids without
+// locality): optional sampling of each vertex's first arcs, a dominant root,
+// then the remaining arcs; fills f.cc, f.tu, f.tv (and the arc lists when
+// f.head is set) like enqueue_hook_csr.  Needs nnz < 2^31.
+rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f);
+int ghook_sample_arcs(const rst_ctx *ctx, const rst_csr *g);
+// one workgroup samples arcs; counters[kCntProbeArcs], [kCntProbeCross] (zeroed
+// by the caller beforehand) receive how many there were and how many left
+// their 8192-id tile
+rst_status enqueue_locality_probe(rst_ctx *ctx, const rst_csr *g, const uint8_t *vmask,
+                                  int32_t *counters);
 
 // euler.hip
 // one designated root, after all hooks: the root's claim, end-of-list
