@@ -17,6 +17,21 @@
 
 namespace rst {
 
+// Maximum of d over the workgroup, then one atomic per workgroup (one per
+// wave on a single word serialised the pass).  Called by all threads.
+template <int B>
+__device__ __forceinline__ void block_max_to(int32_t d, int32_t *out) {
+  __shared__ int32_t s_max[B / 64];
+  for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o, 64));
+  if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t m = s_max[0];
+    for (int w = 1; w < B / 64; ++w) m = max(m, s_max[w]);
+    atomicMax(out, m);
+  }
+}
+
 __device__ __forceinline__ bool depth_is_root(int32_t v, int32_t p, int64_t n) {
   return p == v || p < 0 || p >= n;   // out-of-range parents are taken as roots
 }
@@ -95,9 +110,7 @@ __global__ __launch_bounds__(B) void k_depth_out(int64_t n, const int32_t *__res
     }
     depth[x] = d;
   }
-  // wave maximum, one atomic per wave
-  for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(&counters[kCntDepthMax], d);
+  block_max_to<B>(d, &counters[kCntDepthMax]);
 }
 
 // Fallback after counters[kCntGOverflow] (more trees than the ruling set
@@ -112,8 +125,7 @@ __global__ __launch_bounds__(B) void k_depth_out_rounds(int64_t n, const int32_t
     if (!depth_is_root((int32_t)x, parent[x], n)) d = -(int32_t)(uint32_t)(w[2 * x] >> 32);
     depth[x] = d;
   }
-  for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o, 64));
-  if ((threadIdx.x & 63) == 0) atomicMax(&counters[kCntDepthMax], d);
+  block_max_to<B>(d, &counters[kCntDepthMax]);
 }
 
 size_t depth_ws_bytes(int64_t n, const GlistPlan &p) {

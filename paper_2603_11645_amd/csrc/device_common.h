@@ -76,6 +76,18 @@ __device__ __forceinline__ int lds_upper_search(const int *s, int len, int k) {
   return lo;
 }
 
+// Store at agent scope (global_store with the sc1 bit on gfx950).  Used for
+// every write of a union-find label or an arc-list head made while hooking is
+// in progress or before it: kernels on other XCDs later compare-and-swap,
+// exchange, overwrite or read these words.  With plain stores, a path-halving
+// store left in one XCD's L2 was seen to land in memory after the final
+// pointer-jumping pass had written the same word from another XCD (a label
+// one hop short of the root, a few vertices in 1 of 40 calls; measured on
+// MI355X), which a release fence at the end of each wave did not prevent.
+__device__ __forceinline__ void store_agent(int32_t *p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Device-scope release by the calling wave (agent-scope fence: this XCD's L2
 // is written back).  Kernels whose waves hook trees through compare-and-swap
 // and path-halving stores in global memory, from many workgroups at once, end

@@ -7,15 +7,15 @@
 // the cross-tile merges only add work.
 //
 // Sec. III-B leaves the order of hooking open.  The sweep here follows the
-// sampling idea of Afforest (Sutton et al.): a vertex first hooks along its
-// first K arcs, which on graphs of average degree well above 2 already joins
-// most vertices into one dominant tree; one workgroup then finds the most
-// frequent root in a sample of vertices.  The full sweep visits the remaining
-// arcs, and a vertex that is already in the dominant tree offers none: the
-// arcs it skips lead either into the dominant tree too or to a vertex outside
-// it, which offers the reverse arc itself (the CSR is symmetric).  Without a
-// dominant tree (chains, meshes: no sample root holds half the sample) each
-// edge is visited once instead, from its larger end.
+// sampling idea of Afforest (Sutton et al.): a vertex first hooks along K of
+// its arcs, which on graphs of average degree well above 2 already joins most
+// vertices into one dominant tree; one workgroup then finds the most frequent
+// root in a sample of vertices.  The full sweep visits the arcs again, and a
+// vertex that is already in the dominant tree offers none: the arcs it skips
+// lead either into the dominant tree too or to a vertex outside it, which
+// offers the reverse arc itself (the CSR is symmetric).  Without a dominant
+// tree (chains, meshes: no sample root holds half the sample) each edge is
+// visited once instead, from its larger end.
 #include "rst_internal.h"
 #include "device_common.h"
 #include "unionfind.h"
@@ -49,14 +49,18 @@ __global__ __launch_bounds__(B) void k_gh_init(int64_t n, int32_t *cc, int32_t *
                                                int32_t *head) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  cc[v] = (int32_t)v;
+  store_agent(&cc[v], (int32_t)v);
   tu[v] = -1;
   tv[v] = -1;
-  if (head) head[v] = -1;
+  if (head) store_agent(&head[v], -1);
 }
 
-// Each vertex hooks along its first K arcs (grid-stride over the vertices: a
-// few workgroups per CU, each ending with one device-scope release).
+// Each vertex hooks along K of its arcs (all of them when it has at most K),
+// taken at pseudo-random positions: on power-law graphs with sorted neighbour
+// lists the first arcs of almost every vertex lead to the same few hubs, and
+// every hook puts an arc at the front of both ends' lists by an exchange on
+// the list head, which serialises on a hub.  Grid-stride over the vertices, a
+// few workgroups per CU, each ending with one device-scope release.
 template <class OffT>
 __global__ __launch_bounds__(kBlock) void k_gh_sample(int64_t n, const OffT *__restrict__ off,
                                                       const int32_t *__restrict__ cols, int K,
@@ -67,8 +71,11 @@ __global__ __launch_bounds__(kBlock) void k_gh_sample(int64_t n, const OffT *__r
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
     if (vmask && vmask[v]) continue;
     const OffT b = off[v], e = off[v + 1];
-    for (int r = 0; r < K && b + (OffT)r < e; ++r) {
-      const int32_t w = cols[b + (OffT)r];
+    const uint64_t deg = (uint64_t)(e - b);
+    for (int r = 0; r < K && (uint64_t)r < deg; ++r) {
+      const uint64_t pos = deg <= (uint64_t)K ? (uint64_t)r
+                                              : gh_mix(((uint64_t)v << 3) | (uint64_t)r) % deg;
+      const int32_t w = cols[b + (OffT)pos];
       if (w != (int32_t)v) hook_edge<true>((int32_t)v, w, cc, tu, tv, head, next);
     }
   }
@@ -117,9 +124,9 @@ __global__ __launch_bounds__(kGhSampleThreads) void k_gh_giant(int64_t n, const 
 }
 
 // The full sweep: a workgroup takes kGhThreads consecutive vertices at a
-// time (grid-stride over such chunks, a few workgroups per CU), scans the
-// degrees of their remaining arcs (from the K-th on) in LDS and walks the
-// union of those arcs with unit stride.  With a dominant root D (counters
+// time (grid-stride over such chunks, a few workgroups per CU), scans their
+// degrees in LDS and walks the union of their arcs with unit stride (arcs
+// already sampled are visited again and join nothing new).  With a dominant root D (counters
 // [kCntGiant] >= 0) a vertex whose root is D offers nothing and the others
 // offer every remaining arc; without one, an arc is hooked from its larger
 // end only.  Also counts the vertices whose first arc stays in their 8192-id
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(kGhSampleThreads) void k_gh_giant(int64_t n, const 
 // device-scope release.
 template <class OffT>
 __global__ __launch_bounds__(kGhThreads) void k_gh_sweep(int64_t n, const OffT *__restrict__ off,
-                                                         const int32_t *__restrict__ cols, int K,
+                                                         const int32_t *__restrict__ cols,
                                                          const uint8_t *__restrict__ vmask,
                                                          int32_t *cc, int32_t *tu, int32_t *tv,
                                                          int32_t *head, int32_t *next,
@@ -148,7 +155,7 @@ __global__ __launch_bounds__(kGhThreads) void k_gh_sweep(int64_t n, const OffT *
     if (v < n && !(vmask && vmask[v])) {
       const OffT b = off[v], e = off[v + 1];
       if (e > b) locals += (cols[b] >> kGhTileShift) == (int32_t)(v >> kGhTileShift);
-      beg = b + (OffT)K;
+      beg = b;
       if (e > beg && !(giant >= 0 && find_root((int32_t)v, cc) == giant)) deg = (int)(e - beg);
     }
     s_beg[t] = beg;
@@ -249,15 +256,15 @@ rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f) {
   const unsigned grid = gh_grid(ctx, grid_for(n, kGhThreads), 2);
   if (g->offset_bytes == 4)
     hipLaunchKernelGGL(k_gh_sweep<int32_t>, dim3(grid), dim3(kGhThreads), 0, ctx->stream, n,
-                       (const int32_t *)g->offsets, g->cols, K, f.vmask, f.cc, f.tu, f.tv, f.head,
+                       (const int32_t *)g->offsets, g->cols, f.vmask, f.cc, f.tu, f.tv, f.head,
                        f.next, f.counters);
   else
     hipLaunchKernelGGL(k_gh_sweep<int64_t>, dim3(grid), dim3(kGhThreads), 0, ctx->stream, n,
-                       (const int64_t *)g->offsets, g->cols, K, f.vmask, f.cc, f.tu, f.tv, f.head,
+                       (const int64_t *)g->offsets, g->cols, f.vmask, f.cc, f.tu, f.tv, f.head,
                        f.next, f.counters);
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_HOOK_GLOBAL, 1);
-  return enqueue_l2_invalidate(ctx);
+  return RST_OK;
 }
 
 rst_status enqueue_locality_probe(rst_ctx *ctx, const rst_csr *g, const uint8_t *vmask,

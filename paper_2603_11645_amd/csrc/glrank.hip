@@ -13,8 +13,10 @@
 // by an atomic counter) so offsets fit 8 bits.  Each ruler leaves one 64-bit
 // word (next ruler or -1 : 32, hops to it : 32) -- a weighted list of about
 // A/k words, ranked the same way at the next level (64-bit words, weighted
-// offsets), until the list fits one workgroup, which ranks it in LDS by
-// pointer jumping.  Each level's codes then become distances to the tail
+// offsets, a new ruler opened after kGlUpperCap words: a level's kernel takes
+// as long as its longest piece, and above level 1 each walk has a whole
+// thread to itself), until the list fits one workgroup, which ranks it in LDS
+// by pointer jumping.  Each level's codes then become distances to the tail
 // (ruler distance less the offset), from the top level down; the consumer of
 // level 1 (the parent rule, or the plain distances) does the last expansion
 // on the fly.
@@ -41,20 +43,21 @@ constexpr int kGlFinalThreads = 1024;
 constexpr int kGlFinalPer = 16;
 constexpr int kGlFinal = kGlFinalThreads * kGlFinalPer;  // words ranked in LDS by one workgroup
 constexpr int64_t kGlHeadCap = (int64_t)1 << 20;          // list heads (trees) handled
+constexpr int kGlUpperCap = 63;                           // words per piece above level 1
 constexpr uint64_t kGlHole = 0x00000000fffffffeull;       // (next -2, w 0): a word of no list
 
 __device__ __forceinline__ uint64_t gl_pack(int32_t next, uint32_t w) {
   return ((uint64_t)w << 32) | (uint32_t)next;
 }
 
-// Words of level `level` (1 = the arcs): level 2 holds the strided rulers,
-// the heads and the opened rulers of level 1; every later level the strided
-// rulers and the heads of the one below.
+// Words of level `level` (1 = the arcs): every level above the first holds
+// the strided rulers, the heads and the opened rulers of the one below
+// (dyn1: rulers opened at level 1; lvl[l]: at level l >= 2).
 __device__ __forceinline__ int64_t gl_words(int level, int64_t A, int k1, int k, int64_t H,
-                                            int64_t dyn) {
+                                            int64_t dyn1, const int32_t *lvl) {
   int64_t N = A;
-  if (level >= 2) N = (A + k1 - 1) / k1 + H + dyn;
-  for (int l = 3; l <= level; ++l) N = (N + k - 1) / k + H;
+  if (level >= 2) N = (A + k1 - 1) / k1 + H + dyn1;
+  for (int l = 3; l <= level; ++l) N = (N + k - 1) / k + H + lvl[l - 1];
   return N;
 }
 
@@ -127,21 +130,22 @@ __global__ __launch_bounds__(kGlThreads) void k_glist_heads(int64_t A, const uin
 // Ruler q < Rs starts at word q*k; ruler Rs + j at heads_in[j] (when that word
 // is strided it is already ruler h/k: the head's slot is left a hole, and the
 // head list of the next level names h/k); further rulers are opened by walks
-// (level 1 only).  Each ruler's word of the next level goes to rw_out[ruler].
+// that reach the piece cap.  Each ruler's word of the next level goes to
+// rw_out[ruler].
 template <bool kL1>
 __global__ __launch_bounds__(kGlThreads) void k_gwalk(int level, int64_t A, int k1, int k,
                                                       void *words, const int32_t *heads_in,
                                                       int32_t *heads_out, uint64_t *rw_out,
                                                       int64_t rw_cap, int64_t hcap,
-                                                      int32_t *counters) {
+                                                      int32_t *counters, int32_t *lvl) {
   if (counters[kCntGOverflow]) return;
   const int64_t H = counters[kCntGHeads];
   if (H > hcap) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&counters[kCntGOverflow], 1);
     return;
   }
-  const int64_t N = gl_words(level, A, k1, k, H, counters[kCntGDyn]);
-  const int kk = kL1 ? k1 : k;            // a power of two
+  const int64_t N = gl_words(level, A, k1, k, H, counters[kCntGDyn], lvl);
+  const int kk = level == 1 ? k1 : k;    // a power of two
   const int ksh = __builtin_ctz((unsigned)kk);
   const int32_t kmask = kk - 1;
   const int64_t Rs = (N + kk - 1) >> ksh;
@@ -151,6 +155,8 @@ __global__ __launch_bounds__(kGlThreads) void k_gwalk(int level, int64_t A, int 
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&counters[kCntGOverflow], 1);
     return;
   }
+  // rulers opened by this level's walks are numbered from R0 on
+  int32_t *dyn = level == 1 ? &counters[kCntGDyn] : &lvl[level];
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < R0; q += stride) {
     int64_t e;
@@ -178,7 +184,7 @@ __global__ __launch_bounds__(kGlThreads) void k_gwalk(int level, int64_t A, int 
         if ((s & kmask) == 0) { rw_out[rid] = gl_pack(s >> ksh, off + 1); break; }
         if (off == (uint32_t)kGlCap) {
           // open a ruler at s: the piece so far ends there
-          const int64_t nr = R0 + atomicAdd(&counters[kCntGDyn], 1);
+          const int64_t nr = R0 + atomicAdd(dyn, 1);
           if (nr >= limit) {
             atomicOr(&counters[kCntGOverflow], 1);
             rw_out[rid] = gl_pack(-1, off + 1);
@@ -194,17 +200,34 @@ __global__ __launch_bounds__(kGlThreads) void k_gwalk(int level, int64_t A, int 
         s = w[e];
       }
     } else {
+      // 64-bit words (next, weight); codes (offset << 32 | ruler)
       uint64_t *w = reinterpret_cast<uint64_t *>(words);
       uint64_t cur = w[e];
       if (cur == kGlHole) { rw_out[rid] = kGlHole; continue; }
       uint32_t off = 0;
+      int len = 0;
+      // level 1 in this form (weighted arcs) keeps the level-1 cap
+      const int cap = level == 1 ? kGlCap : kGlUpperCap;
       while (true) {
         const int32_t nx = (int32_t)(uint32_t)cur;
         const uint32_t wt = (uint32_t)(cur >> 32);
         w[e] = ((uint64_t)off << 32) | (uint32_t)rid;
         if (nx < 0 || nx >= N || ++steps > N) { rw_out[rid] = gl_pack(-1, off + wt); break; }
         if ((nx & kmask) == 0) { rw_out[rid] = gl_pack(nx >> ksh, off + wt); break; }
-        off += wt;
+        if (++len == cap) {
+          const int64_t nr = R0 + atomicAdd(dyn, 1);
+          if (nr >= limit) {
+            atomicOr(&counters[kCntGOverflow], 1);
+            rw_out[rid] = gl_pack(-1, off + wt);
+            break;
+          }
+          rw_out[rid] = gl_pack((int32_t)nr, off + wt);
+          rid = nr;
+          off = 0;
+          len = 0;
+        } else {
+          off += wt;
+        }
         e = nx;
         cur = w[e];
       }
@@ -222,12 +245,13 @@ __global__ __launch_bounds__(kGlThreads) void k_gwalk(int level, int64_t A, int 
 // the same workgroup: every version of a word read there is a true (next, w)
 // pair, so a read of a word its owner is rewriting only speeds the jump up.
 __global__ __launch_bounds__(kGlFinalThreads) void k_gfinal(int level, int64_t A, int k1, int k,
-                                                            uint64_t *words, int32_t *counters) {
+                                                            uint64_t *words, int32_t *counters,
+                                                            const int32_t *lvl) {
   __shared__ uint64_t s_w[kGlFinal];
   __shared__ int s_more[3];
   if (counters[kCntGOverflow]) return;
   const int64_t H = counters[kCntGHeads];
-  const int64_t N = gl_words(level, A, k1, k, H, counters[kCntGDyn]);
+  const int64_t N = gl_words(level, A, k1, k, H, counters[kCntGDyn], lvl);
   const int tid = threadIdx.x;
   if (tid == 0) {
     counters[kCntGTopWords] = (int32_t)N;
@@ -307,9 +331,10 @@ __global__ __launch_bounds__(kGlFinalThreads) void k_gfinal(int level, int64_t A
 __global__ __launch_bounds__(kGlThreads) void k_gexpand(int level, int64_t A, int k1, int k,
                                                         uint64_t *words, const uint64_t *__restrict__ rw,
                                                         int64_t rw_cap,
-                                                        const int32_t *__restrict__ counters) {
+                                                        const int32_t *__restrict__ counters,
+                                                        const int32_t *__restrict__ lvl) {
   if (counters[kCntGOverflow]) return;
-  const int64_t N = gl_words(level, A, k1, k, counters[kCntGHeads], counters[kCntGDyn]);
+  const int64_t N = gl_words(level, A, k1, k, counters[kCntGHeads], counters[kCntGDyn], lvl);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < N; j += stride) {
     const uint64_t c = words[j];
@@ -399,7 +424,7 @@ GlistPlan glist_plan(int64_t A, int64_t max_heads, int k1) {
   p.cap[0] = 0;
   while (true) {
     const int kk = L == 1 ? p.k1 : p.k;
-    const int64_t dynb = L == 1 ? A / kGlCap + 1 : 0;
+    const int64_t dynb = bound / (L == 1 ? kGlCap : kGlUpperCap) + 1;   // opened rulers
     const int64_t next_bound = (bound + kk - 1) / kk + dynb;
     // ruler words of level L (= words of level L + 1)
     p.cap[L] = next_bound + 2 * p.hcap + 2;
@@ -412,7 +437,7 @@ GlistPlan glist_plan(int64_t A, int64_t max_heads, int k1) {
 }
 
 size_t glist_ws_bytes(const GlistPlan &p) {
-  size_t b = 2 * ws_bytes((size_t)p.hcap, 4);
+  size_t b = 2 * ws_bytes((size_t)p.hcap, 4) + ws_bytes(2 * kGlMaxLevels, 4);
   for (int L = 1; L < p.levels; ++L) b += ws_bytes((size_t)p.cap[L], 8);
   return b;
 }
@@ -421,6 +446,7 @@ void glist_take(rst_ctx *ctx, const GlistPlan &p, GlistBufs &g) {
   g.plan = p;
   g.heads[0] = ws_take<int32_t>(ctx, (size_t)p.hcap);
   g.heads[1] = ws_take<int32_t>(ctx, (size_t)p.hcap);
+  g.lvl = ws_take<int32_t>(ctx, 2 * kGlMaxLevels);
   for (int L = 1; L < p.levels; ++L) g.rw[L] = ws_take<uint64_t>(ctx, (size_t)p.cap[L]);
 }
 
@@ -460,6 +486,7 @@ rst_status enqueue_glist_from_succ(rst_ctx *ctx, int64_t A, const int32_t *succ,
 rst_status enqueue_glist_rank(rst_ctx *ctx, void *w1, bool w1_wide, GlistBufs &g,
                               int32_t *counters) {
   const GlistPlan &p = g.plan;
+  RST_TRY(enqueue_fill(ctx, g.lvl, 2 * kGlMaxLevels, 0));   // rulers opened per level
   // walks, bottom up
   for (int L = 1; L < p.levels; ++L) {
     void *words = L == 1 ? w1 : static_cast<void *>(g.rw[L - 1]);
@@ -472,27 +499,28 @@ rst_status enqueue_glist_rank(rst_ctx *ctx, void *w1, bool w1_wide, GlistBufs &g
       if (w1_wide)   // 64-bit (successor, weight) words at level 1 as well
         hipLaunchKernelGGL(k_gwalk<false>, dim3(grid), dim3(kGlThreads), 0, ctx->stream, L, p.A,
                            p.k1, p.k1, words, g.heads[0], g.heads[1], g.rw[1], p.cap[1], p.hcap,
-                           counters);
+                           counters, g.lvl);
       else
         hipLaunchKernelGGL(k_gwalk<true>, dim3(grid), dim3(kGlThreads), 0, ctx->stream, L, p.A,
                            p.k1, p.k, words, g.heads[0], g.heads[1], g.rw[1], p.cap[1], p.hcap,
-                           counters);
+                           counters, g.lvl);
       RST_HIP(hipGetLastError());
       RST_KMARK(ctx, RST_KERNEL_RANK_WALK, 1);
     } else {
       hipLaunchKernelGGL(k_gwalk<false>, dim3(grid), dim3(kGlThreads), 0, ctx->stream, L, p.A,
                          p.k1, p.k, words, g.heads[(L - 1) & 1], g.heads[L & 1], g.rw[L], p.cap[L],
-                         p.hcap, counters);
+                         p.hcap, counters, g.lvl);
       RST_HIP(hipGetLastError());
     }
   }
   // the top level, then the codes of each level below it, top down
   hipLaunchKernelGGL(k_gfinal, dim3(1), dim3(kGlFinalThreads), 0, ctx->stream, p.levels, p.A, p.k1,
-                     p.k, g.rw[p.levels - 1], counters);
+                     p.k, g.rw[p.levels - 1], counters, g.lvl);
   RST_HIP(hipGetLastError());
   for (int L = p.levels - 1; L >= 2; --L) {
     hipLaunchKernelGGL(k_gexpand, dim3(gl_grid(ctx, p.cap[L - 1])), dim3(kGlThreads), 0,
-                       ctx->stream, L, p.A, p.k1, p.k, g.rw[L - 1], g.rw[L], p.cap[L], counters);
+                       ctx->stream, L, p.A, p.k1, p.k, g.rw[L - 1], g.rw[L], p.cap[L], counters,
+                       g.lvl);
     RST_HIP(hipGetLastError());
   }
   return RST_OK;

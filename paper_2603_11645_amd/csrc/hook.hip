@@ -61,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_validate(int64_t n, int64_t nnz,
 
 __global__ void k_iota(int32_t *p, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = (int32_t)i;
+  if (i < count) store_agent(&p[i], (int32_t)i);
 }
 
 // ---------------------------------------------------------------------------
@@ -449,7 +449,7 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
     eb[j2] = -1;
     if (i < cnt) {
       const int m = -lp[r[j2]] - 1;
-      cc[v0 + i] = (int32_t)(v0 + m);
+      store_agent(&cc[v0 + i], (int32_t)(v0 + m));
       ea[j2] = eu[i];
       eb[j2] = ev[i];
       tu[v0 + i] = ea[j2] >= 0 ? (int32_t)(v0 + ea[j2]) : -1;
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
     const int i = tid + j2 * kTileThreads;
     if (i < cnt) {
       const int h = lhead[i];
-      head[v0 + i] = h >= 0 ? arc0 + h : -1;
+      store_agent(&head[v0 + i], h >= 0 ? arc0 + h : -1);
       const int n0 = lnext[2 * i], n1 = lnext[2 * i + 1];
       reinterpret_cast<int2 *>(next)[v0 + i] =
           make_int2(n0 >= 0 ? arc0 + n0 : -1, n1 >= 0 ? arc0 + n1 : -1);
@@ -826,7 +826,7 @@ __global__ __launch_bounds__(kTileThreads) void k_cross_lds(const int64_t *__res
     const int32_t key = keys[hi];
     const int32_t root = keys[lds_find_rec(hi, par)];
     const int2 e = edge_at(g);
-    cc[key] = root;
+    store_agent(&cc[key], root);
     tu[key] = e.x;
     tv[key] = e.y;
     if (head) link_slot(key, e.x, e.y, head, next);
@@ -880,24 +880,6 @@ __global__ __launch_bounds__(kTileThreads) void k_late_hooks(
     hooked = true;
   }
   if (hooked) block_release_device();   // block-uniform: only blocks that hooked
-}
-
-// Drops every line of every XCD's L2 (an agent-scope acquire by one wave of
-// each workgroup; workgroups are dealt to the XCDs in turn, so a grid of one
-// workgroup per CU reaches all of them).  Runs once after the last hooking
-// kernel: the hooks were made by compare-and-swap and list heads changed by
-// exchanges, which update memory beyond the L2 of the XCD that issued them,
-// while a line of those arrays that another XCD read during hooking could
-// still sit in its L2; the kernels after hooking read labels and list heads
-// with plain loads.
-__global__ __launch_bounds__(64) void k_l2_invalidate() {
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-rst_status enqueue_l2_invalidate(rst_ctx *ctx) {
-  hipLaunchKernelGGL(k_l2_invalidate, dim3(ctx->num_cus), dim3(64), 0, ctx->stream);
-  RST_HIP(hipGetLastError());
-  return RST_OK;
 }
 
 // Edge-list hooking without recording (labels of a given forest).
@@ -1092,7 +1074,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
                               chunks, chunk_cap, f));
   }
   RST_HIP(hipGetLastError());
-  return enqueue_l2_invalidate(ctx);
+  return RST_OK;
 }
 
 rst_status enqueue_hook_coo(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *eu,
@@ -1103,7 +1085,6 @@ rst_status enqueue_hook_coo(rst_ctx *ctx, int64_t n, int64_t t, const int32_t *e
     hipLaunchKernelGGL(k_hook_coo, dim3(grid_for(t, kBlock)), dim3(kBlock), 0, ctx->stream, t, n,
                        eu, ev, cc, counters);
     RST_HIP(hipGetLastError());
-    RST_TRY(enqueue_l2_invalidate(ctx));
   }
   return RST_OK;
 }

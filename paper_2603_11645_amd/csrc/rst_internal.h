@@ -192,9 +192,6 @@ rst_status enqueue_fill(rst_ctx *ctx, int32_t *p, int64_t count, int32_t value);
 // counters[0..31] = 0, counters[32] = root (the one-root buffer that follows them)
 rst_status enqueue_reset_counters(rst_ctx *ctx, int32_t *counters, int32_t root);
 rst_status enqueue_validate(rst_ctx *ctx, const rst_csr *g, int32_t *counters);
-// one small launch that drops every line of every XCD's L2 (run after hooking,
-// before plain loads of the labels and list heads that atomics changed)
-rst_status enqueue_l2_invalidate(rst_ctx *ctx);
 // cross: int2 [hook_cross_capacity], tile_cross: int32 [hook_tile_words], 8-byte aligned
 rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64_t *chunks,
                             int64_t chunk_cap, int2 *cross, int32_t *tile_cross);
@@ -299,6 +296,7 @@ struct GlistPlan {
 struct GlistBufs {
   GlistPlan plan;
   int32_t *heads[2] = {nullptr, nullptr};   // list heads per level (alternating)
+  int32_t *lvl = nullptr;                   // [2 kGlMaxLevels]: rulers opened per level
   uint64_t *rw[kGlMaxLevels] = {};          // rw[L]: ruler words of level L
 };
 // max_heads: an upper bound on the number of lists (capped internally)

@@ -7,17 +7,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "device_common.h"
+
 namespace rst {
 
 // Root of x with path halving.  Invariant cc[y] <= y (equality iff y is a root)
-// makes the walk strictly decreasing, so it ends even on stale reads; the plain
-// stores only ever replace a non-root's pointer by one of its ancestors.
+// makes the walk strictly decreasing, so it ends even on stale reads; the
+// stores (agent scope, see store_agent) only ever replace a non-root's pointer
+// by one of its ancestors.
 __device__ __forceinline__ int32_t find_root(int32_t x, int32_t *cc) {
   int32_t cur = cc[x];
   if (cur != x) {
     int32_t prev = x, nxt;
     while (cur > (nxt = cc[cur])) {
-      cc[prev] = nxt;
+      store_agent(&cc[prev], nxt);
       prev = cur;
       cur = nxt;
     }

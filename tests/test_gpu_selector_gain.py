@@ -4,8 +4,9 @@ The shipped network (selector_weights.bin, trained on the GPU by the library's
 own kernels on graphs of seed 1000) chooses BFS or GConn+Euler for each graph
 of a third family sample (seed 3000, disjoint from training and evaluation).
 Both methods are timed standalone on every graph (median of 3 after a
-warm-up): the selector's total time must be clearly below always running
-GConn+Euler (the fallback) and close to the per-graph best.  The single-graph
+warm-up): the selector must save at least half of what choosing the faster
+method with hindsight saves over always running GConn+Euler (the fallback),
+and stay within 10% of the per-graph best.  The single-graph
 entry point with RST_AUTO must follow the same choice and return verified
 trees.
 """
@@ -49,8 +50,11 @@ def test_selector_gain_over_always_gconn(ctx):
     res = S.evaluate(ctx, norm, params, ds)
     print(res)
     assert res["chose_bfs"] > 0
-    # clearly less time than the method without the selector ...
-    assert res["gain_vs_always_gconn"] > 0.1 * res["ms_always_gconn"], res
+    # less time than the method without the selector: at least half of what
+    # choosing with hindsight would save ...
+    available = res["ms_always_gconn"] - res["ms_best"]
+    assert available > 0, res
+    assert res["gain_vs_always_gconn"] >= 0.5 * available, res
     # ... and close to choosing the faster method with hindsight
     assert res["regret_vs_best"] <= 0.1 * res["ms_best"], res
 
