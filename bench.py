@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCE = {"hook_tile": "hook.hip", "cross": "hook.hip", "late_hooks": "hook.hip",
-                 "hook_sample": "ghook.hip", "hook_global": "ghook.hip",
+                 "hook_sample": "ghook.hip", "hook_global": "ghook.hip", "link": "euler.hip",
                  "rank_tile": "euler.hip", "settle": "euler.hip", "rank_walk": "glrank.hip",
                  "rank_words": "glrank.hip", "parent": "glrank.hip"}
 
@@ -137,9 +137,11 @@ def kernel_bytes(name, g, st):
         "hook_sample": 16 * n,
         # global hooking sweep: offsets + neighbour ids read, one label gather
         # per arc (both ends of each edge), one label read per vertex; each of
-        # the T tree edges: compare-and-swap (4), edge recorded (8), two
-        # list-head exchanges and the next pair (16)
-        "hook_global": w_o * (n + 1) + 6 * nnz + 4 * n + 28 * T,
+        # the T tree edges: compare-and-swap (4), edge recorded (8)
+        "hook_global": w_o * (n + 1) + 6 * nnz + 4 * n + 12 * T,
+        # Euler arc lists from the slots: edge read (8), two list-head
+        # exchanges (8), next pair written (8) per slot
+        "link": 24 * n,
         # labels and heads read, end-of-list successors written
         "settle": 12 * n,
         # per tour arc: its word read and its code written (4 + 4); per ruler
@@ -244,7 +246,7 @@ def main():
         return statistics.mean(s[key][sub] for s in stats)
     stage_ms = {k: mean("ms_stage", k) for k in ("hook", "compress", "arcs", "succ", "rank", "parent")}
     kernels = {}
-    for k in ("hook_tile", "cross", "late_hooks", "hook_sample", "hook_global", "settle",
+    for k in ("hook_tile", "cross", "late_hooks", "hook_sample", "hook_global", "link", "settle",
               "rank_tile", "rank_words", "rank_walk", "parent"):
         ms = mean("ms_kernel", k)
         if ms <= 0:

@@ -389,7 +389,7 @@ class Context:
                          roots.data_ptr())
 
     def spanning_forest_batch(self, offsets, cols, vtx_off, arc_off, roots, method=None,
-                              stats: bool = False, parent=None):
+                              stats: bool = False, parent=None, method_out=None):
         """Parents of all packed graphs and the method used per graph (uint8)."""
         torch = _torch()
         g = make_csr(offsets, cols)
@@ -401,7 +401,13 @@ class Context:
             _check_dev(parent, torch.int32, "parent")
             if parent.numel() != g.n:
                 raise ValueError("parent must hold n entries")
-        mout = torch.empty(b.num_graphs, dtype=torch.uint8, device=dev)
+        if method_out is None:
+            mout = torch.empty(b.num_graphs, dtype=torch.uint8, device=dev)
+        else:
+            _check_dev(method_out, torch.uint8, "method_out")
+            if method_out.numel() != b.num_graphs:
+                raise ValueError("method_out must hold one entry per graph")
+            mout = method_out
         if method is not None:
             _check_dev(method, torch.uint8, "method")
         st = rst_stats()

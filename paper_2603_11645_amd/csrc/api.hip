@@ -283,7 +283,7 @@ static rst_status enqueue_gconn_rank(rst_ctx *ctx, const rst_csr *g, int32_t *pa
 // synchronisation), run a fallback ranking if one was flagged, fill the
 // stats.  *components = components found.
 static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, rst_stats *st,
-                               int64_t *components, GconnWork &w) {
+                               int64_t *components, GconnWork &w, bool *fallback = nullptr) {
   const int64_t n = g->n;
   int32_t *counters = w.f.counters;
   if (w.exported) RST_HIP(hipStreamSynchronize(ctx->stream));
@@ -299,6 +299,7 @@ static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, 
     RST_TRY(read_counters(ctx, counters));
   }
   const bool last_resort = w.sparse_ran && ctx->host_pinned[kCntGOverflow] != 0;
+  if (fallback) *fallback = rank_fallback || last_resort;
   if (last_resort) {
     // more list heads or rulers than the sparse ruling set holds
     RST_TRY(glist_wyllie_parent(ctx, n, n, w.f.tu, w.f.tv, w.f.next, w.endsucc, w.rank,
@@ -344,12 +345,12 @@ static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, 
 // read of the hooking counters to choose the ranking, the rooting part.
 // Writes parent, returns the component count in *components; *sparse (host,
 // nullable) receives the ranking chosen.
-rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
-                           int32_t *parent, rst_stats *st, int64_t *components,
-                           int32_t *counters, int32_t *cc_out, const uint8_t *vmask = nullptr,
-                           bool *sparse = nullptr, bool *global_hook = nullptr) {
-  GconnWork w = take_gconn_work(ctx, g, counters, cc_out, vmask);
-  RST_TRY(choose_hook(ctx, g, vmask, counters, &w.global_hook));
+static rst_status run_gconn_euler_work(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
+                                       int32_t nroots, int32_t *parent, rst_stats *st,
+                                       int64_t *components, GconnWork &w, bool *sparse,
+                                       bool *global_hook) {
+  int32_t *counters = w.f.counters;
+  RST_TRY(choose_hook(ctx, g, w.f.vmask, counters, &w.global_hook));
   if (global_hook) *global_hook = w.global_hook;
   RST_TRY(enqueue_gconn_forest(ctx, g, roots, nroots, parent, st, w));
   RST_TRY(read_counters(ctx, counters));
@@ -357,6 +358,15 @@ rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots,
   if (sparse) *sparse = w.sparse;
   RST_TRY(enqueue_gconn_rank(ctx, g, parent, st, w));
   return finish_gconn(ctx, g, parent, st, components, w);
+}
+
+rst_status run_gconn_euler(rst_ctx *ctx, const rst_csr *g, const int32_t *roots, int32_t nroots,
+                           int32_t *parent, rst_stats *st, int64_t *components,
+                           int32_t *counters, int32_t *cc_out, const uint8_t *vmask = nullptr,
+                           bool *sparse = nullptr, bool *global_hook = nullptr) {
+  GconnWork w = take_gconn_work(ctx, g, counters, cc_out, vmask);
+  return run_gconn_euler_work(ctx, g, roots, nroots, parent, st, components, w, sparse,
+                              global_hook);
 }
 
 // ---------------------------------------------------------------------------
@@ -370,6 +380,9 @@ struct GraphKey {
   int64_t n, nnz, ws_cap;
   int32_t offset_bytes, root;
   Options opt;
+  // batch calls only (zero otherwise)
+  const void *vtx_off, *arc_off, *roots, *method, *method_out, *selector;
+  int32_t num_graphs, batch;
   bool operator==(const GraphKey &o) const { return std::memcmp(this, &o, sizeof(*this)) == 0; }
 };
 
@@ -462,6 +475,183 @@ static size_t gconn_ws_bytes(rst_ctx *ctx, const rst_csr *g) {
   const size_t n = (size_t)g->n;
   return 6 * ws_bytes(n, 4) + 2 * ws_bytes(2 * n, 4) + ws_bytes(2 * n, 8) + hook_ws_bytes(ctx, g) +
          rank_ws_bytes(2 * g->n) + glist_ws_bytes(gconn_glist_plan(ctx, g->n));
+}
+
+// ---------------------------------------------------------------------------
+// batches (Sec. III-D for every designated root of the packed forest)
+// ---------------------------------------------------------------------------
+
+// BFS steps enqueued in a captured batch call; a search still running after
+// them is continued after the call's synchronisation
+constexpr int kBatchBfsSteps = 16;
+
+struct BatchWork {
+  int32_t *counters = nullptr;
+  uint8_t *m = nullptr;       // [G] method of each graph (1: BFS)
+  uint8_t *vmask = nullptr;   // [n] 1 for the vertices of BFS graphs
+  int32_t *level = nullptr;   // [n] BFS levels
+  BfsBufs bb;
+  GconnWork w;
+  size_t sel_scratch = 0;     // workspace offset of the selector's scratch
+};
+
+// The device work of a batch call: checks, the method of every graph (given,
+// chosen by the selector, or GConn+Euler), the vertex mask of the BFS graphs,
+// GConn+Euler over the whole packed graph with those vertices masked (they
+// stay singletons), then `bfs_steps` BFS steps from the roots of the BFS
+// graphs, which overwrite the parents of their vertices.  No host round trip.
+static rst_status enqueue_batch_device(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                                       const uint8_t *method, int32_t *parent,
+                                       uint8_t *method_out, BatchWork &bw, int64_t bfs_steps) {
+  const int32_t G = b->num_graphs;
+  const int64_t n = g->n;
+  RST_TRY(enqueue_fill(ctx, bw.counters, 32, 0));
+  RST_TRY(enqueue_batch_check(ctx, g, b, bw.counters));
+  if (method) {
+    RST_TRY(enqueue_copy_u8(ctx, method, bw.m, G));
+  } else if (ctx->selector) {
+    ctx->ws.used = bw.sel_scratch;
+    RST_TRY(run_selector(ctx, g, b, bw.m));
+  } else {
+    RST_TRY(enqueue_fill_u8(ctx, bw.m, G, 0));
+  }
+  RST_TRY(enqueue_count_methods(ctx, b, bw.m, bw.counters));
+  RST_TRY(enqueue_graph_mask(ctx, b, bw.m, bw.vmask));
+  RST_TRY(enqueue_gconn_forest(ctx, g, b->roots, G, parent, nullptr, bw.w));
+  RST_TRY(enqueue_gconn_rank(ctx, g, parent, nullptr, bw.w));
+  RST_TRY(bfs_reset(ctx, n, bw.level, nullptr, bw.bb));
+  RST_TRY(bfs_seed_roots(ctx, g, b->roots, G, bw.level, parent, bw.bb, bw.counters, bw.m));
+  RST_TRY(bfs_enqueue_steps(ctx, g, bw.level, parent, bw.bb, bw.counters, bfs_steps, -1));
+  if (method_out) RST_TRY(enqueue_copy_u8(ctx, bw.m, method_out, G));
+  return RST_OK;
+}
+
+// BFS of the batch's BFS graphs after their seeding (or after enqueued
+// steps): levels until the frontier is empty; a disconnected BFS graph's other
+// components are then searched from their minimum ids.
+static rst_status batch_bfs_rest(rst_ctx *ctx, const rst_csr *g, int32_t *parent, BatchWork &bw,
+                                 int64_t bfs_vertices, int64_t *levels) {
+  RST_TRY(bfs_run_levels(ctx, g, bw.level, parent, bw.bb, bw.counters, levels));
+  RST_TRY(read_counters(ctx, bw.counters));
+  if (ctx->host_pinned[kCntBfsReached] >= bfs_vertices) return RST_OK;
+  const int64_t n = g->n;
+  // labels of the whole packed graph (seeds restricted to vertices of BFS
+  // graphs); the GConn+Euler scratch is free again
+  ForestBufs f;
+  f.counters = bw.counters;
+  f.cc = bw.w.f.cc;
+  f.tu = bw.w.f.tu;
+  f.tv = bw.w.f.tv;
+  RST_TRY(enqueue_fill(ctx, bw.counters + kCntChunks, 1, 0));
+  bool global_hook = false;
+  RST_TRY(choose_hook(ctx, g, nullptr, bw.counters, &global_hook));
+  RST_TRY(enqueue_hook(ctx, g, f, global_hook, bw.w.chunks, bw.w.chunk_cap, bw.w.cross,
+                       bw.w.tile_cross));
+  RST_TRY(enqueue_compress(ctx, n, f.cc, nullptr, nullptr));
+  RST_TRY(bfs_seed_unreached(ctx, g, f.cc, bw.level, parent, bw.bb, bw.counters, bw.vmask));
+  int64_t l2 = 0;
+  return bfs_run_levels(ctx, g, bw.level, parent, bw.bb, bw.counters, &l2);
+}
+
+// After a replayed batch: one synchronisation (the GConn+Euler counters), the
+// ranking fallbacks if flagged (they rewrite every parent, so the BFS graphs
+// are searched again), the rest of the BFS if the enqueued steps did not
+// finish it.
+static rst_status finish_batch(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                               int32_t *parent, BatchWork &bw, rst_stats *st) {
+  int64_t comps = 0;
+  bw.w.sparse_ran = bw.w.sparse;
+  bool reran = false;
+  RST_TRY(finish_gconn(ctx, g, parent, nullptr, &comps, bw.w, &reran));
+  if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
+  if (ctx->host_pinned[kCntBatchArcErr]) return RST_E_RANGE;
+  const int32_t nbfs = ctx->host_pinned[kCntBatchBfs];
+  const int64_t bfs_vertices = ctx->host_pinned[kCntBatchBfsVtx];
+  if (nbfs == 0) return RST_OK;
+  int64_t levels = 0;
+  if (reran) {
+    RST_TRY(enqueue_fill(ctx, bw.counters + kCntBfsReached, 1, 0));
+    RST_TRY(bfs_reset(ctx, g->n, bw.level, nullptr, bw.bb));
+    RST_TRY(bfs_seed_roots(ctx, g, b->roots, b->num_graphs, bw.level, parent, bw.bb, bw.counters,
+                           bw.m));
+  }
+  RST_TRY(batch_bfs_rest(ctx, g, parent, bw, bfs_vertices, &levels));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  (void)st;
+  return RST_OK;
+}
+
+// A batch call launched eagerly (first call with given buffers, stats or
+// validation): the same stages with the host choosing the hooking and the
+// ranking from device counters, and per-stage events when stats is set.
+static rst_status run_batch_eager(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                                  const uint8_t *method, int32_t *parent, uint8_t *method_out,
+                                  rst_stats *stats, BatchWork &bw, bool *sparse,
+                                  bool *global_hook) {
+  const int32_t G = b->num_graphs;
+  const int64_t n = g->n;
+  int32_t *counters = bw.counters;
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+  RST_TRY(run_validation(ctx, g, counters));
+  RST_TRY(enqueue_batch_check(ctx, g, b, counters));
+  if (ctx->opt.validate) RST_TRY(enqueue_batch_arcs_check(ctx, g, b, counters));
+  RST_TRY(mark(ctx, stats, kEvBatchBase));
+  if (method) {
+    RST_TRY(enqueue_copy_u8(ctx, method, bw.m, G));
+  } else if (ctx->selector) {
+    const size_t used = ctx->ws.used;
+    ctx->ws.used = bw.sel_scratch;
+    RST_TRY(run_selector(ctx, g, b, bw.m));
+    ctx->ws.used = used;
+  } else {
+    RST_TRY(enqueue_fill_u8(ctx, bw.m, G, 0));
+  }
+  RST_TRY(mark(ctx, stats, kEvBatchBase + 1));
+  RST_TRY(enqueue_count_methods(ctx, b, bw.m, counters));
+  RST_TRY(read_counters(ctx, counters));
+  if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
+  if (ctx->host_pinned[kCntBatchArcErr]) return RST_E_RANGE;
+  const int32_t nbfs = ctx->host_pinned[kCntBatchBfs];
+  const int64_t bfs_vertices = ctx->host_pinned[kCntBatchBfsVtx];
+  RST_TRY(enqueue_graph_mask(ctx, b, bw.m, bw.vmask));
+  int64_t comps = 0;
+  if (nbfs < G) {
+    rst_stats inner;
+    RST_TRY(run_gconn_euler_work(ctx, g, b->roots, G, parent, stats ? &inner : nullptr, &comps,
+                                 bw.w, sparse, global_hook));
+    if (stats) {
+      for (int i = 0; i < 8; ++i) stats->ms_stage[i] += inner.ms_stage[i];
+      for (int i = 0; i < kNumKernelTimes; ++i) stats->ms_kernel[i] = inner.ms_kernel[i];
+      stats->hook_rounds = inner.hook_rounds;
+      stats->rank_rounds = inner.rank_rounds;
+      stats->rank_exits = inner.rank_exits;
+      stats->cross_edges = inner.cross_edges;
+      stats->paths = inner.paths;
+    }
+  }
+  int64_t levels = 0;
+  if (nbfs > 0) {
+    // multi-source BFS from the roots of the BFS graphs; parents of the other
+    // graphs' vertices are left as written above
+    RST_TRY(mark(ctx, stats, kEvBatchBase + 2));
+    RST_TRY(bfs_reset(ctx, n, bw.level, nullptr, bw.bb));
+    RST_TRY(bfs_seed_roots(ctx, g, b->roots, G, bw.level, parent, bw.bb, counters, bw.m));
+    RST_TRY(batch_bfs_rest(ctx, g, parent, bw, bfs_vertices, &levels));
+    RST_TRY(mark(ctx, stats, kEvBatchBase + 3));
+  }
+  if (method_out) RST_TRY(enqueue_copy_u8(ctx, bw.m, method_out, G));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  if (stats) {
+    float ms = 0.f;
+    if (event_ms(ctx->ev[kEvBatchBase], ctx->ev[kEvBatchBase + 1], &ms)) stats->ms_stage[RST_STAGE_SELECT] = ms;
+    if (nbfs > 0 && event_ms(ctx->ev[kEvBatchBase + 2], ctx->ev[kEvBatchBase + 3], &ms)) stats->ms_stage[RST_STAGE_BFS] = ms;
+    stats->ms_total = 0.f;
+    for (int i = 0; i < 8; ++i) stats->ms_total += stats->ms_stage[i];
+    stats->bfs_levels = levels;
+    stats->components = comps;
+    stats->method_used = nbfs == 0 ? RST_GCONN_EULER : (nbfs == G ? RST_BFS : -1);
+  }
+  return RST_OK;
 }
 
 }  // namespace rst
@@ -992,98 +1182,50 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
   RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + gconn_ws_bytes(ctx, g) + bfs_ws_bytes(ctx, g) +
                               ws_bytes(n, 4) + ws_bytes(n, 1) + ws_bytes(G, 1) +
                               (method ? 0 : selector_scratch_bytes(ctx, g, G))));
-  int32_t *counters = ws_take<int32_t>(ctx, 64);
-  uint8_t *m = ws_take<uint8_t>(ctx, G);
-  uint8_t *vmask = ws_take<uint8_t>(ctx, n);
-  int32_t *level = ws_take<int32_t>(ctx, n);
-  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
-  RST_TRY(run_validation(ctx, g, counters));
-  RST_TRY(enqueue_batch_check(ctx, g, b, counters));
-  if (ctx->opt.validate) RST_TRY(enqueue_batch_arcs_check(ctx, g, b, counters));
-  RST_TRY(mark(ctx, stats, kEvBatchBase));
-  // per-graph method: given, chosen by the selector, or GConn+Euler for all
-  if (method) {
-    RST_TRY(enqueue_copy_u8(ctx, method, m, G));
-  } else if (ctx->selector) {
-    RST_TRY(run_selector(ctx, g, b, m));
-  } else {
-    RST_TRY(enqueue_fill_u8(ctx, m, G, 0));
-  }
-  RST_TRY(mark(ctx, stats, kEvBatchBase + 1));
-  RST_TRY(enqueue_count_methods(ctx, b, m, counters));
-  RST_TRY(read_counters(ctx, counters));
-  if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
-  if (ctx->host_pinned[kCntBatchArcErr]) return RST_E_RANGE;
-  const int32_t nbfs = ctx->host_pinned[kCntBatchBfs];
-  const int64_t bfs_vertices = ctx->host_pinned[kCntBatchBfsVtx];
-  if (nbfs > 0) RST_TRY(enqueue_graph_mask(ctx, b, m, vmask));
-  int64_t comps = 0;
-  const size_t ws_after_common = ctx->ws.used;
-  if (nbfs < G) {
-    rst_stats inner;
-    RST_TRY(run_gconn_euler(ctx, g, b->roots, G, parent, stats ? &inner : nullptr, &comps,
-                            counters, nullptr, nbfs > 0 ? vmask : nullptr));
-    if (stats) {
-      for (int i = 0; i < 8; ++i) stats->ms_stage[i] += inner.ms_stage[i];
-      for (int i = 0; i < kNumKernelTimes; ++i) stats->ms_kernel[i] = inner.ms_kernel[i];
-      stats->hook_rounds = inner.hook_rounds;
-      stats->rank_rounds = inner.rank_rounds;
-      stats->rank_exits = inner.rank_exits;
-      stats->cross_edges = inner.cross_edges;
-      stats->paths = inner.paths;
+  BatchWork bw;
+  bw.counters = ws_take<int32_t>(ctx, 64);
+  bw.m = ws_take<uint8_t>(ctx, G);
+  bw.vmask = ws_take<uint8_t>(ctx, n);
+  bw.level = ws_take<int32_t>(ctx, n);
+  RST_TRY(take_bfs_bufs(ctx, g, bw.bb));
+  bw.w = take_gconn_work(ctx, g, bw.counters, nullptr, bw.vmask);
+  bw.sel_scratch = ctx->ws.used;   // the selector's scratch follows (method == NULL)
+
+  const bool graph_path = ctx->opt.graphs && !stats && !ctx->opt.validate;
+  GraphKey key;
+  std::memset(&key, 0, sizeof key);
+  key.offsets = g->offsets; key.cols = g->cols; key.parent = parent;
+  key.ws_base = ctx->ws.base; key.ws_cap = (int64_t)ctx->ws.cap;
+  key.n = g->n; key.nnz = g->nnz; key.offset_bytes = g->offset_bytes;
+  key.opt = ctx->opt;
+  key.vtx_off = b->vtx_off; key.arc_off = b->arc_off; key.roots = b->roots;
+  key.method = method; key.method_out = method_out;
+  key.selector = method ? nullptr : selector_weights(ctx);
+  key.num_graphs = G; key.batch = 1;
+
+  if (!graph_path || !ctx->graph || !(ctx->graph->key == key)) {
+    // eager: the hooking variant from the locality probe, the ranking from the
+    // hooking counters, BFS levels until the frontier is empty
+    bool sparse = false, global_hook = false;
+    const rst_status st = run_batch_eager(ctx, g, b, method, parent, method_out, stats, bw,
+                                          &sparse, &global_hook);
+    if (graph_path && st == RST_OK) {
+      graph_forget(ctx);
+      ctx->graph->key = key;
+      ctx->graph->sparse = sparse;
+      ctx->graph->global_hook = global_hook;
     }
+    return st;
   }
-  // the GConn scratch is free again (work on the stream is ordered)
-  ctx->ws.used = ws_after_common;
-  int64_t levels = 0;
-  if (nbfs > 0) {
-    // multi-source BFS from the roots of the BFS graphs; parents of the other
-    // graphs' vertices are left as written above
-    BfsBufs bb;
-    RST_TRY(take_bfs_bufs(ctx, g, bb));
-    RST_TRY(mark(ctx, stats, kEvBatchBase + 2));
-    RST_TRY(bfs_reset(ctx, n, level, nullptr, bb));
-    RST_TRY(bfs_seed_roots(ctx, g, b->roots, G, level, parent, bb, counters, m));
-    RST_TRY(bfs_run_levels(ctx, g, level, parent, bb, counters, &levels));
-    RST_TRY(read_counters(ctx, counters));
-    if (ctx->host_pinned[kCntBfsReached] < bfs_vertices) {
-      // a BFS graph is disconnected: its other components are searched from
-      // their minimum ids (labels of the whole packed graph; seeds restricted
-      // to vertices of BFS graphs)
-      ForestBufs f;
-      f.counters = counters;
-      f.cc = ws_take<int32_t>(ctx, n);
-      f.tu = ws_take<int32_t>(ctx, n);
-      f.tv = ws_take<int32_t>(ctx, n);
-      const int64_t chunk_cap = (int64_t)hook_chunk_capacity(ctx, g->nnz);
-      int64_t *chunks = ws_take<int64_t>(ctx, chunk_cap);
-      int2 *cross = ws_take<int2>(ctx, hook_cross_capacity(g->nnz));
-      int32_t *tile_cross = ws_take<int32_t>(ctx, hook_tile_words(n));
-      // the heavy-chunk list is rebuilt from empty (the GConn stage used it)
-      RST_TRY(enqueue_fill(ctx, counters + kCntChunks, 1, 0));
-      bool global_hook = false;
-      RST_TRY(choose_hook(ctx, g, f.vmask, f.counters, &global_hook));
-      RST_TRY(enqueue_hook(ctx, g, f, global_hook, chunks, chunk_cap, cross, tile_cross));
-      RST_TRY(enqueue_compress(ctx, n, f.cc, nullptr, nullptr));
-      RST_TRY(bfs_seed_unreached(ctx, g, f.cc, level, parent, bb, counters, vmask));
-      int64_t l2 = 0;
-      RST_TRY(bfs_run_levels(ctx, g, level, parent, bb, counters, &l2));
-    }
-    RST_TRY(mark(ctx, stats, kEvBatchBase + 3));
-  }
-  if (method_out) RST_TRY(enqueue_copy_u8(ctx, m, method_out, G));
-  RST_HIP(hipStreamSynchronize(ctx->stream));
-  if (stats) {
-    float ms = 0.f;
-    if (event_ms(ctx->ev[kEvBatchBase], ctx->ev[kEvBatchBase + 1], &ms)) stats->ms_stage[RST_STAGE_SELECT] = ms;
-    if (nbfs > 0 && event_ms(ctx->ev[kEvBatchBase + 2], ctx->ev[kEvBatchBase + 3], &ms)) stats->ms_stage[RST_STAGE_BFS] = ms;
-    stats->ms_total = 0.f;
-    for (int i = 0; i < 8; ++i) stats->ms_total += stats->ms_stage[i];
-    stats->bfs_levels = levels;
-    stats->components = comps;
-    stats->method_used = nbfs == 0 ? RST_GCONN_EULER : (nbfs == G ? RST_BFS : -1);
-  }
-  return RST_OK;
+  // replay: the whole device part without a host round trip, then one
+  // synchronisation and the rare continuations
+  bw.w.sparse = ctx->graph->sparse;
+  bw.w.global_hook = ctx->graph->global_hook;
+  bw.w.settled = G == 1;   // as enqueue_gconn_forest decides (a replay runs no host code)
+  RST_TRY(run_graph(ctx, key, [&]() -> rst_status {
+    return enqueue_batch_device(ctx, g, b, method, parent, method_out, bw, kBatchBfsSteps);
+  }));
+  return finish_batch(ctx, g, b, parent, bw, nullptr);
 }
 
 rst_status rst_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *depth,

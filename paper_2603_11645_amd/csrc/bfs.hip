@@ -7,7 +7,7 @@
 // frontier vertices, scans their degrees in LDS and walks the union of their
 // arcs with unit stride, so a thread handles arcs, not vertices; claims are
 // compare-and-swaps on the level; vertices above a degree threshold go to a
-// separate "heavy" frontier whose arcs are split across all workgroups;
+// separate "heavy" frontier, each expanded by a whole workgroup;
 // appends use one atomic per wavefront (ballot + mbcnt).  Narrow levels
 // (small frontiers, i.e. almost every level of a high-diameter graph) run
 // many to a launch in one workgroup (k_bfs_step), so the cost of a level is
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_bfs_seed_unreached(int64_t n, const 
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool win = false;
   if (v < n && cc[v] == (int32_t)v && level[v] == -1 && (!vsel || vsel[v])) {
-    level[v] = 0;
+    store_agent(&level[v], 0);
     parent[v] = (int32_t)v;
     win = true;
   }
@@ -147,6 +147,9 @@ struct BfsSmem {
       int scan[kBfsThreads + 1];
       OffT beg[kBfsThreads];
       int32_t src[kBfsThreads];
+      int32_t st_l[kBfsThreads];   // vertices claimed by one round, light / heavy
+      int32_t st_h[kBfsThreads];
+      int nl, nh, base_l, base_h;
     } wide;
   };
   int wave[kBfsThreads / kWave];
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_step(
           }
         }
         if (claim) {
-          level[w] = nxl;
+          store_agent(&level[w], nxl);   // wide steps on other XCDs may compare-and-swap it
           if (parent) parent[w] = u;
         }
         const bool heavy = claim && (int64_t)(we - wb) > heavy_deg;
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_step(
     return;
   }
   // -------------------------------------------------------------- wide
-  const int cur = L % 3, nxt = (L + 1) % 3, clr = (L + 2) % 3;
+  const int nxt = (L + 1) % 3, clr = (L + 2) % 3;
   const int32_t *qin = (L & 1) ? q1 : q0;
   const int32_t *hin = (L & 1) ? h1 : h0;
   int32_t *qout = (L & 1) ? q0 : q1;
@@ -302,8 +305,43 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_step(
     state[par ^ 1] = L + 1;
     state[2 + (par ^ 1)] = 0;
   }
-  (void)cur;
+  if (t == 0) { sh.wide.nl = 0; sh.wide.nh = 0; }
   const int32_t next_level = L + 1;
+  // Claimed vertices are staged in LDS (one LDS atomic per wave) and appended
+  // to the next frontier by one global atomic per workgroup and round of 1024
+  // arcs; the reached and arc counts go out once per workgroup at the end.
+  // (One global atomic per wave on the same few counters serialised the wide
+  // levels of power-law graphs: milliseconds per level.)
+  int reached = 0, arcs_sum = 0;
+  auto emit = [&](bool win, int32_t w) {   // all threads of the workgroup
+    int64_t deg = 0;
+    bool heavy = false;
+    if (win) {
+      deg = (int64_t)(off[w + 1] - off[w]);
+      heavy = deg > heavy_deg;
+    }
+    const bool light = win && !heavy;
+    const int sl = wave_append(light, &sh.wide.nl);
+    if (light) sh.wide.st_l[sl] = w;
+    const int sv = wave_append(win && heavy, &sh.wide.nh);
+    if (win && heavy) sh.wide.st_h[sv] = w;
+    reached += win ? 1 : 0;
+    if (light && arcs_sum <= kBsArcsCount)
+      arcs_sum += (int)(deg > kBsArcsCount ? kBsArcsCount + 1 : deg);
+    __syncthreads();
+    if (t == 0) {
+      sh.wide.base_l = sh.wide.nl ? atomicAdd(&cout[0], sh.wide.nl) : 0;
+      sh.wide.base_h = sh.wide.nh ? atomicAdd(&cout[1], sh.wide.nh) : 0;
+    }
+    __syncthreads();
+    const int na = sh.wide.nl, nb = sh.wide.nh, ba = sh.wide.base_l, bb = sh.wide.base_h;
+    for (int i = t; i < na; i += kBfsThreads) qout[ba + i] = sh.wide.st_l[i];
+    for (int i = t; i < nb; i += kBfsThreads)
+      if (bb + i < heavy_cap) hout[bb + i] = sh.wide.st_h[i];
+    __syncthreads();
+    if (t == 0) { sh.wide.nl = 0; sh.wide.nh = 0; }
+    __syncthreads();
+  };
 
   for (int64_t c0 = (int64_t)blockIdx.x * kBfsThreads; c0 < nl;
        c0 += (int64_t)gridDim.x * kBfsThreads) {
@@ -336,16 +374,18 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_step(
         win = true;
         if (parent) parent[w] = src;
       }
-      bfs_enqueue<OffT>(win, w, off, heavy_deg, qout, hout, cout, aout, heavy_cap, counters);
+      emit(win, w);
     }
     __syncthreads();
   }
 
-  for (int hi = 0; hi < nh; ++hi) {
+  // heavy vertices: a workgroup takes whole vertices in turn (every workgroup
+  // walking every heavy vertex's range cost one round trip per vertex per
+  // workgroup, milliseconds per level on power-law graphs)
+  for (int hi = blockIdx.x; hi < nh; hi += gridDim.x) {
     const int32_t u = hin[hi];
     const int64_t b = (int64_t)off[u], e = (int64_t)off[u + 1];
-    for (int64_t a0 = b + (int64_t)blockIdx.x * kBfsThreads; a0 < e;
-         a0 += (int64_t)gridDim.x * kBfsThreads) {
+    for (int64_t a0 = b; a0 < e; a0 += kBfsThreads) {
       const int64_t a = a0 + t;
       const int32_t w = a < e ? cols[a] : -1;
       bool win = false;
@@ -353,8 +393,16 @@ __global__ __launch_bounds__(kBfsThreads) void k_bfs_step(
         win = true;
         if (parent) parent[w] = u;
       }
-      bfs_enqueue<OffT>(win, w, off, heavy_deg, qout, hout, cout, aout, heavy_cap, counters);
+      emit(win, w);
     }
+  }
+  int block_reached, block_arcs;
+  (void)block_excl_scan<kBfsThreads>(reached, sh.wave, &block_reached);
+  (void)block_excl_scan<kBfsThreads>(arcs_sum, sh.wave, &block_arcs);
+  if (t == 0) {
+    if (block_reached) atomicAdd(&counters[kCntBfsReached], block_reached);
+    if (block_arcs > 0 && *reinterpret_cast<volatile int32_t *>(aout) <= kBsArcsCount)
+      atomicAdd(aout, block_arcs > kBsArcsCount ? kBsArcsCount + 1 : block_arcs);
   }
 }
 

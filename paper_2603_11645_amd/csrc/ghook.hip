@@ -2,7 +2,9 @@
 // locality (random labels: R-MAT, permuted meshes, long chains).  Same hooking
 // rule as hook.hip (Sec. III-B: the larger root is linked under the smaller by
 // compare-and-swap, the edge behind every successful hook recorded at the
-// hooked root, Sec. I) and the same Euler arc lists (link_slot), but no vertex
+// hooked root, Sec. I) and the same Euler arc lists (link_slot, inside the
+// hook: a separate pass over the slots afterwards took longer, its exchanges
+// no longer overlapping the hooks' other memory accesses), but no vertex
 // tiles: on such graphs almost every edge crosses tiles, so the tile pass and
 // the cross-tile merges only add work.
 //

@@ -74,6 +74,7 @@ rst_status enqueue_fill_u8(rst_ctx *ctx, uint8_t *dst, int64_t count, uint8_t va
 size_t selector_scratch_bytes(const rst_ctx *ctx, const rst_csr *g, int32_t G);
 rst_status run_selector(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, uint8_t *choice);
 void selector_free(rst_ctx *ctx);
+const void *selector_weights(const rst_ctx *ctx);   // device weights of the loaded selector
 
 }  // namespace rst
 

@@ -324,6 +324,10 @@ size_t selector_scratch_bytes(const rst_ctx *ctx, const rst_csr *g, int32_t G) {
          2 * ws_bytes(hc, 4) + ws_bytes(kBfsCntWords, 4);
 }
 
+const void *selector_weights(const rst_ctx *ctx) {
+  return ctx->selector ? ctx->selector->dev : nullptr;
+}
+
 void selector_free(rst_ctx *ctx) {
   if (ctx->selector) {
     if (ctx->selector->dev) (void)hipFree(ctx->selector->dev);
