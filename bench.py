@@ -137,8 +137,9 @@ def kernel_bytes(name, g, st):
         "hook_sample": 16 * n,
         # global hooking sweep: offsets + neighbour ids read, one label gather
         # per arc (both ends of each edge), one label read per vertex; each of
-        # the T tree edges: compare-and-swap (4), edge recorded (8)
-        "hook_global": w_o * (n + 1) + 6 * nnz + 4 * n + 12 * T,
+        # the T tree edges: compare-and-swap (4), edge recorded (8), two
+        # list-head exchanges and the next pair (16)
+        "hook_global": w_o * (n + 1) + 6 * nnz + 4 * n + 28 * T,
         # Euler arc lists from the slots: edge read (8), two list-head
         # exchanges (8), next pair written (8) per slot
         "link": 24 * n,

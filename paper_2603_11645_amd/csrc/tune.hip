@@ -66,7 +66,10 @@ static std::vector<Knob> knobs_for(rst_method method) {
     return {{RST_OPT_BFS_LEVELS_PER_SYNC, {4, 8, 16, 32, 64, 128}},
             {RST_OPT_BFS_GRID, {0, 512, 1024, 2048, 4096}},
             {RST_OPT_BFS_HEAVY_DEGREE, {256, 1024, 4096, 16384}}};
-  return {{RST_OPT_SWEEP_BLOCK, {64, 128, 256, 512, 1024}},
+  // hooking variant and its sampling first: they decide which kernels run
+  return {{RST_OPT_HOOK_MODE, {1, 2}},
+          {RST_OPT_HOOK_SAMPLE, {-1, 0, 1, 2, 3}},
+          {RST_OPT_SWEEP_BLOCK, {64, 128, 256, 512, 1024}},
           {RST_OPT_HEAVY_DEGREE, {256, 1024, 4096, 16384}},
           {RST_OPT_RANK_ELEMS_PER_THREAD, {1, 2, 4, 8}},
           {RST_OPT_RANK_STRIDE, {4, 8, 16, 32, 64}}};
