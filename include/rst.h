@@ -214,6 +214,18 @@ rst_status rst_spanning_tree(rst_ctx *ctx, const rst_csr *g, int32_t root, rst_m
 rst_status rst_components(rst_ctx *ctx, const rst_csr *g, int32_t *label,
                           int64_t *num_components);
 
+/* Component labels as rst_components, allocating nothing: for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Hooking always runs the global
+ * sweep (RST_OPT_HOOK_MODE is ignored).  Its scratch is one fixed 128 MiB
+ * device array per GPU, held from the first context on that GPU until the
+ * process ends, so n <= 16,777,184 and nnz < 2^31 are required (else
+ * RST_E_INVAL, nothing is run).  Every call on a GPU uses that GPU's array and
+ * clears what must start at zero: calls that overlap on one GPU race.
+ * label: device int32 [n]; num_components: host, nullable.  Synchronous. */
+rst_status rst_components_noalloc(rst_ctx *ctx, const rst_csr *g, int32_t *label,
+                                  int64_t *num_components);
+
 /* The connectivity stage alone (Sec. III-B with the spanning-edge marking of
  * Sec. I): label as in rst_components, and for every vertex x that stopped being
  * a component root, the graph edge (tu[x], tv[x]) whose hook made it a non-root;

@@ -57,7 +57,8 @@ STAGES = ["hook", "compress", "arcs", "succ", "rank", "parent", "bfs", "select"]
 # symbols the header declares (checked by the CPU test-suite)
 EXPORTS = [
     "rst_create", "rst_destroy", "rst_set_stream", "rst_set_option", "rst_spanning_tree",
-    "rst_components", "rst_spanning_forest", "rst_bfs", "rst_root_forest", "rst_list_rank",
+    "rst_components", "rst_components_noalloc", "rst_spanning_forest", "rst_bfs",
+    "rst_root_forest", "rst_list_rank",
     "rst_spanning_forest_batch", "rst_selector_load", "rst_status_string", "rst_features",
     "rst_feature_stats", "rst_mlp_forward", "rst_mlp_train_step", "rst_get_option",
     "rst_verify", "rst_autotune", "rst_tune_save", "rst_tune_load", "rst_tree_depth",
@@ -144,6 +145,7 @@ def load_library(path: Optional[str] = None):
             "rst_spanning_tree": (S, [P, ctypes.POINTER(rst_csr), i32, ctypes.c_int, P,
                                       ctypes.POINTER(rst_stats)]),
             "rst_components": (S, [P, ctypes.POINTER(rst_csr), P, ctypes.POINTER(i64)]),
+            "rst_components_noalloc": (S, [P, ctypes.POINTER(rst_csr), P, ctypes.POINTER(i64)]),
             "rst_spanning_forest": (S, [P, ctypes.POINTER(rst_csr), P, P, P, ctypes.POINTER(i64)]),
             "rst_bfs": (S, [P, ctypes.POINTER(rst_csr), i32, P, P, ctypes.POINTER(rst_stats)]),
             "rst_root_forest": (S, [P, i64, i64, P, P, P, i32, P]),
@@ -316,6 +318,19 @@ class Context:
         _check_dev(label, torch.int32, "label")
         k = ctypes.c_int64(0)
         self._call("rst_components", ctypes.byref(g), ctypes.c_void_p(label.data_ptr()),
+                   ctypes.byref(k))
+        return label, int(k.value)
+
+    def components_noalloc(self, offsets, cols, label=None):
+        """rst_components_noalloc: the labels without device allocation by the
+        library (label must be given or is allocated here, by torch)."""
+        torch = _torch()
+        g = make_csr(offsets, cols)
+        if label is None:
+            label = torch.empty(g.n, dtype=torch.int32, device=offsets.device)
+        _check_dev(label, torch.int32, "label")
+        k = ctypes.c_int64(0)
+        self._call("rst_components_noalloc", ctypes.byref(g), ctypes.c_void_p(label.data_ptr()),
                    ctypes.byref(k))
         return label, int(k.value)
 

@@ -670,6 +670,11 @@ rst_status rst_create(rst_ctx **out, int device, void *hip_stream) {
   if (!ctx) return RST_E_NOMEM;
   ctx->device = device;
   ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  // the allocation-free entry point's scratch address on this device
+  if (noalloc_init(device) != RST_OK) {
+    delete ctx;
+    return RST_E_DEVICE;
+  }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       cus > 0)

@@ -347,6 +347,12 @@ rst_status run_pr_rst(rst_ctx *ctx, const rst_csr *g, int32_t root, int32_t *par
 // int32 [n] scratch.
 rst_status enqueue_verify(rst_ctx *ctx, const rst_csr *g, int32_t root, const int32_t *label,
                           const int32_t *parent, int32_t *anc0, int32_t *anc1, int32_t *vc);
+// noalloc.hip: device address of the file-scope scratch of
+// rst_components_noalloc, taken once per device (rst_create); the largest n
+// that scratch holds
+rst_status noalloc_init(int device);
+int64_t noalloc_max_vertices();
+
 // tune.hip
 void tune_free(rst_ctx *ctx);
 // api.hip
