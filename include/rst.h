@@ -287,8 +287,10 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
 /* ---- learned BFS / GConn+Euler selector (per graph of a batch) ------------
  * Features of graph g, feat[g*8 + k]: log n, log(1 + m), mean degree,
  * log(1 + degree variance), log(1 + max degree), and for probes s = 0, 1, 2
- * log2(1 + depth reached by a BFS capped at 64 levels) from the source
- * vtx_off[g] + (the (3g + s + 1)-th output of the splitmix64 generator seeded
+ * log2(1 + d), d = the depth a BFS from the source reaches before it stops:
+ * min(eccentricity of the source, 64, the first radius whose ball -- the
+ * vertices within that many hops -- holds at least 1024 vertices); the source
+ * is vtx_off[g] + (the (3g + s + 1)-th output of the splitmix64 generator seeded
  * with 0) mod n_g (splitmix64: Steele, Lea, Flood 2014; state += 0x9E3779B97F4A7C15,
  * then the finaliser).  Degree moments use arcs of the
  * CSR; m counts each undirected edge once (arcs / 2).

@@ -16,7 +16,7 @@ import oracle as _core
 
 N_IN, N_H, N_OUT = 8, 64, 2
 N_PARAMS = N_H * N_IN + N_H + N_H * N_H + N_H + N_OUT * N_H + N_OUT
-PROBES, PROBE_LEVELS = 3, 64
+PROBES, PROBE_LEVELS, PROBE_BALL = 3, 64, 1024
 _M64 = (1 << 64) - 1
 
 
@@ -64,9 +64,21 @@ def features(offsets, cols, vtx_off):
         for s in range(PROBES):
             src = probe_source(g, s, b, n) - b
             level, _, _ = _core.bfs(n, loc_off, loc_cols, src)
-            depth = min(int(level.max()), PROBE_LEVELS)
-            out[g, 5 + s] = math.log2(1.0 + depth)
+            out[g, 5 + s] = math.log2(1.0 + probe_depth(level))
     return out
+
+
+def probe_depth(level):
+    """Depth reached by a probe, from the BFS levels of its graph (-1 where
+    unreached): the source's eccentricity, capped at PROBE_LEVELS levels and
+    at the first radius whose ball (vertices within that many hops) holds at
+    least PROBE_BALL vertices."""
+    reach = level[level >= 0]
+    ecc = int(reach.max())
+    ball = np.cumsum(np.bincount(reach, minlength=ecc + 1))
+    big = np.nonzero(ball >= PROBE_BALL)[0]
+    first_big = int(big[0]) if big.size else ecc
+    return min(ecc, PROBE_LEVELS, first_big)
 
 
 def unpack(params):

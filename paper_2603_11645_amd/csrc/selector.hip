@@ -2,9 +2,14 @@
 //
 // Features of graph g (8 values):  log n, log(1+m), mean degree,
 // log(1+variance of degree), log(1+max degree), and for three seeded sources
-// log2(1 + depth reached by a BFS capped at kProbeLevels levels).  The degree
-// moments are one segmented reduction (a block per graph); the depth probes
-// are three capped multi-source BFS runs over the packed graph.
+// log2(1 + depth reached by a capped BFS): the BFS stops at kProbeLevels
+// levels, at the source's eccentricity, or at the first level whose ball
+// (vertices within that many hops) holds kProbeBall vertices, so a probe
+// costs at most about kProbeBall vertices' arcs whatever the graph (an
+// uncapped search visits all of a low-diameter graph: three of them over a
+// 4096-graph batch took longer than its spanning forests).  The degree
+// moments are one segmented reduction (a block per graph); each probe is one
+// workgroup that keeps the visited set and the frontier in LDS.
 //
 // Network: 8 -> 64 -> 64 -> 2, ReLU, fp32, inputs z-scored with stored
 // statistics; logit 0 = GConn+Euler, logit 1 = BFS; the larger logit wins and
@@ -31,6 +36,10 @@ constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kH * kIn, kOffW2 = kOffB1 + kH,
 static_assert(kParams == 4866, "parameter layout");
 constexpr int kProbeLevels = 64;
 constexpr int kProbes = 3;
+constexpr int kProbeBall = 1024;     // a probe stops once its ball holds this many vertices
+constexpr int kProbeThreads = 256;
+constexpr int kProbeHash = 4096;     // visited set: < kProbeBall + kProbeThreads keys
+static_assert(kProbeHash >= 2 * (kProbeBall + kProbeThreads), "probe hash load");
 
 struct Selector {
   float *dev = nullptr;   // [16 + kParams]: mean[8], std[8], parameters
@@ -91,34 +100,94 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-// probe source of every graph for probe s: vtx_off[g] + (the (3g + s + 1)-th
-// output of splitmix64 seeded with 0) mod n_g
-__global__ void k_probe_sources(int32_t G, const int64_t *__restrict__ vtx_off, int s,
-                                int32_t *src) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= G) return;
+// One probe per workgroup: graph g = blockIdx.x / kProbes, probe s =
+// blockIdx.x % kProbes, source vtx_off[g] + (the (3g + s + 1)-th output of
+// splitmix64 seeded with 0) mod n_g.  Level after level the frontier's arcs
+// are walked with unit stride (degree prefix in LDS); a neighbour not yet in
+// the LDS hash set of visited vertices joins the next frontier.  The probe
+// stops at kProbeLevels levels, when the next frontier is empty, or once the
+// visited vertices number kProbeBall (the level that reached it counts).
+template <class OffT>
+__global__ __launch_bounds__(kProbeThreads) void k_probe(const OffT *__restrict__ off,
+                                                         const int32_t *__restrict__ cols,
+                                                         const int64_t *__restrict__ vtx_off,
+                                                         float *feat) {
+  __shared__ int32_t keys[kProbeHash];
+  __shared__ int32_t fr[2][kProbeBall];
+  __shared__ OffT beg[kProbeBall];
+  __shared__ int32_t sc[kProbeBall + 1];
+  __shared__ int s_wave[kProbeThreads / kWave];
+  __shared__ int s_new;
+  const int t = threadIdx.x;
+  const int g = blockIdx.x / kProbes, s = blockIdx.x % kProbes;
   const int64_t b = vtx_off[g], n = vtx_off[g + 1] - b;
-  const uint64_t h = splitmix64(((uint64_t)g * kProbes + (uint64_t)s) * 0x9E3779B97F4A7C15ull);
-  src[g] = (int32_t)(b + (n > 0 ? (int64_t)(h % (uint64_t)n) : 0));
-}
-
-// depth reached by probe s in graph g: max level over its vertices (capped)
-__global__ __launch_bounds__(kBlock) void k_probe_depth(const int64_t *__restrict__ vtx_off,
-                                                        const int32_t *__restrict__ level, int s,
-                                                        float *feat) {
-  __shared__ int s_max[kBlock];
-  const int g = blockIdx.x;
-  const int64_t b = vtx_off[g], e = vtx_off[g + 1];
-  int mx = 0;
-  for (int64_t v = b + threadIdx.x; v < e; v += kBlock) mx = level[v] > mx ? level[v] : mx;
-  s_max[threadIdx.x] = mx;
-  __syncthreads();
-  for (int o = kBlock / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o && s_max[threadIdx.x + o] > s_max[threadIdx.x])
-      s_max[threadIdx.x] = s_max[threadIdx.x + o];
+  for (int i = t; i < kProbeHash; i += kProbeThreads) keys[i] = -1;
+  int depth = 0;
+  if (n > 0) {
+    const uint64_t h = splitmix64(((uint64_t)g * kProbes + (uint64_t)s) * 0x9E3779B97F4A7C15ull);
+    const int32_t src = (int32_t)(b + (int64_t)(h % (uint64_t)n));
     __syncthreads();
+    auto insert = [&](int32_t w) -> bool {   // true if w was not in the set
+      uint32_t hh = ((uint32_t)w * 0x9E3779B1u) >> (32 - 12);
+      while (true) {
+        const int32_t old = atomicCAS(&keys[hh], -1, w);
+        if (old == -1) return true;
+        if (old == w) return false;
+        hh = (hh + 1) & (kProbeHash - 1);
+      }
+    };
+    if (t == 0) { insert(src); fr[0][0] = src; }
+    int c = 0, nf = 1, total = 1;
+    while (depth < kProbeLevels) {
+      // degree prefix of the frontier (at most kProbeBall vertices, 4 per thread)
+      int d[kProbeBall / kProbeThreads];
+      int mine = 0;
+#pragma unroll
+      for (int q = 0; q < kProbeBall / kProbeThreads; ++q) {
+        const int i = t * (kProbeBall / kProbeThreads) + q;
+        d[q] = 0;
+        if (i < nf) {
+          const int32_t u = fr[c][i];
+          const OffT bu = off[u];
+          d[q] = (int)(off[u + 1] - bu);
+          beg[i] = bu;
+        }
+        mine += d[q];
+      }
+      int arcs;
+      int run = block_excl_scan<kProbeThreads>(mine, s_wave, &arcs);
+#pragma unroll
+      for (int q = 0; q < kProbeBall / kProbeThreads; ++q) {
+        const int i = t * (kProbeBall / kProbeThreads) + q;
+        if (i < nf) sc[i] = run;
+        run += d[q];
+      }
+      if (t == 0) { sc[nf] = arcs; s_new = 0; }
+      __syncthreads();
+      for (int k0 = 0; k0 < arcs; k0 += kProbeThreads) {
+        const int k = k0 + t;
+        if (k < arcs) {
+          const int j = lds_upper_search(sc, nf, k);
+          const int32_t w = cols[beg[j] + (OffT)(k - sc[j])];
+          if (insert(w)) {
+            const int idx = atomicAdd(&s_new, 1);
+            if (idx < kProbeBall) fr[c ^ 1][idx] = w;
+          }
+        }
+        __syncthreads();
+        if (total + s_new >= kProbeBall) break;   // the ball is full: this level ends the probe
+      }
+      const int nn = s_new;
+      __syncthreads();                            // s_new, sc and beg are rewritten next level
+      if (nn == 0) break;                         // the source's eccentricity
+      ++depth;
+      total += nn;
+      if (total >= kProbeBall) break;
+      c ^= 1;
+      nf = nn;
+    }
   }
-  if (threadIdx.x == 0) feat[(int64_t)g * kIn + 5 + s] = log2f(1.0f + (float)s_max[0]);
+  if (t == 0) feat[(int64_t)g * kIn + 5 + s] = log2f(1.0f + (float)depth);
 }
 
 // ---------------------------------------------------------------------------
@@ -263,30 +332,21 @@ __global__ void k_feature_stats(int64_t B, const float *__restrict__ X, float *n
 // host side
 // ---------------------------------------------------------------------------
 
-rst_status enqueue_features(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, float *feat,
-                            int32_t *src, int32_t *level, BfsBufs &bb, int32_t *counters) {
+rst_status enqueue_features(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, float *feat) {
   const int32_t G = b->num_graphs;
-  if (g->offset_bytes == 4)
+  const unsigned probes = (unsigned)G * kProbes;
+  if (g->offset_bytes == 4) {
     hipLaunchKernelGGL(k_degree_moments<int32_t>, dim3((unsigned)G), dim3(kBlock), 0, ctx->stream,
                        (const int32_t *)g->offsets, b->vtx_off, feat);
-  else
+    hipLaunchKernelGGL(k_probe<int32_t>, dim3(probes), dim3(kProbeThreads), 0, ctx->stream,
+                       (const int32_t *)g->offsets, g->cols, b->vtx_off, feat);
+  } else {
     hipLaunchKernelGGL(k_degree_moments<int64_t>, dim3((unsigned)G), dim3(kBlock), 0, ctx->stream,
                        (const int64_t *)g->offsets, b->vtx_off, feat);
-  RST_HIP(hipGetLastError());
-  for (int s = 0; s < kProbes; ++s) {
-    hipLaunchKernelGGL(k_probe_sources, dim3(grid_for(G, kBlock)), dim3(kBlock), 0, ctx->stream, G,
-                       b->vtx_off, s, src);
-    RST_HIP(hipGetLastError());
-    RST_TRY(bfs_reset(ctx, g->n, level, nullptr, bb));
-    RST_TRY(bfs_seed_roots(ctx, g, src, G, level, nullptr, bb, counters, nullptr));
-    // every step expands at least one level: a fixed count covers the cap,
-    // with no host synchronisation (the batch call can capture it)
-    RST_TRY(bfs_enqueue_steps(ctx, g, level, nullptr, bb, counters, kProbeLevels + 2,
-                              kProbeLevels));
-    hipLaunchKernelGGL(k_probe_depth, dim3((unsigned)G), dim3(kBlock), 0, ctx->stream, b->vtx_off,
-                       level, s, feat);
-    RST_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_probe<int64_t>, dim3(probes), dim3(kProbeThreads), 0, ctx->stream,
+                       (const int64_t *)g->offsets, g->cols, b->vtx_off, feat);
   }
+  RST_HIP(hipGetLastError());
   return RST_OK;
 }
 
@@ -302,26 +362,15 @@ rst_status enqueue_mlp_forward(rst_ctx *ctx, int64_t B, const float *norm, const
 rst_status run_selector(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, uint8_t *choice) {
   const int32_t G = b->num_graphs;
   float *feat = ws_take<float>(ctx, (size_t)G * kIn);
-  int32_t *src = ws_take<int32_t>(ctx, G);
-  int32_t *level = ws_take<int32_t>(ctx, g->n);
-  int32_t *counters = ws_take<int32_t>(ctx, 64);
-  BfsBufs bb;
-  bb.heavy_cap = (int64_t)bfs_heavy_capacity(ctx, g->n, g->nnz);
-  bb.q[0] = ws_take<int32_t>(ctx, g->n);
-  bb.q[1] = ws_take<int32_t>(ctx, g->n);
-  bb.h[0] = ws_take<int32_t>(ctx, bb.heavy_cap);
-  bb.h[1] = ws_take<int32_t>(ctx, bb.heavy_cap);
-  bb.cnt = ws_take<int32_t>(ctx, kBfsCntWords);
-  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
-  RST_TRY(enqueue_features(ctx, g, b, feat, src, level, bb, counters));
+  RST_TRY(enqueue_features(ctx, g, b, feat));
   return enqueue_mlp_forward(ctx, G, ctx->selector->dev, ctx->selector->dev + 16, feat, nullptr,
                              choice);
 }
 
 size_t selector_scratch_bytes(const rst_ctx *ctx, const rst_csr *g, int32_t G) {
-  const size_t hc = bfs_heavy_capacity(ctx, g->n, g->nnz);
-  return ws_bytes((size_t)G * kIn, 4) + ws_bytes(G, 4) + 3 * ws_bytes(g->n, 4) + ws_bytes(64, 4) +
-         2 * ws_bytes(hc, 4) + ws_bytes(kBfsCntWords, 4);
+  (void)ctx;
+  (void)g;
+  return ws_bytes((size_t)G * kIn, 4);
 }
 
 const void *selector_weights(const rst_ctx *ctx) {
@@ -346,21 +395,9 @@ rst_status rst_features(rst_ctx *ctx, const rst_csr *g, const rst_batch *b, floa
   if (!ctx || !b || !feat || b->num_graphs < 1 || !b->vtx_off) return RST_E_INVAL;
   if (!g || g->n < 1 || !g->offsets || (g->offset_bytes != 4 && g->offset_bytes != 8))
     return RST_E_INVAL;
+  if (g->nnz > 0 && !g->cols) return RST_E_INVAL;
   RST_HIP(hipSetDevice(ctx->device));
-  const int32_t G = b->num_graphs;
-  RST_TRY(ws_reserve(ctx, selector_scratch_bytes(ctx, g, G)));
-  int32_t *src = ws_take<int32_t>(ctx, G);
-  int32_t *level = ws_take<int32_t>(ctx, g->n);
-  int32_t *counters = ws_take<int32_t>(ctx, 64);
-  BfsBufs bb;
-  bb.heavy_cap = (int64_t)bfs_heavy_capacity(ctx, g->n, g->nnz);
-  bb.q[0] = ws_take<int32_t>(ctx, g->n);
-  bb.q[1] = ws_take<int32_t>(ctx, g->n);
-  bb.h[0] = ws_take<int32_t>(ctx, bb.heavy_cap);
-  bb.h[1] = ws_take<int32_t>(ctx, bb.heavy_cap);
-  bb.cnt = ws_take<int32_t>(ctx, kBfsCntWords);
-  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
-  RST_TRY(enqueue_features(ctx, g, b, feat, src, level, bb, counters));
+  RST_TRY(enqueue_features(ctx, g, b, feat));
   RST_HIP(hipStreamSynchronize(ctx->stream));
   return RST_OK;
 }

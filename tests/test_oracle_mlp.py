@@ -6,6 +6,7 @@ import math
 import numpy as np
 import pytest
 
+import oracle
 from oracle import mlp as M
 from paper_2603_11645_amd import inputs as I
 
@@ -128,3 +129,32 @@ def test_features_closed_forms():
     long = I.pack([I.path(500)])
     f = M.features(long.graph.offsets, long.graph.cols, long.vtx_off)
     assert np.all(f[0, 5:] == math.log2(1 + 64))
+
+
+def test_probe_stops_at_the_ball_cap():
+    """A broom: a hub with 1500 leaves and a 100-vertex handle.  From the hub
+    the ball of radius 1 already holds 1501 >= 1024 vertices, so the probe
+    stops at depth 1 although the handle is 100 hops long; from the handle's
+    far end the ball first reaches 1024 vertices at radius 100 (the hub's
+    leaves), past the 64-level cap."""
+    hub_leaves, handle = 1500, 100
+    n = 1 + hub_leaves + handle
+    eu = np.concatenate([np.zeros(hub_leaves, np.int32),
+                         np.arange(hub_leaves + 1, n - 1, dtype=np.int32),
+                         np.array([0], np.int32)])
+    ev = np.concatenate([np.arange(1, hub_leaves + 1, dtype=np.int32),
+                         np.arange(hub_leaves + 2, n, dtype=np.int32),
+                         np.array([hub_leaves + 1], np.int32)])
+    g = I.csr_from_edges(n, eu, ev)
+    level_hub, _, _ = oracle.bfs(n, g.offsets, g.cols, 0)
+    assert int(level_hub.max()) == handle
+    assert M.probe_depth(level_hub) == 1
+    level_end, _, _ = oracle.bfs(n, g.offsets, g.cols, n - 1)
+    assert M.probe_depth(level_end) == 64
+    # a 40 x 40 grid from a corner: r + 1 vertices at distance r <= 39, so the
+    # ball of radius 39 holds 820; then 79 - r at distance r: 859, 897, 934,
+    # 970, 1005, 1039 for r = 40 .. 45, first >= 1024 at r = 45 (< 64, < 78)
+    grid = I.grid(40, 40, 0.0, seed=1)
+    level_c, _, _ = oracle.bfs(grid.n, grid.offsets, grid.cols, 0)
+    assert int(level_c.max()) == 78
+    assert M.probe_depth(level_c) == 45
