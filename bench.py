@@ -39,6 +39,9 @@ WORKLOADS = {
     "C3": "R-MAT scale 22, edge factor 16, a=.57 b=.19 c=.19, largest component (seed 3), root 0",
     "C4": "random Hamiltonian path over 2^24 vertices + 0.5% shortcuts of span <= 64 (seed 4), "
           "int64 offsets, root 0",
+    "C5": "batch of 4096 graphs, n log-uniform in [1000, 200000] (seed 5): even members 2D grids "
+          "with 10% deletions re-joined, odd members R-MAT edge factor 8 (largest component); "
+          "packed CSR with offset tables, root local 0, method per graph chosen by the selector",
 }
 
 
@@ -132,9 +135,11 @@ def kernel_bytes(name, g, st):
         # edge recorded (8), two list-head exchanges and the next pair (16)
         "late_hooks": 16 * X + 28 * (n - 1),
         # global hooking, first part: every vertex's label, edge slot and list
-        # head initialised (16 n); with sampling, per vertex its offsets and
-        # first arcs read and their two labels gathered
-        "hook_sample": 16 * n,
+        # head initialised (16 n); with K sampled arcs per vertex (K = 2 when
+        # nnz >= 6 n), per vertex its offsets (2 w_o) and per sample the arc
+        # (4) and the two labels (8) read, and, since the dominant tree forms
+        # there, every tree edge's compare-and-swap, record and list links (28)
+        "hook_sample": 16 * n + ((2 * w_o + 12 * 2) * n + 28 * T if nnz >= 6 * n else 0),
         # global hooking sweep: offsets + neighbour ids read, one label gather
         # per arc (both ends of each edge), one label read per vertex; each of
         # the T tree edges: compare-and-swap (4), edge recorded (8), two
@@ -159,6 +164,93 @@ def kernel_bytes(name, g, st):
     }.get(name)
 
 
+def run_batch(args, np, torch, rst, I):
+    """C5: one step is one call of rst_spanning_forest_batch over the packed
+    batch (selector features and inference, GConn+Euler over the GConn graphs,
+    multi-source BFS over the BFS graphs; replayed as a captured HIP graph).
+    The same batch is also timed with every graph by GConn+Euler and every
+    graph by BFS; the selector's gain is the difference to always GConn+Euler."""
+    G = args.batch_graphs
+    t0 = time.perf_counter()
+    workers = min(16, os.cpu_count() or 1)
+    b = I.uneven_batch(G, seed=5, nmin=1000, nmax=args.batch_nmax, workers=workers)
+    g = b.graph
+    log("[bench] workload C5: %d graphs, n=%d m=%d nnz=%d (generated in %.1fs, %d workers)"
+        % (G, g.n, g.m, g.nnz, time.perf_counter() - t0, workers))
+    torch.cuda.set_device(0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    args_dev = (dev(g.offsets_typed()), dev(g.cols), dev(b.vtx_off), dev(b.arc_off), dev(b.roots))
+    ctx = rst.Context(0)
+    ctx.selector_load_default()
+    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    mout = torch.empty(G, dtype=torch.uint8, device="cuda")
+    res = {}
+    for mode, method in (("selector", None), ("gconn", np.zeros(G, np.uint8)),
+                         ("bfs", np.ones(G, np.uint8))):
+        m = dev(method) if method is not None else None
+
+        def step():
+            ctx.spanning_forest_batch(*args_dev, method=m, parent=parent, method_out=mout)
+        steps = args.steps if mode == "selector" else max(1, min(args.steps, 5))
+        wall, per = timed_calls(step, steps, args.warmup, torch)
+        res[mode] = {"ms": statistics.mean(per), "median_ms": statistics.median(per),
+                     "calls": steps, "bfs_graphs": int(mout.cpu().numpy().sum())}
+        log("[bench] C5 %s: %s ms" % (mode, ", ".join("%.2f" % x for x in per)))
+        if mode == "selector":
+            sel_parent = parent.cpu().numpy()
+            sel_method = mout.cpu().numpy().copy()
+    ms = res["selector"]["ms"]
+    _, _, st = ctx.spanning_forest_batch(*args_dev, stats=True)
+    line = {
+        "metric": "RST edges/sec and ms per RST, GConn+Euler vs GPU BFS, exact-verified",
+        "value": g.m / (ms * 1e-3), "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "median_ms": round(res["selector"]["median_ms"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["C5"], "name": "C5", "graphs": G, "n": g.n, "m": g.m,
+                   "nnz": g.nnz, "offset_bytes": g.offset_bytes, "method": "selector",
+                   "parallelism": "single GPU"},
+        "ms_per_graph": round(ms / G, 6),
+        "modes": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                  for k, v in res.items()},
+        "selector_gain_ms": round(res["gconn"]["ms"] - ms, 4),
+        "stage_ms_eager": {k: round(v, 4) for k, v in st["ms_stage"].items()},
+        "paths": st["paths"],
+    }
+    checks = {}
+    if not args.no_cpu:
+        import oracle
+        oracle.build(force=False)
+        t1 = time.perf_counter()
+        code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, sel_parent, b.roots)
+        checks["forest"] = oracle.VERIFY_CODES[code]
+        log("[bench] oracle verification of the packed forest: %s (%.1fs)"
+            % (checks["forest"], time.perf_counter() - t1))
+        # the oracle on a bounded sample: the first 256 graphs, scaled to the batch
+        k = min(256, G)
+        sub = I.pack([I.batch_member(i, 5, 1000, args.batch_nmax) for i in range(k)])
+        sg = sub.graph
+        times = []
+        for i in range(3):
+            t2 = time.perf_counter()
+            label, fu, fv = oracle.uf_forest(sg.n, sg.offsets, sg.cols)
+            oracle.dfs_root(sg.n, fu, fv, sub.roots)
+            times.append(time.perf_counter() - t2)
+        t = statistics.median(times)
+        line["cpu_baseline"] = {
+            "value": sg.m / t, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "the first %d graphs of the batch (%d vertices, %d edges): sequential "
+                      "union-find forest + DFS rooting at every graph's root, median of 3; "
+                      "1 of %d host cores used" % (k, sg.n, sg.m, os.cpu_count() or 1),
+            "ms_per_batch_scaled": round(t * 1e3 * g.m / sg.m, 1)}
+    else:
+        line["cpu_baseline"] = None
+    line["verify"] = checks
+    line["verified"] = all(v == "ok" for v in checks.values()) if checks else None
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +264,8 @@ def main():
     ap.add_argument("--no-bfs", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
+    ap.add_argument("--batch-graphs", type=int, default=4096, help="C5: graphs in the batch")
+    ap.add_argument("--batch-nmax", type=int, default=200000, help="C5: largest graph size")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -186,6 +280,8 @@ def main():
     import paper_2603_11645_amd as rst
     from paper_2603_11645_amd import inputs as I
 
+    if args.workload == "C5":
+        return run_batch(args, np, torch, rst, I)
     t0 = time.perf_counter()
     g = I.config(args.workload)
     log("[bench] workload %s: n=%d m=%d nnz=%d (generated in %.1fs)"
@@ -263,8 +359,13 @@ def main():
                 "traffic": tr["bytes_per_launch"] if tr else None,
                 "traffic_GBps": round(tr["bytes_per_launch"] / (kernels[dom]["ms_per_launch"] * 1e-3)
                                       / 1e9, 1) if tr else None,
-                "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                "scaled by a plain copy's readings (profiles/traffic.json)",
+                "traffic_frac": round(tr["bytes_per_launch"] / (kernels[dom]["ms_per_launch"] * 1e-3)
+                                      / 1e9 / HBM_PEAK_GBS, 4) if tr else None,
+                "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE x%.4f + WRITE_SIZE "
+                                "x%.4f (scales from a plain 256 MiB copy's readings; "
+                                "profiles/traffic.json); achieved and frac count the algorithmic "
+                                "bytes only" % ((tr["fetch_scale"], tr["write_scale"]) if tr
+                                                else (float("nan"), float("nan"))),
                 "launch_ms": kernels[dom]["ms_per_launch"],
                 "algorithmic_bytes_per_launch": kernels[dom]["algorithmic_bytes_per_launch"]}
 

@@ -617,6 +617,7 @@ static rst_status run_batch_eager(rst_ctx *ctx, const rst_csr *g, const rst_batc
   int64_t comps = 0;
   if (nbfs < G) {
     rst_stats inner;
+    std::memset(&inner, 0, sizeof inner);
     RST_TRY(run_gconn_euler_work(ctx, g, b->roots, G, parent, stats ? &inner : nullptr, &comps,
                                  bw.w, sparse, global_hook));
     if (stats) {
