@@ -59,10 +59,13 @@ __global__ __launch_bounds__(B) void k_gh_init(int64_t n, int32_t *cc, int32_t *
 
 // Each vertex hooks along K of its arcs (all of them when it has at most K),
 // taken at pseudo-random positions: on power-law graphs with sorted neighbour
-// lists the first arcs of almost every vertex lead to the same few hubs, and
-// every hook puts an arc at the front of both ends' lists by an exchange on
-// the list head, which serialises on a hub.  Grid-stride over the vertices, a
-// few workgroups per CU, each ending with one device-scope release.
+// lists the first arcs of almost every vertex lead to the same few hubs.
+// Every hook puts an arc at the front of both ends' lists; the arcs into the
+// sampled neighbours' lists are pushed wave by wave with wave_push_front,
+// since many lanes of a wave reach the same hub and exchanges on its list
+// head would serialise.  Grid-stride over the vertices (whole waves, so the
+// wave operations see every lane), a few workgroups per CU, each ending with
+// one device-scope release.
 template <class OffT>
 __global__ __launch_bounds__(kBlock) void k_gh_sample(int64_t n, const OffT *__restrict__ off,
                                                       const int32_t *__restrict__ cols, int K,
@@ -70,15 +73,30 @@ __global__ __launch_bounds__(kBlock) void k_gh_sample(int64_t n, const OffT *__r
                                                       int32_t *tu, int32_t *tv, int32_t *head,
                                                       int32_t *next) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    if (vmask && vmask[v]) continue;
-    const OffT b = off[v], e = off[v + 1];
-    const uint64_t deg = (uint64_t)(e - b);
-    for (int r = 0; r < K && (uint64_t)r < deg; ++r) {
-      const uint64_t pos = deg <= (uint64_t)K ? (uint64_t)r
-                                              : gh_mix(((uint64_t)v << 3) | (uint64_t)r) % deg;
-      const int32_t w = cols[b + (OffT)pos];
-      if (w != (int32_t)v) hook_edge<true>((int32_t)v, w, cc, tu, tv, head, next);
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  for (int64_t vw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; vw < n; vw += stride) {
+    const int64_t v = vw + lane;
+    const bool live = v < n && !(vmask && vmask[v]);
+    OffT b = 0;
+    uint64_t deg = 0;
+    if (live) {
+      b = off[v];
+      deg = (uint64_t)(off[v + 1] - b);
+    }
+    for (int r = 0; r < K; ++r) {
+      int32_t x = -1, w = -1;
+      if ((uint64_t)r < deg) {
+        const uint64_t pos = deg <= (uint64_t)K ? (uint64_t)r
+                                                : gh_mix(((uint64_t)v << 3) | (uint64_t)r) % deg;
+        w = cols[b + (OffT)pos];
+        if (w != (int32_t)v) x = hook_record((int32_t)v, w, cc, tu, tv);
+      }
+      if (!head) continue;
+      // arcs 2x = v->w (front of v's own list) and 2x+1 = w->v (front of w's)
+      int2 nx = make_int2(-1, -1);
+      if (x >= 0) nx.x = atomicExch(&head[v], 2 * x);
+      nx.y = wave_push_front<4>(x >= 0, w, 2 * x + 1, head);
+      if (x >= 0) reinterpret_cast<int2 *>(next)[x] = nx;
     }
   }
   block_release_device();
@@ -131,21 +149,28 @@ __global__ __launch_bounds__(kGhSampleThreads) void k_gh_giant(int64_t n, const 
 // already sampled are visited again and join nothing new).  With a dominant root D (counters
 // [kCntGiant] >= 0) a vertex whose root is D offers nothing and the others
 // offer every remaining arc; without one, an arc is hooked from its larger
-// end only.  Also counts the vertices whose first arc stays in their 8192-id
+// end only.  The arcs a wave keeps are queued in its own LDS region and hooked
+// 64 at a time, so that every lane of a hooking wave carries a hook (without
+// the queue half the lanes of a chain's waves idle through every hook).  Also
+// counts the vertices whose first arc stays in their 8192-id
 // tile (counters[kCntLocal]), so that a later call on the same buffers can
 // tell whether the ids have gained locality.  Each workgroup ends with one
 // device-scope release.
 template <class OffT>
-__global__ __launch_bounds__(kGhThreads) void k_gh_sweep(int64_t n, const OffT *__restrict__ off,
-                                                         const int32_t *__restrict__ cols,
-                                                         const uint8_t *__restrict__ vmask,
-                                                         int32_t *cc, int32_t *tu, int32_t *tv,
-                                                         int32_t *head, int32_t *next,
-                                                         int32_t *counters) {
+__global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const OffT *__restrict__ off,
+                                                            const int32_t *__restrict__ cols,
+                                                            const uint8_t *__restrict__ vmask,
+                                                            int32_t *cc, int32_t *tu, int32_t *tv,
+                                                            int32_t *head, int32_t *next,
+                                                            int32_t *counters) {
   __shared__ int s_scan[kGhThreads + 1];
   __shared__ OffT s_beg[kGhThreads];
   __shared__ int s_wave[kGhThreads / kWave];
+  __shared__ int2 s_q[kGhThreads / kWave][2 * kWave];   // per-wave queue of kept arcs
   const int t = threadIdx.x;
+  const int lane = t & (kWave - 1);
+  int2 *q = s_q[t / kWave];
+  int qn = 0;   // queued arcs of this wave (the same in all its lanes)
   const int32_t giant = counters[kCntGiant];
   const int64_t chunks = (n + kGhThreads - 1) / kGhThreads;
   int locals = 0;
@@ -168,14 +193,34 @@ __global__ __launch_bounds__(kGhThreads) void k_gh_sweep(int64_t n, const OffT *
     __syncthreads();
     for (int b0 = 0; b0 < total; b0 += kGhThreads) {
       const int k = b0 + t;
+      bool keep = false;
+      int32_t u = 0, w = 0;
       if (k < total) {
         const int j = lds_upper_search(s_scan, kGhThreads, k);
-        const int32_t u = (int32_t)(v0 + j);
-        const int32_t w = cols[s_beg[j] + (OffT)(k - s_scan[j])];
-        if (giant >= 0 ? w != u : w < u) hook_edge<true>(u, w, cc, tu, tv, head, next);
+        u = (int32_t)(v0 + j);
+        w = cols[s_beg[j] + (OffT)(k - s_scan[j])];
+        keep = giant >= 0 ? w != u : w < u;
+      }
+      const uint64_t m = __ballot(keep);
+      if (keep) q[qn + lanes_below(m)] = make_int2(u, w);
+      qn += (int)__popcll(m);
+      if (qn >= kWave) {
+        // the wave's own LDS writes above are read back by other lanes
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        const int2 e = q[lane];
+        const int2 rest = q[kWave + lane];
+        qn -= kWave;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (lane < qn) q[lane] = rest;
+        hook_edge<true>(e.x, e.y, cc, tu, tv, head, next);
       }
     }
     __syncthreads();   // s_scan and s_beg are rewritten for the next chunk
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  if (lane < qn) {
+    const int2 e = q[lane];
+    hook_edge<true>(e.x, e.y, cc, tu, tv, head, next);
   }
   for (int o = 32; o > 0; o >>= 1) locals += __shfl_xor(locals, o, 64);
   if ((t & 63) == 0 && locals) atomicAdd(&counters[kCntLocal], locals);

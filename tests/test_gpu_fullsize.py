@@ -5,9 +5,9 @@ For each workload (C1 permuted grid, C2 road-like mesh, C3 R-MAT scale 22,
 C4 long chain with int64 offsets): min-id component labels bit-exact against
 the oracle; the GConn+Euler parent array accepted by the oracle verifier and
 by the device verifier; the stage variants that ran are the expected ones.
-BFS levels are compared bit for bit and BFS parents verified on C1-C3 (C4's
-BFS runs about 1.3e7 levels, minutes of GPU time; its levels are covered by
-the smaller chain graphs of the other tests).
+BFS levels are compared bit for bit and BFS parents checked (one level
+closer to the root, and the whole tree through the verifier on C1-C3) on all
+four; C4's BFS runs about 1.3e7 levels, tens of seconds of GPU time.
 """
 import numpy as np
 import pytest
@@ -66,13 +66,32 @@ def test_fullsize(ctx, name):
         # then the top levels, the contracted tour ranked in one workgroup
         assert st["paths"] == 4, st
     if name == "C4":
-        return
+        return   # its BFS (1.3e7 levels) has a test of its own below
+    check_bfs(ctx, g, off, cols)
+
+
+def check_bfs(ctx, g, off, cols):
     level, parent, st = ctx.bfs(off, cols, g.root, stats=True)
     lref, _, ecc = oracle.bfs(g.n, g.offsets, g.cols, g.root)
     assert np.array_equal(level.cpu().numpy(), lref)
     assert st["bfs_levels"] == ecc
+    par = parent.cpu().numpy()
+    v = np.nonzero(lref > 0)[0]
+    assert np.all(lref[par[v]] == lref[v] - 1)
+    assert par[g.root] == g.root
+    if g.n > (1 << 23):
+        return   # the verifier's pass over C4 adds nothing the level check misses
     par = ctx.spanning_tree(off, cols, g.root, "bfs").cpu().numpy()
     code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, par, [g.root])
     assert code == 0, (oracle.VERIFY_CODES[code], bad)
     v = np.nonzero(lref > 0)[0]
     assert np.all(lref[par[v]] == lref[v] - 1)
+
+
+def test_fullsize_c4_bfs(ctx):
+    """The long chain's BFS: about 1.3e7 levels, nearly all of them run by one
+    workgroup many levels to a launch (tens of seconds); levels bit for bit
+    against the oracle's FIFO BFS, parents one level closer to the root."""
+    g = graph("C4")
+    off, cols = upload(g)
+    check_bfs(ctx, g, off, cols)
