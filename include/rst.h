@@ -167,8 +167,8 @@ typedef enum {
                                 * HIP graph on the second and replays it while they
                                 * stay the same; 0: launch eagerly                 */
   RST_OPT_RANK_STRIDE = 8,     /* sparse ruling set (tours without id locality):
-                                * every k-th arc starts a ruler, k in 4, 8, 16
-                                * (default), 32, 64                                */
+                                * every k-th arc starts a ruler, k in 4, 8, 16, 32,
+                                * 64; 0 (default): 16, or 32 above 2^24 arcs      */
   RST_OPT_HOOK_MODE = 9,       /* hooking of GConn+Euler and rst_components: 0
                                 * (default) chooses by sampling arcs: when most
                                 * leave their source's 8192-id tile the global

@@ -751,7 +751,8 @@ rst_status rst_set_option(rst_ctx *ctx, rst_option opt, int64_t value) {
       ctx->opt.graphs = value ? 1 : 0;
       return RST_OK;
     case RST_OPT_RANK_STRIDE:
-      if (value != 4 && value != 8 && value != 16 && value != 32 && value != 64) return RST_E_INVAL;
+      if (value != 0 && value != 4 && value != 8 && value != 16 && value != 32 && value != 64)
+        return RST_E_INVAL;
       ctx->opt.rank_stride = (int)value;
       return RST_OK;
     case RST_OPT_HOOK_MODE:

@@ -96,7 +96,7 @@ __global__ __launch_bounds__(B) void k_depth_words(int64_t n, const int32_t *__r
 template <int B>
 __global__ __launch_bounds__(B) void k_depth_out(int64_t n, const int32_t *__restrict__ parent,
                                                  const uint64_t *__restrict__ w,
-                                                 const uint64_t *__restrict__ rw1, int64_t rw1_cap,
+                                                 const uint32_t *__restrict__ d1, int64_t rw1_cap,
                                                  int32_t *depth, int32_t *counters) {
   if (counters[kCntGOverflow]) return;   // block-uniform: the caller falls back
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(B) void k_depth_out(int64_t n, const int32_t *__res
     if (!depth_is_root((int32_t)x, parent[x], n)) {
       const uint64_t c = w[2 * x];
       const uint32_t rid = (uint32_t)c;
-      const uint32_t dist = rid < rw1_cap ? (uint32_t)(rw1[rid] >> 32) - (uint32_t)(c >> 32) : 0u;
+      const uint32_t dist = rid < rw1_cap ? d1[rid] - (uint32_t)(c >> 32) : 0u;
       d = -(int32_t)dist;
     }
     depth[x] = d;
@@ -150,7 +150,7 @@ rst_status run_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_
   RST_SWEEP(ctx, k_depth_words, n, n, parent, head, next, w, gl.heads[0], plan.hcap, counters);
   RST_HIP(hipGetLastError());
   RST_TRY(enqueue_glist_rank(ctx, w, true, gl, counters));
-  RST_SWEEP(ctx, k_depth_out, n, n, parent, w, gl.rw[1], plan.cap[1], depth, counters);
+  RST_SWEEP(ctx, k_depth_out, n, n, parent, w, gl.d1, plan.cap[1], depth, counters);
   RST_HIP(hipGetLastError());
   RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
                          hipMemcpyDeviceToHost, ctx->stream));

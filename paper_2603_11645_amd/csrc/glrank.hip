@@ -346,13 +346,28 @@ __global__ __launch_bounds__(kGlThreads) void k_gexpand(int level, int64_t A, in
   }
 }
 
+// The level-1 rulers' distances, once ranked, as one 32-bit word each: the
+// consumers below gather them at random (two per forest slot), and the
+// compact array stays in an XCD's L2 far longer than the 64-bit words.
+__global__ __launch_bounds__(kGlThreads) void k_gdist1(int64_t A, int k1,
+                                                       const uint64_t *__restrict__ rw1,
+                                                       int64_t rw1_cap, uint32_t *d1,
+                                                       const int32_t *__restrict__ counters) {
+  if (counters[kCntGOverflow]) return;
+  int64_t R1 = (A + k1 - 1) / k1 + counters[kCntGHeads] + counters[kCntGDyn];
+  if (R1 > rw1_cap) R1 = rw1_cap;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < R1; j += stride)
+    d1[j] = (uint32_t)(rw1[j] >> 32);
+}
+
 // distance to the tail of a level-1 arc from its code (0 for an arc no walk
 // reached, which only malformed input leaves)
-__device__ __forceinline__ uint32_t gl_arc_dist(int32_t code, const uint64_t *__restrict__ rw1,
+__device__ __forceinline__ uint32_t gl_arc_dist(int32_t code, const uint32_t *__restrict__ d1,
                                                 int64_t rw1_cap) {
   const uint32_t c = (uint32_t)code;
   if ((int64_t)(c >> kGlOffBits) >= rw1_cap) return 0u;
-  return (uint32_t)(rw1[c >> kGlOffBits] >> 32) - (c & (uint32_t)kGlCap);
+  return d1[c >> kGlOffBits] - (c & (uint32_t)kGlCap);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,7 +382,7 @@ template <int B>
 __global__ __launch_bounds__(B) void k_gparent(int64_t slots, int64_t n, const int32_t *__restrict__ tu,
                                                const int32_t *__restrict__ tv,
                                                const int32_t *__restrict__ w1,
-                                               const uint64_t *__restrict__ rw1, int64_t rw1_cap,
+                                               const uint32_t *__restrict__ d1, int64_t rw1_cap,
                                                const int32_t *__restrict__ cc,
                                                const int32_t *__restrict__ comp_root, int32_t *parent,
                                                int32_t *counters, int32_t *host_out) {
@@ -381,8 +396,8 @@ __global__ __launch_bounds__(B) void k_gparent(int64_t slots, int64_t n, const i
     if (a >= 0) {
       const int32_t b = tv[x];
       const int2 c = reinterpret_cast<const int2 *>(w1)[x];
-      const uint32_t d0 = gl_arc_dist(c.x, rw1, rw1_cap), d1 = gl_arc_dist(c.y, rw1, rw1_cap);
-      if (d0 > d1) parent[b] = a;   // a->b comes first in the tour: it descends
+      const uint32_t da = gl_arc_dist(c.x, d1, rw1_cap), db = gl_arc_dist(c.y, d1, rw1_cap);
+      if (da > db) parent[b] = a;   // a->b comes first in the tour: it descends
       else parent[a] = b;
     }
   }
@@ -396,12 +411,12 @@ __global__ __launch_bounds__(B) void k_gparent(int64_t slots, int64_t n, const i
 }
 
 __global__ __launch_bounds__(kGlThreads) void k_gdist(int64_t A, const int32_t *__restrict__ w1,
-                                                      const uint64_t *__restrict__ rw1,
+                                                      const uint32_t *__restrict__ d1,
                                                       int64_t rw1_cap, int32_t *dist,
                                                       const int32_t *__restrict__ counters) {
   if (counters[kCntGOverflow]) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < A) dist[e] = (int32_t)gl_arc_dist(w1[e], rw1, rw1_cap);
+  if (e < A) dist[e] = (int32_t)gl_arc_dist(w1[e], d1, rw1_cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -412,7 +427,12 @@ GlistPlan glist_plan(int64_t A, int64_t max_heads, int k1) {
   GlistPlan p;
   p.A = A;
   p.hcap = max_heads < kGlHeadCap ? (max_heads < 1 ? 1 : max_heads) : kGlHeadCap;
-  // level-1 stride: as asked, doubled while the ruler ids would not fit 24 bits
+  // level-1 stride: as asked (0: 16, and 32 above 2^24 arcs, which keeps the
+  // rulers' compact distances, gathered at random by the consumers, near the
+  // size of one XCD's L2: on a 2^25-arc tour stride 32 cut the parent pass
+  // 512 -> 478 us for a walk 1044 -> 1080 us; longer pieces make the walk
+  // itself slower), doubled while the ruler ids would not fit 24 bits
+  if (k1 <= 0) k1 = A > ((int64_t)1 << 24) ? 32 : 16;
   int s = 2;                         // a power of two, at least k1
   while (s < k1) s *= 2;
   while (s < 4096 && (A + s - 1) / s + A / kGlCap + p.hcap + 2 >= kGlRidLimit - 1) s *= 2;
@@ -437,7 +457,8 @@ GlistPlan glist_plan(int64_t A, int64_t max_heads, int k1) {
 }
 
 size_t glist_ws_bytes(const GlistPlan &p) {
-  size_t b = 2 * ws_bytes((size_t)p.hcap, 4) + ws_bytes(2 * kGlMaxLevels, 4);
+  size_t b = 2 * ws_bytes((size_t)p.hcap, 4) + ws_bytes(2 * kGlMaxLevels, 4) +
+             ws_bytes((size_t)p.cap[1], 4);
   for (int L = 1; L < p.levels; ++L) b += ws_bytes((size_t)p.cap[L], 8);
   return b;
 }
@@ -448,6 +469,7 @@ void glist_take(rst_ctx *ctx, const GlistPlan &p, GlistBufs &g) {
   g.heads[1] = ws_take<int32_t>(ctx, (size_t)p.hcap);
   g.lvl = ws_take<int32_t>(ctx, 2 * kGlMaxLevels);
   for (int L = 1; L < p.levels; ++L) g.rw[L] = ws_take<uint64_t>(ctx, (size_t)p.cap[L]);
+  g.d1 = ws_take<uint32_t>(ctx, (size_t)p.cap[1]);
 }
 
 static unsigned gl_grid(const rst_ctx *ctx, int64_t items) {
@@ -523,6 +545,9 @@ rst_status enqueue_glist_rank(rst_ctx *ctx, void *w1, bool w1_wide, GlistBufs &g
                        g.lvl);
     RST_HIP(hipGetLastError());
   }
+  hipLaunchKernelGGL(k_gdist1, dim3(gl_grid(ctx, p.cap[1])), dim3(kGlThreads), 0, ctx->stream,
+                     p.A, p.k1, g.rw[1], p.cap[1], g.d1, counters);
+  RST_HIP(hipGetLastError());
   return RST_OK;
 }
 
@@ -533,7 +558,7 @@ rst_status enqueue_glist_parent(rst_ctx *ctx, int64_t slots, int64_t n, const in
   const int64_t items = (cc && n > slots) ? n : slots;
   if (cc) host_out = nullptr;   // the component count is only final after this pass
   RST_KMARK(ctx, RST_KERNEL_PARENT, 0);
-  RST_SWEEP(ctx, k_gparent, items, slots, n, tu, tv, w1, g.rw[1], g.plan.cap[1], cc, comp_root,
+  RST_SWEEP(ctx, k_gparent, items, slots, n, tu, tv, w1, g.d1, g.plan.cap[1], cc, comp_root,
             parent, counters, host_out);
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_PARENT, 1);
@@ -543,7 +568,7 @@ rst_status enqueue_glist_parent(rst_ctx *ctx, int64_t slots, int64_t n, const in
 rst_status enqueue_glist_dist(rst_ctx *ctx, int64_t A, const int32_t *w1, const GlistBufs &g,
                               int32_t *dist, const int32_t *counters) {
   hipLaunchKernelGGL(k_gdist, dim3(grid_for(A, kGlThreads)), dim3(kGlThreads), 0, ctx->stream, A,
-                     w1, g.rw[1], g.plan.cap[1], dist, counters);
+                     w1, g.d1, g.plan.cap[1], dist, counters);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }

@@ -28,7 +28,8 @@ struct Options {
   int sweep_block = 256;         // threads per block of the per-vertex/per-slot sweeps
   int bfs_heavy_degree = 1024;   // BFS: frontier vertices above this are split over blocks
   int graphs = 1;                // capture the device work of a call as a HIP graph and replay it
-  int rank_stride = 16;          // sparse ruling set: every k-th arc starts a ruler
+  int rank_stride = 0;           // sparse ruling set: every k-th arc starts a ruler
+                                 // (0: 16, or 32 above 2^24 arcs)
   int hook_mode = 0;             // 0: by a locality probe, 1: vertex tiles, 2: global sweep
   int hook_sample = -1;          // global sweep: arcs each vertex hooks first (-1: by degree)
 };
@@ -299,6 +300,8 @@ struct GlistBufs {
   int32_t *heads[2] = {nullptr, nullptr};   // list heads per level (alternating)
   int32_t *lvl = nullptr;                   // [2 kGlMaxLevels]: rulers opened per level
   uint64_t *rw[kGlMaxLevels] = {};          // rw[L]: ruler words of level L
+  uint32_t *d1 = nullptr;                   // [cap[1]]: each level-1 ruler's distance
+                                            // to the tail (after the ranking)
 };
 // max_heads: an upper bound on the number of lists (capped internally)
 GlistPlan glist_plan(int64_t A, int64_t max_heads, int k1);

@@ -72,7 +72,7 @@ static std::vector<Knob> knobs_for(rst_method method) {
           {RST_OPT_SWEEP_BLOCK, {64, 128, 256, 512, 1024}},
           {RST_OPT_HEAVY_DEGREE, {256, 1024, 4096, 16384}},
           {RST_OPT_RANK_ELEMS_PER_THREAD, {1, 2, 4, 8}},
-          {RST_OPT_RANK_STRIDE, {4, 8, 16, 32, 64}}};
+          {RST_OPT_RANK_STRIDE, {0, 4, 8, 16, 32, 64}}};
 }
 
 // Device check of a candidate's output against component labels computed

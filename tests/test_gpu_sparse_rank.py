@@ -99,7 +99,7 @@ def test_every_stride(ctx, rst):
     succ = lists_from_order(rs.permutation(A).astype(np.int32), 5, rs)
     exp, _ = oracle.list_rank(succ)
     try:
-        for k in (4, 8, 16, 32, 64):
+        for k in (4, 8, 16, 32, 64, 0):
             ctx.set_option(rst.OPT_RANK_STRIDE, k)
             assert ctx.get_option(rst.OPT_RANK_STRIDE) == k
             got = ctx.list_rank(dev(succ)).cpu().numpy()
@@ -107,7 +107,7 @@ def test_every_stride(ctx, rst):
         with pytest.raises(rst.RstError):
             ctx.set_option(rst.OPT_RANK_STRIDE, 12)
     finally:
-        ctx.set_option(rst.OPT_RANK_STRIDE, 16)
+        ctx.set_option(rst.OPT_RANK_STRIDE, 0)
 
 
 @pytest.mark.parametrize("n,ntrees", [(300000, 1), (400000, 5), (250000, 3000)])

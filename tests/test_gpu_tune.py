@@ -107,7 +107,7 @@ def test_sweep_block_sizes(ctx, rst, block):
 
 CANDIDATES = {5: {64, 128, 256, 512, 1024}, 4: {256, 1024, 4096, 16384}, 3: {1, 2, 4, 8},
               1: {4, 8, 16, 32, 64, 128}, 2: {0, 512, 1024, 2048, 4096}, 6: {256, 1024, 4096, 16384},
-              8: {4, 8, 16, 32, 64}, 9: {0, 1, 2}, 10: {-1, 0, 1, 2, 3}}
+              8: {0, 4, 8, 16, 32, 64}, 9: {0, 1, 2}, 10: {-1, 0, 1, 2, 3}}
 
 
 @pytest.mark.parametrize("method,keys", [("gconn", {3, 4, 5, 8, 9, 10}), ("bfs", {1, 2, 6})])
