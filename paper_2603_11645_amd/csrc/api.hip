@@ -1187,7 +1187,7 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
   const int32_t G = b->num_graphs;
   const int64_t n = g->n;
   RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + gconn_ws_bytes(ctx, g) + bfs_ws_bytes(ctx, g) +
-                              ws_bytes(n, 4) + ws_bytes(n, 1) + ws_bytes(G, 1) +
+                              ws_bytes(n, 4) + ws_bytes(n, 1) + ws_bytes(G, 1) + ws_bytes(G, 4) +
                               (method ? 0 : selector_scratch_bytes(ctx, g, G))));
   BatchWork bw;
   bw.counters = ws_take<int32_t>(ctx, 64);
@@ -1195,7 +1195,12 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
   bw.vmask = ws_take<uint8_t>(ctx, n);
   bw.level = ws_take<int32_t>(ctx, n);
   RST_TRY(take_bfs_bufs(ctx, g, bw.bb));
+  int32_t *giants = ws_take<int32_t>(ctx, G);
   bw.w = take_gconn_work(ctx, g, bw.counters, nullptr, bw.vmask);
+  // the global sweep seeks a dominant tree in every packed graph
+  bw.w.f.vtx_off = b->vtx_off;
+  bw.w.f.num_graphs = G;
+  bw.w.f.giants = giants;
   bw.sel_scratch = ctx->ws.used;   // the selector's scratch follows (method == NULL)
 
   const bool graph_path = ctx->opt.graphs && !stats && !ctx->opt.validate;

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_gh_sample(int64_t n, const OffT *__r
         const uint64_t pos = deg <= (uint64_t)K ? (uint64_t)r
                                                 : gh_mix(((uint64_t)v << 3) | (uint64_t)r) % deg;
         w = cols[b + (OffT)pos];
-        if (w != (int32_t)v) x = hook_record((int32_t)v, w, cc, tu, tv);
+        if (w != (int32_t)v) x = hook_record<true>((int32_t)v, w, cc, tu, tv);
       }
       if (!head) continue;
       // arcs 2x = v->w (front of v's own list) and 2x+1 = w->v (front of w's)
@@ -143,13 +143,74 @@ __global__ __launch_bounds__(kGhSampleThreads) void k_gh_giant(int64_t n, const 
   }
 }
 
+// Batches: one workgroup per packed graph g finds the most frequent root among
+// up to kGhBatchSamples of its (unmasked) vertices (all of them when it has no
+// more) and writes it to giants[g] when it holds at least half of them, else
+// -1; counters[kCntGiant] becomes 0 when some graph has one.  Skipping one
+// dominant tree per graph is sound because no edge joins two packed graphs.
+constexpr int kGhBatchThreads = 256;
+constexpr int kGhBatchSamples = 1024;
+constexpr int kGhBatchHash = 2048;
+__global__ __launch_bounds__(kGhBatchThreads) void k_gh_giants(const int64_t *__restrict__ vtx_off,
+                                                               const int32_t *__restrict__ cc,
+                                                               const uint8_t *__restrict__ vmask,
+                                                               int32_t *giants, int32_t *counters) {
+  __shared__ int32_t keys[kGhBatchHash];
+  __shared__ int32_t cnts[kGhBatchHash];
+  __shared__ int s_valid;
+  __shared__ unsigned long long s_best;
+  const int t = threadIdx.x;
+  const int g = blockIdx.x;
+  const int64_t lo = vtx_off[g], ng = vtx_off[g + 1] - lo;
+  for (int i = t; i < kGhBatchHash; i += kGhBatchThreads) { keys[i] = -1; cnts[i] = 0; }
+  if (t == 0) { s_valid = 0; s_best = 0ull; }
+  __syncthreads();
+  int valid = 0;
+  for (int i = t; i < kGhBatchSamples && (int64_t)i < ng; i += kGhBatchThreads) {
+    const int64_t off = ng <= kGhBatchSamples ? (int64_t)i
+                                              : (int64_t)(gh_mix(((uint64_t)g << 20) ^ (uint64_t)i) % (uint64_t)ng);
+    const int32_t v = (int32_t)(lo + off);
+    if (vmask && vmask[v]) continue;
+    ++valid;
+    const int32_t r = gh_root(v, cc);
+    uint32_t h = ((uint32_t)r * 0x9E3779B1u) >> (32 - 11);
+    while (true) {   // at most 1024 keys in 2048 slots: a free slot exists
+      const int32_t old = atomicCAS(&keys[h], -1, r);
+      if (old == -1 || old == r) { atomicAdd(&cnts[h], 1); break; }
+      h = (h + 1) & (kGhBatchHash - 1);
+    }
+  }
+  atomicAdd(&s_valid, valid);
+  __syncthreads();
+  for (int i = t; i < kGhBatchHash; i += kGhBatchThreads)
+    if (cnts[i] > 0)
+      atomicMax(&s_best, ((unsigned long long)(uint32_t)cnts[i] << 32) | (uint32_t)keys[i]);
+  __syncthreads();
+  if (t == 0) {
+    const int best = (int)(s_best >> 32);
+    const bool found = s_valid > 0 && 2 * best >= s_valid;
+    store_agent(&giants[g], found ? (int32_t)(uint32_t)s_best : -1);
+    if (found) atomicMax(&counters[kCntGiant], 0);
+  }
+}
+
+// graph of vertex v: the last g with vtx_off[g] <= v
+__device__ __forceinline__ int gh_graph_of(const int64_t *__restrict__ vtx_off, int G, int64_t v) {
+  int lo = 0, hi = G;   // vtx_off[lo] <= v < vtx_off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (vtx_off[mid] <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
 // The full sweep: a workgroup takes kGhThreads consecutive vertices at a
 // time (grid-stride over such chunks, a few workgroups per CU), scans their
 // degrees in LDS and walks the union of their arcs with unit stride (arcs
 // already sampled are visited again and join nothing new).  With a dominant root D (counters
-// [kCntGiant] >= 0) a vertex whose root is D offers nothing and the others
-// offer every remaining arc; without one, an arc is hooked from its larger
-// end only.  The arcs a wave keeps are queued in its own LDS region and hooked
+// [kCntGiant] >= 0; in a batch, giants[g] of the vertex's graph g) a vertex
+// whose root is D offers nothing and the others offer every remaining arc;
+// without one, an arc is hooked from its larger end only.  The arcs a wave keeps are queued in its own LDS region and hooked
 // 64 at a time, so that every lane of a hooking wave carries a hook (without
 // the queue half the lanes of a chain's waves idle through every hook).  Also
 // counts the vertices whose first arc stays in their 8192-id
@@ -162,7 +223,10 @@ __global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const Off
                                                             const uint8_t *__restrict__ vmask,
                                                             int32_t *cc, int32_t *tu, int32_t *tv,
                                                             int32_t *head, int32_t *next,
-                                                            int32_t *counters) {
+                                                            int32_t *counters,
+                                                            const int64_t *__restrict__ vtx_off,
+                                                            int num_graphs,
+                                                            const int32_t *__restrict__ giants) {
   __shared__ int s_scan[kGhThreads + 1];
   __shared__ OffT s_beg[kGhThreads];
   __shared__ int s_wave[kGhThreads / kWave];
@@ -183,7 +247,12 @@ __global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const Off
       const OffT b = off[v], e = off[v + 1];
       if (e > b) locals += (cols[b] >> kGhTileShift) == (int32_t)(v >> kGhTileShift);
       beg = b;
-      if (e > beg && !(giant >= 0 && find_root((int32_t)v, cc) == giant)) deg = (int)(e - beg);
+      if (e > beg) {
+        // the dominant root this vertex's tree is compared with
+        const int32_t d = giant < 0 ? -1
+                        : giants ? giants[gh_graph_of(vtx_off, num_graphs, v)] : giant;
+        if (!(d >= 0 && find_root((int32_t)v, cc) == d)) deg = (int)(e - beg);
+      }
     }
     s_beg[t] = beg;
     int total;
@@ -292,8 +361,14 @@ rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f) {
                          (const int64_t *)g->offsets, g->cols, K, f.vmask, f.cc, f.tu, f.tv,
                          f.head, f.next);
     RST_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_gh_giant, dim3(1), dim3(kGhSampleThreads), 0, ctx->stream, n, f.cc,
-                       f.vmask, f.counters);
+    if (f.giants && f.num_graphs > 1) {
+      RST_TRY(enqueue_fill(ctx, f.counters + kCntGiant, 1, -1));
+      hipLaunchKernelGGL(k_gh_giants, dim3(f.num_graphs), dim3(kGhBatchThreads), 0, ctx->stream,
+                         f.vtx_off, f.cc, f.vmask, f.giants, f.counters);
+    } else {
+      hipLaunchKernelGGL(k_gh_giant, dim3(1), dim3(kGhSampleThreads), 0, ctx->stream, n, f.cc,
+                         f.vmask, f.counters);
+    }
     RST_HIP(hipGetLastError());
   } else {
     RST_TRY(enqueue_fill(ctx, f.counters + kCntGiant, 1, -1));
@@ -301,14 +376,16 @@ rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f) {
   RST_KMARK(ctx, RST_KERNEL_HOOK_SAMPLE, 1);
   RST_KMARK(ctx, RST_KERNEL_HOOK_GLOBAL, 0);
   const unsigned grid = gh_grid(ctx, grid_for(n, kGhThreads), 2);
+  // per-graph dominant roots only when they were sought (sampling ran)
+  const int32_t *batch_giants = (K > 0 && f.giants && f.num_graphs > 1) ? f.giants : nullptr;
   if (g->offset_bytes == 4)
     hipLaunchKernelGGL(k_gh_sweep<int32_t>, dim3(grid), dim3(kGhThreads), 0, ctx->stream, n,
                        (const int32_t *)g->offsets, g->cols, f.vmask, f.cc, f.tu, f.tv, f.head,
-                       f.next, f.counters);
+                       f.next, f.counters, f.vtx_off, f.num_graphs, batch_giants);
   else
     hipLaunchKernelGGL(k_gh_sweep<int64_t>, dim3(grid), dim3(kGhThreads), 0, ctx->stream, n,
                        (const int64_t *)g->offsets, g->cols, f.vmask, f.cc, f.tu, f.tv, f.head,
-                       f.next, f.counters);
+                       f.next, f.counters, f.vtx_off, f.num_graphs, batch_giants);
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_HOOK_GLOBAL, 1);
   return RST_OK;

@@ -155,6 +155,13 @@ struct ForestBufs {
   // its own edges in LDS, later hooks link with atomic exchanges.
   int32_t *head = nullptr;
   int32_t *next = nullptr;
+  // Batches (global sweep): graph g owns vertices [vtx_off[g], vtx_off[g+1]);
+  // giants[g] is the root of g's dominant tree or -1 ([num_graphs], written by
+  // the hooking itself).  Without them the whole graph has one dominant tree
+  // at most, counters[kCntGiant].
+  const int64_t *vtx_off = nullptr;
+  int32_t num_graphs = 0;
+  int32_t *giants = nullptr;
 };
 
 enum {

@@ -40,7 +40,15 @@ __device__ __forceinline__ void link_slot(int32_t x, int32_t a, int32_t b, int32
 
 // Hook the trees of u and v by compare-and-swap of the larger root; on
 // success record (u,v) at the hooked root and return that root (the slot),
-// else -1 (u and v were already in one tree).
+// else -1 (u and v were already in one tree).  kTestFirst: read the root's
+// word before the compare-and-swap and skip it when the root has been hooked
+// already (the word of a hooked root only ever moves up its ancestors, so
+// the value read is a valid next step).  Where many lanes reach the same few
+// roots at once (sampled arcs into hubs) the failing compare-and-swaps on one
+// address serialised: testing first cut the sampling pass of an R-MAT graph
+// with hubs of degree 1.6e5 from 1.17 to 0.68 ms; where almost every
+// compare-and-swap succeeds (a chain's sweep) the extra load cost 3%.
+template <bool kTestFirst = false>
 __device__ __forceinline__ int32_t hook_record(int32_t u, int32_t v, int32_t *cc, int32_t *tu,
                                                int32_t *tv) {
   int32_t ru = find_root(u, cc);
@@ -48,7 +56,9 @@ __device__ __forceinline__ int32_t hook_record(int32_t u, int32_t v, int32_t *cc
   while (ru != rv) {
     const int32_t lo = ru < rv ? ru : rv;
     const int32_t hi = ru < rv ? rv : ru;
-    const int32_t old = atomicCAS(&cc[hi], hi, lo);
+    int32_t old = hi;
+    if (kTestFirst) old = cc[hi];
+    if (old == hi) old = atomicCAS(&cc[hi], hi, lo);
     if (old == hi) {
       tu[hi] = u;
       tv[hi] = v;

@@ -128,3 +128,30 @@ def test_many_small_graphs(rst):
         parent.fill_(-7)
         c.spanning_forest_batch(*args, method=m, parent=parent, method_out=mout)
         check(b, parent.cpu().numpy(), method)
+
+
+@pytest.mark.parametrize("sample", [2, 1])
+def test_global_sweep_with_a_dominant_tree_per_graph(rst, sample):
+    """The global sweep forced over a batch, with sampling: every packed graph
+    gets its own dominant tree, whose vertices offer no arcs (sound because no
+    edge joins two graphs); members of every kind, some by BFS, replays."""
+    G = 600
+    graphs = [I.batch_member(k, seed=13, nmin=50, nmax=6000) for k in range(G)]
+    graphs[7] = I.random_graph(3000, 800, seed=5, connected=False)
+    graphs[8] = I.long_chain(3000, 0.01, 16, seed=4, offset_bytes=4)
+    graphs[9] = I.path(1)
+    b = I.pack(graphs)
+    method = (np.arange(G) % 5 == 4).astype(np.uint8)
+    c = rst.Context(0)
+    c.set_option(rst.OPT_HOOK_MODE, 2)
+    c.set_option(rst.OPT_HOOK_SAMPLE, sample)
+    g = b.graph
+    args = (dev(g.offsets_typed()), dev(g.cols), dev(b.vtx_off), dev(b.arc_off), dev(b.roots))
+    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for m in (np.zeros(G, np.uint8), method):
+        for call in range(3):
+            parent.fill_(-7)
+            c.spanning_forest_batch(*args, method=dev(m), parent=parent)
+            check(b, parent.cpu().numpy(), m)
+    _, _, st = c.spanning_forest_batch(*args, method=dev(method), stats=True)
+    assert st["paths"] & rst.PATH_HOOK_GLOBAL and st["paths"] & rst.PATH_HOOK_GIANT, st["paths"]
