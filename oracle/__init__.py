@@ -70,6 +70,8 @@ def _load():
     lib.oracle_tree_depth.argtypes = [i64, P, P]
     lib.oracle_pr_rst.restype = i64
     lib.oracle_pr_rst.argtypes = [i64, P, P, P, i32, i64, P]
+    lib.oracle_bcc.restype = i64
+    lib.oracle_bcc.argtypes = [i64, P, P, P, P]
     _lib = lib
     return lib
 
@@ -225,3 +227,32 @@ def pr_rst(n, offsets, cols, roots, max_iters: int = -1):
     if it < 0:
         raise ValueError("oracle_pr_rst failed (%d)" % it)
     return parent, int(it)
+
+
+def bcc(n, offsets, cols):
+    """Biconnected components by Hopcroft and Tarjan's depth-first search:
+    (arc_label[nnz] int32, -1 on self-loops; articulation[n] uint8; count)."""
+    off, c = _csr(offsets, cols)
+    nnz = int(off[n])
+    label = np.empty(max(nnz, 1), dtype=np.int32)
+    art = np.empty(max(n, 1), dtype=np.uint8)
+    k = _load().oracle_bcc(n, _p(off), _p(c), _p(label), _p(art))
+    if k < 0:
+        raise MemoryError
+    return label[:nnz].copy(), art[:n].copy(), int(k)
+
+
+def canonical_labels(label):
+    """Each entry's label replaced by the smallest index carrying the same
+    label (-1 stays -1): equal partitions give equal arrays, whatever the
+    label values."""
+    lab = np.asarray(label)
+    out = np.full(lab.shape, -1, dtype=np.int64)
+    m = lab >= 0
+    idx = np.nonzero(m)[0]
+    if idx.size:
+        _, inv = np.unique(lab[m], return_inverse=True)
+        first = np.full(inv.max() + 1, np.iinfo(np.int64).max, dtype=np.int64)
+        np.minimum.at(first, inv, idx)
+        out[m] = first[inv]
+    return out

@@ -570,3 +570,123 @@ done:
   free(anc); free(np); free(wx); free(wy); free(on); free(label); free(fu); free(fv); free(is_root);
   return iters;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Biconnected components: the downstream use of a rooted spanning tree that */
+/* Sec. I and the opening of Sec. IV name (Tarjan and Vishkin's parallel     */
+/* method takes an RST as input).  The oracle is the sequential depth-first  */
+/* method of Hopcroft and Tarjan: edges are stacked as the search meets them; */
+/* when the search returns from child w to its parent p with low[w] >=       */
+/* pre[p], the edges stacked since the tree edge p->w, that edge included,   */
+/* form one component, and p is an articulation point unless it roots the    */
+/* search (a root is one when it has two or more search children).           */
+/* Every undirected edge copy is stacked once (from the side where the other  */
+/* end was seen first); the reverse arcs take the label of a stacked arc     */
+/* between the same two vertices (parallel copies lie on a common 2-cycle, so */
+/* they share a component).  Self-loops get -1.                               */
+/* arc_label[nnz] in [0, components), art[n] in {0, 1}.  Returns the number   */
+/* of components.                                                             */
+/* ------------------------------------------------------------------------- */
+static int cmp_u64(const void *a, const void *b) {
+  const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+  return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+int64_t oracle_bcc(int64_t n, const int64_t *off, const int32_t *cols, int32_t *arc_label,
+                   uint8_t *art) {
+  const int64_t nnz = off[n];
+  int64_t *pre = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *low = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *it = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+  int64_t *pa = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));     /* arc entering v */
+  int32_t *par = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  uint8_t *skipped = calloc((size_t)(n > 0 ? n : 1), 1);
+  int32_t *vs = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));     /* vertex stack */
+  int64_t *es = malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1)); /* edge stack */
+  int64_t comps = 0;
+  if (!pre || !low || !it || !pa || !par || !skipped || !vs || !es) { comps = ORC_ENOMEM; goto done; }
+  for (int64_t v = 0; v < n; ++v) { pre[v] = -1; art[v] = 0; }
+  for (int64_t a = 0; a < nnz; ++a) arc_label[a] = -1;
+  int64_t clock = 0;
+  for (int64_t s = 0; s < n; ++s) {
+    if (pre[s] >= 0) continue;
+    int64_t top = 0, etop = 0, root_children = 0;
+    pre[s] = low[s] = clock++;
+    it[s] = off[s];
+    par[s] = -1;
+    pa[s] = -1;
+    vs[top++] = (int32_t)s;
+    while (top > 0) {
+      const int32_t u = vs[top - 1];
+      if (it[u] < off[u + 1]) {
+        const int64_t a = it[u]++;
+        const int32_t w = cols[a];
+        if (w == u) continue;                                    /* self-loop */
+        if (pre[w] < 0) {                                        /* tree edge */
+          es[etop++] = a;
+          pre[w] = low[w] = clock++;
+          it[w] = off[w];
+          par[w] = u;
+          pa[w] = a;
+          vs[top++] = w;
+          if (u == s) ++root_children;
+        } else if (pre[w] < pre[u]) {
+          if (w == par[u] && !skipped[u]) { skipped[u] = 1; continue; }  /* the tree edge back */
+          es[etop++] = a;                                        /* back edge */
+          if (pre[w] < low[u]) low[u] = pre[w];
+        }
+        /* pre[w] > pre[u]: a descendant's edge, stacked from its side */
+      } else {
+        --top;
+        if (u == s) break;
+        const int32_t p = par[u];
+        if (low[u] < low[p]) low[p] = low[u];
+        if (low[u] >= pre[p]) {
+          int64_t e;
+          do {
+            e = es[--etop];
+            arc_label[e] = (int32_t)comps;
+          } while (e != pa[u]);
+          ++comps;
+          if (p != s) art[p] = 1;
+        }
+      }
+    }
+    if (root_children >= 2) art[s] = 1;
+  }
+  /* the arcs not stacked take the label of a stacked arc between the same
+     ends: (pair key, label) entries sorted by key, then a binary search */
+  {
+    int64_t k = 0;
+    for (int64_t a = 0; a < nnz; ++a) k += arc_label[a] >= 0;
+    uint64_t *pk = malloc(sizeof(uint64_t) * 2 * (size_t)(k > 0 ? k : 1));
+    if (!pk) { comps = ORC_ENOMEM; goto done; }
+    k = 0;
+    for (int64_t u = 0; u < n; ++u)
+      for (int64_t a = off[u]; a < off[u + 1]; ++a) {
+        if (arc_label[a] < 0) continue;
+        const uint64_t x = (uint64_t)u, y = (uint64_t)(uint32_t)cols[a];
+        pk[2 * k] = (x < y ? x : y) * (uint64_t)n + (x < y ? y : x);
+        pk[2 * k + 1] = (uint64_t)(uint32_t)arc_label[a];
+        ++k;
+      }
+    qsort(pk, (size_t)k, 2 * sizeof(uint64_t), cmp_u64);   /* by the pair key */
+    for (int64_t u = 0; u < n; ++u)
+      for (int64_t a = off[u]; a < off[u + 1]; ++a) {
+        const int32_t w = cols[a];
+        if (arc_label[a] >= 0 || w == (int32_t)u) continue;
+        const uint64_t x = (uint64_t)u, y = (uint64_t)(uint32_t)w;
+        const uint64_t key = (x < y ? x : y) * (uint64_t)n + (x < y ? y : x);
+        int64_t lo = 0, hi = k;                                  /* first entry >= key */
+        while (lo < hi) {
+          const int64_t mid = (lo + hi) / 2;
+          if (pk[2 * mid] < key) lo = mid + 1; else hi = mid;
+        }
+        if (lo < k && pk[2 * lo] == key) arc_label[a] = (int32_t)pk[2 * lo + 1];
+      }
+    free(pk);
+  }
+done:
+  free(pre); free(low); free(it); free(pa); free(par); free(skipped); free(vs); free(es);
+  return comps;
+}
