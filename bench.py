@@ -376,6 +376,20 @@ def main():
     torch.cuda.synchronize()
     depth_ms = (time.perf_counter() - t1) * 1e3
 
+    # the downstream consumer: biconnected components from the same tree
+    # (Tarjan-Vishkin on the RST), one warm-up and 3 timed calls
+    ctx.biconnected(off, cols, gp)
+    torch.cuda.synchronize()
+    bts = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        blab, bart, bk = ctx.biconnected(off, cols, gp)
+        torch.cuda.synchronize()
+        bts.append((time.perf_counter() - t1) * 1e3)
+    downstream = {"kind": "biconnected components (Tarjan-Vishkin) from the GConn+Euler tree",
+                  "ms": round(statistics.median(bts), 3), "components": int(bk),
+                  "articulation_points": int(bart.sum().item())}
+
     bfs = None
     bfs_parent = bfs_level = None
     if not args.no_bfs:
@@ -425,6 +439,7 @@ def main():
         "rank_rulers": last["rank_exits"], "cross_edges": last["cross_edges"],
         "roofline": roofline,
         "gconn_tree_depth": int(gconn_depth), "tree_depth_ms": round(depth_ms, 3),
+        "downstream": downstream,
         "bfs": bfs,
         "paper_context": "GConn+Euler up to 300x faster than optimised BFS on high-diameter "
                          "graphs, NVIDIA L40S (other hardware; context only)",
@@ -441,6 +456,14 @@ def main():
             checks["bfs_levels_bit_exact"] = bool(np.array_equal(lref, bfs_level))
         dref, dmax = oracle.tree_depth(gpu_parent)
         checks["gconn_tree_depth_exact"] = dmax == gconn_depth
+        t2 = time.perf_counter()
+        lref, aref, kref = oracle.bcc(g.n, g.offsets, g.cols)
+        downstream["cpu_oracle_ms"] = round((time.perf_counter() - t2) * 1e3, 1)
+        checks["downstream_bit_exact"] = bool(
+            kref == downstream["components"]
+            and np.array_equal(oracle.canonical_labels(lref),
+                               oracle.canonical_labels(blab.cpu().numpy()))
+            and np.array_equal(aref, bart.cpu().numpy()))
         log("[bench] cpu baseline (oracle, 1 + 5 runs)")
         line["cpu_baseline"] = cpu_baseline(g, root)
     else:

@@ -269,6 +269,27 @@ rst_status rst_list_rank(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *
 rst_status rst_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *depth,
                           int64_t *max_depth);
 
+/* Biconnected components of a connected graph from a rooted spanning tree of
+ * it: the downstream use of an RST that Sec. I and the opening of Sec. IV name
+ * (Tarjan and Vishkin's method).  The tree's preorder numbers and subtree
+ * sizes come from its Euler tour (Sec. III-D), weighted 1 on down arcs and 0
+ * on up arcs and ranked like rst_tree_depth's; tree edges are joined when a
+ * subtree reaches past its parent's subtree or a non-tree edge links them,
+ * and the connected components of those joins (hooking + pointer jumping,
+ * Sec. III-B) are the biconnected components.
+ * g: the graph (nnz < 2^31); parent: device int32 [n], a rooted spanning
+ * tree of g with one root (P[r] = r; e.g. from rst_spanning_tree; check it
+ * with rst_verify: any other array gives unspecified labels, never an access
+ * outside the buffers).  arc_label: device int32 [nnz] receives for every arc
+ * the label of its component -- the smallest vertex v whose tree edge
+ * {P[v], v} lies in it -- and -1 for self-loops; articulation: device uint8
+ * [n], nullable, receives 1 for every vertex whose arcs lie in two or more
+ * components; num_components: host, nullable.  Errors: RST_E_INVAL,
+ * RST_E_DISCONNECTED (parent has more than one root), RST_E_RANGE (its tour
+ * gives preorder numbers outside [0, n): not a tree).  Synchronous. */
+rst_status rst_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent,
+                           int32_t *arc_label, uint8_t *articulation, int64_t *num_components);
+
 /* Rooted spanning forest of G packed graphs in one pass: graph g is rooted at
  * roots[g].  method: device uint8 [G] per graph (0 = GConn+Euler, nonzero =
  * BFS), or NULL to let the loaded selector choose (GConn+Euler if none is

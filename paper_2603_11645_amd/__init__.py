@@ -62,6 +62,7 @@ EXPORTS = [
     "rst_spanning_forest_batch", "rst_selector_load", "rst_status_string", "rst_features",
     "rst_feature_stats", "rst_mlp_forward", "rst_mlp_train_step", "rst_get_option",
     "rst_verify", "rst_autotune", "rst_tune_save", "rst_tune_load", "rst_tree_depth",
+    "rst_biconnected",
 ]
 
 N_FEATURES = 8
@@ -166,6 +167,7 @@ def load_library(path: Optional[str] = None):
                                  ctypes.POINTER(rst_tune_result)]),
             "rst_tune_save": (S, [P, ctypes.c_char_p]),
             "rst_tree_depth": (S, [P, i64, P, P, ctypes.POINTER(i64)]),
+            "rst_biconnected": (S, [P, ctypes.POINTER(rst_csr), P, P, P, ctypes.POINTER(i64)]),
             "rst_tune_load": (S, [P, ctypes.c_char_p, ctypes.POINTER(rst_csr), ctypes.c_int,
                                   ctypes.POINTER(i32)]),
         }
@@ -393,6 +395,21 @@ class Context:
         self._call("rst_tree_depth", n, ctypes.c_void_p(parent.data_ptr()),
                    ctypes.c_void_p(depth.data_ptr()), ctypes.byref(mx))
         return depth, int(mx.value)
+
+    def biconnected(self, offsets, cols, parent):
+        """rst_biconnected: (arc_label int32 device [nnz], articulation uint8
+        device [n], number of components) from the rooted spanning tree
+        `parent` of the graph."""
+        torch = _torch()
+        g = make_csr(offsets, cols)
+        _check_dev(parent, torch.int32, "parent")
+        label = torch.empty(max(int(g.nnz), 1), dtype=torch.int32, device=offsets.device)
+        art = torch.empty(g.n, dtype=torch.uint8, device=offsets.device)
+        k = ctypes.c_int64(0)
+        self._call("rst_biconnected", ctypes.byref(g), ctypes.c_void_p(parent.data_ptr()),
+                   ctypes.c_void_p(label.data_ptr()), ctypes.c_void_p(art.data_ptr()),
+                   ctypes.byref(k))
+        return label[:int(g.nnz)], art, int(k.value)
 
     # -- batches and the selector ---------------------------------------------
     def _batch(self, vtx_off, arc_off, roots):

@@ -1,0 +1,357 @@
+// bcc.hip -- biconnected components from a rooted spanning tree: the
+// downstream use of an RST that Sec. I and the opening of Sec. IV name, by
+// the parallel method of Tarjan and Vishkin.
+//
+// Given a spanning tree T of a connected graph G rooted at r (parent P):
+//  1. pre(v), nd(v): preorder number and subtree size from the Euler tour of
+//     T (run_tour_preorder: the tour weighted 1 on down arcs and 0 on up
+//     arcs, ranked by the sparse ruling set); v's subtree is the preorder
+//     range [pre(v), pre(v) + nd(v)).
+//  2. local(v) = (min, max) of pre(v) and of pre(w) over v's non-tree arcs
+//     (v, w) (arcs to P(v) or to a child count as tree arcs, parallel copies
+//     included; self-loops count as nothing), stored at position pre(v).
+//  3. low(v), high(v): min and max of local over v's subtree range, by a
+//     range-extremum structure (per 64-position block the prefix and suffix
+//     extremes, a sparse table over the blocks).
+//  4. An auxiliary graph on the tree edges, each named by its child vertex:
+//     tree edge v and its parent's tree edge P(v) (P(v) not the root) are
+//     joined when low(v) < pre(P(v)) or high(v) >= pre(P(v)) + nd(P(v)) (a
+//     vertex of v's subtree has a non-tree edge leaving P(v)'s subtree);
+//     non-tree edge (u, w) with pre(u) < pre(w) and w outside u's subtree
+//     joins tree edges u and w.  Its connected components -- min-id hooking
+//     by compare-and-swap as in the hooking pass, then pointer jumping -- are
+//     the biconnected components of the tree edges, each labelled by its
+//     smallest child vertex.
+//  5. Every arc takes its component: a tree arc (or a parallel copy) the one
+//     of its child's tree edge, a non-tree arc the one of the tree edge of its
+//     end with the larger preorder number; a vertex whose arcs carry two or
+//     more labels is an articulation point.
+#include "rst_internal.h"
+#include "device_common.h"
+#include "unionfind.h"
+
+namespace rst {
+
+constexpr int kBcChunk = 1024;   // vertices per workgroup step of the arc passes
+constexpr int kBcBlock = 64;     // preorder positions per block of the extremum structure
+constexpr int kBcThreads = 256;
+
+__device__ __forceinline__ int2 bc_comb(int2 a, int2 b) {
+  return make_int2(a.x < b.x ? a.x : b.x, a.y > b.y ? a.y : b.y);
+}
+
+// Calls f(j, u, w, a) for every arc a = (u -> w) of the vertices
+// [v0, v0 + kBcChunk) (j = u - v0): their degrees scanned in LDS, the union
+// of their arcs walked with unit stride.  Called by all threads of the
+// workgroup; ends with a barrier.
+template <class OffT, class F>
+__device__ __forceinline__ void bc_chunk_arcs(int64_t n, int64_t v0, const OffT *__restrict__ off,
+                                              const int32_t *__restrict__ cols, int *s_scan,
+                                              OffT *s_beg, int *s_wave, F f) {
+  const int t = threadIdx.x;
+  const int64_t v = v0 + t;
+  int deg = 0;
+  OffT beg = 0;
+  if (v < n) {
+    beg = off[v];
+    deg = (int)(off[v + 1] - beg);
+  }
+  s_beg[t] = beg;
+  int total;
+  const int excl = block_excl_scan<kBcChunk>(deg, s_wave, &total);
+  s_scan[t] = excl;
+  if (t == kBcChunk - 1) s_scan[kBcChunk] = excl + deg;
+  __syncthreads();
+  for (int b0 = 0; b0 < total; b0 += kBcChunk) {
+    const int k = b0 + t;
+    if (k < total) {
+      const int j = lds_upper_search(s_scan, kBcChunk, k);
+      const OffT a = s_beg[j] + (OffT)(k - s_scan[j]);
+      f(j, (int32_t)(v0 + j), cols[a], (int64_t)a);
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool bc_is_root(int32_t v, int32_t p, int64_t n) {
+  return p == v || p < 0 || p >= n;
+}
+
+// Step 2: local extremes, stored at each vertex's preorder position.
+template <class OffT>
+__global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT *__restrict__ off,
+                                                        const int32_t *__restrict__ cols,
+                                                        const int32_t *__restrict__ parent,
+                                                        const int32_t *__restrict__ pre, int2 *A,
+                                                        int32_t *counters) {
+  __shared__ int s_scan[kBcChunk + 1];
+  __shared__ OffT s_beg[kBcChunk];
+  __shared__ int s_wave[kBcChunk / kWave];
+  __shared__ int s_lo[kBcChunk], s_hi[kBcChunk];
+  const int t = threadIdx.x;
+  const int64_t chunks = (n + kBcChunk - 1) / kBcChunk;
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const int64_t v0 = c * kBcChunk, v = v0 + t;
+    const int32_t pv = v < n ? pre[v] : 0;
+    s_lo[t] = pv;   // published by the scan's barriers
+    s_hi[t] = pv;
+    bc_chunk_arcs(n, v0, off, cols, s_scan, s_beg, s_wave,
+                  [&](int j, int32_t u, int32_t w, int64_t) {
+                    if (w == u || w < 0 || w >= n) return;
+                    if (w == parent[u] || parent[w] == u) return;   // tree arc or a copy
+                    const int32_t pw = pre[w];
+                    atomicMin(&s_lo[j], pw);
+                    atomicMax(&s_hi[j], pw);
+                  });
+    if (v < n) {
+      if (pv >= 0 && pv < n) A[pv] = make_int2(s_lo[t], s_hi[t]);
+      else atomicOr(&counters[kCntRangeErr], 1);
+    }
+  }
+}
+
+// Step 3a: one wave per block of 64 positions: prefix and suffix extremes
+// within the block, and the block's extremes (level 0 of the sparse table).
+__global__ __launch_bounds__(kBcThreads) void k_bcc_blocks(int64_t n, const int2 *__restrict__ A,
+                                                           int2 *pfx, int2 *sfx, int2 *st0) {
+  const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int lane = (int)(threadIdx.x & (kWave - 1));
+  const int64_t nb = (n + kBcBlock - 1) / kBcBlock;
+  if (b >= nb) return;   // a whole wave
+  const int64_t i = b * kBcBlock + lane;
+  const int2 x = i < n ? A[i] : make_int2(INT32_MAX, INT32_MIN);
+  int2 f = x, s = x;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int2 u = make_int2(__shfl_up(f.x, o, 64), __shfl_up(f.y, o, 64));
+    const int2 d = make_int2(__shfl_down(s.x, o, 64), __shfl_down(s.y, o, 64));
+    if (lane >= o) f = bc_comb(f, u);
+    if (lane + o < kWave) s = bc_comb(s, d);
+  }
+  if (i < n) {
+    pfx[i] = f;
+    sfx[i] = s;
+  }
+  if (lane == 0) st0[b] = s;
+}
+
+// Step 3b: level k of the sparse table over blocks (extremes of 2^k blocks).
+__global__ __launch_bounds__(kBcThreads) void k_bcc_sparse(int64_t nb, int k, int2 *st) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t h = (int64_t)1 << (k - 1);
+  if (i + 2 * h > nb) return;
+  st[k * nb + i] = bc_comb(st[(k - 1) * nb + i], st[(k - 1) * nb + i + h]);
+}
+
+// extremes of local over positions [l, r] (0 <= l <= r < n)
+__device__ __forceinline__ int2 bc_range(int64_t l, int64_t r, const int2 *__restrict__ A,
+                                         const int2 *__restrict__ pfx, const int2 *__restrict__ sfx,
+                                         const int2 *__restrict__ st, int64_t nb) {
+  const int64_t bl = l / kBcBlock, br = r / kBcBlock;
+  if (bl == br) {
+    if (l % kBcBlock == 0) return pfx[r];
+    if (r % kBcBlock == kBcBlock - 1) return sfx[l];
+    int2 m = A[l];
+    for (int64_t i = l + 1; i <= r; ++i) m = bc_comb(m, A[i]);
+    return m;
+  }
+  int2 m = bc_comb(sfx[l], pfx[r]);
+  if (br - bl > 1) {
+    const int64_t i = bl + 1, j = br - 1;
+    const int k = 63 - __builtin_clzll((unsigned long long)(j - i + 1));
+    m = bc_comb(m, st[k * nb + i]);
+    m = bc_comb(m, st[k * nb + j - ((int64_t)1 << k) + 1]);
+  }
+  return m;
+}
+
+// every tree edge its own component to begin with (agent-scope stores: the
+// hooking kernels after this one compare-and-swap these words)
+template <int B>
+__global__ __launch_bounds__(B) void k_bcc_iota(int64_t n, int32_t *L) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) store_agent(&L[v], (int32_t)v);
+}
+
+// Step 4, tree edges: v joins its parent's tree edge when a vertex of v's
+// subtree reaches outside the parent's subtree.  Ends with a device-scope
+// release per workgroup (hooks in global memory, read on every XCD next).
+template <int B>
+__global__ __launch_bounds__(B) void k_bcc_rule_tree(int64_t n, const int32_t *__restrict__ parent,
+                                                     const int32_t *__restrict__ pre,
+                                                     const int32_t *__restrict__ nd,
+                                                     const int2 *__restrict__ A,
+                                                     const int2 *__restrict__ pfx,
+                                                     const int2 *__restrict__ sfx,
+                                                     const int2 *__restrict__ st, int64_t nb,
+                                                     int32_t *L, int32_t *counters) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) {
+    const int32_t p = parent[v];
+    if (!bc_is_root((int32_t)v, p, n) && !bc_is_root(p, parent[p], n)) {
+      const int64_t pv = pre[v], sv = nd[v], pp = pre[p], sp = nd[p];
+      if (pv < 0 || sv < 1 || pv + sv > n || pp < 0 || sp < 1 || pp + sp > n) {
+        atomicOr(&counters[kCntRangeErr], 1);
+      } else {
+        const int2 lh = bc_range(pv, pv + sv - 1, A, pfx, sfx, st, nb);
+        if (lh.x < pp || lh.y >= pp + sp) hook_edge<false>((int32_t)v, p, L, nullptr, nullptr);
+      }
+    }
+  }
+  block_release_device();
+}
+
+// Step 4, non-tree edges: (u, w) with pre(u) < pre(w) and w outside u's
+// subtree joins the tree edges of u and w.  Ends with a release as above.
+template <class OffT>
+__global__ __launch_bounds__(kBcChunk, 8) void k_bcc_rule_cross(int64_t n, const OffT *__restrict__ off,
+                                                             const int32_t *__restrict__ cols,
+                                                             const int32_t *__restrict__ parent,
+                                                             const int32_t *__restrict__ pre,
+                                                             const int32_t *__restrict__ nd,
+                                                             int32_t *L) {
+  __shared__ int s_scan[kBcChunk + 1];
+  __shared__ OffT s_beg[kBcChunk];
+  __shared__ int s_wave[kBcChunk / kWave];
+  const int64_t chunks = (n + kBcChunk - 1) / kBcChunk;
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x)
+    bc_chunk_arcs(n, c * kBcChunk, off, cols, s_scan, s_beg, s_wave,
+                  [&](int, int32_t u, int32_t w, int64_t) {
+                    if (w == u || w < 0 || w >= n) return;
+                    if (w == parent[u] || parent[w] == u) return;
+                    const int64_t pu = pre[u], pw = pre[w];
+                    if (pu < pw && pw >= pu + nd[u]) hook_edge<false>(u, w, L, nullptr, nullptr);
+                  });
+  block_release_device();
+}
+
+// Step 5: arc labels, articulation points, and the number of components
+// (tree edges that are their component's smallest child).
+template <class OffT>
+__global__ __launch_bounds__(kBcChunk, 8) void k_bcc_arcs(int64_t n, const OffT *__restrict__ off,
+                                                       const int32_t *__restrict__ cols,
+                                                       const int32_t *__restrict__ parent,
+                                                       const int32_t *__restrict__ pre,
+                                                       const int32_t *__restrict__ L,
+                                                       int32_t *arc_label, uint8_t *art,
+                                                       int32_t *counters) {
+  __shared__ int s_scan[kBcChunk + 1];
+  __shared__ OffT s_beg[kBcChunk];
+  __shared__ int s_wave[kBcChunk / kWave];
+  __shared__ int s_mn[kBcChunk], s_mx[kBcChunk];
+  const int t = threadIdx.x;
+  const int64_t chunks = (n + kBcChunk - 1) / kBcChunk;
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const int64_t v0 = c * kBcChunk, v = v0 + t;
+    s_mn[t] = INT32_MAX;   // published by the scan's barriers
+    s_mx[t] = -1;
+    bc_chunk_arcs(n, v0, off, cols, s_scan, s_beg, s_wave,
+                  [&](int j, int32_t u, int32_t w, int64_t a) {
+                    int32_t lab = -1;
+                    if (w != u && w >= 0 && w < n) {
+                      const int32_t child = parent[w] == u ? w
+                                          : parent[u] == w ? u
+                                          : (pre[u] > pre[w] ? u : w);
+                      lab = L[child];
+                      atomicMin(&s_mn[j], lab);
+                      atomicMax(&s_mx[j], lab);
+                    }
+                    arc_label[a] = lab;
+                  });
+    bool comp = false;
+    if (v < n) {
+      if (art) art[v] = (s_mn[t] != INT32_MAX && s_mn[t] != s_mx[t]) ? 1 : 0;
+      comp = !bc_is_root((int32_t)v, parent[v], n) && L[v] == (int32_t)v;
+    }
+    wave_count(comp, &counters[kCntComponents]);
+  }
+}
+
+static unsigned bc_grid(const rst_ctx *ctx, int64_t n) {
+  const int64_t chunks = (n + kBcChunk - 1) / kBcChunk;
+  const int64_t cap = (int64_t)ctx->num_cus * 2;
+  return (unsigned)(chunks < cap ? (chunks < 1 ? 1 : chunks) : cap);
+}
+
+template <class OffT>
+static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, const int32_t *parent,
+                                const int32_t *pre, const int32_t *nd, int2 *A, int2 *pfx,
+                                int2 *sfx, int2 *st, int64_t nb, int levels, int32_t *L,
+                                int32_t *arc_label, uint8_t *art, int32_t *counters) {
+  const int64_t n = g->n;
+  const OffT *off = static_cast<const OffT *>(g->offsets);
+  const unsigned grid = bc_grid(ctx, n);
+  hipLaunchKernelGGL(k_bcc_local<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off, g->cols,
+                     parent, pre, A, counters);
+  RST_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_bcc_blocks, dim3(grid_for(nb * kWave, kBcThreads)), dim3(kBcThreads), 0,
+                     ctx->stream, n, A, pfx, sfx, st);
+  RST_HIP(hipGetLastError());
+  for (int k = 1; k < levels; ++k) {
+    hipLaunchKernelGGL(k_bcc_sparse, dim3(grid_for(nb, kBcThreads)), dim3(kBcThreads), 0,
+                       ctx->stream, nb, k, st);
+    RST_HIP(hipGetLastError());
+  }
+  RST_SWEEP(ctx, k_bcc_iota, n, n, L);
+  RST_HIP(hipGetLastError());
+  RST_SWEEP(ctx, k_bcc_rule_tree, n, n, parent, pre, nd, A, pfx, sfx, st, nb, L, counters);
+  RST_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_bcc_rule_cross<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off,
+                     g->cols, parent, pre, nd, L);
+  RST_HIP(hipGetLastError());
+  RST_TRY(enqueue_compress(ctx, n, L, nullptr, nullptr));
+  hipLaunchKernelGGL(k_bcc_arcs<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off, g->cols,
+                     parent, pre, L, arc_label, art, counters);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
+rst_status run_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent,
+                           int32_t *arc_label, uint8_t *art, int64_t *num_components) {
+  const int64_t n = g->n;
+  const GlistPlan plan = glist_plan(2 * n, n / 2 + 1, ctx->opt.rank_stride);
+  const int64_t nb = (n + kBcBlock - 1) / kBcBlock;
+  int levels = 1;   // floor(log2 nb) + 1
+  while (((int64_t)1 << levels) <= nb) ++levels;
+  RST_TRY(ws_reserve(ctx, depth_ws_bytes(n, plan) + 3 * ws_bytes((size_t)n, 4) +
+                              3 * ws_bytes((size_t)n, 8) + ws_bytes((size_t)(levels * nb), 8)));
+  int32_t *counters = ws_take<int32_t>(ctx, 64);
+  int32_t *pre = ws_take<int32_t>(ctx, n);
+  int32_t *nd = ws_take<int32_t>(ctx, n);
+  int32_t *L = ws_take<int32_t>(ctx, n);
+  int2 *A = ws_take<int2>(ctx, n);
+  int2 *pfx = ws_take<int2>(ctx, n);
+  int2 *sfx = ws_take<int2>(ctx, n);
+  int2 *st = ws_take<int2>(ctx, (size_t)(levels * nb));
+  RST_TRY(enqueue_fill(ctx, counters, 32, 0));
+  RST_TRY(run_tour_preorder(ctx, n, parent, pre, nd, counters));
+  if (ctx->host_pinned[kCntBccRoots] != 1) return RST_E_DISCONNECTED;
+  if (g->offset_bytes == 4)
+    RST_TRY(bc_arc_passes<int32_t>(ctx, g, parent, pre, nd, A, pfx, sfx, st, nb, levels, L,
+                                   arc_label, art, counters));
+  else
+    RST_TRY(bc_arc_passes<int64_t>(ctx, g, parent, pre, nd, A, pfx, sfx, st, nb, levels, L,
+                                   arc_label, art, counters));
+  RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
+                         hipMemcpyDeviceToHost, ctx->stream));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->host_pinned[kCntRangeErr]) return RST_E_RANGE;
+  if (num_components) *num_components = ctx->host_pinned[kCntComponents];
+  return RST_OK;
+}
+
+}  // namespace rst
+
+using namespace rst;
+
+extern "C" rst_status rst_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent,
+                                      int32_t *arc_label, uint8_t *articulation,
+                                      int64_t *num_components) {
+  if (!ctx || !g || !parent || g->n < 1 || !g->offsets) return RST_E_INVAL;
+  if (g->nnz < 0 || (g->nnz > 0 && (!g->cols || !arc_label))) return RST_E_INVAL;
+  if (g->offset_bytes != 4 && g->offset_bytes != 8) return RST_E_INVAL;
+  // arc ids of the tour (2n) and the per-workgroup arc counts are int32
+  if (g->n >= ((int64_t)1 << 30) || g->nnz >= ((int64_t)1 << 31)) return RST_E_INVAL;
+  RST_HIP(hipSetDevice(ctx->device));
+  return run_biconnected(ctx, g, parent, arc_label, articulation, num_components);
+}

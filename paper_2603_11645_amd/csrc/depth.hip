@@ -51,19 +51,21 @@ __global__ __launch_bounds__(B) void k_depth_link(int64_t n, const int32_t *__re
   reinterpret_cast<int2 *>(next)[x] = nx;
 }
 
+// weight of the successor arc, 0 past the tail: depth (kPre false) +1 down
+// (even id), -1 up (odd id); preorder (kPre true) 1 down, 0 up
+template <bool kPre>
 __device__ __forceinline__ uint64_t depth_word(int32_t succ) {
-  // weight of the successor arc: +1 down (even id), -1 up (odd id), 0 past the tail
-  const uint32_t w = succ < 0 ? 0u : ((succ & 1) ? 0xffffffffu : 1u);
+  const uint32_t w = succ < 0 ? 0u : ((succ & 1) ? (kPre ? 0u : 0xffffffffu) : 1u);
   return ((uint64_t)w << 32) | (uint32_t)succ;
 }
 
 // Level-1 words (successor, weight) of both arcs of every slot, and the list
 // heads (the first out-arc of every root with arcs).
-template <int B>
-__global__ __launch_bounds__(B) void k_depth_words(int64_t n, const int32_t *__restrict__ parent,
-                                                   const int32_t *__restrict__ head,
-                                                   const int32_t *__restrict__ next, uint64_t *w,
-                                                   int32_t *heads, int64_t hcap, int32_t *counters) {
+template <bool kPre>
+__device__ __forceinline__ void tour_words(int64_t n, const int32_t *__restrict__ parent,
+                                           const int32_t *__restrict__ head,
+                                           const int32_t *__restrict__ next, uint64_t *w,
+                                           int32_t *heads, int64_t hcap, int32_t *counters) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool is_head = false;
   int32_t h = -1;
@@ -82,13 +84,29 @@ __global__ __launch_bounds__(B) void k_depth_words(int64_t n, const int32_t *__r
       // first unless p roots its tree (the end of the tour)
       int32_t s1 = nx.x;
       if (s1 == -1) s1 = depth_is_root(p, parent[p], n) ? -1 : head[p];
-      out.x = depth_word(s0);
-      out.y = depth_word(s1);
+      out.x = depth_word<kPre>(s0);
+      out.y = depth_word<kPre>(s1);
     }
     reinterpret_cast<ulonglong2 *>(w)[x] = out;
   }
   const int slot = wave_append(is_head, &counters[kCntGHeads]);
   if (is_head && slot < hcap) heads[slot] = h;
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_depth_words(int64_t n, const int32_t *__restrict__ parent,
+                                                   const int32_t *__restrict__ head,
+                                                   const int32_t *__restrict__ next, uint64_t *w,
+                                                   int32_t *heads, int64_t hcap, int32_t *counters) {
+  tour_words<false>(n, parent, head, next, w, heads, hcap, counters);
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_pre_words(int64_t n, const int32_t *__restrict__ parent,
+                                                 const int32_t *__restrict__ head,
+                                                 const int32_t *__restrict__ next, uint64_t *w,
+                                                 int32_t *heads, int64_t hcap, int32_t *counters) {
+  tour_words<true>(n, parent, head, next, w, heads, hcap, counters);
 }
 
 // depth[x] = -(weighted distance after the down arc 2x), 0 at roots; the
@@ -126,6 +144,59 @@ __global__ __launch_bounds__(B) void k_depth_out_rounds(int64_t n, const int32_t
     depth[x] = d;
   }
   block_max_to<B>(d, &counters[kCntDepthMax]);
+}
+
+// Preorder number and subtree size of every vertex of a tree (one root) from
+// the preorder-weighted tour: D(e) = number of down arcs after arc e, so
+// pre(x) = (n - 1) - D(2x) and nd(x) = D(2x) - D(2x+1) + 1 (the down arcs
+// strictly inside x's excursion are its descendants'); the root has pre 0
+// and nd n.  Roots are counted into counters[kCntBccRoots].
+__device__ __forceinline__ void pre_store(int64_t n, int64_t x, bool root, uint32_t d0,
+                                          uint32_t d1, int32_t *pre, int32_t *nd) {
+  if (root) {
+    pre[x] = 0;
+    nd[x] = (int32_t)n;
+  } else {
+    pre[x] = (int32_t)(n - 1) - (int32_t)d0;
+    nd[x] = (int32_t)d0 - (int32_t)d1 + 1;
+  }
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_pre_out(int64_t n, const int32_t *__restrict__ parent,
+                                               const uint64_t *__restrict__ w,
+                                               const uint32_t *__restrict__ d1, int64_t rw1_cap,
+                                               int32_t *pre, int32_t *nd, int32_t *counters) {
+  if (counters[kCntGOverflow]) return;   // block-uniform: the caller falls back
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool root = false;
+  if (x < n) {
+    root = depth_is_root((int32_t)x, parent[x], n);
+    uint32_t a = 0, b = 0;
+    if (!root) {
+      const uint64_t c0 = w[2 * x], c1 = w[2 * x + 1];
+      const uint32_t r0 = (uint32_t)c0, r1 = (uint32_t)c1;
+      a = r0 < rw1_cap ? d1[r0] - (uint32_t)(c0 >> 32) : 0u;
+      b = r1 < rw1_cap ? d1[r1] - (uint32_t)(c1 >> 32) : 0u;
+    }
+    pre_store(n, x, root, a, b, pre, nd);
+  }
+  wave_count(root, &counters[kCntBccRoots]);
+}
+
+template <int B>
+__global__ __launch_bounds__(B) void k_pre_out_rounds(int64_t n, const int32_t *__restrict__ parent,
+                                                      const uint64_t *__restrict__ w, int32_t *pre,
+                                                      int32_t *nd, int32_t *counters) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool root = false;
+  if (x < n) {
+    root = depth_is_root((int32_t)x, parent[x], n);
+    const uint32_t a = root ? 0u : (uint32_t)(w[2 * x] >> 32);
+    const uint32_t b = root ? 0u : (uint32_t)(w[2 * x + 1] >> 32);
+    pre_store(n, x, root, a, b, pre, nd);
+  }
+  wave_count(root, &counters[kCntBccRoots]);
 }
 
 size_t depth_ws_bytes(int64_t n, const GlistPlan &p) {
@@ -167,6 +238,40 @@ rst_status run_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_
     RST_HIP(hipStreamSynchronize(ctx->stream));
   }
   if (max_depth) *max_depth = ctx->host_pinned[kCntDepthMax];
+  return RST_OK;
+}
+
+rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *pre,
+                              int32_t *nd, int32_t *counters) {
+  const GlistPlan plan = glist_plan(2 * n, n / 2 + 1, ctx->opt.rank_stride);
+  int32_t *head = ws_take<int32_t>(ctx, n);
+  int32_t *next = ws_take<int32_t>(ctx, 2 * n);
+  uint64_t *w = ws_take<uint64_t>(ctx, 2 * n);
+  GlistBufs gl;
+  glist_take(ctx, plan, gl);
+  RST_TRY(enqueue_fill(ctx, head, n, -1));
+  RST_SWEEP(ctx, k_depth_link, n, n, parent, head, next);
+  RST_HIP(hipGetLastError());
+  RST_SWEEP(ctx, k_pre_words, n, n, parent, head, next, w, gl.heads[0], plan.hcap, counters);
+  RST_HIP(hipGetLastError());
+  RST_TRY(enqueue_glist_rank(ctx, w, true, gl, counters));
+  RST_SWEEP(ctx, k_pre_out, n, n, parent, w, gl.d1, plan.cap[1], pre, nd, counters);
+  RST_HIP(hipGetLastError());
+  RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
+                         hipMemcpyDeviceToHost, ctx->stream));
+  RST_HIP(hipStreamSynchronize(ctx->stream));
+  if (ctx->host_pinned[kCntGOverflow]) {
+    // rebuild the words (the walks overwrote them) and rank every arc
+    RST_TRY(enqueue_fill(ctx, counters + kCntBccRoots, 1, 0));
+    RST_SWEEP(ctx, k_pre_words, n, n, parent, head, next, w, gl.heads[0], plan.hcap, counters);
+    RST_HIP(hipGetLastError());
+    RST_TRY(enqueue_rank_rounds(ctx, 2 * n, w, rank_rounds_for(2 * n), nullptr, nullptr));
+    RST_SWEEP(ctx, k_pre_out_rounds, n, n, parent, w, pre, nd, counters);
+    RST_HIP(hipGetLastError());
+    RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    RST_HIP(hipStreamSynchronize(ctx->stream));
+  }
   return RST_OK;
 }
 
