@@ -42,8 +42,8 @@ __device__ __forceinline__ int2 bc_comb(int2 a, int2 b) {
 
 // Calls f(j, u, w, a) for every arc a = (u -> w) of the vertices
 // [v0, v0 + kBcChunk) (j = u - v0): their degrees scanned in LDS, the union
-// of their arcs walked with unit stride.  Called by all threads of the
-// workgroup; ends with a barrier.
+// of their arcs walked with unit stride; lanes past the last arc call it with
+// j = -1.  Called by all threads of the workgroup; ends with a barrier.
 template <class OffT, class F>
 __device__ __forceinline__ void bc_chunk_arcs(int64_t n, int64_t v0, const OffT *__restrict__ off,
                                               const int32_t *__restrict__ cols, int *s_scan,
@@ -64,13 +64,39 @@ __device__ __forceinline__ void bc_chunk_arcs(int64_t n, int64_t v0, const OffT 
   __syncthreads();
   for (int b0 = 0; b0 < total; b0 += kBcChunk) {
     const int k = b0 + t;
+    // every lane calls f (j = -1 past the arcs), so f may use wave operations
+    int j = -1;
+    int32_t w = -1;
+    int64_t a = -1;
     if (k < total) {
-      const int j = lds_upper_search(s_scan, kBcChunk, k);
-      const OffT a = s_beg[j] + (OffT)(k - s_scan[j]);
-      f(j, (int32_t)(v0 + j), cols[a], (int64_t)a);
+      j = lds_upper_search(s_scan, kBcChunk, k);
+      a = (int64_t)(s_beg[j] + (OffT)(k - s_scan[j]));
+      w = cols[a];
     }
+    f(j, (int32_t)(v0 + j), w, a);
   }
   __syncthreads();
+}
+
+// Extremes (x: min, y: max) of the lanes of each run of equal j (runs are
+// contiguous: the arcs of a vertex sit on consecutive lanes), combined into
+// s_x[j], s_y[j] by the run's last lane only.  Called by all lanes of the wave
+// (j < 0: no vertex, value ignored).  The arcs of a hub fill whole waves:
+// an LDS atomic per arc on one word serialised the pass (15 ms on a graph
+// with hubs of degree 1.6e5).
+__device__ __forceinline__ void bc_run_extremes(int j, int2 val, int *s_x, int *s_y) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int jo = __shfl_up(j, o, 64);
+    const int2 w = make_int2(__shfl_up(val.x, o, 64), __shfl_up(val.y, o, 64));
+    if (lane >= o && jo == j) val = bc_comb(val, w);
+  }
+  const int jn = __shfl_down(j, 1, 64);
+  if (j >= 0 && (lane == kWave - 1 || jn != j)) {
+    atomicMin(&s_x[j], val.x);
+    atomicMax(&s_y[j], val.y);
+  }
 }
 
 __device__ __forceinline__ bool bc_is_root(int32_t v, int32_t p, int64_t n) {
@@ -97,11 +123,15 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT
     s_hi[t] = pv;
     bc_chunk_arcs(n, v0, off, cols, s_scan, s_beg, s_wave,
                   [&](int j, int32_t u, int32_t w, int64_t) {
-                    if (w == u || w < 0 || w >= n) return;
-                    if (w == parent[u] || parent[w] == u) return;   // tree arc or a copy
-                    const int32_t pw = pre[w];
-                    atomicMin(&s_lo[j], pw);
-                    atomicMax(&s_hi[j], pw);
+                    int2 val = make_int2(INT32_MAX, INT32_MIN);
+                    // non-tree arcs only (arcs to the parent or a child, and
+                    // their parallel copies, are tree arcs)
+                    if (j >= 0 && w != u && w >= 0 && w < n && w != parent[u] &&
+                        parent[w] != u) {
+                      const int32_t pw = pre[w];
+                      val = make_int2(pw, pw);
+                    }
+                    bc_run_extremes(j, val, s_lo, s_hi);
                   });
     if (v < n) {
       if (pv >= 0 && pv < n) A[pv] = make_int2(s_lo[t], s_hi[t]);
@@ -194,7 +224,7 @@ __global__ __launch_bounds__(B) void k_bcc_rule_tree(int64_t n, const int32_t *_
         atomicOr(&counters[kCntRangeErr], 1);
       } else {
         const int2 lh = bc_range(pv, pv + sv - 1, A, pfx, sfx, st, nb);
-        if (lh.x < pp || lh.y >= pp + sp) hook_edge<false>((int32_t)v, p, L, nullptr, nullptr);
+        if (lh.x < pp || lh.y >= pp + sp) hook_join<true>((int32_t)v, p, L);
       }
     }
   }
@@ -216,11 +246,11 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_rule_cross(int64_t n, const
   const int64_t chunks = (n + kBcChunk - 1) / kBcChunk;
   for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x)
     bc_chunk_arcs(n, c * kBcChunk, off, cols, s_scan, s_beg, s_wave,
-                  [&](int, int32_t u, int32_t w, int64_t) {
-                    if (w == u || w < 0 || w >= n) return;
+                  [&](int j, int32_t u, int32_t w, int64_t) {
+                    if (j < 0 || w == u || w < 0 || w >= n) return;
                     if (w == parent[u] || parent[w] == u) return;
                     const int64_t pu = pre[u], pw = pre[w];
-                    if (pu < pw && pw >= pu + nd[u]) hook_edge<false>(u, w, L, nullptr, nullptr);
+                    if (pu < pw && pw >= pu + nd[u]) hook_join<true>(u, w, L);
                   });
   block_release_device();
 }
@@ -248,15 +278,16 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_arcs(int64_t n, const OffT 
     bc_chunk_arcs(n, v0, off, cols, s_scan, s_beg, s_wave,
                   [&](int j, int32_t u, int32_t w, int64_t a) {
                     int32_t lab = -1;
-                    if (w != u && w >= 0 && w < n) {
+                    int2 val = make_int2(INT32_MAX, -1);
+                    if (j >= 0 && w != u && w >= 0 && w < n) {
                       const int32_t child = parent[w] == u ? w
                                           : parent[u] == w ? u
                                           : (pre[u] > pre[w] ? u : w);
                       lab = L[child];
-                      atomicMin(&s_mn[j], lab);
-                      atomicMax(&s_mx[j], lab);
+                      val = make_int2(lab, lab);
                     }
-                    arc_label[a] = lab;
+                    if (j >= 0) arc_label[a] = lab;
+                    bc_run_extremes(j, val, s_mn, s_mx);
                   });
     bool comp = false;
     if (v < n) {

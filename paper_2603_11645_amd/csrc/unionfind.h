@@ -70,6 +70,23 @@ __device__ __forceinline__ int32_t hook_record(int32_t u, int32_t v, int32_t *cc
   return -1;
 }
 
+// Join the trees of u and v, recording nothing (labels only); kTestFirst as
+// for hook_record.
+template <bool kTestFirst>
+__device__ __forceinline__ void hook_join(int32_t u, int32_t v, int32_t *cc) {
+  int32_t ru = find_root(u, cc);
+  int32_t rv = find_root(v, cc);
+  while (ru != rv) {
+    const int32_t lo = ru < rv ? ru : rv;
+    const int32_t hi = ru < rv ? rv : ru;
+    int32_t old = hi;
+    if (kTestFirst) old = cc[hi];
+    if (old == hi) old = atomicCAS(&cc[hi], hi, lo);
+    if (old == hi) return;
+    if (ru == hi) ru = old; else rv = old;
+  }
+}
+
 // Hook the trees of u and v; on success record (u,v) at the hooked root (and
 // link its two arcs when head is non-NULL).
 template <bool kRecord>
@@ -81,15 +98,7 @@ __device__ __forceinline__ void hook_edge(int32_t u, int32_t v, int32_t *cc, int
     if (x >= 0 && head) link_slot(x, u, v, head, next);
     return;
   }
-  int32_t ru = find_root(u, cc);
-  int32_t rv = find_root(v, cc);
-  while (ru != rv) {
-    const int32_t lo = ru < rv ? ru : rv;
-    const int32_t hi = ru < rv ? rv : ru;
-    const int32_t old = atomicCAS(&cc[hi], hi, lo);
-    if (old == hi) return;
-    if (ru == hi) ru = old; else rv = old;
-  }
+  hook_join<false>(u, v, cc);
 }
 
 // Put `item` in front of list `key` (head[key]) for every lane with `pred`,
