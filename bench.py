@@ -262,6 +262,8 @@ def main():
                          "else --steps)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-bfs", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the library defaults instead of the committed autotuner cache")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--batch-graphs", type=int, default=4096, help="C5: graphs in the batch")
@@ -291,6 +293,19 @@ def main():
     off = torch.from_numpy(g.offsets_typed()).cuda()
     cols = torch.from_numpy(g.cols).cuda()
     ctx = rst.Context(0)
+    # the autotuner's choice for this graph's size class (paper_2603_11645_amd/
+    # autotune.py writes the cache; every timed output is verified either way)
+    tuning = {"cache": None, "applied": False}
+    tune_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2603_11645_amd",
+                             "tuned_gfx950.json")
+    if not args.no_tune and os.path.exists(tune_path):
+        applied = ctx.tune_load(tune_path, off, cols, "gconn")
+        tuning = {"cache": "paper_2603_11645_amd/tuned_gfx950.json", "applied": applied,
+                  "options": {k: ctx.get_option(getattr(rst, k)) for k in
+                              ("OPT_HOOK_MODE", "OPT_HOOK_SAMPLE", "OPT_SWEEP_BLOCK",
+                               "OPT_HEAVY_DEGREE", "OPT_RANK_ELEMS_PER_THREAD",
+                               "OPT_RANK_STRIDE")}}
+        log("[bench] tuning cache: %s" % tuning)
 
     if args.calibrate_copy:
         src = torch.empty(64 << 20, dtype=torch.int32, device="cuda").fill_(1)
@@ -440,6 +455,7 @@ def main():
         "roofline": roofline,
         "gconn_tree_depth": int(gconn_depth), "tree_depth_ms": round(depth_ms, 3),
         "downstream": downstream,
+        "tuning": tuning,
         "bfs": bfs,
         "paper_context": "GConn+Euler up to 300x faster than optimised BFS on high-diameter "
                          "graphs, NVIDIA L40S (other hardware; context only)",
