@@ -147,6 +147,13 @@ static bool wants_sparse_rank(const rst_ctx *ctx, const rst_csr *g, bool global)
 static rst_status enqueue_hook(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, bool global,
                                int64_t *chunks, int64_t chunk_cap, int2 *cross,
                                int32_t *tile_cross) {
+  if (f.gsel) {
+    // a batch hooked graph by graph: the tile pass over the graphs with id
+    // locality (it initialises every vertex, the others as singletons), then
+    // the global sweep over the rest; no edge joins two graphs
+    RST_TRY(enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross));
+    return enqueue_hook_global(ctx, g, f, false);
+  }
   if (global) return enqueue_hook_global(ctx, g, f);
   return enqueue_hook_csr(ctx, g, f, chunks, chunk_cap, cross, tile_cross);
 }
@@ -319,8 +326,8 @@ static rst_status finish_gconn(rst_ctx *ctx, const rst_csr *g, int32_t *parent, 
       (!w.global_hook && ctx->host_pinned[kCntCrossOverflow] ? RST_PATH_CROSS_GLOBAL : 0) |
       (last_resort ? RST_PATH_RANK_GLOBAL : 0) | (groups ? RST_PATH_CROSS_GROUPS : 0) |
       (w.sparse_ran && !last_resort ? RST_PATH_RANK_SPARSE : 0) |
-      (w.global_hook ? RST_PATH_HOOK_GLOBAL : 0) |
-      (w.global_hook && ctx->host_pinned[kCntGiant] >= 0 ? RST_PATH_HOOK_GIANT : 0);
+      (w.global_hook || w.f.gsel ? RST_PATH_HOOK_GLOBAL : 0) |
+      ((w.global_hook || w.f.gsel) && ctx->host_pinned[kCntGiant] >= 0 ? RST_PATH_HOOK_GIANT : 0);
   if (ctx->host_pinned[kCntRangeErr]) return RST_E_INVAL;
   if (ctx->host_pinned[kCntRootErr]) return RST_E_INVAL;
   *components = ctx->host_pinned[kCntComponents];
@@ -350,11 +357,13 @@ static rst_status run_gconn_euler_work(rst_ctx *ctx, const rst_csr *g, const int
                                        int64_t *components, GconnWork &w, bool *sparse,
                                        bool *global_hook) {
   int32_t *counters = w.f.counters;
-  RST_TRY(choose_hook(ctx, g, w.f.vmask, counters, &w.global_hook));
+  // a batch hooked graph by graph decides on the device (f.gsel)
+  if (w.f.gsel) w.global_hook = false;
+  else RST_TRY(choose_hook(ctx, g, w.f.vmask, counters, &w.global_hook));
   if (global_hook) *global_hook = w.global_hook;
   RST_TRY(enqueue_gconn_forest(ctx, g, roots, nroots, parent, st, w));
   RST_TRY(read_counters(ctx, counters));
-  w.sparse = wants_sparse_rank(ctx, g, w.global_hook);
+  w.sparse = w.f.gsel ? true : wants_sparse_rank(ctx, g, w.global_hook);
   if (sparse) *sparse = w.sparse;
   RST_TRY(enqueue_gconn_rank(ctx, g, parent, st, w));
   return finish_gconn(ctx, g, parent, st, components, w);
@@ -489,6 +498,7 @@ struct BatchWork {
   int32_t *counters = nullptr;
   uint8_t *m = nullptr;       // [G] method of each graph (1: BFS)
   uint8_t *vmask = nullptr;   // [n] 1 for the vertices of BFS graphs
+  uint8_t *gsel = nullptr;    // [n] hooking graph by graph: 1 for the global sweep's graphs
   int32_t *level = nullptr;   // [n] BFS levels
   BfsBufs bb;
   GconnWork w;
@@ -517,6 +527,7 @@ static rst_status enqueue_batch_device(rst_ctx *ctx, const rst_csr *g, const rst
   }
   RST_TRY(enqueue_count_methods(ctx, b, bw.m, bw.counters));
   RST_TRY(enqueue_graph_mask(ctx, b, bw.m, bw.vmask));
+  if (bw.w.f.gsel) RST_TRY(enqueue_batch_hook_split(ctx, g, b, bw.m, bw.gsel));
   RST_TRY(enqueue_gconn_forest(ctx, g, b->roots, G, parent, nullptr, bw.w));
   RST_TRY(enqueue_gconn_rank(ctx, g, parent, nullptr, bw.w));
   RST_TRY(bfs_reset(ctx, n, bw.level, nullptr, bw.bb));
@@ -614,6 +625,7 @@ static rst_status run_batch_eager(rst_ctx *ctx, const rst_csr *g, const rst_batc
   const int32_t nbfs = ctx->host_pinned[kCntBatchBfs];
   const int64_t bfs_vertices = ctx->host_pinned[kCntBatchBfsVtx];
   RST_TRY(enqueue_graph_mask(ctx, b, bw.m, bw.vmask));
+  if (bw.w.f.gsel) RST_TRY(enqueue_batch_hook_split(ctx, g, b, bw.m, bw.gsel));
   int64_t comps = 0;
   if (nbfs < G) {
     rst_stats inner;
@@ -1187,20 +1199,24 @@ rst_status rst_spanning_forest_batch(rst_ctx *ctx, const rst_csr *g, const rst_b
   const int32_t G = b->num_graphs;
   const int64_t n = g->n;
   RST_TRY(ws_reserve(ctx, ws_bytes(64, 4) + gconn_ws_bytes(ctx, g) + bfs_ws_bytes(ctx, g) +
-                              ws_bytes(n, 4) + ws_bytes(n, 1) + ws_bytes(G, 1) + ws_bytes(G, 4) +
+                              ws_bytes(n, 4) + 2 * ws_bytes(n, 1) + ws_bytes(G, 1) + ws_bytes(G, 4) +
                               (method ? 0 : selector_scratch_bytes(ctx, g, G))));
   BatchWork bw;
   bw.counters = ws_take<int32_t>(ctx, 64);
   bw.m = ws_take<uint8_t>(ctx, G);
   bw.vmask = ws_take<uint8_t>(ctx, n);
+  bw.gsel = ws_take<uint8_t>(ctx, n);
   bw.level = ws_take<int32_t>(ctx, n);
   RST_TRY(take_bfs_bufs(ctx, g, bw.bb));
   int32_t *giants = ws_take<int32_t>(ctx, G);
   bw.w = take_gconn_work(ctx, g, bw.counters, nullptr, bw.vmask);
-  // the global sweep seeks a dominant tree in every packed graph
+  // the global sweep seeks a dominant tree in every packed graph; with the
+  // hooking variant left to the library, each graph gets its own (tile pass
+  // where its ids carry locality, global sweep where they do not)
   bw.w.f.vtx_off = b->vtx_off;
   bw.w.f.num_graphs = G;
   bw.w.f.giants = giants;
+  if (ctx->opt.hook_mode == 0 && G > 1 && g->nnz < ((int64_t)1 << 31)) bw.w.f.gsel = bw.gsel;
   bw.sel_scratch = ctx->ws.used;   // the selector's scratch follows (method == NULL)
 
   const bool graph_path = ctx->opt.graphs && !stats && !ctx->opt.validate;

@@ -19,6 +19,53 @@ __global__ __launch_bounds__(kBlock) void k_graph_mask(const int64_t *__restrict
   for (int64_t v = b + threadIdx.x; v < e; v += kBlock) vmask[v] = m;
 }
 
+// Hooking variant per graph of a batch (GConn+Euler graphs; BFS graphs get 0):
+// up to 4 arcs of each of up to kSplitSamples pseudo-randomly chosen vertices,
+// and the share of them that leave their source's 8192-id tile.  More than
+// half: the graph's ids carry no locality and the global sweep hooks it
+// (gsel 1 for its vertices), else the tile pass (gsel 0).
+constexpr int kSplitThreads = 256;
+constexpr int kSplitSamples = 1024;
+constexpr int kSplitTileShift = 13;   // the tile pass's 8192-id tiles
+
+__device__ __forceinline__ uint64_t split_mix(uint64_t z) {   // splitmix64 finaliser
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <class OffT>
+__global__ __launch_bounds__(kSplitThreads) void k_batch_hook_split(const int64_t *__restrict__ vtx_off,
+                                                                    const OffT *__restrict__ off,
+                                                                    const int32_t *__restrict__ cols,
+                                                                    const uint8_t *__restrict__ method,
+                                                                    uint8_t *gsel) {
+  __shared__ int s_arcs, s_cross;
+  const int g = blockIdx.x;
+  const int64_t lo = vtx_off[g], ng = vtx_off[g + 1] - lo;
+  if (threadIdx.x == 0) { s_arcs = 0; s_cross = 0; }
+  __syncthreads();
+  if (!method[g]) {
+    int arcs = 0, cross = 0;
+    for (int i = threadIdx.x; i < kSplitSamples && (int64_t)i < ng; i += kSplitThreads) {
+      const int64_t v = lo + (ng <= kSplitSamples ? (int64_t)i
+                                                  : (int64_t)(split_mix(((uint64_t)g << 20) ^ i) %
+                                                              (uint64_t)ng));
+      const OffT b = off[v], e = off[v + 1];
+      for (OffT a = b; a < e && a < b + 4; ++a) {
+        ++arcs;
+        cross += (cols[a] >> kSplitTileShift) != (int32_t)(v >> kSplitTileShift);
+      }
+    }
+    atomicAdd(&s_arcs, arcs);
+    atomicAdd(&s_cross, cross);
+  }
+  __syncthreads();
+  const uint8_t sel = (!method[g] && 2 * s_cross > s_arcs) ? 1 : 0;
+  for (int64_t v = lo + threadIdx.x; v < lo + ng; v += kSplitThreads) gsel[v] = sel;
+}
+
 // Consistency of the offset tables and roots: vtx_off non-decreasing, the
 // arc table matching the CSR offsets, every root inside its own graph.
 template <class OffT>
@@ -113,6 +160,20 @@ rst_status enqueue_graph_mask(rst_ctx *ctx, const rst_batch *b, const uint8_t *m
                               uint8_t *vmask) {
   hipLaunchKernelGGL(k_graph_mask, dim3((unsigned)b->num_graphs), dim3(kBlock), 0, ctx->stream,
                      b->vtx_off, method, vmask);
+  RST_HIP(hipGetLastError());
+  return RST_OK;
+}
+
+rst_status enqueue_batch_hook_split(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                                    const uint8_t *method, uint8_t *gsel) {
+  if (g->offset_bytes == 4)
+    hipLaunchKernelGGL(k_batch_hook_split<int32_t>, dim3((unsigned)b->num_graphs),
+                       dim3(kSplitThreads), 0, ctx->stream, b->vtx_off,
+                       (const int32_t *)g->offsets, g->cols, method, gsel);
+  else
+    hipLaunchKernelGGL(k_batch_hook_split<int64_t>, dim3((unsigned)b->num_graphs),
+                       dim3(kSplitThreads), 0, ctx->stream, b->vtx_off,
+                       (const int64_t *)g->offsets, g->cols, method, gsel);
   RST_HIP(hipGetLastError());
   return RST_OK;
 }

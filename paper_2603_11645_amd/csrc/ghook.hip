@@ -71,12 +71,14 @@ __global__ __launch_bounds__(kBlock) void k_gh_sample(int64_t n, const OffT *__r
                                                       const int32_t *__restrict__ cols, int K,
                                                       const uint8_t *__restrict__ vmask, int32_t *cc,
                                                       int32_t *tu, int32_t *tv, int32_t *head,
-                                                      int32_t *next) {
+                                                      int32_t *next,
+                                                      const uint8_t *__restrict__ gsel) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int lane = (int)(threadIdx.x & (kWave - 1));
   for (int64_t vw = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane; vw < n; vw += stride) {
     const int64_t v = vw + lane;
-    const bool live = v < n && !(vmask && vmask[v]);
+    // (in a batch hooked graph by graph, only the global sweep's graphs)
+    const bool live = v < n && !(vmask && vmask[v]) && !(gsel && !gsel[v]);
     OffT b = 0;
     uint64_t deg = 0;
     if (live) {
@@ -154,6 +156,7 @@ constexpr int kGhBatchHash = 2048;
 __global__ __launch_bounds__(kGhBatchThreads) void k_gh_giants(const int64_t *__restrict__ vtx_off,
                                                                const int32_t *__restrict__ cc,
                                                                const uint8_t *__restrict__ vmask,
+                                                               const uint8_t *__restrict__ gsel,
                                                                int32_t *giants, int32_t *counters) {
   __shared__ int32_t keys[kGhBatchHash];
   __shared__ int32_t cnts[kGhBatchHash];
@@ -170,7 +173,7 @@ __global__ __launch_bounds__(kGhBatchThreads) void k_gh_giants(const int64_t *__
     const int64_t off = ng <= kGhBatchSamples ? (int64_t)i
                                               : (int64_t)(gh_mix(((uint64_t)g << 20) ^ (uint64_t)i) % (uint64_t)ng);
     const int32_t v = (int32_t)(lo + off);
-    if (vmask && vmask[v]) continue;
+    if ((vmask && vmask[v]) || (gsel && !gsel[v])) continue;
     ++valid;
     const int32_t r = gh_root(v, cc);
     uint32_t h = ((uint32_t)r * 0x9E3779B1u) >> (32 - 11);
@@ -226,7 +229,8 @@ __global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const Off
                                                             int32_t *counters,
                                                             const int64_t *__restrict__ vtx_off,
                                                             int num_graphs,
-                                                            const int32_t *__restrict__ giants) {
+                                                            const int32_t *__restrict__ giants,
+                                                            const uint8_t *__restrict__ gsel) {
   __shared__ int s_scan[kGhThreads + 1];
   __shared__ OffT s_beg[kGhThreads];
   __shared__ int s_wave[kGhThreads / kWave];
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const Off
     const int64_t v = v0 + t;
     int deg = 0;
     OffT beg = 0;
-    if (v < n && !(vmask && vmask[v])) {
+    if (v < n && !(vmask && vmask[v]) && !(gsel && !gsel[v])) {
       const OffT b = off[v], e = off[v + 1];
       if (e > b) locals += (cols[b] >> kGhTileShift) == (int32_t)(v >> kGhTileShift);
       beg = b;
@@ -344,27 +348,29 @@ int ghook_sample_arcs(const rst_ctx *ctx, const rst_csr *g) {
   return g->nnz >= 6 * g->n ? 2 : 0;
 }
 
-rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f) {
+rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, bool init) {
   const int64_t n = g->n;
   const int K = ghook_sample_arcs(ctx, g);
   RST_KMARK(ctx, RST_KERNEL_HOOK_SAMPLE, 0);
-  RST_SWEEP(ctx, k_gh_init, n, n, f.cc, f.tu, f.tv, f.head);
-  RST_HIP(hipGetLastError());
+  if (init) {
+    RST_SWEEP(ctx, k_gh_init, n, n, f.cc, f.tu, f.tv, f.head);
+    RST_HIP(hipGetLastError());
+  }
   if (K > 0) {
     const unsigned sgrid = gh_grid(ctx, grid_for(n, kBlock), 8);
     if (g->offset_bytes == 4)
       hipLaunchKernelGGL(k_gh_sample<int32_t>, dim3(sgrid), dim3(kBlock), 0, ctx->stream, n,
                          (const int32_t *)g->offsets, g->cols, K, f.vmask, f.cc, f.tu, f.tv,
-                         f.head, f.next);
+                         f.head, f.next, f.gsel);
     else
       hipLaunchKernelGGL(k_gh_sample<int64_t>, dim3(sgrid), dim3(kBlock), 0, ctx->stream, n,
                          (const int64_t *)g->offsets, g->cols, K, f.vmask, f.cc, f.tu, f.tv,
-                         f.head, f.next);
+                         f.head, f.next, f.gsel);
     RST_HIP(hipGetLastError());
     if (f.giants && f.num_graphs > 1) {
       RST_TRY(enqueue_fill(ctx, f.counters + kCntGiant, 1, -1));
       hipLaunchKernelGGL(k_gh_giants, dim3(f.num_graphs), dim3(kGhBatchThreads), 0, ctx->stream,
-                         f.vtx_off, f.cc, f.vmask, f.giants, f.counters);
+                         f.vtx_off, f.cc, f.vmask, f.gsel, f.giants, f.counters);
     } else {
       hipLaunchKernelGGL(k_gh_giant, dim3(1), dim3(kGhSampleThreads), 0, ctx->stream, n, f.cc,
                          f.vmask, f.counters);
@@ -381,11 +387,11 @@ rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f) {
   if (g->offset_bytes == 4)
     hipLaunchKernelGGL(k_gh_sweep<int32_t>, dim3(grid), dim3(kGhThreads), 0, ctx->stream, n,
                        (const int32_t *)g->offsets, g->cols, f.vmask, f.cc, f.tu, f.tv, f.head,
-                       f.next, f.counters, f.vtx_off, f.num_graphs, batch_giants);
+                       f.next, f.counters, f.vtx_off, f.num_graphs, batch_giants, f.gsel);
   else
     hipLaunchKernelGGL(k_gh_sweep<int64_t>, dim3(grid), dim3(kGhThreads), 0, ctx->stream, n,
                        (const int64_t *)g->offsets, g->cols, f.vmask, f.cc, f.tu, f.tv, f.head,
-                       f.next, f.counters, f.vtx_off, f.num_graphs, batch_giants);
+                       f.next, f.counters, f.vtx_off, f.num_graphs, batch_giants, f.gsel);
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_HOOK_GLOBAL, 1);
   return RST_OK;

@@ -142,7 +142,8 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
     int64_t n, const OffT *__restrict__ off, const int32_t *__restrict__ cols, int32_t *cc,
     int32_t *tu, int32_t *tv, int2 *cross, int32_t *tile_cross, int32_t *tile_lvl,
     int64_t *region_of, int32_t *counters, int64_t *chunks, int64_t chunk_cap, int heavy_deg,
-    const uint8_t *__restrict__ vmask, int32_t *head, int32_t *next, int vec_cols) {
+    const uint8_t *__restrict__ vmask, int32_t *head, int32_t *next, int vec_cols,
+    const uint8_t *__restrict__ gsel) {
   __shared__ int lp[kTile];
   __shared__ __align__(16) int16_t s16[2 * kTile];
   __shared__ int s_gbase[kTile / kTileGroup + 1];   // light arcs before each group; [last] = all
@@ -191,8 +192,9 @@ __global__ __launch_bounds__(kTileThreads, 8) void k_hook_tile(
   for (int j = 0; j < kTilePer; ++j) {
     const int li = tid * kTilePer + j;
     dg[j] = 0;
-    // a masked vertex (its graph is handled by another method) offers no arcs
-    if (li < cnt && !(vmask && vmask[v0 + li])) {
+    // a masked vertex (its graph is handled by another method, or hooked by
+    // the global sweep) offers no arcs
+    if (li < cnt && !(vmask && vmask[v0 + li]) && !(gsel && gsel[v0 + li])) {
       const int64_t d = (int64_t)(o[j + 1] - o[j]);
       if (d > light_max) {
         const int64_t v = v0 + li;
@@ -1054,7 +1056,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     hipLaunchKernelGGL(k_hook_tile<int32_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
                        off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, region_of,
                        f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask, f.head,
-                       f.next, vec_cols);
+                       f.next, vec_cols, f.gsel);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));
@@ -1066,7 +1068,7 @@ rst_status enqueue_hook_csr(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, int64
     hipLaunchKernelGGL(k_hook_tile<int64_t>, dim3(tiles), dim3(kTileThreads), 0, ctx->stream, n,
                        off, g->cols, f.cc, f.tu, f.tv, cross, tile_cross, tile_lvl, region_of,
                        f.counters, chunks, chunk_cap, ctx->opt.heavy_degree, f.vmask, f.head,
-                       f.next, vec_cols);
+                       f.next, vec_cols, f.gsel);
     RST_HIP(hipGetLastError());
     RST_KMARK(ctx, RST_KERNEL_HOOK_TILE, 1);
     RST_TRY(launch_cross(ctx, tiles, levels, region_of, cross, tile_cross, tile_lvl, kept_list, f));

@@ -60,6 +60,11 @@ struct GraphCache;
 // batch.hip
 rst_status enqueue_graph_mask(rst_ctx *ctx, const rst_batch *b, const uint8_t *method,
                               uint8_t *vmask);
+// per vertex of a batch: 1 when its graph (a GConn+Euler one) is hooked by the
+// global sweep -- most of a sample of its arcs leave their source's 8192-id
+// tile -- else 0
+rst_status enqueue_batch_hook_split(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
+                                    const uint8_t *method, uint8_t *gsel);
 rst_status enqueue_batch_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
                                int32_t *counters);
 rst_status enqueue_batch_arcs_check(rst_ctx *ctx, const rst_csr *g, const rst_batch *b,
@@ -162,6 +167,10 @@ struct ForestBufs {
   const int64_t *vtx_off = nullptr;
   int32_t num_graphs = 0;
   int32_t *giants = nullptr;
+  // Batches hooked graph by graph (nullable): per vertex 1 when its graph is
+  // hooked by the global sweep, 0 when by the tile pass (which then runs
+  // first and also initialises every vertex the sweep hooks).
+  const uint8_t *gsel = nullptr;
 };
 
 enum {
@@ -220,7 +229,8 @@ size_t hook_chunk_capacity(const rst_ctx *ctx, int64_t nnz);
 // locality): optional sampling of each vertex's first arcs, a dominant root,
 // then the remaining arcs; fills f.cc, f.tu, f.tv (and the arc lists when
 // f.head is set) like enqueue_hook_csr.  Needs nnz < 2^31.
-rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f);
+// init false: every vertex was initialised by the tile pass (f.gsel batches)
+rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, bool init = true);
 int ghook_sample_arcs(const rst_ctx *ctx, const rst_csr *g);
 // one workgroup samples arcs; counters[kCntProbeArcs], [kCntProbeCross] (zeroed
 // by the caller beforehand) receive how many there were and how many left

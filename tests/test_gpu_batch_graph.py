@@ -155,3 +155,27 @@ def test_global_sweep_with_a_dominant_tree_per_graph(rst, sample):
             check(b, parent.cpu().numpy(), m)
     _, _, st = c.spanning_forest_batch(*args, method=dev(method), stats=True)
     assert st["paths"] & rst.PATH_HOOK_GLOBAL and st["paths"] & rst.PATH_HOOK_GIANT, st["paths"]
+
+
+def test_hooking_chosen_graph_by_graph(rst):
+    """With the hooking variant left to the library, every GConn+Euler graph of
+    a batch gets its own: the tile pass for graphs whose ids carry locality
+    (meshes numbered along the mesh), the global sweep with its own dominant
+    tree for the others (R-MAT, permuted grids, long chains); replays."""
+    graphs = [I.road_mesh(200, 0.15, 0.01, seed=21), I.rmat_lcc(15, 8, seed=22),
+              I.grid_permuted(150, seed=23), I.long_chain(30000, 0.01, 16, seed=24, offset_bytes=4),
+              I.road_mesh(90, 0.1, 0.0, seed=25), I.random_graph(20000, 40000, seed=26),
+              I.path(500), I.star(3000, 7)]
+    b = I.pack(graphs)
+    G = b.num_graphs
+    c = rst.Context(0)
+    g = b.graph
+    args = (dev(g.offsets_typed()), dev(g.cols), dev(b.vtx_off), dev(b.arc_off), dev(b.roots))
+    parent = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for m in (np.zeros(G, np.uint8), (np.arange(G) % 3 == 2).astype(np.uint8)):
+        for call in range(3):
+            parent.fill_(-7)
+            c.spanning_forest_batch(*args, method=dev(m), parent=parent)
+            check(b, parent.cpu().numpy(), m)
+    _, _, st = c.spanning_forest_batch(*args, method=dev(np.zeros(G, np.uint8)), stats=True)
+    assert st["paths"] & rst.PATH_HOOK_GLOBAL, st["paths"]
