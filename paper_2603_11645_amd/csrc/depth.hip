@@ -101,6 +101,36 @@ __global__ __launch_bounds__(B) void k_depth_words(int64_t n, const int32_t *__r
   tour_words<false>(n, parent, head, next, w, heads, hcap, counters);
 }
 
+// Preorder ranking in 32-bit words: each arc's word is its successor (-2 for
+// an arc of no list), the weight (1 down, 0 up) following from the
+// successor's parity in the walk; list heads as above.
+template <int B>
+__global__ __launch_bounds__(B) void k_pre_words32(int64_t n, const int32_t *__restrict__ parent,
+                                                   const int32_t *__restrict__ head,
+                                                   const int32_t *__restrict__ next, int32_t *w,
+                                                   int32_t *heads, int64_t hcap, int32_t *counters) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool is_head = false;
+  int32_t h = -1;
+  if (x < n) {
+    const int32_t p = parent[x];
+    int2 out = make_int2(-2, -2);
+    if (depth_is_root((int32_t)x, p, n)) {
+      h = head[x];
+      is_head = h >= 0;
+    } else {
+      const int2 nx = reinterpret_cast<const int2 *>(next)[x];
+      out.x = nx.y != -1 ? nx.y : head[x];
+      int32_t s1 = nx.x;
+      if (s1 == -1) s1 = depth_is_root(p, parent[p], n) ? -1 : head[p];
+      out.y = s1;
+    }
+    reinterpret_cast<int2 *>(w)[x] = out;
+  }
+  const int slot = wave_append(is_head, &counters[kCntGHeads]);
+  if (is_head && slot < hcap) heads[slot] = h;
+}
+
 template <int B>
 __global__ __launch_bounds__(B) void k_pre_words(int64_t n, const int32_t *__restrict__ parent,
                                                  const int32_t *__restrict__ head,
@@ -162,9 +192,10 @@ __device__ __forceinline__ void pre_store(int64_t n, int64_t x, bool root, uint3
   }
 }
 
+// codes (ruler << 8 | weight walked since it) of both arcs, from the 32-bit walk
 template <int B>
 __global__ __launch_bounds__(B) void k_pre_out(int64_t n, const int32_t *__restrict__ parent,
-                                               const uint64_t *__restrict__ w,
+                                               const int32_t *__restrict__ w,
                                                const uint32_t *__restrict__ d1, int64_t rw1_cap,
                                                int32_t *pre, int32_t *nd, int32_t *counters) {
   if (counters[kCntGOverflow]) return;   // block-uniform: the caller falls back
@@ -174,10 +205,10 @@ __global__ __launch_bounds__(B) void k_pre_out(int64_t n, const int32_t *__restr
     root = depth_is_root((int32_t)x, parent[x], n);
     uint32_t a = 0, b = 0;
     if (!root) {
-      const uint64_t c0 = w[2 * x], c1 = w[2 * x + 1];
-      const uint32_t r0 = (uint32_t)c0, r1 = (uint32_t)c1;
-      a = r0 < rw1_cap ? d1[r0] - (uint32_t)(c0 >> 32) : 0u;
-      b = r1 < rw1_cap ? d1[r1] - (uint32_t)(c1 >> 32) : 0u;
+      const int2 c = reinterpret_cast<const int2 *>(w)[x];
+      const uint32_t r0 = (uint32_t)c.x >> 8, r1 = (uint32_t)c.y >> 8;
+      a = r0 < rw1_cap ? d1[r0] - ((uint32_t)c.x & 255u) : 0u;
+      b = r1 < rw1_cap ? d1[r1] - ((uint32_t)c.y & 255u) : 0u;
     }
     pre_store(n, x, root, a, b, pre, nd);
   }
@@ -252,10 +283,13 @@ rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int
   RST_TRY(enqueue_fill(ctx, head, n, -1));
   RST_SWEEP(ctx, k_depth_link, n, n, parent, head, next);
   RST_HIP(hipGetLastError());
-  RST_SWEEP(ctx, k_pre_words, n, n, parent, head, next, w, gl.heads[0], plan.hcap, counters);
+  // 32-bit words with the weights from the arcs' parity: half the bytes of
+  // (successor, weight) words under the random walk
+  int32_t *w32 = reinterpret_cast<int32_t *>(w);
+  RST_SWEEP(ctx, k_pre_words32, n, n, parent, head, next, w32, gl.heads[0], plan.hcap, counters);
   RST_HIP(hipGetLastError());
-  RST_TRY(enqueue_glist_rank(ctx, w, true, gl, counters));
-  RST_SWEEP(ctx, k_pre_out, n, n, parent, w, gl.d1, plan.cap[1], pre, nd, counters);
+  RST_TRY(enqueue_glist_rank(ctx, w32, false, gl, counters, true));
+  RST_SWEEP(ctx, k_pre_out, n, n, parent, w32, gl.d1, plan.cap[1], pre, nd, counters);
   RST_HIP(hipGetLastError());
   RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
                          hipMemcpyDeviceToHost, ctx->stream));

@@ -132,7 +132,11 @@ __global__ __launch_bounds__(kGlThreads) void k_glist_heads(int64_t A, const uin
 // head list of the next level names h/k); further rulers are opened by walks
 // that reach the piece cap.  Each ruler's word of the next level goes to
 // rw_out[ruler].
-template <bool kL1>
+// kW01 (32-bit words only): the arcs weigh 1 when their id is even and 0 when
+// it is odd (the down and up arcs of a tour by parent edges, whose preorder
+// count this ranks), instead of 1 each; a code's offset is then the weight
+// walked since the ruler, still at most the piece's arcs.
+template <bool kL1, bool kW01 = false>
 __global__ __launch_bounds__(kGlThreads) void k_gwalk(int level, int64_t A, int k1, int k,
                                                       void *words, const int32_t *heads_in,
                                                       int32_t *heads_out, uint64_t *rw_out,
@@ -177,24 +181,28 @@ __global__ __launch_bounds__(kGlThreads) void k_gwalk(int level, int64_t A, int 
       int32_t *w = reinterpret_cast<int32_t *>(words);
       int32_t s = w[e];
       if (s == -2) { rw_out[rid] = kGlHole; continue; }
-      uint32_t off = 0;
+      uint32_t off = 0;   // weight walked since the ruler
+      uint32_t len = 0;   // arcs walked since the ruler
       while (true) {
         w[e] = (int32_t)(((uint32_t)rid << kGlOffBits) | off);
         if (s < 0 || s >= N || ++steps > N) { rw_out[rid] = gl_pack(-1, off); break; }
-        if ((s & kmask) == 0) { rw_out[rid] = gl_pack(s >> ksh, off + 1); break; }
-        if (off == (uint32_t)kGlCap) {
+        const uint32_t ws = kW01 ? (uint32_t)(~s & 1) : 1u;   // weight of the successor
+        if ((s & kmask) == 0) { rw_out[rid] = gl_pack(s >> ksh, off + ws); break; }
+        if (len == (uint32_t)kGlCap) {
           // open a ruler at s: the piece so far ends there
           const int64_t nr = R0 + atomicAdd(dyn, 1);
           if (nr >= limit) {
             atomicOr(&counters[kCntGOverflow], 1);
-            rw_out[rid] = gl_pack(-1, off + 1);
+            rw_out[rid] = gl_pack(-1, off + ws);
             break;
           }
-          rw_out[rid] = gl_pack((int32_t)nr, off + 1);
+          rw_out[rid] = gl_pack((int32_t)nr, off + ws);
           rid = nr;
           off = 0;
+          len = 0;
         } else {
-          ++off;
+          off += ws;
+          ++len;
         }
         e = s;
         s = w[e];
@@ -506,7 +514,7 @@ rst_status enqueue_glist_from_succ(rst_ctx *ctx, int64_t A, const int32_t *succ,
 }
 
 rst_status enqueue_glist_rank(rst_ctx *ctx, void *w1, bool w1_wide, GlistBufs &g,
-                              int32_t *counters) {
+                              int32_t *counters, bool w01) {
   const GlistPlan &p = g.plan;
   RST_TRY(enqueue_fill(ctx, g.lvl, 2 * kGlMaxLevels, 0));   // rulers opened per level
   // walks, bottom up
@@ -522,6 +530,10 @@ rst_status enqueue_glist_rank(rst_ctx *ctx, void *w1, bool w1_wide, GlistBufs &g
         hipLaunchKernelGGL(k_gwalk<false>, dim3(grid), dim3(kGlThreads), 0, ctx->stream, L, p.A,
                            p.k1, p.k1, words, g.heads[0], g.heads[1], g.rw[1], p.cap[1], p.hcap,
                            counters, g.lvl);
+      else if (w01)
+        hipLaunchKernelGGL((k_gwalk<true, true>), dim3(grid), dim3(kGlThreads), 0, ctx->stream, L,
+                           p.A, p.k1, p.k, words, g.heads[0], g.heads[1], g.rw[1], p.cap[1],
+                           p.hcap, counters, g.lvl);
       else
         hipLaunchKernelGGL(k_gwalk<true>, dim3(grid), dim3(kGlThreads), 0, ctx->stream, L, p.A,
                            p.k1, p.k, words, g.heads[0], g.heads[1], g.rw[1], p.cap[1], p.hcap,

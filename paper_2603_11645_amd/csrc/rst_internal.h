@@ -334,10 +334,11 @@ rst_status enqueue_glist_from_slots(rst_ctx *ctx, int64_t slots, int64_t n, cons
 // level-1 words and list heads from a successor array; haspred: A bytes scratch
 rst_status enqueue_glist_from_succ(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *w1,
                                    uint8_t *haspred, GlistBufs &g, int32_t *counters);
-// w1: int32 level-1 words (unit weights), or with w1_wide uint64 (successor,
-// weight) words, whose codes become (offset << 32 | ruler)
+// w1: int32 level-1 words (unit weights; with w01 weight 1 on even arc ids and
+// 0 on odd ones), or with w1_wide uint64 (successor, weight) words, whose
+// codes become (offset << 32 | ruler)
 rst_status enqueue_glist_rank(rst_ctx *ctx, void *w1, bool w1_wide, GlistBufs &g,
-                              int32_t *counters);
+                              int32_t *counters, bool w01 = false);
 rst_status enqueue_glist_parent(rst_ctx *ctx, int64_t slots, int64_t n, const int32_t *tu,
                                 const int32_t *tv, const int32_t *w1, const GlistBufs &g,
                                 const int32_t *cc, const int32_t *comp_root, int32_t *parent,
