@@ -35,15 +35,22 @@ namespace rst {
 constexpr int kBcChunk = 1024;   // vertices per workgroup step of the arc passes
 constexpr int kBcBlock = 64;     // preorder positions per block of the extremum structure
 constexpr int kBcThreads = 256;
+// Vertices with more arcs than kBcHeavy leave the chunk passes: their arcs are
+// cut into items of kBcSlice arcs, one workgroup step each, so that no
+// workgroup walks a hub's arcs alone (on R-MAT graphs the low ids are the
+// hubs, and a chunk of them held tens of millions of arcs: 43 ms on C3).
+constexpr int kBcHeavy = 256;
+constexpr int kBcSlice = 4096;
 
 __device__ __forceinline__ int2 bc_comb(int2 a, int2 b) {
   return make_int2(a.x < b.x ? a.x : b.x, a.y > b.y ? a.y : b.y);
 }
 
 // Calls f(j, u, w, a) for every arc a = (u -> w) of the vertices
-// [v0, v0 + kBcChunk) (j = u - v0): their degrees scanned in LDS, the union
-// of their arcs walked with unit stride; lanes past the last arc call it with
-// j = -1.  Called by all threads of the workgroup; ends with a barrier.
+// [v0, v0 + kBcChunk) (j = u - v0) with at most kBcHeavy arcs: their degrees
+// scanned in LDS, the union of their arcs walked with unit stride; lanes past
+// the last arc call it with j = -1.  Called by all threads of the workgroup;
+// ends with a barrier.
 template <class OffT, class F>
 __device__ __forceinline__ void bc_chunk_arcs(int64_t n, int64_t v0, const OffT *__restrict__ off,
                                               const int32_t *__restrict__ cols, int *s_scan,
@@ -54,7 +61,8 @@ __device__ __forceinline__ void bc_chunk_arcs(int64_t n, int64_t v0, const OffT 
   OffT beg = 0;
   if (v < n) {
     beg = off[v];
-    deg = (int)(off[v + 1] - beg);
+    const int64_t d = (int64_t)(off[v + 1] - beg);
+    deg = d > kBcHeavy ? 0 : (int)d;   // heavy vertices: the item passes
   }
   s_beg[t] = beg;
   int total;
@@ -109,6 +117,7 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT
                                                         const int32_t *__restrict__ cols,
                                                         const int32_t *__restrict__ parent,
                                                         const int32_t *__restrict__ pre, int2 *A,
+                                                        int64_t *items, int64_t item_cap,
                                                         int32_t *counters) {
   __shared__ int s_scan[kBcChunk + 1];
   __shared__ OffT s_beg[kBcChunk];
@@ -119,6 +128,16 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT
   for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
     const int64_t v0 = c * kBcChunk, v = v0 + t;
     const int32_t pv = v < n ? pre[v] : 0;
+    if (v < n) {
+      // a heavy vertex's arcs become items (v, slice) for the item passes
+      const int64_t d = (int64_t)(off[v + 1] - off[v]);
+      if (d > kBcHeavy) {
+        const int64_t ns = (d + kBcSlice - 1) / kBcSlice;
+        const int64_t base = atomicAdd(&counters[kCntBccItems], (int32_t)ns);
+        if (base + ns > item_cap) atomicOr(&counters[kCntRangeErr], 1);
+        for (int64_t k = 0; k < ns && base + k < item_cap; ++k) items[base + k] = (v << 32) | k;
+      }
+    }
     s_lo[t] = pv;   // published by the scan's barriers
     s_hi[t] = pv;
     bc_chunk_arcs(n, v0, off, cols, s_scan, s_beg, s_wave,
@@ -136,6 +155,65 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT
     if (v < n) {
       if (pv >= 0 && pv < n) A[pv] = make_int2(s_lo[t], s_hi[t]);
       else atomicOr(&counters[kCntRangeErr], 1);
+    }
+  }
+}
+
+// The arcs [a0, a1) of heavy item `it` (vertex v, slice k).
+template <class OffT>
+__device__ __forceinline__ int64_t bc_item(const int64_t *__restrict__ items, int64_t it,
+                                           const OffT *__restrict__ off, int64_t *a0, int64_t *a1) {
+  const int64_t item = items[it];
+  const int64_t v = item >> 32, k = item & 0xffffffff;
+  const int64_t b = (int64_t)off[v], e = (int64_t)off[v + 1];
+  *a0 = b + k * kBcSlice;
+  *a1 = *a0 + kBcSlice < e ? *a0 + kBcSlice : e;
+  return v;
+}
+
+// extremes over the workgroup, in thread 0 (called by all threads)
+__device__ __forceinline__ int2 bc_block_extremes(int2 x, int2 *s_red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+    x = bc_comb(x, make_int2(__shfl_xor(x.x, o, 64), __shfl_xor(x.y, o, 64)));
+  if ((threadIdx.x & (kWave - 1)) == 0) s_red[threadIdx.x / kWave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < kBcThreads / kWave; ++w) x = bc_comb(x, s_red[w]);
+  __syncthreads();
+  return x;
+}
+
+// Step 2 for heavy vertices: each item's extremes into A[pre(v)] by atomics
+// (after k_bcc_local wrote the vertex's own).
+template <class OffT>
+__global__ __launch_bounds__(kBcThreads) void k_bcc_local_heavy(int64_t n, const OffT *__restrict__ off,
+                                                                const int32_t *__restrict__ cols,
+                                                                const int32_t *__restrict__ parent,
+                                                                const int32_t *__restrict__ pre,
+                                                                int2 *A, const int64_t *__restrict__ items,
+                                                                int64_t item_cap,
+                                                                const int32_t *__restrict__ counters) {
+  __shared__ int2 s_red[kBcThreads / kWave];
+  int64_t count = counters[kCntBccItems];
+  if (count > item_cap) count = item_cap;
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    int64_t a0, a1;
+    const int32_t u = (int32_t)bc_item(items, it, off, &a0, &a1);
+    const int32_t pu = parent[u];
+    int2 x = make_int2(INT32_MAX, INT32_MIN);
+    for (int64_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+      const int32_t w = cols[a];
+      if (w != u && w >= 0 && w < n && w != pu && parent[w] != u) {
+        const int32_t pw = pre[w];
+        x = bc_comb(x, make_int2(pw, pw));
+      }
+    }
+    x = bc_block_extremes(x, s_red);
+    const int32_t pv = pre[u];
+    if (threadIdx.x == 0 && pv >= 0 && pv < n && x.x <= x.y) {
+      atomicMin(&reinterpret_cast<int *>(A)[2 * (int64_t)pv], x.x);
+      atomicMax(&reinterpret_cast<int *>(A)[2 * (int64_t)pv + 1], x.y);
     }
   }
 }
@@ -255,6 +333,88 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_rule_cross(int64_t n, const
   block_release_device();
 }
 
+// Step 4 for heavy vertices' non-tree edges.  Ends with a release as above.
+template <class OffT>
+__global__ __launch_bounds__(kBcThreads) void k_bcc_cross_heavy(int64_t n, const OffT *__restrict__ off,
+                                                                const int32_t *__restrict__ cols,
+                                                                const int32_t *__restrict__ parent,
+                                                                const int32_t *__restrict__ pre,
+                                                                const int32_t *__restrict__ nd,
+                                                                int32_t *L, const int64_t *__restrict__ items,
+                                                                int64_t item_cap,
+                                                                const int32_t *__restrict__ counters) {
+  int64_t count = counters[kCntBccItems];
+  if (count > item_cap) count = item_cap;
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    int64_t a0, a1;
+    const int32_t u = (int32_t)bc_item(items, it, off, &a0, &a1);
+    const int32_t pu_par = parent[u];
+    const int64_t pu = pre[u], su = nd[u];
+    for (int64_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+      const int32_t w = cols[a];
+      if (w == u || w < 0 || w >= n || w == pu_par || parent[w] == u) continue;
+      const int64_t pw = pre[w];
+      if (pu < pw && pw >= pu + su) hook_join<true>(u, w, L);
+    }
+  }
+  block_release_device();
+}
+
+// Step 5 for heavy vertices: arc labels, and each vertex's label extremes into
+// ext[v] (initialised by k_bcc_arcs) by atomics; k_bcc_art_heavy then decides
+// the articulation points.
+template <class OffT>
+__global__ __launch_bounds__(kBcThreads) void k_bcc_arcs_heavy(int64_t n, const OffT *__restrict__ off,
+                                                               const int32_t *__restrict__ cols,
+                                                               const int32_t *__restrict__ parent,
+                                                               const int32_t *__restrict__ pre,
+                                                               const int32_t *__restrict__ L,
+                                                               int32_t *arc_label, int2 *ext,
+                                                               const int64_t *__restrict__ items,
+                                                               int64_t item_cap,
+                                                               const int32_t *__restrict__ counters) {
+  __shared__ int2 s_red[kBcThreads / kWave];
+  int64_t count = counters[kCntBccItems];
+  if (count > item_cap) count = item_cap;
+  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
+    int64_t a0, a1;
+    const int32_t u = (int32_t)bc_item(items, it, off, &a0, &a1);
+    const int32_t pu = parent[u];
+    int2 x = make_int2(INT32_MAX, -1);
+    for (int64_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+      const int32_t w = cols[a];
+      int32_t lab = -1;
+      if (w != u && w >= 0 && w < n) {
+        const int32_t child = parent[w] == u ? w : pu == w ? u : (pre[u] > pre[w] ? u : w);
+        lab = L[child];
+        x = bc_comb(x, make_int2(lab, lab));
+      }
+      arc_label[a] = lab;
+    }
+    x = bc_block_extremes(x, s_red);
+    if (threadIdx.x == 0 && x.y >= 0) {
+      atomicMin(&reinterpret_cast<int *>(ext)[2 * (int64_t)u], x.x);
+      atomicMax(&reinterpret_cast<int *>(ext)[2 * (int64_t)u + 1], x.y);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBcThreads) void k_bcc_art_heavy(const int64_t *__restrict__ items,
+                                                              int64_t item_cap, const int2 *__restrict__ ext,
+                                                              uint8_t *art,
+                                                              const int32_t *__restrict__ counters) {
+  int64_t count = counters[kCntBccItems];
+  if (count > item_cap) count = item_cap;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < count; it += stride) {
+    const int64_t item = items[it];
+    if ((item & 0xffffffff) != 0) continue;   // once per vertex
+    const int64_t v = item >> 32;
+    const int2 e = ext[v];
+    art[v] = (e.x != INT32_MAX && e.x != e.y) ? 1 : 0;
+  }
+}
+
 // Step 5: arc labels, articulation points, and the number of components
 // (tree edges that are their component's smallest child).
 template <class OffT>
@@ -264,7 +424,7 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_arcs(int64_t n, const OffT 
                                                        const int32_t *__restrict__ pre,
                                                        const int32_t *__restrict__ L,
                                                        int32_t *arc_label, uint8_t *art,
-                                                       int32_t *counters) {
+                                                       int2 *ext, int32_t *counters) {
   __shared__ int s_scan[kBcChunk + 1];
   __shared__ OffT s_beg[kBcChunk];
   __shared__ int s_wave[kBcChunk / kWave];
@@ -291,6 +451,9 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_arcs(int64_t n, const OffT 
                   });
     bool comp = false;
     if (v < n) {
+      // a heavy vertex's arcs are the item pass's; its extremes start from
+      // its own chunk's (none)
+      if ((int64_t)(off[v + 1] - off[v]) > kBcHeavy) ext[v] = make_int2(s_mn[t], s_mx[t]);
       if (art) art[v] = (s_mn[t] != INT32_MAX && s_mn[t] != s_mx[t]) ? 1 : 0;
       comp = !bc_is_root((int32_t)v, parent[v], n) && L[v] == (int32_t)v;
     }
@@ -308,12 +471,17 @@ template <class OffT>
 static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, const int32_t *parent,
                                 const int32_t *pre, const int32_t *nd, int2 *A, int2 *pfx,
                                 int2 *sfx, int2 *st, int64_t nb, int levels, int32_t *L,
-                                int32_t *arc_label, uint8_t *art, int32_t *counters) {
+                                int64_t *items, int64_t item_cap, int32_t *arc_label, uint8_t *art,
+                                int32_t *counters) {
   const int64_t n = g->n;
   const OffT *off = static_cast<const OffT *>(g->offsets);
   const unsigned grid = bc_grid(ctx, n);
+  const unsigned hgrid = (unsigned)(ctx->num_cus * 4);
   hipLaunchKernelGGL(k_bcc_local<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off, g->cols,
-                     parent, pre, A, counters);
+                     parent, pre, A, items, item_cap, counters);
+  RST_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_bcc_local_heavy<OffT>, dim3(hgrid), dim3(kBcThreads), 0, ctx->stream, n, off,
+                     g->cols, parent, pre, A, items, item_cap, counters);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_blocks, dim3(grid_for(nb * kWave, kBcThreads)), dim3(kBcThreads), 0,
                      ctx->stream, n, A, pfx, sfx, st);
@@ -330,10 +498,24 @@ static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, const int32_t *p
   hipLaunchKernelGGL(k_bcc_rule_cross<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off,
                      g->cols, parent, pre, nd, L);
   RST_HIP(hipGetLastError());
-  RST_TRY(enqueue_compress(ctx, n, L, nullptr, nullptr));
-  hipLaunchKernelGGL(k_bcc_arcs<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off, g->cols,
-                     parent, pre, L, arc_label, art, counters);
+  hipLaunchKernelGGL(k_bcc_cross_heavy<OffT>, dim3(hgrid), dim3(kBcThreads), 0, ctx->stream, n, off,
+                     g->cols, parent, pre, nd, L, items, item_cap, counters);
   RST_HIP(hipGetLastError());
+  RST_TRY(enqueue_compress(ctx, n, L, nullptr, nullptr));
+  // the range structure is done with: pfx holds each heavy vertex's label
+  // extremes from here on (indexed by vertex)
+  int2 *ext = pfx;
+  hipLaunchKernelGGL(k_bcc_arcs<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off, g->cols,
+                     parent, pre, L, arc_label, art, ext, counters);
+  RST_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_bcc_arcs_heavy<OffT>, dim3(hgrid), dim3(kBcThreads), 0, ctx->stream, n, off,
+                     g->cols, parent, pre, L, arc_label, ext, items, item_cap, counters);
+  RST_HIP(hipGetLastError());
+  if (art) {
+    hipLaunchKernelGGL(k_bcc_art_heavy, dim3(grid_for(item_cap, kBcThreads)), dim3(kBcThreads), 0,
+                       ctx->stream, items, item_cap, ext, art, counters);
+    RST_HIP(hipGetLastError());
+  }
   return RST_OK;
 }
 
@@ -344,8 +526,11 @@ rst_status run_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent
   const int64_t nb = (n + kBcBlock - 1) / kBcBlock;
   int levels = 1;   // floor(log2 nb) + 1
   while (((int64_t)1 << levels) <= nb) ++levels;
+  // heavy items: every heavy vertex has more than kBcHeavy arcs
+  const int64_t item_cap = g->nnz / kBcHeavy + g->nnz / kBcSlice + 1;
   RST_TRY(ws_reserve(ctx, depth_ws_bytes(n, plan) + 3 * ws_bytes((size_t)n, 4) +
-                              3 * ws_bytes((size_t)n, 8) + ws_bytes((size_t)(levels * nb), 8)));
+                              3 * ws_bytes((size_t)n, 8) + ws_bytes((size_t)(levels * nb), 8) +
+                              ws_bytes((size_t)item_cap, 8)));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
   int32_t *pre = ws_take<int32_t>(ctx, n);
   int32_t *nd = ws_take<int32_t>(ctx, n);
@@ -354,15 +539,16 @@ rst_status run_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent
   int2 *pfx = ws_take<int2>(ctx, n);
   int2 *sfx = ws_take<int2>(ctx, n);
   int2 *st = ws_take<int2>(ctx, (size_t)(levels * nb));
+  int64_t *items = ws_take<int64_t>(ctx, (size_t)item_cap);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
   RST_TRY(run_tour_preorder(ctx, n, parent, pre, nd, counters));
   if (ctx->host_pinned[kCntBccRoots] != 1) return RST_E_DISCONNECTED;
   if (g->offset_bytes == 4)
     RST_TRY(bc_arc_passes<int32_t>(ctx, g, parent, pre, nd, A, pfx, sfx, st, nb, levels, L,
-                                   arc_label, art, counters));
+                                   items, item_cap, arc_label, art, counters));
   else
     RST_TRY(bc_arc_passes<int64_t>(ctx, g, parent, pre, nd, A, pfx, sfx, st, nb, levels, L,
-                                   arc_label, art, counters));
+                                   items, item_cap, arc_label, art, counters));
   RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
                          hipMemcpyDeviceToHost, ctx->stream));
   RST_HIP(hipStreamSynchronize(ctx->stream));

@@ -203,6 +203,7 @@ enum {
   kCntProbeArcs = 25,      // locality probe: sampled arcs
   kCntProbeCross = 26,     //   of those, arcs leaving their source's 8192-id tile
   kCntBccRoots = 27,       // biconnectivity: roots of the given parent array
+  kCntBccItems = 29,       //   items of heavy vertices' arcs (not read back)
   kCntTotal = 28,          // counters read back after a call (the ones above)
 };
 

@@ -47,7 +47,7 @@ def upload(g):
 
 
 @pytest.mark.parametrize("name", ["C1", "C2", "C3", "C4"])
-def test_fullsize(ctx, name):
+def test_fullsize(ctx, rst, name):
     g = graph(name)
     off, cols = upload(g)
     k_ref, lab_ref = oracle.components(g.n, g.offsets, g.cols)
@@ -65,9 +65,25 @@ def test_fullsize(ctx, name):
         # mesh: its 10k kept cross edges merged in LDS per group of tiles and
         # then the top levels, the contracted tour ranked in one workgroup
         assert st["paths"] == 4, st
+    check_tuned(rst, g, off, cols, k_ref, lab_ref)
     if name == "C4":
         return   # its BFS (1.3e7 levels) has a test of its own below
     check_bfs(ctx, g, off, cols)
+
+
+def check_tuned(rst, g, off, cols, k_ref, lab_ref):
+    """The launch configuration the benchmark times: the committed autotuner
+    cache's setting for this graph's size class (bench.py applies it)."""
+    import os
+    path = os.path.join(os.path.dirname(rst.__file__), "tuned_gfx950.json")
+    c = rst.Context(0)
+    assert c.tune_load(path, off, cols, "gconn")
+    label, k = c.components(off, cols)
+    assert k == k_ref and np.array_equal(label.cpu().numpy(), lab_ref)
+    par = c.spanning_tree(off, cols, g.root, "gconn")
+    par = c.spanning_tree(off, cols, g.root, "gconn")   # the captured graph's replay
+    code, bad = oracle.verify_rst(g.n, g.offsets, g.cols, par.cpu().numpy(), [g.root])
+    assert code == 0, (oracle.VERIFY_CODES[code], bad)
 
 
 def check_bfs(ctx, g, off, cols):
