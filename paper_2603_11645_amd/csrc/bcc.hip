@@ -286,8 +286,7 @@ __global__ __launch_bounds__(B) void k_bcc_iota(int64_t n, int32_t *L) {
 // release per workgroup (hooks in global memory, read on every XCD next).
 template <int B>
 __global__ __launch_bounds__(B) void k_bcc_rule_tree(int64_t n, const int32_t *__restrict__ parent,
-                                                     const int32_t *__restrict__ pre,
-                                                     const int32_t *__restrict__ nd,
+                                                     const int2 *__restrict__ pn,
                                                      const int2 *__restrict__ A,
                                                      const int2 *__restrict__ pfx,
                                                      const int2 *__restrict__ sfx,
@@ -297,7 +296,9 @@ __global__ __launch_bounds__(B) void k_bcc_rule_tree(int64_t n, const int32_t *_
   if (v < n) {
     const int32_t p = parent[v];
     if (!bc_is_root((int32_t)v, p, n) && !bc_is_root(p, parent[p], n)) {
-      const int64_t pv = pre[v], sv = nd[v], pp = pre[p], sp = nd[p];
+      // preorder number and subtree size of v and of its parent, one word each
+      const int2 a = pn[v], b = pn[p];
+      const int64_t pv = a.x, sv = a.y, pp = b.x, sp = b.y;
       if (pv < 0 || sv < 1 || pv + sv > n || pp < 0 || sp < 1 || pp + sp > n) {
         atomicOr(&counters[kCntRangeErr], 1);
       } else {
@@ -469,7 +470,8 @@ static unsigned bc_grid(const rst_ctx *ctx, int64_t n) {
 
 template <class OffT>
 static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, const int32_t *parent,
-                                const int32_t *pre, const int32_t *nd, int2 *A, int2 *pfx,
+                                const int32_t *pre, const int32_t *nd, const int2 *pn, int2 *A,
+                                int2 *pfx,
                                 int2 *sfx, int2 *st, int64_t nb, int levels, int32_t *L,
                                 int64_t *items, int64_t item_cap, int32_t *arc_label, uint8_t *art,
                                 int32_t *counters) {
@@ -493,7 +495,7 @@ static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, const int32_t *p
   }
   RST_SWEEP(ctx, k_bcc_iota, n, n, L);
   RST_HIP(hipGetLastError());
-  RST_SWEEP(ctx, k_bcc_rule_tree, n, n, parent, pre, nd, A, pfx, sfx, st, nb, L, counters);
+  RST_SWEEP(ctx, k_bcc_rule_tree, n, n, parent, pn, A, pfx, sfx, st, nb, L, counters);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_rule_cross<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off,
                      g->cols, parent, pre, nd, L);
@@ -529,11 +531,12 @@ rst_status run_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent
   // heavy items: every heavy vertex has more than kBcHeavy arcs
   const int64_t item_cap = g->nnz / kBcHeavy + g->nnz / kBcSlice + 1;
   RST_TRY(ws_reserve(ctx, depth_ws_bytes(n, plan) + 3 * ws_bytes((size_t)n, 4) +
-                              3 * ws_bytes((size_t)n, 8) + ws_bytes((size_t)(levels * nb), 8) +
+                              4 * ws_bytes((size_t)n, 8) + ws_bytes((size_t)(levels * nb), 8) +
                               ws_bytes((size_t)item_cap, 8)));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
   int32_t *pre = ws_take<int32_t>(ctx, n);
   int32_t *nd = ws_take<int32_t>(ctx, n);
+  int2 *pn = ws_take<int2>(ctx, n);
   int32_t *L = ws_take<int32_t>(ctx, n);
   int2 *A = ws_take<int2>(ctx, n);
   int2 *pfx = ws_take<int2>(ctx, n);
@@ -541,13 +544,13 @@ rst_status run_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent
   int2 *st = ws_take<int2>(ctx, (size_t)(levels * nb));
   int64_t *items = ws_take<int64_t>(ctx, (size_t)item_cap);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
-  RST_TRY(run_tour_preorder(ctx, n, parent, pre, nd, counters));
+  RST_TRY(run_tour_preorder(ctx, n, parent, pre, nd, pn, counters));
   if (ctx->host_pinned[kCntBccRoots] != 1) return RST_E_DISCONNECTED;
   if (g->offset_bytes == 4)
-    RST_TRY(bc_arc_passes<int32_t>(ctx, g, parent, pre, nd, A, pfx, sfx, st, nb, levels, L,
+    RST_TRY(bc_arc_passes<int32_t>(ctx, g, parent, pre, nd, pn, A, pfx, sfx, st, nb, levels, L,
                                    items, item_cap, arc_label, art, counters));
   else
-    RST_TRY(bc_arc_passes<int64_t>(ctx, g, parent, pre, nd, A, pfx, sfx, st, nb, levels, L,
+    RST_TRY(bc_arc_passes<int64_t>(ctx, g, parent, pre, nd, pn, A, pfx, sfx, st, nb, levels, L,
                                    items, item_cap, arc_label, art, counters));
   RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
                          hipMemcpyDeviceToHost, ctx->stream));

@@ -182,14 +182,12 @@ __global__ __launch_bounds__(B) void k_depth_out_rounds(int64_t n, const int32_t
 // strictly inside x's excursion are its descendants'); the root has pre 0
 // and nd n.  Roots are counted into counters[kCntBccRoots].
 __device__ __forceinline__ void pre_store(int64_t n, int64_t x, bool root, uint32_t d0,
-                                          uint32_t d1, int32_t *pre, int32_t *nd) {
-  if (root) {
-    pre[x] = 0;
-    nd[x] = (int32_t)n;
-  } else {
-    pre[x] = (int32_t)(n - 1) - (int32_t)d0;
-    nd[x] = (int32_t)d0 - (int32_t)d1 + 1;
-  }
+                                          uint32_t d1, int32_t *pre, int32_t *nd, int2 *pn) {
+  const int32_t p = root ? 0 : (int32_t)(n - 1) - (int32_t)d0;
+  const int32_t s = root ? (int32_t)n : (int32_t)d0 - (int32_t)d1 + 1;
+  pre[x] = p;
+  nd[x] = s;
+  pn[x] = make_int2(p, s);   // both in one word for gathers that need both
 }
 
 // codes (ruler << 8 | weight walked since it) of both arcs, from the 32-bit walk
@@ -197,7 +195,8 @@ template <int B>
 __global__ __launch_bounds__(B) void k_pre_out(int64_t n, const int32_t *__restrict__ parent,
                                                const int32_t *__restrict__ w,
                                                const uint32_t *__restrict__ d1, int64_t rw1_cap,
-                                               int32_t *pre, int32_t *nd, int32_t *counters) {
+                                               int32_t *pre, int32_t *nd, int2 *pn,
+                                               int32_t *counters) {
   if (counters[kCntGOverflow]) return;   // block-uniform: the caller falls back
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool root = false;
@@ -210,7 +209,7 @@ __global__ __launch_bounds__(B) void k_pre_out(int64_t n, const int32_t *__restr
       a = r0 < rw1_cap ? d1[r0] - ((uint32_t)c.x & 255u) : 0u;
       b = r1 < rw1_cap ? d1[r1] - ((uint32_t)c.y & 255u) : 0u;
     }
-    pre_store(n, x, root, a, b, pre, nd);
+    pre_store(n, x, root, a, b, pre, nd, pn);
   }
   wave_count(root, &counters[kCntBccRoots]);
 }
@@ -218,14 +217,14 @@ __global__ __launch_bounds__(B) void k_pre_out(int64_t n, const int32_t *__restr
 template <int B>
 __global__ __launch_bounds__(B) void k_pre_out_rounds(int64_t n, const int32_t *__restrict__ parent,
                                                       const uint64_t *__restrict__ w, int32_t *pre,
-                                                      int32_t *nd, int32_t *counters) {
+                                                      int32_t *nd, int2 *pn, int32_t *counters) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool root = false;
   if (x < n) {
     root = depth_is_root((int32_t)x, parent[x], n);
     const uint32_t a = root ? 0u : (uint32_t)(w[2 * x] >> 32);
     const uint32_t b = root ? 0u : (uint32_t)(w[2 * x + 1] >> 32);
-    pre_store(n, x, root, a, b, pre, nd);
+    pre_store(n, x, root, a, b, pre, nd, pn);
   }
   wave_count(root, &counters[kCntBccRoots]);
 }
@@ -273,7 +272,7 @@ rst_status run_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_
 }
 
 rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *pre,
-                              int32_t *nd, int32_t *counters) {
+                              int32_t *nd, int2 *pn, int32_t *counters) {
   const GlistPlan plan = glist_plan(2 * n, n / 2 + 1, ctx->opt.rank_stride);
   int32_t *head = ws_take<int32_t>(ctx, n);
   int32_t *next = ws_take<int32_t>(ctx, 2 * n);
@@ -289,7 +288,7 @@ rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int
   RST_SWEEP(ctx, k_pre_words32, n, n, parent, head, next, w32, gl.heads[0], plan.hcap, counters);
   RST_HIP(hipGetLastError());
   RST_TRY(enqueue_glist_rank(ctx, w32, false, gl, counters, true));
-  RST_SWEEP(ctx, k_pre_out, n, n, parent, w32, gl.d1, plan.cap[1], pre, nd, counters);
+  RST_SWEEP(ctx, k_pre_out, n, n, parent, w32, gl.d1, plan.cap[1], pre, nd, pn, counters);
   RST_HIP(hipGetLastError());
   RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
                          hipMemcpyDeviceToHost, ctx->stream));
@@ -300,7 +299,7 @@ rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int
     RST_SWEEP(ctx, k_pre_words, n, n, parent, head, next, w, gl.heads[0], plan.hcap, counters);
     RST_HIP(hipGetLastError());
     RST_TRY(enqueue_rank_rounds(ctx, 2 * n, w, rank_rounds_for(2 * n), nullptr, nullptr));
-    RST_SWEEP(ctx, k_pre_out_rounds, n, n, parent, w, pre, nd, counters);
+    RST_SWEEP(ctx, k_pre_out_rounds, n, n, parent, w, pre, nd, pn, counters);
     RST_HIP(hipGetLastError());
     RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
                            hipMemcpyDeviceToHost, ctx->stream));

@@ -365,7 +365,7 @@ rst_status run_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_
 // less the counters); counters (device, 64) read back; synchronous
 size_t depth_ws_bytes(int64_t n, const GlistPlan &p);
 rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *pre,
-                             int32_t *nd, int32_t *counters);
+                             int32_t *nd, int2 *pn, int32_t *counters);
 // bcc.hip: biconnected components from a rooted spanning tree (synchronous)
 rst_status run_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent,
                            int32_t *arc_label, uint8_t *art, int64_t *num_components);
