@@ -282,30 +282,31 @@ __global__ __launch_bounds__(B) void k_bcc_iota(int64_t n, int32_t *L) {
 }
 
 // Step 4, tree edges: v joins its parent's tree edge when a vertex of v's
-// subtree reaches outside the parent's subtree.  Ends with a device-scope
-// release per workgroup (hooks in global memory, read on every XCD next).
-template <int B>
-__global__ __launch_bounds__(B) void k_bcc_rule_tree(int64_t n, const int32_t *__restrict__ parent,
-                                                     const int2 *__restrict__ pn,
-                                                     const int2 *__restrict__ A,
-                                                     const int2 *__restrict__ pfx,
-                                                     const int2 *__restrict__ sfx,
-                                                     const int2 *__restrict__ st, int64_t nb,
-                                                     int32_t *L, int32_t *counters) {
-  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) {
+// subtree reaches outside the parent's subtree.  Grid-stride over the
+// vertices with a few workgroups per CU, each ending with one device-scope
+// release (hooks in global memory, read on every XCD next): a release writes
+// back the XCD's L2, and one per 256 vertices cost C4's pass as much as its
+// gathers.
+__global__ __launch_bounds__(kBcThreads) void k_bcc_rule_tree(int64_t n, const int32_t *__restrict__ parent,
+                                                              const int2 *__restrict__ pn,
+                                                              const int2 *__restrict__ A,
+                                                              const int2 *__restrict__ pfx,
+                                                              const int2 *__restrict__ sfx,
+                                                              const int2 *__restrict__ st, int64_t nb,
+                                                              int32_t *L, int32_t *counters) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
     const int32_t p = parent[v];
-    if (!bc_is_root((int32_t)v, p, n) && !bc_is_root(p, parent[p], n)) {
-      // preorder number and subtree size of v and of its parent, one word each
-      const int2 a = pn[v], b = pn[p];
-      const int64_t pv = a.x, sv = a.y, pp = b.x, sp = b.y;
-      if (pv < 0 || sv < 1 || pv + sv > n || pp < 0 || sp < 1 || pp + sp > n) {
-        atomicOr(&counters[kCntRangeErr], 1);
-      } else {
-        const int2 lh = bc_range(pv, pv + sv - 1, A, pfx, sfx, st, nb);
-        if (lh.x < pp || lh.y >= pp + sp) hook_join<true>((int32_t)v, p, L);
-      }
+    if (bc_is_root((int32_t)v, p, n) || bc_is_root(p, parent[p], n)) continue;
+    // preorder number and subtree size of v and of its parent, one word each
+    const int2 a = pn[v], b = pn[p];
+    const int64_t pv = a.x, sv = a.y, pp = b.x, sp = b.y;
+    if (pv < 0 || sv < 1 || pv + sv > n || pp < 0 || sp < 1 || pp + sp > n) {
+      atomicOr(&counters[kCntRangeErr], 1);
+      continue;
     }
+    const int2 lh = bc_range(pv, pv + sv - 1, A, pfx, sfx, st, nb);
+    if (lh.x < pp || lh.y >= pp + sp) hook_join<true>((int32_t)v, p, L);
   }
   block_release_device();
 }
@@ -495,7 +496,10 @@ static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, const int32_t *p
   }
   RST_SWEEP(ctx, k_bcc_iota, n, n, L);
   RST_HIP(hipGetLastError());
-  RST_SWEEP(ctx, k_bcc_rule_tree, n, n, parent, pn, A, pfx, sfx, st, nb, L, counters);
+  const int64_t tblocks = (n + kBcThreads - 1) / kBcThreads;
+  const unsigned tgrid = (unsigned)(tblocks < ctx->num_cus * 8 ? tblocks : ctx->num_cus * 8);
+  hipLaunchKernelGGL(k_bcc_rule_tree, dim3(tgrid), dim3(kBcThreads), 0, ctx->stream, n, parent, pn,
+                     A, pfx, sfx, st, nb, L, counters);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_rule_cross<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off,
                      g->cols, parent, pre, nd, L);

@@ -2,8 +2,9 @@
 // (the tree-depth comparison of Sec. IV-B, Fig. 2; the tour of Sec. III-D).
 //
 // The forest is given by its parent array.  Non-root v holds the edge
-// (P[v], v) in slot v: arc 2v = P[v] -> v goes down, arc 2v+1 = v -> P[v]
-// goes up; every vertex's out-arcs form a list (atomic exchange), the tour
+// (P[v], v) in slot v, as arcs 2v and 2v+1: the one whose id has an even
+// number of one bits goes down (P[v] -> v), the other up (v -> P[v]), see
+// tour_down; every vertex's out-arcs form a list (atomic exchange), the tour
 // successor is next(rev e) or, at the end of a list, the first out-arc of the
 // arc's head, and the tour of each tree starts at its root's first out-arc and
 // ends at the arc whose successor would wrap around to it.  Along a tour the
@@ -36,6 +37,19 @@ __device__ __forceinline__ bool depth_is_root(int32_t v, int32_t p, int64_t n) {
   return p == v || p < 0 || p >= n;   // out-of-range parents are taken as roots
 }
 
+// The down arc of slot x: 2x when x has an even number of one bits, else
+// 2x+1 (the up arc is the other one), so an arc goes down iff its id has an
+// even number of one bits.  The ruling set's rulers are the arc ids divisible
+// by its stride; with every down arc even they were all down arcs, a climb of
+// up arcs held none, and one lane walked all of it (a chain-like tree's tour:
+// 2.8 ms against 1.1 ms for a tour of the same length numbered by hooking).
+__device__ __forceinline__ int32_t tour_down(int64_t x) {
+  return (int32_t)(2 * x + (__popcll((unsigned long long)x) & 1));
+}
+__device__ __forceinline__ bool tour_arc_down(int32_t e) {
+  return (__popc((uint32_t)e) & 1) == 0;
+}
+
 // Out-arc lists of the forest of parent edges (head = -1 beforehand).
 template <int B>
 __global__ __launch_bounds__(B) void k_depth_link(int64_t n, const int32_t *__restrict__ parent,
@@ -45,18 +59,38 @@ __global__ __launch_bounds__(B) void k_depth_link(int64_t n, const int32_t *__re
   const int32_t p = parent[x];
   int2 nx = make_int2(-1, -1);
   if (!depth_is_root((int32_t)x, p, n)) {
-    nx.x = atomicExch(&head[p], (int32_t)(2 * x));        // arc 2x = p -> x
-    nx.y = atomicExch(&head[x], (int32_t)(2 * x + 1));    // arc 2x+1 = x -> p
+    const int32_t dn = tour_down(x);
+    const int32_t nd = atomicExch(&head[p], dn);       // p -> x
+    const int32_t nu = atomicExch(&head[x], dn ^ 1);   // x -> p
+    nx = (dn & 1) ? make_int2(nu, nd) : make_int2(nd, nu);   // next[2x], next[2x+1]
   }
   reinterpret_cast<int2 *>(next)[x] = nx;
 }
 
-// weight of the successor arc, 0 past the tail: depth (kPre false) +1 down
-// (even id), -1 up (odd id); preorder (kPre true) 1 down, 0 up
+// weight of the successor arc, 0 past the tail: depth (kPre false) +1 down,
+// -1 up; preorder (kPre true) 1 down, 0 up
 template <bool kPre>
 __device__ __forceinline__ uint64_t depth_word(int32_t succ) {
-  const uint32_t w = succ < 0 ? 0u : ((succ & 1) ? (kPre ? 0u : 0xffffffffu) : 1u);
+  const uint32_t w = succ < 0 ? 0u : (tour_arc_down(succ) ? 1u : (kPre ? 0u : 0xffffffffu));
   return ((uint64_t)w << 32) | (uint32_t)succ;
+}
+
+// Successors of the down and the up arc of non-root x (child of p): after
+// p -> x comes the arc after x -> p in x's list, or x's first (x's list holds
+// x -> p); after x -> p the arc after p -> x in p's list, or p's first unless
+// p roots its tree (the end of the tour).
+__device__ __forceinline__ int2 tour_succ(int64_t x, int32_t p, int64_t n,
+                                          const int32_t *__restrict__ parent,
+                                          const int32_t *__restrict__ head,
+                                          const int32_t *__restrict__ next) {
+  const int2 nx = reinterpret_cast<const int2 *>(next)[x];
+  const bool odd = tour_down(x) & 1;
+  const int32_t after_down = odd ? nx.y : nx.x, after_up = odd ? nx.x : nx.y;
+  int2 s;
+  s.x = after_up != -1 ? after_up : head[x];
+  s.y = after_down;
+  if (s.y == -1) s.y = depth_is_root(p, parent[p], n) ? -1 : head[p];
+  return s;
 }
 
 // Level-1 words (successor, weight) of both arcs of every slot, and the list
@@ -76,16 +110,9 @@ __device__ __forceinline__ void tour_words(int64_t n, const int32_t *__restrict_
       h = head[x];
       is_head = h >= 0;
     } else {
-      const int2 nx = reinterpret_cast<const int2 *>(next)[x];
-      // successor of 2x = p -> x: the arc after 2x+1 in x's list, or x's first
-      // (x is no root, so its list holds at least 2x+1)
-      const int32_t s0 = nx.y != -1 ? nx.y : head[x];
-      // successor of 2x+1 = x -> p: the arc after 2x in p's list, or p's
-      // first unless p roots its tree (the end of the tour)
-      int32_t s1 = nx.x;
-      if (s1 == -1) s1 = depth_is_root(p, parent[p], n) ? -1 : head[p];
-      out.x = depth_word<kPre>(s0);
-      out.y = depth_word<kPre>(s1);
+      const int2 sc = tour_succ(x, p, n, parent, head, next);
+      const uint64_t wd = depth_word<kPre>(sc.x), wu = depth_word<kPre>(sc.y);
+      if (tour_down(x) & 1) { out.x = wu; out.y = wd; } else { out.x = wd; out.y = wu; }
     }
     reinterpret_cast<ulonglong2 *>(w)[x] = out;
   }
@@ -103,7 +130,7 @@ __global__ __launch_bounds__(B) void k_depth_words(int64_t n, const int32_t *__r
 
 // Preorder ranking in 32-bit words: each arc's word is its successor (-2 for
 // an arc of no list), the weight (1 down, 0 up) following from the
-// successor's parity in the walk; list heads as above.
+// successor's id in the walk (tour_arc_down); list heads as above.
 template <int B>
 __global__ __launch_bounds__(B) void k_pre_words32(int64_t n, const int32_t *__restrict__ parent,
                                                    const int32_t *__restrict__ head,
@@ -119,11 +146,8 @@ __global__ __launch_bounds__(B) void k_pre_words32(int64_t n, const int32_t *__r
       h = head[x];
       is_head = h >= 0;
     } else {
-      const int2 nx = reinterpret_cast<const int2 *>(next)[x];
-      out.x = nx.y != -1 ? nx.y : head[x];
-      int32_t s1 = nx.x;
-      if (s1 == -1) s1 = depth_is_root(p, parent[p], n) ? -1 : head[p];
-      out.y = s1;
+      const int2 sc = tour_succ(x, p, n, parent, head, next);
+      out = (tour_down(x) & 1) ? make_int2(sc.y, sc.x) : sc;
     }
     reinterpret_cast<int2 *>(w)[x] = out;
   }
@@ -139,7 +163,7 @@ __global__ __launch_bounds__(B) void k_pre_words(int64_t n, const int32_t *__res
   tour_words<true>(n, parent, head, next, w, heads, hcap, counters);
 }
 
-// depth[x] = -(weighted distance after the down arc 2x), 0 at roots; the
+// depth[x] = -(weighted distance after x's down arc), 0 at roots; the
 // largest depth goes to counters[kCntDepthMax].
 template <int B>
 __global__ __launch_bounds__(B) void k_depth_out(int64_t n, const int32_t *__restrict__ parent,
@@ -151,7 +175,7 @@ __global__ __launch_bounds__(B) void k_depth_out(int64_t n, const int32_t *__res
   int32_t d = 0;
   if (x < n) {
     if (!depth_is_root((int32_t)x, parent[x], n)) {
-      const uint64_t c = w[2 * x];
+      const uint64_t c = w[tour_down(x)];
       const uint32_t rid = (uint32_t)c;
       const uint32_t dist = rid < rw1_cap ? d1[rid] - (uint32_t)(c >> 32) : 0u;
       d = -(int32_t)dist;
@@ -170,17 +194,17 @@ __global__ __launch_bounds__(B) void k_depth_out_rounds(int64_t n, const int32_t
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int32_t d = 0;
   if (x < n) {
-    if (!depth_is_root((int32_t)x, parent[x], n)) d = -(int32_t)(uint32_t)(w[2 * x] >> 32);
+    if (!depth_is_root((int32_t)x, parent[x], n)) d = -(int32_t)(uint32_t)(w[tour_down(x)] >> 32);
     depth[x] = d;
   }
   block_max_to<B>(d, &counters[kCntDepthMax]);
 }
 
 // Preorder number and subtree size of every vertex of a tree (one root) from
-// the preorder-weighted tour: D(e) = number of down arcs after arc e, so
-// pre(x) = (n - 1) - D(2x) and nd(x) = D(2x) - D(2x+1) + 1 (the down arcs
-// strictly inside x's excursion are its descendants'); the root has pre 0
-// and nd n.  Roots are counted into counters[kCntBccRoots].
+// the preorder-weighted tour: D(e) = number of down arcs after arc e, so with
+// x's down arc d and up arc u, pre(x) = (n - 1) - D(d) and nd(x) = D(d) -
+// D(u) + 1 (the down arcs strictly inside x's excursion are its
+// descendants'); the root has pre 0 and nd n.  Roots are counted into counters[kCntBccRoots].
 __device__ __forceinline__ void pre_store(int64_t n, int64_t x, bool root, uint32_t d0,
                                           uint32_t d1, int32_t *pre, int32_t *nd, int2 *pn) {
   const int32_t p = root ? 0 : (int32_t)(n - 1) - (int32_t)d0;
@@ -204,7 +228,8 @@ __global__ __launch_bounds__(B) void k_pre_out(int64_t n, const int32_t *__restr
     root = depth_is_root((int32_t)x, parent[x], n);
     uint32_t a = 0, b = 0;
     if (!root) {
-      const int2 c = reinterpret_cast<const int2 *>(w)[x];
+      int2 c = reinterpret_cast<const int2 *>(w)[x];
+      if (tour_down(x) & 1) c = make_int2(c.y, c.x);   // (down, up)
       const uint32_t r0 = (uint32_t)c.x >> 8, r1 = (uint32_t)c.y >> 8;
       a = r0 < rw1_cap ? d1[r0] - ((uint32_t)c.x & 255u) : 0u;
       b = r1 < rw1_cap ? d1[r1] - ((uint32_t)c.y & 255u) : 0u;
@@ -222,8 +247,9 @@ __global__ __launch_bounds__(B) void k_pre_out_rounds(int64_t n, const int32_t *
   bool root = false;
   if (x < n) {
     root = depth_is_root((int32_t)x, parent[x], n);
-    const uint32_t a = root ? 0u : (uint32_t)(w[2 * x] >> 32);
-    const uint32_t b = root ? 0u : (uint32_t)(w[2 * x + 1] >> 32);
+    const int32_t dn = tour_down(x);
+    const uint32_t a = root ? 0u : (uint32_t)(w[dn] >> 32);
+    const uint32_t b = root ? 0u : (uint32_t)(w[dn ^ 1] >> 32);
     pre_store(n, x, root, a, b, pre, nd, pn);
   }
   wave_count(root, &counters[kCntBccRoots]);
@@ -282,7 +308,7 @@ rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int
   RST_TRY(enqueue_fill(ctx, head, n, -1));
   RST_SWEEP(ctx, k_depth_link, n, n, parent, head, next);
   RST_HIP(hipGetLastError());
-  // 32-bit words with the weights from the arcs' parity: half the bytes of
+  // 32-bit words with the weights from the arcs' ids: half the bytes of
   // (successor, weight) words under the random walk
   int32_t *w32 = reinterpret_cast<int32_t *>(w);
   RST_SWEEP(ctx, k_pre_words32, n, n, parent, head, next, w32, gl.heads[0], plan.hcap, counters);

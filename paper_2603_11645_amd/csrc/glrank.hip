@@ -132,10 +132,10 @@ __global__ __launch_bounds__(kGlThreads) void k_glist_heads(int64_t A, const uin
 // head list of the next level names h/k); further rulers are opened by walks
 // that reach the piece cap.  Each ruler's word of the next level goes to
 // rw_out[ruler].
-// kW01 (32-bit words only): the arcs weigh 1 when their id is even and 0 when
-// it is odd (the down and up arcs of a tour by parent edges, whose preorder
-// count this ranks), instead of 1 each; a code's offset is then the weight
-// walked since the ruler, still at most the piece's arcs.
+// kW01 (32-bit words only): the arcs weigh 1 when their id has an even number
+// of one bits and 0 otherwise (the down and up arcs of a tour by parent
+// edges, whose preorder count this ranks), instead of 1 each; a code's offset
+// is then the weight walked since the ruler, still at most the piece's arcs.
 template <bool kL1, bool kW01 = false>
 __global__ __launch_bounds__(kGlThreads) void k_gwalk(int level, int64_t A, int k1, int k,
                                                       void *words, const int32_t *heads_in,
@@ -186,7 +186,8 @@ __global__ __launch_bounds__(kGlThreads) void k_gwalk(int level, int64_t A, int 
       while (true) {
         w[e] = (int32_t)(((uint32_t)rid << kGlOffBits) | off);
         if (s < 0 || s >= N || ++steps > N) { rw_out[rid] = gl_pack(-1, off); break; }
-        const uint32_t ws = kW01 ? (uint32_t)(~s & 1) : 1u;   // weight of the successor
+        // weight of the successor
+        const uint32_t ws = kW01 ? (uint32_t)(~__popc((uint32_t)s) & 1) : 1u;
         if ((s & kmask) == 0) { rw_out[rid] = gl_pack(s >> ksh, off + ws); break; }
         if (len == (uint32_t)kGlCap) {
           // open a ruler at s: the piece so far ends there

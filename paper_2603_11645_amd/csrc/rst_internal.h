@@ -335,8 +335,9 @@ rst_status enqueue_glist_from_slots(rst_ctx *ctx, int64_t slots, int64_t n, cons
 // level-1 words and list heads from a successor array; haspred: A bytes scratch
 rst_status enqueue_glist_from_succ(rst_ctx *ctx, int64_t A, const int32_t *succ, int32_t *w1,
                                    uint8_t *haspred, GlistBufs &g, int32_t *counters);
-// w1: int32 level-1 words (unit weights; with w01 weight 1 on even arc ids and
-// 0 on odd ones), or with w1_wide uint64 (successor, weight) words, whose
+// w1: int32 level-1 words (unit weights; with w01 weight 1 on arc ids with an
+// even number of one bits and 0 on the others), or with w1_wide uint64
+// (successor, weight) words, whose
 // codes become (offset << 32 | ruler)
 rst_status enqueue_glist_rank(rst_ctx *ctx, void *w1, bool w1_wide, GlistBufs &g,
                               int32_t *counters, bool w01 = false);
