@@ -115,8 +115,7 @@ __device__ __forceinline__ bool bc_is_root(int32_t v, int32_t p, int64_t n) {
 template <class OffT>
 __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT *__restrict__ off,
                                                         const int32_t *__restrict__ cols,
-                                                        const int32_t *__restrict__ parent,
-                                                        const int32_t *__restrict__ pre, int2 *A,
+                                                        const int4 *__restrict__ R, int2 *A,
                                                         int64_t *items, int64_t item_cap,
                                                         int32_t *counters) {
   __shared__ int s_scan[kBcChunk + 1];
@@ -127,7 +126,7 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT
   const int64_t chunks = (n + kBcChunk - 1) / kBcChunk;
   for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
     const int64_t v0 = c * kBcChunk, v = v0 + t;
-    const int32_t pv = v < n ? pre[v] : 0;
+    const int32_t pv = v < n ? R[v].y : 0;
     if (v < n) {
       // a heavy vertex's arcs become items (v, slice) for the item passes
       const int64_t d = (int64_t)(off[v + 1] - off[v]);
@@ -145,10 +144,9 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT
                     int2 val = make_int2(INT32_MAX, INT32_MIN);
                     // non-tree arcs only (arcs to the parent or a child, and
                     // their parallel copies, are tree arcs)
-                    if (j >= 0 && w != u && w >= 0 && w < n && w != parent[u] &&
-                        parent[w] != u) {
-                      const int32_t pw = pre[w];
-                      val = make_int2(pw, pw);
+                    if (j >= 0 && w != u && w >= 0 && w < n) {
+                      const int4 rw = R[w];
+                      if (w != R[u].x && rw.x != u) val = make_int2(rw.y, rw.y);
                     }
                     bc_run_extremes(j, val, s_lo, s_hi);
                   });
@@ -189,8 +187,7 @@ __device__ __forceinline__ int2 bc_block_extremes(int2 x, int2 *s_red) {
 template <class OffT>
 __global__ __launch_bounds__(kBcThreads) void k_bcc_local_heavy(int64_t n, const OffT *__restrict__ off,
                                                                 const int32_t *__restrict__ cols,
-                                                                const int32_t *__restrict__ parent,
-                                                                const int32_t *__restrict__ pre,
+                                                                const int4 *__restrict__ R,
                                                                 int2 *A, const int64_t *__restrict__ items,
                                                                 int64_t item_cap,
                                                                 const int32_t *__restrict__ counters) {
@@ -200,17 +197,17 @@ __global__ __launch_bounds__(kBcThreads) void k_bcc_local_heavy(int64_t n, const
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
     int64_t a0, a1;
     const int32_t u = (int32_t)bc_item(items, it, off, &a0, &a1);
-    const int32_t pu = parent[u];
+    const int4 ru = R[u];
     int2 x = make_int2(INT32_MAX, INT32_MIN);
     for (int64_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
       const int32_t w = cols[a];
-      if (w != u && w >= 0 && w < n && w != pu && parent[w] != u) {
-        const int32_t pw = pre[w];
-        x = bc_comb(x, make_int2(pw, pw));
+      if (w != u && w >= 0 && w < n && w != ru.x) {
+        const int4 rw = R[w];
+        if (rw.x != u) x = bc_comb(x, make_int2(rw.y, rw.y));
       }
     }
     x = bc_block_extremes(x, s_red);
-    const int32_t pv = pre[u];
+    const int32_t pv = ru.y;
     if (threadIdx.x == 0 && pv >= 0 && pv < n && x.x <= x.y) {
       atomicMin(&reinterpret_cast<int *>(A)[2 * (int64_t)pv], x.x);
       atomicMax(&reinterpret_cast<int *>(A)[2 * (int64_t)pv + 1], x.y);
@@ -287,8 +284,7 @@ __global__ __launch_bounds__(B) void k_bcc_iota(int64_t n, int32_t *L) {
 // release (hooks in global memory, read on every XCD next): a release writes
 // back the XCD's L2, and one per 256 vertices cost C4's pass as much as its
 // gathers.
-__global__ __launch_bounds__(kBcThreads) void k_bcc_rule_tree(int64_t n, const int32_t *__restrict__ parent,
-                                                              const int2 *__restrict__ pn,
+__global__ __launch_bounds__(kBcThreads) void k_bcc_rule_tree(int64_t n, const int4 *__restrict__ R,
                                                               const int2 *__restrict__ A,
                                                               const int2 *__restrict__ pfx,
                                                               const int2 *__restrict__ sfx,
@@ -296,11 +292,12 @@ __global__ __launch_bounds__(kBcThreads) void k_bcc_rule_tree(int64_t n, const i
                                                               int32_t *L, int32_t *counters) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    const int32_t p = parent[v];
-    if (bc_is_root((int32_t)v, p, n) || bc_is_root(p, parent[p], n)) continue;
-    // preorder number and subtree size of v and of its parent, one word each
-    const int2 a = pn[v], b = pn[p];
-    const int64_t pv = a.x, sv = a.y, pp = b.x, sp = b.y;
+    const int4 a = R[v];
+    const int32_t p = a.x;
+    if (bc_is_root((int32_t)v, p, n)) continue;
+    const int4 b = R[p];
+    if (bc_is_root(p, b.x, n)) continue;
+    const int64_t pv = a.y, sv = a.z, pp = b.y, sp = b.z;
     if (pv < 0 || sv < 1 || pv + sv > n || pp < 0 || sp < 1 || pp + sp > n) {
       atomicOr(&counters[kCntRangeErr], 1);
       continue;
@@ -316,9 +313,7 @@ __global__ __launch_bounds__(kBcThreads) void k_bcc_rule_tree(int64_t n, const i
 template <class OffT>
 __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_rule_cross(int64_t n, const OffT *__restrict__ off,
                                                              const int32_t *__restrict__ cols,
-                                                             const int32_t *__restrict__ parent,
-                                                             const int32_t *__restrict__ pre,
-                                                             const int32_t *__restrict__ nd,
+                                                             const int4 *__restrict__ R,
                                                              int32_t *L) {
   __shared__ int s_scan[kBcChunk + 1];
   __shared__ OffT s_beg[kBcChunk];
@@ -328,9 +323,10 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_rule_cross(int64_t n, const
     bc_chunk_arcs(n, c * kBcChunk, off, cols, s_scan, s_beg, s_wave,
                   [&](int j, int32_t u, int32_t w, int64_t) {
                     if (j < 0 || w == u || w < 0 || w >= n) return;
-                    if (w == parent[u] || parent[w] == u) return;
-                    const int64_t pu = pre[u], pw = pre[w];
-                    if (pu < pw && pw >= pu + nd[u]) hook_join<true>(u, w, L);
+                    const int4 ru = R[u], rw = R[w];
+                    if (w == ru.x || rw.x == u) return;
+                    const int64_t pu = ru.y, pw = rw.y;
+                    if (pu < pw && pw >= pu + ru.z) hook_join<true>(u, w, L);
                   });
   block_release_device();
 }
@@ -339,9 +335,7 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_rule_cross(int64_t n, const
 template <class OffT>
 __global__ __launch_bounds__(kBcThreads) void k_bcc_cross_heavy(int64_t n, const OffT *__restrict__ off,
                                                                 const int32_t *__restrict__ cols,
-                                                                const int32_t *__restrict__ parent,
-                                                                const int32_t *__restrict__ pre,
-                                                                const int32_t *__restrict__ nd,
+                                                                const int4 *__restrict__ R,
                                                                 int32_t *L, const int64_t *__restrict__ items,
                                                                 int64_t item_cap,
                                                                 const int32_t *__restrict__ counters) {
@@ -350,16 +344,35 @@ __global__ __launch_bounds__(kBcThreads) void k_bcc_cross_heavy(int64_t n, const
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
     int64_t a0, a1;
     const int32_t u = (int32_t)bc_item(items, it, off, &a0, &a1);
-    const int32_t pu_par = parent[u];
-    const int64_t pu = pre[u], su = nd[u];
+    const int4 ru = R[u];
+    const int64_t pu = ru.y, su = ru.z;
     for (int64_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
       const int32_t w = cols[a];
-      if (w == u || w < 0 || w >= n || w == pu_par || parent[w] == u) continue;
-      const int64_t pw = pre[w];
+      if (w == u || w < 0 || w >= n || w == ru.x) continue;
+      const int4 rw = R[w];
+      if (rw.x == u) continue;
+      const int64_t pw = rw.y;
       if (pu < pw && pw >= pu + su) hook_join<true>(u, w, L);
     }
   }
   block_release_device();
+}
+
+// Step 5 setup: each vertex's final label into its record (R[x].w = L[x],
+// L compressed).
+__global__ __launch_bounds__(kBcThreads) void k_bcc_pack_labels(int64_t n, const int32_t *__restrict__ L,
+                                                                int4 *R) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < n) reinterpret_cast<int32_t *>(R)[4 * x + 3] = L[x];
+}
+
+// The label of arc u -> w (u != w): its tree edge's when it is one (named by
+// the child), else that of the tree edge of its later end in preorder.
+__device__ __forceinline__ int32_t bc_arc_label(int32_t u, int32_t w, const int4 &ru,
+                                                const int4 &rw) {
+  if (rw.x == u) return rw.w;        // w is u's child
+  if (ru.x == w) return ru.w;        // w is u's parent
+  return ru.y > rw.y ? ru.w : rw.w;  // non-tree: the later end's tree edge
 }
 
 // Step 5 for heavy vertices: arc labels, and each vertex's label extremes into
@@ -368,9 +381,7 @@ __global__ __launch_bounds__(kBcThreads) void k_bcc_cross_heavy(int64_t n, const
 template <class OffT>
 __global__ __launch_bounds__(kBcThreads) void k_bcc_arcs_heavy(int64_t n, const OffT *__restrict__ off,
                                                                const int32_t *__restrict__ cols,
-                                                               const int32_t *__restrict__ parent,
-                                                               const int32_t *__restrict__ pre,
-                                                               const int32_t *__restrict__ L,
+                                                               const int4 *__restrict__ R,
                                                                int32_t *arc_label, int2 *ext,
                                                                const int64_t *__restrict__ items,
                                                                int64_t item_cap,
@@ -381,14 +392,13 @@ __global__ __launch_bounds__(kBcThreads) void k_bcc_arcs_heavy(int64_t n, const 
   for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
     int64_t a0, a1;
     const int32_t u = (int32_t)bc_item(items, it, off, &a0, &a1);
-    const int32_t pu = parent[u];
+    const int4 ru = R[u];
     int2 x = make_int2(INT32_MAX, -1);
     for (int64_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
       const int32_t w = cols[a];
       int32_t lab = -1;
       if (w != u && w >= 0 && w < n) {
-        const int32_t child = parent[w] == u ? w : pu == w ? u : (pre[u] > pre[w] ? u : w);
-        lab = L[child];
+        lab = bc_arc_label(u, w, ru, R[w]);
         x = bc_comb(x, make_int2(lab, lab));
       }
       arc_label[a] = lab;
@@ -417,14 +427,30 @@ __global__ __launch_bounds__(kBcThreads) void k_bcc_art_heavy(const int64_t *__r
   }
 }
 
+// Sum of x over the workgroup added to *out by one atomic.  Called by all
+// threads.
+template <int B>
+__device__ __forceinline__ void bc_block_add(int x, int32_t *out) {
+  __shared__ int s_sum[B / kWave];
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  if ((threadIdx.x & (kWave - 1)) == 0) s_sum[threadIdx.x / kWave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < B / kWave; ++w) t += s_sum[w];
+    if (t) atomicAdd(out, t);
+  }
+}
+
 // Step 5: arc labels, articulation points, and the number of components
-// (tree edges that are their component's smallest child).
+// (tree edges that are their component's smallest child), counted per
+// workgroup: a tree whose edges are mostly bridges has about as many
+// components as vertices, and an atomic per wave on the one counter
+// serialised the pass (C4: 3.2 ms).
 template <class OffT>
 __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_arcs(int64_t n, const OffT *__restrict__ off,
                                                        const int32_t *__restrict__ cols,
-                                                       const int32_t *__restrict__ parent,
-                                                       const int32_t *__restrict__ pre,
-                                                       const int32_t *__restrict__ L,
+                                                       const int4 *__restrict__ R,
                                                        int32_t *arc_label, uint8_t *art,
                                                        int2 *ext, int32_t *counters) {
   __shared__ int s_scan[kBcChunk + 1];
@@ -433,6 +459,7 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_arcs(int64_t n, const OffT 
   __shared__ int s_mn[kBcChunk], s_mx[kBcChunk];
   const int t = threadIdx.x;
   const int64_t chunks = (n + kBcChunk - 1) / kBcChunk;
+  int comps = 0;
   for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
     const int64_t v0 = c * kBcChunk, v = v0 + t;
     s_mn[t] = INT32_MAX;   // published by the scan's barriers
@@ -442,25 +469,22 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_arcs(int64_t n, const OffT 
                     int32_t lab = -1;
                     int2 val = make_int2(INT32_MAX, -1);
                     if (j >= 0 && w != u && w >= 0 && w < n) {
-                      const int32_t child = parent[w] == u ? w
-                                          : parent[u] == w ? u
-                                          : (pre[u] > pre[w] ? u : w);
-                      lab = L[child];
+                      lab = bc_arc_label(u, w, R[u], R[w]);
                       val = make_int2(lab, lab);
                     }
                     if (j >= 0) arc_label[a] = lab;
                     bc_run_extremes(j, val, s_mn, s_mx);
                   });
-    bool comp = false;
     if (v < n) {
       // a heavy vertex's arcs are the item pass's; its extremes start from
       // its own chunk's (none)
       if ((int64_t)(off[v + 1] - off[v]) > kBcHeavy) ext[v] = make_int2(s_mn[t], s_mx[t]);
       if (art) art[v] = (s_mn[t] != INT32_MAX && s_mn[t] != s_mx[t]) ? 1 : 0;
-      comp = !bc_is_root((int32_t)v, parent[v], n) && L[v] == (int32_t)v;
+      const int4 rv = R[v];
+      comps += !bc_is_root((int32_t)v, rv.x, n) && rv.w == (int32_t)v;
     }
-    wave_count(comp, &counters[kCntComponents]);
   }
+  bc_block_add<kBcChunk>(comps, &counters[kCntComponents]);
 }
 
 static unsigned bc_grid(const rst_ctx *ctx, int64_t n) {
@@ -470,9 +494,7 @@ static unsigned bc_grid(const rst_ctx *ctx, int64_t n) {
 }
 
 template <class OffT>
-static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, const int32_t *parent,
-                                const int32_t *pre, const int32_t *nd, const int2 *pn, int2 *A,
-                                int2 *pfx,
+static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, int4 *R, int2 *A, int2 *pfx,
                                 int2 *sfx, int2 *st, int64_t nb, int levels, int32_t *L,
                                 int64_t *items, int64_t item_cap, int32_t *arc_label, uint8_t *art,
                                 int32_t *counters) {
@@ -481,10 +503,10 @@ static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, const int32_t *p
   const unsigned grid = bc_grid(ctx, n);
   const unsigned hgrid = (unsigned)(ctx->num_cus * 4);
   hipLaunchKernelGGL(k_bcc_local<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off, g->cols,
-                     parent, pre, A, items, item_cap, counters);
+                     R, A, items, item_cap, counters);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_local_heavy<OffT>, dim3(hgrid), dim3(kBcThreads), 0, ctx->stream, n, off,
-                     g->cols, parent, pre, A, items, item_cap, counters);
+                     g->cols, R, A, items, item_cap, counters);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_blocks, dim3(grid_for(nb * kWave, kBcThreads)), dim3(kBcThreads), 0,
                      ctx->stream, n, A, pfx, sfx, st);
@@ -498,24 +520,27 @@ static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, const int32_t *p
   RST_HIP(hipGetLastError());
   const int64_t tblocks = (n + kBcThreads - 1) / kBcThreads;
   const unsigned tgrid = (unsigned)(tblocks < ctx->num_cus * 8 ? tblocks : ctx->num_cus * 8);
-  hipLaunchKernelGGL(k_bcc_rule_tree, dim3(tgrid), dim3(kBcThreads), 0, ctx->stream, n, parent, pn,
-                     A, pfx, sfx, st, nb, L, counters);
+  hipLaunchKernelGGL(k_bcc_rule_tree, dim3(tgrid), dim3(kBcThreads), 0, ctx->stream, n, R, A, pfx,
+                     sfx, st, nb, L, counters);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_rule_cross<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off,
-                     g->cols, parent, pre, nd, L);
+                     g->cols, R, L);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_cross_heavy<OffT>, dim3(hgrid), dim3(kBcThreads), 0, ctx->stream, n, off,
-                     g->cols, parent, pre, nd, L, items, item_cap, counters);
+                     g->cols, R, L, items, item_cap, counters);
   RST_HIP(hipGetLastError());
   RST_TRY(enqueue_compress(ctx, n, L, nullptr, nullptr));
+  hipLaunchKernelGGL(k_bcc_pack_labels, dim3(grid_for(n, kBcThreads)), dim3(kBcThreads), 0,
+                     ctx->stream, n, L, R);
+  RST_HIP(hipGetLastError());
   // the range structure is done with: pfx holds each heavy vertex's label
   // extremes from here on (indexed by vertex)
   int2 *ext = pfx;
   hipLaunchKernelGGL(k_bcc_arcs<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off, g->cols,
-                     parent, pre, L, arc_label, art, ext, counters);
+                     R, arc_label, art, ext, counters);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_arcs_heavy<OffT>, dim3(hgrid), dim3(kBcThreads), 0, ctx->stream, n, off,
-                     g->cols, parent, pre, L, arc_label, ext, items, item_cap, counters);
+                     g->cols, R, arc_label, ext, items, item_cap, counters);
   RST_HIP(hipGetLastError());
   if (art) {
     hipLaunchKernelGGL(k_bcc_art_heavy, dim3(grid_for(item_cap, kBcThreads)), dim3(kBcThreads), 0,
@@ -534,13 +559,13 @@ rst_status run_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent
   while (((int64_t)1 << levels) <= nb) ++levels;
   // heavy items: every heavy vertex has more than kBcHeavy arcs
   const int64_t item_cap = g->nnz / kBcHeavy + g->nnz / kBcSlice + 1;
-  RST_TRY(ws_reserve(ctx, depth_ws_bytes(n, plan) + 3 * ws_bytes((size_t)n, 4) +
-                              4 * ws_bytes((size_t)n, 8) + ws_bytes((size_t)(levels * nb), 8) +
-                              ws_bytes((size_t)item_cap, 8)));
+  RST_TRY(ws_reserve(ctx, depth_ws_bytes(n, plan) + ws_bytes((size_t)n, 16) +
+                              ws_bytes((size_t)n, 4) + 3 * ws_bytes((size_t)n, 8) +
+                              ws_bytes((size_t)(levels * nb), 8) + ws_bytes((size_t)item_cap, 8)));
   int32_t *counters = ws_take<int32_t>(ctx, 64);
-  int32_t *pre = ws_take<int32_t>(ctx, n);
-  int32_t *nd = ws_take<int32_t>(ctx, n);
-  int2 *pn = ws_take<int2>(ctx, n);
+  // per vertex (parent, pre, nd, label): one gather for all that an arc pass
+  // needs of its far end
+  int4 *R = ws_take<int4>(ctx, n);
   int32_t *L = ws_take<int32_t>(ctx, n);
   int2 *A = ws_take<int2>(ctx, n);
   int2 *pfx = ws_take<int2>(ctx, n);
@@ -548,14 +573,14 @@ rst_status run_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent
   int2 *st = ws_take<int2>(ctx, (size_t)(levels * nb));
   int64_t *items = ws_take<int64_t>(ctx, (size_t)item_cap);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
-  RST_TRY(run_tour_preorder(ctx, n, parent, pre, nd, pn, counters));
+  RST_TRY(run_tour_preorder(ctx, n, parent, R, counters));
   if (ctx->host_pinned[kCntBccRoots] != 1) return RST_E_DISCONNECTED;
   if (g->offset_bytes == 4)
-    RST_TRY(bc_arc_passes<int32_t>(ctx, g, parent, pre, nd, pn, A, pfx, sfx, st, nb, levels, L,
-                                   items, item_cap, arc_label, art, counters));
+    RST_TRY(bc_arc_passes<int32_t>(ctx, g, R, A, pfx, sfx, st, nb, levels, L, items, item_cap,
+                                   arc_label, art, counters));
   else
-    RST_TRY(bc_arc_passes<int64_t>(ctx, g, parent, pre, nd, pn, A, pfx, sfx, st, nb, levels, L,
-                                   items, item_cap, arc_label, art, counters));
+    RST_TRY(bc_arc_passes<int64_t>(ctx, g, R, A, pfx, sfx, st, nb, levels, L, items, item_cap,
+                                   arc_label, art, counters));
   RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
                          hipMemcpyDeviceToHost, ctx->stream));
   RST_HIP(hipStreamSynchronize(ctx->stream));

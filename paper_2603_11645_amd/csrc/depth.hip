@@ -50,7 +50,18 @@ __device__ __forceinline__ bool tour_arc_down(int32_t e) {
   return (__popc((uint32_t)e) & 1) == 0;
 }
 
-// Out-arc lists of the forest of parent edges (head = -1 beforehand).
+// Out-arc lists of the forest of parent edges, in two passes: every non-root
+// x's list starts as its up arc alone (which so stays last), then every
+// child puts its down arc in front of its parent's list.  (An exchange for
+// the up arc as well cost a chain-like tree's linking a third of its time.)
+template <int B>
+__global__ __launch_bounds__(B) void k_depth_heads(int64_t n, const int32_t *__restrict__ parent,
+                                                   int32_t *head) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  head[x] = depth_is_root((int32_t)x, parent[x], n) ? -1 : tour_down(x) ^ 1;
+}
+
 template <int B>
 __global__ __launch_bounds__(B) void k_depth_link(int64_t n, const int32_t *__restrict__ parent,
                                                   int32_t *head, int32_t *next) {
@@ -60,9 +71,8 @@ __global__ __launch_bounds__(B) void k_depth_link(int64_t n, const int32_t *__re
   int2 nx = make_int2(-1, -1);
   if (!depth_is_root((int32_t)x, p, n)) {
     const int32_t dn = tour_down(x);
-    const int32_t nd = atomicExch(&head[p], dn);       // p -> x
-    const int32_t nu = atomicExch(&head[x], dn ^ 1);   // x -> p
-    nx = (dn & 1) ? make_int2(nu, nd) : make_int2(nd, nu);   // next[2x], next[2x+1]
+    const int32_t nd = atomicExch(&head[p], dn);   // p -> x; x -> p ends x's list
+    nx = (dn & 1) ? make_int2(-1, nd) : make_int2(nd, -1);   // next[2x], next[2x+1]
   }
   reinterpret_cast<int2 *>(next)[x] = nx;
 }
@@ -205,13 +215,13 @@ __global__ __launch_bounds__(B) void k_depth_out_rounds(int64_t n, const int32_t
 // x's down arc d and up arc u, pre(x) = (n - 1) - D(d) and nd(x) = D(d) -
 // D(u) + 1 (the down arcs strictly inside x's excursion are its
 // descendants'); the root has pre 0 and nd n.  Roots are counted into counters[kCntBccRoots].
-__device__ __forceinline__ void pre_store(int64_t n, int64_t x, bool root, uint32_t d0,
-                                          uint32_t d1, int32_t *pre, int32_t *nd, int2 *pn) {
+// Each vertex's record R[x] = (parent, pre, nd, 0): one 16-byte gather
+// serves a consumer that needs several of them for a random vertex.
+__device__ __forceinline__ void pre_store(int64_t n, int64_t x, int32_t par, bool root, uint32_t d0,
+                                          uint32_t d1, int4 *R) {
   const int32_t p = root ? 0 : (int32_t)(n - 1) - (int32_t)d0;
   const int32_t s = root ? (int32_t)n : (int32_t)d0 - (int32_t)d1 + 1;
-  pre[x] = p;
-  nd[x] = s;
-  pn[x] = make_int2(p, s);   // both in one word for gathers that need both
+  R[x] = make_int4(par, p, s, 0);
 }
 
 // codes (ruler << 8 | weight walked since it) of both arcs, from the 32-bit walk
@@ -219,13 +229,13 @@ template <int B>
 __global__ __launch_bounds__(B) void k_pre_out(int64_t n, const int32_t *__restrict__ parent,
                                                const int32_t *__restrict__ w,
                                                const uint32_t *__restrict__ d1, int64_t rw1_cap,
-                                               int32_t *pre, int32_t *nd, int2 *pn,
-                                               int32_t *counters) {
+                                               int4 *R, int32_t *counters) {
   if (counters[kCntGOverflow]) return;   // block-uniform: the caller falls back
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool root = false;
   if (x < n) {
-    root = depth_is_root((int32_t)x, parent[x], n);
+    const int32_t par = parent[x];
+    root = depth_is_root((int32_t)x, par, n);
     uint32_t a = 0, b = 0;
     if (!root) {
       int2 c = reinterpret_cast<const int2 *>(w)[x];
@@ -234,23 +244,24 @@ __global__ __launch_bounds__(B) void k_pre_out(int64_t n, const int32_t *__restr
       a = r0 < rw1_cap ? d1[r0] - ((uint32_t)c.x & 255u) : 0u;
       b = r1 < rw1_cap ? d1[r1] - ((uint32_t)c.y & 255u) : 0u;
     }
-    pre_store(n, x, root, a, b, pre, nd, pn);
+    pre_store(n, x, par, root, a, b, R);
   }
   wave_count(root, &counters[kCntBccRoots]);
 }
 
 template <int B>
 __global__ __launch_bounds__(B) void k_pre_out_rounds(int64_t n, const int32_t *__restrict__ parent,
-                                                      const uint64_t *__restrict__ w, int32_t *pre,
-                                                      int32_t *nd, int2 *pn, int32_t *counters) {
+                                                      const uint64_t *__restrict__ w, int4 *R,
+                                                      int32_t *counters) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool root = false;
   if (x < n) {
-    root = depth_is_root((int32_t)x, parent[x], n);
+    const int32_t par = parent[x];
+    root = depth_is_root((int32_t)x, par, n);
     const int32_t dn = tour_down(x);
     const uint32_t a = root ? 0u : (uint32_t)(w[dn] >> 32);
     const uint32_t b = root ? 0u : (uint32_t)(w[dn ^ 1] >> 32);
-    pre_store(n, x, root, a, b, pre, nd, pn);
+    pre_store(n, x, par, root, a, b, R);
   }
   wave_count(root, &counters[kCntBccRoots]);
 }
@@ -271,7 +282,8 @@ rst_status run_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_
   GlistBufs gl;
   glist_take(ctx, plan, gl);
   RST_TRY(enqueue_fill(ctx, counters, 32, 0));
-  RST_TRY(enqueue_fill(ctx, head, n, -1));
+  RST_SWEEP(ctx, k_depth_heads, n, n, parent, head);
+  RST_HIP(hipGetLastError());
   RST_SWEEP(ctx, k_depth_link, n, n, parent, head, next);
   RST_HIP(hipGetLastError());
   RST_SWEEP(ctx, k_depth_words, n, n, parent, head, next, w, gl.heads[0], plan.hcap, counters);
@@ -297,15 +309,16 @@ rst_status run_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_
   return RST_OK;
 }
 
-rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *pre,
-                              int32_t *nd, int2 *pn, int32_t *counters) {
+rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int4 *R,
+                              int32_t *counters) {
   const GlistPlan plan = glist_plan(2 * n, n / 2 + 1, ctx->opt.rank_stride);
   int32_t *head = ws_take<int32_t>(ctx, n);
   int32_t *next = ws_take<int32_t>(ctx, 2 * n);
   uint64_t *w = ws_take<uint64_t>(ctx, 2 * n);
   GlistBufs gl;
   glist_take(ctx, plan, gl);
-  RST_TRY(enqueue_fill(ctx, head, n, -1));
+  RST_SWEEP(ctx, k_depth_heads, n, n, parent, head);
+  RST_HIP(hipGetLastError());
   RST_SWEEP(ctx, k_depth_link, n, n, parent, head, next);
   RST_HIP(hipGetLastError());
   // 32-bit words with the weights from the arcs' ids: half the bytes of
@@ -314,7 +327,7 @@ rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int
   RST_SWEEP(ctx, k_pre_words32, n, n, parent, head, next, w32, gl.heads[0], plan.hcap, counters);
   RST_HIP(hipGetLastError());
   RST_TRY(enqueue_glist_rank(ctx, w32, false, gl, counters, true));
-  RST_SWEEP(ctx, k_pre_out, n, n, parent, w32, gl.d1, plan.cap[1], pre, nd, pn, counters);
+  RST_SWEEP(ctx, k_pre_out, n, n, parent, w32, gl.d1, plan.cap[1], R, counters);
   RST_HIP(hipGetLastError());
   RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
                          hipMemcpyDeviceToHost, ctx->stream));
@@ -325,7 +338,7 @@ rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int
     RST_SWEEP(ctx, k_pre_words, n, n, parent, head, next, w, gl.heads[0], plan.hcap, counters);
     RST_HIP(hipGetLastError());
     RST_TRY(enqueue_rank_rounds(ctx, 2 * n, w, rank_rounds_for(2 * n), nullptr, nullptr));
-    RST_SWEEP(ctx, k_pre_out_rounds, n, n, parent, w, pre, nd, pn, counters);
+    RST_SWEEP(ctx, k_pre_out_rounds, n, n, parent, w, R, counters);
     RST_HIP(hipGetLastError());
     RST_HIP(hipMemcpyAsync(ctx->host_pinned, counters, kCntTotal * sizeof(int32_t),
                            hipMemcpyDeviceToHost, ctx->stream));

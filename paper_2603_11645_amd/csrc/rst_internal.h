@@ -361,12 +361,13 @@ rst_status enqueue_endsucc(rst_ctx *ctx, int64_t n, const int32_t *head, const i
 // *max_depth (host, nullable) the largest; synchronous
 rst_status run_tree_depth(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *depth,
                           int64_t *max_depth);
-// preorder numbers and subtree sizes of the tree given by parent (device);
-// its buffers come from the workspace after the caller's (depth_ws_bytes
-// less the counters); counters (device, 64) read back; synchronous
+// preorder numbers and subtree sizes of the tree given by parent (device),
+// as records R[x] = (parent[x], pre(x), nd(x), 0); its buffers come from the
+// workspace after the caller's (depth_ws_bytes less the counters); counters
+// (device, 64) read back; synchronous
 size_t depth_ws_bytes(int64_t n, const GlistPlan &p);
-rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int32_t *pre,
-                             int32_t *nd, int2 *pn, int32_t *counters);
+rst_status run_tour_preorder(rst_ctx *ctx, int64_t n, const int32_t *parent, int4 *R,
+                             int32_t *counters);
 // bcc.hip: biconnected components from a rooted spanning tree (synchronous)
 rst_status run_biconnected(rst_ctx *ctx, const rst_csr *g, const int32_t *parent,
                            int32_t *arc_label, uint8_t *art, int64_t *num_components);
