@@ -144,13 +144,18 @@ __global__ __launch_bounds__(kBlock) void k_pr_reverse(int64_t n, const int32_t 
 }
 
 // Final re-rooting targets: min id of every tree (atomic minimum over its
-// vertices) ...
+// vertices, skipped where the minimum read beforehand is already smaller:
+// in one large tree every vertex's atomic would go to the same word) ...
 __global__ __launch_bounds__(kBlock) void k_pr_minid(int64_t n, const int32_t *__restrict__ anc,
                                                      int levels, const int32_t *__restrict__ changed,
                                                      int32_t *minid) {
   const int32_t *rep = anc + (size_t)pr_top(changed, levels) * (size_t)n;
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) atomicMin(&minid[rep[v]], (int32_t)v);
+  if (v < n) {
+    int32_t *m = &minid[rep[v]];
+    if ((int32_t)v < __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMin(m, (int32_t)v);
+  }
 }
 
 // ... then on[t] = 1 for the designated root and for the minimum id of every
