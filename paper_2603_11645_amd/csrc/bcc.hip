@@ -523,6 +523,9 @@ static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, int4 *R, int2 *A
   hipLaunchKernelGGL(k_bcc_rule_tree, dim3(tgrid), dim3(kBcThreads), 0, ctx->stream, n, R, A, pfx,
                      sfx, st, nb, L, counters);
   RST_HIP(hipGetLastError());
+  // the tree rule's joins follow the tree, so its union-find paths are long:
+  // every word to its root before the non-tree edges' finds
+  RST_TRY(enqueue_compress(ctx, n, L, nullptr, nullptr));
   hipLaunchKernelGGL(k_bcc_rule_cross<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off,
                      g->cols, R, L);
   RST_HIP(hipGetLastError());
