@@ -111,13 +111,25 @@ __device__ __forceinline__ bool bc_is_root(int32_t v, int32_t p, int64_t n) {
   return p == v || p < 0 || p >= n;
 }
 
-// Step 2: local extremes, stored at each vertex's preorder position.
+// The rule of step 4 for non-tree edge (u, w), seen from u: with pre(u) <
+// pre(w) and w outside u's subtree it joins the tree edges of u and w.
+__device__ __forceinline__ void bc_cross(int32_t u, int32_t w, const int4 &ru, const int4 &rw,
+                                         int32_t *L) {
+  const int64_t pu = ru.y, pw = rw.y;
+  if (pu < pw && pw >= pu + ru.z) hook_join<true>(u, w, L);
+}
+
+// Step 2: local extremes, stored at each vertex's preorder position; the
+// same pass over the arcs applies step 4's rule to the non-tree edges (the
+// joins of step 4 commute, and both need the far end's record).  Ends with a
+// device-scope release per workgroup (hooks in global memory, read on every
+// XCD next).
 template <class OffT>
 __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT *__restrict__ off,
                                                         const int32_t *__restrict__ cols,
                                                         const int4 *__restrict__ R, int2 *A,
-                                                        int64_t *items, int64_t item_cap,
-                                                        int32_t *counters) {
+                                                        int32_t *L, int64_t *items,
+                                                        int64_t item_cap, int32_t *counters) {
   __shared__ int s_scan[kBcChunk + 1];
   __shared__ OffT s_beg[kBcChunk];
   __shared__ int s_wave[kBcChunk / kWave];
@@ -145,8 +157,11 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT
                     // non-tree arcs only (arcs to the parent or a child, and
                     // their parallel copies, are tree arcs)
                     if (j >= 0 && w != u && w >= 0 && w < n) {
-                      const int4 rw = R[w];
-                      if (w != R[u].x && rw.x != u) val = make_int2(rw.y, rw.y);
+                      const int4 ru = R[u], rw = R[w];
+                      if (w != ru.x && rw.x != u) {
+                        val = make_int2(rw.y, rw.y);
+                        bc_cross(u, w, ru, rw, L);
+                      }
                     }
                     bc_run_extremes(j, val, s_lo, s_hi);
                   });
@@ -155,6 +170,7 @@ __global__ __launch_bounds__(kBcChunk, 8) void k_bcc_local(int64_t n, const OffT
       else atomicOr(&counters[kCntRangeErr], 1);
     }
   }
+  block_release_device();
 }
 
 // The arcs [a0, a1) of heavy item `it` (vertex v, slice k).
@@ -183,12 +199,14 @@ __device__ __forceinline__ int2 bc_block_extremes(int2 x, int2 *s_red) {
 }
 
 // Step 2 for heavy vertices: each item's extremes into A[pre(v)] by atomics
-// (after k_bcc_local wrote the vertex's own).
+// (after k_bcc_local wrote the vertex's own), and step 4's rule for its
+// non-tree edges.  Ends with a release as k_bcc_local.
 template <class OffT>
 __global__ __launch_bounds__(kBcThreads) void k_bcc_local_heavy(int64_t n, const OffT *__restrict__ off,
                                                                 const int32_t *__restrict__ cols,
                                                                 const int4 *__restrict__ R,
-                                                                int2 *A, const int64_t *__restrict__ items,
+                                                                int2 *A, int32_t *L,
+                                                                const int64_t *__restrict__ items,
                                                                 int64_t item_cap,
                                                                 const int32_t *__restrict__ counters) {
   __shared__ int2 s_red[kBcThreads / kWave];
@@ -203,7 +221,10 @@ __global__ __launch_bounds__(kBcThreads) void k_bcc_local_heavy(int64_t n, const
       const int32_t w = cols[a];
       if (w != u && w >= 0 && w < n && w != ru.x) {
         const int4 rw = R[w];
-        if (rw.x != u) x = bc_comb(x, make_int2(rw.y, rw.y));
+        if (rw.x != u) {
+          x = bc_comb(x, make_int2(rw.y, rw.y));
+          bc_cross(u, w, ru, rw, L);
+        }
       }
     }
     x = bc_block_extremes(x, s_red);
@@ -213,6 +234,7 @@ __global__ __launch_bounds__(kBcThreads) void k_bcc_local_heavy(int64_t n, const
       atomicMax(&reinterpret_cast<int *>(A)[2 * (int64_t)pv + 1], x.y);
     }
   }
+  block_release_device();
 }
 
 // Step 3a: one wave per block of 64 positions: prefix and suffix extremes
@@ -304,56 +326,6 @@ __global__ __launch_bounds__(kBcThreads) void k_bcc_rule_tree(int64_t n, const i
     }
     const int2 lh = bc_range(pv, pv + sv - 1, A, pfx, sfx, st, nb);
     if (lh.x < pp || lh.y >= pp + sp) hook_join<true>((int32_t)v, p, L);
-  }
-  block_release_device();
-}
-
-// Step 4, non-tree edges: (u, w) with pre(u) < pre(w) and w outside u's
-// subtree joins the tree edges of u and w.  Ends with a release as above.
-template <class OffT>
-__global__ __launch_bounds__(kBcChunk, 8) void k_bcc_rule_cross(int64_t n, const OffT *__restrict__ off,
-                                                             const int32_t *__restrict__ cols,
-                                                             const int4 *__restrict__ R,
-                                                             int32_t *L) {
-  __shared__ int s_scan[kBcChunk + 1];
-  __shared__ OffT s_beg[kBcChunk];
-  __shared__ int s_wave[kBcChunk / kWave];
-  const int64_t chunks = (n + kBcChunk - 1) / kBcChunk;
-  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x)
-    bc_chunk_arcs(n, c * kBcChunk, off, cols, s_scan, s_beg, s_wave,
-                  [&](int j, int32_t u, int32_t w, int64_t) {
-                    if (j < 0 || w == u || w < 0 || w >= n) return;
-                    const int4 ru = R[u], rw = R[w];
-                    if (w == ru.x || rw.x == u) return;
-                    const int64_t pu = ru.y, pw = rw.y;
-                    if (pu < pw && pw >= pu + ru.z) hook_join<true>(u, w, L);
-                  });
-  block_release_device();
-}
-
-// Step 4 for heavy vertices' non-tree edges.  Ends with a release as above.
-template <class OffT>
-__global__ __launch_bounds__(kBcThreads) void k_bcc_cross_heavy(int64_t n, const OffT *__restrict__ off,
-                                                                const int32_t *__restrict__ cols,
-                                                                const int4 *__restrict__ R,
-                                                                int32_t *L, const int64_t *__restrict__ items,
-                                                                int64_t item_cap,
-                                                                const int32_t *__restrict__ counters) {
-  int64_t count = counters[kCntBccItems];
-  if (count > item_cap) count = item_cap;
-  for (int64_t it = blockIdx.x; it < count; it += gridDim.x) {
-    int64_t a0, a1;
-    const int32_t u = (int32_t)bc_item(items, it, off, &a0, &a1);
-    const int4 ru = R[u];
-    const int64_t pu = ru.y, su = ru.z;
-    for (int64_t a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
-      const int32_t w = cols[a];
-      if (w == u || w < 0 || w >= n || w == ru.x) continue;
-      const int4 rw = R[w];
-      if (rw.x == u) continue;
-      const int64_t pw = rw.y;
-      if (pu < pw && pw >= pu + su) hook_join<true>(u, w, L);
-    }
   }
   block_release_device();
 }
@@ -502,11 +474,13 @@ static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, int4 *R, int2 *A
   const OffT *off = static_cast<const OffT *>(g->offsets);
   const unsigned grid = bc_grid(ctx, n);
   const unsigned hgrid = (unsigned)(ctx->num_cus * 4);
+  RST_SWEEP(ctx, k_bcc_iota, n, n, L);
+  RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_local<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off, g->cols,
-                     R, A, items, item_cap, counters);
+                     R, A, L, items, item_cap, counters);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_local_heavy<OffT>, dim3(hgrid), dim3(kBcThreads), 0, ctx->stream, n, off,
-                     g->cols, R, A, items, item_cap, counters);
+                     g->cols, R, A, L, items, item_cap, counters);
   RST_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_bcc_blocks, dim3(grid_for(nb * kWave, kBcThreads)), dim3(kBcThreads), 0,
                      ctx->stream, n, A, pfx, sfx, st);
@@ -516,21 +490,10 @@ static rst_status bc_arc_passes(rst_ctx *ctx, const rst_csr *g, int4 *R, int2 *A
                        ctx->stream, nb, k, st);
     RST_HIP(hipGetLastError());
   }
-  RST_SWEEP(ctx, k_bcc_iota, n, n, L);
-  RST_HIP(hipGetLastError());
   const int64_t tblocks = (n + kBcThreads - 1) / kBcThreads;
   const unsigned tgrid = (unsigned)(tblocks < ctx->num_cus * 8 ? tblocks : ctx->num_cus * 8);
   hipLaunchKernelGGL(k_bcc_rule_tree, dim3(tgrid), dim3(kBcThreads), 0, ctx->stream, n, R, A, pfx,
                      sfx, st, nb, L, counters);
-  RST_HIP(hipGetLastError());
-  // the tree rule's joins follow the tree, so its union-find paths are long:
-  // every word to its root before the non-tree edges' finds
-  RST_TRY(enqueue_compress(ctx, n, L, nullptr, nullptr));
-  hipLaunchKernelGGL(k_bcc_rule_cross<OffT>, dim3(grid), dim3(kBcChunk), 0, ctx->stream, n, off,
-                     g->cols, R, L);
-  RST_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_bcc_cross_heavy<OffT>, dim3(hgrid), dim3(kBcThreads), 0, ctx->stream, n, off,
-                     g->cols, R, L, items, item_cap, counters);
   RST_HIP(hipGetLastError());
   RST_TRY(enqueue_compress(ctx, n, L, nullptr, nullptr));
   hipLaunchKernelGGL(k_bcc_pack_labels, dim3(grid_for(n, kBcThreads)), dim3(kBcThreads), 0,
