@@ -17,7 +17,12 @@
 // lead either into the dominant tree too or to a vertex outside it, which
 // offers the reverse arc itself (the CSR is symmetric).  Without a dominant
 // tree (chains, meshes: no sample root holds half the sample) each edge is
-// visited once instead, from its larger end.
+// visited once instead, from its larger end, after a first pass without
+// finds: every vertex hooks to the smallest of the first kGhMinArcs
+// neighbours when that one is smaller than itself (pointers to smaller ids
+// cannot close a cycle, so this is a forest of valid hooks, taken reading
+// only the vertex's own arcs); on a chain with random ids it hooks two
+// thirds of the vertices, and the sweep skips those edges.
 #include "rst_internal.h"
 #include "device_common.h"
 #include "unionfind.h"
@@ -29,6 +34,7 @@ constexpr int kGhSampleThreads = 1024;
 constexpr int kGhSamplePer = 4;       // sampled vertices per thread (giant, probe)
 constexpr int kGhHash = 8192;         // LDS hash slots of the root count
 constexpr int kGhTileShift = 13;      // the tile pass's tile: 8192 consecutive ids
+constexpr int kGhMinArcs = 16;        // arcs the first pass looks at per vertex
 
 // counter-based sample index (splitmix64 finaliser of seed ^ i)
 __device__ __forceinline__ uint64_t gh_mix(uint64_t z) {
@@ -55,6 +61,33 @@ __global__ __launch_bounds__(B) void k_gh_init(int64_t n, int32_t *cc, int32_t *
   tu[v] = -1;
   tv[v] = -1;
   if (head) store_agent(&head[v], -1);
+}
+
+// The first pass without a dominant tree: v (still a root, fresh from
+// k_gh_init) hooks to m, the smallest of its first kGhMinArcs neighbours, when
+// m < v; the edge (v, m) goes to slot v and its arcs onto the lists.  Only
+// v's own word changes, so no compare-and-swap is needed; the sweep after it
+// reads the words (agent-scope stores).
+template <class OffT>
+__global__ __launch_bounds__(kBlock) void k_gh_minhook(int64_t n, const OffT *__restrict__ off,
+                                                       const int32_t *__restrict__ cols,
+                                                       const uint8_t *__restrict__ vmask,
+                                                       int32_t *cc, int32_t *tu, int32_t *tv,
+                                                       int32_t *head, int32_t *next) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n || (vmask && vmask[v])) return;
+  const OffT b = off[v], e = off[v + 1];
+  const OffT last = e - b > kGhMinArcs ? b + kGhMinArcs : e;
+  int32_t m = (int32_t)v;
+  for (OffT a = b; a < last; ++a) {
+    const int32_t w = cols[a];
+    if (w >= 0 && w < m) m = w;
+  }
+  if (m == (int32_t)v) return;
+  store_agent(&cc[v], m);
+  tu[v] = (int32_t)v;
+  tv[v] = m;
+  if (head) link_slot((int32_t)v, (int32_t)v, m, head, next);
 }
 
 // Each vertex hooks along K of its arcs (all of them when it has at most K),
@@ -230,9 +263,11 @@ __global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const Off
                                                             const int64_t *__restrict__ vtx_off,
                                                             int num_graphs,
                                                             const int32_t *__restrict__ giants,
-                                                            const uint8_t *__restrict__ gsel) {
+                                                            const uint8_t *__restrict__ gsel,
+                                                            int minhook) {
   __shared__ int s_scan[kGhThreads + 1];
   __shared__ OffT s_beg[kGhThreads];
+  __shared__ int32_t s_min[kGhThreads];   // the first pass's edge (v, s_min) or -1
   __shared__ int s_wave[kGhThreads / kWave];
   __shared__ int2 s_q[kGhThreads / kWave][2 * kWave];   // per-wave queue of kept arcs
   const int t = threadIdx.x;
@@ -247,6 +282,9 @@ __global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const Off
     const int64_t v = v0 + t;
     int deg = 0;
     OffT beg = 0;
+    // slot v holds (v, m) only when the first pass hooked v (a root never
+    // records an edge that starts at itself before the sweep below)
+    s_min[t] = (minhook && v < n && tu[v] == (int32_t)v) ? tv[v] : -1;
     if (v < n && !(vmask && vmask[v]) && !(gsel && !gsel[v])) {
       const OffT b = off[v], e = off[v + 1];
       if (e > b) locals += (cols[b] >> kGhTileShift) == (int32_t)(v >> kGhTileShift);
@@ -272,7 +310,7 @@ __global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const Off
         const int j = lds_upper_search(s_scan, kGhThreads, k);
         u = (int32_t)(v0 + j);
         w = cols[s_beg[j] + (OffT)(k - s_scan[j])];
-        keep = giant >= 0 ? w != u : w < u;
+        keep = giant >= 0 ? w != u : (w < u && w != s_min[j]);
       }
       const uint64_t m = __ballot(keep);
       if (keep) q[qn + lanes_below(m)] = make_int2(u, w);
@@ -351,6 +389,9 @@ int ghook_sample_arcs(const rst_ctx *ctx, const rst_csr *g) {
 rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, bool init) {
   const int64_t n = g->n;
   const int K = ghook_sample_arcs(ctx, g);
+  // the first pass needs every vertex a root with an empty slot (fresh init)
+  // and is meant for sweeps without a dominant tree
+  const int minhook = (init && K == 0 && !f.gsel) ? 1 : 0;
   RST_KMARK(ctx, RST_KERNEL_HOOK_SAMPLE, 0);
   if (init) {
     RST_SWEEP(ctx, k_gh_init, n, n, f.cc, f.tu, f.tv, f.head);
@@ -378,6 +419,17 @@ rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, bo
     RST_HIP(hipGetLastError());
   } else {
     RST_TRY(enqueue_fill(ctx, f.counters + kCntGiant, 1, -1));
+    if (minhook) {
+      if (g->offset_bytes == 4)
+        hipLaunchKernelGGL(k_gh_minhook<int32_t>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
+                           ctx->stream, n, (const int32_t *)g->offsets, g->cols, f.vmask, f.cc,
+                           f.tu, f.tv, f.head, f.next);
+      else
+        hipLaunchKernelGGL(k_gh_minhook<int64_t>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
+                           ctx->stream, n, (const int64_t *)g->offsets, g->cols, f.vmask, f.cc,
+                           f.tu, f.tv, f.head, f.next);
+      RST_HIP(hipGetLastError());
+    }
   }
   RST_KMARK(ctx, RST_KERNEL_HOOK_SAMPLE, 1);
   RST_KMARK(ctx, RST_KERNEL_HOOK_GLOBAL, 0);
@@ -387,11 +439,11 @@ rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, bo
   if (g->offset_bytes == 4)
     hipLaunchKernelGGL(k_gh_sweep<int32_t>, dim3(grid), dim3(kGhThreads), 0, ctx->stream, n,
                        (const int32_t *)g->offsets, g->cols, f.vmask, f.cc, f.tu, f.tv, f.head,
-                       f.next, f.counters, f.vtx_off, f.num_graphs, batch_giants, f.gsel);
+                       f.next, f.counters, f.vtx_off, f.num_graphs, batch_giants, f.gsel, minhook);
   else
     hipLaunchKernelGGL(k_gh_sweep<int64_t>, dim3(grid), dim3(kGhThreads), 0, ctx->stream, n,
                        (const int64_t *)g->offsets, g->cols, f.vmask, f.cc, f.tu, f.tv, f.head,
-                       f.next, f.counters, f.vtx_off, f.num_graphs, batch_giants, f.gsel);
+                       f.next, f.counters, f.vtx_off, f.num_graphs, batch_giants, f.gsel, minhook);
   RST_HIP(hipGetLastError());
   RST_KMARK(ctx, RST_KERNEL_HOOK_GLOBAL, 1);
   return RST_OK;
