@@ -65,15 +65,15 @@ __global__ __launch_bounds__(B) void k_gh_init(int64_t n, int32_t *cc, int32_t *
 
 // The first pass without a dominant tree: v (still a root, fresh from
 // k_gh_init) hooks to m, the smallest of its first kGhMinArcs neighbours, when
-// m < v; the edge (v, m) goes to slot v and its arcs onto the lists.  Only
-// v's own word changes, so no compare-and-swap is needed; the sweep after it
-// reads the words (agent-scope stores).
+// m < v; the edge (v, m) goes to slot v.  Only v's own word changes, so no
+// compare-and-swap is needed; the sweep after it reads the words (agent-scope
+// stores) and puts the slot's arcs onto the lists (there the exchanges
+// overlap the sweep's finds; here they cost the pass most of its time).
 template <class OffT>
 __global__ __launch_bounds__(kBlock) void k_gh_minhook(int64_t n, const OffT *__restrict__ off,
                                                        const int32_t *__restrict__ cols,
                                                        const uint8_t *__restrict__ vmask,
-                                                       int32_t *cc, int32_t *tu, int32_t *tv,
-                                                       int32_t *head, int32_t *next) {
+                                                       int32_t *cc, int32_t *tu, int32_t *tv) {
   const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n || (vmask && vmask[v])) return;
   const OffT b = off[v], e = off[v + 1];
@@ -87,7 +87,6 @@ __global__ __launch_bounds__(kBlock) void k_gh_minhook(int64_t n, const OffT *__
   store_agent(&cc[v], m);
   tu[v] = (int32_t)v;
   tv[v] = m;
-  if (head) link_slot((int32_t)v, (int32_t)v, m, head, next);
 }
 
 // Each vertex hooks along K of its arcs (all of them when it has at most K),
@@ -283,8 +282,11 @@ __global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const Off
     int deg = 0;
     OffT beg = 0;
     // slot v holds (v, m) only when the first pass hooked v (a root never
-    // records an edge that starts at itself before the sweep below)
-    s_min[t] = (minhook && v < n && tu[v] == (int32_t)v) ? tv[v] : -1;
+    // records an edge that starts at itself before the sweep below); its
+    // arcs go onto the lists here
+    const int32_t mv = (minhook && v < n && tu[v] == (int32_t)v) ? tv[v] : -1;
+    s_min[t] = mv;
+    if (mv >= 0 && head) link_slot((int32_t)v, (int32_t)v, mv, head, next);
     if (v < n && !(vmask && vmask[v]) && !(gsel && !gsel[v])) {
       const OffT b = off[v], e = off[v + 1];
       if (e > b) locals += (cols[b] >> kGhTileShift) == (int32_t)(v >> kGhTileShift);
@@ -423,11 +425,11 @@ rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, bo
       if (g->offset_bytes == 4)
         hipLaunchKernelGGL(k_gh_minhook<int32_t>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
                            ctx->stream, n, (const int32_t *)g->offsets, g->cols, f.vmask, f.cc,
-                           f.tu, f.tv, f.head, f.next);
+                           f.tu, f.tv);
       else
         hipLaunchKernelGGL(k_gh_minhook<int64_t>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
                            ctx->stream, n, (const int64_t *)g->offsets, g->cols, f.vmask, f.cc,
-                           f.tu, f.tv, f.head, f.next);
+                           f.tu, f.tv);
       RST_HIP(hipGetLastError());
     }
   }
