@@ -21,6 +21,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -116,12 +118,29 @@ def cpu_baseline(g, root, runs=5):
             "ms_per_rst": round(t * 1e3, 2), "runs_ms": [round(x * 1e3, 2) for x in times]}
 
 
-def kernel_bytes(name, g, st):
+def first_pass_hooks(g, arcs=16):
+    """Vertices the global sweep's first pass hooks (the smallest of the
+    first `arcs` neighbours is smaller than the vertex), and the arcs it reads."""
+    off = g.offsets.astype(np.int64)
+    deg = np.diff(off)
+    m = np.arange(g.n, dtype=np.int64)
+    for k in range(arcs):
+        sel = np.nonzero(deg > k)[0]
+        if sel.size == 0:
+            break
+        m[sel] = np.minimum(m[sel], g.cols[off[sel] + k])
+    return int(np.count_nonzero(m < np.arange(g.n))), int(np.minimum(deg, arcs).sum())
+
+
+def kernel_bytes(name, g, st, K, first):
     """Algorithmic bytes per launch of the kernels the library times: what
-    the method must move (int32 ids, w_o-byte offsets), not what the caches do."""
+    the method must move (int32 ids, w_o-byte offsets), not what the caches do.
+    K: arcs sampled per vertex by the global hooking; first: (hooks, arcs
+    read) of its first pass, which runs when K is 0."""
     n, nnz, A = g.n, g.nnz, 2 * g.n
     w_o = g.offset_bytes
     T = n - st["components"]
+    T1, a1 = first if K == 0 else (0, 0)
     X = st["cross_edges"]
     R1 = st["rank_exits"]          # rulers of the sparse ruling set (words of level 2)
     return {
@@ -135,16 +154,24 @@ def kernel_bytes(name, g, st):
         # edge recorded (8), two list-head exchanges and the next pair (16)
         "late_hooks": 16 * X + 28 * (n - 1),
         # global hooking, first part: every vertex's label, edge slot and list
-        # head initialised (16 n); with K sampled arcs per vertex (K = 2 when
-        # nnz >= 6 n), per vertex its offsets (2 w_o) and per sample the arc
-        # (4) and the two labels (8) read, and, since the dominant tree forms
-        # there, every tree edge's compare-and-swap, record and list links (28)
-        "hook_sample": 16 * n + ((2 * w_o + 12 * 2) * n + 28 * T if nnz >= 6 * n else 0),
-        # global hooking sweep: offsets + neighbour ids read, one label gather
-        # per arc (both ends of each edge), one label read per vertex; each of
-        # the T tree edges: compare-and-swap (4), edge recorded (8), two
-        # list-head exchanges and the next pair (16)
-        "hook_global": w_o * (n + 1) + 6 * nnz + 4 * n + 28 * T,
+        # head initialised (16 n); with K sampled arcs per vertex, per vertex
+        # its offsets (2 w_o) and per sample the arc (4) and the two labels (8)
+        # read, and, since the dominant tree forms there, every tree edge's
+        # compare-and-swap, record and list links (28); with K = 0 the first
+        # pass: offsets (2 w_o per vertex), the arcs it reads (4 each), and
+        # per hook the label, edge and edge slot written (12)
+        "hook_sample": 16 * n + ((2 * w_o + 12 * K) * n + 28 * T if K > 0
+                                 else 2 * w_o * n + 4 * a1 + 12 * T1),
+        # global hooking sweep: offsets + neighbour ids read, one label read
+        # per vertex, and either (K > 0) one label gather per arc and per tree
+        # edge its compare-and-swap (4), record (8), two list-head exchanges
+        # and the next pair (16), or (K = 0) the slot of every vertex read
+        # (4, its edge 4 more when the first pass hooked it), the first pass's
+        # edges linked (16 each), and each remaining edge -- visited once, from
+        # its larger end -- two label gathers (8), its tree edges 28 as above
+        "hook_global": (w_o * (n + 1) + 6 * nnz + 4 * n + 28 * T if K > 0 else
+                        w_o * (n + 1) + 4 * nnz + 8 * n + 4 * T1 + 16 * T1
+                        + 8 * max(nnz // 2 - T1, 0) + 28 * (T - T1)),
         # Euler arc lists from the slots: edge read (8), two list-head
         # exchanges (8), next pair written (8) per slot
         "link": 24 * n,
@@ -277,7 +304,6 @@ def main():
               "independent graphs would be spread over GPUs by edge count.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import paper_2603_11645_amd as rst
     from paper_2603_11645_amd import inputs as I
@@ -306,6 +332,13 @@ def main():
                                "OPT_HEAVY_DEGREE", "OPT_RANK_ELEMS_PER_THREAD",
                                "OPT_RANK_STRIDE")}}
         log("[bench] tuning cache: %s" % tuning)
+
+    # arcs the global hooking samples per vertex (the library's default when
+    # the option is unset); with none, its first pass hooks what it can alone
+    K_hook = ctx.get_option(rst.OPT_HOOK_SAMPLE)
+    if K_hook < 0:
+        K_hook = 2 if g.nnz >= 6 * g.n else 0
+    first = first_pass_hooks(g) if K_hook == 0 else (0, 0)
 
     if args.calibrate_copy:
         src = torch.empty(64 << 20, dtype=torch.int32, device="cuda").fill_(1)
@@ -363,7 +396,7 @@ def main():
         ms = mean("ms_kernel", k)
         if ms <= 0:
             continue                      # not run on this path
-        b = kernel_bytes(k, g, last)
+        b = kernel_bytes(k, g, last, K_hook, first)
         kernels[k] = {"ms_per_launch": round(ms, 5), "algorithmic_bytes_per_launch": int(b),
                       "achieved_GBps": round(b / (ms * 1e-3) / 1e9, 1)}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_launch"])
@@ -376,11 +409,13 @@ def main():
                                       / 1e9, 1) if tr else None,
                 "traffic_frac": round(tr["bytes_per_launch"] / (kernels[dom]["ms_per_launch"] * 1e-3)
                                       / 1e9 / HBM_PEAK_GBS, 4) if tr else None,
-                "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE x%.4f + WRITE_SIZE "
-                                "x%.4f (scales from a plain 256 MiB copy's readings; "
-                                "profiles/traffic.json); achieved and frac count the algorithmic "
-                                "bytes only" % ((tr["fetch_scale"], tr["write_scale"]) if tr
-                                                else (float("nan"), float("nan"))),
+                "traffic_note": ("HBM bytes per launch from rocprofv3 FETCH_SIZE x%.4f + WRITE_SIZE "
+                                 "x%.4f (scales from a plain 256 MiB copy's readings; "
+                                 "profiles/traffic.json); achieved and frac count the algorithmic "
+                                 "bytes only" % (tr["fetch_scale"], tr["write_scale"]) if tr else
+                                 "no counter profile of this kernel's current source in "
+                                 "profiles/traffic.json; achieved and frac count the algorithmic "
+                                 "bytes only"),
                 "launch_ms": kernels[dom]["ms_per_launch"],
                 "algorithmic_bytes_per_launch": kernels[dom]["algorithmic_bytes_per_launch"]}
 

@@ -286,7 +286,14 @@ __global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const Off
     // arcs go onto the lists here
     const int32_t mv = (minhook && v < n && tu[v] == (int32_t)v) ? tv[v] : -1;
     s_min[t] = mv;
-    if (mv >= 0 && head) link_slot((int32_t)v, (int32_t)v, mv, head, next);
+    if (head && minhook) {
+      // arc 2v = v -> mv onto v's own list, 2v+1 = mv -> v onto mv's, grouped
+      // per wave by target (on graphs with hubs most vertices pick a hub)
+      int2 nx = make_int2(-1, -1);
+      if (mv >= 0) nx.x = atomicExch(&head[v], (int32_t)(2 * v));
+      nx.y = wave_push_front<2>(mv >= 0, mv, (int32_t)(2 * v + 1), head);
+      if (mv >= 0) reinterpret_cast<int2 *>(next)[v] = nx;
+    }
     if (v < n && !(vmask && vmask[v]) && !(gsel && !gsel[v])) {
       const OffT b = off[v], e = off[v + 1];
       if (e > b) locals += (cols[b] >> kGhTileShift) == (int32_t)(v >> kGhTileShift);
@@ -312,7 +319,7 @@ __global__ __launch_bounds__(kGhThreads, 8) void k_gh_sweep(int64_t n, const Off
         const int j = lds_upper_search(s_scan, kGhThreads, k);
         u = (int32_t)(v0 + j);
         w = cols[s_beg[j] + (OffT)(k - s_scan[j])];
-        keep = giant >= 0 ? w != u : (w < u && w != s_min[j]);
+        keep = (giant >= 0 ? w != u : w < u) && w != s_min[j];
       }
       const uint64_t m = __ballot(keep);
       if (keep) q[qn + lanes_below(m)] = make_int2(u, w);
@@ -391,12 +398,25 @@ int ghook_sample_arcs(const rst_ctx *ctx, const rst_csr *g) {
 rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, bool init) {
   const int64_t n = g->n;
   const int K = ghook_sample_arcs(ctx, g);
-  // the first pass needs every vertex a root with an empty slot (fresh init)
-  // and is meant for sweeps without a dominant tree
+  // the first pass needs every vertex a root with an empty slot (fresh init);
+  // it serves sweeps without a dominant tree (on graphs with random ids and
+  // hubs it leaves many small trees where sampling finds the dominant one:
+  // C3's sweep 0.05 -> 1.7 ms with it in place of the sampled hooks)
   const int minhook = (init && K == 0 && !f.gsel) ? 1 : 0;
   RST_KMARK(ctx, RST_KERNEL_HOOK_SAMPLE, 0);
   if (init) {
     RST_SWEEP(ctx, k_gh_init, n, n, f.cc, f.tu, f.tv, f.head);
+    RST_HIP(hipGetLastError());
+  }
+  if (minhook) {
+    if (g->offset_bytes == 4)
+      hipLaunchKernelGGL(k_gh_minhook<int32_t>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
+                         ctx->stream, n, (const int32_t *)g->offsets, g->cols, f.vmask, f.cc,
+                         f.tu, f.tv);
+    else
+      hipLaunchKernelGGL(k_gh_minhook<int64_t>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
+                         ctx->stream, n, (const int64_t *)g->offsets, g->cols, f.vmask, f.cc,
+                         f.tu, f.tv);
     RST_HIP(hipGetLastError());
   }
   if (K > 0) {
@@ -421,17 +441,6 @@ rst_status enqueue_hook_global(rst_ctx *ctx, const rst_csr *g, ForestBufs &f, bo
     RST_HIP(hipGetLastError());
   } else {
     RST_TRY(enqueue_fill(ctx, f.counters + kCntGiant, 1, -1));
-    if (minhook) {
-      if (g->offset_bytes == 4)
-        hipLaunchKernelGGL(k_gh_minhook<int32_t>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
-                           ctx->stream, n, (const int32_t *)g->offsets, g->cols, f.vmask, f.cc,
-                           f.tu, f.tv);
-      else
-        hipLaunchKernelGGL(k_gh_minhook<int64_t>, dim3(grid_for(n, kBlock)), dim3(kBlock), 0,
-                           ctx->stream, n, (const int64_t *)g->offsets, g->cols, f.vmask, f.cc,
-                           f.tu, f.tv);
-      RST_HIP(hipGetLastError());
-    }
   }
   RST_KMARK(ctx, RST_KERNEL_HOOK_SAMPLE, 1);
   RST_KMARK(ctx, RST_KERNEL_HOOK_GLOBAL, 0);
