@@ -3,6 +3,10 @@ sampling of each vertex's first arcs, the dominant tree found from a sample,
 then the remaining arcs (Sec. III-B hooking with the edge of every union
 recorded, Sec. I).
 
+Without a dominant tree to seek, the sweep starts with a pass without finds
+(every vertex hooked to the smallest of its first 16 neighbours when that is
+smaller than itself); its edge cases get a graph of their own below.
+
 Min-id component labels are unique, so they are compared bit for bit with the
 oracle's union-find; spanning trees go through the oracle verifier; on tree
 inputs the rooted spanning tree is unique and compared bit for bit.  Every
@@ -100,6 +104,54 @@ def run_case(ctx, rst, g, mode, sample):
 def test_forced_modes(ctx, rst, name, mode, sample):
     try:
         run_case(ctx, rst, graph(name), mode, sample)
+    finally:
+        ctx.set_option(rst.OPT_HOOK_MODE, 0)
+        ctx.set_option(rst.OPT_HOOK_SAMPLE, -1)
+
+
+def first_pass_cases():
+    """A random graph in CSR rows of their own order: rows reversed (the
+    smallest neighbour of every vertex of degree above 16 lies beyond the 16
+    arcs the first pass reads), every first-pass edge of even vertices given a
+    parallel copy, self-loops on every 7th vertex, and a separate path
+    n-3 - n-2 - n-1, whose smallest vertex has only larger neighbours (it
+    stays a root)."""
+    base = I.random_graph(30000, 90000, seed=21)
+    hub_u = np.full(40, 12345, np.int32)             # a vertex of degree 40+
+    hub_v = np.arange(20000, 20040, dtype=np.int32)
+    eu, ev = base.edge_list()
+    eu = np.concatenate([eu, hub_u]).astype(np.int32)
+    ev = np.concatenate([ev, hub_v]).astype(np.int32)
+    n = base.n + 3                                    # a path n-3 .. n-1 apart
+    eu = np.concatenate([eu, [n - 3, n - 2]]).astype(np.int32)
+    ev = np.concatenate([ev, [n - 2, n - 1]]).astype(np.int32)
+    g = I.csr_from_edges(n, eu, ev, name="first_pass")
+    rows = []
+    for v in range(n):
+        r = list(g.cols[g.offsets[v]:g.offsets[v + 1]][::-1])
+        if v % 2 == 0 and r:
+            small = [w for w in r[:16] if w < v]
+            if small:
+                r.append(min(small))                  # parallel copy of the first-pass edge
+        if v % 7 == 0:
+            r.append(v)                               # self-loop
+        rows.append(r)
+    # parallel copies must be symmetric: add the reverse arc for every copy
+    for v in range(0, n, 2):
+        small = [w for w in list(g.cols[g.offsets[v]:g.offsets[v + 1]][::-1])[:16] if w < v]
+        if small:
+            rows[min(small)].append(v)
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    cols = np.array([w for r in rows for w in r], dtype=np.int32)
+    return I.Graph(name="first_pass", n=n, offsets=off, cols=cols)
+
+
+def test_first_pass_edge_cases(ctx, rst):
+    g = first_pass_cases()
+    try:
+        for mode, sample in [(2, 0), (2, -1), (2, 2)]:
+            run_case(ctx, rst, g, mode, sample)
     finally:
         ctx.set_option(rst.OPT_HOOK_MODE, 0)
         ctx.set_option(rst.OPT_HOOK_SAMPLE, -1)
