@@ -21,7 +21,9 @@
 //     joins tree edges u and w.  Its connected components -- min-id hooking
 //     by compare-and-swap as in the hooking pass, then pointer jumping -- are
 //     the biconnected components of the tree edges, each labelled by its
-//     smallest child vertex.
+//     smallest child vertex.  The joins commute, so the non-tree edges' are
+//     made in step 2's pass over the arcs, which reads the same far-end
+//     record, and the tree edges' after step 3.
 //  5. Every arc takes its component: a tree arc (or a parallel copy) the one
 //     of its child's tree edge, a non-tree arc the one of the tree edge of its
 //     end with the larger preorder number; a vertex whose arcs carry two or
